@@ -1,0 +1,246 @@
+/*
+ * gf.h -- C ABI of the MI355X galaxy-fitting hot path.
+ *
+ * Barsdell, Barnes & Fluke, "Fitting Galaxies on GPUs", Sec. 2 describe the
+ * fitting loop as five steps: (1) evaluate the model on a grid from the
+ * current parameters, (2) convolve it with the PSF, (3) compare model and
+ * observation, (4) adjust the parameters, (5) test for completion.  Sec. 3
+ * identifies steps 1-3 as transform, FFT (+ transform) and transform + reduce,
+ * common to most fitting routines, and argues that the image should stay in
+ * device memory for all iterations with only O(1) results going back.  This
+ * library implements steps 1-3 as separate calls, their derivatives, and a
+ * whole device-resident Levenberg-Marquardt loop (steps 4-5).
+ *
+ * Conventions for every call:
+ *   - Pointers named as device pointers are caller-owned device memory (for
+ *     example a torch tensor's data_ptr()); the library never frees them.
+ *     Host arrays are copied before the call returns.
+ *   - Images are FP32, row-major.  Batches are flat: stamp s occupies the
+ *     offsets reported by gf_batch_offsets() in each flat array.
+ *   - Work is enqueued on the context's stream (gf_set_stream) and runs
+ *     asynchronously; argument and shape errors are detected on the host and
+ *     returned before anything is enqueued.  A failure of an earlier
+ *     asynchronous launch surfaces as GF_EDEVICE from a later call.
+ *   - No C++ exception crosses this boundary.  gf_last_error() returns a
+ *     message for the last non-GF_OK status of a context.
+ *   - A context is not thread-safe; use one per host thread.
+ *
+ * Model (the readings the paper leaves open, fixed here):
+ *   - parameters per component: x0, y0, Ie, Re, n, q, phi; one sky per stamp;
+ *     P = 7 * n_comp + 1 floats per stamp.  phi is in radians, counter-
+ *     clockwise from +x (x runs along columns); q = b/a in (0, 1].
+ *   - surface brightness: Ie exp(-b_n [(R/Re)^(1/n) - 1]) with
+ *     R^2 = x'^2 + y'^2 / q^2, (x', y') the offsets rotated by phi, and b_n the
+ *     root of P(2n, b_n) = 1/2 (P the regularised lower incomplete gamma).
+ *   - pixel (row i, col j) is centred on (x = j, y = i); its value is the mean
+ *     over S x S sub-samples at x = j + (s + 1/2)/S - 1/2 (same for y).
+ *   - the model of an H x W stamp with a K x K PSF (K odd, c = (K-1)/2) is
+ *     evaluated on a padded grid of Mh x Mw = (H+K-1) x (W+K-1) pixels that
+ *     starts at stamp pixel (-c, -c); the convolution keeps the "valid" part
+ *       out[y][x] = sum_{u,v} psf[u][v] pad[y+K-1-u][x+K-1-v]
+ *     and the sky is added after it.  chi^2 = sum w (d - m)^2.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_ctx gf_ctx;
+typedef struct gf_batch gf_batch;
+typedef struct gf_psf gf_psf;
+
+typedef enum {
+  GF_OK = 0,
+  GF_EINVAL = 1,    /* null pointer or out-of-range argument */
+  GF_ESHAPE = 2,    /* sizes that the library does not support or that disagree */
+  GF_ENOMEM = 3,    /* device or host allocation failed */
+  GF_EDEVICE = 4,   /* a HIP call or an earlier asynchronous launch failed */
+  GF_ENUMERIC = 5,  /* non-finite input where a finite value is required */
+  GF_ENOTCONV = 6   /* per-stamp LM status: stopped without meeting ftol/xtol */
+} gf_status;
+
+#define GF_NPC 7           /* parameters per Sersic component */
+#define GF_MAX_COMP 4      /* components per stamp */
+#define GF_MAX_K 129       /* largest PSF side */
+#define GF_MAX_FFT 2048    /* largest FFT side; stamps need H+K-1, W+K-1 <= this */
+#define GF_MAX_OVERSAMPLE 8
+
+/* Convolution path of a prepared PSF. */
+#define GF_CONV_AUTO 0     /* chosen per stamp from the PSF and grid size */
+#define GF_CONV_FFT 1      /* Fourier-space product (Sec. 3, step 2) */
+#define GF_CONV_DIRECT 2   /* direct sum over taps */
+
+/* gf_jacobian modes. */
+#define GF_JAC_FULL 0      /* d m / d theta images */
+#define GF_JAC_ADJOINT 1   /* vector-Jacobian product sum_i c_i d m_i / d theta */
+
+/* ------------------------------------------------------------- contexts */
+
+/* Create a context on HIP device `device`; builds the b_n table (FP64 on the
+ * host, FP32 on the device).  *ctx is set to NULL on failure. */
+gf_status gf_create(gf_ctx **ctx, int device);
+void gf_destroy(gf_ctx *ctx);
+/* All later work of this context is enqueued on `hip_stream` (a hipStream_t;
+ * NULL = the default stream). */
+gf_status gf_set_stream(gf_ctx *ctx, void *hip_stream);
+const char *gf_last_error(const gf_ctx *ctx);
+/* Block until all work enqueued by this context has finished; returns
+ * GF_EDEVICE if any of it failed. */
+gf_status gf_synchronize(gf_ctx *ctx);
+
+/* --------------------------------------------------------------- batches */
+
+/* Describe n_stamps stamps (host arrays, copied): stamp s is H[s] x W[s]
+ * pixels, has a K[s] x K[s] PSF (K odd) and n_comp[s] components.
+ * shared_image != 0 declares that every stamp shares one observation and one
+ * PSF (a likelihood batch: many parameter vectors against one image); all
+ * stamps must then have the same H, W, K and n_comp, and data/weight/psf
+ * arrays hold a single image.  Errors: GF_EINVAL, GF_ESHAPE (K even or above
+ * GF_MAX_K, padded side above GF_MAX_FFT, n_comp outside 1..GF_MAX_COMP). */
+gf_status gf_batch_create(gf_ctx *ctx, int n_stamps, const int32_t *H, const int32_t *W, const int32_t *K,
+                          const int32_t *n_comp, int shared_image, gf_batch **out);
+void gf_batch_destroy(gf_batch *batch);
+
+/* Flat array sizes (elements) for a batch; any output may be NULL.
+ *   n_pix: sum H*W        (model, residual images)
+ *   n_pad: sum Mh*Mw      (padded model grids, per channel)
+ *   n_psf: sum K*K        (PSF taps; K*K when shared)
+ *   n_par: sum P          (parameters)
+ *   n_img: n_pix, or H*W when shared (data, weight)
+ *   n_jac: sum P*H*W      (full Jacobian images) */
+gf_status gf_batch_sizes(const gf_batch *batch, int64_t *n_pix, int64_t *n_pad, int64_t *n_psf, int64_t *n_par,
+                         int64_t *n_img, int64_t *n_jac);
+/* Per-stamp offsets (host arrays of n_stamps int64, any may be NULL) into
+ * the flat arrays above. */
+gf_status gf_batch_offsets(const gf_batch *batch, int64_t *pix, int64_t *pad, int64_t *psf, int64_t *par,
+                           int64_t *img, int64_t *jac);
+int gf_batch_count(const gf_batch *batch);
+
+/* ------------------------------------------------------------------ PSF */
+
+/* Prepare the PSF of every stamp (device array of n_psf floats, taps used as
+ * given: normalise them beforehand if unit sum is wanted).  For stamps on the
+ * FFT path this computes the optical transfer function on an L x L grid
+ * (L = smallest 2^a 3^b 5^c >= the padded side) on the device; the prepared
+ * object owns that memory.  `mode` is GF_CONV_AUTO, GF_CONV_FFT or
+ * GF_CONV_DIRECT.  The psf array must stay valid while *out is used. */
+gf_status gf_psf_prepare(gf_ctx *ctx, const gf_batch *batch, const float *psf, int mode, gf_psf **out);
+void gf_psf_destroy(gf_psf *psf);
+/* Host array of n_stamps ints: 1 where the stamp uses the FFT path. */
+gf_status gf_psf_paths(const gf_psf *psf, int32_t *uses_fft, int32_t *fft_side);
+
+/* ------------------------------------------------------ step 1: evaluate */
+
+/* Paper Sec. 2 step 1 / Sec. 3 item 1 (a per-pixel transform).  theta:
+ * device [n_par] FP32.  Writes model_pad (device [n_pad]): the sum of all
+ * components, mean of oversample^2 sub-samples, no sky.  oversample in
+ * 1..GF_MAX_OVERSAMPLE. */
+gf_status gf_eval_model(gf_ctx *ctx, const gf_batch *batch, const float *theta, int oversample, float *model_pad);
+
+/* ----------------------------------------------------- step 2: convolve */
+
+/* Paper Sec. 2 step 2 / Sec. 3 item 2 (FFT + pointwise transform).  in:
+ * device, n_ch channels per stamp; stamp s, channel c starts at
+ * pad_off[s]*n_ch + c*Mh*Mw.  out: device; stamp s, channel c starts at
+ * pix_off[s]*n_ch + c*H*W.  n_ch in 1..64. */
+gf_status gf_convolve_psf(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *in, int n_ch,
+                          float *out);
+
+/* Steps 1-2 plus sky: out (device [n_pix]) = conv(components) + sky, the
+ * model image that step 3 compares with the observation.  work as in
+ * gf_likelihood (NULL = context workspace). */
+gf_status gf_model(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *theta, int oversample,
+                   float *out, void *work);
+
+/* ------------------------------------------------------- step 3: compare */
+
+/* Paper Sec. 2 step 3 / Sec. 3 item 3 (transform + reduce: the sum of squared
+ * differences).  model: device [n_pix] convolved model without sky; the sky
+ * is read from theta (device [n_par]).  data, weight: device [n_img]
+ * (weight = inverse variance, 0 masks a pixel).  resid (nullable): device
+ * [n_pix] = sqrt(w) (d - m - sky).  chi2: device [2 * n_stamps], an FP32
+ * (hi, lo) pair per stamp whose exact sum is the compensated chi^2.  The
+ * reduction order is fixed, so results are bitwise reproducible. */
+gf_status gf_chi2(gf_ctx *ctx, const gf_batch *batch, const float *model, const float *theta, const float *data,
+                  const float *weight, float *resid, float *chi2);
+
+/* Steps 1-3 in one call: chi2 (device [2 * n_stamps], (hi, lo) pairs as in
+ * gf_chi2) of every stamp at theta (device [n_par] FP32).  work: device
+ * scratch of at least gf_likelihood_workspace() bytes, or NULL to use the
+ * context's own workspace (which then grows on the first call). */
+gf_status gf_likelihood(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *theta, int oversample,
+                        const float *data, const float *weight, float *chi2, void *work);
+int64_t gf_likelihood_workspace(const gf_batch *batch, const gf_psf *psf);
+
+/* ------------------------------------------------------- derivatives */
+
+/* Derivatives of the model m = conv(components) + sky.
+ * GF_JAC_FULL: out = device [n_jac]; stamp s holds P images of H*W,
+ *   d m / d theta_p, the last one (sky) all ones.  cot, weight ignored.
+ * GF_JAC_ADJOINT: out = device [n_par];
+ *   out[p] = scale * sum_i cot_i * (weight ? sqrt(weight_i) : 1) * d m_i / d theta_p
+ *   computed by correlating the cotangent with the PSF and contracting it
+ *   with the point derivatives on the padded grid (no Jacobian images).
+ *   With cot = resid from gf_chi2 and scale = -2 this is d chi^2 / d theta.
+ * The derivative of b_n in n comes from the same table as b_n. */
+gf_status gf_jacobian(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *theta, int oversample,
+                      int mode, const float *cot, const float *weight, float scale, float *out);
+
+/* ----------------------------------------------- steps 4-5: LM fitting */
+
+typedef struct {
+  int32_t max_iter;     /* iteration cap (default 100) */
+  int32_t oversample;   /* S (default 5) */
+  double lambda0;       /* initial damping (1e-3) */
+  double lambda_up;     /* factor on a rejected step (10) */
+  double lambda_down;   /* divisor on an accepted step (10) */
+  double lambda_max;    /* give up above this (1e10) */
+  double ftol;          /* stop when (chi2 - chi2')/chi2' < ftol on an accepted step (1e-5) */
+  double xtol;          /* stop when max |dtheta_i| / max(|theta_i|, 1) < xtol on an accepted step (1e-10) */
+  const double *lo;     /* device [n_par] lower bounds or NULL */
+  const double *hi;     /* device [n_par] upper bounds or NULL */
+  const uint8_t *free_mask; /* device [n_par], nonzero = fitted, or NULL = all free */
+  int32_t poll_every;   /* iterations between host checks of the active-stamp count (default 4) */
+  int32_t use_graph;    /* capture one iteration in a HIP graph and replay it (default 1) */
+} gf_lm_opts;
+
+typedef struct {
+  double chi2;     /* chi^2 at the returned parameters */
+  double lambda;   /* damping at exit */
+  int32_t iters;   /* iterations taken */
+  int32_t nfev;    /* model evaluations (steps 1-3) */
+  int32_t njev;    /* Jacobian evaluations */
+  int32_t status;  /* GF_OK (converged) or GF_ENOTCONV */
+  int32_t reason;  /* 1 ftol, 2 xtol, 3 chi2 = 0, 4 lambda above lambda_max, 5 iteration cap */
+  int32_t pad;
+} gf_lm_result;
+
+void gf_lm_opts_default(gf_lm_opts *opts);
+
+/* Levenberg-Marquardt over every stamp of the batch at once (Marquardt 1963;
+ * the paper's galfit route for step 4).  Per stamp and iteration:
+ *   A = J^T W J, g = J^T W (d - m) over the free parameters,
+ *   (A + lambda diag(max(A_ii, 1e-12 max A_jj))) delta = g  by FP64 Cholesky
+ *   (not positive definite: lambda *= up, try again),
+ *   theta' = clip(theta + delta, lo, hi); accept iff chi2(theta') < chi2(theta)
+ *   (lambda /= down), else reject (lambda *= up).
+ * theta_io: device [n_par] FP64, start in, best accepted point out.
+ * res: device [n_stamps].  data, weight: device [n_img].  All iterations run
+ * on the device; the host only reads the count of still-active stamps every
+ * poll_every iterations.  Stamps that finish stop costing work.
+ * Returns GF_OK when the call ran (per-stamp outcomes are in res). */
+gf_status gf_fit_lm(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
+                    double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
+
+/* Library version string. */
+const char *gf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

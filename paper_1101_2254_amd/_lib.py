@@ -1,0 +1,206 @@
+"""ctypes binding of ``libgf.so`` (declared in ``include/gf.h``).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Importing this module does not touch the GPU; :func:`lib` loads the
+library and raises if it has not been built, so no call can fall back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgf.so")
+
+GF_OK, GF_EINVAL, GF_ESHAPE, GF_ENOMEM, GF_EDEVICE, GF_ENUMERIC, GF_ENOTCONV = range(7)
+STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ESHAPE", 3: "GF_ENOMEM", 4: "GF_EDEVICE", 5: "GF_ENUMERIC",
+                6: "GF_ENOTCONV"}
+GF_NPC = 7
+GF_MAX_COMP = 4
+GF_CONV_AUTO, GF_CONV_FFT, GF_CONV_DIRECT = 0, 1, 2
+GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
+
+# Every symbol that include/gf.h declares.
+EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_synchronize", "gf_batch_create",
+           "gf_batch_destroy", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
+           "gf_psf_destroy", "gf_psf_paths", "gf_eval_model", "gf_convolve_psf", "gf_model", "gf_chi2", "gf_likelihood",
+           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_version")
+
+
+class GfLmOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("oversample", ctypes.c_int32), ("lambda0", ctypes.c_double),
+                ("lambda_up", ctypes.c_double), ("lambda_down", ctypes.c_double),
+                ("lambda_max", ctypes.c_double), ("ftol", ctypes.c_double), ("xtol", ctypes.c_double),
+                ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("free_mask", ctypes.c_void_p),
+                ("poll_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class GfLmResult(ctypes.Structure):
+    _fields_ = [("chi2", ctypes.c_double), ("lambda_", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("nfev", ctypes.c_int32), ("njev", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reason", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_lib = None
+
+
+class GfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgf.so (built by ``paper_1101_2254_amd.build``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1101_2254_amd.build` "
+                           "(there is no other implementation to fall back to)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, flt = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    pvp = ctypes.POINTER(ctypes.c_void_p)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "gf_create": (i32, [pvp, i32]),
+        "gf_destroy": (None, [vp]),
+        "gf_set_stream": (i32, [vp, vp]),
+        "gf_last_error": (ctypes.c_char_p, [vp]),
+        "gf_synchronize": (i32, [vp]),
+        "gf_batch_create": (i32, [vp, i32, vp, vp, vp, vp, i32, pvp]),
+        "gf_batch_destroy": (None, [vp]),
+        "gf_batch_sizes": (i32, [vp, pi64, pi64, pi64, pi64, pi64, pi64]),
+        "gf_batch_offsets": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "gf_batch_count": (i32, [vp]),
+        "gf_psf_prepare": (i32, [vp, vp, vp, i32, pvp]),
+        "gf_psf_destroy": (None, [vp]),
+        "gf_psf_paths": (i32, [vp, vp, vp]),
+        "gf_eval_model": (i32, [vp, vp, vp, i32, vp]),
+        "gf_convolve_psf": (i32, [vp, vp, vp, vp, i32, vp]),
+        "gf_model": (i32, [vp, vp, vp, vp, i32, vp, vp]),
+        "gf_chi2": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "gf_likelihood": (i32, [vp, vp, vp, vp, i32, vp, vp, vp, vp]),
+        "gf_likelihood_workspace": (i64, [vp, vp]),
+        "gf_jacobian": (i32, [vp, vp, vp, vp, i32, i32, vp, vp, flt, vp]),
+        "gf_lm_opts_default": (None, [ctypes.POINTER(GfLmOpts)]),
+        "gf_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
+        "gf_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return _lib
+
+
+def check(status: int, ctx=None, what: str = "") -> None:
+    if status != GF_OK:
+        msg = lib().gf_last_error(ctx).decode() if ctx else what
+        raise GfError(status, msg or what)
+
+
+# Thin wrappers with the C names (pointers as ints).
+def gf_create(device: int = 0) -> int:
+    p = ctypes.c_void_p()
+    check(lib().gf_create(ctypes.byref(p), device), None, "gf_create failed")
+    return p.value
+
+
+def gf_destroy(ctx: int) -> None:
+    lib().gf_destroy(ctx)
+
+
+def gf_set_stream(ctx: int, stream: int) -> None:
+    check(lib().gf_set_stream(ctx, stream), ctx)
+
+
+def gf_synchronize(ctx: int) -> None:
+    check(lib().gf_synchronize(ctx), ctx)
+
+
+def gf_batch_create(ctx: int, H, W, K, ncomp, shared: bool) -> int:
+    n = len(H)
+    arr = ctypes.c_int32 * n
+    h, w, k, c = arr(*H), arr(*W), arr(*K), arr(*ncomp)
+    p = ctypes.c_void_p()
+    check(lib().gf_batch_create(ctx, n, h, w, k, c, int(shared), ctypes.byref(p)), ctx)
+    return p.value
+
+
+def gf_batch_destroy(b: int) -> None:
+    lib().gf_batch_destroy(b)
+
+
+def gf_batch_sizes(b: int) -> dict:
+    v = [ctypes.c_int64() for _ in range(6)]
+    check(lib().gf_batch_sizes(b, *[ctypes.byref(x) for x in v]), None, "gf_batch_sizes failed")
+    return dict(zip(("n_pix", "n_pad", "n_psf", "n_par", "n_img", "n_jac"), (x.value for x in v)))
+
+
+def gf_batch_offsets(b: int, n: int) -> dict:
+    arrs = [(ctypes.c_int64 * n)() for _ in range(6)]
+    check(lib().gf_batch_offsets(b, *arrs), None, "gf_batch_offsets failed")
+    return dict(zip(("pix", "pad", "psf", "par", "img", "jac"), ([int(v) for v in a] for a in arrs)))
+
+
+def gf_psf_prepare(ctx: int, b: int, taps_ptr: int, mode: int) -> int:
+    p = ctypes.c_void_p()
+    check(lib().gf_psf_prepare(ctx, b, taps_ptr, mode, ctypes.byref(p)), ctx)
+    return p.value
+
+
+def gf_psf_destroy(p: int) -> None:
+    lib().gf_psf_destroy(p)
+
+
+def gf_psf_paths(p: int, n: int):
+    f = (ctypes.c_int32 * n)()
+    s = (ctypes.c_int32 * n)()
+    check(lib().gf_psf_paths(p, f, s), None, "gf_psf_paths failed")
+    return list(f), list(s)
+
+
+def gf_eval_model(ctx, b, theta_ptr, oversample, out_ptr):
+    check(lib().gf_eval_model(ctx, b, theta_ptr, oversample, out_ptr), ctx)
+
+
+def gf_convolve_psf(ctx, b, psf, in_ptr, n_ch, out_ptr):
+    check(lib().gf_convolve_psf(ctx, b, psf, in_ptr, n_ch, out_ptr), ctx)
+
+
+def gf_model(ctx, b, psf, theta_ptr, oversample, out_ptr, work_ptr):
+    check(lib().gf_model(ctx, b, psf, theta_ptr, oversample, out_ptr, work_ptr), ctx)
+
+
+def gf_chi2(ctx, b, model_ptr, theta_ptr, data_ptr, weight_ptr, resid_ptr, chi2_ptr):
+    check(lib().gf_chi2(ctx, b, model_ptr, theta_ptr, data_ptr, weight_ptr, resid_ptr, chi2_ptr), ctx)
+
+
+def gf_likelihood(ctx, b, psf, theta_ptr, oversample, data_ptr, weight_ptr, chi2_ptr, work_ptr):
+    check(lib().gf_likelihood(ctx, b, psf, theta_ptr, oversample, data_ptr, weight_ptr, chi2_ptr, work_ptr), ctx)
+
+
+def gf_likelihood_workspace(b, psf) -> int:
+    return int(lib().gf_likelihood_workspace(b, psf))
+
+
+def gf_jacobian(ctx, b, psf, theta_ptr, oversample, mode, cot_ptr, weight_ptr, scale, out_ptr):
+    check(lib().gf_jacobian(ctx, b, psf, theta_ptr, oversample, mode, cot_ptr, weight_ptr, float(scale), out_ptr),
+          ctx)
+
+
+def gf_lm_opts_default() -> GfLmOpts:
+    o = GfLmOpts()
+    lib().gf_lm_opts_default(ctypes.byref(o))
+    return o
+
+
+def gf_fit_lm(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, opts: GfLmOpts, res_ptr):
+    check(lib().gf_fit_lm(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), res_ptr), ctx)
+
+
+def gf_version() -> str:
+    return lib().gf_version().decode()

@@ -1,0 +1,823 @@
+// gf_api.cpp -- host side of libgf: contexts, batches, PSF preparation
+// (FFT plans, OTFs, work lists), the step 1-3 entry points, derivatives and
+// the device-resident Levenberg-Marquardt driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gf_internal.h"
+
+namespace gf {
+std::vector<float2> build_bn_table();
+hipError_t launch_eval(hipStream_t, const gf_batch *, const float *, int, const float2 *, float *, const int *);
+hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float2 *, float *, const int *);
+hipError_t launch_eval_jac(hipStream_t, const gf_batch *, const float *, int, const float2 *, float *, int,
+                           const int *);
+hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int, const float2 *, float *, int,
+                             const int *);
+hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float2 *, const float *,
+                                   float *);
+hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
+                           float *, const int *);
+hipError_t launch_fft_corr(hipStream_t, const gf_batch *, const gf_psf *, const float *, float2 *, float2 *, float *);
+hipError_t launch_fft_otf(hipStream_t, const gf_batch *, const gf_psf *, const float *, const Work *, int,
+                          const Work *, int, const int64_t *, float2 *, const int64_t *);
+hipError_t launch_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float *, bool,
+                         const int *);
+hipError_t launch_chi2(hipStream_t, const gf_batch *, const float *, const void *, bool, const float *,
+                       const float *, float *, float2 *, unsigned int *, float2 *, const int *);
+hipError_t launch_cot_prep(hipStream_t, const gf_batch *, const float *, const float *, float, float *, float2 *);
+hipError_t launch_adjoint_final(hipStream_t, const gf_batch *, const int32_t *, const float *, const float2 *,
+                                float *);
+hipError_t launch_jac_assemble(hipStream_t, const gf_batch *, const float *, int, float *);
+hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *);
+hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
+                            const float *, float *, int, int, const int *);
+hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
+hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
+hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, int, const gf_lm_opts *, LMState *,
+                           double *, const double *, double *, int *, int *);
+hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
+                            const double *, int *, int *, int *);
+hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
+}  // namespace gf
+
+using namespace gf;
+
+namespace {
+
+gf_status fail(gf_ctx *c, gf_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define GF_TRY(ctx, expr)                                                                                   \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, GF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t upload(T **d, const std::vector<T> &h) {
+  *d = nullptr;
+  if (h.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void **)d, h.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+// Bump allocator over the context workspace; run once with base == nullptr
+// to size it.
+struct Arena {
+  char *base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T *take(int64_t n) {
+    const size_t a = (off + 255) & ~(size_t)255;
+    off = a + (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+    return base ? (T *)(base + a) : nullptr;
+  }
+};
+
+gf_status ensure_ws(gf_ctx *c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return GF_OK;
+  GF_TRY(c, hipStreamSynchronize(c->stream));
+  dfree(c->ws);
+  c->ws_bytes = 0;
+  const size_t nb = bytes + bytes / 4;
+  if (hipMalloc(&c->ws, nb) != hipSuccess) {
+    c->ws = nullptr;
+    return fail(c, GF_ENOMEM, "workspace allocation of " + std::to_string(nb) + " bytes failed");
+  }
+  c->ws_bytes = nb;
+  return GF_OK;
+}
+
+gf_status ensure_counters(gf_ctx *c, int64_t n) {
+  if (n <= c->n_counters) return GF_OK;
+  GF_TRY(c, hipStreamSynchronize(c->stream));
+  dfree(c->d_counters);
+  c->n_counters = 0;
+  const int64_t nn = std::max<int64_t>(n, 1024);
+  if (hipMalloc((void **)&c->d_counters, nn * sizeof(unsigned int)) != hipSuccess)
+    return fail(c, GF_ENOMEM, "counter allocation failed");
+  GF_TRY(c, hipMemset(c->d_counters, 0, nn * sizeof(unsigned int)));
+  c->n_counters = nn;
+  return GF_OK;
+}
+
+bool smooth(int v) {
+  for (int p : {2, 3, 5})
+    while (v % p == 0) v /= p;
+  return v == 1;
+}
+
+// Smallest even 2^a 3^b 5^c >= m.
+int fft_side(int m) {
+  int L = std::max(m, 8);
+  if (L & 1) ++L;
+  while (!smooth(L)) L += 2;
+  return L;
+}
+
+FftPlan make_plan(int L, int tw_off) {
+  FftPlan p;
+  std::memset(&p, 0, sizeof(p));
+  p.L = L;
+  p.tw_off = tw_off;
+  std::vector<int> rad;
+  int v = L;
+  while (v % 8 == 0) { rad.push_back(8); v /= 8; }
+  if (v % 4 == 0) { rad.push_back(4); v /= 4; }
+  if (v % 2 == 0) { rad.push_back(2); v /= 2; }
+  while (v % 5 == 0) { rad.push_back(5); v /= 5; }
+  while (v % 3 == 0) { rad.push_back(3); v /= 3; }
+  p.nstages = (int)rad.size();
+  int ns = 1;
+  for (int s = 0; s < p.nstages; ++s) {
+    p.radix[s] = rad[s];
+    p.ns[s] = ns;
+    p.ns_magic[s] = magic_for((uint32_t)ns);
+    p.nb_magic[s] = magic_for((uint32_t)(L / rad[s]));
+    ns *= rad[s];
+  }
+  return p;
+}
+
+
+int padded_P(int nc) { return kNPC * nc + 1; }
+
+}  // namespace
+
+extern "C" {
+
+const char *gf_version(void) { return "libgf 0.1 (gfx950)"; }
+
+gf_status gf_create(gf_ctx **out, int device) {
+  if (!out) return GF_EINVAL;
+  *out = nullptr;
+  gf_ctx *c = new (std::nothrow) gf_ctx();
+  if (!c) return GF_ENOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return GF_EDEVICE;
+  }
+  std::vector<float2> tab = build_bn_table();
+  if (upload(&c->d_bn, tab) != hipSuccess) {
+    delete c;
+    return GF_EDEVICE;
+  }
+  if (hipHostMalloc((void **)&c->h_pinned, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess) {
+    dfree(c->d_bn);
+    delete c;
+    return GF_ENOMEM;
+  }
+  if (ensure_counters(c, 1024) != GF_OK) {
+    dfree(c->d_bn);
+    (void)hipHostFree(c->h_pinned);
+    delete c;
+    return GF_ENOMEM;
+  }
+  *out = c;
+  return GF_OK;
+}
+
+void gf_destroy(gf_ctx *c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  dfree(c->d_bn);
+  dfree(c->d_counters);
+  dfree(c->ws);
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  delete c;
+}
+
+gf_status gf_set_stream(gf_ctx *c, void *stream) {
+  if (!c) return GF_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return GF_OK;
+}
+
+const char *gf_last_error(const gf_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+gf_status gf_synchronize(gf_ctx *c) {
+  if (!c) return GF_EINVAL;
+  GF_TRY(c, hipStreamSynchronize(c->stream));
+  return GF_OK;
+}
+
+// ------------------------------------------------------------------ batches
+gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, const int32_t *K,
+                          const int32_t *nc, int shared, gf_batch **out) {
+  if (!c || !out || !H || !W || !K || !nc || n <= 0) return fail(c, GF_EINVAL, "gf_batch_create: bad argument");
+  *out = nullptr;
+  gf_batch *b = new (std::nothrow) gf_batch();
+  if (!b) return fail(c, GF_ENOMEM, "gf_batch_create: host allocation");
+  b->ctx = c;
+  b->n = n;
+  b->shared = shared != 0;
+  b->h_desc.resize(n);
+  int64_t pix = 0, pad = 0, psf = 0, par = 0, jac = 0;
+  for (int s = 0; s < n; ++s) {
+    if (H[s] <= 0 || W[s] <= 0 || K[s] <= 0 || (K[s] % 2) == 0 || K[s] > GF_MAX_K || nc[s] < 1 ||
+        nc[s] > GF_MAX_COMP || H[s] + K[s] - 1 > GF_MAX_FFT || W[s] + K[s] - 1 > GF_MAX_FFT) {
+      delete b;
+      return fail(c, GF_ESHAPE, "gf_batch_create: unsupported shape for stamp " + std::to_string(s));
+    }
+    if (b->shared && (H[s] != H[0] || W[s] != W[0] || K[s] != K[0] || nc[s] != nc[0])) {
+      delete b;
+      return fail(c, GF_ESHAPE, "gf_batch_create: shared-image batch needs identical stamps");
+    }
+    StampDesc &d = b->h_desc[s];
+    d.H = H[s];
+    d.W = W[s];
+    d.K = K[s];
+    d.ncomp = nc[s];
+    d.Mh = H[s] + K[s] - 1;
+    d.Mw = W[s] + K[s] - 1;
+    d.P = padded_P(nc[s]);
+    d.pad0 = 0;
+    d.pix = pix;
+    d.pad = pad;
+    d.par = par;
+    d.jac = jac;
+    d.img = b->shared ? 0 : pix;
+    d.psf = b->shared ? 0 : psf;
+    pix += (int64_t)d.H * d.W;
+    pad += (int64_t)d.Mh * d.Mw;
+    psf += (int64_t)d.K * d.K;
+    par += d.P;
+    jac += (int64_t)d.P * d.H * d.W;
+    b->max_nc = std::max(b->max_nc, d.ncomp);
+    b->max_P = std::max(b->max_P, d.P);
+    if (s > 0 && (d.H != H[0] || d.W != W[0] || d.K != K[0] || d.ncomp != nc[0])) b->uniform = false;
+  }
+  b->n_pix = pix;
+  b->n_pad = pad;
+  b->n_psf = b->shared ? (int64_t)K[0] * K[0] : psf;
+  b->n_par = par;
+  b->n_img = b->shared ? (int64_t)H[0] * W[0] : pix;
+  b->n_jac = jac;
+  for (int s = 0; s < n; ++s) {
+    const StampDesc &d = b->h_desc[s];
+    b->h_eval_first.push_back((int32_t)b->h_eval.size());
+    const int ne = (d.Mh * d.Mw + kEvalTile - 1) / kEvalTile;
+    for (int u = 0; u < ne; ++u) b->h_eval.push_back({s, u});
+    b->h_pix_first.push_back((int32_t)b->h_pix.size());
+    const int np = (d.H * d.W + kPixChunk - 1) / kPixChunk;
+    for (int u = 0; u < np; ++u) b->h_pix.push_back({s, u});
+    b->h_neq_first.push_back((int32_t)b->h_neq.size());
+    const int nq = (d.H * d.W + kNeqChunk - 1) / kNeqChunk;
+    for (int u = 0; u < nq; ++u) b->h_neq.push_back({s, u});
+  }
+  b->h_eval_first.push_back((int32_t)b->h_eval.size());
+  b->h_pix_first.push_back((int32_t)b->h_pix.size());
+  b->h_neq_first.push_back((int32_t)b->h_neq.size());
+  if (b->h_eval.size() > 0x7fffffffu) {
+    delete b;
+    return fail(c, GF_ESHAPE, "gf_batch_create: batch too large");
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&b->d_desc, b->h_desc);
+  if (e == hipSuccess) e = upload(&b->d_eval, b->h_eval);
+  if (e == hipSuccess) e = upload(&b->d_pix, b->h_pix);
+  if (e == hipSuccess) e = upload(&b->d_neq, b->h_neq);
+  if (e == hipSuccess) e = upload(&b->d_pix_first, b->h_pix_first);
+  if (e == hipSuccess) e = upload(&b->d_neq_first, b->h_neq_first);
+  if (e == hipSuccess) e = upload(&b->d_eval_first, b->h_eval_first);
+  if (e != hipSuccess) {
+    gf_batch_destroy(b);
+    return fail(c, GF_EDEVICE, std::string("gf_batch_create: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return GF_OK;
+}
+
+void gf_batch_destroy(gf_batch *b) {
+  if (!b) return;
+  dfree(b->d_desc);
+  dfree(b->d_eval);
+  dfree(b->d_pix);
+  dfree(b->d_neq);
+  dfree(b->d_pix_first);
+  dfree(b->d_neq_first);
+  dfree(b->d_eval_first);
+  delete b;
+}
+
+int gf_batch_count(const gf_batch *b) { return b ? b->n : 0; }
+
+gf_status gf_batch_sizes(const gf_batch *b, int64_t *n_pix, int64_t *n_pad, int64_t *n_psf, int64_t *n_par,
+                         int64_t *n_img, int64_t *n_jac) {
+  if (!b) return GF_EINVAL;
+  if (n_pix) *n_pix = b->n_pix;
+  if (n_pad) *n_pad = b->n_pad;
+  if (n_psf) *n_psf = b->n_psf;
+  if (n_par) *n_par = b->n_par;
+  if (n_img) *n_img = b->n_img;
+  if (n_jac) *n_jac = b->n_jac;
+  return GF_OK;
+}
+
+gf_status gf_batch_offsets(const gf_batch *b, int64_t *pix, int64_t *pad, int64_t *psf, int64_t *par, int64_t *img,
+                           int64_t *jac) {
+  if (!b) return GF_EINVAL;
+  for (int s = 0; s < b->n; ++s) {
+    const StampDesc &d = b->h_desc[s];
+    if (pix) pix[s] = d.pix;
+    if (pad) pad[s] = d.pad;
+    if (psf) psf[s] = d.psf;
+    if (par) par[s] = d.par;
+    if (img) img[s] = d.img;
+    if (jac) jac[s] = d.jac;
+  }
+  return GF_OK;
+}
+
+// ---------------------------------------------------------------------- PSF
+gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mode, gf_psf **out) {
+  if (!c || !b || !taps || !out || mode < GF_CONV_AUTO || mode > GF_CONV_DIRECT)
+    return fail(c, GF_EINVAL, "gf_psf_prepare: bad argument");
+  *out = nullptr;
+  gf_psf *p = new (std::nothrow) gf_psf();
+  if (!p) return fail(c, GF_ENOMEM, "gf_psf_prepare: host allocation");
+  p->ctx = c;
+  p->batch = b;
+  p->d_taps = taps;
+  const int n = b->n;
+  p->h_path.resize(n);
+  p->h_s1.assign(n, 0);
+  p->h_s2.assign(n, 0);
+  p->h_s1a.assign(n, 0);
+  p->h_s2a.assign(n, 0);
+  std::vector<int> plan_of_L(GF_MAX_FFT + 1, -1);
+  std::vector<float2> tw;
+  std::vector<int64_t> otf_tmp(n, 0), otf_off(n, 0);
+  std::vector<Work> otf_rows, otf_cols;
+  int64_t otf_tmp_n = 0;
+  for (int s = 0; s < n; ++s) {
+    const StampDesc &d = b->h_desc[s];
+    bool fft = mode == GF_CONV_FFT || (mode == GF_CONV_AUTO && d.K > 15);
+    if (mode == GF_CONV_DIRECT && d.K > kDirectMaxK) {
+      delete p;
+      return fail(c, GF_ESHAPE, "gf_psf_prepare: PSF too large for the direct path");
+    }
+    if (!fft && d.K > kDirectMaxK) fft = true;
+    PathDesc &pd = p->h_path[s];
+    pd.fft = fft ? 1 : 0;
+    pd.L = 0;
+    pd.plan = -1;
+    pd.pad0 = 0;
+    pd.otf = 0;
+    if (!fft) {
+      ++p->n_direct;
+      const int tx = (d.W + kDirectTW - 1) / kDirectTW, ty = (d.H + kDirectTH - 1) / kDirectTH;
+      for (int u = 0; u < tx * ty; ++u) p->h_direct.push_back({s, u});
+      const int ax = (d.Mw + kDirectTW - 1) / kDirectTW, ay = (d.Mh + kDirectTH - 1) / kDirectTH;
+      for (int u = 0; u < ax * ay; ++u) p->h_adirect.push_back({s, u});
+      continue;
+    }
+    ++p->n_fft;
+    const int L = fft_side(std::max(d.Mh, d.Mw));
+    if (L > GF_MAX_FFT) {
+      delete p;
+      return fail(c, GF_ESHAPE, "gf_psf_prepare: padded grid exceeds the largest FFT side");
+    }
+    if (plan_of_L[L] < 0) {
+      plan_of_L[L] = (int)p->h_plans.size();
+      p->h_plans.push_back(make_plan(L, (int)tw.size()));
+      for (int k = 0; k < L; ++k) {
+        const double a = -2.0 * M_PI * (double)k / (double)L;
+        tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+      }
+    }
+    p->max_L = std::max(p->max_L, L);
+    pd.L = L;
+    pd.plan = plan_of_L[L];
+    const int Lh = L / 2 + 1;
+    const int T = kFftCap / L, C = kFftCap / (L + 1);
+    const int cols = (Lh + C - 1) / C;
+    for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_rows.push_back({s, u});
+    for (int u = 0; u < cols; ++u) p->h_cols.push_back({s, u});
+    for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) p->h_irows.push_back({s, u});
+    for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) p->h_arows.push_back({s, u});
+    for (int u = 0; u < cols; ++u) p->h_acols.push_back({s, u});
+    for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_airows.push_back({s, u});
+    p->h_s1[s] = p->n_s1;
+    p->n_s1 += (int64_t)d.Mh * Lh;
+    p->h_s2[s] = p->n_s2;
+    p->n_s2 += (int64_t)d.H * Lh;
+    p->h_s1a[s] = p->n_s1a;
+    p->n_s1a += (int64_t)d.H * Lh;
+    p->h_s2a[s] = p->n_s2a;
+    p->n_s2a += (int64_t)d.Mh * Lh;
+    if (!b->shared || s == 0) {
+      otf_off[s] = p->n_otf;
+      pd.otf = p->n_otf;
+      p->n_otf += (int64_t)L * Lh;
+      otf_tmp[s] = otf_tmp_n;
+      otf_tmp_n += (int64_t)d.K * Lh;
+      for (int u = 0; u < (d.K + 2 * T - 1) / (2 * T); ++u) otf_rows.push_back({s, u});
+      for (int u = 0; u < cols; ++u) otf_cols.push_back({s, u});
+    } else {
+      pd.otf = 0;
+    }
+  }
+  hipError_t e = hipSuccess;
+  Work *d_orows = nullptr, *d_ocols = nullptr;
+  int64_t *d_otmp = nullptr, *d_ooff = nullptr;
+  if (e == hipSuccess) e = upload(&p->d_path, p->h_path);
+  if (e == hipSuccess) e = upload(&p->d_plans, p->h_plans);
+  if (e == hipSuccess) e = upload(&p->d_tw, tw);
+  if (e == hipSuccess) e = upload(&p->d_rows, p->h_rows);
+  if (e == hipSuccess) e = upload(&p->d_cols, p->h_cols);
+  if (e == hipSuccess) e = upload(&p->d_irows, p->h_irows);
+  if (e == hipSuccess) e = upload(&p->d_arows, p->h_arows);
+  if (e == hipSuccess) e = upload(&p->d_acols, p->h_acols);
+  if (e == hipSuccess) e = upload(&p->d_airows, p->h_airows);
+  if (e == hipSuccess) e = upload(&p->d_s1, p->h_s1);
+  if (e == hipSuccess) e = upload(&p->d_s2, p->h_s2);
+  if (e == hipSuccess) e = upload(&p->d_s1a, p->h_s1a);
+  if (e == hipSuccess) e = upload(&p->d_s2a, p->h_s2a);
+  if (e == hipSuccess) e = upload(&p->d_direct, p->h_direct);
+  if (e == hipSuccess) e = upload(&p->d_adirect, p->h_adirect);
+  if (e == hipSuccess) e = upload(&d_orows, otf_rows);
+  if (e == hipSuccess) e = upload(&d_ocols, otf_cols);
+  if (e == hipSuccess) e = upload(&d_otmp, otf_tmp);
+  if (e == hipSuccess) e = upload(&d_ooff, otf_off);
+  if (e == hipSuccess && p->n_otf > 0) e = hipMalloc((void **)&p->d_otf, p->n_otf * sizeof(float2));
+  if (e != hipSuccess) {
+    dfree(d_orows);
+    dfree(d_ocols);
+    dfree(d_otmp);
+    dfree(d_ooff);
+    gf_psf_destroy(p);
+    return fail(c, GF_EDEVICE, std::string("gf_psf_prepare: ") + hipGetErrorString(e));
+  }
+  gf_status st = GF_OK;
+  if (!otf_rows.empty()) {
+    st = ensure_ws(c, (size_t)otf_tmp_n * sizeof(float2) + 256);
+    if (st == GF_OK) {
+      e = launch_fft_otf(c->stream, b, p, taps, d_orows, (int)otf_rows.size(), d_ocols, (int)otf_cols.size(),
+                         d_otmp, (float2 *)c->ws, d_ooff);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) st = fail(c, GF_EDEVICE, std::string("gf_psf_prepare (OTF): ") + hipGetErrorString(e));
+    }
+  }
+  dfree(d_orows);
+  dfree(d_ocols);
+  dfree(d_otmp);
+  dfree(d_ooff);
+  if (st != GF_OK) {
+    gf_psf_destroy(p);
+    return st;
+  }
+  *out = p;
+  return GF_OK;
+}
+
+void gf_psf_destroy(gf_psf *p) {
+  if (!p) return;
+  dfree(p->d_path);
+  dfree(p->d_plans);
+  dfree(p->d_tw);
+  dfree(p->d_otf);
+  dfree(p->d_rows);
+  dfree(p->d_cols);
+  dfree(p->d_irows);
+  dfree(p->d_arows);
+  dfree(p->d_acols);
+  dfree(p->d_airows);
+  dfree(p->d_s1);
+  dfree(p->d_s2);
+  dfree(p->d_s1a);
+  dfree(p->d_s2a);
+  dfree(p->d_direct);
+  dfree(p->d_adirect);
+  delete p;
+}
+
+gf_status gf_psf_paths(const gf_psf *p, int32_t *uses_fft, int32_t *side) {
+  if (!p) return GF_EINVAL;
+  for (size_t s = 0; s < p->h_path.size(); ++s) {
+    if (uses_fft) uses_fft[s] = p->h_path[s].fft;
+    if (side) side[s] = p->h_path[s].L;
+  }
+  return GF_OK;
+}
+
+// ------------------------------------------------------------ steps 1-3
+gf_status gf_eval_model(gf_ctx *c, const gf_batch *b, const float *theta, int S, float *out) {
+  if (!c || !b || !theta || !out) return fail(c, GF_EINVAL, "gf_eval_model: null argument");
+  if (b->ctx != c) return fail(c, GF_EINVAL, "gf_eval_model: batch belongs to another context");
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_eval_model: oversample out of range");
+  GF_TRY(c, launch_eval(c->stream, b, theta, S, c->d_bn, out, nullptr));
+  return GF_OK;
+}
+
+static gf_status convolve(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *in, int n_ch, float *out,
+                          float2 *S1, float2 *S2, const int *mask) {
+  GF_TRY(c, launch_fft_conv(c->stream, b, p, in, n_ch, S1, S2, out, mask));
+  GF_TRY(c, launch_direct(c->stream, b, p, in, n_ch, out, false, mask));
+  return GF_OK;
+}
+
+gf_status gf_convolve_psf(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *in, int n_ch, float *out) {
+  if (!c || !b || !p || !in || !out) return fail(c, GF_EINVAL, "gf_convolve_psf: null argument");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_convolve_psf: PSF prepared for another batch");
+  if (n_ch < 1 || n_ch > 64) return fail(c, GF_EINVAL, "gf_convolve_psf: n_ch out of range");
+  Arena a;
+  a.take<float2>(p->n_s1 * n_ch);
+  a.take<float2>(p->n_s2 * n_ch);
+  gf_status st = ensure_ws(c, a.off);
+  if (st != GF_OK) return st;
+  a = Arena{(char *)c->ws, 0};
+  float2 *S1 = a.take<float2>(p->n_s1 * n_ch);
+  float2 *S2 = a.take<float2>(p->n_s2 * n_ch);
+  return convolve(c, b, p, in, n_ch, out, S1, S2, nullptr);
+}
+
+gf_status gf_chi2(gf_ctx *c, const gf_batch *b, const float *model, const float *theta, const float *data,
+                  const float *weight, float *resid, float *chi2) {
+  if (!c || !b || !model || !theta || !data || !weight || !chi2) return fail(c, GF_EINVAL, "gf_chi2: null argument");
+  gf_status st = ensure_counters(c, b->n);
+  if (st != GF_OK) return st;
+  Arena a;
+  a.take<float2>((int64_t)b->h_pix.size());
+  st = ensure_ws(c, a.off);
+  if (st != GF_OK) return st;
+  a = Arena{(char *)c->ws, 0};
+  float2 *part = a.take<float2>((int64_t)b->h_pix.size());
+  GF_TRY(c, launch_chi2(c->stream, b, model, theta, false, data, weight, resid, part, c->d_counters,
+                        (float2 *)chi2, nullptr));
+  return GF_OK;
+}
+
+static void likelihood_layout(const gf_batch *b, const gf_psf *p, Arena &a, float **mpad, float **mconv,
+                              float2 **S1, float2 **S2, float2 **part) {
+  *mpad = a.take<float>(b->n_pad);
+  *mconv = a.take<float>(b->n_pix);
+  *S1 = a.take<float2>(p->n_s1);
+  *S2 = a.take<float2>(p->n_s2);
+  *part = a.take<float2>((int64_t)b->h_pix.size());
+}
+
+int64_t gf_likelihood_workspace(const gf_batch *b, const gf_psf *p) {
+  if (!b || !p) return -1;
+  Arena a;
+  float *m1, *m2;
+  float2 *s1, *s2, *pt;
+  likelihood_layout(b, p, a, &m1, &m2, &s1, &s2, &pt);
+  return (int64_t)a.off;
+}
+
+gf_status gf_likelihood(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *theta, int S, const float *data,
+                        const float *weight, float *chi2, void *work) {
+  if (!c || !b || !p || !theta || !data || !weight || !chi2) return fail(c, GF_EINVAL, "gf_likelihood: null argument");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_likelihood: PSF prepared for another batch");
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_likelihood: oversample out of range");
+  gf_status st = ensure_counters(c, b->n);
+  if (st != GF_OK) return st;
+  if (!work) {
+    st = ensure_ws(c, (size_t)gf_likelihood_workspace(b, p));
+    if (st != GF_OK) return st;
+    work = c->ws;
+  }
+  Arena a{(char *)work, 0};
+  float *mpad, *mconv;
+  float2 *S1, *S2, *part;
+  likelihood_layout(b, p, a, &mpad, &mconv, &S1, &S2, &part);
+  GF_TRY(c, launch_eval(c->stream, b, theta, S, c->d_bn, mpad, nullptr));
+  st = convolve(c, b, p, mpad, 1, mconv, S1, S2, nullptr);
+  if (st != GF_OK) return st;
+  GF_TRY(c, launch_chi2(c->stream, b, mconv, theta, false, data, weight, nullptr, part, c->d_counters,
+                        (float2 *)chi2, nullptr));
+  return GF_OK;
+}
+
+gf_status gf_model(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *theta, int S, float *out,
+                   void *work) {
+  if (!c || !b || !p || !theta || !out) return fail(c, GF_EINVAL, "gf_model: null argument");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_model: PSF prepared for another batch");
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_model: oversample out of range");
+  if (!work) {
+    gf_status st = ensure_ws(c, (size_t)gf_likelihood_workspace(b, p));
+    if (st != GF_OK) return st;
+    work = c->ws;
+  }
+  Arena a{(char *)work, 0};
+  float *mpad, *mconv;
+  float2 *S1, *S2, *part;
+  likelihood_layout(b, p, a, &mpad, &mconv, &S1, &S2, &part);
+  GF_TRY(c, launch_eval(c->stream, b, theta, S, c->d_bn, mpad, nullptr));
+  gf_status st = convolve(c, b, p, mpad, 1, out, S1, S2, nullptr);
+  if (st != GF_OK) return st;
+  GF_TRY(c, launch_add_sky(c->stream, b, theta, out));
+  return GF_OK;
+}
+
+// -------------------------------------------------------------- derivatives
+gf_status gf_jacobian(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *theta, int S, int mode,
+                      const float *cot, const float *weight, float scale, float *out) {
+  if (!c || !b || !p || !theta || !out) return fail(c, GF_EINVAL, "gf_jacobian: null argument");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_jacobian: PSF prepared for another batch");
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_jacobian: oversample out of range");
+  if (mode == GF_JAC_FULL) {
+    const int nchan = kNPC * b->max_nc;
+    Arena a;
+    a.take<float>(b->n_pad * nchan);
+    a.take<float>(b->n_pix * nchan);
+    a.take<float2>(p->n_s1 * nchan);
+    a.take<float2>(p->n_s2 * nchan);
+    gf_status st = ensure_ws(c, a.off);
+    if (st != GF_OK) return st;
+    a = Arena{(char *)c->ws, 0};
+    float *cpad = a.take<float>(b->n_pad * nchan);
+    float *jc = a.take<float>(b->n_pix * nchan);
+    float2 *S1 = a.take<float2>(p->n_s1 * nchan);
+    float2 *S2 = a.take<float2>(p->n_s2 * nchan);
+    GF_TRY(c, launch_eval_jac(c->stream, b, theta, S, c->d_bn, cpad, nchan, nullptr));
+    st = convolve(c, b, p, cpad, nchan, jc, S1, S2, nullptr);
+    if (st != GF_OK) return st;
+    GF_TRY(c, launch_jac_assemble(c->stream, b, jc, nchan, out));
+    return GF_OK;
+  }
+  if (mode != GF_JAC_ADJOINT) return fail(c, GF_EINVAL, "gf_jacobian: unknown mode");
+  if (!cot) return fail(c, GF_EINVAL, "gf_jacobian: adjoint mode needs a cotangent image");
+  Arena a;
+  a.take<float>(b->n_pix);
+  a.take<float2>((int64_t)b->h_pix.size());
+  a.take<float2>(p->n_s1a);
+  a.take<float2>(p->n_s2a);
+  a.take<float>(b->n_pad);
+  a.take<float>((int64_t)b->h_eval.size() * (kMaxP - 1));
+  gf_status st = ensure_ws(c, a.off);
+  if (st != GF_OK) return st;
+  a = Arena{(char *)c->ws, 0};
+  float *cimg = a.take<float>(b->n_pix);
+  float2 *spart = a.take<float2>((int64_t)b->h_pix.size());
+  float2 *S1 = a.take<float2>(p->n_s1a);
+  float2 *S2 = a.take<float2>(p->n_s2a);
+  float *adj = a.take<float>(b->n_pad);
+  float *cpart = a.take<float>((int64_t)b->h_eval.size() * (kMaxP - 1));
+  GF_TRY(c, launch_cot_prep(c->stream, b, cot, weight, scale, cimg, spart));
+  GF_TRY(c, launch_fft_corr(c->stream, b, p, cimg, S1, S2, adj));
+  GF_TRY(c, launch_direct(c->stream, b, p, cimg, 1, adj, true, nullptr));
+  GF_TRY(c, launch_adjoint_contract(c->stream, b, theta, S, c->d_bn, adj, cpart));
+  GF_TRY(c, launch_adjoint_final(c->stream, b, b->d_eval_first, cpart, spart, out));
+  return GF_OK;
+}
+
+// ------------------------------------------------------------------ LM fit
+void gf_lm_opts_default(gf_lm_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_iter = 100;
+  o->oversample = 5;
+  o->lambda0 = 1e-3;
+  o->lambda_up = 10.0;
+  o->lambda_down = 10.0;
+  o->lambda_max = 1e10;
+  o->ftol = 1e-5;
+  o->xtol = 1e-10;
+  o->lo = nullptr;
+  o->hi = nullptr;
+  o->free_mask = nullptr;
+  o->poll_every = 4;
+  o->use_graph = 1;
+}
+
+namespace {
+
+struct LMBufs {
+  float *cpad, *jc, *mpad, *mconv, *npart;
+  float2 *S1, *S2, *chi2t, *cpart;
+  double *Ag, *theta_t;
+  LMState *st;
+  int *mjac, *mtrial, *cnt;
+};
+
+void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a, LMBufs &B) {
+  B.cpad = a.take<float>(b->n_pad * nchan);
+  B.jc = a.take<float>(b->n_pix * nchan);
+  B.S1 = a.take<float2>(p->n_s1 * nchan);
+  B.S2 = a.take<float2>(p->n_s2 * nchan);
+  B.npart = a.take<float>((int64_t)b->h_neq.size() * nacc);
+  B.Ag = a.take<double>((int64_t)b->n * (kMaxP * kMaxP + kMaxP));
+  B.theta_t = a.take<double>(b->n_par);
+  B.mpad = a.take<float>(b->n_pad);
+  B.mconv = a.take<float>(b->n_pix);
+  B.chi2t = a.take<float2>(b->n);
+  B.cpart = a.take<float2>((int64_t)b->h_pix.size());
+  B.st = a.take<LMState>(b->n);
+  B.mjac = a.take<int>(b->n);
+  B.mtrial = a.take<int>(b->n);
+  B.cnt = a.take<int>(16);
+}
+
+}  // namespace
+
+gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *data, const float *weight,
+                    double *theta, const gf_lm_opts *opts, gf_lm_result *res) {
+  if (!c || !b || !p || !data || !weight || !theta || !res) return fail(c, GF_EINVAL, "gf_fit_lm: null argument");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_fit_lm: PSF prepared for another batch");
+  gf_lm_opts o;
+  if (opts) o = *opts; else gf_lm_opts_default(&o);
+  if (o.max_iter < 0 || o.oversample < 1 || o.oversample > GF_MAX_OVERSAMPLE || !(o.lambda_up > 1.0) ||
+      !(o.lambda_down > 1.0) || !(o.lambda0 > 0.0))
+    return fail(c, GF_EINVAL, "gf_fit_lm: invalid options");
+  if (o.poll_every < 1) o.poll_every = 1;
+  if (b->max_nc > 2) return fail(c, GF_ESHAPE, "gf_fit_lm: at most two components per stamp");
+  const int nchan = kNPC * b->max_nc;
+  const int P = b->max_P;
+  const int nacc = P * (P + 1) / 2 + P + 1;
+  gf_status st = ensure_counters(c, b->n);
+  if (st != GF_OK) return st;
+  Arena a;
+  LMBufs B;
+  lm_layout(b, p, nchan, nacc, a, B);
+  st = ensure_ws(c, a.off);
+  if (st != GF_OK) return st;
+  a = Arena{(char *)c->ws, 0};
+  lm_layout(b, p, nchan, nacc, a, B);
+  const int S = o.oversample;
+
+  hipStream_t cs = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  GF_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  GF_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+    (void)hipEventDestroy(ev);
+  };
+  auto run = [&]() -> gf_status {
+    GF_TRY(c, hipEventRecord(ev, c->stream));
+    GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
+    // start point: clip, evaluate, chi2
+    GF_TRY(c, launch_lm_clip(cs, b->n_par, theta, o.lo, o.hi, B.theta_t));
+    GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr));
+    GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, nullptr));
+    GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, nullptr));
+    GF_TRY(c, launch_chi2(cs, b, B.mconv, B.theta_t, true, data, weight, nullptr, B.cpart, c->d_counters, B.chi2t,
+                          nullptr));
+    GF_TRY(c, launch_lm_init(cs, b, o.lambda0, B.chi2t, B.st, B.mjac, B.mtrial, B.cnt));
+    auto iteration = [&]() -> gf_status {
+      GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac));
+      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac));
+      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac));
+      GF_TRY(c, launch_lm_solve(cs, b, B.npart, nacc, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial));
+      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial));
+      GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial));
+      GF_TRY(c, launch_chi2(cs, b, B.mconv, B.theta_t, true, data, weight, nullptr, B.cpart, c->d_counters,
+                            B.chi2t, B.mtrial));
+      GF_TRY(c, launch_lm_update(cs, b, &o, B.chi2t, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
+      return GF_OK;
+    };
+    if (o.use_graph && o.max_iter > 0) {
+      GF_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      gf_status s2 = iteration();
+      hipError_t ce = hipStreamEndCapture(cs, &graph);
+      if (s2 != GF_OK) return s2;
+      GF_TRY(c, ce);
+      GF_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    for (int it = 0; it < o.max_iter; ++it) {
+      if (exec) {
+        GF_TRY(c, hipGraphLaunch(exec, cs));
+      } else {
+        gf_status s2 = iteration();
+        if (s2 != GF_OK) return s2;
+      }
+      if ((it + 1) % o.poll_every == 0 || it + 1 == o.max_iter) {
+        GF_TRY(c, hipMemcpyAsync(c->h_pinned, B.cnt, sizeof(int), hipMemcpyDeviceToHost, cs));
+        GF_TRY(c, hipStreamSynchronize(cs));
+        if (*(volatile int *)c->h_pinned == 0) break;
+      }
+    }
+    GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
+    GF_TRY(c, hipEventRecord(ev, cs));
+    GF_TRY(c, hipStreamWaitEvent(c->stream, ev, 0));
+    return GF_OK;
+  };
+  st = run();
+  cleanup();
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// gf_internal.h -- structures shared by the host side and the HIP kernels of
+// libgf (the MI355X galaxy-fitting hot path).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gf.h"
+
+namespace gf {
+
+constexpr int kNPC = GF_NPC;
+constexpr int kMaxComp = GF_MAX_COMP;
+constexpr int kMaxP = kNPC * kMaxComp + 1;
+constexpr int kThreads = 256;          // threads per workgroup for pixel kernels (4 wave64)
+constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one per thread)
+constexpr int kPixChunk = 2048;        // pixels per chi^2 workgroup (8 per thread)
+constexpr int kNeqChunk = 4096;        // pixels per normal-equation workgroup (16 per thread)
+constexpr int kFftCap = 2048;          // complex values per LDS ping-pong buffer
+constexpr int kFftMaxStages = 12;
+constexpr int kDirectTH = 16;          // direct convolution output tile rows
+constexpr int kDirectTW = 64;          // direct convolution output tile columns
+constexpr int kDirectMaxK = 41;        // largest PSF side on the direct path
+
+// b_n table: nodes n_i = kBnLo + i*h, i = -2 .. kBnNodes+1 (two guard nodes at
+// each end for the slope stencil); device copy holds (b_n, db_n/dn) per node.
+constexpr double kBnLo = 0.2;
+constexpr double kBnHi = 10.0;
+constexpr int kBnNodes = 4097;
+
+// Per-stamp geometry and flat-array offsets.
+struct StampDesc {
+  int32_t H, W, K, ncomp;
+  int32_t Mh, Mw, P, pad0;
+  int64_t pix, pad, psf, par, img, jac;
+};
+
+// Per-stamp convolution path chosen by gf_psf_prepare.
+struct PathDesc {
+  int32_t fft;    // 1 = FFT path, 0 = direct
+  int32_t L;      // FFT side (0 on the direct path)
+  int32_t plan;   // index into the plan table (-1 on the direct path)
+  int32_t pad0;
+  int64_t otf;    // offset of this stamp's OTF (complex elements)
+};
+
+// Mixed-radix Stockham plan for one FFT side L (radix-r stage s works on
+// sub-transforms of size ns[s]; nb = L / r butterflies per transform).
+struct FftPlan {
+  int32_t L, nstages, tw_off, pad0;
+  int32_t radix[kFftMaxStages];
+  int32_t ns[kFftMaxStages];
+  uint32_t ns_magic[kFftMaxStages];
+  uint32_t nb_magic[kFftMaxStages];
+};
+
+// Unit of work of a launch: (stamp, unit within the stamp).
+struct Work {
+  int32_t stamp;
+  int32_t unit;
+};
+
+// Per-component constants of the evaluation kernels (computed per workgroup).
+struct CompC {
+  int32_t ix, iy;    // integer part of the centre
+  float fx, fy;      // centre minus integer part
+  float cs, sn;      // cos phi, sin phi
+  float iq2;         // 1/q^2
+  float a1, a0;      // t = exp2(a1 * log2(R^2) + a0)
+  float b1;          // b_n * log2(e)
+  float lie;         // log2(Ie)
+  float ie, re, n, q, bn, dbn;
+};
+
+// LM per-stamp state (device).
+struct LMState {
+  double lambda;
+  double chi2;        // chi^2 at theta
+  double chi2_trial;
+  int32_t iters, nfev, njev, status, reason;
+  int32_t active;     // still iterating
+  int32_t need_jac;   // Jacobian at theta not yet formed
+  int32_t trial;      // a trial point was produced this iteration
+};
+
+// Fast division by a runtime constant d (x, d < 2^16): m = ceil(2^32/d), m = 0 for d = 1.
+inline uint32_t magic_for(uint32_t d) {
+  return d <= 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d);
+}
+
+}  // namespace gf
+
+// ---------------------------------------------------------------- host objects
+struct gf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  float2 *d_bn = nullptr;      // b_n table (kBnNodes entries)
+  unsigned int *d_counters = nullptr;  // self-resetting completion counters
+  int64_t n_counters = 0;
+  void *ws = nullptr;          // grow-only workspace
+  size_t ws_bytes = 0;
+  int *h_pinned = nullptr;     // pinned host word for LM polling
+};
+
+struct gf_batch {
+  gf_ctx *ctx = nullptr;
+  int n = 0;
+  bool shared = false;
+  std::vector<gf::StampDesc> h_desc;
+  gf::StampDesc *d_desc = nullptr;
+  int64_t n_pix = 0, n_pad = 0, n_psf = 0, n_par = 0, n_img = 0, n_jac = 0;
+  int max_nc = 0, max_P = 0;
+  // work lists
+  std::vector<gf::Work> h_eval, h_pix, h_neq;
+  gf::Work *d_eval = nullptr, *d_pix = nullptr, *d_neq = nullptr;
+  std::vector<int32_t> h_pix_first, h_neq_first, h_eval_first;   // first unit index per stamp (+ total)
+  int32_t *d_pix_first = nullptr, *d_neq_first = nullptr, *d_eval_first = nullptr;
+  bool uniform = true;
+};
+
+struct gf_psf {
+  gf_ctx *ctx = nullptr;
+  const gf_batch *batch = nullptr;
+  const float *d_taps = nullptr;
+  std::vector<gf::PathDesc> h_path;
+  gf::PathDesc *d_path = nullptr;
+  std::vector<gf::FftPlan> h_plans;
+  gf::FftPlan *d_plans = nullptr;
+  float2 *d_tw = nullptr;      // twiddles of every plan, concatenated
+  float2 *d_otf = nullptr;     // OTFs [L][L/2+1] per stamp (one if shared)
+  int64_t n_otf = 0;
+  int max_L = 0;
+  // FFT work lists: forward rows (padded rows), columns, inverse rows (output rows)
+  std::vector<gf::Work> h_rows, h_cols, h_irows, h_arows, h_acols, h_airows;
+  gf::Work *d_rows = nullptr, *d_cols = nullptr, *d_irows = nullptr;
+  gf::Work *d_arows = nullptr, *d_acols = nullptr, *d_airows = nullptr;  // adjoint (correlation) lists
+  std::vector<int64_t> h_s1, h_s2;   // per-stamp offsets (complex) into the two spectra buffers, per channel
+  int64_t n_s1 = 0, n_s2 = 0, n_s1a = 0, n_s2a = 0;
+  int64_t *d_s1 = nullptr, *d_s2 = nullptr, *d_s1a = nullptr, *d_s2a = nullptr;
+  std::vector<int64_t> h_s1a, h_s2a;
+  // direct path tiles
+  std::vector<gf::Work> h_direct, h_adirect;
+  gf::Work *d_direct = nullptr, *d_adirect = nullptr;
+  int n_fft = 0, n_direct = 0;
+};

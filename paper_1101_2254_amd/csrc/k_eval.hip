@@ -1,0 +1,333 @@
+// k_eval.hip -- step 1 of the fitting loop (model evaluation on the pixel
+// grid, a per-pixel transform: Barsdell et al., Sec. 2 step 1 and Sec. 3
+// item 1) and its derivatives, for gfx950.
+//
+// Each workgroup of 256 threads (four wave64) owns 256 consecutive pixels of
+// one stamp's padded grid, one pixel per thread, so every wave stores one
+// contiguous 256-byte segment.  The work is arithmetic: per sub-sample and
+// component one log2 and two exp2 (hardware v_log_f32 / v_exp_f32) plus about
+// nine FMA-class operations; the output is 4 bytes per pixel.
+//
+// Sub-sample offsets relative to the centre are formed as
+//     dx = (j - round(x0)) + ((s + 1/2)/S - 1/2 - (x0 - round(x0)))
+// so that dx keeps full relative precision near the centre, where the
+// Sersic cusp (R/Re)^(1/n) is steep, and is exactly zero when the centre
+// sits on a sub-sample.
+#include "gf_internal.h"
+
+namespace gf {
+
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Cubic Hermite lookup of (b_n, db_n/dn) in the FP32 table built on the host.
+__device__ __forceinline__ void bn_lookup(float n, const float2 *__restrict__ tab, float &b, float &db) {
+  const float h = (float)((kBnHi - kBnLo) / (kBnNodes - 1));
+  float u = (n - (float)kBnLo) / h;
+  u = fminf(fmaxf(u, 0.0f), (float)(kBnNodes - 1) - 1e-3f);
+  int i = (int)u;
+  float t = u - (float)i;
+  float2 p0 = tab[i], p1 = tab[i + 1];
+  float t2 = t * t, t3 = t2 * t;
+  float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
+  b = h00 * p0.x + h01 * p1.x + h * (h10 * p0.y + h11 * p1.y);
+  float d00 = 6.f * t2 - 6.f * t, d10 = 3.f * t2 - 4.f * t + 1.f, d11 = 3.f * t2 - 2.f * t;
+  db = (d00 * (p0.x - p1.x)) / h + d10 * p0.y + d11 * p1.y;
+}
+
+// Per-component constants from the parameter vector (float or double).
+template <typename TT>
+__device__ void comp_setup(const TT *__restrict__ t, const float2 *__restrict__ bn_tab, CompC &c) {
+  TT x0 = t[0], y0 = t[1];
+  TT rx = rint(x0), ry = rint(y0);
+  c.ix = (int)rx;
+  c.iy = (int)ry;
+  c.fx = (float)(x0 - rx);
+  c.fy = (float)(y0 - ry);
+  float ie = (float)t[2], re = (float)t[3], n = (float)t[4], q = (float)t[5], phi = (float)t[6];
+  float sn, cs;
+  sincosf(phi, &sn, &cs);
+  float bn, dbn;
+  bn_lookup(n, bn_tab, bn, dbn);
+  c.cs = cs;
+  c.sn = sn;
+  c.iq2 = 1.0f / (q * q);
+  c.a1 = 0.5f / n;
+  c.a0 = -log2f(re) / n;
+  c.b1 = bn * 1.4426950408889634f;
+  c.lie = log2f(ie);
+  c.ie = ie;
+  c.re = re;
+  c.n = n;
+  c.q = q;
+  c.bn = bn;
+  c.dbn = dbn;
+}
+
+template <int S>
+__device__ __forceinline__ float sub_off(int s) {
+  return ((float)s + 0.5f) / (float)S - 0.5f;
+}
+
+// ----------------------------------------------------------------- values
+template <typename TT, int S>
+__global__ __launch_bounds__(kThreads) void k_eval(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
+                                                   const TT *__restrict__ theta, const float2 *__restrict__ bn_tab,
+                                                   float *__restrict__ out, const int *__restrict__ mask) {
+  __shared__ CompC cc[kMaxComp];
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp;
+  if (mask && !mask[s]) return;
+  const StampDesc d = desc[s];
+  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, cc[threadIdx.x]);
+  __syncthreads();
+  const int npad = d.Mh * d.Mw;
+  const int p = w.unit * kEvalTile + (int)threadIdx.x;
+  if (p >= npad) return;
+  const int pi = p / d.Mw, pj = p - pi * d.Mw;
+  const int c0 = (d.K - 1) >> 1;
+  const int i = pi - c0, j = pj - c0;
+  float acc = 0.0f;
+  for (int k = 0; k < d.ncomp; ++k) {
+    const CompC C = cc[k];
+    const float jx = (float)(j - C.ix), iy = (float)(i - C.iy);
+    const float peak = C.lie + C.b1;
+    float ox[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) ox[a] = jx + (sub_off<S>(a) - C.fx);
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      const float dy = iy + (sub_off<S>(b) - C.fy);
+      const float dysn = dy * C.sn, dycs = dy * C.cs;
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        const float dx = ox[a];
+        const float xp = fmaf(dx, C.cs, dysn);
+        const float yp = fmaf(-dx, C.sn, dycs);
+        const float r2 = fmaf(C.iq2 * yp, yp, xp * xp);
+        const float t = fast_exp2(fmaf(fast_log2(r2), C.a1, C.a0));
+        acc += fast_exp2(fmaf(-C.b1, t, peak));
+      }
+    }
+  }
+  out[d.pad + p] = acc * (1.0f / (float)(S * S));
+}
+
+// -------------------------------------------------------------- derivatives
+// Point derivatives of one component at offset (dx, dy) from its centre,
+// accumulated into g[0..6] in parameter order [x0, y0, Ie, Re, n, q, phi];
+// the Ie slot holds I/Ie (the model is linear in Ie).  With u = R/Re,
+// t = u^(1/n), E = b_n t:  dI/dRe = I E/(n Re),  dI/dn = I (b'_n (1-t) + E ln u/n^2),
+// dI/d(R^2) = -I E/(2 n R^2).  At R = 0 exactly the 1/R^2 and ln u terms are 0.
+struct PointGrad {
+  float g[kNPC];
+};
+
+__device__ __forceinline__ void point_grad(const CompC &C, float dx, float dy, float *g) {
+  const float xp = fmaf(dx, C.cs, dy * C.sn);
+  const float yp = fmaf(-dx, C.sn, dy * C.cs);
+  const float r2 = fmaf(C.iq2 * yp, yp, xp * xp);
+  const float l2 = fast_log2(r2);
+  const float t = fast_exp2(fmaf(l2, C.a1, C.a0));
+  const float J = fast_exp2(C.b1 * (1.0f - t));        // I / Ie
+  const float I = J * C.ie;
+  const float E = C.bn * t;
+  const bool nz = r2 > 0.0f;
+  const float inv_n = 1.0f / C.n;
+  // ln u = (log2(R^2)/2 - log2 Re) ln 2 = (l2 * a1 + a0) * n * ln 2
+  const float lnu = fmaf(l2, C.a1, C.a0) * C.n * 0.69314718055994531f;
+  const float G = nz ? (-I * E * 0.5f * inv_n / r2) : 0.0f;   // dI / d(R^2)
+  g[0] += G * (-2.0f) * fmaf(xp, C.cs, -yp * C.sn * C.iq2);
+  g[1] += G * (-2.0f) * fmaf(xp, C.sn, yp * C.cs * C.iq2);
+  g[2] += J;
+  g[3] += I * E * inv_n / C.re;
+  g[4] += I * (C.dbn * (1.0f - t) + (nz ? E * lnu * inv_n * inv_n : 0.0f));
+  g[5] += G * (-2.0f) * yp * yp * C.iq2 / C.q;
+  g[6] += G * 2.0f * xp * yp * (1.0f - C.iq2);
+}
+
+// Writes 7 * ncomp channels per stamp on the padded grid: channel 7k + p is
+// the sub-sample mean of d I_k / d theta_{k,p} (p = 2 holds I_k / Ie_k).
+// Layout: out[jac_pad_off(s) + ch * Mh*Mw + pixel] with jac_pad_off = 7 * pad
+// offset scaled by the channel count of the batch (chan_stride channels per
+// stamp).
+template <typename TT, int S>
+__global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restrict__ desc,
+                                                       const Work *__restrict__ work, const TT *__restrict__ theta,
+                                                       const float2 *__restrict__ bn_tab, float *__restrict__ out,
+                                                       int chan_stride, const int *__restrict__ mask) {
+  __shared__ CompC cc[kMaxComp];
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp;
+  if (mask && !mask[s]) return;
+  const StampDesc d = desc[s];
+  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, cc[threadIdx.x]);
+  __syncthreads();
+  const int npad = d.Mh * d.Mw;
+  const int p = w.unit * kEvalTile + (int)threadIdx.x;
+  if (p >= npad) return;
+  const int pi = p / d.Mw, pj = p - pi * d.Mw;
+  const int c0 = (d.K - 1) >> 1;
+  const int i = pi - c0, j = pj - c0;
+  float *o = out + d.pad * (int64_t)chan_stride + p;
+  for (int k = 0; k < d.ncomp; ++k) {
+    const CompC C = cc[k];
+    const float jx = (float)(j - C.ix), iy = (float)(i - C.iy);
+    float g[kNPC] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int b = 0; b < S; ++b) {
+      const float dy = iy + (((float)b + 0.5f) / (float)S - 0.5f - C.fy);
+#pragma unroll
+      for (int a = 0; a < S; ++a) point_grad(C, jx + (sub_off<S>(a) - C.fx), dy, g);
+    }
+#pragma unroll
+    for (int q = 0; q < kNPC; ++q) o[(int64_t)(kNPC * k + q) * npad] = g[q] * (1.0f / (float)(S * S));
+  }
+}
+
+// Adjoint contraction on the padded grid: for every stamp,
+//   part[chunk][p] = sum over the chunk's pixels of adj[pixel] * dM/dtheta_p
+// (component parameters only; the sky term is added by the caller).
+// adj holds one padded grid per stamp at desc.pad.
+template <typename TT, int S>
+__global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *__restrict__ desc,
+                                                               const Work *__restrict__ work,
+                                                               const TT *__restrict__ theta,
+                                                               const float2 *__restrict__ bn_tab,
+                                                               const float *__restrict__ adj,
+                                                               float *__restrict__ part) {
+  __shared__ CompC cc[kMaxComp];
+  __shared__ float red[kThreads / 64][kMaxP];
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp;
+  const StampDesc d = desc[s];
+  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, cc[threadIdx.x]);
+  __syncthreads();
+  const int npad = d.Mh * d.Mw;
+  const int p = w.unit * kEvalTile + (int)threadIdx.x;
+  const int nq = kNPC * d.ncomp;
+  float acc[kMaxP - 1];
+#pragma unroll
+  for (int q = 0; q < kMaxP - 1; ++q) acc[q] = 0.0f;
+  if (p < npad) {
+    const int pi = p / d.Mw, pj = p - pi * d.Mw;
+    const int c0 = (d.K - 1) >> 1;
+    const int i = pi - c0, j = pj - c0;
+    const float a = adj[d.pad + p] * (1.0f / (float)(S * S));
+    for (int k = 0; k < d.ncomp; ++k) {
+      const CompC C = cc[k];
+      const float jx = (float)(j - C.ix), iy = (float)(i - C.iy);
+      float g[kNPC] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+      for (int b = 0; b < S; ++b) {
+        const float dy = iy + (((float)b + 0.5f) / (float)S - 0.5f - C.fy);
+#pragma unroll
+        for (int aa = 0; aa < S; ++aa) point_grad(C, jx + (sub_off<S>(aa) - C.fx), dy, g);
+      }
+      // Ie slot: dI/dIe = I/Ie
+#pragma unroll
+      for (int q = 0; q < kNPC; ++q) {
+#pragma unroll
+        for (int kk = 0; kk < kMaxComp; ++kk)
+          if (kk == k) acc[kNPC * kk + q] = a * g[q];
+      }
+    }
+  }
+  // block reduction in a fixed order: wave shuffles, then the four waves
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kMaxP - 1; ++q) {
+    float v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wv][q] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nq) {
+    float v = 0.0f;
+#pragma unroll
+    for (int ww = 0; ww < kThreads / 64; ++ww) v += red[ww][threadIdx.x];
+    part[(int64_t)blockIdx.x * (kMaxP - 1) + threadIdx.x] = v;
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+template <typename TT>
+static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float2 *bn,
+                                float *out, const int *mask) {
+  dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
+  if (grid.x == 0) return hipSuccess;
+  switch (S) {
+#define GF_EVAL_CASE(SS)                                                                          \
+  case SS:                                                                                        \
+    hipLaunchKernelGGL((k_eval<TT, SS>), grid, block, 0, st, b->d_desc, b->d_eval, theta, bn, out, mask); \
+    break;
+    GF_EVAL_CASE(1) GF_EVAL_CASE(2) GF_EVAL_CASE(3) GF_EVAL_CASE(4)
+    GF_EVAL_CASE(5) GF_EVAL_CASE(6) GF_EVAL_CASE(7) GF_EVAL_CASE(8)
+#undef GF_EVAL_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, int S, const float2 *bn, float *out,
+                       const int *mask) {
+  return launch_eval_t<float>(st, b, theta, S, bn, out, mask);
+}
+
+hipError_t launch_eval_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float2 *bn,
+                         float *out, const int *mask) {
+  return launch_eval_t<double>(st, b, theta, S, bn, out, mask);
+}
+
+template <typename TT>
+static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float2 *bn,
+                                    float *out, int chan_stride, const int *mask) {
+  dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
+  if (grid.x == 0) return hipSuccess;
+  switch (S) {
+#define GF_EVALJ_CASE(SS)                                                                                   \
+  case SS:                                                                                                  \
+    hipLaunchKernelGGL((k_eval_jac<TT, SS>), grid, block, 0, st, b->d_desc, b->d_eval, theta, bn, out,      \
+                       chan_stride, mask);                                                                  \
+    break;
+    GF_EVALJ_CASE(1) GF_EVALJ_CASE(2) GF_EVALJ_CASE(3) GF_EVALJ_CASE(4)
+    GF_EVALJ_CASE(5) GF_EVALJ_CASE(6) GF_EVALJ_CASE(7) GF_EVALJ_CASE(8)
+#undef GF_EVALJ_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_jac(hipStream_t st, const gf_batch *b, const float *theta, int S, const float2 *bn,
+                           float *out, int chan_stride, const int *mask) {
+  return launch_eval_jac_t<float>(st, b, theta, S, bn, out, chan_stride, mask);
+}
+
+hipError_t launch_eval_jac_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float2 *bn,
+                             float *out, int chan_stride, const int *mask) {
+  return launch_eval_jac_t<double>(st, b, theta, S, bn, out, chan_stride, mask);
+}
+
+hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const float *theta, int S, const float2 *bn,
+                                   const float *adj, float *part) {
+  dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
+  if (grid.x == 0) return hipSuccess;
+  switch (S) {
+#define GF_ADJ_CASE(SS)                                                                                        \
+  case SS:                                                                                                     \
+    hipLaunchKernelGGL((k_adjoint_contract<float, SS>), grid, block, 0, st, b->d_desc, b->d_eval, theta, bn, adj, \
+                       part);                                                                                  \
+    break;
+    GF_ADJ_CASE(1) GF_ADJ_CASE(2) GF_ADJ_CASE(3) GF_ADJ_CASE(4)
+    GF_ADJ_CASE(5) GF_ADJ_CASE(6) GF_ADJ_CASE(7) GF_ADJ_CASE(8)
+#undef GF_ADJ_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gf

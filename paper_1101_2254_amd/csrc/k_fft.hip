@@ -1,0 +1,427 @@
+// k_fft.hip -- step 2 of the fitting loop in Fourier space (Barsdell et al.,
+// Sec. 3 item 2: FFT plus a pointwise transform), hand-written for gfx950.
+//
+// The linear convolution of an Mh x Mw padded grid with a K x K PSF is taken
+// from the circular convolution on an L x L grid with L >= max(Mh, Mw): the
+// kept "valid" rows and columns K-1 .. M-1 never see a wrapped tap.  Three
+// launches per convolution, each a batch of independent 1-D transforms held in
+// LDS (two ping-pong buffers of kFftCap complex values per workgroup):
+//   rows   : two real rows per complex transform (z = a + i b), length L,
+//            split into the half spectra A, B (L/2+1 bins) -> spectra S1[row][k]
+//   columns: per bin k, forward transform over rows, times the OTF (or its
+//            conjugate for the adjoint correlation), inverse transform, keep
+//            the wanted rows -> S2[row][k]
+//   irows  : rebuild two Hermitian spectra as Z = A + i B, inverse transform,
+//            real part -> first row, imaginary part -> second row, crop.
+// The 1/L^2 of the inverse transform is folded into the OTF.
+//
+// Transforms are mixed-radix Stockham passes (radix 2, 3, 4, 5, 8) with FP32
+// twiddles that the host computes in FP64.  The column kernel strides its LDS
+// transforms by L+1 complex values so the transposing loads and stores of
+// neighbouring bins fall in different LDS banks.
+#include "gf_internal.h"
+
+namespace gf {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 mul_i(float2 a) { return make_float2(-a.y, a.x); }   // i a
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // -i a
+
+__device__ __forceinline__ int fdiv(int x, uint32_t m) { return m ? (int)__umulhi((uint32_t)x, m) : x; }
+
+// ------------------------------------------------------------ small DFTs
+// Forward: X_k = sum_n x_n exp(-2 pi i n k / R); inverse uses +i.
+template <bool INV>
+__device__ __forceinline__ void dft2(float2 *v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2 *v) {
+  const float s3 = 0.86602540378443865f;
+  float2 a = v[0], b = v[1], c = v[2];
+  float2 t1 = cadd(b, c);
+  float2 t2 = make_float2(fmaf(-0.5f, t1.x, a.x), fmaf(-0.5f, t1.y, a.y));
+  float2 m = mul_i(cscale(csub(b, c), s3));
+  v[0] = cadd(a, t1);
+  v[1] = INV ? cadd(t2, m) : csub(t2, m);
+  v[2] = INV ? csub(t2, m) : cadd(t2, m);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 *v) {
+  float2 a = v[0], b = v[1], c = v[2], d = v[3];
+  float2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = csub(b, d);
+  float2 m = mul_i(d1);
+  v[0] = cadd(s0, s1);
+  v[2] = csub(s0, s1);
+  v[1] = INV ? cadd(d0, m) : csub(d0, m);
+  v[3] = INV ? csub(d0, m) : cadd(d0, m);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft5(float2 *v) {
+  const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+  const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+  float2 a = v[0];
+  float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  float2 p1 = make_float2(a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y);
+  float2 p2 = make_float2(a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y);
+  float2 q1 = mul_i(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+  float2 q2 = mul_i(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+  v[0] = make_float2(a.x + t1.x + t2.x, a.y + t1.y + t2.y);
+  v[1] = INV ? cadd(p1, q1) : csub(p1, q1);
+  v[4] = INV ? csub(p1, q1) : cadd(p1, q1);
+  v[2] = INV ? cadd(p2, q2) : csub(p2, q2);
+  v[3] = INV ? csub(p2, q2) : cadd(p2, q2);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 *v) {
+  const float r = 0.70710678118654752f;
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  // o[k] *= w^k, w = exp(-+ i pi/4)
+  float2 o1 = INV ? make_float2(r * (o[1].x - o[1].y), r * (o[1].x + o[1].y))
+                  : make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));
+  float2 o2 = INV ? mul_i(o[2]) : mul_mi(o[2]);
+  float2 o3 = INV ? make_float2(-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y))
+                  : make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 *v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else if constexpr (R == 5) dft5<INV>(v);
+  else dft8<INV>(v);
+}
+
+// One Stockham pass over T transforms of length L (stride Ls) from `in` to
+// `out`.  Butterfly j of a transform reads x[j + r L/R], twiddles input r by
+// W_{Ns R}^{r k} (k = j mod Ns), does a radix-R DFT and writes to
+// (j div Ns) Ns R + k + r Ns.
+template <int R, bool INV>
+__device__ __forceinline__ void stockham_pass(const float2 *__restrict__ in, float2 *__restrict__ out, int T, int L,
+                                              int Ls, int Ns, uint32_t ns_m, uint32_t nb_m,
+                                              const float2 *__restrict__ tw) {
+  const int nb = L / R;
+  const int total = T * nb;
+  const int twstep = L / (Ns * R);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int t = fdiv(idx, nb_m);
+    const int j = idx - t * nb;
+    const int jd = fdiv(j, ns_m);
+    const int k = j - jd * Ns;
+    const float2 *src = in + t * Ls + j;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[r * nb];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[r * k * twstep];
+        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      }
+    }
+    dft<R, INV>(v);
+    float2 *dst = out + t * Ls + jd * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r * Ns] = v[r];
+  }
+}
+
+// Full transform; returns the buffer that holds the result.
+template <bool INV>
+__device__ float2 *lds_fft(float2 *a, float2 *b, int T, int Ls, const FftPlan &pl, const float2 *tw) {
+  const int L = pl.L;
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int R = pl.radix[s], Ns = pl.ns[s];
+    const uint32_t nsm = pl.ns_magic[s], nbm = pl.nb_magic[s];
+    switch (R) {
+      case 2: stockham_pass<2, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 3: stockham_pass<3, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 4: stockham_pass<4, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 5: stockham_pass<5, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
+      default: stockham_pass<8, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
+    }
+    __syncthreads();
+    float2 *tmp = a;
+    a = b;
+    b = tmp;
+  }
+  return a;
+}
+
+// Geometry of one launch mode.
+enum { MODE_CONV = 0, MODE_CORR = 1, MODE_OTF = 2 };
+
+struct Geo {
+  int in_rows, in_cols, in_col0;   // row pass input (cols placed at in_col0 on the L grid)
+  int col_row0;                    // rows of S1 placed at this row of the L grid
+  int out_row0, out_rows;          // column pass keeps rows out_row0 .. +out_rows (all L for OTF)
+  int out_col0, out_cols;          // inverse row pass keeps these columns
+};
+
+__device__ __forceinline__ Geo geo_of(int mode, const StampDesc &d, int L) {
+  Geo g;
+  const int km1 = d.K - 1;
+  if (mode == MODE_CONV) {
+    g.in_rows = d.Mh; g.in_cols = d.Mw; g.in_col0 = 0; g.col_row0 = 0;
+    g.out_row0 = km1; g.out_rows = d.H; g.out_col0 = km1; g.out_cols = d.W;
+  } else if (mode == MODE_CORR) {
+    g.in_rows = d.H; g.in_cols = d.W; g.in_col0 = km1; g.col_row0 = km1;
+    g.out_row0 = 0; g.out_rows = d.Mh; g.out_col0 = 0; g.out_cols = d.Mw;
+  } else {
+    g.in_rows = d.K; g.in_cols = d.K; g.in_col0 = 0; g.col_row0 = 0;
+    g.out_row0 = 0; g.out_rows = L; g.out_col0 = 0; g.out_cols = 0;
+  }
+  return g;
+}
+
+// ------------------------------------------------------------ row pass
+// in: real images; stamp s channel ch starts at in_base(s) * n_ch + ch * plane.
+// S1: spectra; stamp s channel ch starts at s1_off[s] * n_ch + ch * in_rows * (L/2+1).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restrict__ desc,
+                                                       const PathDesc *__restrict__ path,
+                                                       const FftPlan *__restrict__ plans,
+                                                       const float2 *__restrict__ tw_all,
+                                                       const Work *__restrict__ work, const float *__restrict__ in,
+                                                       int n_ch, const int64_t *__restrict__ s1_off,
+                                                       float2 *__restrict__ S1, const int *__restrict__ mask) {
+  extern __shared__ float2 lds[];
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp, ch = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const StampDesc d = desc[s];
+  const PathDesc pd = path[s];
+  const FftPlan &pl = plans[pd.plan];
+  const int L = pl.L, Lh = L / 2 + 1;
+  const Geo g = geo_of(MODE, d, L);
+  const int T = kFftCap / L;
+  float2 *bufA = lds, *bufB = lds + kFftCap, *tw = lds + 2 * kFftCap;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
+
+  int64_t in_base, plane;
+  if (MODE == MODE_CONV) { in_base = d.pad; plane = (int64_t)d.Mh * d.Mw; }
+  else if (MODE == MODE_CORR) { in_base = d.pix; plane = (int64_t)d.H * d.W; }
+  else { in_base = d.psf; plane = (int64_t)d.K * d.K; }
+  const float *src = in + in_base * n_ch + ch * plane;
+  const int r0 = w.unit * 2 * T;
+  for (int idx = threadIdx.x; idx < T * L; idx += blockDim.x) {
+    const int t = idx / L, n = idx - t * L;
+    const int ra = r0 + 2 * t, rb = ra + 1;
+    const int c = n - g.in_col0;
+    const bool cin = c >= 0 && c < g.in_cols;
+    const float a = (cin && ra < g.in_rows) ? src[(int64_t)ra * g.in_cols + c] : 0.0f;
+    const float b = (cin && rb < g.in_rows) ? src[(int64_t)rb * g.in_cols + c] : 0.0f;
+    bufA[t * L + n] = make_float2(a, b);
+  }
+  __syncthreads();
+  const float2 *X = lds_fft<false>(bufA, bufB, T, L, pl, tw);
+  float2 *dst = S1 + s1_off[s] * n_ch + (int64_t)ch * g.in_rows * Lh;
+  for (int idx = threadIdx.x; idx < T * Lh; idx += blockDim.x) {
+    const int t = idx / Lh, k = idx - t * Lh;
+    const int ra = r0 + 2 * t, rb = ra + 1;
+    if (ra >= g.in_rows) continue;
+    const float2 zk = X[t * L + k];
+    const float2 zc = cconj(X[t * L + (k == 0 ? 0 : L - k)]);
+    const float2 A = cscale(cadd(zk, zc), 0.5f);
+    const float2 B = cscale(mul_mi(csub(zk, zc)), 0.5f);
+    dst[(int64_t)ra * Lh + k] = A;
+    if (rb < g.in_rows) dst[(int64_t)rb * Lh + k] = B;
+  }
+}
+
+// ---------------------------------------------------------- column pass
+// S1 rows 0 .. in_rows-1 sit at L-grid rows col_row0 ..; MODE_CONV multiplies
+// by the OTF, MODE_CORR by its conjugate, MODE_OTF only transforms forward and
+// scales by 1/L^2 (writing the OTF itself).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restrict__ desc,
+                                                       const PathDesc *__restrict__ path,
+                                                       const FftPlan *__restrict__ plans,
+                                                       const float2 *__restrict__ tw_all,
+                                                       const Work *__restrict__ work, int n_ch,
+                                                       const int64_t *__restrict__ s1_off,
+                                                       const float2 *__restrict__ S1,
+                                                       const float2 *__restrict__ otf,
+                                                       const int64_t *__restrict__ s2_off, float2 *__restrict__ S2,
+                                                       const int *__restrict__ mask) {
+  extern __shared__ float2 lds[];
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp, ch = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const StampDesc d = desc[s];
+  const PathDesc pd = path[s];
+  const FftPlan &pl = plans[pd.plan];
+  const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
+  const Geo g = geo_of(MODE, d, L);
+  const int C = kFftCap / Ls;
+  const int k0 = w.unit * C;
+  const int nc = min(C, Lh - k0);
+  float2 *bufA = lds, *bufB = lds + kFftCap, *tw = lds + 2 * kFftCap;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
+
+  const float2 *src = S1 + s1_off[s] * n_ch + (int64_t)ch * g.in_rows * Lh;
+  for (int idx = threadIdx.x; idx < C * L; idx += blockDim.x) {
+    const int y = idx / C, c = idx - y * C;
+    const int r = y - g.col_row0;
+    float2 v = make_float2(0.f, 0.f);
+    if (c < nc && r >= 0 && r < g.in_rows) v = src[(int64_t)r * Lh + k0 + c];
+    bufA[c * Ls + y] = v;
+  }
+  __syncthreads();
+  float2 *X = lds_fft<false>(bufA, bufB, C, Ls, pl, tw);
+  float2 *Y = (X == bufA) ? bufB : bufA;
+  if (MODE == MODE_OTF) {
+    const float sc = 1.0f / ((float)L * (float)L);
+    float2 *dst = S2 + s2_off[s];
+    for (int idx = threadIdx.x; idx < C * L; idx += blockDim.x) {
+      const int y = idx / C, c = idx - y * C;
+      if (c < nc) dst[(int64_t)y * Lh + k0 + c] = cscale(X[c * Ls + y], sc);
+    }
+    return;
+  }
+  const float2 *H = otf + pd.otf;
+  for (int idx = threadIdx.x; idx < C * L; idx += blockDim.x) {
+    const int y = idx / C, c = idx - y * C;
+    if (c < nc) {
+      const float2 h = H[(int64_t)y * Lh + k0 + c];
+      X[c * Ls + y] = (MODE == MODE_CORR) ? cmulc(X[c * Ls + y], h) : cmul(X[c * Ls + y], h);
+    }
+  }
+  __syncthreads();
+  X = lds_fft<true>(X, Y, C, Ls, pl, tw);
+  float2 *dst = S2 + s2_off[s] * n_ch + (int64_t)ch * g.out_rows * Lh;
+  for (int idx = threadIdx.x; idx < C * g.out_rows; idx += blockDim.x) {
+    const int y = idx / C, c = idx - y * C;
+    if (c < nc) dst[(int64_t)y * Lh + k0 + c] = X[c * Ls + g.out_row0 + y];
+  }
+}
+
+// ------------------------------------------------------ inverse row pass
+// out: stamp s channel ch starts at out_base(s) * n_ch + ch * out_rows * out_cols.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restrict__ desc,
+                                                        const PathDesc *__restrict__ path,
+                                                        const FftPlan *__restrict__ plans,
+                                                        const float2 *__restrict__ tw_all,
+                                                        const Work *__restrict__ work, int n_ch,
+                                                        const int64_t *__restrict__ s2_off,
+                                                        const float2 *__restrict__ S2, float *__restrict__ out,
+                                                        const int *__restrict__ mask) {
+  extern __shared__ float2 lds[];
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp, ch = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const StampDesc d = desc[s];
+  const PathDesc pd = path[s];
+  const FftPlan &pl = plans[pd.plan];
+  const int L = pl.L, Lh = L / 2 + 1;
+  const Geo g = geo_of(MODE, d, L);
+  const int T = kFftCap / L;
+  float2 *bufA = lds, *bufB = lds + kFftCap, *tw = lds + 2 * kFftCap;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
+
+  const float2 *src = S2 + s2_off[s] * n_ch + (int64_t)ch * g.out_rows * Lh;
+  const int r0 = w.unit * 2 * T;
+  for (int idx = threadIdx.x; idx < T * L; idx += blockDim.x) {
+    const int t = idx / L, k = idx - t * L;
+    const int ra = r0 + 2 * t, rb = ra + 1;
+    const bool neg = k > L / 2;
+    const int kk = neg ? L - k : k;
+    float2 A = (ra < g.out_rows) ? src[(int64_t)ra * Lh + kk] : make_float2(0.f, 0.f);
+    float2 B = (rb < g.out_rows) ? src[(int64_t)rb * Lh + kk] : make_float2(0.f, 0.f);
+    if (neg) {
+      A = cconj(A);
+      B = cconj(B);
+    }
+    bufA[t * L + k] = cadd(A, mul_i(B));
+  }
+  __syncthreads();
+  const float2 *X = lds_fft<true>(bufA, bufB, T, L, pl, tw);
+  int64_t out_base = (MODE == MODE_CONV) ? d.pix : d.pad;
+  float *dst = out + out_base * n_ch + (int64_t)ch * g.out_rows * g.out_cols;
+  for (int idx = threadIdx.x; idx < T * g.out_cols; idx += blockDim.x) {
+    const int t = idx / g.out_cols, x = idx - t * g.out_cols;
+    const int ra = r0 + 2 * t, rb = ra + 1;
+    const float2 v = X[t * L + g.out_col0 + x];
+    if (ra < g.out_rows) dst[(int64_t)ra * g.out_cols + x] = v.x;
+    if (rb < g.out_rows) dst[(int64_t)rb * g.out_cols + x] = v.y;
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+static size_t fft_lds_bytes(int max_L) { return (size_t)(2 * kFftCap + max_L) * sizeof(float2); }
+
+hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
+                           float2 *S1, float2 *S2, float *out, const int *mask) {
+  if (p->h_rows.empty()) return hipSuccess;
+  const size_t lds = fft_lds_bytes(p->max_L);
+  dim3 blk(kThreads);
+  hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)p->h_rows.size(), n_ch), blk, lds, st, b->d_desc,
+                     p->d_path, p->d_plans, p->d_tw, p->d_rows, in, n_ch, p->d_s1, S1, mask);
+  hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)p->h_cols.size(), n_ch), blk, lds, st, b->d_desc,
+                     p->d_path, p->d_plans, p->d_tw, p->d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask);
+  hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)p->h_irows.size(), n_ch), blk, lds, st, b->d_desc,
+                     p->d_path, p->d_plans, p->d_tw, p->d_irows, n_ch, p->d_s2, S2, out, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_corr(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, float2 *S1,
+                           float2 *S2, float *out) {
+  if (p->h_arows.empty()) return hipSuccess;
+  const size_t lds = fft_lds_bytes(p->max_L);
+  dim3 blk(kThreads);
+  hipLaunchKernelGGL((k_fft_rows<MODE_CORR>), dim3((unsigned)p->h_arows.size(), 1), blk, lds, st, b->d_desc,
+                     p->d_path, p->d_plans, p->d_tw, p->d_arows, in, 1, p->d_s1a, S1, (const int *)nullptr);
+  hipLaunchKernelGGL((k_fft_cols<MODE_CORR>), dim3((unsigned)p->h_acols.size(), 1), blk, lds, st, b->d_desc,
+                     p->d_path, p->d_plans, p->d_tw, p->d_acols, 1, p->d_s1a, S1, p->d_otf, p->d_s2a, S2,
+                     (const int *)nullptr);
+  hipLaunchKernelGGL((k_fft_irows<MODE_CORR>), dim3((unsigned)p->h_airows.size(), 1), blk, lds, st, b->d_desc,
+                     p->d_path, p->d_plans, p->d_tw, p->d_airows, 1, p->d_s2a, S2, out, (const int *)nullptr);
+  return hipGetLastError();
+}
+
+// OTF of every FFT stamp: rows of the K x K taps, then forward columns over
+// all L rows scaled by 1/L^2.  S1 holds K rows of spectra per stamp.
+hipError_t launch_fft_otf(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *taps,
+                          const gf::Work *rows, int n_rows, const gf::Work *cols, int n_cols, const int64_t *s1_off,
+                          float2 *S1, const int64_t *otf_off) {
+  if (n_rows == 0) return hipSuccess;
+  const size_t lds = fft_lds_bytes(p->max_L);
+  dim3 blk(kThreads);
+  hipLaunchKernelGGL((k_fft_rows<MODE_OTF>), dim3((unsigned)n_rows, 1), blk, lds, st, b->d_desc, p->d_path,
+                     p->d_plans, p->d_tw, rows, taps, 1, s1_off, S1, (const int *)nullptr);
+  hipLaunchKernelGGL((k_fft_cols<MODE_OTF>), dim3((unsigned)n_cols, 1), blk, lds, st, b->d_desc, p->d_path,
+                     p->d_plans, p->d_tw, cols, 1, s1_off, S1, (const float2 *)nullptr, otf_off, p->d_otf,
+                     (const int *)nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace gf

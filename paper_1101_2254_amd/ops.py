@@ -1,0 +1,282 @@
+"""Tensor-level API over libgf (PyTorch-ROCm provides device memory and streams).
+
+Every function validates shapes and dtypes on the host, hands raw device
+pointers and sizes to the C ABI of ``include/gf.h`` on the current torch
+stream, and returns torch tensors.  No step of the method runs in torch.
+
+Parameter vectors: ``[x0, y0, Ie, Re, n, q, phi] * ncomp + [sky]`` per stamp,
+flattened over the batch (``Batch.offsets['par']``).  Images are flattened
+row-major per stamp at ``Batch.offsets['pix']`` (model, residual),
+``['pad']`` (padded grids), ``['img']`` (data, weight) and ``['psf']``.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+GF_CONV_AUTO, GF_CONV_FFT, GF_CONV_DIRECT = L.GF_CONV_AUTO, L.GF_CONV_FFT, L.GF_CONV_DIRECT
+
+LM_RESULT_DTYPE = np.dtype([("chi2", "<f8"), ("lambda", "<f8"), ("iters", "<i4"), ("nfev", "<i4"),
+                            ("njev", "<i4"), ("status", "<i4"), ("reason", "<i4"), ("pad", "<i4")])
+
+
+def _ptr(t):
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _need(t, dtype, n, name):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    return t
+
+
+class Context:
+    """A libgf context bound to one HIP device; work goes on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        self.ptr = L.gf_create(device)
+
+    def bind_stream(self):
+        L.gf_set_stream(self.ptr, torch.cuda.current_stream(self.device).cuda_stream)
+
+    def synchronize(self):
+        L.gf_synchronize(self.ptr)
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            L.gf_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Stamp geometry of a batch (``gf_batch``)."""
+
+    def __init__(self, ctx: Context, H, W, K, ncomp, shared: bool = False):
+        self.ctx = ctx
+        self.H, self.W, self.K, self.ncomp = list(map(int, H)), list(map(int, W)), list(map(int, K)), list(
+            map(int, ncomp))
+        self.n = len(self.H)
+        self.shared = bool(shared)
+        self.ptr = L.gf_batch_create(ctx.ptr, self.H, self.W, self.K, self.ncomp, self.shared)
+        self.sizes = L.gf_batch_sizes(self.ptr)
+        self.offsets = L.gf_batch_offsets(self.ptr, self.n)
+        self.P = [7 * c + 1 for c in self.ncomp]
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            L.gf_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Psf:
+    """Prepared PSFs of a batch (``gf_psf``); keeps the taps tensor alive."""
+
+    def __init__(self, ctx: Context, batch: Batch, taps: torch.Tensor, mode: int = GF_CONV_AUTO):
+        _need(taps, torch.float32, batch.sizes["n_psf"], "taps")
+        self.ctx, self.batch, self.taps = ctx, batch, taps
+        ctx.bind_stream()
+        self.ptr = L.gf_psf_prepare(ctx.ptr, batch.ptr, _ptr(taps), int(mode))
+        self.uses_fft, self.fft_side = L.gf_psf_paths(self.ptr, batch.n)
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            L.gf_psf_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _empty(ctx, n, dtype=torch.float32):
+    return torch.empty(int(max(n, 1)), dtype=dtype, device=ctx.device)
+
+
+def eval_model(ctx: Context, batch: Batch, theta: torch.Tensor, oversample: int = 5, out=None) -> torch.Tensor:
+    """Step 1 (gf_eval_model): padded model grids, no sky, flat [n_pad]."""
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    out = _empty(ctx, batch.sizes["n_pad"]) if out is None else _need(out, torch.float32, batch.sizes["n_pad"], "out")
+    ctx.bind_stream()
+    L.gf_eval_model(ctx.ptr, batch.ptr, _ptr(theta), int(oversample), _ptr(out))
+    return out
+
+
+def convolve_psf(ctx: Context, batch: Batch, psf: Psf, model_pad: torch.Tensor, n_ch: int = 1, out=None):
+    """Step 2 (gf_convolve_psf): valid convolution, flat [n_pix * n_ch]."""
+    _need(model_pad, torch.float32, batch.sizes["n_pad"] * n_ch, "model_pad")
+    n = batch.sizes["n_pix"] * n_ch
+    out = _empty(ctx, n) if out is None else _need(out, torch.float32, n, "out")
+    ctx.bind_stream()
+    L.gf_convolve_psf(ctx.ptr, batch.ptr, psf.ptr, _ptr(model_pad), int(n_ch), _ptr(out))
+    return out
+
+
+def model(ctx: Context, batch: Batch, psf: Psf, theta: torch.Tensor, oversample: int = 5, out=None):
+    """Steps 1-2 plus sky (gf_model): flat [n_pix]."""
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    out = _empty(ctx, batch.sizes["n_pix"]) if out is None else _need(out, torch.float32, batch.sizes["n_pix"], "out")
+    ctx.bind_stream()
+    L.gf_model(ctx.ptr, batch.ptr, psf.ptr, _ptr(theta), int(oversample), _ptr(out), 0)
+    return out
+
+
+def chi2(ctx: Context, batch: Batch, model_img: torch.Tensor, theta: torch.Tensor, data: torch.Tensor,
+         weight: torch.Tensor, want_resid: bool = False):
+    """Step 3 (gf_chi2).  Returns (pairs [n, 2] FP32 (hi, lo), resid or None)."""
+    _need(model_img, torch.float32, batch.sizes["n_pix"], "model")
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    _need(data, torch.float32, batch.sizes["n_img"], "data")
+    _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    pairs = torch.empty((batch.n, 2), dtype=torch.float32, device=ctx.device)
+    resid = _empty(ctx, batch.sizes["n_pix"]) if want_resid else None
+    ctx.bind_stream()
+    L.gf_chi2(ctx.ptr, batch.ptr, _ptr(model_img), _ptr(theta), _ptr(data), _ptr(weight), _ptr(resid), _ptr(pairs))
+    return pairs, resid
+
+
+def pairs_to_f64(pairs: torch.Tensor) -> torch.Tensor:
+    """Unpack (hi, lo) FP32 pairs into the FP64 values they represent."""
+    return pairs[:, 0].double() + pairs[:, 1].double()
+
+
+def likelihood(ctx: Context, batch: Batch, psf: Psf, theta: torch.Tensor, data: torch.Tensor, weight: torch.Tensor,
+               oversample: int = 5, work=None, out=None) -> torch.Tensor:
+    """Steps 1-3 in one call (gf_likelihood): (hi, lo) chi2 pairs [n, 2]."""
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    _need(data, torch.float32, batch.sizes["n_img"], "data")
+    _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    out = torch.empty((batch.n, 2), dtype=torch.float32, device=ctx.device) if out is None else out
+    ctx.bind_stream()
+    L.gf_likelihood(ctx.ptr, batch.ptr, psf.ptr, _ptr(theta), int(oversample), _ptr(data), _ptr(weight), _ptr(out),
+                    _ptr(work))
+    return out
+
+
+def likelihood_workspace(ctx: Context, batch: Batch, psf: Psf) -> torch.Tensor:
+    n = L.gf_likelihood_workspace(batch.ptr, psf.ptr)
+    return torch.empty(int(n), dtype=torch.uint8, device=ctx.device)
+
+
+def jacobian_full(ctx: Context, batch: Batch, psf: Psf, theta: torch.Tensor, oversample: int = 5, out=None):
+    """d m / d theta images (gf_jacobian, GF_JAC_FULL), flat [n_jac]."""
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    out = _empty(ctx, batch.sizes["n_jac"]) if out is None else _need(out, torch.float32, batch.sizes["n_jac"], "out")
+    ctx.bind_stream()
+    L.gf_jacobian(ctx.ptr, batch.ptr, psf.ptr, _ptr(theta), int(oversample), L.GF_JAC_FULL, 0, 0, 1.0, _ptr(out))
+    return out
+
+
+def jacobian_adjoint(ctx: Context, batch: Batch, psf: Psf, theta: torch.Tensor, cot: torch.Tensor, weight=None,
+                     scale: float = 1.0, oversample: int = 5, out=None):
+    """scale * sum_i cot_i (sqrt(w_i)) d m_i / d theta (gf_jacobian, GF_JAC_ADJOINT), flat [n_par]."""
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    _need(cot, torch.float32, batch.sizes["n_pix"], "cot")
+    if weight is not None:
+        _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    out = _empty(ctx, batch.sizes["n_par"]) if out is None else _need(out, torch.float32, batch.sizes["n_par"], "out")
+    ctx.bind_stream()
+    L.gf_jacobian(ctx.ptr, batch.ptr, psf.ptr, _ptr(theta), int(oversample), L.GF_JAC_ADJOINT, _ptr(cot),
+                  _ptr(weight), float(scale), _ptr(out))
+    return out
+
+
+def lm_options(**kw) -> L.GfLmOpts:
+    o = L.gf_lm_opts_default()
+    for k, v in kw.items():
+        if k in ("lo", "hi", "free_mask"):
+            continue
+        if k == "lambda_":
+            k = "lambda0"
+        setattr(o, k, v)
+    return o
+
+
+def fit_lm(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: torch.Tensor, theta0: torch.Tensor,
+           lo=None, hi=None, free=None, **opts):
+    """Levenberg-Marquardt over the whole batch on the device (gf_fit_lm).
+
+    theta0: float64 device tensor [n_par] (not modified).  Returns
+    (theta float64 tensor, numpy structured array of per-stamp results)."""
+    n_par = batch.sizes["n_par"]
+    _need(theta0, torch.float64, n_par, "theta0")
+    _need(data, torch.float32, batch.sizes["n_img"], "data")
+    _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    o = lm_options(**opts)
+    if lo is not None:
+        o.lo = _ptr(_need(lo, torch.float64, n_par, "lo"))
+    if hi is not None:
+        o.hi = _ptr(_need(hi, torch.float64, n_par, "hi"))
+    if free is not None:
+        o.free_mask = _ptr(_need(free, torch.uint8, n_par, "free"))
+    theta = theta0.clone()
+    res = torch.empty(batch.n * LM_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_fit_lm(ctx.ptr, batch.ptr, psf.ptr, _ptr(data), _ptr(weight), _ptr(theta), o, _ptr(res))
+    info = np.frombuffer(res.cpu().numpy().tobytes(), dtype=LM_RESULT_DTYPE)
+    return theta, info
+
+
+# ------------------------------------------------------------------ autograd
+class Chi2Fn(torch.autograd.Function):
+    """chi^2 per stamp (FP64 from the compensated pair) with the adjoint
+    gradient d chi^2 / d theta = -2 sum_i sqrt(w_i) r_i d m_i / d theta."""
+
+    @staticmethod
+    def forward(fctx, theta, ctx, batch, psf, data, weight, oversample):
+        mp = eval_model(ctx, batch, theta, oversample)
+        m = convolve_psf(ctx, batch, psf, mp)
+        pairs, resid = chi2(ctx, batch, m, theta, data, weight, want_resid=True)
+        fctx.save_for_backward(theta, resid, weight)
+        fctx.gf = (ctx, batch, psf, oversample)
+        return pairs_to_f64(pairs)
+
+    @staticmethod
+    def backward(fctx, g):
+        theta, resid, weight = fctx.saved_tensors
+        ctx, batch, psf, oversample = fctx.gf
+        grad = jacobian_adjoint(ctx, batch, psf, theta, resid, weight, -2.0, oversample)
+        per = torch.repeat_interleave(g.to(torch.float32), torch.tensor(batch.P, device=g.device))
+        return grad * per, None, None, None, None, None, None
+
+
+class ModelFn(torch.autograd.Function):
+    """Model image conv(components) + sky with the vector-Jacobian product
+    computed by the adjoint kernels."""
+
+    @staticmethod
+    def forward(fctx, theta, ctx, batch, psf, oversample):
+        fctx.save_for_backward(theta)
+        fctx.gf = (ctx, batch, psf, oversample)
+        return model(ctx, batch, psf, theta, oversample)
+
+    @staticmethod
+    def backward(fctx, g):
+        (theta,) = fctx.saved_tensors
+        ctx, batch, psf, oversample = fctx.gf
+        return jacobian_adjoint(ctx, batch, psf, theta, g.contiguous().to(torch.float32), None, 1.0,
+                                oversample), None, None, None, None
