@@ -6,9 +6,11 @@
 // lies below its mean, so b_n < 2n and the power series
 //     P(a, x) = x^a e^-x / Gamma(a+1) * sum_{k>=0} x^k / ((a+1)(a+2)...(a+k))
 // converges for every x we need.  The root is found by the Illinois variant
-// of regula falsi on [0, 2n].  Node slopes db_n/dn come from fourth-order
-// central differences of the node values (two guard nodes at each end), so
-// the device can interpolate with cubic Hermite polynomials.
+// of regula falsi on [0, 2n].  The first and second derivatives at each node
+// come from fourth-order central differences of the FP64 node values (two
+// guard nodes at each end), so the device can interpolate b_n from (b, b')
+// and b'_n from (b', b'') with cubic Hermite polynomials, never differencing
+// FP32 values.
 #include <cmath>
 #include <vector>
 
@@ -55,15 +57,16 @@ static double bn_root(double n) {
   return x;
 }
 
-std::vector<float2> build_bn_table() {
+std::vector<float4> build_bn_table() {
   const double h = (kBnHi - kBnLo) / (kBnNodes - 1);
   std::vector<double> b(kBnNodes + 4);
   for (int i = -2; i < kBnNodes + 2; ++i) b[i + 2] = bn_root(kBnLo + i * h);
-  std::vector<float2> tab(kBnNodes);
+  std::vector<float4> tab(kBnNodes);
   for (int i = 0; i < kBnNodes; ++i) {
     const double *c = &b[i + 2];
-    const double slope = (-c[2] + 8.0 * c[1] - 8.0 * c[-1] + c[-2]) / (12.0 * h);
-    tab[i] = make_float2((float)c[0], (float)slope);
+    const double d1 = (-c[2] + 8.0 * c[1] - 8.0 * c[-1] + c[-2]) / (12.0 * h);
+    const double d2 = (-c[2] + 16.0 * c[1] - 30.0 * c[0] + 16.0 * c[-1] - c[-2]) / (12.0 * h * h);
+    tab[i] = make_float4((float)c[0], (float)d1, (float)d2, 0.0f);
   }
   return tab;
 }

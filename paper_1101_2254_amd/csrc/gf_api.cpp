@@ -10,14 +10,14 @@
 #include "gf_internal.h"
 
 namespace gf {
-std::vector<float2> build_bn_table();
-hipError_t launch_eval(hipStream_t, const gf_batch *, const float *, int, const float2 *, float *, const int *);
-hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float2 *, float *, const int *);
-hipError_t launch_eval_jac(hipStream_t, const gf_batch *, const float *, int, const float2 *, float *, int,
+std::vector<float4> build_bn_table();
+hipError_t launch_eval(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, const int *);
+hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, const int *);
+hipError_t launch_eval_jac(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, int,
                            const int *);
-hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int, const float2 *, float *, int,
+hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, int,
                              const int *);
-hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float2 *, const float *,
+hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float4 *, const float *,
                                    float *);
 hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
                            float *, const int *);
@@ -171,7 +171,7 @@ gf_status gf_create(gf_ctx **out, int device) {
     delete c;
     return GF_EDEVICE;
   }
-  std::vector<float2> tab = build_bn_table();
+  std::vector<float4> tab = build_bn_table();
   if (upload(&c->d_bn, tab) != hipSuccess) {
     delete c;
     return GF_EDEVICE;

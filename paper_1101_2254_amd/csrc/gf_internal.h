@@ -26,7 +26,8 @@ constexpr int kDirectTW = 64;          // direct convolution output tile columns
 constexpr int kDirectMaxK = 41;        // largest PSF side on the direct path
 
 // b_n table: nodes n_i = kBnLo + i*h, i = -2 .. kBnNodes+1 (two guard nodes at
-// each end for the slope stencil); device copy holds (b_n, db_n/dn) per node.
+// each end for the difference stencils); the device copy holds
+// (b_n, db_n/dn, d2b_n/dn2, 0) per node.
 constexpr double kBnLo = 0.2;
 constexpr double kBnHi = 10.0;
 constexpr int kBnNodes = 4097;
@@ -67,6 +68,7 @@ struct Work {
 struct CompC {
   int32_t ix, iy;    // integer part of the centre
   float fx, fy;      // centre minus integer part
+  float ox[GF_MAX_OVERSAMPLE], oy[GF_MAX_OVERSAMPLE];  // sub-sample offset minus (fx, fy)
   float cs, sn;      // cos phi, sin phi
   float iq2;         // 1/q^2
   float a1, a0;      // t = exp2(a1 * log2(R^2) + a0)
@@ -98,7 +100,7 @@ struct gf_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  float2 *d_bn = nullptr;      // b_n table (kBnNodes entries)
+  float4 *d_bn = nullptr;      // b_n table (kBnNodes entries)
   unsigned int *d_counters = nullptr;  // self-resetting completion counters
   int64_t n_counters = 0;
   void *ws = nullptr;          // grow-only workspace

@@ -10,9 +10,10 @@
 //
 // Sub-sample offsets relative to the centre are formed as
 //     dx = (j - round(x0)) + ((s + 1/2)/S - 1/2 - (x0 - round(x0)))
-// so that dx keeps full relative precision near the centre, where the
-// Sersic cusp (R/Re)^(1/n) is steep, and is exactly zero when the centre
-// sits on a sub-sample.
+// with the second bracket computed once per workgroup to one rounding, so
+// that dx keeps full relative precision near the centre, where the Sersic
+// cusp (R/Re)^(1/n) is steep, and is exactly zero when the centre sits on a
+// sub-sample.
 #include "gf_internal.h"
 
 namespace gf {
@@ -20,30 +21,42 @@ namespace gf {
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Cubic Hermite lookup of (b_n, db_n/dn) in the FP32 table built on the host.
-__device__ __forceinline__ void bn_lookup(float n, const float2 *__restrict__ tab, float &b, float &db) {
+// Cubic Hermite lookup of b_n (from node values and slopes) and of db_n/dn
+// (from node slopes and curvatures) in the FP32 table built on the host.
+__device__ __forceinline__ void bn_lookup(float n, const float4 *__restrict__ tab, float &b, float &db) {
   const float h = (float)((kBnHi - kBnLo) / (kBnNodes - 1));
   float u = (n - (float)kBnLo) / h;
   u = fminf(fmaxf(u, 0.0f), (float)(kBnNodes - 1) - 1e-3f);
-  int i = (int)u;
-  float t = u - (float)i;
-  float2 p0 = tab[i], p1 = tab[i + 1];
-  float t2 = t * t, t3 = t2 * t;
-  float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
+  const int i = (int)u;
+  const float t = u - (float)i;
+  const float4 p0 = tab[i], p1 = tab[i + 1];
+  const float t2 = t * t, t3 = t2 * t;
+  const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
   b = h00 * p0.x + h01 * p1.x + h * (h10 * p0.y + h11 * p1.y);
-  float d00 = 6.f * t2 - 6.f * t, d10 = 3.f * t2 - 4.f * t + 1.f, d11 = 3.f * t2 - 2.f * t;
-  db = (d00 * (p0.x - p1.x)) / h + d10 * p0.y + d11 * p1.y;
+  db = h00 * p0.y + h01 * p1.y + h * (h10 * p0.z + h11 * p1.z);
 }
 
 // Per-component constants from the parameter vector (float or double).
+// The sub-sample offsets relative to the fractional centre,
+//   (s + 1/2)/S - 1/2 - f = ((2s + 1 - S) - 2S f) / (2S),
+// take one FMA (exact numerator up to one rounding) and one division, so a
+// sub-sample within 1e-7 px of the centre keeps its distance to full
+// relative precision; the Sersic cusp makes the value at such a point very
+// sensitive to that distance for large n.
 template <typename TT>
-__device__ void comp_setup(const TT *__restrict__ t, const float2 *__restrict__ bn_tab, CompC &c) {
+__device__ void comp_setup(const TT *__restrict__ t, const float4 *__restrict__ bn_tab, int S, CompC &c) {
   TT x0 = t[0], y0 = t[1];
   TT rx = rint(x0), ry = rint(y0);
   c.ix = (int)rx;
   c.iy = (int)ry;
   c.fx = (float)(x0 - rx);
   c.fy = (float)(y0 - ry);
+  const float twoS = 2.0f * (float)S;
+  for (int a = 0; a < GF_MAX_OVERSAMPLE; ++a) {
+    const float num = (float)(2 * a + 1 - S);
+    c.ox[a] = fmaf(-twoS, c.fx, num) / twoS;
+    c.oy[a] = fmaf(-twoS, c.fy, num) / twoS;
+  }
   float ie = (float)t[2], re = (float)t[3], n = (float)t[4], q = (float)t[5], phi = (float)t[6];
   float sn, cs;
   sincosf(phi, &sn, &cs);
@@ -64,22 +77,17 @@ __device__ void comp_setup(const TT *__restrict__ t, const float2 *__restrict__ 
   c.dbn = dbn;
 }
 
-template <int S>
-__device__ __forceinline__ float sub_off(int s) {
-  return ((float)s + 0.5f) / (float)S - 0.5f;
-}
-
 // ----------------------------------------------------------------- values
 template <typename TT, int S>
 __global__ __launch_bounds__(kThreads) void k_eval(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
-                                                   const TT *__restrict__ theta, const float2 *__restrict__ bn_tab,
+                                                   const TT *__restrict__ theta, const float4 *__restrict__ bn_tab,
                                                    float *__restrict__ out, const int *__restrict__ mask) {
   __shared__ CompC cc[kMaxComp];
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
   const StampDesc d = desc[s];
-  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, cc[threadIdx.x]);
+  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, S, cc[threadIdx.x]);
   __syncthreads();
   const int npad = d.Mh * d.Mw;
   const int p = w.unit * kEvalTile + (int)threadIdx.x;
@@ -94,10 +102,10 @@ __global__ __launch_bounds__(kThreads) void k_eval(const StampDesc *__restrict__
     const float peak = C.lie + C.b1;
     float ox[S];
 #pragma unroll
-    for (int a = 0; a < S; ++a) ox[a] = jx + (sub_off<S>(a) - C.fx);
+    for (int a = 0; a < S; ++a) ox[a] = jx + C.ox[a];
 #pragma unroll
     for (int b = 0; b < S; ++b) {
-      const float dy = iy + (sub_off<S>(b) - C.fy);
+      const float dy = iy + C.oy[b];
       const float dysn = dy * C.sn, dycs = dy * C.cs;
 #pragma unroll
       for (int a = 0; a < S; ++a) {
@@ -154,14 +162,14 @@ __device__ __forceinline__ void point_grad(const CompC &C, float dx, float dy, f
 template <typename TT, int S>
 __global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restrict__ desc,
                                                        const Work *__restrict__ work, const TT *__restrict__ theta,
-                                                       const float2 *__restrict__ bn_tab, float *__restrict__ out,
+                                                       const float4 *__restrict__ bn_tab, float *__restrict__ out,
                                                        int chan_stride, const int *__restrict__ mask) {
   __shared__ CompC cc[kMaxComp];
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
   const StampDesc d = desc[s];
-  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, cc[threadIdx.x]);
+  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, S, cc[threadIdx.x]);
   __syncthreads();
   const int npad = d.Mh * d.Mw;
   const int p = w.unit * kEvalTile + (int)threadIdx.x;
@@ -176,9 +184,9 @@ __global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restri
     float g[kNPC] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int b = 0; b < S; ++b) {
-      const float dy = iy + (((float)b + 0.5f) / (float)S - 0.5f - C.fy);
+      const float dy = iy + cc[k].oy[b];
 #pragma unroll
-      for (int a = 0; a < S; ++a) point_grad(C, jx + (sub_off<S>(a) - C.fx), dy, g);
+      for (int a = 0; a < S; ++a) point_grad(C, jx + C.ox[a], dy, g);
     }
 #pragma unroll
     for (int q = 0; q < kNPC; ++q) o[(int64_t)(kNPC * k + q) * npad] = g[q] * (1.0f / (float)(S * S));
@@ -193,7 +201,7 @@ template <typename TT, int S>
 __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *__restrict__ desc,
                                                                const Work *__restrict__ work,
                                                                const TT *__restrict__ theta,
-                                                               const float2 *__restrict__ bn_tab,
+                                                               const float4 *__restrict__ bn_tab,
                                                                const float *__restrict__ adj,
                                                                float *__restrict__ part) {
   __shared__ CompC cc[kMaxComp];
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   const StampDesc d = desc[s];
-  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, cc[threadIdx.x]);
+  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, S, cc[threadIdx.x]);
   __syncthreads();
   const int npad = d.Mh * d.Mw;
   const int p = w.unit * kEvalTile + (int)threadIdx.x;
@@ -220,9 +228,9 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
       float g[kNPC] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
       for (int b = 0; b < S; ++b) {
-        const float dy = iy + (((float)b + 0.5f) / (float)S - 0.5f - C.fy);
+        const float dy = iy + cc[k].oy[b];
 #pragma unroll
-        for (int aa = 0; aa < S; ++aa) point_grad(C, jx + (sub_off<S>(aa) - C.fx), dy, g);
+        for (int aa = 0; aa < S; ++aa) point_grad(C, jx + C.ox[aa], dy, g);
       }
       // Ie slot: dI/dIe = I/Ie
 #pragma unroll
@@ -253,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
 
 // ----------------------------------------------------------------- launchers
 template <typename TT>
-static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float2 *bn,
+static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
                                 float *out, const int *mask) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
@@ -271,18 +279,18 @@ static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *the
   return hipGetLastError();
 }
 
-hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, int S, const float2 *bn, float *out,
+hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn, float *out,
                        const int *mask) {
   return launch_eval_t<float>(st, b, theta, S, bn, out, mask);
 }
 
-hipError_t launch_eval_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float2 *bn,
+hipError_t launch_eval_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
                          float *out, const int *mask) {
   return launch_eval_t<double>(st, b, theta, S, bn, out, mask);
 }
 
 template <typename TT>
-static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float2 *bn,
+static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
                                     float *out, int chan_stride, const int *mask) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
@@ -301,17 +309,17 @@ static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT 
   return hipGetLastError();
 }
 
-hipError_t launch_eval_jac(hipStream_t st, const gf_batch *b, const float *theta, int S, const float2 *bn,
+hipError_t launch_eval_jac(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn,
                            float *out, int chan_stride, const int *mask) {
   return launch_eval_jac_t<float>(st, b, theta, S, bn, out, chan_stride, mask);
 }
 
-hipError_t launch_eval_jac_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float2 *bn,
+hipError_t launch_eval_jac_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
                              float *out, int chan_stride, const int *mask) {
   return launch_eval_jac_t<double>(st, b, theta, S, bn, out, chan_stride, mask);
 }
 
-hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const float *theta, int S, const float2 *bn,
+hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn,
                                    const float *adj, float *part) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
