@@ -1,0 +1,336 @@
+"""Benchmark of the galaxy-fitting hot path on one MI355X.
+
+Default workload (one 512x512 image, Sersic bulge + exponential disk, 65x65
+Moffat PSF on a 576-point FFT grid, 15 free parameters, Poisson + read noise):
+one step is one whole Levenberg-Marquardt fit from the seeded perturbed start
+to the relative chi^2 tolerance 1e-5, run by gf_fit_lm on the device, i.e. one
+pass of every stage of the hot path (parameter set-up, Sersic evaluation with
+5x5 oversampling and its derivatives, FFT convolution, chi^2 and residual,
+normal equations, FP64 solve and damping update).
+
+  value   = model evaluations per second counted in output pixels (Mpix/s):
+            512^2 x (trial evaluations + Jacobian evaluations) per fit / time
+            per fit.  Every one of them runs steps 1-3 over the whole image.
+  fits/s  = fits per second (reported beside it).
+
+`--workload c4` runs the likelihood batch instead (1024 parameter vectors
+against one 256x256 image with a 33x33 Moffat PSF; one step = steps 1-3 for all
+vectors through gf_likelihood).
+
+The roofline entry is for the kernel with the largest share of the step's GPU
+time, measured with HIP events recorded by the library on the stream each
+kernel is launched on (a separate, non-graph fit with per-kernel timing on).
+The CPU baseline times the FP64 oracle on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed FMA)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=["c2", "c4"], default="c2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--breakdown", action="store_true", help="print the per-kernel breakdown to stderr")
+    return ap.parse_args()
+
+
+# Algorithmic work per unit (see the roofline notes in the design document).
+# Evaluation: FP32 operations per sub-sample and component, counting an FMA as
+# two and a transcendental (log2 / exp2) as one.
+EVAL_FLOP_PER_SUB = 17
+EVAL_JAC_FLOP_PER_SUB = 54
+
+
+def kernel_work(name, geo, launches_per_step):
+    """(bound, algorithmic units per launch, unit) for a kernel of the step."""
+    npix, npad, nch, ncomp, S, L, H = (geo[k] for k in ("npix", "npad", "nch", "ncomp", "S", "L", "H"))
+    Lh = L // 2 + 1
+    if name == "k_eval":
+        return "alu", npad * ncomp * S * S * EVAL_FLOP_PER_SUB, "flop"
+    if name == "k_eval_jac":
+        return "alu", npad * ncomp * S * S * EVAL_JAC_FLOP_PER_SUB, "flop"
+    if name == "k_chi2":
+        # model read per pixel; data and weight per distinct image
+        return "hbm", npix * 4 + geo.get("nimg", npix) * 8, "byte"
+    if name == "k_gram":
+        return "hbm", npix * (4 * nch + 8), "byte"
+    if name in ("k_fft_rows", "k_fft_cols", "k_fft_irows"):
+        c = geo.get("chan_" + name, 1)
+        if name == "k_fft_rows":
+            return "hbm", c * (npad * 4 + (npad // geo["Mw"]) * Lh * 8), "byte"
+        if name == "k_fft_cols":
+            return "hbm", c * ((npad // geo["Mw"]) * Lh * 8 + H * Lh * 8) + L * Lh * 8, "byte"
+        return "hbm", c * (H * Lh * 8 + npix * 4), "byte"
+    return None, 0, None
+
+
+def run_c2(args, torch, ops, synth):
+    dev = torch.device("cuda", 0)
+    st = synth.c2()
+    ctx = ops.Context(0)
+    batch = ops.Batch(ctx, [st.H], [st.W], [st.K], [2])
+    taps = torch.from_numpy(st.psf.astype(np.float32).ravel()).to(dev)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_FFT)
+    # observation: the model at the truth (rendered by the library) plus noise
+    truth32 = torch.from_numpy(st.truth.astype(np.float32)).to(dev)
+    m_true = ops.model(ctx, batch, psf, truth32, 5).cpu().numpy().astype(np.float64).reshape(st.H, st.W)
+    d, w = synth.add_poisson_read_noise(m_true, st.meta["read_noise"], st.meta["gain"], st.noise_seed)
+    data = torch.from_numpy(d.astype(np.float32).ravel()).to(dev)
+    weight = torch.from_numpy(w.astype(np.float32).ravel()).to(dev)
+    lo, hi = synth.bounds(2, st.H, st.W)
+    lo_t = torch.from_numpy(lo).to(dev)
+    hi_t = torch.from_numpy(hi).to(dev)
+    theta0 = torch.from_numpy(st.start).to(dev)
+    opts = dict(ftol=1e-5, max_iter=100)
+
+    def step(**kw):
+        o = dict(opts)
+        o.update(kw)
+        return ops.fit_lm(ctx, batch, psf, data, weight, theta0, lo=lo_t, hi=hi_t, **o)
+
+    K = args.steps if args.steps is not None else 20
+    W = args.warmup if args.warmup is not None else 3
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(K):
+        th, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    info = infos[-1]
+    nfev, njev, iters = int(info["nfev"][0]), int(info["njev"][0]), int(info["iters"][0])
+    if any(int(i["nfev"][0]) != nfev or int(i["njev"][0]) != njev for i in infos):
+        raise RuntimeError("fits of the same input took different paths")
+    ms = t / K * 1e3
+    npix = st.H * st.W
+    mpix_s = (nfev + njev) * npix / (ms * 1e-3) / 1e6
+    # per-kernel breakdown of one fit (no graph, events on the launching stream)
+    from paper_1101_2254_amd import _lib
+    _lib.gf_profile_start(ctx.ptr)
+    step(use_graph=0)
+    torch.cuda.synchronize()
+    _lib.gf_profile_stop(ctx.ptr)
+    prof = _lib.gf_profile_read(ctx.ptr)
+    geo = dict(npix=npix, npad=(st.H + st.K - 1) * (st.W + st.K - 1), Mw=st.W + st.K - 1, H=st.H, nch=14, ncomp=2,
+               S=5, L=psf.fft_side[0])
+    result = dict(
+        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
+        value=round(mpix_s, 3), unit="Mpix/s", ms_per_step=round(ms, 4), fits_per_s=round(1e3 / ms, 3),
+        lm=dict(iters=iters, nfev=nfev, njev=njev, status=int(info["status"][0]), chi2=float(info["chi2"][0]),
+                chi2_per_dof=float(info["chi2"][0]) / (npix - 15)),
+        config=dict(workload="C2: one 512x512 image, Sersic bulge + exponential disk, 65x65 Moffat PSF "
+                             "(beta=3, FWHM=3 px), 576-point FFT convolution, 5x5 oversampling, 15-parameter "
+                             "LM fit to chi2 rel tol 1e-5; one step = one whole fit",
+                    image=[st.H, st.W], psf=st.K, fft_side=psf.fft_side[0], params=15, oversample=5),
+    )
+    return result, prof, geo, dict(st=st, nfev=nfev, njev=njev, iters=iters, npix=npix)
+
+
+def run_c4(args, torch, ops, synth):
+    dev = torch.device("cuda", 0)
+    base = synth.c4_truth()
+    nvec = 1024
+    ctx = ops.Context(0)
+    batch = ops.Batch(ctx, [256] * nvec, [256] * nvec, [33] * nvec, [1] * nvec, shared=True)
+    taps = torch.from_numpy(base.psf.astype(np.float32).ravel()).to(dev)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_FFT)
+    one = ops.Batch(ctx, [256], [256], [33], [1])
+    psf1 = ops.Psf(ctx, one, taps, ops.GF_CONV_FFT)
+    m_true = ops.model(ctx, one, psf1, torch.from_numpy(base.truth.astype(np.float32)).to(dev), 5)
+    d, w = synth.add_gaussian_noise(m_true.cpu().numpy().astype(np.float64).reshape(256, 256), base.noise_sigma,
+                                    base.noise_seed)
+    data = torch.from_numpy(d.astype(np.float32).ravel()).to(dev)
+    weight = torch.from_numpy(w.astype(np.float32).ravel()).to(dev)
+    K = args.steps if args.steps is not None else 50
+    W = args.warmup if args.warmup is not None else 3
+    thetas = [torch.from_numpy(synth.c4_vectors(s, nvec).astype(np.float32).ravel()).to(dev) for s in range(K + W)]
+    work = ops.likelihood_workspace(ctx, batch, psf)
+    out = torch.empty((nvec, 2), dtype=torch.float32, device=dev)
+    for s in range(W):
+        ops.likelihood(ctx, batch, psf, thetas[s], data, weight, 5, work=work, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        ops.likelihood(ctx, batch, psf, thetas[W + s], data, weight, 5, work=work, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms = t / K * 1e3
+    npix = 256 * 256 * nvec
+    from paper_1101_2254_amd import _lib
+    _lib.gf_profile_start(ctx.ptr)
+    ops.likelihood(ctx, batch, psf, thetas[0], data, weight, 5, work=work, out=out)
+    torch.cuda.synchronize()
+    _lib.gf_profile_stop(ctx.ptr)
+    prof = _lib.gf_profile_read(ctx.ptr)
+    geo = dict(npix=npix, npad=288 * 288 * nvec, Mw=288, H=256 * nvec, nch=1, ncomp=1, S=5, L=psf.fft_side[0],
+               nimg=256 * 256)
+    result = dict(
+        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
+        value=round(npix / (ms * 1e-3) / 1e6, 3), unit="Mpix/s", ms_per_step=round(ms, 4),
+        config=dict(workload="C4: likelihood batch, 1024 parameter vectors x one 256x256 image, 33x33 Moffat PSF, "
+                             "288-point FFT, 5x5 oversampling; one step = steps 1-3 for all vectors",
+                    image=[256, 256], psf=33, fft_side=psf.fft_side[0], vectors=nvec, oversample=5),
+    )
+    return result, prof, geo, dict(base=base, thetas_host=synth.c4_vectors(W, nvec), npix=npix)
+
+
+def roofline(prof, geo):
+    total = sum(v[1] for v in prof.values())
+    name = max(prof, key=lambda k: prof[k][1])
+    launches, tot_ms = prof[name]
+    bound, units, what = kernel_work(name, geo, launches)
+    avg_s = tot_ms / launches * 1e-3
+    stages = {}
+    for k, (n, t) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        b, u, wu = kernel_work(k, geo, n)
+        e = dict(launches=n, ms_total=round(t, 4), share=round(t / total, 4))
+        if b == "hbm":
+            e.update(bound="hbm", gbs=round(u / (t / n * 1e-3) / 1e9, 1), frac=round(u / (t / n * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        elif b == "alu":
+            e.update(bound="alu", tflops=round(u / (t / n * 1e-3) / 1e12, 2),
+                     frac=round(u / (t / n * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4))
+        stages[k] = e
+    if bound == "hbm":
+        ach = units / avg_s / 1e9
+        rl = dict(bound="hbm", kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                  frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    else:
+        ach = units / avg_s / 1e12
+        rl = dict(bound="alu", kernel=name, achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                  frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
+    rl["avg_launch_us"] = round(avg_s * 1e6, 2)
+    return rl, stages
+
+
+def cpu_baseline_c2(extra, seconds):
+    """The oracle on its own rendering of the same observation (FP64 model at
+    the FP32 truth, the same seeded noise): the first LM iterations of the fit."""
+    from oracle import gfo
+    import synth
+    st = extra["st"]
+    threads = os.cpu_count() or 1
+    gfo.set_threads(threads)
+    lo, hi = synth.bounds(2, st.H, st.W)
+    psf = st.psf.astype(np.float32).astype(np.float64)
+    m_true = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf, 5)
+    d, w = synth.add_poisson_read_noise(m_true, st.meta["read_noise"], st.meta["gain"], st.noise_seed)
+    d = d.astype(np.float32).astype(np.float64)
+    w = w.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    iters = evals = 0
+    n_it = 1
+    while True:
+        _, info = gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=n_it)
+        evals += info["nfev"] + info["njev"]
+        iters += info["iters"]
+        if time.perf_counter() - t0 >= seconds or n_it >= 8:
+            break
+        n_it += 1
+    t = time.perf_counter() - t0
+    mpix = evals * extra["npix"] / t / 1e6
+    return dict(value=round(mpix, 5), unit="Mpix/s", cores=gfo.get_threads(), kind="oracle",
+                sample=f"FP64 oracle LM on its own rendering of the same 512x512 observation: {iters} iterations "
+                       f"in runs of 1..{n_it} iterations ({evals} model + Jacobian evaluations, direct "
+                       f"convolution), {t:.1f} s on {gfo.get_threads()} threads",
+                fits_per_s_est=round(1.0 / (t / evals * (extra["nfev"] + extra["njev"])), 6))
+
+
+def cpu_baseline_c4(extra, seconds):
+    """The oracle on its own rendering of the same image: steps 1-3 for as many
+    of the step's parameter vectors as fit in the time budget."""
+    from oracle import gfo
+    import synth
+    threads = os.cpu_count() or 1
+    gfo.set_threads(threads)
+    base = extra["base"]
+    psf = base.psf.astype(np.float32).astype(np.float64)
+    m_true = gfo.model(256, 256, base.truth.astype(np.float32).astype(np.float64), psf, 5)
+    d, w = synth.add_gaussian_noise(m_true, base.noise_sigma, base.noise_seed)
+    d = d.astype(np.float32).astype(np.float64)
+    w = w.astype(np.float32).astype(np.float64)
+    th = extra["thetas_host"].astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds and n < th.shape[0]:
+        gfo.chi2(d, w, gfo.model(256, 256, th[n], psf, 5))
+        n += 1
+    t = time.perf_counter() - t0
+    return dict(value=round(n * 256 * 256 / t / 1e6, 5), unit="Mpix/s", cores=gfo.get_threads(), kind="oracle",
+                sample=f"FP64 oracle eval + direct convolution + chi2 of {n} of the step's parameter vectors on "
+                       f"its own rendering of the image, {t:.1f} s on {gfo.get_threads()} threads")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {max(args.gpus, world)} is not supported "
+              "(the hot path shards as described in the design notes, but only the one-GPU kernel is built)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_1101_2254_amd import ops
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
+    if args.workload == "c2":
+        result, prof, geo, extra = run_c2(args, torch, ops, synth)
+    else:
+        result, prof, geo, extra = run_c4(args, torch, ops, synth)
+    geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = 1
+    if args.workload == "c2":
+        # per fit the FFT passes run 14 channels (Jacobian) and 1 channel (trial) per launch: use the average
+        n_jac = extra["njev"]
+        n_trial = extra["nfev"]
+        avg = (14 * n_jac + 1 * n_trial) / max(n_jac + n_trial, 1)
+        for k in ("rows", "cols", "irows"):
+            geo["chan_k_fft_" + k] = avg
+    rl, stages = roofline(prof, geo)
+    print(f"bench: {result['value']} {result['unit']}, {result['ms_per_step']} ms/step", file=sys.stderr,
+          flush=True)
+    if args.breakdown:
+        print(json.dumps(stages, indent=1), file=sys.stderr)
+    out = dict(metric=result["metric"], value=result["value"], unit=result["unit"], n_gpus=1,
+               steps=args.steps if args.steps is not None else (20 if args.workload == "c2" else 50),
+               warmup=args.warmup if args.warmup is not None else 3, ms_per_step=result["ms_per_step"],
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)",
+               config=result["config"], roofline=rl)
+    for k in ("fits_per_s", "lm"):
+        if k in result:
+            out[k] = result[k]
+    out["stages"] = stages
+    if not args.no_cpu:
+        cb = cpu_baseline_c2(extra, args.cpu_seconds) if args.workload == "c2" else cpu_baseline_c4(
+            extra, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -236,6 +236,19 @@ void gf_lm_opts_default(gf_lm_opts *opts);
 gf_status gf_fit_lm(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
                     double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
 
+/* ------------------------------------------------------------ profiling */
+
+/* Per-kernel timing: while enabled, every kernel launch of this context is
+ * bracketed by HIP events recorded on the stream it is launched on (launches
+ * inside a captured HIP graph are not timed).  gf_profile_start clears the
+ * records; gf_profile_kernels synchronizes the device and returns the number
+ * of distinct kernel names; gf_profile_get returns the name, the number of
+ * timed launches and their summed duration in milliseconds for index i. */
+gf_status gf_profile_start(gf_ctx *ctx);
+gf_status gf_profile_stop(gf_ctx *ctx);
+int gf_profile_kernels(gf_ctx *ctx);
+gf_status gf_profile_get(gf_ctx *ctx, int i, char *name, int name_cap, int64_t *launches, double *total_ms);
+
 /* Library version string. */
 const char *gf_version(void);
 

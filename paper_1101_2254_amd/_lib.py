@@ -25,7 +25,8 @@ GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
 EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_synchronize", "gf_batch_create",
            "gf_batch_destroy", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
            "gf_psf_destroy", "gf_psf_paths", "gf_eval_model", "gf_convolve_psf", "gf_model", "gf_chi2", "gf_likelihood",
-           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_version")
+           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_profile_start",
+           "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_version")
 
 
 class GfLmOpts(ctypes.Structure):
@@ -86,6 +87,10 @@ def lib() -> ctypes.CDLL:
         "gf_jacobian": (i32, [vp, vp, vp, vp, i32, i32, vp, vp, flt, vp]),
         "gf_lm_opts_default": (None, [ctypes.POINTER(GfLmOpts)]),
         "gf_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
+        "gf_profile_start": (i32, [vp]),
+        "gf_profile_stop": (i32, [vp]),
+        "gf_profile_kernels": (i32, [vp]),
+        "gf_profile_get": (i32, [vp, i32, ctypes.c_char_p, i32, pi64, ctypes.POINTER(ctypes.c_double)]),
         "gf_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -200,6 +205,29 @@ def gf_lm_opts_default() -> GfLmOpts:
 
 def gf_fit_lm(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, opts: GfLmOpts, res_ptr):
     check(lib().gf_fit_lm(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), res_ptr), ctx)
+
+
+def gf_profile_start(ctx):
+    check(lib().gf_profile_start(ctx), ctx)
+
+
+def gf_profile_stop(ctx):
+    check(lib().gf_profile_stop(ctx), ctx)
+
+
+def gf_profile_read(ctx) -> dict:
+    """{kernel name: (launches, total ms)} of the timed launches."""
+    n = lib().gf_profile_kernels(ctx)
+    if n < 0:
+        raise GfError(GF_EDEVICE, "gf_profile_kernels failed")
+    out = {}
+    for i in range(n):
+        buf = ctypes.create_string_buffer(128)
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        check(lib().gf_profile_get(ctx, i, buf, 128, ctypes.byref(cnt), ctypes.byref(ms)), ctx)
+        out[buf.value.decode()] = (int(cnt.value), float(ms.value))
+    return out
 
 
 def gf_version() -> str:

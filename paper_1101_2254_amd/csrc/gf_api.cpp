@@ -37,14 +37,20 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *, float *, int, int, const int *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
-hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, int, const gf_lm_opts *, LMState *,
-                           double *, const double *, double *, int *, int *);
+hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
+                           const double *, double *, int *, int *, int *);
+hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const double *, const float *,
+                            const float *, float2 *, const int *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
                             const double *, int *, int *, int *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 }  // namespace gf
 
 using namespace gf;
+
+namespace gf {
+thread_local Profiler *t_prof = nullptr;
+}
 
 namespace {
 
@@ -198,6 +204,7 @@ void gf_destroy(gf_ctx *c) {
   dfree(c->d_counters);
   dfree(c->ws);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -404,7 +411,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     pd.L = L;
     pd.plan = plan_of_L[L];
     const int Lh = L / 2 + 1;
-    const int T = kFftCap / L, C = kFftCap / (L + 1);
+    const int T = kFftCap / (L + 1), C = kFftCap / L;
     const int cols = (Lh + C - 1) / C;
     for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_rows.push_back({s, u});
     for (int u = 0; u < cols; ++u) p->h_cols.push_back({s, u});
@@ -517,6 +524,7 @@ gf_status gf_psf_paths(const gf_psf *p, int32_t *uses_fft, int32_t *side) {
 
 // ------------------------------------------------------------ steps 1-3
 gf_status gf_eval_model(gf_ctx *c, const gf_batch *b, const float *theta, int S, float *out) {
+  ProfBind pb_(c);
   if (!c || !b || !theta || !out) return fail(c, GF_EINVAL, "gf_eval_model: null argument");
   if (b->ctx != c) return fail(c, GF_EINVAL, "gf_eval_model: batch belongs to another context");
   if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_eval_model: oversample out of range");
@@ -532,6 +540,7 @@ static gf_status convolve(gf_ctx *c, const gf_batch *b, const gf_psf *p, const f
 }
 
 gf_status gf_convolve_psf(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *in, int n_ch, float *out) {
+  ProfBind pb_(c);
   if (!c || !b || !p || !in || !out) return fail(c, GF_EINVAL, "gf_convolve_psf: null argument");
   if (p->batch != b) return fail(c, GF_EINVAL, "gf_convolve_psf: PSF prepared for another batch");
   if (n_ch < 1 || n_ch > 64) return fail(c, GF_EINVAL, "gf_convolve_psf: n_ch out of range");
@@ -548,6 +557,7 @@ gf_status gf_convolve_psf(gf_ctx *c, const gf_batch *b, const gf_psf *p, const f
 
 gf_status gf_chi2(gf_ctx *c, const gf_batch *b, const float *model, const float *theta, const float *data,
                   const float *weight, float *resid, float *chi2) {
+  ProfBind pb_(c);
   if (!c || !b || !model || !theta || !data || !weight || !chi2) return fail(c, GF_EINVAL, "gf_chi2: null argument");
   gf_status st = ensure_counters(c, b->n);
   if (st != GF_OK) return st;
@@ -582,6 +592,7 @@ int64_t gf_likelihood_workspace(const gf_batch *b, const gf_psf *p) {
 
 gf_status gf_likelihood(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *theta, int S, const float *data,
                         const float *weight, float *chi2, void *work) {
+  ProfBind pb_(c);
   if (!c || !b || !p || !theta || !data || !weight || !chi2) return fail(c, GF_EINVAL, "gf_likelihood: null argument");
   if (p->batch != b) return fail(c, GF_EINVAL, "gf_likelihood: PSF prepared for another batch");
   if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_likelihood: oversample out of range");
@@ -606,6 +617,7 @@ gf_status gf_likelihood(gf_ctx *c, const gf_batch *b, const gf_psf *p, const flo
 
 gf_status gf_model(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *theta, int S, float *out,
                    void *work) {
+  ProfBind pb_(c);
   if (!c || !b || !p || !theta || !out) return fail(c, GF_EINVAL, "gf_model: null argument");
   if (p->batch != b) return fail(c, GF_EINVAL, "gf_model: PSF prepared for another batch");
   if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_model: oversample out of range");
@@ -628,6 +640,7 @@ gf_status gf_model(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *t
 // -------------------------------------------------------------- derivatives
 gf_status gf_jacobian(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *theta, int S, int mode,
                       const float *cot, const float *weight, float scale, float *out) {
+  ProfBind pb_(c);
   if (!c || !b || !p || !theta || !out) return fail(c, GF_EINVAL, "gf_jacobian: null argument");
   if (p->batch != b) return fail(c, GF_EINVAL, "gf_jacobian: PSF prepared for another batch");
   if (S < 1 || S > GF_MAX_OVERSAMPLE) return fail(c, GF_EINVAL, "gf_jacobian: oversample out of range");
@@ -728,6 +741,7 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
 
 gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *data, const float *weight,
                     double *theta, const gf_lm_opts *opts, gf_lm_result *res) {
+  ProfBind pb_(c);
   if (!c || !b || !p || !data || !weight || !theta || !res) return fail(c, GF_EINVAL, "gf_fit_lm: null argument");
   if (p->batch != b) return fail(c, GF_EINVAL, "gf_fit_lm: PSF prepared for another batch");
   gf_lm_opts o;
@@ -738,8 +752,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   if (o.poll_every < 1) o.poll_every = 1;
   if (b->max_nc > 2) return fail(c, GF_ESHAPE, "gf_fit_lm: at most two components per stamp");
   const int nchan = kNPC * b->max_nc;
-  const int P = b->max_P;
-  const int nacc = P * (P + 1) / 2 + P + 1;
+  const int nacc = 256;  // 16 x 16 Gram matrix per workgroup
   gf_status st = ensure_counters(c, b->n);
   if (st != GF_OK) return st;
   Arena a;
@@ -780,13 +793,12 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac));
-      GF_TRY(c, launch_lm_solve(cs, b, B.npart, nacc, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial));
+      GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial));
       GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial));
-      GF_TRY(c, launch_chi2(cs, b, B.mconv, B.theta_t, true, data, weight, nullptr, B.cpart, c->d_counters,
-                            B.chi2t, B.mtrial));
-      GF_TRY(c, launch_lm_update(cs, b, &o, B.chi2t, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
+      GF_TRY(c, launch_chi2_part(cs, b, B.mconv, B.theta_t, data, weight, B.cpart, B.mtrial));
+      GF_TRY(c, launch_lm_update(cs, b, &o, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
       return GF_OK;
     };
     if (o.use_graph && o.max_iter > 0) {
@@ -818,6 +830,56 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   st = run();
   cleanup();
   return st;
+}
+
+// ---------------------------------------------------------------- profiling
+gf_status gf_profile_start(gf_ctx *c) {
+  if (!c) return GF_EINVAL;
+  GF_TRY(c, hipStreamSynchronize(c->stream));
+  c->prof.recs.clear();
+  c->prof.used = 0;
+  c->prof.on = true;
+  return GF_OK;
+}
+
+gf_status gf_profile_stop(gf_ctx *c) {
+  if (!c) return GF_EINVAL;
+  c->prof.on = false;
+  return GF_OK;
+}
+
+int gf_profile_kernels(gf_ctx *c) {
+  if (!c) return -1;
+  if (hipDeviceSynchronize() != hipSuccess) return -1;
+  std::vector<std::string> names;
+  for (const auto &r : c->prof.recs)
+    if (std::find(names.begin(), names.end(), r.name) == names.end()) names.push_back(r.name);
+  return (int)names.size();
+}
+
+gf_status gf_profile_get(gf_ctx *c, int i, char *name, int name_cap, int64_t *launches, double *total_ms) {
+  if (!c || i < 0) return GF_EINVAL;
+  GF_TRY(c, hipDeviceSynchronize());
+  std::vector<std::string> names;
+  for (const auto &r : c->prof.recs)
+    if (std::find(names.begin(), names.end(), r.name) == names.end()) names.push_back(r.name);
+  if (i >= (int)names.size()) return fail(c, GF_EINVAL, "gf_profile_get: index out of range");
+  int64_t n = 0;
+  double tot = 0.0;
+  for (const auto &r : c->prof.recs) {
+    if (names[i] != r.name) continue;
+    float ms = 0.0f;
+    GF_TRY(c, hipEventElapsedTime(&ms, r.a, r.b));
+    tot += ms;
+    ++n;
+  }
+  if (name && name_cap > 0) {
+    std::strncpy(name, names[i].c_str(), (size_t)name_cap - 1);
+    name[name_cap - 1] = 0;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = tot;
+  return GF_OK;
 }
 
 }  // extern "C"

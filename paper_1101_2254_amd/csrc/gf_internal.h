@@ -18,8 +18,8 @@ constexpr int kMaxP = kNPC * kMaxComp + 1;
 constexpr int kThreads = 256;          // threads per workgroup for pixel kernels (4 wave64)
 constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one per thread)
 constexpr int kPixChunk = 2048;        // pixels per chi^2 workgroup (8 per thread)
-constexpr int kNeqChunk = 4096;        // pixels per normal-equation workgroup (16 per thread)
-constexpr int kFftCap = 2048;          // complex values per LDS ping-pong buffer
+constexpr int kNeqChunk = 4096;        // pixels per normal-equation workgroup (16 waves, 256 per wave)
+constexpr int kFftCap = 3840;          // complex values in the FFT LDS buffer (T*L <= this)
 constexpr int kFftMaxStages = 12;
 constexpr int kDirectTH = 16;          // direct convolution output tile rows
 constexpr int kDirectTW = 64;          // direct convolution output tile columns
@@ -75,6 +75,7 @@ struct CompC {
   float b1;          // b_n * log2(e)
   float lie;         // log2(Ie)
   float ie, re, n, q, bn, dbn;
+  float inv_n, inv_re, inv_q;
 };
 
 // LM per-stamp state (device).
@@ -93,6 +94,53 @@ inline uint32_t magic_for(uint32_t d) {
   return d <= 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d);
 }
 
+// ---------------------------------------------------------------- profiling
+// Optional per-launch timing with HIP events recorded on the launching
+// stream around each kernel (never inside a graph capture).  Entry points
+// bind their context's profiler to the calling thread; launchers open a
+// ProfScope named after the kernel.
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+extern thread_local Profiler *t_prof;
+
+struct ProfScope {
+  Profiler *p = nullptr;
+  hipStream_t s = nullptr;
+  ProfRec r{};
+  ProfScope(hipStream_t st, const char *name) : s(st) {
+    if (!t_prof || !t_prof->on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    r.name = name;
+    r.a = t_prof->get();
+    r.b = t_prof->get();
+    if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) return;
+    p = t_prof;
+  }
+  ~ProfScope() {
+    if (!p) return;
+    if (hipEventRecord(r.b, s) == hipSuccess) p->recs.push_back(r);
+  }
+};
+
 }  // namespace gf
 
 // ---------------------------------------------------------------- host objects
@@ -106,7 +154,17 @@ struct gf_ctx {
   void *ws = nullptr;          // grow-only workspace
   size_t ws_bytes = 0;
   int *h_pinned = nullptr;     // pinned host word for LM polling
+  gf::Profiler prof;
 };
+
+namespace gf {
+// Binds a context's profiler to the calling thread for one entry point.
+struct ProfBind {
+  Profiler *prev;
+  explicit ProfBind(gf_ctx *c) : prev(t_prof) { t_prof = c ? &c->prof : nullptr; }
+  ~ProfBind() { t_prof = prev; }
+};
+}  // namespace gf
 
 struct gf_batch {
   gf_ctx *ctx = nullptr;

@@ -82,6 +82,7 @@ hipError_t launch_direct(hipStream_t st, const gf_batch *b, const gf_psf *p, con
   int maxK = 1;
   for (const auto &d : b->h_desc) maxK = d.K > maxK ? d.K : maxK;
   const size_t lds = direct_lds_bytes(maxK);
+  ProfScope ps(st, corr ? "k_direct_corr" : "k_direct");
   if (corr)
     hipLaunchKernelGGL((k_direct<1>), dim3((unsigned)lst.size(), n_ch), dim3(kThreads), lds, st, b->d_desc,
                        p->d_adirect, in, n_ch, p->d_taps, out, mask);

@@ -75,6 +75,9 @@ __device__ void comp_setup(const TT *__restrict__ t, const float4 *__restrict__ 
   c.q = q;
   c.bn = bn;
   c.dbn = dbn;
+  c.inv_n = 1.0f / n;
+  c.inv_re = 1.0f / re;
+  c.inv_q = 1.0f / q;
 }
 
 // ----------------------------------------------------------------- values
@@ -136,22 +139,25 @@ __device__ __forceinline__ void point_grad(const CompC &C, float dx, float dy, f
   const float yp = fmaf(-dx, C.sn, dy * C.cs);
   const float r2 = fmaf(C.iq2 * yp, yp, xp * xp);
   const float l2 = fast_log2(r2);
-  const float t = fast_exp2(fmaf(l2, C.a1, C.a0));
-  const float J = fast_exp2(C.b1 * (1.0f - t));        // I / Ie
+  const float lt = fmaf(l2, C.a1, C.a0);               // log2 t
+  const float t = fast_exp2(lt);
+  const float omt = 1.0f - t;
+  const float J = fast_exp2(C.b1 * omt);               // I / Ie
   const float I = J * C.ie;
   const float E = C.bn * t;
   const bool nz = r2 > 0.0f;
-  const float inv_n = 1.0f / C.n;
-  // ln u = (log2(R^2)/2 - log2 Re) ln 2 = (l2 * a1 + a0) * n * ln 2
-  const float lnu = fmaf(l2, C.a1, C.a0) * C.n * 0.69314718055994531f;
-  const float G = nz ? (-I * E * 0.5f * inv_n / r2) : 0.0f;   // dI / d(R^2)
-  g[0] += G * (-2.0f) * fmaf(xp, C.cs, -yp * C.sn * C.iq2);
-  g[1] += G * (-2.0f) * fmaf(xp, C.sn, yp * C.cs * C.iq2);
+  // ln u = (log2(R^2)/2 - log2 Re) ln 2 = log2(t) * n * ln 2
+  const float lnu = lt * (C.n * 0.69314718055994531f);
+  const float IE = I * E;
+  const float G = nz ? (IE * (-0.5f * C.inv_n)) * __builtin_amdgcn_rcpf(r2) : 0.0f;   // dI / d(R^2)
+  const float m2G = -2.0f * G;
+  g[0] = fmaf(m2G, fmaf(xp, C.cs, -yp * C.sn * C.iq2), g[0]);
+  g[1] = fmaf(m2G, fmaf(xp, C.sn, yp * C.cs * C.iq2), g[1]);
   g[2] += J;
-  g[3] += I * E * inv_n / C.re;
-  g[4] += I * (C.dbn * (1.0f - t) + (nz ? E * lnu * inv_n * inv_n : 0.0f));
-  g[5] += G * (-2.0f) * yp * yp * C.iq2 / C.q;
-  g[6] += G * 2.0f * xp * yp * (1.0f - C.iq2);
+  g[3] = fmaf(IE, C.inv_n * C.inv_re, g[3]);
+  g[4] = fmaf(I, fmaf(C.dbn, omt, nz ? E * lnu * (C.inv_n * C.inv_n) : 0.0f), g[4]);
+  g[5] = fmaf(m2G * yp * yp, C.iq2 * C.inv_q, g[5]);
+  g[6] = fmaf(-m2G * xp * yp, 1.0f - C.iq2, g[6]);
 }
 
 // Writes 7 * ncomp channels per stamp on the padded grid: channel 7k + p is
@@ -265,6 +271,7 @@ static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *the
                                 float *out, const int *mask) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
+  ProfScope ps(st, "k_eval");
   switch (S) {
 #define GF_EVAL_CASE(SS)                                                                          \
   case SS:                                                                                        \
@@ -294,6 +301,7 @@ static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT 
                                     float *out, int chan_stride, const int *mask) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
+  ProfScope ps(st, "k_eval_jac");
   switch (S) {
 #define GF_EVALJ_CASE(SS)                                                                                   \
   case SS:                                                                                                  \
@@ -323,6 +331,7 @@ hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const floa
                                    const float *adj, float *part) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
+  ProfScope ps(st, "k_adjoint_contract");
   switch (S) {
 #define GF_ADJ_CASE(SS)                                                                                        \
   case SS:                                                                                                     \

@@ -5,7 +5,7 @@
 // from the circular convolution on an L x L grid with L >= max(Mh, Mw): the
 // kept "valid" rows and columns K-1 .. M-1 never see a wrapped tap.  Three
 // launches per convolution, each a batch of independent 1-D transforms held in
-// LDS (two ping-pong buffers of kFftCap complex values per workgroup):
+// one LDS buffer of kFftCap complex values per workgroup:
 //   rows   : two real rows per complex transform (z = a + i b), length L,
 //            split into the half spectra A, B (L/2+1 bins) -> spectra S1[row][k]
 //   columns: per bin k, forward transform over rows, times the OTF (or its
@@ -16,9 +16,7 @@
 // The 1/L^2 of the inverse transform is folded into the OTF.
 //
 // Transforms are mixed-radix Stockham passes (radix 2, 3, 4, 5, 8) with FP32
-// twiddles that the host computes in FP64.  The column kernel strides its LDS
-// transforms by L+1 complex values so the transposing loads and stores of
-// neighbouring bins fall in different LDS banks.
+// twiddles that the host computes in FP64, done in place in LDS.
 #include "gf_internal.h"
 
 namespace gf {
@@ -37,6 +35,22 @@ __device__ __forceinline__ float2 mul_i(float2 a) { return make_float2(-a.y, a.x
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // -i a
 
 __device__ __forceinline__ int fdiv(int x, uint32_t m) { return m ? (int)__umulhi((uint32_t)x, m) : x; }
+
+// Division of x < 2^16 by a divisor fixed for the whole workgroup.
+struct FDiv {
+  uint32_t m;
+  __device__ __forceinline__ explicit FDiv(int d) : m(d <= 1 ? 0u : 0xffffffffu / (uint32_t)d + 1u) {}
+  __device__ __forceinline__ int operator()(int x) const { return fdiv(x, m); }
+};
+
+// LDS index with one padding slot per 32 complex values: the strided
+// accesses of the early Stockham passes (stride R) then spread over the banks.
+__device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
+constexpr int kFftLds = kFftCap + kFftCap / 32 + 1;
+// Loops that move up to kFftCap values between memory and LDS are unrolled
+// this many times so each thread issues all of its global loads before it
+// waits on any of them.
+constexpr int kFftIters = (kFftCap + kThreads - 1) / kThreads;
 
 // ------------------------------------------------------------ small DFTs
 // Forward: X_k = sum_n x_n exp(-2 pi i n k / R); inverse uses +i.
@@ -120,60 +134,71 @@ __device__ __forceinline__ void dft(float2 *v) {
   else dft8<INV>(v);
 }
 
-// One Stockham pass over T transforms of length L (stride Ls) from `in` to
-// `out`.  Butterfly j of a transform reads x[j + r L/R], twiddles input r by
+// One in-place Stockham pass over T transforms of length L (stride Ls).
+// Butterfly j of a transform reads x[j + r L/R], twiddles input r by
 // W_{Ns R}^{r k} (k = j mod Ns), does a radix-R DFT and writes to
-// (j div Ns) Ns R + k + r Ns.
+// (j div Ns) Ns R + k + r Ns.  Every thread first loads all of its
+// butterflies (at most 16 complex values: T L <= kFftCap guarantees one
+// round), the workgroup synchronises, and then all results are stored, so a
+// single LDS buffer suffices.
 template <int R, bool INV>
-__device__ __forceinline__ void stockham_pass(const float2 *__restrict__ in, float2 *__restrict__ out, int T, int L,
-                                              int Ls, int Ns, uint32_t ns_m, uint32_t nb_m,
-                                              const float2 *__restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(float2 *__restrict__ buf, int T, int L, int Ls, int Ns, uint32_t ns_m,
+                                              uint32_t nb_m, const float2 *__restrict__ tw) {
+  constexpr int NB = 16 / R;
   const int nb = L / R;
   const int total = T * nb;
   const int twstep = L / (Ns * R);
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int t = fdiv(idx, nb_m);
-    const int j = idx - t * nb;
-    const int jd = fdiv(j, ns_m);
-    const int k = j - jd * Ns;
-    const float2 *src = in + t * Ls + j;
-    float2 v[R];
+  float2 v[NB][R];
+  int dst[NB];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[r * nb];
-    if (Ns > 1) {
+  for (int b = 0; b < NB; ++b) {
+    const int idx = (int)threadIdx.x + b * (int)blockDim.x;
+    dst[b] = -1;
+    if (idx < total) {
+      const int t = fdiv(idx, nb_m);
+      const int j = idx - t * nb;
+      const int jd = fdiv(j, ns_m);
+      const int k = j - jd * Ns;
+      const int src = t * Ls + j;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const float2 w = tw[r * k * twstep];
-        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      for (int r = 0; r < R; ++r) v[b][r] = buf[lp(src + r * nb)];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 w = tw[r * k * twstep];
+          v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+        }
       }
+      dft<R, INV>(v[b]);
+      dst[b] = t * Ls + jd * Ns * R + k;
     }
-    dft<R, INV>(v);
-    float2 *dst = out + t * Ls + jd * Ns * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) dst[r * Ns] = v[r];
   }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (dst[b] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lp(dst[b] + r * Ns)] = v[b][r];
+    }
+  }
+  __syncthreads();
 }
 
-// Full transform; returns the buffer that holds the result.
+// Full transform of T transforms in place (T * L <= kFftCap).
 template <bool INV>
-__device__ float2 *lds_fft(float2 *a, float2 *b, int T, int Ls, const FftPlan &pl, const float2 *tw) {
+__device__ __forceinline__ void lds_fft(float2 *buf, int T, int Ls, const FftPlan &pl, const float2 *tw) {
   const int L = pl.L;
   for (int s = 0; s < pl.nstages; ++s) {
     const int R = pl.radix[s], Ns = pl.ns[s];
     const uint32_t nsm = pl.ns_magic[s], nbm = pl.nb_magic[s];
     switch (R) {
-      case 2: stockham_pass<2, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 3: stockham_pass<3, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 4: stockham_pass<4, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 5: stockham_pass<5, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
-      default: stockham_pass<8, INV>(a, b, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 2: stockham_pass<2, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 3: stockham_pass<3, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 4: stockham_pass<4, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 5: stockham_pass<5, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      default: stockham_pass<8, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
     }
-    __syncthreads();
-    float2 *tmp = a;
-    a = b;
-    b = tmp;
   }
-  return a;
 }
 
 // Geometry of one launch mode.
@@ -202,9 +227,16 @@ __device__ __forceinline__ Geo geo_of(int mode, const StampDesc &d, int L) {
   return g;
 }
 
+// Spectra are stored bin-major ("transposed"): S1 of a channel is
+// [L/2+1 bins][in_rows rows] and S2 is [L/2+1 bins][out_rows rows], so the
+// column pass reads and writes whole contiguous columns and the row passes
+// exchange runs of 2T consecutive rows per bin.  Row transforms sit in LDS with
+// stride L+1 (odd in units of 8 bytes), so the bin-major exchanges hit
+// distinct LDS banks.
+
 // ------------------------------------------------------------ row pass
 // in: real images; stamp s channel ch starts at in_base(s) * n_ch + ch * plane.
-// S1: spectra; stamp s channel ch starts at s1_off[s] * n_ch + ch * in_rows * (L/2+1).
+// S1: stamp s channel ch starts at s1_off[s] * n_ch + ch * (L/2+1) * in_rows.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restrict__ desc,
                                                        const PathDesc *__restrict__ path,
@@ -220,10 +252,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   const FftPlan &pl = plans[pd.plan];
-  const int L = pl.L, Lh = L / 2 + 1;
+  const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int T = kFftCap / L;
-  float2 *bufA = lds, *bufB = lds + kFftCap, *tw = lds + 2 * kFftCap;
+  const int T = kFftCap / Ls;
+  float2 *buf = lds, *tw = lds + kFftLds;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
   int64_t in_base, plane;
@@ -232,35 +264,48 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   else { in_base = d.psf; plane = (int64_t)d.K * d.K; }
   const float *src = in + in_base * n_ch + ch * plane;
   const int r0 = w.unit * 2 * T;
-  for (int idx = threadIdx.x; idx < T * L; idx += blockDim.x) {
-    const int t = idx / L, n = idx - t * L;
-    const int ra = r0 + 2 * t, rb = ra + 1;
-    const int c = n - g.in_col0;
-    const bool cin = c >= 0 && c < g.in_cols;
-    const float a = (cin && ra < g.in_rows) ? src[(int64_t)ra * g.in_cols + c] : 0.0f;
-    const float b = (cin && rb < g.in_rows) ? src[(int64_t)rb * g.in_cols + c] : 0.0f;
-    bufA[t * L + n] = make_float2(a, b);
+  const FDiv divL(L);
+  {
+    float va[kFftIters], vb[kFftIters];
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      const int t = divL(idx), n = idx - t * L;
+      const int ra = r0 + 2 * t, rb = ra + 1;
+      const int c = n - g.in_col0;
+      const bool cin = idx < T * L && c >= 0 && c < g.in_cols;
+      va[it] = (cin && ra < g.in_rows) ? src[(int64_t)ra * g.in_cols + c] : 0.0f;
+      vb[it] = (cin && rb < g.in_rows) ? src[(int64_t)rb * g.in_cols + c] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      if (idx < T * L) {
+        const int t = divL(idx), n = idx - t * L;
+        buf[lp(t * Ls + n)] = make_float2(va[it], vb[it]);
+      }
+    }
   }
   __syncthreads();
-  const float2 *X = lds_fft<false>(bufA, bufB, T, L, pl, tw);
-  float2 *dst = S1 + s1_off[s] * n_ch + (int64_t)ch * g.in_rows * Lh;
-  for (int idx = threadIdx.x; idx < T * Lh; idx += blockDim.x) {
-    const int t = idx / Lh, k = idx - t * Lh;
-    const int ra = r0 + 2 * t, rb = ra + 1;
-    if (ra >= g.in_rows) continue;
-    const float2 zk = X[t * L + k];
-    const float2 zc = cconj(X[t * L + (k == 0 ? 0 : L - k)]);
-    const float2 A = cscale(cadd(zk, zc), 0.5f);
-    const float2 B = cscale(mul_mi(csub(zk, zc)), 0.5f);
-    dst[(int64_t)ra * Lh + k] = A;
-    if (rb < g.in_rows) dst[(int64_t)rb * Lh + k] = B;
+  lds_fft<false>(buf, T, Ls, pl, tw);
+  float2 *dst = S1 + s1_off[s] * n_ch + (int64_t)ch * Lh * g.in_rows;
+  const int nr = min(2 * T, g.in_rows - r0);
+  const FDiv divNr(nr);
+  for (int idx = threadIdx.x; idx < Lh * nr; idx += blockDim.x) {
+    const int k = divNr(idx), rr = idx - k * nr;
+    const int t = rr >> 1;
+    const float2 zk = buf[lp(t * Ls + k)];
+    const float2 zc = cconj(buf[lp(t * Ls + (k == 0 ? 0 : L - k))]);
+    const float2 v = (rr & 1) ? cscale(mul_mi(csub(zk, zc)), 0.5f) : cscale(cadd(zk, zc), 0.5f);
+    dst[(int64_t)k * g.in_rows + r0 + rr] = v;
   }
 }
 
 // ---------------------------------------------------------- column pass
-// S1 rows 0 .. in_rows-1 sit at L-grid rows col_row0 ..; MODE_CONV multiplies
-// by the OTF, MODE_CORR by its conjugate, MODE_OTF only transforms forward and
-// scales by 1/L^2 (writing the OTF itself).
+// Column k of S1 (rows 0 .. in_rows-1) sits at L-grid rows col_row0 ..;
+// MODE_CONV multiplies by the OTF, MODE_CORR by its conjugate, MODE_OTF only
+// transforms forward and scales by 1/L^2 (writing the OTF itself, bin-major
+// [L/2+1][L]).
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restrict__ desc,
                                                        const PathDesc *__restrict__ path,
@@ -279,48 +324,64 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   const FftPlan &pl = plans[pd.plan];
-  const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
+  const int L = pl.L, Lh = L / 2 + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int C = kFftCap / Ls;
+  const int C = kFftCap / L;
   const int k0 = w.unit * C;
   const int nc = min(C, Lh - k0);
-  float2 *bufA = lds, *bufB = lds + kFftCap, *tw = lds + 2 * kFftCap;
+  float2 *buf = lds, *tw = lds + kFftLds;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
-  const float2 *src = S1 + s1_off[s] * n_ch + (int64_t)ch * g.in_rows * Lh;
-  for (int idx = threadIdx.x; idx < C * L; idx += blockDim.x) {
-    const int y = idx / C, c = idx - y * C;
-    const int r = y - g.col_row0;
-    float2 v = make_float2(0.f, 0.f);
-    if (c < nc && r >= 0 && r < g.in_rows) v = src[(int64_t)r * Lh + k0 + c];
-    bufA[c * Ls + y] = v;
+  const float2 *src = S1 + s1_off[s] * n_ch + (int64_t)ch * Lh * g.in_rows + (int64_t)k0 * g.in_rows;
+  const FDiv divL(L);
+  {
+    float2 v[kFftIters];
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      const int c = divL(idx), y = idx - c * L;
+      const int r = y - g.col_row0;
+      v[it] = (idx < C * L && c < nc && r >= 0 && r < g.in_rows) ? src[(int64_t)c * g.in_rows + r]
+                                                                  : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      if (idx < C * L) buf[lp(idx)] = v[it];
+    }
   }
   __syncthreads();
-  float2 *X = lds_fft<false>(bufA, bufB, C, Ls, pl, tw);
-  float2 *Y = (X == bufA) ? bufB : bufA;
+  lds_fft<false>(buf, C, L, pl, tw);
   if (MODE == MODE_OTF) {
     const float sc = 1.0f / ((float)L * (float)L);
-    float2 *dst = S2 + s2_off[s];
-    for (int idx = threadIdx.x; idx < C * L; idx += blockDim.x) {
-      const int y = idx / C, c = idx - y * C;
-      if (c < nc) dst[(int64_t)y * Lh + k0 + c] = cscale(X[c * Ls + y], sc);
-    }
+    float2 *dst = S2 + s2_off[s] + (int64_t)k0 * L;
+    for (int idx = threadIdx.x; idx < nc * L; idx += blockDim.x) dst[idx] = cscale(buf[lp(idx)], sc);
     return;
   }
-  const float2 *H = otf + pd.otf;
-  for (int idx = threadIdx.x; idx < C * L; idx += blockDim.x) {
-    const int y = idx / C, c = idx - y * C;
-    if (c < nc) {
-      const float2 h = H[(int64_t)y * Lh + k0 + c];
-      X[c * Ls + y] = (MODE == MODE_CORR) ? cmulc(X[c * Ls + y], h) : cmul(X[c * Ls + y], h);
+  const float2 *H = otf + pd.otf + (int64_t)k0 * L;
+  {
+    float2 hv[kFftIters];
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      hv[it] = idx < nc * L ? H[idx] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      if (idx < nc * L) {
+        const float2 x = buf[lp(idx)];
+        buf[lp(idx)] = (MODE == MODE_CORR) ? cmulc(x, hv[it]) : cmul(x, hv[it]);
+      }
     }
   }
   __syncthreads();
-  X = lds_fft<true>(X, Y, C, Ls, pl, tw);
-  float2 *dst = S2 + s2_off[s] * n_ch + (int64_t)ch * g.out_rows * Lh;
-  for (int idx = threadIdx.x; idx < C * g.out_rows; idx += blockDim.x) {
-    const int y = idx / C, c = idx - y * C;
-    if (c < nc) dst[(int64_t)y * Lh + k0 + c] = X[c * Ls + g.out_row0 + y];
+  lds_fft<true>(buf, C, L, pl, tw);
+  float2 *dst = S2 + s2_off[s] * n_ch + (int64_t)ch * Lh * g.out_rows + (int64_t)k0 * g.out_rows;
+  const FDiv divR(g.out_rows);
+  for (int idx = threadIdx.x; idx < nc * g.out_rows; idx += blockDim.x) {
+    const int c = divR(idx), y = idx - c * g.out_rows;
+    dst[idx] = buf[lp(c * L + g.out_row0 + y)];
   }
 }
 
@@ -342,60 +403,86 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   const FftPlan &pl = plans[pd.plan];
-  const int L = pl.L, Lh = L / 2 + 1;
+  const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int T = kFftCap / L;
-  float2 *bufA = lds, *bufB = lds + kFftCap, *tw = lds + 2 * kFftCap;
+  const int T = kFftCap / Ls;
+  float2 *buf = lds, *tw = lds + kFftLds;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
-  const float2 *src = S2 + s2_off[s] * n_ch + (int64_t)ch * g.out_rows * Lh;
+  const float2 *src = S2 + s2_off[s] * n_ch + (int64_t)ch * Lh * g.out_rows;
   const int r0 = w.unit * 2 * T;
-  for (int idx = threadIdx.x; idx < T * L; idx += blockDim.x) {
-    const int t = idx / L, k = idx - t * L;
-    const int ra = r0 + 2 * t, rb = ra + 1;
-    const bool neg = k > L / 2;
-    const int kk = neg ? L - k : k;
-    float2 A = (ra < g.out_rows) ? src[(int64_t)ra * Lh + kk] : make_float2(0.f, 0.f);
-    float2 B = (rb < g.out_rows) ? src[(int64_t)rb * Lh + kk] : make_float2(0.f, 0.f);
-    if (neg) {
-      A = cconj(A);
-      B = cconj(B);
+  const FDiv divT(T);
+  {
+    float2 va[kFftIters], vb[kFftIters];
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      const int k = divT(idx), t = idx - k * T;
+      const int ra = r0 + 2 * t, rb = ra + 1;
+      const bool ok = idx < T * L;
+      const int kk = k > L / 2 ? L - k : k;
+      const float2 *col = src + (int64_t)kk * g.out_rows;
+      va[it] = (ok && ra < g.out_rows) ? col[ra] : make_float2(0.f, 0.f);
+      vb[it] = (ok && rb < g.out_rows) ? col[rb] : make_float2(0.f, 0.f);
     }
-    bufA[t * L + k] = cadd(A, mul_i(B));
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      if (idx < T * L) {
+        const int k = divT(idx), t = idx - k * T;
+        float2 A = va[it], B = vb[it];
+        if (k > L / 2) {
+          A = cconj(A);
+          B = cconj(B);
+        }
+        buf[lp(t * Ls + k)] = cadd(A, mul_i(B));
+      }
+    }
   }
   __syncthreads();
-  const float2 *X = lds_fft<true>(bufA, bufB, T, L, pl, tw);
+  lds_fft<true>(buf, T, Ls, pl, tw);
   int64_t out_base = (MODE == MODE_CONV) ? d.pix : d.pad;
   float *dst = out + out_base * n_ch + (int64_t)ch * g.out_rows * g.out_cols;
+  const FDiv divC(g.out_cols);
   for (int idx = threadIdx.x; idx < T * g.out_cols; idx += blockDim.x) {
-    const int t = idx / g.out_cols, x = idx - t * g.out_cols;
+    const int t = divC(idx), x = idx - t * g.out_cols;
     const int ra = r0 + 2 * t, rb = ra + 1;
-    const float2 v = X[t * L + g.out_col0 + x];
+    const float2 v = buf[lp(t * Ls + g.out_col0 + x)];
     if (ra < g.out_rows) dst[(int64_t)ra * g.out_cols + x] = v.x;
     if (rb < g.out_rows) dst[(int64_t)rb * g.out_cols + x] = v.y;
   }
 }
 
 // ----------------------------------------------------------------- launchers
-static size_t fft_lds_bytes(int max_L) { return (size_t)(2 * kFftCap + max_L) * sizeof(float2); }
+static size_t fft_lds_bytes(int max_L) { return (size_t)(kFftLds + max_L) * sizeof(float2); }
 
 hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
                            float2 *S1, float2 *S2, float *out, const int *mask) {
   if (p->h_rows.empty()) return hipSuccess;
   const size_t lds = fft_lds_bytes(p->max_L);
   dim3 blk(kThreads);
-  hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)p->h_rows.size(), n_ch), blk, lds, st, b->d_desc,
-                     p->d_path, p->d_plans, p->d_tw, p->d_rows, in, n_ch, p->d_s1, S1, mask);
-  hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)p->h_cols.size(), n_ch), blk, lds, st, b->d_desc,
-                     p->d_path, p->d_plans, p->d_tw, p->d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask);
-  hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)p->h_irows.size(), n_ch), blk, lds, st, b->d_desc,
-                     p->d_path, p->d_plans, p->d_tw, p->d_irows, n_ch, p->d_s2, S2, out, mask);
+  {
+    ProfScope ps(st, "k_fft_rows");
+    hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)p->h_rows.size(), n_ch), blk, lds, st, b->d_desc,
+                       p->d_path, p->d_plans, p->d_tw, p->d_rows, in, n_ch, p->d_s1, S1, mask);
+  }
+  {
+    ProfScope ps(st, "k_fft_cols");
+    hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)p->h_cols.size(), n_ch), blk, lds, st, b->d_desc,
+                       p->d_path, p->d_plans, p->d_tw, p->d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask);
+  }
+  {
+    ProfScope ps(st, "k_fft_irows");
+    hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)p->h_irows.size(), n_ch), blk, lds, st,
+                       b->d_desc, p->d_path, p->d_plans, p->d_tw, p->d_irows, n_ch, p->d_s2, S2, out, mask);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_fft_corr(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, float2 *S1,
                            float2 *S2, float *out) {
   if (p->h_arows.empty()) return hipSuccess;
+  ProfScope ps(st, "k_fft_corr");
   const size_t lds = fft_lds_bytes(p->max_L);
   dim3 blk(kThreads);
   hipLaunchKernelGGL((k_fft_rows<MODE_CORR>), dim3((unsigned)p->h_arows.size(), 1), blk, lds, st, b->d_desc,

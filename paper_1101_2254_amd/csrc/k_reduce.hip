@@ -5,10 +5,11 @@
 //
 // Sums are FP32 with error-free transformations: each thread keeps a (hi, lo)
 // pair updated by TwoSum (Knuth), pairs are combined through wave64 shuffles
-// and then across the workgroup's four waves in a fixed order, and the last
-// workgroup of a stamp to finish (found with a per-stamp counter that resets
-// itself) adds the workgroup partials in index order.  Nothing depends on the
-// order in which workgroups run, so results are bitwise reproducible.
+// and then across the workgroup's four waves in a fixed order, and a second
+// small launch adds the workgroup partials of each stamp in a fixed order.
+// Nothing depends on the order in which workgroups run, so results are
+// bitwise reproducible.  (No cross-workgroup fences: on this chip a
+// device-scope release writes back the L2 of the issuing XCD.)
 #include "gf_internal.h"
 
 namespace gf {
@@ -75,14 +76,13 @@ __device__ __forceinline__ float sky_of(const TT *theta, const StampDesc &d) {
 }
 
 // ------------------------------------------------------------------ chi^2
-// r = sqrt(w) (d - m - sky); chi2[s] = (hi, lo) of sum r^2.
+// r = sqrt(w) (d - m - sky); per workgroup a (hi, lo) partial of sum r^2.
 template <typename TT>
 __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
-                                                   const int32_t *__restrict__ first, const float *__restrict__ model,
-                                                   const TT *__restrict__ theta, const float *__restrict__ data,
-                                                   const float *__restrict__ weight, float *__restrict__ resid,
-                                                   float2 *__restrict__ part, unsigned int *__restrict__ counters,
-                                                   float2 *__restrict__ chi2, const int *__restrict__ mask) {
+                                                   const float *__restrict__ model, const TT *__restrict__ theta,
+                                                   const float *__restrict__ data, const float *__restrict__ weight,
+                                                   float *__restrict__ resid, float2 *__restrict__ part,
+                                                   const int *__restrict__ mask) {
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
@@ -102,36 +102,54 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
     }
   }
   const F2 tot = block_sum(acc);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = make_float2(tot.hi, tot.lo);
-    __threadfence();
-    const unsigned int n_units = (unsigned)(first[s + 1] - first[s]);
-    const unsigned int prev = atomicAdd(&counters[s], 1u);
-    if (prev == n_units - 1) {
-      __threadfence();
-      F2 r = {0.f, 0.f};
-      for (int u = first[s]; u < first[s + 1]; ++u) {
-        const float2 v = part[u];
-        F2 t = {v.x, v.y};
-        r = f2_add(r, t);
-      }
-      chi2[s] = make_float2(r.hi, r.lo);
-      counters[s] = 0u;
-    }
+  if (threadIdx.x == 0) part[blockIdx.x] = make_float2(tot.hi, tot.lo);
+}
+
+// One wave64 per stamp: the workgroup partials of the stamp, added in a fixed
+// order (each lane walks its strided share, then a shuffle tree).
+__global__ __launch_bounds__(64) void k_pair_final(const int32_t *__restrict__ first, const float2 *__restrict__ part,
+                                                   float2 *__restrict__ out, const int *__restrict__ mask) {
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  F2 r = {0.f, 0.f};
+  for (int u = first[s] + (int)threadIdx.x; u < first[s + 1]; u += 64) {
+    const float2 v = part[u];
+    F2 t = {v.x, v.y};
+    r = f2_add(r, t);
   }
+  r = wave_sum(r);
+  if (threadIdx.x == 0) out[s] = make_float2(r.hi, r.lo);
+}
+
+hipError_t launch_chi2_part(hipStream_t st, const gf_batch *b, const float *model, const double *theta,
+                            const float *data, const float *weight, float2 *part, const int *mask) {
+  dim3 grid((unsigned)b->h_pix.size()), blk(kThreads);
+  if (grid.x == 0) return hipSuccess;
+  ProfScope ps(st, "k_chi2");
+  hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, model, theta, data, weight,
+                     (float *)nullptr, part, mask);
+  return hipGetLastError();
 }
 
 hipError_t launch_chi2(hipStream_t st, const gf_batch *b, const float *model, const void *theta, bool theta_f64,
                        const float *data, const float *weight, float *resid, float2 *part, unsigned int *counters,
                        float2 *chi2, const int *mask) {
+  (void)counters;
   dim3 grid((unsigned)b->h_pix.size()), blk(kThreads);
   if (grid.x == 0) return hipSuccess;
-  if (theta_f64)
-    hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, b->d_pix_first, model,
-                       (const double *)theta, data, weight, resid, part, counters, chi2, mask);
-  else
-    hipLaunchKernelGGL((k_chi2<float>), grid, blk, 0, st, b->d_desc, b->d_pix, b->d_pix_first, model,
-                       (const float *)theta, data, weight, resid, part, counters, chi2, mask);
+  {
+    ProfScope ps(st, "k_chi2");
+    if (theta_f64)
+      hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, model, (const double *)theta,
+                         data, weight, resid, part, mask);
+    else
+      hipLaunchKernelGGL((k_chi2<float>), grid, blk, 0, st, b->d_desc, b->d_pix, model, (const float *)theta, data,
+                         weight, resid, part, mask);
+  }
+  {
+    ProfScope ps(st, "k_pair_final");
+    hipLaunchKernelGGL(k_pair_final, dim3(b->n), dim3(64), 0, st, b->d_pix_first, part, chi2, mask);
+  }
   return hipGetLastError();
 }
 
@@ -251,104 +269,96 @@ hipError_t launch_add_sky(hipStream_t st, const gf_batch *b, const float *theta,
 }
 
 // --------------------------------------------------- normal equations
-// For the stamps flagged in mask, per workgroup chunk of pixels:
-//   A_pq = sum w j_p j_q (q <= p), g_p = sum w j_p r, chi2 = sum w r^2,
-// with j the Jacobian row (convolved channels, Ie channels hold I/Ie; the
-// sky column is 1) and r = d - m, m = sky + sum_k Ie_k * chan(Ie_k).
-// jc: stamp s, channel ch at pix * nchan + ch * H*W (nchan = 7 * the
-// largest component count of the batch).
+// For the stamps flagged in mask, per workgroup chunk of kNeqChunk pixels,
+// the Gram matrix of the augmented Jacobian rows x = [j_0 .. j_{P-1}, r, 0..]
+// (16 columns: the P parameter derivatives with the sky column equal to 1,
+// then the residual r = d - m with m = sky + sum_k Ie_k chan(Ie_k)):
+//     G = sum_pixels w x x^T,
+// which holds A = J^T W J, g = J^T W r and chi^2 = r^T W r at once.  Each
+// wave64 accumulates 16 pixels per step with four v_mfma_f32_16x16x4f32
+// (FP32 in, FP32 accumulate): lane (i, k) feeds x_i of pixel k as the A
+// operand and w x_i as the B operand.  jc: stamp s, channel ch at
+// pix * nchan + ch * H*W (nchan = 7 * the largest component count).
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGramThreads = 1024;
+
 template <int NC>
-__global__ __launch_bounds__(kThreads) void k_normal_eq(const StampDesc *__restrict__ desc,
-                                                        const Work *__restrict__ work, const float *__restrict__ jc,
-                                                        const double *__restrict__ theta,
-                                                        const float *__restrict__ data,
-                                                        const float *__restrict__ weight, float *__restrict__ part,
-                                                        int nacc_stride, int nchan, const int *__restrict__ mask) {
+__global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
+                                                   const float *__restrict__ jc, int nchan,
+                                                   const double *__restrict__ theta, const float *__restrict__ data,
+                                                   const float *__restrict__ weight, float *__restrict__ part,
+                                                   const int *__restrict__ mask) {
   constexpr int P = kNPC * NC + 1;
-  constexpr int NA = P * (P + 1) / 2 + P + 1;
-  __shared__ float red[kThreads / 64][NA];
-  const Work w = work[blockIdx.x];
-  const int s = w.stamp;
+  static_assert(P + 1 <= 16, "augmented Jacobian must fit 16 columns");
+  __shared__ float red[kGramThreads / 64][256];
+  const Work wk = work[blockIdx.x];
+  const int s = wk.stamp;
   if (mask && !mask[s]) return;
   const StampDesc d = desc[s];
   if (d.ncomp != NC) return;
   const int npix = d.H * d.W;
-  const int64_t plane = npix;
   const float *J = jc + d.pix * (int64_t)nchan;
   float ie[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) ie[k] = (float)theta[d.par + kNPC * k + 2];
   const float sky = (float)theta[d.par + kNPC * NC];
-  float acc[NA];
-#pragma unroll
-  for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
-  const int p0 = w.unit * kNeqChunk;
-#pragma unroll 1
-  for (int k = 0; k < kNeqChunk / kThreads; ++k) {
-    const int p = p0 + k * kThreads + (int)threadIdx.x;
-    if (p >= npix) break;
-    float j[P];
-#pragma unroll
-    for (int q = 0; q < P - 1; ++q) j[q] = J[q * plane + p];
-    j[P - 1] = 1.0f;
-    float m = sky;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) m = fmaf(ie[c], j[kNPC * c + 2], m);
-    const float wt = weight[d.img + p];
-    const float r = data[d.img + p] - m;
-    const float wr = wt * r;
-    int a = 0;
-#pragma unroll
-    for (int p1 = 0; p1 < P; ++p1) {
-      const float wj = wt * j[p1];
-#pragma unroll
-      for (int p2 = 0; p2 <= p1; ++p2) {
-        acc[a] = fmaf(wj, j[p2], acc[a]);
-        ++a;
-      }
-    }
-#pragma unroll
-    for (int p1 = 0; p1 < P; ++p1) {
-      acc[a] = fmaf(wr, j[p1], acc[a]);
-      ++a;
-    }
-    acc[a] = fmaf(wr, r, acc[a]);
-  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  constexpr int per_wave = kNeqChunk / (kGramThreads / 64);
+  const int base = wk.unit * kNeqChunk + wv * per_wave;
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int ich = i < P - 1 ? i : 0;  // channel read by this lane (clamped for the sky / residual lanes)
+#pragma unroll 4
+  for (int g = 0; g < per_wave; g += 16) {
 #pragma unroll
-  for (int a = 0; a < NA; ++a) {
-    float v = acc[a];
+    for (int q = 0; q < 4; ++q) {
+      const int p = base + g + 4 * kk + q;
+      const bool ok = p < npix;
+      const int pc = ok ? p : npix - 1;  // in-bounds address for the straight-line loads
+      const float wt = weight[d.img + pc];
+      const float jv = J[(int64_t)ich * npix + pc];
+      const float dv = data[d.img + pc];
+      float m = sky;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[wv][a] = v;
+      for (int c = 0; c < NC; ++c) m = fmaf(ie[c], J[(int64_t)(kNPC * c + 2) * npix + pc], m);
+      float x = (i < P - 1) ? jv : (i == P - 1) ? 1.0f : (i == P) ? dv - m : 0.0f;
+      x = ok ? x : 0.0f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, (ok ? wt : 0.0f) * x, acc, 0, 0, 0);
+    }
   }
+  // lane (col = lane % 16, rows 4*(lane/16) .. +3) holds G[row][col]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wv][(4 * kk + r) * 16 + i] = acc[r];
   __syncthreads();
-  for (int a = threadIdx.x; a < NA; a += blockDim.x) {
+  if (threadIdx.x < 256) {
+    const int e = threadIdx.x;  // 256 entries, one per thread
     float v = 0.0f;
 #pragma unroll
-    for (int ww = 0; ww < kThreads / 64; ++ww) v += red[ww][a];
-    part[(int64_t)blockIdx.x * nacc_stride + a] = v;
+    for (int ww = 0; ww < kGramThreads / 64; ++ww) v += red[ww][e];
+    part[(int64_t)blockIdx.x * 256 + e] = v;
   }
 }
 
 hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, const double *theta,
                             const float *data, const float *weight, float *part, int nacc_stride, int nchan,
                             const int *mask) {
-  dim3 grid((unsigned)b->h_neq.size()), blk(kThreads);
+  (void)nacc_stride;
+  dim3 grid((unsigned)b->h_neq.size()), blk(kGramThreads);
   if (grid.x == 0) return hipSuccess;
+  ProfScope ps(st, "k_gram");
   bool has1 = false, has2 = false;
   for (const auto &d : b->h_desc) {
     has1 |= d.ncomp == 1;
     has2 |= d.ncomp == 2;
   }
   if (has1)
-    hipLaunchKernelGGL((k_normal_eq<1>), grid, blk, 0, st, b->d_desc, b->d_neq, jc, theta, data, weight, part,
-                       nacc_stride, nchan, mask);
+    hipLaunchKernelGGL((k_gram<1>), grid, blk, 0, st, b->d_desc, b->d_neq, jc, nchan, theta, data, weight, part, mask);
   if (has2)
-    hipLaunchKernelGGL((k_normal_eq<2>), grid, blk, 0, st, b->d_desc, b->d_neq, jc, theta, data, weight, part,
-                       nacc_stride, nchan, mask);
+    hipLaunchKernelGGL((k_gram<2>), grid, blk, 0, st, b->d_desc, b->d_neq, jc, nchan, theta, data, weight, part, mask);
   return hipGetLastError();
 }
+
 
 // ------------------------------------------------------------- LM kernels
 struct LMParams {
@@ -400,89 +410,115 @@ __global__ void k_lm_clip(int64_t n_par, double *__restrict__ theta, const doubl
   theta_t[i] = v;
 }
 
-// One wave64 per stamp: form A, g (FP64 sums of the workgroup partials) when
-// the Jacobian is new, damp, factor by Cholesky, solve, write the clipped
-// trial point.
-__global__ __launch_bounds__(64) void k_lm_solve(const StampDesc *__restrict__ desc,
-                                                 const int32_t *__restrict__ neq_first,
-                                                 const float *__restrict__ part, int nacc_stride,
-                                                 LMParams prm, LMState *__restrict__ st,
-                                                 double *__restrict__ Ag /* per stamp kMaxP*kMaxP + kMaxP */,
-                                                 const double *__restrict__ theta, double *__restrict__ theta_t,
-                                                 int *__restrict__ mjac, int *__restrict__ mtrial) {
-  __shared__ double A[kMaxP * kMaxP];
-  __shared__ double g[kMaxP];
-  __shared__ double Lm[kMaxP * kMaxP];
-  __shared__ double y[kMaxP];
-  __shared__ int idx[kMaxP];
+// Solve for one stamp per workgroup of 1024 threads.  When the Jacobian is
+// new, four slices of 256 threads add the 256 Gram entries over the stamp's
+// workgroup partials in FP64 (eight independent chains per thread, slices
+// combined in a fixed order) and A = G[0..P-1][0..P-1]
+// (symmetrised from the lower triangle), g = G[0..P-1][P] are kept in Ag.
+// Then the damped system over the free parameters is factored by a Cholesky
+// in which lane i of the first wave keeps row i in registers and the finished
+// rows are broadcast through LDS; lane 0 does the two triangular solves in
+// FP64 and writes the clipped trial point.  Block 0 also clears the count of
+// active stamps that the update kernel of this iteration fills.
+constexpr int kSolveThreads = 1024;
+
+template <int NC>
+__global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__restrict__ desc,
+                                                       const int32_t *__restrict__ neq_first,
+                                                       const float *__restrict__ part, LMParams prm,
+                                                       LMState *__restrict__ st, double *__restrict__ Ag,
+                                                       const double *__restrict__ theta, double *__restrict__ theta_t,
+                                                       int *__restrict__ mjac, int *__restrict__ mtrial,
+                                                       int *__restrict__ active_count) {
+  constexpr int P = kNPC * NC + 1;
+  __shared__ double G[kSolveThreads / 256][256];
+  __shared__ double Lr[P][P];
+  __shared__ double y[P];
+  __shared__ double dmax_s;
+  __shared__ int idx[P];
   __shared__ int nf_s, ok_s;
   const int s = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  if (s == 0 && tid == 0) *active_count = 0;
+  const StampDesc d = desc[s];
+  if (d.ncomp != NC) return;
   LMState S = st[s];
   if (!S.active) return;
-  const StampDesc d = desc[s];
-  const int P = kNPC * d.ncomp + 1;
   double *Ags = Ag + (int64_t)s * (kMaxP * kMaxP + kMaxP);
   if (S.need_jac) {
-    // accumulator order: lower triangle row-major (p1 >= p2), then g, then chi2
-    const int NA = P * (P + 1) / 2 + P + 1;
-    for (int a = lane; a < NA - 1; a += 64) {
-      double v = 0.0;
-      for (int u = neq_first[s]; u < neq_first[s + 1]; ++u) v += (double)part[(int64_t)u * nacc_stride + a];
-      if (a < P * (P + 1) / 2) {
-        int p1 = 0;
-        while ((p1 + 1) * (p1 + 2) / 2 <= a) ++p1;
-        const int p2 = a - p1 * (p1 + 1) / 2;
-        Ags[p1 * kMaxP + p2] = v;
-        Ags[p2 * kMaxP + p1] = v;
-      } else {
-        Ags[kMaxP * kMaxP + (a - P * (P + 1) / 2)] = v;
-      }
+    // thread (slice, entry): slice sl adds partials u0 + sl, u0 + sl + 4, ...
+    constexpr int NS = kSolveThreads / 256;
+    const int e = tid & 255, sl = tid >> 8;
+    const int u0 = neq_first[s], u1 = neq_first[s + 1];
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int u = u0 + sl;
+    for (; u + 7 * NS < u1; u += 8 * NS) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] += (double)part[(int64_t)(u + q * NS) * 256 + e];
+    }
+    for (; u < u1; u += NS) v[0] += (double)part[(int64_t)u * 256 + e];
+    G[sl][e] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    __syncthreads();
+    if (tid < 256) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) t += G[q][tid];
+      G[0][tid] = t;
     }
     __syncthreads();
-  }
-  if (lane == 0) {
-    int nf = 0;
-    for (int p = 0; p < P; ++p)
-      if (!prm.free_mask || prm.free_mask[d.par + p]) idx[nf++] = p;
-    nf_s = nf;
-  }
-  __syncthreads();
-  const int nf = nf_s;
-  for (int e = lane; e < nf * nf; e += 64) {
-    const int a = e / nf, b = e - a * nf;
-    A[e] = Ags[idx[a] * kMaxP + idx[b]];
-  }
-  for (int a = lane; a < nf; a += 64) g[a] = Ags[kMaxP * kMaxP + idx[a]];
-  __syncthreads();
-  if (lane == 0) {
-    double dmax = 0.0;
-    for (int a = 0; a < nf; ++a) dmax = fmax(dmax, A[a * nf + a]);
-    for (int a = 0; a < nf; ++a) {
-      const double da = fmax(A[a * nf + a], 1e-12 * dmax);
-      A[a * nf + a] += S.lambda * da;
+    if (tid < P * P) {
+      const int a = tid / P, b = tid - a * P;
+      const int hi = a > b ? a : b, lo = a > b ? b : a;
+      Ags[a * kMaxP + b] = G[0][hi * 16 + lo];
     }
+    if (tid < P) Ags[kMaxP * kMaxP + tid] = G[0][tid * 16 + P];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int nf = 0;
+    double dm = 0.0;
+    for (int p = 0; p < P; ++p)
+      if (!prm.free_mask || prm.free_mask[d.par + p]) {
+        idx[nf++] = p;
+        dm = fmax(dm, Ags[p * kMaxP + p]);
+      }
+    nf_s = nf;
+    dmax_s = dm;
     ok_s = 1;
   }
   __syncthreads();
-  // Cholesky A = L L^T, column by column; rows of a column in parallel.
-  for (int j = 0; j < nf; ++j) {
-    if (lane == 0) {
-      double sj = A[j * nf + j];
-      for (int k = 0; k < j; ++k) sj -= Lm[j * nf + k] * Lm[j * nf + k];
-      if (!(sj > 0.0) || !isfinite(sj)) ok_s = 0;
-      Lm[j * nf + j] = sqrt(fmax(sj, 0.0));
+  const int nf = nf_s;
+  // lane i < nf holds row i of the damped matrix (later of L)
+  double row[P];
+  const bool mine = tid < nf;
+#pragma unroll
+  for (int k = 0; k < P; ++k) row[k] = (mine && k < nf) ? Ags[idx[tid] * kMaxP + idx[k]] : 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    if (mine && k == tid) row[k] += S.lambda * fmax(row[k], 1e-12 * dmax_s);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (j < nf) {
+      if (tid == j) {
+        double sj = row[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sj -= row[k] * row[k];
+        if (!(sj > 0.0) || !isfinite(sj)) ok_s = 0;
+        row[j] = sqrt(fmax(sj, 0.0));
+#pragma unroll
+        for (int k = 0; k <= j; ++k) Lr[j][k] = row[k];
+      }
+      __syncthreads();
+      if (ok_s && mine && tid > j) {
+        double t = row[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) t -= row[k] * Lr[j][k];
+        row[j] = t / Lr[j][j];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (!ok_s) break;
-    for (int i = j + 1 + lane; i < nf; i += 64) {
-      double t = A[i * nf + j];
-      for (int k = 0; k < j; ++k) t -= Lm[i * nf + k] * Lm[j * nf + k];
-      Lm[i * nf + j] = t / Lm[j * nf + j];
-    }
-    __syncthreads();
   }
-  if (lane == 0) {
+  if (tid == 0) {
     S.iters += 1;
     if (S.need_jac) {
       S.need_jac = 0;
@@ -500,14 +536,14 @@ __global__ __launch_bounds__(64) void k_lm_solve(const StampDesc *__restrict__ d
       }
     } else {
       for (int i = 0; i < nf; ++i) {
-        double t = g[i];
-        for (int k = 0; k < i; ++k) t -= Lm[i * nf + k] * y[k];
-        y[i] = t / Lm[i * nf + i];
+        double t = Ags[kMaxP * kMaxP + idx[i]];
+        for (int k = 0; k < i; ++k) t -= Lr[i][k] * y[k];
+        y[i] = t / Lr[i][i];
       }
       for (int i = nf - 1; i >= 0; --i) {
         double t = y[i];
-        for (int k = i + 1; k < nf; ++k) t -= Lm[k * nf + i] * y[k];
-        y[i] = t / Lm[i * nf + i];
+        for (int k = i + 1; k < nf; ++k) t -= Lr[k][i] * y[k];
+        y[i] = t / Lr[i][i];
       }
       for (int p = 0; p < P; ++p) theta_t[d.par + p] = theta[d.par + p];
       for (int a = 0; a < nf; ++a) {
@@ -524,65 +560,71 @@ __global__ __launch_bounds__(64) void k_lm_solve(const StampDesc *__restrict__ d
   }
 }
 
-// Accept or reject the trial point, update lambda, test the stop rules and
-// count the stamps still active (single workgroup).
-__global__ __launch_bounds__(1024) void k_lm_update(const StampDesc *__restrict__ desc, int n, LMParams prm,
-                                                    const float2 *__restrict__ chi2t, LMState *__restrict__ st,
-                                                    double *__restrict__ theta, const double *__restrict__ theta_t,
-                                                    int *__restrict__ mjac, int *__restrict__ mtrial,
-                                                    int *__restrict__ active_count) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  int mine = 0;
-  for (int s = threadIdx.x; s < n; s += blockDim.x) {
-    LMState S = st[s];
-    if (!S.active) continue;
-    const StampDesc d = desc[s];
-    const int P = kNPC * d.ncomp + 1;
-    if (S.trial) {
-      S.nfev += 1;
-      const double c2 = (double)chi2t[s].x + (double)chi2t[s].y;
-      S.chi2_trial = c2;
-      if (c2 < S.chi2) {
-        double step = 0.0;
-        for (int p = 0; p < P; ++p) {
-          const int64_t i = d.par + p;
-          if (prm.free_mask && !prm.free_mask[i]) continue;
-          const double sc = fmax(fabs(theta[i]), 1.0);
-          step = fmax(step, fabs(theta_t[i] - theta[i]) / sc);
-        }
-        const double rel = c2 > 0.0 ? (S.chi2 - c2) / c2 : 0.0;
-        for (int p = 0; p < P; ++p) theta[d.par + p] = theta_t[d.par + p];
-        S.chi2 = c2;
-        S.lambda /= prm.lambda_down;
-        S.need_jac = 1;
-        if (c2 == 0.0) {
-          S.active = 0; S.status = GF_OK; S.reason = 3;
-        } else if (rel < prm.ftol) {
-          S.active = 0; S.status = GF_OK; S.reason = 1;
-        } else if (step < prm.xtol) {
-          S.active = 0; S.status = GF_OK; S.reason = 2;
-        }
-      } else {
-        S.lambda *= prm.lambda_up;
-        if (S.lambda > prm.lambda_max) {
-          S.active = 0; S.status = GF_ENOTCONV; S.reason = 4;
-        }
+// Finish the trial chi^2 of every active stamp (one wave per stamp: its
+// workgroup partials added in a fixed order), accept or reject the trial
+// point, update lambda, test the stop rules, and count the stamps still
+// active.
+__global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ desc,
+                                                  const int32_t *__restrict__ pix_first,
+                                                  const float2 *__restrict__ part, LMParams prm,
+                                                  LMState *__restrict__ st, double *__restrict__ theta,
+                                                  const double *__restrict__ theta_t, int *__restrict__ mjac,
+                                                  int *__restrict__ mtrial, int *__restrict__ active_count) {
+  const int s = blockIdx.x;
+  LMState S = st[s];
+  if (!S.active) return;
+  const StampDesc d = desc[s];
+  const int P = kNPC * d.ncomp + 1;
+  double c2 = 0.0;
+  if (S.trial) {
+    F2 r = {0.f, 0.f};
+    for (int u = pix_first[s] + (int)threadIdx.x; u < pix_first[s + 1]; u += 64) {
+      const float2 v = part[u];
+      F2 t = {v.x, v.y};
+      r = f2_add(r, t);
+    }
+    r = wave_sum(r);
+    c2 = (double)r.hi + (double)r.lo;
+  }
+  if (threadIdx.x != 0) return;
+  if (S.trial) {
+    S.nfev += 1;
+    S.chi2_trial = c2;
+    if (c2 < S.chi2) {
+      double step = 0.0;
+      for (int p = 0; p < P; ++p) {
+        const int64_t i = d.par + p;
+        if (prm.free_mask && !prm.free_mask[i]) continue;
+        const double sc = fmax(fabs(theta[i]), 1.0);
+        step = fmax(step, fabs(theta_t[i] - theta[i]) / sc);
+      }
+      const double rel = c2 > 0.0 ? (S.chi2 - c2) / c2 : 0.0;
+      for (int p = 0; p < P; ++p) theta[d.par + p] = theta_t[d.par + p];
+      S.chi2 = c2;
+      S.lambda /= prm.lambda_down;
+      S.need_jac = 1;
+      if (c2 == 0.0) {
+        S.active = 0; S.status = GF_OK; S.reason = 3;
+      } else if (rel < prm.ftol) {
+        S.active = 0; S.status = GF_OK; S.reason = 1;
+      } else if (step < prm.xtol) {
+        S.active = 0; S.status = GF_OK; S.reason = 2;
+      }
+    } else {
+      S.lambda *= prm.lambda_up;
+      if (S.lambda > prm.lambda_max) {
+        S.active = 0; S.status = GF_ENOTCONV; S.reason = 4;
       }
     }
-    if (S.active && S.iters >= prm.max_iter) {
-      S.active = 0; S.status = GF_ENOTCONV; S.reason = 5;
-    }
-    S.trial = 0;
-    mtrial[s] = 0;
-    mjac[s] = S.active && S.need_jac;
-    st[s] = S;
-    mine += S.active;
   }
-  atomicAdd(&cnt, mine);
-  __syncthreads();
-  if (threadIdx.x == 0) *active_count = cnt;
+  if (S.active && S.iters >= prm.max_iter) {
+    S.active = 0; S.status = GF_ENOTCONV; S.reason = 5;
+  }
+  S.trial = 0;
+  mtrial[s] = 0;
+  mjac[s] = S.active && S.need_jac;
+  st[s] = S;
+  if (S.active) atomicAdd(active_count, 1);
 }
 
 __global__ void k_lm_result(int n, const LMState *__restrict__ st, gf_lm_result *__restrict__ res) {
@@ -615,22 +657,32 @@ hipError_t launch_lm_clip(hipStream_t st, int64_t n_par, double *theta, const do
   return hipGetLastError();
 }
 
-hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, int nacc_stride,
-                           const gf_lm_opts *o, LMState *S, double *Ag, const double *theta, double *theta_t,
-                           int *mjac, int *mtrial) {
+hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, const gf_lm_opts *o, LMState *S,
+                           double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial, int *cnt) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask};
-  hipLaunchKernelGGL(k_lm_solve, dim3(b->n), dim3(64), 0, st, b->d_desc, b->d_neq_first, part, nacc_stride, prm, S,
-                     Ag, theta, theta_t, mjac, mtrial);
+  ProfScope ps(st, "k_lm_solve");
+  bool has1 = false, has2 = false;
+  for (const auto &d : b->h_desc) {
+    has1 |= d.ncomp == 1;
+    has2 |= d.ncomp == 2;
+  }
+  if (has1)
+    hipLaunchKernelGGL((k_lm_solve<1>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part, prm, S,
+                       Ag, theta, theta_t, mjac, mtrial, cnt);
+  if (has2)
+    hipLaunchKernelGGL((k_lm_solve<2>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part, prm, S,
+                       Ag, theta, theta_t, mjac, mtrial, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const float2 *chi2t,
-                            LMState *S, double *theta, const double *theta_t, int *mjac, int *mtrial, int *cnt) {
+hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const float2 *part, LMState *S,
+                            double *theta, const double *theta_t, int *mjac, int *mtrial, int *cnt) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask};
-  hipLaunchKernelGGL(k_lm_update, dim3(1), dim3(1024), 0, st, b->d_desc, b->n, prm, chi2t, S, theta, theta_t, mjac,
-                     mtrial, cnt);
+  ProfScope ps(st, "k_lm_update");
+  hipLaunchKernelGGL(k_lm_update, dim3(b->n), dim3(64), 0, st, b->d_desc, b->d_pix_first, part, prm, S, theta,
+                     theta_t, mjac, mtrial, cnt);
   return hipGetLastError();
 }
 
