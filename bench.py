@@ -47,10 +47,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--breakdown", action="store_true", help="print the per-kernel breakdown to stderr")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB device buffer three times (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -74,6 +76,9 @@ def kernel_work(name, geo, launches_per_step):
         return "hbm", npix * 4 + geo.get("nimg", npix) * 8, "byte"
     if name == "k_gram":
         return "hbm", npix * (4 * nch + 8), "byte"
+    if name in ("k_fft_rows", "k_fft_cols", "k_fft_irows") and "fft_bytes" in geo:
+        per_ch, once = geo["fft_bytes"][name]
+        return "hbm", geo.get("chan_" + name, 1) * per_ch + once, "byte"
     if name in ("k_fft_rows", "k_fft_cols", "k_fft_irows"):
         c = geo.get("chan_" + name, 1)
         if name == "k_fft_rows":
@@ -147,6 +152,83 @@ def run_c2(args, torch, ops, synth):
                     image=[st.H, st.W], psf=st.K, fft_side=psf.fft_side[0], params=15, oversample=5),
     )
     return result, prof, geo, dict(st=st, nfev=nfev, njev=njev, iters=iters, npix=npix)
+
+
+def run_c3(args, torch, ops, synth):
+    """4096 uneven single-Sersic stamps fitted in one gf_fit_lm call (ftol 1e-5)."""
+    dev = torch.device("cuda", 0)
+    stamps = synth.c3(4096)
+    n = len(stamps)
+    ctx = ops.Context(0)
+    H = [s.H for s in stamps]
+    K = [s.K for s in stamps]
+    batch = ops.Batch(ctx, H, H, K, [1] * n)
+    taps = torch.from_numpy(np.concatenate([s.psf.astype(np.float32).ravel() for s in stamps])).to(dev)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
+    truth = torch.from_numpy(np.concatenate([s.truth for s in stamps]).astype(np.float32)).to(dev)
+    m_true = ops.model(ctx, batch, psf, truth, 5).cpu().numpy().astype(np.float64)
+    off = batch.offsets["pix"]
+    d = np.empty_like(m_true)
+    w = np.empty_like(m_true)
+    for i, st in enumerate(stamps):
+        sl = slice(off[i], off[i] + st.H * st.W)
+        d[sl], w[sl] = synth.add_gaussian_noise(m_true[sl], st.noise_sigma, st.noise_seed)
+    data = torch.from_numpy(d.astype(np.float32)).to(dev)
+    weight = torch.from_numpy(w.astype(np.float32)).to(dev)
+    lo = np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in stamps])
+    hi = np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in stamps])
+    lo_t, hi_t = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    theta0 = torch.from_numpy(np.concatenate([s.start for s in stamps])).to(dev)
+
+    def step(**kw):
+        o = dict(ftol=1e-5, max_iter=100)
+        o.update(kw)
+        return ops.fit_lm(ctx, batch, psf, data, weight, theta0, lo=lo_t, hi=hi_t, **o)
+
+    K_ = args.steps if args.steps is not None else 5
+    W = args.warmup if args.warmup is not None else 1
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K_):
+        _, info = step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms = t / K_ * 1e3
+    from paper_1101_2254_amd import _lib
+    _lib.gf_profile_start(ctx.ptr)
+    step(use_graph=0)
+    torch.cuda.synchronize()
+    _lib.gf_profile_stop(ctx.ptr)
+    prof = _lib.gf_profile_read(ctx.ptr)
+    npix = int(sum(s.H * s.W for s in stamps))
+    npad = int(sum((s.H + s.K - 1) ** 2 for s in stamps))
+    evals = int(info["nfev"].sum() + info["njev"].sum())
+    result = dict(
+        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
+        value=round(n / (ms * 1e-3), 2), unit="fits/s", ms_per_step=round(ms, 3),
+        mpix_per_s=round(evals / n * npix / n * n / (ms * 1e-3) / 1e6, 2),
+        lm=dict(iters_mean=float(info["iters"].mean()), iters_max=int(info["iters"].max()),
+                converged=float((info["status"] == 0).mean()), nfev=int(info["nfev"].sum()),
+                njev=int(info["njev"].sum())),
+        config=dict(workload="C3: 4096 uneven single-Sersic stamps (32..256 px, Gaussian/Moffat PSF 15..33 px), "
+                             "one gf_fit_lm call to chi2 rel tol 1e-5; one step = the whole batch",
+                    stamps=n, pixels=npix, oversample=5,
+                    fft_stamps=int(sum(psf.uses_fft)), direct_stamps=int(n - sum(psf.uses_fft))),
+    )
+    fb = {"k_fft_rows": [0, 0], "k_fft_cols": [0, 0], "k_fft_irows": [0, 0]}
+    for st, uf, L in zip(stamps, psf.uses_fft, psf.fft_side):
+        if not uf:
+            continue
+        M, Lh = st.H + st.K - 1, L // 2 + 1
+        fb["k_fft_rows"][0] += M * M * 4 + M * Lh * 8
+        fb["k_fft_cols"][0] += M * Lh * 8 + st.H * Lh * 8
+        fb["k_fft_cols"][1] += L * Lh * 8
+        fb["k_fft_irows"][0] += st.H * Lh * 8 + st.H * st.W * 4
+    geo = dict(npix=npix, npad=npad, Mw=1, H=1, nch=7, ncomp=1, S=5, L=2, fft_bytes=fb)
+    return result, prof, geo, dict(stamps=stamps, info=info, npix=npix, nfev=int(info["nfev"].sum()),
+                                   njev=int(info["njev"].sum()))
 
 
 def run_c4(args, torch, ops, synth):
@@ -283,6 +365,41 @@ def cpu_baseline_c4(extra, seconds):
                        f"its own rendering of the image, {t:.1f} s on {gfo.get_threads()} threads")
 
 
+def cpu_baseline_c3(extra, seconds):
+    """Stratified sample: per stamp size, the oracle's first LM iteration on its
+    own rendering of one stamp of that size, scaled by the GPU run's mean
+    iteration count for that size (extrapolated)."""
+    from oracle import gfo
+    import synth
+    gfo.set_threads(os.cpu_count() or 1)
+    stamps, info = extra["stamps"], extra["info"]
+    total = 0.0
+    used = []
+    t_all = time.perf_counter()
+    for N in synth.C3_SIZES:
+        idx = [i for i, st in enumerate(stamps) if st.H == N]
+        if not idx:
+            continue
+        st = stamps[idx[0]]
+        psf = st.psf.astype(np.float32).astype(np.float64)
+        m = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf, 5)
+        d, w = synth.add_gaussian_noise(m, st.noise_sigma, st.noise_seed)
+        lo, hi = synth.bounds(1, st.H, st.W)
+        t0 = time.perf_counter()
+        gfo.fit_lm(st.start, psf, d.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64),
+                   5, lo=lo, hi=hi, ftol=1e-5, max_iter=1)
+        t1 = time.perf_counter() - t0
+        iters = float(np.mean(info["iters"][idx]))
+        total += t1 * iters * len(idx)
+        used.append(f"{N}:{t1 * 1e3:.0f}ms")
+        if time.perf_counter() - t_all > seconds * 4:
+            break
+    return dict(value=round(len(stamps) / total, 4), unit="fits/s", cores=gfo.get_threads(), kind="oracle",
+                sample="extrapolated: one oracle LM iteration (start evaluation + Jacobian + step) per stamp size "
+                       "on its own rendering, times the GPU run's mean iterations per size and the stamps per size ("
+                       + ", ".join(used) + ")")
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -297,20 +414,40 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=src.numel() * 4, copies=3)))
+        return
     print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
     if args.workload == "c2":
         result, prof, geo, extra = run_c2(args, torch, ops, synth)
+    elif args.workload == "c3":
+        result, prof, geo, extra = run_c3(args, torch, ops, synth)
     else:
         result, prof, geo, extra = run_c4(args, torch, ops, synth)
     geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = 1
-    if args.workload == "c2":
-        # per fit the FFT passes run 14 channels (Jacobian) and 1 channel (trial) per launch: use the average
+    if args.workload in ("c2", "c3"):
+        # per fit the FFT passes run 7 n_comp channels (Jacobian) and 1 channel (trial) per launch: use the average
         n_jac = extra["njev"]
         n_trial = extra["nfev"]
-        avg = (14 * n_jac + 1 * n_trial) / max(n_jac + n_trial, 1)
+        nch = 14 if args.workload == "c2" else 7
+        avg = (nch * n_jac + 1 * n_trial) / max(n_jac + n_trial, 1)
         for k in ("rows", "cols", "irows"):
             geo["chan_k_fft_" + k] = avg
     rl, stages = roofline(prof, geo)
+    if args.workload == "c3":
+        # finished stamps skip their work units, so per-launch bytes of the
+        # whole batch overstate what a launch moves: report times only
+        for k in stages:
+            for f in ("bound", "gbs", "tflops", "frac"):
+                stages[k].pop(f, None)
+        rl = dict(bound=None, kernel=rl["kernel"], achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                  avg_launch_us=rl["avg_launch_us"],
+                  note="per-launch work varies as stamps finish; see the C2 and C4 workloads for rooflines")
     print(f"bench: {result['value']} {result['unit']}, {result['ms_per_step']} ms/step", file=sys.stderr,
           flush=True)
     if args.breakdown:
@@ -321,14 +458,17 @@ def main():
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data="synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)",
                config=result["config"], roofline=rl)
-    for k in ("fits_per_s", "lm"):
+    for k in ("fits_per_s", "lm", "mpix_per_s"):
         if k in result:
             out[k] = result[k]
     out["stages"] = stages
     if not args.no_cpu:
-        cb = cpu_baseline_c2(extra, args.cpu_seconds) if args.workload == "c2" else cpu_baseline_c4(
-            extra, args.cpu_seconds)
-        out["cpu_baseline"] = cb
+        if args.workload == "c2":
+            out["cpu_baseline"] = cpu_baseline_c2(extra, args.cpu_seconds)
+        elif args.workload == "c3":
+            out["cpu_baseline"] = cpu_baseline_c3(extra, args.cpu_seconds)
+        else:
+            out["cpu_baseline"] = cpu_baseline_c4(extra, args.cpu_seconds)
     print(json.dumps(out))
 
 

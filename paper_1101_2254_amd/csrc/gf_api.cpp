@@ -37,8 +37,8 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *, float *, int, int, const int *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
-hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
-                           const double *, double *, int *, int *, int *);
+hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, double *, const gf_lm_opts *, LMState *,
+                           double *, const double *, double *, int *, int *, int *);
 hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const double *, const float *,
                             const float *, float2 *, const int *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
@@ -419,6 +419,12 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) p->h_arows.push_back({s, u});
     for (int u = 0; u < cols; ++u) p->h_acols.push_back({s, u});
     for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_airows.push_back({s, u});
+    {
+      const int Tn = std::min(T, kFftNarrowT), Cn = std::min(C, kFftNarrowC);
+      for (int u = 0; u < (d.Mh + 2 * Tn - 1) / (2 * Tn); ++u) p->h_rows_n.push_back({s, u});
+      for (int u = 0; u < (Lh + Cn - 1) / Cn; ++u) p->h_cols_n.push_back({s, u});
+      for (int u = 0; u < (d.H + 2 * Tn - 1) / (2 * Tn); ++u) p->h_irows_n.push_back({s, u});
+    }
     p->h_s1[s] = p->n_s1;
     p->n_s1 += (int64_t)d.Mh * Lh;
     p->h_s2[s] = p->n_s2;
@@ -451,6 +457,9 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   if (e == hipSuccess) e = upload(&p->d_arows, p->h_arows);
   if (e == hipSuccess) e = upload(&p->d_acols, p->h_acols);
   if (e == hipSuccess) e = upload(&p->d_airows, p->h_airows);
+  if (e == hipSuccess) e = upload(&p->d_rows_n, p->h_rows_n);
+  if (e == hipSuccess) e = upload(&p->d_cols_n, p->h_cols_n);
+  if (e == hipSuccess) e = upload(&p->d_irows_n, p->h_irows_n);
   if (e == hipSuccess) e = upload(&p->d_s1, p->h_s1);
   if (e == hipSuccess) e = upload(&p->d_s2, p->h_s2);
   if (e == hipSuccess) e = upload(&p->d_s1a, p->h_s1a);
@@ -504,6 +513,9 @@ void gf_psf_destroy(gf_psf *p) {
   dfree(p->d_arows);
   dfree(p->d_acols);
   dfree(p->d_airows);
+  dfree(p->d_rows_n);
+  dfree(p->d_cols_n);
+  dfree(p->d_irows_n);
   dfree(p->d_s1);
   dfree(p->d_s2);
   dfree(p->d_s1a);
@@ -714,7 +726,7 @@ namespace {
 struct LMBufs {
   float *cpad, *jc, *mpad, *mconv, *npart;
   float2 *S1, *S2, *chi2t, *cpart;
-  double *Ag, *theta_t;
+  double *Ag, *theta_t, *Gsum;
   LMState *st;
   int *mjac, *mtrial, *cnt;
 };
@@ -726,6 +738,7 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.S2 = a.take<float2>(p->n_s2 * nchan);
   B.npart = a.take<float>((int64_t)b->h_neq.size() * nacc);
   B.Ag = a.take<double>((int64_t)b->n * (kMaxP * kMaxP + kMaxP));
+  B.Gsum = a.take<double>((int64_t)b->n * 256);
   B.theta_t = a.take<double>(b->n_par);
   B.mpad = a.take<float>(b->n_pad);
   B.mconv = a.take<float>(b->n_pix);
@@ -793,7 +806,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac));
-      GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
+      GF_TRY(c, launch_lm_solve(cs, b, B.npart, B.Gsum, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial));
       GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial));

@@ -18,9 +18,11 @@ constexpr int kMaxP = kNPC * kMaxComp + 1;
 constexpr int kThreads = 256;          // threads per workgroup for pixel kernels (4 wave64)
 constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one per thread)
 constexpr int kPixChunk = 2048;        // pixels per chi^2 workgroup (8 per thread)
-constexpr int kNeqChunk = 4096;        // pixels per normal-equation workgroup (16 waves, 256 per wave)
+constexpr int kNeqChunk = 1024;        // pixels per normal-equation workgroup (256 per wave)
 constexpr int kFftCap = 3840;          // complex values in the FFT LDS buffer (T*L <= this)
 constexpr int kFftMaxStages = 12;
+constexpr int kFftNarrowT = 1;         // row pairs per workgroup in the narrow launch shape
+constexpr int kFftNarrowC = 2;         // bins per workgroup in the narrow launch shape
 constexpr int kDirectTH = 16;          // direct convolution output tile rows
 constexpr int kDirectTW = 64;          // direct convolution output tile columns
 constexpr int kDirectMaxK = 41;        // largest PSF side on the direct path
@@ -198,6 +200,8 @@ struct gf_psf {
   std::vector<gf::Work> h_rows, h_cols, h_irows, h_arows, h_acols, h_airows;
   gf::Work *d_rows = nullptr, *d_cols = nullptr, *d_irows = nullptr;
   gf::Work *d_arows = nullptr, *d_acols = nullptr, *d_airows = nullptr;  // adjoint (correlation) lists
+  std::vector<gf::Work> h_rows_n, h_cols_n, h_irows_n;                // narrow launch shape
+  gf::Work *d_rows_n = nullptr, *d_cols_n = nullptr, *d_irows_n = nullptr;
   std::vector<int64_t> h_s1, h_s2;   // per-stamp offsets (complex) into the two spectra buffers, per channel
   int64_t n_s1 = 0, n_s2 = 0, n_s1a = 0, n_s2a = 0;
   int64_t *d_s1 = nullptr, *d_s2 = nullptr, *d_s1a = nullptr, *d_s2a = nullptr;

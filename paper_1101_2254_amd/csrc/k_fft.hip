@@ -244,7 +244,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
                                                        const float2 *__restrict__ tw_all,
                                                        const Work *__restrict__ work, const float *__restrict__ in,
                                                        int n_ch, const int64_t *__restrict__ s1_off,
-                                                       float2 *__restrict__ S1, const int *__restrict__ mask) {
+                                                       float2 *__restrict__ S1, const int *__restrict__ mask,
+                                                       int tmax) {
   extern __shared__ float2 lds[];
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   const FftPlan &pl = plans[pd.plan];
   const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int T = kFftCap / Ls;
+  const int T = min(kFftCap / Ls, tmax);
   float2 *buf = lds, *tw = lds + kFftLds;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
                                                        const float2 *__restrict__ S1,
                                                        const float2 *__restrict__ otf,
                                                        const int64_t *__restrict__ s2_off, float2 *__restrict__ S2,
-                                                       const int *__restrict__ mask) {
+                                                       const int *__restrict__ mask, int tmax) {
   extern __shared__ float2 lds[];
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
   const FftPlan &pl = plans[pd.plan];
   const int L = pl.L, Lh = L / 2 + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int C = kFftCap / L;
+  const int C = min(kFftCap / L, tmax);
   const int k0 = w.unit * C;
   const int nc = min(C, Lh - k0);
   float2 *buf = lds, *tw = lds + kFftLds;
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
                                                         const Work *__restrict__ work, int n_ch,
                                                         const int64_t *__restrict__ s2_off,
                                                         const float2 *__restrict__ S2, float *__restrict__ out,
-                                                        const int *__restrict__ mask) {
+                                                        const int *__restrict__ mask, int tmax) {
   extern __shared__ float2 lds[];
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   const FftPlan &pl = plans[pd.plan];
   const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int T = kFftCap / Ls;
+  const int T = min(kFftCap / Ls, tmax);
   float2 *buf = lds, *tw = lds + kFftLds;
   for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
@@ -456,25 +457,36 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
 // ----------------------------------------------------------------- launchers
 static size_t fft_lds_bytes(int max_L) { return (size_t)(kFftLds + max_L) * sizeof(float2); }
 
+// Small jobs (fewer than two workgroups per CU in the wide shape) use the
+// narrow shape: one row pair or two bins per workgroup, so more CUs share the
+// latency-bound work.
 hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
                            float2 *S1, float2 *S2, float *out, const int *mask) {
   if (p->h_rows.empty()) return hipSuccess;
   const size_t lds = fft_lds_bytes(p->max_L);
   dim3 blk(kThreads);
+  const bool narrow = (int64_t)p->h_cols.size() * n_ch < 2 * 256;
+  const std::vector<Work> &rows = narrow ? p->h_rows_n : p->h_rows;
+  const std::vector<Work> &cols = narrow ? p->h_cols_n : p->h_cols;
+  const std::vector<Work> &irows = narrow ? p->h_irows_n : p->h_irows;
+  const Work *d_rows = narrow ? p->d_rows_n : p->d_rows;
+  const Work *d_cols = narrow ? p->d_cols_n : p->d_cols;
+  const Work *d_irows = narrow ? p->d_irows_n : p->d_irows;
+  const int tr = narrow ? kFftNarrowT : 1 << 20, tc = narrow ? kFftNarrowC : 1 << 20;
   {
     ProfScope ps(st, "k_fft_rows");
-    hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)p->h_rows.size(), n_ch), blk, lds, st, b->d_desc,
-                       p->d_path, p->d_plans, p->d_tw, p->d_rows, in, n_ch, p->d_s1, S1, mask);
+    hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)rows.size(), n_ch), blk, lds, st, b->d_desc,
+                       p->d_path, p->d_plans, p->d_tw, d_rows, in, n_ch, p->d_s1, S1, mask, tr);
   }
   {
     ProfScope ps(st, "k_fft_cols");
-    hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)p->h_cols.size(), n_ch), blk, lds, st, b->d_desc,
-                       p->d_path, p->d_plans, p->d_tw, p->d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask);
+    hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)cols.size(), n_ch), blk, lds, st, b->d_desc,
+                       p->d_path, p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
   }
   {
     ProfScope ps(st, "k_fft_irows");
-    hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)p->h_irows.size(), n_ch), blk, lds, st,
-                       b->d_desc, p->d_path, p->d_plans, p->d_tw, p->d_irows, n_ch, p->d_s2, S2, out, mask);
+    hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)irows.size(), n_ch), blk, lds, st, b->d_desc,
+                       p->d_path, p->d_plans, p->d_tw, d_irows, n_ch, p->d_s2, S2, out, mask, tr);
   }
   return hipGetLastError();
 }
@@ -486,12 +498,13 @@ hipError_t launch_fft_corr(hipStream_t st, const gf_batch *b, const gf_psf *p, c
   const size_t lds = fft_lds_bytes(p->max_L);
   dim3 blk(kThreads);
   hipLaunchKernelGGL((k_fft_rows<MODE_CORR>), dim3((unsigned)p->h_arows.size(), 1), blk, lds, st, b->d_desc,
-                     p->d_path, p->d_plans, p->d_tw, p->d_arows, in, 1, p->d_s1a, S1, (const int *)nullptr);
+                     p->d_path, p->d_plans, p->d_tw, p->d_arows, in, 1, p->d_s1a, S1, (const int *)nullptr, 1 << 20);
   hipLaunchKernelGGL((k_fft_cols<MODE_CORR>), dim3((unsigned)p->h_acols.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_acols, 1, p->d_s1a, S1, p->d_otf, p->d_s2a, S2,
-                     (const int *)nullptr);
+                     (const int *)nullptr, 1 << 20);
   hipLaunchKernelGGL((k_fft_irows<MODE_CORR>), dim3((unsigned)p->h_airows.size(), 1), blk, lds, st, b->d_desc,
-                     p->d_path, p->d_plans, p->d_tw, p->d_airows, 1, p->d_s2a, S2, out, (const int *)nullptr);
+                     p->d_path, p->d_plans, p->d_tw, p->d_airows, 1, p->d_s2a, S2, out, (const int *)nullptr,
+                     1 << 20);
   return hipGetLastError();
 }
 
@@ -504,10 +517,10 @@ hipError_t launch_fft_otf(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   const size_t lds = fft_lds_bytes(p->max_L);
   dim3 blk(kThreads);
   hipLaunchKernelGGL((k_fft_rows<MODE_OTF>), dim3((unsigned)n_rows, 1), blk, lds, st, b->d_desc, p->d_path,
-                     p->d_plans, p->d_tw, rows, taps, 1, s1_off, S1, (const int *)nullptr);
+                     p->d_plans, p->d_tw, rows, taps, 1, s1_off, S1, (const int *)nullptr, 1 << 20);
   hipLaunchKernelGGL((k_fft_cols<MODE_OTF>), dim3((unsigned)n_cols, 1), blk, lds, st, b->d_desc, p->d_path,
                      p->d_plans, p->d_tw, cols, 1, s1_off, S1, (const float2 *)nullptr, otf_off, p->d_otf,
-                     (const int *)nullptr);
+                     (const int *)nullptr, 1 << 20);
   return hipGetLastError();
 }
 

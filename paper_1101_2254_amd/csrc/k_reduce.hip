@@ -281,7 +281,15 @@ hipError_t launch_add_sky(hipStream_t st, const gf_batch *b, const float *theta,
 // pix * nchan + ch * H*W (nchan = 7 * the largest component count).
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGramThreads = 1024;
+// Orders LDS traffic between the lanes of one wave (LDS operations of a wave
+// complete in issue order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kGramThreads = 256;
 
 template <int NC>
 __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
@@ -410,31 +418,63 @@ __global__ void k_lm_clip(int64_t n_par, double *__restrict__ theta, const doubl
   theta_t[i] = v;
 }
 
-// Solve for one stamp per workgroup of 1024 threads.  When the Jacobian is
-// new, four slices of 256 threads add the 256 Gram entries over the stamp's
-// workgroup partials in FP64 (eight independent chains per thread, slices
-// combined in a fixed order) and A = G[0..P-1][0..P-1]
+// Solve for one stamp per wave.  When the Jacobian is new, A = G[0..P-1][0..P-1]
 // (symmetrised from the lower triangle), g = G[0..P-1][P] are kept in Ag.
-// Then the damped system over the free parameters is factored by a Cholesky
-// in which lane i of the first wave keeps row i in registers and the finished
-// rows are broadcast through LDS; lane 0 does the two triangular solves in
+// Then the wave factors the damped system over the free parameters by a
+// Cholesky in which lane i keeps row i in registers and the finished rows are
+// broadcast through LDS (only wave-level ordering is needed); lane 0 does the two triangular solves in
 // FP64 and writes the clipped trial point.  Block 0 also clears the count of
 // active stamps that the update kernel of this iteration fills.
-constexpr int kSolveThreads = 1024;
+constexpr int kSolveThreads = 64;
+constexpr int kReduceThreads = 1024;
+
+// FP64 sums of the Gram partials of every stamp whose Jacobian is new: four
+// slices of 256 threads, each thread issuing its loads 32 at a time, the
+// slices combined in a fixed order.
+__global__ __launch_bounds__(kReduceThreads) void k_gram_reduce(const int32_t *__restrict__ neq_first,
+                                                                const float *__restrict__ part,
+                                                                double *__restrict__ Gsum,
+                                                                const int *__restrict__ mask) {
+  constexpr int NS = kReduceThreads / 256;
+  __shared__ double G[NS][256];
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  const int tid = threadIdx.x, e = tid & 255, sl = tid >> 8;
+  const int u0 = neq_first[s], u1 = neq_first[s + 1];
+  double acc = 0.0;
+  const float *pe = part + e;
+  for (int ub = u0 + sl; ub < u1; ub += 32 * NS) {
+    // straight-line loads from clamped addresses; out-of-range ones weigh 0
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) v[q] = pe[(int64_t)min(ub + q * NS, u1 - 1) * 256];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc += (ub + q * NS < u1) ? (double)v[q] : 0.0;
+  }
+  G[sl][e] = acc;
+  __syncthreads();
+  if (tid < 256) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) t += G[q][tid];
+    Gsum[(int64_t)s * 256 + tid] = t;
+  }
+}
 
 template <int NC>
 __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__restrict__ desc,
-                                                       const int32_t *__restrict__ neq_first,
-                                                       const float *__restrict__ part, LMParams prm,
+                                                       const double *__restrict__ Gsum, LMParams prm,
                                                        LMState *__restrict__ st, double *__restrict__ Ag,
                                                        const double *__restrict__ theta, double *__restrict__ theta_t,
                                                        int *__restrict__ mjac, int *__restrict__ mtrial,
                                                        int *__restrict__ active_count) {
   constexpr int P = kNPC * NC + 1;
-  __shared__ double G[kSolveThreads / 256][256];
   __shared__ double Lr[P][P];
   __shared__ double y[P];
   __shared__ double dmax_s;
+  __shared__ double As[P * P];
+  __shared__ double th_s[P], lo_s[P], hi_s[P], g_s[P];
+  __shared__ int fr_s[P];
   __shared__ int idx[P];
   __shared__ int nf_s, ok_s;
   const int s = blockIdx.x;
@@ -445,54 +485,62 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
   LMState S = st[s];
   if (!S.active) return;
   double *Ags = Ag + (int64_t)s * (kMaxP * kMaxP + kMaxP);
-  if (S.need_jac) {
-    // thread (slice, entry): slice sl adds partials u0 + sl, u0 + sl + 4, ...
-    constexpr int NS = kSolveThreads / 256;
-    const int e = tid & 255, sl = tid >> 8;
-    const int u0 = neq_first[s], u1 = neq_first[s + 1];
-    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int u = u0 + sl;
-    for (; u + 7 * NS < u1; u += 8 * NS) {
+  // A and g of this iteration in LDS: from the fresh Gram sums (and kept in
+  // Ag for later iterations) or from Ag (written by an earlier launch).
+  {
+    // each lane moves ceil(P*P/64) entries, all loads issued before any store
+    constexpr int NE = (P * P + kSolveThreads - 1) / kSolveThreads;
+    const double *Gs = Gsum + (int64_t)s * 256;
+    double v[NE];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] += (double)part[(int64_t)(u + q * NS) * 256 + e];
-    }
-    for (; u < u1; u += NS) v[0] += (double)part[(int64_t)u * 256 + e];
-    G[sl][e] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-    __syncthreads();
-    if (tid < 256) {
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < NS; ++q) t += G[q][tid];
-      G[0][tid] = t;
-    }
-    __syncthreads();
-    if (tid < P * P) {
-      const int a = tid / P, b = tid - a * P;
+    for (int q = 0; q < NE; ++q) {
+      const int e = min(tid + q * kSolveThreads, P * P - 1);
+      const int a = e / P, b = e - a * P;
       const int hi = a > b ? a : b, lo = a > b ? b : a;
-      Ags[a * kMaxP + b] = G[0][hi * 16 + lo];
+      v[q] = S.need_jac ? Gs[hi * 16 + lo] : Ags[a * kMaxP + b];
     }
-    if (tid < P) Ags[kMaxP * kMaxP + tid] = G[0][tid * 16 + P];
-    __syncthreads();
+    const double gv = S.need_jac ? Gs[min(tid, P - 1) * 16 + P] : Ags[kMaxP * kMaxP + min(tid, P - 1)];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * kSolveThreads;
+      if (e < P * P) {
+        As[e] = v[q];
+        if (S.need_jac) Ags[(e / P) * kMaxP + (e % P)] = v[q];
+      }
+    }
+    if (tid < P) {
+      g_s[tid] = gv;
+      if (S.need_jac) Ags[kMaxP * kMaxP + tid] = gv;
+    }
   }
+  // stage the per-parameter data through LDS with parallel loads
+  if (tid < P) {
+    const int64_t i = d.par + tid;
+    th_s[tid] = theta[i];
+    lo_s[tid] = prm.lo ? prm.lo[i] : -INFINITY;
+    hi_s[tid] = prm.hi ? prm.hi[i] : INFINITY;
+    fr_s[tid] = prm.free_mask ? (int)prm.free_mask[i] : 1;
+  }
+  wave_sync();
   if (tid == 0) {
     int nf = 0;
     double dm = 0.0;
     for (int p = 0; p < P; ++p)
-      if (!prm.free_mask || prm.free_mask[d.par + p]) {
+      if (fr_s[p]) {
         idx[nf++] = p;
-        dm = fmax(dm, Ags[p * kMaxP + p]);
+        dm = fmax(dm, As[p * P + p]);
       }
     nf_s = nf;
     dmax_s = dm;
     ok_s = 1;
   }
-  __syncthreads();
+  wave_sync();
   const int nf = nf_s;
   // lane i < nf holds row i of the damped matrix (later of L)
   double row[P];
   const bool mine = tid < nf;
 #pragma unroll
-  for (int k = 0; k < P; ++k) row[k] = (mine && k < nf) ? Ags[idx[tid] * kMaxP + idx[k]] : 0.0;
+  for (int k = 0; k < P; ++k) row[k] = (mine && k < nf) ? As[idx[tid] * P + idx[k]] : 0.0;
 #pragma unroll
   for (int k = 0; k < P; ++k)
     if (mine && k == tid) row[k] += S.lambda * fmax(row[k], 1e-12 * dmax_s);
@@ -508,14 +556,14 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
 #pragma unroll
         for (int k = 0; k <= j; ++k) Lr[j][k] = row[k];
       }
-      __syncthreads();
+      wave_sync();
       if (ok_s && mine && tid > j) {
         double t = row[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) t -= row[k] * Lr[j][k];
         row[j] = t / Lr[j][j];
       }
-      __syncthreads();
+      wave_sync();
     }
   }
   if (tid == 0) {
@@ -536,7 +584,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
       }
     } else {
       for (int i = 0; i < nf; ++i) {
-        double t = Ags[kMaxP * kMaxP + idx[i]];
+        double t = g_s[idx[i]];
         for (int k = 0; k < i; ++k) t -= Lr[i][k] * y[k];
         y[i] = t / Lr[i][i];
       }
@@ -545,18 +593,20 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
         for (int k = i + 1; k < nf; ++k) t -= Lr[k][i] * y[k];
         y[i] = t / Lr[i][i];
       }
-      for (int p = 0; p < P; ++p) theta_t[d.par + p] = theta[d.par + p];
-      for (int a = 0; a < nf; ++a) {
-        const int64_t i = d.par + idx[a];
-        double v = theta[i] + y[a];
-        if (prm.lo && v < prm.lo[i]) v = prm.lo[i];
-        if (prm.hi && v > prm.hi[i]) v = prm.hi[i];
-        theta_t[i] = v;
-      }
       S.trial = 1;
       mtrial[s] = 1;
     }
     st[s] = S;
+  }
+  wave_sync();
+  // trial point theta' = clip(theta + delta) on the free parameters
+  if (ok_s && tid < P) {
+    int a = -1;
+    for (int q = 0; q < nf; ++q)
+      if (idx[q] == tid) a = q;
+    double v = th_s[tid];
+    if (a >= 0) v = fmin(fmax(v + y[a], lo_s[tid]), hi_s[tid]);
+    theta_t[d.par + tid] = v;
   }
 }
 
@@ -575,31 +625,36 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
   if (!S.active) return;
   const StampDesc d = desc[s];
   const int P = kNPC * d.ncomp + 1;
+  const int lane = threadIdx.x;
   double c2 = 0.0;
+  double stp = 0.0;
+  double th = 0.0, tt = 0.0;
   if (S.trial) {
     F2 r = {0.f, 0.f};
-    for (int u = pix_first[s] + (int)threadIdx.x; u < pix_first[s + 1]; u += 64) {
+    for (int u = pix_first[s] + lane; u < pix_first[s + 1]; u += 64) {
       const float2 v = part[u];
       F2 t = {v.x, v.y};
       r = f2_add(r, t);
     }
     r = wave_sum(r);
     c2 = (double)r.hi + (double)r.lo;
+    if (lane < P) {
+      const int64_t i = d.par + lane;
+      th = theta[i];
+      tt = theta_t[i];
+      if (!prm.free_mask || prm.free_mask[i]) stp = fabs(tt - th) / fmax(fabs(th), 1.0);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) stp = fmax(stp, __shfl_xor(stp, off, 64));
   }
-  if (threadIdx.x != 0) return;
+  const bool accept = S.trial && c2 < S.chi2;
+  if (accept && lane < P) theta[d.par + lane] = tt;
+  if (lane != 0) return;
   if (S.trial) {
     S.nfev += 1;
     S.chi2_trial = c2;
-    if (c2 < S.chi2) {
-      double step = 0.0;
-      for (int p = 0; p < P; ++p) {
-        const int64_t i = d.par + p;
-        if (prm.free_mask && !prm.free_mask[i]) continue;
-        const double sc = fmax(fabs(theta[i]), 1.0);
-        step = fmax(step, fabs(theta_t[i] - theta[i]) / sc);
-      }
+    if (accept) {
       const double rel = c2 > 0.0 ? (S.chi2 - c2) / c2 : 0.0;
-      for (int p = 0; p < P; ++p) theta[d.par + p] = theta_t[d.par + p];
       S.chi2 = c2;
       S.lambda /= prm.lambda_down;
       S.need_jac = 1;
@@ -607,7 +662,7 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
         S.active = 0; S.status = GF_OK; S.reason = 3;
       } else if (rel < prm.ftol) {
         S.active = 0; S.status = GF_OK; S.reason = 1;
-      } else if (step < prm.xtol) {
+      } else if (stp < prm.xtol) {
         S.active = 0; S.status = GF_OK; S.reason = 2;
       }
     } else {
@@ -657,8 +712,13 @@ hipError_t launch_lm_clip(hipStream_t st, int64_t n_par, double *theta, const do
   return hipGetLastError();
 }
 
-hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, const gf_lm_opts *o, LMState *S,
-                           double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial, int *cnt) {
+hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, double *Gsum, const gf_lm_opts *o,
+                           LMState *S, double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial,
+                           int *cnt) {
+  {
+    ProfScope ps(st, "k_gram_reduce");
+    hipLaunchKernelGGL(k_gram_reduce, dim3(b->n), dim3(kReduceThreads), 0, st, b->d_neq_first, part, Gsum, mjac);
+  }
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask};
   ProfScope ps(st, "k_lm_solve");
@@ -668,11 +728,11 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
     has2 |= d.ncomp == 2;
   }
   if (has1)
-    hipLaunchKernelGGL((k_lm_solve<1>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part, prm, S,
-                       Ag, theta, theta_t, mjac, mtrial, cnt);
+    hipLaunchKernelGGL((k_lm_solve<1>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, Gsum, prm, S, Ag, theta,
+                       theta_t, mjac, mtrial, cnt);
   if (has2)
-    hipLaunchKernelGGL((k_lm_solve<2>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part, prm, S,
-                       Ag, theta, theta_t, mjac, mtrial, cnt);
+    hipLaunchKernelGGL((k_lm_solve<2>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, Gsum, prm, S, Ag, theta,
+                       theta_t, mjac, mtrial, cnt);
   return hipGetLastError();
 }
 

@@ -232,16 +232,18 @@ def test_chi2_and_residual(ctx, gfo):
 
 def test_likelihood_shared_image(ctx, gfo):
     """The likelihood batch: many vectors against one 256x256 image with the
-    33x33 Moffat PSF; three vectors checked against the oracle."""
+    33x33 Moffat PSF; three vectors checked against the oracle.  48 vectors
+    take the wide FFT launch shape, the 4-vector batch the narrow one."""
     base = synth.c4_truth()
     truth64 = base.truth.astype(np.float32).astype(np.float64)
     m = gfo.model(256, 256, truth64, base.psf.astype(np.float32).astype(np.float64), 5)
     d, w = synth.add_gaussian_noise(m, 0.02, base.noise_seed)
-    th = synth.c4_vectors(0, 32)
-    gb = GpuBatch(ctx, [base] * 32, thetas=list(th), data=[d], weights=[w], shared=True)
+    th = synth.c4_vectors(0, 48)
+    gb = GpuBatch(ctx, [base] * 48, thetas=list(th), data=[d], weights=[w], shared=True)
+    assert len(gb.psf.uses_fft) == 48
     pairs = ops.likelihood(ctx, gb.batch, gb.psf, gb.theta, gb.data, gb.weight, 5)
     chi = ops.pairs_to_f64(pairs).cpu().numpy()
-    for s in (0, 7, 31):
+    for s in (0, 7, 47):
         ref = gfo.chi2(gb.d32[0], gb.w32[0], gfo.model(256, 256, gb.th64(s), gb.psf64(0), 5))
         assert chi[s] == pytest.approx(ref, rel=1e-5), s
     # the separate calls give the same numbers
@@ -249,6 +251,10 @@ def test_likelihood_shared_image(ctx, gfo):
     mc = ops.convolve_psf(ctx, gb.batch, gb.psf, mp)
     p2, _ = ops.chi2(ctx, gb.batch, mc, gb.theta, gb.data, gb.weight)
     assert torch.equal(pairs, p2)
+    # a small batch of the same vectors (narrow launch shape) agrees
+    gs = GpuBatch(ctx, [base] * 4, thetas=list(th[[0, 7, 13, 47]]), data=[d], weights=[w], shared=True)
+    chi_s = ops.pairs_to_f64(ops.likelihood(ctx, gs.batch, gs.psf, gs.theta, gs.data, gs.weight, 5)).cpu().numpy()
+    np.testing.assert_allclose(chi_s, chi[[0, 7, 13, 47]], rtol=1e-6)
 
 
 def test_model_entry_point(ctx, gfo):
@@ -369,3 +375,42 @@ def test_fit_lm_batch_default_tolerance(ctx, gfo):
         o = gb.batch.offsets["par"][s]
         assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), s
         _param_close(fit[o:o + 8], ref, 1, 0.02)
+
+
+def test_fit_lm_uneven_batch_c3(ctx, gfo):
+    """64 stamps with the uneven-size priors (32..256 px, PSF 15..33, Gaussian
+    or Moffat) fitted in one call; six small ones checked against the oracle
+    from the same start, and one refitted alone must give bitwise the same
+    result (a stamp's computation does not depend on the rest of the batch)."""
+    g = synth.rng(31337)
+    stamps = [synth.c3_stamp(g, int(g.choice(synth.C3_SIZES)), i, 31337) for i in range(64)]
+    ths = [st.truth.astype(np.float32).astype(np.float64) for st in stamps]
+    data, weights = _observed(gfo, stamps, ths, 900)
+    gb = GpuBatch(ctx, stamps, data=data, weights=weights)
+    lo = np.concatenate([synth.bounds(1, st.H, st.W)[0] for st in stamps])
+    hi = np.concatenate([synth.bounds(1, st.H, st.W)[1] for st in stamps])
+    start = np.concatenate([st.start for st in stamps])
+    opts = dict(ftol=1e-12, xtol=1e-10, max_iter=200)
+    fit, res = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(start, torch.float64),
+                          lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), **opts)
+    fit = fit.cpu().numpy()
+    assert np.all(np.isfinite(fit))
+    assert np.all(res["iters"] >= 1)
+    small = [s for s, st in enumerate(stamps) if st.H <= 64][:6]
+    for s in small:
+        st = stamps[s]
+        l, h = synth.bounds(1, st.H, st.W)
+        ref, info = gfo.fit_lm(st.start, gb.psf64(s), gb.d32[s].astype(np.float64), gb.w32[s].astype(np.float64),
+                               5, lo=l, hi=h, **opts)
+        o = gb.batch.offsets["par"][s]
+        assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), s
+        _param_close(fit[o:o + 8], ref, 1, 0.02)
+    # the same stamp alone
+    s = small[0]
+    one = GpuBatch(ctx, [stamps[s]], data=[data[s]], weights=[weights[s]])
+    l, h = synth.bounds(1, stamps[s].H, stamps[s].W)
+    f1, r1 = ops.fit_lm(ctx, one.batch, one.psf, one.data, one.weight, to_dev(stamps[s].start, torch.float64),
+                        lo=to_dev(l, torch.float64), hi=to_dev(h, torch.float64), **opts)
+    o = gb.batch.offsets["par"][s]
+    np.testing.assert_array_equal(f1.cpu().numpy(), fit[o:o + 8])
+    assert r1["chi2"][0] == res["chi2"][s] and r1["iters"][0] == res["iters"][s]
