@@ -52,6 +52,7 @@ extern "C" {
 typedef struct gf_ctx gf_ctx;
 typedef struct gf_batch gf_batch;
 typedef struct gf_psf gf_psf;
+typedef struct gf_cnn gf_cnn;
 
 typedef enum {
   GF_OK = 0,
@@ -235,6 +236,95 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  * Returns GF_OK when the call ran (per-stamp outcomes are in res). */
 gf_status gf_fit_lm(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
                     double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
+
+/* ------------------------------------------------------------ starting points
+ *
+ * The paper's outlook (Sec. 5) notes that a fit only finds the minimum near
+ * its starting point and that global strategies help avoid local minima and
+ * unphysical results; these calls produce starting points for single-Sersic
+ * stamps (P = 8: x0, y0, Ie, Re, n, q, phi, sky) for gf_fit_lm.
+ *
+ * Default guess (image moments), gf_moments_guess, per stamp of an H x W
+ * batch with one component:
+ *   sky     = median of the outer 4-pixel frame, s = its RMS about the median;
+ *   weights v = (d - sky) * clamp((d - sky)/s - 2, 0, 1)  (a ramp from 2 s to 3 s);
+ *   centre  = v-weighted mean of (x, y); q and phi from the v-weighted second
+ *             moments (q = sqrt(minor/major eigenvalue), phi = major axis
+ *             angle in [0, pi)), q clamped to [0.05, 1];
+ *   Re      = elliptical radius (axes q, phi) at which the cumulative v
+ *             reaches half of sum(v), linear between neighbouring pixels;
+ *   n = 2;  Ie = F / (2 pi n Re^2 q e^{b_n} b_n^{-2n} Gamma(2n)) with
+ *             F = sum(d - sky) over the stamp (the flux of a Sersic profile).
+ * data: device [n_img]; theta: device [n_par] FP64.  The frame must hold at
+ * most 16384 pixels.  Stamps with no positive weight get the stamp centre,
+ * Re = 2, q = 1, phi = 0 and Ie from F (at least 1e-3). */
+gf_status gf_moments_guess(gf_ctx *ctx, const gf_batch *batch, const float *data, double *theta);
+
+/* Learned proposal (a convolutional network, trained on rendered stamps):
+ *   input  side x side stamp, normalised as asinh((d - m) / s) with m, s the
+ *          mean and population standard deviation of the outer 4-pixel frame;
+ *   4 x [3x3 convolution, stride 2, padding 1, ReLU], channels 32, 32, 64, 64;
+ *   dense (side/16)^2*64 -> 256, ReLU, dense 256 -> 8.
+ * BF16 operands with FP32 accumulation on the matrix cores; FP32 master
+ * weights; mean-squared-error loss; Adam (beta1 0.9, beta2 0.999, eps 1e-8)
+ * with bias correction.
+ * Parameters in canonical order and layout (gf_cnn_param_count floats):
+ *   w1 [32][3][3][1], b1 [32], w2 [32][3][3][32], b2 [32], w3 [64][3][3][32],
+ *   b3 [64], w4 [64][3][3][64], b4 [64], w5 [256][(side/16)^2*64] (input
+ *   flattened in (y, x, channel) order), b5 [256], w6 [8][256], b6 [8].
+ * The object owns its weights, Adam moments and the workspace of max_batch
+ * stamps.  side: a multiple of 16 in 16..1024. */
+gf_status gf_cnn_create(gf_ctx *ctx, int side, int max_batch, gf_cnn **out);
+/* Waits for the device and frees the object (safe after gf_destroy of its context). */
+void gf_cnn_destroy(gf_cnn *cnn);
+int64_t gf_cnn_param_count(const gf_cnn *cnn);
+/* He-uniform weights (bound sqrt(6 / fan_in)) from Philox4x64-10 with key
+ * (key, 0x5eed), zero biases; resets Adam. */
+gf_status gf_cnn_init(gf_cnn *cnn, uint64_t key);
+/* params, out: device, canonical layout.  set_params resets Adam. */
+gf_status gf_cnn_set_params(gf_cnn *cnn, const float *params);
+gf_status gf_cnn_get_params(gf_cnn *cnn, float *out);
+/* stamps: device [n][side][side]; out: device [n][8] network outputs
+ * (targets as coded by gf_cnn_encode).  Any n >= 0 (runs in batches). */
+gf_status gf_cnn_forward(gf_cnn *cnn, const float *stamps, int n, float *out);
+/* Loss and gradients for one batch (1 <= n <= max_batch): targets device
+ * [n][8]; grads device canonical layout (nullable); loss device float
+ * (nullable), the mean over the n x 8 outputs. */
+gf_status gf_cnn_gradients(gf_cnn *cnn, const float *stamps, const float *targets, int n, float *grads, float *loss);
+/* gf_cnn_gradients followed by one Adam step with learning rate lr. */
+gf_status gf_cnn_train_step(gf_cnn *cnn, const float *stamps, const float *targets, int n, float lr, float *loss);
+/* Number of Adam steps taken since the last init / set_params. */
+int64_t gf_cnn_steps(const gf_cnn *cnn);
+/* Parameter coding of a side-N stamp (theta device [n][8] FP32 in, targets
+ * device [n][8] out):
+ *   t0 = x0 - N/2, t1 = y0 - N/2, t2 = (ln Ie - a)/b over Ie in [0.5, 5],
+ *   t3 = (ln Re - a)/b over Re in [2, N/4] (a, b: midpoint and half-width of
+ *   the log range), t4 = (n - 3.25)/2.75, (t5, t6) = (1 - q)(cos 2phi, sin 2phi)/0.8,
+ *   t7 = (sky - 0.025)/0.025.
+ * gf_cnn_decode inverts it into FP64 theta, clamping n to [0.2, 10] and
+ * 1 - q to [0, 0.95], phi to [0, pi). */
+gf_status gf_cnn_encode(gf_ctx *ctx, int n, int side, const float *theta, float *targets);
+gf_status gf_cnn_decode(gf_ctx *ctx, int n, int side, const float *targets, double *theta);
+
+/* ------------------------------------------------------------ random numbers
+ * Philox4x64-10 (Salmon et al., SC 2011): block b uses the 256-bit counter
+ * counter + b (counter: host [4], word 0 least significant; null = zero)
+ * and the key (key0, key1).
+ * gf_philox: out device [n_blocks][4] raw words.
+ * gf_normal_noise: out[j] = clean[j] + sigma z_j (clean nullable = 0);
+ *   z_{4b..4b+3} come from block b by Box-Muller on 24-bit uniforms
+ *   u = (w >> 40 + 1/2) 2^-24: (u0, u1) -> sqrt(-2 ln u0)(cos 2pi u1, sin 2pi u1),
+ *   (u2, u3) likewise; computed in FP64, stored FP32.  out may equal clean.
+ * gf_draw_prior: theta device [n][8] FP32, stamp i from blocks 2i, 2i+1
+ *   (uniforms u0..u7): n = 0.5 + 5.5 u0, Re = 2 + (N/4 - 2) u1,
+ *   q = 0.2 + 0.8 u2, phi = pi u3, Ie = 0.5 * 10^u4, x0 = N/2 + 2 u5 - 1,
+ *   y0 = N/2 + 2 u6 - 1, sky = 0.05 u7. */
+gf_status gf_philox(gf_ctx *ctx, uint64_t key0, uint64_t key1, const uint64_t *counter, int64_t n_blocks,
+                    uint64_t *out);
+gf_status gf_normal_noise(gf_ctx *ctx, int64_t n, float sigma, uint64_t key0, uint64_t key1, const uint64_t *counter,
+                          const float *clean, float *out);
+gf_status gf_draw_prior(gf_ctx *ctx, int n, int side, uint64_t key0, uint64_t key1, const uint64_t *counter,
+                        float *theta);
 
 /* ------------------------------------------------------------ profiling */
 

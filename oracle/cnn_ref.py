@@ -147,3 +147,66 @@ def normalise_input(stamps, border: int = 4):
     sig = fr.std(1)
     sig = np.where(sig > 0, sig, 1.0)
     return np.arcsinh((stamps - sky[:, None, None]) / sig[:, None, None])[..., None]
+
+
+# ---------------------------------------------------------------- parameter coding
+# Targets of a single Sersic component plus sky on a side-N stamp (theta =
+# x0, y0, Ie, Re, n, q, phi, sky):
+#   t0 = x0 - N/2, t1 = y0 - N/2,
+#   t2, t3 = ln Ie, ln Re mapped linearly from [ln 0.5, ln 5] and [ln 2, ln N/4] onto [-1, 1],
+#   t4 = n mapped from [0.5, 6] onto [-1, 1],
+#   (t5, t6) = (1 - q)(cos 2 phi, sin 2 phi) / 0.8,
+#   t7 = sky mapped from [0, 0.05] onto [-1, 1].
+def _lin(v, a, b):
+    return (2.0 * v - (a + b)) / (b - a)
+
+
+def _unlin(t, a, b):
+    return 0.5 * ((b - a) * t + (a + b))
+
+
+def encode(theta, side):
+    th = np.asarray(theta, np.float64).reshape(-1, 8)
+    t = np.empty_like(th)
+    t[:, 0] = th[:, 0] - side / 2
+    t[:, 1] = th[:, 1] - side / 2
+    t[:, 2] = _lin(np.log(th[:, 2]), np.log(0.5), np.log(5.0))
+    t[:, 3] = _lin(np.log(th[:, 3]), np.log(2.0), np.log(side / 4))
+    t[:, 4] = _lin(th[:, 4], 0.5, 6.0)
+    t[:, 5] = (1 - th[:, 5]) * np.cos(2 * th[:, 6]) / 0.8
+    t[:, 6] = (1 - th[:, 5]) * np.sin(2 * th[:, 6]) / 0.8
+    t[:, 7] = _lin(th[:, 7], 0.0, 0.05)
+    return t
+
+
+def decode(t, side):
+    """Inverse of encode; n clamped to [0.2, 10], 1 - q to [0, 0.95], phi in [0, pi)."""
+    t = np.asarray(t, np.float64).reshape(-1, 8)
+    th = np.empty_like(t)
+    th[:, 0] = side / 2 + t[:, 0]
+    th[:, 1] = side / 2 + t[:, 1]
+    th[:, 2] = np.exp(_unlin(t[:, 2], np.log(0.5), np.log(5.0)))
+    th[:, 3] = np.exp(_unlin(t[:, 3], np.log(2.0), np.log(side / 4)))
+    th[:, 4] = np.clip(_unlin(t[:, 4], 0.5, 6.0), 0.2, 10.0)
+    e = np.minimum(0.8 * np.hypot(t[:, 5], t[:, 6]), 0.95)
+    th[:, 5] = 1 - e
+    th[:, 6] = np.mod(0.5 * np.arctan2(t[:, 6], t[:, 5]), np.pi)
+    th[:, 7] = _unlin(t[:, 7], 0.0, 0.05)
+    return th
+
+
+def draw_prior(key, counter, n, side):
+    """Prior draws of the uneven-batch workload from Philox uniforms: stamp i
+    uses blocks counter + 2i and + 2i + 1, uniforms u0..u7 in word order."""
+    from .philox_ref import raw_blocks, uniform24
+    u = uniform24(raw_blocks(key, counter, 2 * n)).reshape(n, 8)
+    th = np.empty((n, 8))
+    th[:, 0] = side / 2 + 2 * u[:, 5] - 1
+    th[:, 1] = side / 2 + 2 * u[:, 6] - 1
+    th[:, 2] = 0.5 * 10.0 ** u[:, 4]
+    th[:, 3] = 2 + (side / 4 - 2) * u[:, 1]
+    th[:, 4] = 0.5 + 5.5 * u[:, 0]
+    th[:, 5] = 0.2 + 0.8 * u[:, 2]
+    th[:, 6] = np.pi * u[:, 3]
+    th[:, 7] = 0.05 * u[:, 7]
+    return th

@@ -25,7 +25,10 @@ GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
 EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_synchronize", "gf_batch_create",
            "gf_batch_destroy", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
            "gf_psf_destroy", "gf_psf_paths", "gf_eval_model", "gf_convolve_psf", "gf_model", "gf_chi2", "gf_likelihood",
-           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_profile_start",
+           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_moments_guess",
+           "gf_cnn_create", "gf_cnn_destroy", "gf_cnn_param_count", "gf_cnn_init", "gf_cnn_set_params",
+           "gf_cnn_get_params", "gf_cnn_forward", "gf_cnn_gradients", "gf_cnn_train_step", "gf_cnn_steps",
+           "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_profile_start",
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_version")
 
 
@@ -62,6 +65,7 @@ def lib() -> ctypes.CDLL:
                            "(there is no other implementation to fall back to)")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl, flt = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    u64 = ctypes.c_uint64
     pvp = ctypes.POINTER(ctypes.c_void_p)
     pi64 = ctypes.POINTER(ctypes.c_int64)
     sig = {
@@ -87,6 +91,22 @@ def lib() -> ctypes.CDLL:
         "gf_jacobian": (i32, [vp, vp, vp, vp, i32, i32, vp, vp, flt, vp]),
         "gf_lm_opts_default": (None, [ctypes.POINTER(GfLmOpts)]),
         "gf_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
+        "gf_moments_guess": (i32, [vp, vp, vp, vp]),
+        "gf_cnn_create": (i32, [vp, i32, i32, pvp]),
+        "gf_cnn_destroy": (None, [vp]),
+        "gf_cnn_param_count": (i64, [vp]),
+        "gf_cnn_init": (i32, [vp, u64]),
+        "gf_cnn_set_params": (i32, [vp, vp]),
+        "gf_cnn_get_params": (i32, [vp, vp]),
+        "gf_cnn_forward": (i32, [vp, vp, i32, vp]),
+        "gf_cnn_gradients": (i32, [vp, vp, vp, i32, vp, vp]),
+        "gf_cnn_train_step": (i32, [vp, vp, vp, i32, flt, vp]),
+        "gf_cnn_steps": (i64, [vp]),
+        "gf_cnn_encode": (i32, [vp, i32, i32, vp, vp]),
+        "gf_cnn_decode": (i32, [vp, i32, i32, vp, vp]),
+        "gf_philox": (i32, [vp, u64, u64, vp, i64, vp]),
+        "gf_normal_noise": (i32, [vp, i64, flt, u64, u64, vp, vp, vp]),
+        "gf_draw_prior": (i32, [vp, i32, i32, u64, u64, vp, vp]),
         "gf_profile_start": (i32, [vp]),
         "gf_profile_stop": (i32, [vp]),
         "gf_profile_kernels": (i32, [vp]),
@@ -232,3 +252,75 @@ def gf_profile_read(ctx) -> dict:
 
 def gf_version() -> str:
     return lib().gf_version().decode()
+
+
+# ---------------------------------------------------------------- starting points
+def gf_moments_guess(ctx, b, data_ptr, theta_ptr):
+    check(lib().gf_moments_guess(ctx, b, data_ptr, theta_ptr), ctx)
+
+
+def gf_cnn_create(ctx: int, side: int, max_batch: int) -> int:
+    p = ctypes.c_void_p()
+    check(lib().gf_cnn_create(ctx, side, max_batch, ctypes.byref(p)), ctx)
+    return p.value
+
+
+def gf_cnn_destroy(cnn: int) -> None:
+    lib().gf_cnn_destroy(cnn)
+
+
+def gf_cnn_param_count(cnn: int) -> int:
+    return int(lib().gf_cnn_param_count(cnn))
+
+
+def gf_cnn_init(ctx, cnn, key: int):
+    check(lib().gf_cnn_init(cnn, key), ctx)
+
+
+def gf_cnn_set_params(ctx, cnn, params_ptr):
+    check(lib().gf_cnn_set_params(cnn, params_ptr), ctx)
+
+
+def gf_cnn_get_params(ctx, cnn, out_ptr):
+    check(lib().gf_cnn_get_params(cnn, out_ptr), ctx)
+
+
+def gf_cnn_forward(ctx, cnn, stamps_ptr, n, out_ptr):
+    check(lib().gf_cnn_forward(cnn, stamps_ptr, n, out_ptr), ctx)
+
+
+def gf_cnn_gradients(ctx, cnn, stamps_ptr, targets_ptr, n, grads_ptr, loss_ptr):
+    check(lib().gf_cnn_gradients(cnn, stamps_ptr, targets_ptr, n, grads_ptr, loss_ptr), ctx)
+
+
+def gf_cnn_train_step(ctx, cnn, stamps_ptr, targets_ptr, n, lr, loss_ptr):
+    check(lib().gf_cnn_train_step(cnn, stamps_ptr, targets_ptr, n, float(lr), loss_ptr), ctx)
+
+
+def gf_cnn_steps(cnn) -> int:
+    return int(lib().gf_cnn_steps(cnn))
+
+
+def gf_cnn_encode(ctx, n, side, theta_ptr, targets_ptr):
+    check(lib().gf_cnn_encode(ctx, n, side, theta_ptr, targets_ptr), ctx)
+
+
+def gf_cnn_decode(ctx, n, side, targets_ptr, theta_ptr):
+    check(lib().gf_cnn_decode(ctx, n, side, targets_ptr, theta_ptr), ctx)
+
+
+def _counter(ctr):
+    c = (ctypes.c_uint64 * 4)(*[int(v) & ((1 << 64) - 1) for v in (list(ctr) + [0, 0, 0, 0])[:4]])
+    return c
+
+
+def gf_philox(ctx, key0, key1, ctr, n_blocks, out_ptr):
+    check(lib().gf_philox(ctx, key0, key1, _counter(ctr), n_blocks, out_ptr), ctx)
+
+
+def gf_normal_noise(ctx, n, sigma, key0, key1, ctr, clean_ptr, out_ptr):
+    check(lib().gf_normal_noise(ctx, n, float(sigma), key0, key1, _counter(ctr), clean_ptr, out_ptr), ctx)
+
+
+def gf_draw_prior(ctx, n, side, key0, key1, ctr, theta_ptr):
+    check(lib().gf_draw_prior(ctx, n, side, key0, key1, _counter(ctr), theta_ptr), ctx)

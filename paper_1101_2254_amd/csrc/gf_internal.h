@@ -91,6 +91,22 @@ struct LMState {
   int32_t trial;      // a trial point was produced this iteration
 };
 
+// BF16 values are stored as raw 16-bit words.
+typedef uint16_t bf16_t;
+
+// Epilogue of the BF16 GEMM: v = acc (+ bias[n]) (ReLU) (zero where
+// mask(m, n) <= 0), stored to FP32 and/or BF16 outputs.
+struct Epi {
+  const float *bias;      // [N] or null
+  int relu;
+  const bf16_t *mask;     // null: no mask
+  int ldm;
+  float *outf;            // FP32 output or null
+  int ldf;
+  bf16_t *outb;           // BF16 output or null
+  int ldb;
+};
+
 // Fast division by a runtime constant d (x, d < 2^16): m = ceil(2^32/d), m = 0 for d = 1.
 inline uint32_t magic_for(uint32_t d) {
   return d <= 1 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d);

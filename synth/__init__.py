@@ -192,6 +192,22 @@ def c3_stamp(g: np.random.Generator, N: int, idx: int, seed: int) -> Stamp:
     return Stamp(N, N, psf, truth, start, 0.02, seed * 100000 + idx, "C3:" + kind)
 
 
+def c3_psf(g: np.random.Generator) -> np.ndarray:
+    """PSF from the uneven-batch distribution: K odd ~ U{15..33}, FWHM ~ U[2, 4],
+    Gaussian or Moffat (beta 3) with probability 1/2."""
+    K = int(g.choice(np.arange(15, 34, 2)))
+    fwhm = g.uniform(2.0, 4.0)
+    if g.random() < 0.5:
+        return gaussian_psf(K, fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0))))
+    return moffat_psf(K, fwhm, 3.0)
+
+
+def psf_bank(n: int, seed: int):
+    """n PSFs drawn with c3_psf (training seed 2000, evaluation seed 3000)."""
+    g = rng(seed)
+    return [c3_psf(g) for _ in range(n)]
+
+
 def c3(n_stamps: int = 4096, seed: int = SEED_BASE + 3, sizes=C3_SIZES):
     """Batch of uneven single-Sersic stamps: side ~ U{32,...,256}, n~U[0.5,6],
     Re~U[2, N/4], q~U[0.2,1], PA~U[0,pi], Ie log-uniform [0.5,5], centre
