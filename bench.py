@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
+    ap.add_argument("--train-stamps", type=int, default=200_000, help="C5: rendered training stamps")
+    ap.add_argument("--epochs", type=int, default=4, help="C5: training epochs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--breakdown", action="store_true", help="print the per-kernel breakdown to stderr")
@@ -279,6 +281,117 @@ def run_c4(args, torch, ops, synth):
     return result, prof, geo, dict(base=base, thetas_host=synth.c4_vectors(W, nvec), npix=npix)
 
 
+# Proposal network work per stamp (multiply-adds of the four 3x3 stride-2
+# convolutions at 128 x 128 input plus the two dense layers), times two for
+# FLOPs; a training step costs about three forward passes.
+CNN_MAC_PER_STAMP = (64 * 64 * 32 * 9 * 1 + 32 * 32 * 32 * 9 * 32 + 16 * 16 * 64 * 9 * 32 + 8 * 8 * 64 * 9 * 64
+                     + 4096 * 256 + 256 * 8)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_c5(args, torch, ops, synth):
+    """Learned proposal: train on stamps rendered on the device, then fit 4096
+    fresh 128x128 stamps by LM from the network's proposals and from the
+    image-moment default guess.  One step = proposal + LM for the batch."""
+    from paper_1101_2254_amd import proposal as PR
+    from paper_1101_2254_amd import _lib
+    dev = torch.device("cuda", 0)
+    ctx = ops.Context(0)
+    side, nev = 128, 4096
+    t0 = time.perf_counter()
+    train = PR.RenderedSet(ctx, synth.psf_bank(2048, 2000), args.train_stamps, side, seed=2000)
+    torch.cuda.synchronize()
+    t_render = time.perf_counter() - t0
+    net = PR.ProposalNet(ctx, side, max_batch=256)
+    net.init(2000)
+    print(f"bench: rendered {args.train_stamps} stamps in {t_render:.2f} s; training {args.epochs} epochs",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    losses = PR.train(net, train, epochs=args.epochs, batch=256, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps_trained = net.steps
+    del train
+    ev = PR.RenderedSet(ctx, synth.psf_bank(nev, 3000), nev, side, seed=3000)
+    data = ev.noisy(0, nev, epoch=0).clone()
+    weight = torch.full_like(data, 1.0 / 0.02 ** 2)
+    lo, hi = synth.bounds(1, side, side)
+    lo_t = torch.from_numpy(np.tile(lo, nev)).to(dev)
+    hi_t = torch.from_numpy(np.tile(hi, nev)).to(dev)
+
+    def fit(start, **kw):
+        return ops.fit_lm(ctx, ev.batch, ev.psf, data, weight, start, lo=lo_t, hi=hi_t, ftol=1e-5, max_iter=100,
+                          **kw)
+
+    def step_cnn(**kw):
+        return fit(net.predict(data).reshape(-1).contiguous(), **kw)
+
+    def step_default():
+        return fit(PR.moments_guess(ctx, ev.batch, data))
+
+    K_ = args.steps if args.steps is not None else 5
+    W = args.warmup if args.warmup is not None else 1
+    times = {}
+    infos = {}
+    for name, fn in (("default", step_default), ("cnn", step_cnn)):
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K_):
+            _, infos[name] = fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / K_
+    # training GEMM rate from the library's per-kernel timing of one step
+    xb = ev.noisy(0, 256, epoch=7)
+    tb = PR.encode(ctx, ev.theta[:256].reshape(-1), side)
+    net.train_step(xb, tb, 1e-6)
+    torch.cuda.synchronize()
+    _lib.gf_profile_start(ctx.ptr)
+    net.train_step(xb, tb, 1e-6)
+    torch.cuda.synchronize()
+    _lib.gf_profile_stop(ctx.ptr)
+    tprof = _lib.gf_profile_read(ctx.ptr)
+    _lib.gf_profile_start(ctx.ptr)
+    step_cnn(use_graph=0)
+    torch.cuda.synchronize()
+    _lib.gf_profile_stop(ctx.ptr)
+    prof = _lib.gf_profile_read(ctx.ptr)
+    ic, idf = infos["cnn"], infos["default"]
+    rel = (ic["chi2"] - idf["chi2"]) / idf["chi2"]
+    gemm_ms = tprof.get("k_gemm_bf16", (0, 0.0))[1]
+    step_ms = sum(v[1] for v in tprof.values())
+    train_flop = 3 * 2 * CNN_MAC_PER_STAMP * 256
+    result = dict(
+        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
+        value=round(nev / times["cnn"], 2), unit="fits/s", ms_per_step=round(times["cnn"] * 1e3, 3),
+        fits_per_s=round(nev / times["cnn"], 2),
+        lm=dict(iters_mean=float(ic["iters"].mean()), converged=float((ic["status"] == 0).mean())),
+        c5=dict(
+            default_fits_per_s=round(nev / times["default"], 2),
+            speedup_vs_default=round(times["default"] / times["cnn"], 3),
+            iters_mean_cnn=float(ic["iters"].mean()), iters_mean_default=float(idf["iters"].mean()),
+            converged_cnn=float((ic["status"] == 0).mean()), converged_default=float((idf["status"] == 0).mean()),
+            equal_chi2_frac=float(np.mean(np.abs(rel) <= 1e-5)), cnn_lower_chi2_frac=float(np.mean(rel < -1e-5)),
+            default_lower_chi2_frac=float(np.mean(rel > 1e-5)),
+            train=dict(stamps=args.train_stamps, epochs=args.epochs, steps=steps_trained, batch=256,
+                       render_s=round(t_render, 3), train_s=round(t_train, 3),
+                       stamps_per_s=round(args.epochs * args.train_stamps / t_train, 1),
+                       loss_per_epoch=[round(v, 5) for v in losses],
+                       step_kernel_ms=round(step_ms, 4), gemm_ms=round(gemm_ms, 4),
+                       gemm_tflops=round(train_flop / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms else None,
+                       gemm_frac_bf16_peak=round(train_flop / (gemm_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)
+                       if gemm_ms else None)),
+        config=dict(workload="C5: 4096 fresh 128x128 single-Sersic stamps (uneven-batch priors, Gaussian/Moffat "
+                             "PSF 15..33 px, noise 0.02); one step = network proposal + one gf_fit_lm call to chi2 "
+                             "rel tol 1e-5", stamps=nev, side=side, oversample=5),
+    )
+    npix = nev * side * side
+    fb = {"k_fft_rows": [0, 0], "k_fft_cols": [0, 0], "k_fft_irows": [0, 0]}
+    geo = dict(npix=npix, npad=npix, Mw=1, H=1, nch=7, ncomp=1, S=5, L=2, fft_bytes=fb)
+    return result, prof, geo, dict(info=ic, nfev=int(ic["nfev"].sum()), njev=int(ic["njev"].sum()))
+
+
 def roofline(prof, geo):
     total = sum(v[1] for v in prof.values())
     name = max(prof, key=lambda k: prof[k][1])
@@ -400,6 +513,35 @@ def cpu_baseline_c3(extra, seconds):
                        + ", ".join(used) + ")")
 
 
+def cpu_baseline_c5(extra, seconds):
+    """One oracle LM iteration on its own rendering of a 128x128 C5-like
+    stamp (one per PSF size class), times the GPU run's mean iterations of
+    the network-seeded fits (extrapolated to the 4096-stamp batch)."""
+    from oracle import gfo
+    import synth
+    gfo.set_threads(os.cpu_count() or 1)
+    info = extra["info"]
+    g = synth.rng(3000)
+    ts = []
+    t_all = time.perf_counter()
+    for i in range(4):
+        st = synth.c3_stamp(g, 128, i, 3000)
+        psf = st.psf.astype(np.float32).astype(np.float64)
+        m = gfo.model(128, 128, st.truth, psf, 5)
+        d, w = synth.add_gaussian_noise(m, 0.02, 3000 + i)
+        lo, hi = synth.bounds(1, 128, 128)
+        t0 = time.perf_counter()
+        gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=1)
+        ts.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all > seconds:
+            break
+    per_iter = float(np.mean(ts))
+    total = per_iter * float(info["iters"].mean()) * len(info)
+    return dict(value=round(len(info) / total, 4), unit="fits/s", cores=gfo.get_threads(), kind="oracle",
+                sample=f"extrapolated: {len(ts)} oracle LM iterations on 128x128 stamps "
+                       f"(mean {per_iter * 1e3:.0f} ms) x mean GPU iterations x 4096 stamps")
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -427,10 +569,12 @@ def main():
         result, prof, geo, extra = run_c2(args, torch, ops, synth)
     elif args.workload == "c3":
         result, prof, geo, extra = run_c3(args, torch, ops, synth)
+    elif args.workload == "c5":
+        result, prof, geo, extra = run_c5(args, torch, ops, synth)
     else:
         result, prof, geo, extra = run_c4(args, torch, ops, synth)
     geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = 1
-    if args.workload in ("c2", "c3"):
+    if args.workload in ("c2", "c3", "c5"):
         # per fit the FFT passes run 7 n_comp channels (Jacobian) and 1 channel (trial) per launch: use the average
         n_jac = extra["njev"]
         n_trial = extra["nfev"]
@@ -439,7 +583,7 @@ def main():
         for k in ("rows", "cols", "irows"):
             geo["chan_k_fft_" + k] = avg
     rl, stages = roofline(prof, geo)
-    if args.workload == "c3":
+    if args.workload in ("c3", "c5"):
         # finished stamps skip their work units, so per-launch bytes of the
         # whole batch overstate what a launch moves: report times only
         for k in stages:
@@ -456,9 +600,11 @@ def main():
                steps=args.steps if args.steps is not None else (20 if args.workload == "c2" else 50),
                warmup=args.warmup if args.warmup is not None else 3, ms_per_step=result["ms_per_step"],
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
-               data="synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)",
+               data=("synthetic (seeded; stamps rendered by the library from on-device Philox4x64-10 prior draws and "
+                     "noise)" if args.workload == "c5" else
+                     "synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)"),
                config=result["config"], roofline=rl)
-    for k in ("fits_per_s", "lm", "mpix_per_s"):
+    for k in ("fits_per_s", "lm", "mpix_per_s", "c5"):
         if k in result:
             out[k] = result[k]
     out["stages"] = stages
@@ -467,6 +613,8 @@ def main():
             out["cpu_baseline"] = cpu_baseline_c2(extra, args.cpu_seconds)
         elif args.workload == "c3":
             out["cpu_baseline"] = cpu_baseline_c3(extra, args.cpu_seconds)
+        elif args.workload == "c5":
+            out["cpu_baseline"] = cpu_baseline_c5(extra, args.cpu_seconds)
         else:
             out["cpu_baseline"] = cpu_baseline_c4(extra, args.cpu_seconds)
     print(json.dumps(out))
