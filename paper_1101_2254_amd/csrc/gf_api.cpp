@@ -134,18 +134,49 @@ int fft_side(int m) {
   return L;
 }
 
+// Radices the LDS passes compute in registers.  A pass of radix R gives each
+// of the 256 threads ceil(kFftCap / (256 R)) butterflies, so the busiest
+// thread handles NB(R) R points; the plan is the factorisation of L that
+// minimises the sum over passes of NB(R) R (1 + 0.15 log2 R) + 10 (the last
+// term stands for a pass's two workgroup barriers).  For example 288 = 16 x 18
+// (both passes keep 80-95 % of the threads busy) beats 32 x 9 (47 % busy in
+// the first pass).
+constexpr int kRadices[] = {32, 27, 25, 24, 20, 18, 16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+
+double pass_cost(int R) {
+  const int nb = (kFftCap + kThreads * R - 1) / (kThreads * R);
+  return nb * R * (1.0 + 0.15 * std::log2((double)R)) + 10.0;
+}
+
+// Best factorisation of v into radices no larger than `maxr` (non-increasing
+// order, so each multiset is visited once).
+double best_plan(int v, int maxr, std::vector<int> &out) {
+  if (v == 1) {
+    out.clear();
+    return 0.0;
+  }
+  double best = 1e300;
+  std::vector<int> bestv, tmp;
+  for (int r : kRadices) {
+    if (r > maxr || v % r) continue;
+    const double c = pass_cost(r) + best_plan(v / r, r, tmp);
+    if (c < best) {
+      best = c;
+      bestv.assign(1, r);
+      bestv.insert(bestv.end(), tmp.begin(), tmp.end());
+    }
+  }
+  out = bestv;
+  return best;
+}
+
 FftPlan make_plan(int L, int tw_off) {
   FftPlan p;
   std::memset(&p, 0, sizeof(p));
   p.L = L;
   p.tw_off = tw_off;
   std::vector<int> rad;
-  int v = L;
-  while (v % 8 == 0) { rad.push_back(8); v /= 8; }
-  if (v % 4 == 0) { rad.push_back(4); v /= 4; }
-  if (v % 2 == 0) { rad.push_back(2); v /= 2; }
-  while (v % 5 == 0) { rad.push_back(5); v /= 5; }
-  while (v % 3 == 0) { rad.push_back(3); v /= 3; }
+  best_plan(L, 32, rad);
   p.nstages = (int)rad.size();
   int ns = 1;
   for (int s = 0; s < p.nstages; ++s) {

@@ -17,7 +17,7 @@ constexpr int kMaxComp = GF_MAX_COMP;
 constexpr int kMaxP = kNPC * kMaxComp + 1;
 constexpr int kThreads = 256;          // threads per workgroup for pixel kernels (4 wave64)
 constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one per thread)
-constexpr int kPixChunk = 2048;        // pixels per chi^2 workgroup (8 per thread)
+constexpr int kPixChunk = 4096;        // pixels per chi^2 workgroup (16 per thread)
 constexpr int kNeqChunk = 1024;        // pixels per normal-equation workgroup (256 per wave)
 constexpr int kFftCap = 3840;          // complex values in the FFT LDS buffer (T*L <= this)
 constexpr int kFftMaxStages = 12;

@@ -15,8 +15,13 @@
 //            real part -> first row, imaginary part -> second row, crop.
 // The 1/L^2 of the inverse transform is folded into the OTF.
 //
-// Transforms are mixed-radix Stockham passes (radix 2, 3, 4, 5, 8) with FP32
-// twiddles that the host computes in FP64, done in place in LDS.
+// Transforms are mixed-radix Stockham passes done in place in LDS, with FP32
+// pass twiddles that the host computes in FP64.  A pass's radix is computed
+// in registers: 2, 3, 4, 5 and 8 directly, and the composites 6 ... 32 by one
+// Cooley-Tukey split with compile-time twiddles, so the transform sizes of
+// the workloads (48 ... 576) take two LDS passes each.
+#include <utility>
+
 #include "gf_internal.h"
 
 namespace gf {
@@ -125,26 +130,139 @@ __device__ __forceinline__ void dft8(float2 *v) {
   v[7] = csub(e[3], o3);
 }
 
+// ------------------------------------------------------------ composite DFTs
+// Twiddles W_R^M = exp(-2 pi i M / R) of the in-register composite DFTs are
+// compile-time constants: cos and sin of 2 pi M / R evaluated in double by
+// octant reduction and Taylor series (|x| <= pi/4, 14 terms), then rounded.
+constexpr double kPiD = 3.14159265358979323846;
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+// (cos, sin) of 2 pi m / r for integers m, r > 0.
+struct CS {
+  double c, s;
+};
+constexpr CS unit_root(int m, int r) {
+  m %= r;
+  if (m < 0) m += r;
+  const int oct = (8 * m) / r;                                   // octant 0..7
+  const double x = 2.0 * kPiD * ((double)m / r) - oct * (kPiD / 4.0);   // [0, pi/4)
+  double c, s;
+  if (oct % 2 == 0) {
+    c = taylor_cos(x);
+    s = taylor_sin(x);
+  } else {
+    const double y = kPiD / 4.0 - x;                             // phi = pi/2 - y
+    c = taylor_sin(y);
+    s = taylor_cos(y);
+  }
+  switch (oct / 2) {
+    case 0: return CS{c, s};
+    case 1: return CS{-s, c};
+    case 2: return CS{-c, -s};
+    default: return CS{s, -c};
+  }
+}
+
+// a * W_R^M (forward) or a * conj(W_R^M) (inverse).
+template <int R, int M, bool INV>
+__device__ __forceinline__ float2 twc(float2 a) {
+  if constexpr (M % R == 0) {
+    return a;
+  } else {
+    constexpr CS w = unit_root(M, R);
+    constexpr float c = (float)w.c, sn = (float)w.s;
+    return INV ? make_float2(fmaf(a.x, c, -a.y * sn), fmaf(a.y, c, a.x * sn))
+               : make_float2(fmaf(a.x, c, a.y * sn), fmaf(a.y, c, -a.x * sn));
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 *v);
+
+// Slot B*n1 + n2 holds Y[n2][k1 = n1] after the first stage; it is scaled
+// by W_R^{n2 k1}.
+template <int A, int B, bool INV, int... I>
+__device__ __forceinline__ void tw_apply(float2 *v, std::integer_sequence<int, I...>) {
+  ((v[I] = twc<A * B, (I / B) * (I % B), INV>(v[I])), ...);
+}
+
+// Length R = A B by one Cooley-Tukey split, in place, natural order in and
+// out: n = B n1 + n2, k = k1 + A k2,
+//   X[k1 + A k2] = sum_n2 W_B^{n2 k2} W_R^{n2 k1} sum_n1 x[B n1 + n2] W_A^{n1 k1}.
+template <int A, int B, bool INV>
+__device__ __forceinline__ void dft_ab(float2 *v) {
+#pragma unroll
+  for (int n2 = 0; n2 < B; ++n2) {
+    float2 t[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + n2];
+    dft<A, INV>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) v[B * k1 + n2] = t[k1];
+  }
+  tw_apply<A, B, INV>(v, std::make_integer_sequence<int, A * B>{});
+  float2 o[A * B];
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) {
+    float2 t[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) t[n2] = v[B * k1 + n2];
+    dft<B, INV>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) o[k1 + A * k2] = t[k2];
+  }
+#pragma unroll
+  for (int i = 0; i < A * B; ++i) v[i] = o[i];
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2 *v) {
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 3) dft3<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
   else if constexpr (R == 5) dft5<INV>(v);
-  else dft8<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else if constexpr (R == 6) dft_ab<2, 3, INV>(v);
+  else if constexpr (R == 9) dft_ab<3, 3, INV>(v);
+  else if constexpr (R == 10) dft_ab<2, 5, INV>(v);
+  else if constexpr (R == 12) dft_ab<4, 3, INV>(v);
+  else if constexpr (R == 15) dft_ab<3, 5, INV>(v);
+  else if constexpr (R == 16) dft_ab<4, 4, INV>(v);
+  else if constexpr (R == 18) dft_ab<2, 9, INV>(v);
+  else if constexpr (R == 20) dft_ab<4, 5, INV>(v);
+  else if constexpr (R == 24) dft_ab<8, 3, INV>(v);
+  else if constexpr (R == 25) dft_ab<5, 5, INV>(v);
+  else if constexpr (R == 27) dft_ab<3, 9, INV>(v);
+  else if constexpr (R == 32) dft_ab<8, 4, INV>(v);
+  else static_assert(R == 2, "unsupported radix");
 }
 
 // One in-place Stockham pass over T transforms of length L (stride Ls).
 // Butterfly j of a transform reads x[j + r L/R], twiddles input r by
-// W_{Ns R}^{r k} (k = j mod Ns), does a radix-R DFT and writes to
+// W_{Ns R}^{r k} (k = j mod Ns), does a radix-R DFT in registers and writes to
 // (j div Ns) Ns R + k + r Ns.  Every thread first loads all of its
-// butterflies (at most 16 complex values: T L <= kFftCap guarantees one
-// round), the workgroup synchronises, and then all results are stored, so a
-// single LDS buffer suffices.
+// butterflies (NB of them: T L <= kFftCap guarantees one round), the
+// workgroup synchronises, and then all results are stored, so a single LDS
+// buffer suffices.  For R > 8 the twiddle of input r is formed as
+// W^{(r mod 8) k} W^{8 (r div 8) k} from two table entries.
 template <int R, bool INV>
 __device__ __forceinline__ void stockham_pass(float2 *__restrict__ buf, int T, int L, int Ls, int Ns, uint32_t ns_m,
                                               uint32_t nb_m, const float2 *__restrict__ tw) {
-  constexpr int NB = 16 / R;
+  constexpr int NB = (kFftCap + kThreads * R - 1) / (kThreads * R);
   const int nb = L / R;
   const int total = T * nb;
   const int twstep = L / (Ns * R);
@@ -163,10 +281,26 @@ __device__ __forceinline__ void stockham_pass(float2 *__restrict__ buf, int T, i
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = buf[lp(src + r * nb)];
       if (Ns > 1) {
+        const int ks = k * twstep;
+        if constexpr (R <= 8) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const float2 w = tw[r * k * twstep];
-          v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+          for (int r = 1; r < R; ++r) {
+            const float2 w = tw[r * ks];
+            v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+          }
+        } else {
+          float2 lo[8], hi[(R + 7) / 8];
+          lo[0] = make_float2(1.f, 0.f);
+#pragma unroll
+          for (int a = 1; a < 8; ++a) lo[a] = tw[a * ks];
+          hi[0] = make_float2(1.f, 0.f);
+#pragma unroll
+          for (int c = 1; c < (R + 7) / 8; ++c) hi[c] = tw[8 * c * ks];
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const float2 w = (r >= 8) ? ((r & 7) ? cmul(lo[r & 7], hi[r >> 3]) : hi[r >> 3]) : lo[r];
+            v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+          }
         }
       }
       dft<R, INV>(v[b]);
@@ -196,7 +330,19 @@ __device__ __forceinline__ void lds_fft(float2 *buf, int T, int Ls, const FftPla
       case 3: stockham_pass<3, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
       case 4: stockham_pass<4, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
       case 5: stockham_pass<5, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      default: stockham_pass<8, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 6: stockham_pass<6, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 8: stockham_pass<8, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 9: stockham_pass<9, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 10: stockham_pass<10, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 12: stockham_pass<12, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 15: stockham_pass<15, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 16: stockham_pass<16, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 18: stockham_pass<18, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 20: stockham_pass<20, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 24: stockham_pass<24, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 25: stockham_pass<25, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 27: stockham_pass<27, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      default: stockham_pass<32, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
     }
   }
 }

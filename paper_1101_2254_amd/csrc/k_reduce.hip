@@ -77,12 +77,18 @@ __device__ __forceinline__ float sky_of(const TT *theta, const StampDesc &d) {
 
 // ------------------------------------------------------------------ chi^2
 // r = sqrt(w) (d - m - sky); per workgroup a (hi, lo) partial of sum r^2.
+// Stamps whose image offsets are multiples of four floats (and pointers
+// 16-byte aligned: vec_ok) move four pixels per 16-byte load; every thread
+// issues all of its loads before the first use.  Pixels past the stamp end
+// enter with zero weight, so they add exact zeros.
+constexpr int kChi2Vec = kPixChunk / (4 * kThreads);
+
 template <typename TT>
 __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
                                                    const float *__restrict__ model, const TT *__restrict__ theta,
                                                    const float *__restrict__ data, const float *__restrict__ weight,
                                                    float *__restrict__ resid, float2 *__restrict__ part,
-                                                   const int *__restrict__ mask) {
+                                                   const int *__restrict__ mask, int vec_ok) {
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
@@ -91,19 +97,67 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
   const int npix = d.H * d.W;
   const int p0 = w.unit * kPixChunk;
   F2 acc = {0.f, 0.f};
+  if (vec_ok && ((d.pix | d.img) & 3) == 0) {
+    const float *mp = model + d.pix, *dp = data + d.img, *wp = weight + d.img;
+    float4 mv[kChi2Vec], dv[kChi2Vec], wv[kChi2Vec];
 #pragma unroll
-  for (int k = 0; k < kPixChunk / kThreads; ++k) {
-    const int p = p0 + k * kThreads + (int)threadIdx.x;
-    if (p < npix) {
-      const float wt = weight[d.img + p];
-      const float r = sqrtf(wt) * (data[d.img + p] - (model[d.pix + p] + sky));
-      if (resid) resid[d.pix + p] = r;
-      acc = f2_add1(acc, r * r);
+    for (int k = 0; k < kChi2Vec; ++k) {
+      const int p = p0 + 4 * (k * kThreads + (int)threadIdx.x);
+      if (p + 4 <= npix) {
+        mv[k] = *reinterpret_cast<const float4 *>(mp + p);
+        dv[k] = *reinterpret_cast<const float4 *>(dp + p);
+        wv[k] = *reinterpret_cast<const float4 *>(wp + p);
+      } else {
+        float t[3][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool in = p + j < npix;
+          t[0][j] = in ? mp[p + j] : 0.f;
+          t[1][j] = in ? dp[p + j] : 0.f;
+          t[2][j] = in ? wp[p + j] : 0.f;
+        }
+        mv[k] = make_float4(t[0][0], t[0][1], t[0][2], t[0][3]);
+        dv[k] = make_float4(t[1][0], t[1][1], t[1][2], t[1][3]);
+        wv[k] = make_float4(t[2][0], t[2][1], t[2][2], t[2][3]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kChi2Vec; ++k) {
+      const int p = p0 + 4 * (k * kThreads + (int)threadIdx.x);
+      const float4 r = make_float4(sqrtf(wv[k].x) * (dv[k].x - (mv[k].x + sky)),
+                                   sqrtf(wv[k].y) * (dv[k].y - (mv[k].y + sky)),
+                                   sqrtf(wv[k].z) * (dv[k].z - (mv[k].z + sky)),
+                                   sqrtf(wv[k].w) * (dv[k].w - (mv[k].w + sky)));
+      if (resid) {
+        if (p + 4 <= npix) {
+          *reinterpret_cast<float4 *>(resid + d.pix + p) = r;
+        } else {
+          const float rr[4] = {r.x, r.y, r.z, r.w};
+          for (int j = 0; j < 4 && p + j < npix; ++j) resid[d.pix + p + j] = rr[j];
+        }
+      }
+      acc = f2_add1(acc, r.x * r.x);
+      acc = f2_add1(acc, r.y * r.y);
+      acc = f2_add1(acc, r.z * r.z);
+      acc = f2_add1(acc, r.w * r.w);
+    }
+  } else {
+#pragma unroll 4
+    for (int k = 0; k < kPixChunk / kThreads; ++k) {
+      const int p = p0 + k * kThreads + (int)threadIdx.x;
+      if (p < npix) {
+        const float wt = weight[d.img + p];
+        const float r = sqrtf(wt) * (data[d.img + p] - (model[d.pix + p] + sky));
+        if (resid) resid[d.pix + p] = r;
+        acc = f2_add1(acc, r * r);
+      }
     }
   }
   const F2 tot = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.x] = make_float2(tot.hi, tot.lo);
 }
+
+static inline int aligned16(const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // One wave64 per stamp: the workgroup partials of the stamp, added in a fixed
 // order (each lane walks its strided share, then a shuffle tree).
@@ -126,8 +180,9 @@ hipError_t launch_chi2_part(hipStream_t st, const gf_batch *b, const float *mode
   dim3 grid((unsigned)b->h_pix.size()), blk(kThreads);
   if (grid.x == 0) return hipSuccess;
   ProfScope ps(st, "k_chi2");
+  const int vec_ok = aligned16(model) && aligned16(data) && aligned16(weight);
   hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, model, theta, data, weight,
-                     (float *)nullptr, part, mask);
+                     (float *)nullptr, part, mask, vec_ok);
   return hipGetLastError();
 }
 
@@ -139,12 +194,13 @@ hipError_t launch_chi2(hipStream_t st, const gf_batch *b, const float *model, co
   if (grid.x == 0) return hipSuccess;
   {
     ProfScope ps(st, "k_chi2");
+    const int vec_ok = aligned16(model) && aligned16(data) && aligned16(weight) && aligned16(resid);
     if (theta_f64)
       hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, model, (const double *)theta,
-                         data, weight, resid, part, mask);
+                         data, weight, resid, part, mask, vec_ok);
     else
       hipLaunchKernelGGL((k_chi2<float>), grid, blk, 0, st, b->d_desc, b->d_pix, model, (const float *)theta, data,
-                         weight, resid, part, mask);
+                         weight, resid, part, mask, vec_ok);
   }
   {
     ProfScope ps(st, "k_pair_final");
