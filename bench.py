@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--breakdown", action="store_true", help="print the per-kernel breakdown to stderr")
+    ap.add_argument("--calibrate-peaks", action="store_true",
+                    help="only run the triad / FMA / transcendental probes and print the measured peaks")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB device buffer three times (reference for HBM byte counters)")
     return ap.parse_args()
@@ -392,6 +394,58 @@ def run_c5(args, torch, ops, synth):
     return result, prof, geo, dict(info=ic, nfev=int(ic["nfev"].sum()), njev=int(ic["njev"].sum()))
 
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by the copy calibration: fetch x2, write x1), as
+# summarised in profiles/*_hbm_traffic.md: bytes = once + per_channel x
+# channels per launch.  Valid only while the kernel source is the one the
+# counters were taken on (first 16 hex digits of its SHA-256).
+TRAFFIC = {
+    "c2": dict(kernel="k_fft_cols", source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="8c237da2a3e93720",
+               once=1.18e6, per_channel=3.232e6, summary="profiles/c2_fit_hbm_traffic.md"),
+    "c4": dict(kernel="k_eval", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="8dce2d07f7f0e404",
+               once=383.98e6, per_channel=0.0, summary="profiles/c4_likelihood_hbm_traffic.md"),
+}
+
+
+def stage_roofline(prof, geo):
+    """Steps 2 and 3 as whole stages, with the algorithmic bytes of their
+    definitions: convolution = read the padded model + write the stamp per
+    channel + the OTF once; chi^2 = read model, data and weight (data and
+    weight once per distinct image).  The FFT's own spectra traffic is not
+    counted here (it is in the per-kernel figures of `stages`)."""
+    out = {}
+    L = geo.get("L", 0)
+    if L > 2 and all(k in prof for k in ("k_fft_rows", "k_fft_cols", "k_fft_irows")):
+        n = prof["k_fft_rows"][0]
+        t = sum(prof[k][1] / prof[k][0] for k in ("k_fft_rows", "k_fft_cols", "k_fft_irows")) * 1e-3
+        ch = geo.get("chan_k_fft_rows", 1)
+        b = ch * (4 * geo["npad"] + 4 * geo["npix"]) + L * (L // 2 + 1) * 8
+        out["convolution"] = dict(kernels=["k_fft_rows", "k_fft_cols", "k_fft_irows"], launches=n,
+                                  bytes_per_launch=int(b), us_per_launch=round(t * 1e6, 2),
+                                  gbs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
+    if "k_chi2" in prof:
+        n, ms = prof["k_chi2"]
+        t = ms / n * 1e-3
+        b = 4 * geo["npix"] + 8 * geo.get("nimg", geo["npix"])
+        out["chi2"] = dict(kernels=["k_chi2"], launches=n, bytes_per_launch=int(b), us_per_launch=round(t * 1e6, 2),
+                           gbs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
+    return out
+
+
+def measured_traffic(workload, rl, geo):
+    import hashlib
+    t = TRAFFIC.get(workload)
+    if not t or rl.get("kernel") != t["kernel"]:
+        return None
+    try:
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha16"]:
+                return None
+    except OSError:
+        return None
+    return round(t["once"] + t["per_channel"] * geo.get("chan_" + t["kernel"], 1), 0)
+
+
 def roofline(prof, geo):
     total = sum(v[1] for v in prof.values())
     name = max(prof, key=lambda k: prof[k][1])
@@ -564,6 +618,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=src.numel() * 4, copies=3)))
         return
+    if args.calibrate_peaks:
+        from paper_1101_2254_amd import _lib
+        ctx = ops.Context(0)
+        ctx.bind_stream()
+        out = dict(triad_gbs=_lib.gf_probe(ctx.ptr, 0, 1 << 28, 10), fma_tflops=_lib.gf_probe(ctx.ptr, 1, 4096, 5),
+                   transcendental_gops=_lib.gf_probe(ctx.ptr, 2, 2048, 5))
+        out["triad_frac_of_8tbs"] = round(out["triad_gbs"] / HBM_PEAK_GBS, 4)
+        print(json.dumps(out))
+        return
     print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
     if args.workload == "c2":
         result, prof, geo, extra = run_c2(args, torch, ops, synth)
@@ -583,6 +646,10 @@ def main():
         for k in ("rows", "cols", "irows"):
             geo["chan_k_fft_" + k] = avg
     rl, stages = roofline(prof, geo)
+    rl["traffic"] = measured_traffic(args.workload, rl, geo)
+    stage_rl = stage_roofline(prof, geo) if args.workload in ("c2", "c4") else {}
+    if rl["traffic"] is not None:
+        rl["traffic_source"] = TRAFFIC[args.workload]["summary"]
     if args.workload in ("c3", "c5"):
         # finished stamps skip their work units, so per-launch bytes of the
         # whole batch overstate what a launch moves: report times only
@@ -608,6 +675,8 @@ def main():
         if k in result:
             out[k] = result[k]
     out["stages"] = stages
+    if stage_rl:
+        out["stage_roofline"] = stage_rl
     if not args.no_cpu:
         if args.workload == "c2":
             out["cpu_baseline"] = cpu_baseline_c2(extra, args.cpu_seconds)

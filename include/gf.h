@@ -339,6 +339,16 @@ gf_status gf_profile_stop(gf_ctx *ctx);
 int gf_profile_kernels(gf_ctx *ctx);
 gf_status gf_profile_get(gf_ctx *ctx, int i, char *name, int name_cap, int64_t *launches, double *total_ms);
 
+/* Roofline calibration probes on the context's device (blocking; they
+ * allocate and free their own buffers).
+ *   kind 0: streaming triad c = a + s b over n floats per array, reps times;
+ *           result = GB/s counting 12 bytes per element.
+ *   kind 1: eight independent FP32 FMA chains of n steps per thread (64
+ *           workgroups of 256 per compute unit), reps times; result = TFLOP/s.
+ *   kind 2: four chains of exp2(log2(x) a) (hardware transcendentals) of n
+ *           steps per thread; result = 10^9 transcendental operations/s. */
+gf_status gf_probe(gf_ctx *ctx, int kind, int64_t n, int reps, double *result);
+
 /* Library version string. */
 const char *gf_version(void);
 

@@ -28,7 +28,7 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_moments_guess",
            "gf_cnn_create", "gf_cnn_destroy", "gf_cnn_param_count", "gf_cnn_init", "gf_cnn_set_params",
            "gf_cnn_get_params", "gf_cnn_forward", "gf_cnn_gradients", "gf_cnn_train_step", "gf_cnn_steps",
-           "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_profile_start",
+           "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_version")
 
 
@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
         "gf_philox": (i32, [vp, u64, u64, vp, i64, vp]),
         "gf_normal_noise": (i32, [vp, i64, flt, u64, u64, vp, vp, vp]),
         "gf_draw_prior": (i32, [vp, i32, i32, u64, u64, vp, vp]),
+        "gf_probe": (i32, [vp, i32, i64, i32, ctypes.POINTER(ctypes.c_double)]),
         "gf_profile_start": (i32, [vp]),
         "gf_profile_stop": (i32, [vp]),
         "gf_profile_kernels": (i32, [vp]),
@@ -324,3 +325,9 @@ def gf_normal_noise(ctx, n, sigma, key0, key1, ctr, clean_ptr, out_ptr):
 
 def gf_draw_prior(ctx, n, side, key0, key1, ctr, theta_ptr):
     check(lib().gf_draw_prior(ctx, n, side, key0, key1, _counter(ctr), theta_ptr), ctx)
+
+
+def gf_probe(ctx, kind: int, n: int, reps: int) -> float:
+    r = ctypes.c_double()
+    check(lib().gf_probe(ctx, int(kind), int(n), int(reps), ctypes.byref(r)), ctx)
+    return r.value

@@ -306,6 +306,31 @@ __global__ __launch_bounds__(256) void k_colsum_part(const T *__restrict__ x, in
   }
 }
 
+// BF16 matrices with N % 8 == 0: each thread adds 16-byte vectors of eight
+// columns over a strided subset of the chunk's rows; the row groups are then
+// added in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum_part_v8(const bf16_t *__restrict__ x, int M, int N, int rows_per,
+                                                        float *__restrict__ part) {
+  __shared__ float red[256 * 8];
+  const int cv = N / 8, g = 256 / cv, c8 = threadIdx.x % cv, rg = threadIdx.x / cv;
+  const int r0 = blockIdx.x * rows_per, r1 = min(M, r0 + rows_per);
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int r = r0 + rg; r < r1; r += g) {
+    B8 v;
+    v.u = *reinterpret_cast<const uint4 *>(x + (int64_t)r * N + c8 * 8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] += bf2f(v.h[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[rg * N + c8 * 8 + j] = acc[j];
+  __syncthreads();
+  for (int c = threadIdx.x; c < N; c += 256) {
+    float t = 0.f;
+    for (int q = 0; q < g; ++q) t += red[q * N + c];
+    part[(int64_t)blockIdx.x * N + c] = t;
+  }
+}
+
 __global__ void k_colsum_final(const float *__restrict__ part, int chunks, int N, float *__restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
@@ -477,7 +502,9 @@ hipError_t launch_colsum(hipStream_t st, const void *x, bool is_bf16, int M, int
   const int rows_per = 2048;
   const int chunks = (M + rows_per - 1) / rows_per;
   ProfScope ps(st, "k_colsum");
-  if (is_bf16)
+  if (is_bf16 && N % 8 == 0 && 256 % (N / 8) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0)
+    hipLaunchKernelGGL(k_colsum_part_v8, dim3(chunks), dim3(256), 0, st, (const bf16_t *)x, M, N, rows_per, part);
+  else if (is_bf16)
     hipLaunchKernelGGL(k_colsum_part<bf16_t>, dim3(chunks), dim3(256), 0, st, (const bf16_t *)x, M, N, rows_per, part);
   else
     hipLaunchKernelGGL(k_colsum_part<float>, dim3(chunks), dim3(256), 0, st, (const float *)x, M, N, rows_per, part);
