@@ -265,6 +265,26 @@ def run_c4(args, torch, ops, synth):
     t = time.perf_counter() - t0
     ms = t / K * 1e3
     npix = 256 * 256 * nvec
+    # Metropolis chains on the same batch: one chain per vector, started from
+    # this step's vectors, 2000 steps (each step = steps 1-3 for all chains)
+    n_mc = 2000
+    scale = torch.from_numpy(np.tile(np.abs(base.truth) * 1e-4 + 1e-6, nvec)).to(dev)
+    lo_b, hi_b = synth.bounds(1, 256, 256)
+    lo_m = torch.from_numpy(np.tile(lo_b, nvec)).to(dev)
+    hi_m = torch.from_numpy(np.tile(hi_b, nvec)).to(dev)
+    th_mc = thetas[0].double()
+    ops.mcmc_run(ctx, batch, psf, data, weight, th_mc, scale, 10, key=(4004, 1), lo=lo_m, hi=hi_m,
+                 keep_samples=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, c2_mc, _, acc_mc = ops.mcmc_run(ctx, batch, psf, data, weight, th_mc, scale, n_mc, key=(4004, 1), stream=1,
+                                       lo=lo_m, hi=hi_m, keep_samples=False)
+    torch.cuda.synchronize()
+    t_mc = time.perf_counter() - t0
+    mcmc = dict(chains=nvec, steps=n_mc, ms_per_step=round(t_mc / n_mc * 1e3, 4),
+                mpix_per_s=round(npix * n_mc / t_mc / 1e6, 1),
+                accept_rate=round(float(acc_mc.double().mean().item()) / n_mc, 4),
+                proposal="theta' = theta + (1e-4 |theta_true| + 1e-6) z, flat prior on the fit bounds")
     from paper_1101_2254_amd import _lib
     _lib.gf_profile_start(ctx.ptr)
     ops.likelihood(ctx, batch, psf, thetas[0], data, weight, 5, work=work, out=out)
@@ -279,6 +299,7 @@ def run_c4(args, torch, ops, synth):
         config=dict(workload="C4: likelihood batch, 1024 parameter vectors x one 256x256 image, 33x33 Moffat PSF, "
                              "288-point FFT, 5x5 oversampling; one step = steps 1-3 for all vectors",
                     image=[256, 256], psf=33, fft_side=psf.fft_side[0], vectors=nvec, oversample=5),
+        mcmc=mcmc,
     )
     return result, prof, geo, dict(base=base, thetas_host=synth.c4_vectors(W, nvec), npix=npix)
 
@@ -671,7 +692,7 @@ def main():
                      "noise)" if args.workload == "c5" else
                      "synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)"),
                config=result["config"], roofline=rl)
-    for k in ("fits_per_s", "lm", "mpix_per_s", "c5"):
+    for k in ("fits_per_s", "lm", "mpix_per_s", "c5", "mcmc"):
         if k in result:
             out[k] = result[k]
     out["stages"] = stages

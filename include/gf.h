@@ -237,6 +237,44 @@ void gf_lm_opts_default(gf_lm_opts *opts);
 gf_status gf_fit_lm(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
                     double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
 
+/* ------------------------------------------------------------ MCMC
+ *
+ * The paper names Bayesian sampling (galphat) as the third routine family
+ * built on the same steps 1-3 (Sec. 2).  gf_mcmc_run runs random-walk
+ * Metropolis with one chain per stamp of the batch (typically a
+ * shared-image batch: many chains on one observation):
+ *   target    exp(-chi2(theta)/2), flat prior on [lo, hi] (null: unbounded);
+ *   proposal  theta' = theta + scale * z, z ~ N(0, I) per parameter;
+ *   accept    iff ln u < -(chi2(theta') - chi2(theta))/2 (theta' outside the
+ *             box is rejected without evaluation).
+ * Random numbers: Philox4x64-10 with key (key0, key1); chain c at step t uses
+ * counter (b, c, step0 + t, stream) with b = 0..3 giving the normals
+ * z_{4b..4b+3} (Box-Muller as in gf_normal_noise) and b = 4 word 0 the
+ * uniform u.  Running n steps from step0 and then n more from step0 + n gives
+ * the same chain as 2n steps at once.
+ * theta_io: device [n_par] FP64 start in, last state out.  chi2_out: device
+ * [n_stamps] FP64, chi^2 of the last state.  samples: device FP32
+ * [n_steps / thin][n_par] (the state after steps thin, 2 thin, ...), or null.
+ * accepted: device int32 [n_stamps], incremented per accepted step, or null.
+ * All steps run on the device (one captured HIP graph replayed n_steps times). */
+typedef struct {
+  int32_t n_steps;
+  int32_t oversample;
+  int32_t thin;
+  int32_t use_graph;
+  uint64_t key0, key1;
+  uint64_t stream;
+  int64_t step0;
+  const double *scale;  /* device [n_par] proposal standard deviations (null: no move) */
+  const double *lo;     /* device [n_par] or null */
+  const double *hi;     /* device [n_par] or null */
+} gf_mcmc_opts;
+
+void gf_mcmc_opts_default(gf_mcmc_opts *opts);
+gf_status gf_mcmc_run(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
+                      double *theta_io, double *chi2_out, const gf_mcmc_opts *opts, float *samples,
+                      int32_t *accepted);
+
 /* ------------------------------------------------------------ starting points
  *
  * The paper's outlook (Sec. 5) notes that a fit only finds the minimum near

@@ -25,7 +25,8 @@ GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
 EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_synchronize", "gf_batch_create",
            "gf_batch_destroy", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
            "gf_psf_destroy", "gf_psf_paths", "gf_eval_model", "gf_convolve_psf", "gf_model", "gf_chi2", "gf_likelihood",
-           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_moments_guess",
+           "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_mcmc_opts_default", "gf_mcmc_run",
+           "gf_moments_guess",
            "gf_cnn_create", "gf_cnn_destroy", "gf_cnn_param_count", "gf_cnn_init", "gf_cnn_set_params",
            "gf_cnn_get_params", "gf_cnn_forward", "gf_cnn_gradients", "gf_cnn_train_step", "gf_cnn_steps",
            "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
@@ -38,6 +39,13 @@ class GfLmOpts(ctypes.Structure):
                 ("lambda_max", ctypes.c_double), ("ftol", ctypes.c_double), ("xtol", ctypes.c_double),
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("free_mask", ctypes.c_void_p),
                 ("poll_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class GfMcmcOpts(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("oversample", ctypes.c_int32), ("thin", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("key0", ctypes.c_uint64), ("key1", ctypes.c_uint64),
+                ("stream", ctypes.c_uint64), ("step0", ctypes.c_int64), ("scale", ctypes.c_void_p),
+                ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p)]
 
 
 class GfLmResult(ctypes.Structure):
@@ -91,6 +99,8 @@ def lib() -> ctypes.CDLL:
         "gf_jacobian": (i32, [vp, vp, vp, vp, i32, i32, vp, vp, flt, vp]),
         "gf_lm_opts_default": (None, [ctypes.POINTER(GfLmOpts)]),
         "gf_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
+        "gf_mcmc_opts_default": (None, [ctypes.POINTER(GfMcmcOpts)]),
+        "gf_mcmc_run": (i32, [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfMcmcOpts), vp, vp]),
         "gf_moments_guess": (i32, [vp, vp, vp, vp]),
         "gf_cnn_create": (i32, [vp, i32, i32, pvp]),
         "gf_cnn_destroy": (None, [vp]),
@@ -331,3 +341,15 @@ def gf_probe(ctx, kind: int, n: int, reps: int) -> float:
     r = ctypes.c_double()
     check(lib().gf_probe(ctx, int(kind), int(n), int(reps), ctypes.byref(r)), ctx)
     return r.value
+
+
+# ---------------------------------------------------------------- MCMC
+def gf_mcmc_opts_default() -> GfMcmcOpts:
+    o = GfMcmcOpts()
+    lib().gf_mcmc_opts_default(ctypes.byref(o))
+    return o
+
+
+def gf_mcmc_run(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, chi2_ptr, opts: GfMcmcOpts, samples_ptr, acc_ptr):
+    check(lib().gf_mcmc_run(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, chi2_ptr, ctypes.byref(opts), samples_ptr,
+                            acc_ptr), ctx)

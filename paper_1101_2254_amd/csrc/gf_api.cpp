@@ -44,6 +44,12 @@ hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const 
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
                             const double *, int *, int *, int *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
+hipError_t launch_mcmc_propose(hipStream_t, const gf_batch *, const double *, const double *, const double *,
+                               const double *, uint64_t, uint64_t, uint64_t, int64_t, const int64_t *, double *, int *);
+hipError_t launch_mcmc_init(hipStream_t, int, const float2 *, double *, int64_t *);
+hipError_t launch_mcmc_accept(hipStream_t, const gf_batch *, const float2 *, const int *, uint64_t, uint64_t,
+                              uint64_t, int64_t, int64_t *, double *, const double *, double *, int32_t *, float *,
+                              int);
 }  // namespace gf
 
 using namespace gf;
@@ -874,6 +880,106 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   st = run();
   cleanup();
   return st;
+}
+
+// ---------------------------------------------------------------- MCMC
+void gf_mcmc_opts_default(gf_mcmc_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->n_steps = 1000;
+  o->oversample = 5;
+  o->thin = 1;
+  o->use_graph = 1;
+}
+
+gf_status gf_mcmc_run(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *data, const float *weight,
+                      double *theta, double *chi2, const gf_mcmc_opts *opts, float *samples, int32_t *accepted) {
+  ProfBind pb_(c);
+  if (!c || !b || !p || !data || !weight || !theta || !chi2 || !opts)
+    return fail(c, GF_EINVAL, "gf_mcmc_run: null argument");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_mcmc_run: PSF prepared for another batch");
+  const gf_mcmc_opts o = *opts;
+  if (o.n_steps < 0 || o.thin < 1 || o.oversample < 1 || o.oversample > GF_MAX_OVERSAMPLE || o.step0 < 0)
+    return fail(c, GF_EINVAL, "gf_mcmc_run: invalid options");
+  const int S = o.oversample;
+  Arena a;
+  double *theta_t = nullptr, *chi2_d = nullptr;
+  float *mpad = nullptr, *mconv = nullptr;
+  float2 *S1 = nullptr, *S2 = nullptr, *cpart = nullptr, *pairs = nullptr;
+  int *mask = nullptr;
+  int64_t *tstep = nullptr;
+  auto layout = [&](Arena &ar) {
+    theta_t = ar.take<double>(b->n_par);
+    mpad = ar.take<float>(b->n_pad);
+    mconv = ar.take<float>(b->n_pix);
+    S1 = ar.take<float2>(p->n_s1);
+    S2 = ar.take<float2>(p->n_s2);
+    cpart = ar.take<float2>((int64_t)b->h_pix.size());
+    pairs = ar.take<float2>(b->n);
+    mask = ar.take<int>(b->n);
+    tstep = ar.take<int64_t>(1);
+    chi2_d = chi2;
+  };
+  layout(a);
+  gf_status st = ensure_ws(c, a.off);
+  if (st != GF_OK) return st;
+  st = ensure_counters(c, b->n);
+  if (st != GF_OK) return st;
+  a = Arena{(char *)c->ws, 0};
+  layout(a);
+  hipStream_t cs = c->stream;
+  // chi^2 of the start point
+  GF_TRY(c, launch_eval_d(cs, b, theta, S, c->d_bn, mpad, nullptr));
+  GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, nullptr));
+  GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, nullptr));
+  GF_TRY(c, launch_chi2(cs, b, mconv, theta, true, data, weight, nullptr, cpart, c->d_counters, pairs, nullptr));
+  GF_TRY(c, launch_mcmc_init(cs, b->n, pairs, chi2_d, tstep));
+  auto step = [&](hipStream_t sx) -> gf_status {
+    GF_TRY(c, launch_mcmc_propose(sx, b, theta, o.scale, o.lo, o.hi, o.key0, o.key1, o.stream, o.step0, tstep,
+                                  theta_t, mask));
+    GF_TRY(c, launch_eval_d(sx, b, theta_t, S, c->d_bn, mpad, mask));
+    GF_TRY(c, launch_fft_conv(sx, b, p, mpad, 1, S1, S2, mconv, mask));
+    GF_TRY(c, launch_direct(sx, b, p, mpad, 1, mconv, false, mask));
+    GF_TRY(c, launch_chi2_part(sx, b, mconv, theta_t, data, weight, cpart, mask));
+    GF_TRY(c, launch_mcmc_accept(sx, b, cpart, mask, o.key0, o.key1, o.stream, o.step0, tstep, theta, theta_t, chi2_d,
+                                 accepted, samples, o.thin));
+    return GF_OK;
+  };
+  if (o.use_graph && o.n_steps > 1) {
+    hipStream_t gs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GF_TRY(c, hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    gf_status r = GF_OK;
+    auto body = [&]() -> gf_status {
+      GF_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      GF_TRY(c, hipEventRecord(ev, cs));
+      GF_TRY(c, hipStreamWaitEvent(gs, ev, 0));
+      GF_TRY(c, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      gf_status s2 = step(gs);
+      hipError_t ce = hipStreamEndCapture(gs, &graph);
+      if (s2 != GF_OK) return s2;
+      GF_TRY(c, ce);
+      GF_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      for (int t = 0; t < o.n_steps; ++t) GF_TRY(c, hipGraphLaunch(exec, gs));
+      GF_TRY(c, hipEventRecord(ev, gs));
+      GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
+      return GF_OK;
+    };
+    r = body();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(gs);
+    (void)hipStreamDestroy(gs);
+    if (ev) (void)hipEventDestroy(ev);
+    return r;
+  }
+  for (int t = 0; t < o.n_steps; ++t) {
+    gf_status r = step(cs);
+    if (r != GF_OK) return r;
+  }
+  return GF_OK;
 }
 
 // ---------------------------------------------------------------- profiling

@@ -280,3 +280,35 @@ class ModelFn(torch.autograd.Function):
         ctx, batch, psf, oversample = fctx.gf
         return jacobian_adjoint(ctx, batch, psf, theta, g.contiguous().to(torch.float32), None, 1.0,
                                 oversample), None, None, None, None
+
+
+# ------------------------------------------------------------------ MCMC
+def mcmc_run(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: torch.Tensor, theta0: torch.Tensor,
+             scale: torch.Tensor, n_steps: int, key=(0, 0), stream: int = 0, step0: int = 0, thin: int = 1,
+             lo=None, hi=None, keep_samples: bool = True, oversample: int = 5, use_graph: bool = True):
+    """Random-walk Metropolis, one chain per stamp (gf_mcmc_run).
+
+    Returns (theta float64 [n_par] after the last step, chi2 float64 [n],
+    samples float32 [n_steps // thin, n_par] or None, accepted int32 [n])."""
+    n_par = batch.sizes["n_par"]
+    _need(theta0, torch.float64, n_par, "theta0")
+    _need(scale, torch.float64, n_par, "scale")
+    _need(data, torch.float32, batch.sizes["n_img"], "data")
+    _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    o = L.gf_mcmc_opts_default()
+    o.n_steps, o.oversample, o.thin, o.use_graph = int(n_steps), int(oversample), int(thin), int(bool(use_graph))
+    o.key0, o.key1, o.stream, o.step0 = int(key[0]), int(key[1]), int(stream), int(step0)
+    o.scale = _ptr(scale)
+    if lo is not None:
+        o.lo = _ptr(_need(lo, torch.float64, n_par, "lo"))
+    if hi is not None:
+        o.hi = _ptr(_need(hi, torch.float64, n_par, "hi"))
+    theta = theta0.clone()
+    chi2v = torch.empty(batch.n, dtype=torch.float64, device=ctx.device)
+    nk = int(n_steps) // int(thin)
+    samples = torch.empty((max(nk, 1), n_par), dtype=torch.float32, device=ctx.device) if keep_samples else None
+    acc = torch.zeros(batch.n, dtype=torch.int32, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_mcmc_run(ctx.ptr, batch.ptr, psf.ptr, _ptr(data), _ptr(weight), _ptr(theta), _ptr(chi2v), o,
+                  _ptr(samples), _ptr(acc))
+    return theta, chi2v, (samples[:nk] if samples is not None else None), acc
