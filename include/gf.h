@@ -106,6 +106,21 @@ gf_status gf_batch_create(gf_ctx *ctx, int n_stamps, const int32_t *H, const int
                           const int32_t *n_comp, int shared_image, gf_batch **out);
 void gf_batch_destroy(gf_batch *batch);
 
+/* A batch whose stamps come in observation groups (several fits of one
+ * galaxy, e.g. from different starting points or with different numbers of
+ * components): group[s] in 0 .. G-1, every id used.  All stamps of a group
+ * share one observation (data and weight) and one PSF, so they need the
+ * same H, W and K; n_comp may differ.  Group g's image sits at offset
+ * sum_{g' < g} H_g' W_g' of the data and weight arrays and its PSF at
+ * sum_{g' < g} K_g'^2 of the taps (gf_batch_offsets reports these per
+ * stamp); per-stamp arrays (models, parameters) are laid out as usual.
+ * gf_psf_prepare computes one OTF per group. */
+gf_status gf_batch_create_grouped(gf_ctx *ctx, int n_stamps, const int32_t *H, const int32_t *W, const int32_t *K,
+                                  const int32_t *n_comp, const int32_t *group, gf_batch **out);
+/* Number of observation groups (G for grouped batches, 1 for shared-image
+ * batches, n_stamps otherwise). */
+int gf_batch_groups(const gf_batch *batch);
+
 /* Flat array sizes (elements) for a batch; any output may be NULL.
  *   n_pix: sum H*W        (model, residual images)
  *   n_pad: sum Mh*Mw      (padded model grids, per channel)
@@ -236,6 +251,24 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  * Returns GF_OK when the call ran (per-stamp outcomes are in res). */
 gf_status gf_fit_lm(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
                     double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
+
+/* Best fit per observation group after gf_fit_lm: the member with the
+ * lowest chi^2 among those with status GF_OK (among all members if none
+ * converged); ties go to the lowest stamp index and NaN never wins.
+ * res: device [n_stamps] from gf_fit_lm; theta: device [n_par] FP64 (the
+ * fitted parameters); best: device FP64 [n_groups][29] (the winner's P
+ * parameters, then zeros); best_stamp: device int32 [n_groups] or null. */
+gf_status gf_group_best(gf_ctx *ctx, const gf_batch *batch, const gf_lm_result *res, const double *theta,
+                        double *best, int32_t *best_stamp);
+
+/* Multi-start set for single-Sersic stamps (P = 8): out[g * n_starts + k] =
+ * theta0[g] changed by rule k: 0 none; 1 n = 1 (exponential), Re x 1.5;
+ * 2 n = 4 (de Vaucouleurs), Re x 0.7; 3 phi + pi/2 (the other axis), mod pi.
+ * theta0: device [n_groups][8] FP64; out: device [n_groups * n_starts][8];
+ * 1 <= n_starts <= 4.  With gf_batch_create_grouped (group = g for the
+ * stamps g * n_starts .. + n_starts - 1), gf_fit_lm and gf_group_best this
+ * is the multi-start fit. */
+gf_status gf_expand_starts(gf_ctx *ctx, int n_groups, int n_starts, const double *theta0, double *out);
 
 /* ------------------------------------------------------------ MCMC
  *

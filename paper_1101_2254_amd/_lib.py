@@ -23,7 +23,7 @@ GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
 
 # Every symbol that include/gf.h declares.
 EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_synchronize", "gf_batch_create",
-           "gf_batch_destroy", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
+           "gf_batch_destroy", "gf_batch_create_grouped", "gf_batch_groups", "gf_group_best", "gf_expand_starts", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
            "gf_psf_destroy", "gf_psf_paths", "gf_eval_model", "gf_convolve_psf", "gf_model", "gf_chi2", "gf_likelihood",
            "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_mcmc_opts_default", "gf_mcmc_run",
            "gf_moments_guess",
@@ -84,6 +84,10 @@ def lib() -> ctypes.CDLL:
         "gf_synchronize": (i32, [vp]),
         "gf_batch_create": (i32, [vp, i32, vp, vp, vp, vp, i32, pvp]),
         "gf_batch_destroy": (None, [vp]),
+        "gf_batch_create_grouped": (i32, [vp, i32, vp, vp, vp, vp, vp, pvp]),
+        "gf_batch_groups": (i32, [vp]),
+        "gf_group_best": (i32, [vp, vp, vp, vp, vp, vp]),
+        "gf_expand_starts": (i32, [vp, i32, i32, vp, vp]),
         "gf_batch_sizes": (i32, [vp, pi64, pi64, pi64, pi64, pi64, pi64]),
         "gf_batch_offsets": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "gf_batch_count": (i32, [vp]),
@@ -164,6 +168,27 @@ def gf_batch_create(ctx: int, H, W, K, ncomp, shared: bool) -> int:
     p = ctypes.c_void_p()
     check(lib().gf_batch_create(ctx, n, h, w, k, c, int(shared), ctypes.byref(p)), ctx)
     return p.value
+
+
+def gf_batch_create_grouped(ctx: int, H, W, K, ncomp, group) -> int:
+    n = len(H)
+    arr = ctypes.c_int32 * n
+    h, w, k, c, g = arr(*H), arr(*W), arr(*K), arr(*ncomp), arr(*group)
+    p = ctypes.c_void_p()
+    check(lib().gf_batch_create_grouped(ctx, n, h, w, k, c, g, ctypes.byref(p)), ctx)
+    return p.value
+
+
+def gf_batch_groups(b: int) -> int:
+    return int(lib().gf_batch_groups(b))
+
+
+def gf_group_best(ctx, b, res_ptr, theta_ptr, best_ptr, stamp_ptr):
+    check(lib().gf_group_best(ctx, b, res_ptr, theta_ptr, best_ptr, stamp_ptr), ctx)
+
+
+def gf_expand_starts(ctx, n_groups, n_starts, theta0_ptr, out_ptr):
+    check(lib().gf_expand_starts(ctx, int(n_groups), int(n_starts), theta0_ptr, out_ptr), ctx)
 
 
 def gf_batch_destroy(b: int) -> None:

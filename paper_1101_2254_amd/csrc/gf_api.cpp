@@ -2,6 +2,7 @@
 // (FFT plans, OTFs, work lists), the step 1-3 entry points, derivatives and
 // the device-resident Levenberg-Marquardt driver.
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -44,6 +45,8 @@ hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const 
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
                             const double *, int *, int *, int *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
+hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
+hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
 hipError_t launch_mcmc_propose(hipStream_t, const gf_batch *, const double *, const double *, const double *,
                                const double *, uint64_t, uint64_t, uint64_t, int64_t, const int64_t *, double *, int *);
 hipError_t launch_mcmc_init(hipStream_t, int, const float2 *, double *, int64_t *);
@@ -260,10 +263,30 @@ gf_status gf_synchronize(gf_ctx *c) {
 }
 
 // ------------------------------------------------------------------ batches
-gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, const int32_t *K,
-                          const int32_t *nc, int shared, gf_batch **out) {
+static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t *W, const int32_t *K,
+                              const int32_t *nc, int shared, const int32_t *group, gf_batch **out) {
   if (!c || !out || !H || !W || !K || !nc || n <= 0) return fail(c, GF_EINVAL, "gf_batch_create: bad argument");
   *out = nullptr;
+  // groups: every stamp's observation and PSF, or one per group
+  int G = 0;
+  std::vector<int> gfirst_stamp;
+  if (group) {
+    for (int s = 0; s < n; ++s) {
+      if (group[s] < 0 || group[s] >= n) return fail(c, GF_EINVAL, "gf_batch_create_grouped: group id out of range");
+      G = std::max(G, group[s] + 1);
+    }
+    gfirst_stamp.assign(G, -1);
+    for (int s = 0; s < n; ++s) {
+      int &f = gfirst_stamp[group[s]];
+      if (f < 0) {
+        f = s;
+      } else if (H[s] != H[f] || W[s] != W[f] || K[s] != K[f]) {
+        return fail(c, GF_ESHAPE, "gf_batch_create_grouped: stamps of a group need the same H, W and K");
+      }
+    }
+    for (int g = 0; g < G; ++g)
+      if (gfirst_stamp[g] < 0) return fail(c, GF_EINVAL, "gf_batch_create_grouped: group ids must be 0 .. G-1, all used");
+  }
   gf_batch *b = new (std::nothrow) gf_batch();
   if (!b) return fail(c, GF_ENOMEM, "gf_batch_create: host allocation");
   b->ctx = c;
@@ -271,6 +294,15 @@ gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, 
   b->shared = shared != 0;
   b->h_desc.resize(n);
   int64_t pix = 0, pad = 0, psf = 0, par = 0, jac = 0;
+  std::vector<int64_t> gimg(G, 0), gpsf(G, 0);
+  int64_t gi = 0, gp = 0;
+  for (int g = 0; g < G; ++g) {
+    const int f = gfirst_stamp[g];
+    gimg[g] = gi;
+    gpsf[g] = gp;
+    gi += (int64_t)H[f] * W[f];
+    gp += (int64_t)K[f] * K[f];
+  }
   for (int s = 0; s < n; ++s) {
     if (H[s] <= 0 || W[s] <= 0 || K[s] <= 0 || (K[s] % 2) == 0 || K[s] > GF_MAX_K || nc[s] < 1 ||
         nc[s] > GF_MAX_COMP || H[s] + K[s] - 1 > GF_MAX_FFT || W[s] + K[s] - 1 > GF_MAX_FFT) {
@@ -294,8 +326,8 @@ gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, 
     d.pad = pad;
     d.par = par;
     d.jac = jac;
-    d.img = b->shared ? 0 : pix;
-    d.psf = b->shared ? 0 : psf;
+    d.img = b->shared ? 0 : group ? gimg[group[s]] : pix;
+    d.psf = b->shared ? 0 : group ? gpsf[group[s]] : psf;
     pix += (int64_t)d.H * d.W;
     pad += (int64_t)d.Mh * d.Mw;
     psf += (int64_t)d.K * d.K;
@@ -307,9 +339,20 @@ gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, 
   }
   b->n_pix = pix;
   b->n_pad = pad;
-  b->n_psf = b->shared ? (int64_t)K[0] * K[0] : psf;
+  b->n_psf = b->shared ? (int64_t)K[0] * K[0] : group ? gp : psf;
   b->n_par = par;
-  b->n_img = b->shared ? (int64_t)H[0] * W[0] : pix;
+  b->n_img = b->shared ? (int64_t)H[0] * W[0] : group ? gi : pix;
+  // group membership lists (stamps in increasing order within a group)
+  b->n_groups = group ? G : (b->shared ? 1 : n);
+  {
+    std::vector<int32_t> cnt(b->n_groups + 1, 0);
+    for (int s = 0; s < n; ++s) cnt[(group ? group[s] : b->shared ? 0 : s) + 1] += 1;
+    for (int g = 0; g < b->n_groups; ++g) cnt[g + 1] += cnt[g];
+    b->h_gfirst = cnt;
+    b->h_gmembers.assign(n, 0);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int s = 0; s < n; ++s) b->h_gmembers[fill[group ? group[s] : b->shared ? 0 : s]++] = s;
+  }
   b->n_jac = jac;
   for (int s = 0; s < n; ++s) {
     const StampDesc &d = b->h_desc[s];
@@ -338,12 +381,25 @@ gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, 
   if (e == hipSuccess) e = upload(&b->d_pix_first, b->h_pix_first);
   if (e == hipSuccess) e = upload(&b->d_neq_first, b->h_neq_first);
   if (e == hipSuccess) e = upload(&b->d_eval_first, b->h_eval_first);
+  if (e == hipSuccess) e = upload(&b->d_gfirst, b->h_gfirst);
+  if (e == hipSuccess) e = upload(&b->d_gmembers, b->h_gmembers);
   if (e != hipSuccess) {
     gf_batch_destroy(b);
     return fail(c, GF_EDEVICE, std::string("gf_batch_create: ") + hipGetErrorString(e));
   }
   *out = b;
   return GF_OK;
+}
+
+gf_status gf_batch_create(gf_ctx *c, int n, const int32_t *H, const int32_t *W, const int32_t *K,
+                          const int32_t *nc, int shared, gf_batch **out) {
+  return create_batch(c, n, H, W, K, nc, shared, nullptr, out);
+}
+
+gf_status gf_batch_create_grouped(gf_ctx *c, int n, const int32_t *H, const int32_t *W, const int32_t *K,
+                                  const int32_t *nc, const int32_t *group, gf_batch **out) {
+  if (!group) return fail(c, GF_EINVAL, "gf_batch_create_grouped: null group array");
+  return create_batch(c, n, H, W, K, nc, 0, group, out);
 }
 
 void gf_batch_destroy(gf_batch *b) {
@@ -355,6 +411,8 @@ void gf_batch_destroy(gf_batch *b) {
   dfree(b->d_pix_first);
   dfree(b->d_neq_first);
   dfree(b->d_eval_first);
+  dfree(b->d_gfirst);
+  dfree(b->d_gmembers);
   delete b;
 }
 
@@ -406,6 +464,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   std::vector<int> plan_of_L(GF_MAX_FFT + 1, -1);
   std::vector<float2> tw;
   std::vector<int64_t> otf_tmp(n, 0), otf_off(n, 0);
+  std::map<int64_t, int64_t> otf_of_psf;   // PSF offset -> OTF offset
   std::vector<Work> otf_rows, otf_cols;
   int64_t otf_tmp_n = 0;
   for (int s = 0; s < n; ++s) {
@@ -470,7 +529,9 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     p->n_s1a += (int64_t)d.H * Lh;
     p->h_s2a[s] = p->n_s2a;
     p->n_s2a += (int64_t)d.Mh * Lh;
-    if (!b->shared || s == 0) {
+    auto hit = otf_of_psf.find(d.psf);
+    if (hit == otf_of_psf.end()) {
+      otf_of_psf[d.psf] = p->n_otf;
       otf_off[s] = p->n_otf;
       pd.otf = p->n_otf;
       p->n_otf += (int64_t)L * Lh;
@@ -479,7 +540,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
       for (int u = 0; u < (d.K + 2 * T - 1) / (2 * T); ++u) otf_rows.push_back({s, u});
       for (int u = 0; u < cols; ++u) otf_cols.push_back({s, u});
     } else {
-      pd.otf = 0;
+      pd.otf = hit->second;   // stamps sharing a PSF (same group) share its OTF
     }
   }
   hipError_t e = hipSuccess;
@@ -880,6 +941,23 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   st = run();
   cleanup();
   return st;
+}
+
+gf_status gf_group_best(gf_ctx *c, const gf_batch *b, const gf_lm_result *res, const double *theta, double *best,
+                        int32_t *best_stamp) {
+  if (!c || !b || !res || !theta || !best) return fail(c, GF_EINVAL, "gf_group_best: null argument");
+  ProfBind pb_(c);
+  GF_TRY(c, launch_group_best(c->stream, b, res, theta, best, best_stamp));
+  return GF_OK;
+}
+
+int gf_batch_groups(const gf_batch *b) { return b ? b->n_groups : 0; }
+
+gf_status gf_expand_starts(gf_ctx *c, int n_groups, int n_starts, const double *theta0, double *out) {
+  if (!c || n_groups < 0 || n_starts < 1 || n_starts > 4 || (n_groups > 0 && (!theta0 || !out)))
+    return fail(c, GF_EINVAL, "gf_expand_starts: bad argument (1 <= n_starts <= 4)");
+  GF_TRY(c, launch_expand_starts(c->stream, n_groups, n_starts, theta0, out));
+  return GF_OK;
 }
 
 // ---------------------------------------------------------------- MCMC

@@ -198,6 +198,11 @@ struct gf_batch {
   std::vector<int32_t> h_pix_first, h_neq_first, h_eval_first;   // first unit index per stamp (+ total)
   int32_t *d_pix_first = nullptr, *d_neq_first = nullptr, *d_eval_first = nullptr;
   bool uniform = true;
+  // observation groups (gf_batch_create_grouped): members of group g are
+  // d_gmembers[d_gfirst[g] .. d_gfirst[g+1]); one group per stamp otherwise
+  int n_groups = 0;
+  std::vector<int32_t> h_gfirst, h_gmembers;
+  int32_t *d_gfirst = nullptr, *d_gmembers = nullptr;
 };
 
 struct gf_psf {

@@ -715,6 +715,69 @@ __global__ void k_lm_result(int n, const LMState *__restrict__ st, gf_lm_result 
   res[s] = r;
 }
 
+// Per observation group: the member with the lowest chi^2 among converged
+// members (among all members if none converged); ties go to the lower stamp
+// index, NaN never wins.  One thread per group.
+__global__ void k_group_best(const StampDesc *__restrict__ desc, int G, const int32_t *__restrict__ gfirst,
+                             const int32_t *__restrict__ gmembers, const gf_lm_result *__restrict__ res,
+                             const double *__restrict__ theta, double *__restrict__ best, int32_t *__restrict__ best_stamp) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int pick = -1;
+  for (int pass = 0; pass < 2 && pick < 0; ++pass) {
+    double bc = INFINITY;
+    for (int i = gfirst[g]; i < gfirst[g + 1]; ++i) {
+      const int s = gmembers[i];
+      if (pass == 0 && res[s].status != GF_OK) continue;
+      const double c = res[s].chi2;
+      if (!(c < bc)) continue;   // NaN and ties lose: the lowest index wins
+      bc = c;
+      pick = s;
+    }
+  }
+  if (pick < 0) pick = gmembers[gfirst[g]];   // every chi^2 infinite or NaN
+  if (best_stamp) best_stamp[g] = pick;
+  double *o = best + (int64_t)g * kMaxP;
+  const int P = kNPC * desc[pick].ncomp + 1;
+  for (int q = 0; q < kMaxP; ++q) o[q] = q < P ? theta[desc[pick].par + q] : 0.0;
+}
+
+hipError_t launch_group_best(hipStream_t st, const gf_batch *b, const gf_lm_result *res, const double *theta,
+                             double *best, int32_t *best_stamp) {
+  ProfScope ps(st, "k_group_best");
+  hipLaunchKernelGGL(k_group_best, dim3((b->n_groups + 255) / 256), dim3(256), 0, st, b->d_desc, b->n_groups,
+                     b->d_gfirst, b->d_gmembers, res, theta, best, best_stamp);
+  return hipGetLastError();
+}
+
+// Starting points of a multi-start fit of single-Sersic stamps: start k of
+// group g is theta0[g] with rule k applied: 0 unchanged, 1 n = 1 and Re x 1.5,
+// 2 n = 4 and Re x 0.7, 3 phi + pi/2 (mod pi).
+__global__ void k_expand_starts(int G, int S, const double *__restrict__ theta0, double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G * S) return;
+  const int g = i / S, k = i - g * S;
+  double t[8];
+  for (int q = 0; q < 8; ++q) t[q] = theta0[8 * (int64_t)g + q];
+  if (k == 1) {
+    t[4] = 1.0;
+    t[3] *= 1.5;
+  } else if (k == 2) {
+    t[4] = 4.0;
+    t[3] *= 0.7;
+  } else if (k == 3) {
+    t[6] = fmod(t[6] + 1.5707963267948966, 3.141592653589793);
+    if (t[6] < 0.0) t[6] += 3.141592653589793;
+  }
+  for (int q = 0; q < 8; ++q) out[8 * (int64_t)i + q] = t[q];
+}
+
+hipError_t launch_expand_starts(hipStream_t st, int G, int S, const double *theta0, double *out) {
+  if (G * S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_starts, dim3((G * S + 255) / 256), dim3(256), 0, st, G, S, theta0, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, const float2 *chi2t, LMState *S,
                           int *mjac, int *mtrial, int *cnt) {
   hipLaunchKernelGGL(k_lm_init, dim3((b->n + 255) / 256), dim3(256), 0, st, b->d_desc, b->n, lambda0, chi2t, S,

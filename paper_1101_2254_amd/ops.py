@@ -68,13 +68,18 @@ class Context:
 class Batch:
     """Stamp geometry of a batch (``gf_batch``)."""
 
-    def __init__(self, ctx: Context, H, W, K, ncomp, shared: bool = False):
+    def __init__(self, ctx: Context, H, W, K, ncomp, shared: bool = False, group=None):
         self.ctx = ctx
         self.H, self.W, self.K, self.ncomp = list(map(int, H)), list(map(int, W)), list(map(int, K)), list(
             map(int, ncomp))
         self.n = len(self.H)
         self.shared = bool(shared)
-        self.ptr = L.gf_batch_create(ctx.ptr, self.H, self.W, self.K, self.ncomp, self.shared)
+        self.group = None if group is None else list(map(int, group))
+        if self.group is not None:
+            self.ptr = L.gf_batch_create_grouped(ctx.ptr, self.H, self.W, self.K, self.ncomp, self.group)
+        else:
+            self.ptr = L.gf_batch_create(ctx.ptr, self.H, self.W, self.K, self.ncomp, self.shared)
+        self.n_groups = L.gf_batch_groups(self.ptr)
         self.sizes = L.gf_batch_sizes(self.ptr)
         self.offsets = L.gf_batch_offsets(self.ptr, self.n)
         self.P = [7 * c + 1 for c in self.ncomp]
@@ -217,7 +222,7 @@ def lm_options(**kw) -> L.GfLmOpts:
 
 
 def fit_lm(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: torch.Tensor, theta0: torch.Tensor,
-           lo=None, hi=None, free=None, **opts):
+           lo=None, hi=None, free=None, return_device=False, **opts):
     """Levenberg-Marquardt over the whole batch on the device (gf_fit_lm).
 
     theta0: float64 device tensor [n_par] (not modified).  Returns
@@ -237,8 +242,36 @@ def fit_lm(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: tor
     res = torch.empty(batch.n * LM_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
     ctx.bind_stream()
     L.gf_fit_lm(ctx.ptr, batch.ptr, psf.ptr, _ptr(data), _ptr(weight), _ptr(theta), o, _ptr(res))
+    if return_device:
+        return theta, res
     info = np.frombuffer(res.cpu().numpy().tobytes(), dtype=LM_RESULT_DTYPE)
     return theta, info
+
+
+def lm_info(res: torch.Tensor):
+    """Per-stamp results (numpy structured array) from the device records."""
+    return np.frombuffer(res.cpu().numpy().tobytes(), dtype=LM_RESULT_DTYPE)
+
+
+def group_best(ctx: Context, batch: Batch, res: torch.Tensor, theta: torch.Tensor):
+    """Lowest-chi^2 member per observation group (gf_group_best): (best
+    parameters float64 [n_groups, 29], winning stamp int32 [n_groups])."""
+    _need(theta, torch.float64, batch.sizes["n_par"], "theta")
+    best = torch.empty((batch.n_groups, 29), dtype=torch.float64, device=ctx.device)
+    idx = torch.empty(batch.n_groups, dtype=torch.int32, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_group_best(ctx.ptr, batch.ptr, _ptr(res), _ptr(theta), _ptr(best), _ptr(idx))
+    return best, idx
+
+
+def expand_starts(ctx: Context, theta0: torch.Tensor, n_starts: int) -> torch.Tensor:
+    """Multi-start set [n_groups * n_starts, 8] (gf_expand_starts)."""
+    G = theta0.numel() // 8
+    _need(theta0, torch.float64, G * 8, "theta0")
+    out = torch.empty((max(G * n_starts, 1), 8), dtype=torch.float64, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_expand_starts(ctx.ptr, G, int(n_starts), _ptr(theta0), _ptr(out))
+    return out[:G * n_starts]
 
 
 # ------------------------------------------------------------------ autograd

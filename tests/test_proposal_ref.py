@@ -143,3 +143,17 @@ def test_flux_normalisation_matches_the_sersic_closed_form():
     b = gfo.bn(2.0)
     num = quad(lambda r: 2 * math.pi * r * 0.6 * math.exp(-b * ((r / 3.0) ** 0.5 - 1)), 0, np.inf, limit=400)[0]
     assert MR.sersic_total_flux(1.0, 3.0, 2.0, 0.6) == pytest.approx(num, rel=1e-8)
+
+
+# ---------------------------------------------------------------- multi-start
+def test_multistart_reference_rules():
+    from oracle import multistart_ref as MS
+    th = np.array([[10.0, 11.0, 2.0, 5.0, 2.5, 0.6, 2.0, 0.01]])
+    st = MS.expand_starts(th, 4)
+    np.testing.assert_array_equal(st[0], th[0])
+    assert st[1][4] == 1.0 and st[1][3] == 7.5 and st[2][4] == 4.0 and st[2][3] == pytest.approx(3.5)
+    assert st[3][6] == pytest.approx(2.0 + math.pi / 2 - math.pi)
+    np.testing.assert_array_equal(np.delete(st[3], 6), np.delete(th[0], 6))
+    chi2 = np.array([5.0, 3.0, 3.0, np.nan, 1.0, 2.0])
+    status = np.array([0, 0, 0, 0, 6, 6])
+    assert list(MS.group_best([[0, 1, 2, 3], [4, 5]], chi2, status)) == [1, 4]
