@@ -270,6 +270,38 @@ gf_status gf_group_best(gf_ctx *ctx, const gf_batch *batch, const gf_lm_result *
  * is the multi-start fit. */
 gf_status gf_expand_starts(gf_ctx *ctx, int n_groups, int n_starts, const double *theta0, double *out);
 
+/* ------------------------------------------------------------ downhill simplex
+ *
+ * Nelder & Mead (1965) over every stamp of the batch at once: the paper's
+ * other step-4 route (Sec. 2), on the same steps 1-3.  Per stamp a simplex
+ * of P + 1 vertices (x0 and x0 + step_j e_j) moves by reflection (1),
+ * expansion (2), contraction (1/2) and shrink (1/2) steps; points are
+ * clipped into [lo, hi]; ties in the ordering go to the lower index for the
+ * best vertex and to the higher for the worst.  A stamp stops when
+ * 2 (f_w - f_b) <= ftol (|f_w| + |f_b|) + 1e-300, or after max_iter
+ * iterations.  Each device iteration evaluates one candidate per active
+ * stamp; the host reads the active count every poll_every iterations.
+ * theta_io: device [n_par] start in, best vertex out.  res: device
+ * [n_stamps] (chi2 of the best vertex, iterations, evaluations, status;
+ * lambda and njev are 0).  trace: device FP64 [n_stamps][trace_cap] or null:
+ * chi^2 of every evaluated point of each stamp, in evaluation order (the
+ * first trace_cap of them). */
+typedef struct {
+  int32_t max_iter;     /* default 2000 */
+  int32_t oversample;   /* default 5 */
+  double ftol;          /* default 1e-8 */
+  const double *step;   /* device [n_par]: initial simplex offsets (required) */
+  const double *lo;     /* device [n_par] or null */
+  const double *hi;     /* device [n_par] or null */
+  int32_t poll_every;   /* default 16 */
+  int32_t use_graph;    /* default 1 */
+} gf_simplex_opts;
+
+void gf_simplex_opts_default(gf_simplex_opts *opts);
+gf_status gf_fit_simplex(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data,
+                         const float *weight, double *theta_io, const gf_simplex_opts *opts, gf_lm_result *res,
+                         double *trace, int trace_cap);
+
 /* ------------------------------------------------------------ MCMC
  *
  * The paper names Bayesian sampling (galphat) as the third routine family

@@ -26,6 +26,7 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_batch_destroy", "gf_batch_create_grouped", "gf_batch_groups", "gf_group_best", "gf_expand_starts", "gf_batch_sizes", "gf_batch_offsets", "gf_batch_count", "gf_psf_prepare",
            "gf_psf_destroy", "gf_psf_paths", "gf_eval_model", "gf_convolve_psf", "gf_model", "gf_chi2", "gf_likelihood",
            "gf_likelihood_workspace", "gf_jacobian", "gf_lm_opts_default", "gf_fit_lm", "gf_mcmc_opts_default", "gf_mcmc_run",
+           "gf_simplex_opts_default", "gf_fit_simplex",
            "gf_moments_guess",
            "gf_cnn_create", "gf_cnn_destroy", "gf_cnn_param_count", "gf_cnn_init", "gf_cnn_set_params",
            "gf_cnn_get_params", "gf_cnn_forward", "gf_cnn_gradients", "gf_cnn_train_step", "gf_cnn_steps",
@@ -46,6 +47,12 @@ class GfMcmcOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("key0", ctypes.c_uint64), ("key1", ctypes.c_uint64),
                 ("stream", ctypes.c_uint64), ("step0", ctypes.c_int64), ("scale", ctypes.c_void_p),
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p)]
+
+
+class GfSimplexOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("oversample", ctypes.c_int32), ("ftol", ctypes.c_double),
+                ("step", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
+                ("poll_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class GfLmResult(ctypes.Structure):
@@ -105,6 +112,8 @@ def lib() -> ctypes.CDLL:
         "gf_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
         "gf_mcmc_opts_default": (None, [ctypes.POINTER(GfMcmcOpts)]),
         "gf_mcmc_run": (i32, [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfMcmcOpts), vp, vp]),
+        "gf_simplex_opts_default": (None, [ctypes.POINTER(GfSimplexOpts)]),
+        "gf_fit_simplex": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfSimplexOpts), vp, vp, i32]),
         "gf_moments_guess": (i32, [vp, vp, vp, vp]),
         "gf_cnn_create": (i32, [vp, i32, i32, pvp]),
         "gf_cnn_destroy": (None, [vp]),
@@ -378,3 +387,15 @@ def gf_mcmc_opts_default() -> GfMcmcOpts:
 def gf_mcmc_run(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, chi2_ptr, opts: GfMcmcOpts, samples_ptr, acc_ptr):
     check(lib().gf_mcmc_run(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, chi2_ptr, ctypes.byref(opts), samples_ptr,
                             acc_ptr), ctx)
+
+
+# ---------------------------------------------------------------- simplex
+def gf_simplex_opts_default() -> GfSimplexOpts:
+    o = GfSimplexOpts()
+    lib().gf_simplex_opts_default(ctypes.byref(o))
+    return o
+
+
+def gf_fit_simplex(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, opts: GfSimplexOpts, res_ptr, trace_ptr, trace_cap):
+    check(lib().gf_fit_simplex(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), res_ptr, trace_ptr,
+                               int(trace_cap)), ctx)

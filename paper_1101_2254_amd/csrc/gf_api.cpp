@@ -47,6 +47,14 @@ hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, c
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
 hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
+hipError_t launch_nm_init(hipStream_t, const gf_batch *, const double *, const double *, const gf_simplex_opts *,
+                          double *, double *, void *, int *, int *);
+hipError_t launch_nm_step(hipStream_t, const gf_batch *, const float2 *, const gf_simplex_opts *, void *, double *,
+                          double *, double *, double *, int *, double *, int, int *);
+hipError_t launch_nm_result(hipStream_t, const gf_batch *, const void *, const double *, const double *, double *,
+                            gf_lm_result *);
+hipError_t launch_nm_zero(hipStream_t, int *);
+size_t nm_state_bytes();
 hipError_t launch_mcmc_propose(hipStream_t, const gf_batch *, const double *, const double *, const double *,
                                const double *, uint64_t, uint64_t, uint64_t, int64_t, const int64_t *, double *, int *);
 hipError_t launch_mcmc_init(hipStream_t, int, const float2 *, double *, int64_t *);
@@ -958,6 +966,115 @@ gf_status gf_expand_starts(gf_ctx *c, int n_groups, int n_starts, const double *
     return fail(c, GF_EINVAL, "gf_expand_starts: bad argument (1 <= n_starts <= 4)");
   GF_TRY(c, launch_expand_starts(c->stream, n_groups, n_starts, theta0, out));
   return GF_OK;
+}
+
+// ---------------------------------------------------------------- simplex
+void gf_simplex_opts_default(gf_simplex_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_iter = 2000;
+  o->oversample = 5;
+  o->ftol = 1e-8;
+  o->poll_every = 16;
+  o->use_graph = 1;
+}
+
+gf_status gf_fit_simplex(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *data, const float *weight,
+                         double *theta, const gf_simplex_opts *opts, gf_lm_result *res, double *trace, int trace_cap) {
+  ProfBind pb_(c);
+  if (!c || !b || !p || !data || !weight || !theta || !opts || !res || !opts->step)
+    return fail(c, GF_EINVAL, "gf_fit_simplex: null argument (step is required)");
+  if (p->batch != b) return fail(c, GF_EINVAL, "gf_fit_simplex: PSF prepared for another batch");
+  gf_simplex_opts o = *opts;
+  if (o.max_iter < 0 || o.oversample < 1 || o.oversample > GF_MAX_OVERSAMPLE || !(o.ftol >= 0.0) ||
+      (trace && trace_cap < 1))
+    return fail(c, GF_EINVAL, "gf_fit_simplex: invalid options");
+  if (o.poll_every < 1) o.poll_every = 1;
+  const int S = o.oversample;
+  constexpr int kV = kMaxP + 1;
+  double *X = nullptr, *F = nullptr, *XR = nullptr, *theta_t = nullptr;
+  float *mpad = nullptr, *mconv = nullptr;
+  float2 *S1 = nullptr, *S2 = nullptr, *cpart = nullptr;
+  int *mask = nullptr, *cnt = nullptr;
+  void *state = nullptr;
+  auto layout = [&](Arena &ar) {
+    X = ar.take<double>((int64_t)b->n * kV * kMaxP);
+    F = ar.take<double>((int64_t)b->n * kV);
+    XR = ar.take<double>((int64_t)b->n * kMaxP);
+    theta_t = ar.take<double>(b->n_par);
+    mpad = ar.take<float>(b->n_pad);
+    mconv = ar.take<float>(b->n_pix);
+    S1 = ar.take<float2>(p->n_s1);
+    S2 = ar.take<float2>(p->n_s2);
+    cpart = ar.take<float2>((int64_t)b->h_pix.size());
+    mask = ar.take<int>(b->n);
+    cnt = ar.take<int>(16);
+    state = ar.take<char>((int64_t)b->n * (int64_t)nm_state_bytes());
+  };
+  Arena a;
+  layout(a);
+  gf_status st = ensure_ws(c, a.off);
+  if (st != GF_OK) return st;
+  a = Arena{(char *)c->ws, 0};
+  layout(a);
+  hipStream_t cs = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  GF_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  GF_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+    (void)hipEventDestroy(ev);
+  };
+  auto run = [&]() -> gf_status {
+    GF_TRY(c, hipEventRecord(ev, c->stream));
+    GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
+    GF_TRY(c, launch_nm_init(cs, b, theta, o.step, &o, X, theta_t, state, mask, cnt));
+    auto iteration = [&]() -> gf_status {
+      GF_TRY(c, launch_nm_zero(cs, cnt));
+      GF_TRY(c, launch_eval_d(cs, b, theta_t, S, c->d_bn, mpad, mask));
+      GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, mask));
+      GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, mask));
+      GF_TRY(c, launch_chi2_part(cs, b, mconv, theta_t, data, weight, cpart, mask));
+      GF_TRY(c, launch_nm_step(cs, b, cpart, &o, state, X, F, XR, theta_t, mask, trace, trace_cap, cnt));
+      return GF_OK;
+    };
+    if (o.use_graph) {
+      GF_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      gf_status s2 = iteration();
+      hipError_t ce = hipStreamEndCapture(cs, &graph);
+      if (s2 != GF_OK) return s2;
+      GF_TRY(c, ce);
+      GF_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    // every iteration costs at most P + 2 evaluations (reflection, expansion
+    // or contraction, P shrink points), plus P + 1 for the initial simplex
+    const int64_t max_evals = ((int64_t)o.max_iter + 1) * (b->max_P + 2) + b->max_P + 1;
+    for (int64_t it = 0; it < max_evals; ++it) {
+      if (exec) {
+        GF_TRY(c, hipGraphLaunch(exec, cs));
+      } else {
+        gf_status s2 = iteration();
+        if (s2 != GF_OK) return s2;
+      }
+      if ((it + 1) % o.poll_every == 0 || it + 1 == max_evals) {
+        GF_TRY(c, hipMemcpyAsync(c->h_pinned, cnt, sizeof(int), hipMemcpyDeviceToHost, cs));
+        GF_TRY(c, hipStreamSynchronize(cs));
+        if (*(volatile int *)c->h_pinned == 0) break;
+      }
+    }
+    GF_TRY(c, launch_nm_result(cs, b, state, F, X, theta, res));
+    GF_TRY(c, hipEventRecord(ev, cs));
+    GF_TRY(c, hipStreamWaitEvent(c->stream, ev, 0));
+    return GF_OK;
+  };
+  st = run();
+  cleanup();
+  return st;
 }
 
 // ---------------------------------------------------------------- MCMC

@@ -345,3 +345,33 @@ def mcmc_run(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: t
     L.gf_mcmc_run(ctx.ptr, batch.ptr, psf.ptr, _ptr(data), _ptr(weight), _ptr(theta), _ptr(chi2v), o,
                   _ptr(samples), _ptr(acc))
     return theta, chi2v, (samples[:nk] if samples is not None else None), acc
+
+
+# ------------------------------------------------------------------ downhill simplex
+def fit_simplex(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: torch.Tensor,
+                theta0: torch.Tensor, step: torch.Tensor, lo=None, hi=None, max_iter: int = 2000, ftol: float = 1e-8,
+                oversample: int = 5, poll_every: int = 16, use_graph: bool = True, trace_cap: int = 0):
+    """Nelder-Mead over the whole batch on the device (gf_fit_simplex).
+
+    Returns (theta float64 [n_par], per-stamp results as for fit_lm, trace
+    float64 [n_stamps, trace_cap] of evaluated chi^2 values or None)."""
+    n_par = batch.sizes["n_par"]
+    _need(theta0, torch.float64, n_par, "theta0")
+    _need(step, torch.float64, n_par, "step")
+    _need(data, torch.float32, batch.sizes["n_img"], "data")
+    _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    o = L.gf_simplex_opts_default()
+    o.max_iter, o.oversample, o.ftol = int(max_iter), int(oversample), float(ftol)
+    o.poll_every, o.use_graph = int(poll_every), int(bool(use_graph))
+    o.step = _ptr(step)
+    if lo is not None:
+        o.lo = _ptr(_need(lo, torch.float64, n_par, "lo"))
+    if hi is not None:
+        o.hi = _ptr(_need(hi, torch.float64, n_par, "hi"))
+    theta = theta0.clone()
+    res = torch.empty(batch.n * LM_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    trace = torch.full((batch.n, trace_cap), float("nan"), dtype=torch.float64, device=ctx.device) if trace_cap else None
+    ctx.bind_stream()
+    L.gf_fit_simplex(ctx.ptr, batch.ptr, psf.ptr, _ptr(data), _ptr(weight), _ptr(theta), o, _ptr(res), _ptr(trace),
+                     int(trace_cap))
+    return theta, lm_info(res), trace
