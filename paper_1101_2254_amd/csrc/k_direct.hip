@@ -9,6 +9,7 @@
 //   MODE_CORR:  out[y][x] = sum_{a,b} P[a][b] in[y+a-(K-1)][x+b-(K-1)] (Mh x Mw from H x W, zero outside)
 // The second is the transpose of the first (the adjoint of the PSF blur).
 #include "gf_internal.h"
+#include "bufload.h"
 
 namespace gf {
 
@@ -32,16 +33,41 @@ __global__ __launch_bounds__(kThreads) void k_direct(const StampDesc *__restrict
   const int TWp = kDirectTW + K - 1, THp = kDirectTH + K - 1;
   float *F = smem;               // K*K taps, flipped for MODE_CONV
   float *tile = smem + K * K;    // THp x TWp
-  const float *P = taps + d.psf;
-  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
-    const int a = i / K, b = i - a * K;
-    F[i] = MODE == 0 ? P[(K - 1 - a) * K + (K - 1 - b)] : P[i];
+  // Staging: batches of 8 range-checked loads per thread, all in flight
+  // before the LDS stores (out-of-image halo pixels read zero).
+  const __amdgpu_buffer_rsrc_t prs = make_rsrc(taps + d.psf, (uint32_t)(K * K) * 4u);
+  for (int i0 = 0; i0 < K * K; i0 += 8 * kThreads) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * kThreads + (int)threadIdx.x;
+      const int a = i / K, b = i - a * K;
+      const int src = MODE == 0 ? (K - 1 - a) * K + (K - 1 - b) : i;
+      v[q] = bload_f32(prs, i < K * K ? (uint32_t)src * 4u : kOutOfRange);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * kThreads + (int)threadIdx.x;
+      if (i < K * K) F[i] = v[q];
+    }
   }
   const int64_t ibase = (MODE == 0 ? d.pad : d.pix) * (int64_t)n_ch + (int64_t)ch * Hin * Win;
-  for (int i = threadIdx.x; i < THp * TWp; i += blockDim.x) {
-    const int r = i / TWp, c = i - r * TWp;
-    const int yy = y0 + r + off, xx = x0 + c + off;
-    tile[i] = (yy >= 0 && yy < Hin && xx >= 0 && xx < Win) ? in[ibase + (int64_t)yy * Win + xx] : 0.0f;
+  const __amdgpu_buffer_rsrc_t irs = make_rsrc(in + ibase, (uint32_t)(Hin * Win) * 4u);
+  for (int i0 = 0; i0 < THp * TWp; i0 += 8 * kThreads) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * kThreads + (int)threadIdx.x;
+      const int r = i / TWp, c = i - r * TWp;
+      const int yy = y0 + r + off, xx = x0 + c + off;
+      const bool ok = i < THp * TWp && yy >= 0 && yy < Hin && xx >= 0 && xx < Win;
+      v[q] = bload_f32(irs, ok ? (uint32_t)(yy * Win + xx) * 4u : kOutOfRange);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * kThreads + (int)threadIdx.x;
+      if (i < THp * TWp) tile[i] = v[q];
+    }
   }
   __syncthreads();
   const int x = threadIdx.x & (kDirectTW - 1);

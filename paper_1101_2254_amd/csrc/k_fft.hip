@@ -23,6 +23,7 @@
 #include <utility>
 
 #include "gf_internal.h"
+#include "bufload.h"
 
 namespace gf {
 
@@ -54,8 +55,29 @@ __device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
 constexpr int kFftLds = kFftCap + kFftCap / 32 + 1;
 // Loops that move up to kFftCap values between memory and LDS are unrolled
 // this many times so each thread issues all of its global loads before it
-// waits on any of them.
+// waits on any of them.  The loads go through range-checked buffer
+// resources: an element outside the valid region gets an out-of-range
+// offset and reads zero, so no load sits under a branch (a load under a
+// branch makes the compiler wait for it inside the branch, which turns the
+// batch into one round trip per load).
 constexpr int kFftIters = (kFftCap + kThreads - 1) / kThreads;
+constexpr int kTwIters = (GF_MAX_FFT + kThreads - 1) / kThreads;
+
+// Stage the L twiddles of a plan into LDS (loads first, then stores).
+__device__ __forceinline__ void stage_twiddles(float2 *tw, const float2 *__restrict__ src, int L) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, (uint32_t)L * 8u);
+  float2 t[kTwIters];
+#pragma unroll
+  for (int it = 0; it < kTwIters; ++it) {
+    const int i = (int)threadIdx.x + it * kThreads;
+    t[it] = bload_f32x2(rs, (uint32_t)i * 8u);
+  }
+#pragma unroll
+  for (int it = 0; it < kTwIters; ++it) {
+    const int i = (int)threadIdx.x + it * kThreads;
+    if (i < L) tw[i] = t[it];
+  }
+}
 
 // ------------------------------------------------------------ small DFTs
 // Forward: X_k = sum_n x_n exp(-2 pi i n k / R); inverse uses +i.
@@ -403,13 +425,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   const Geo g = geo_of(MODE, d, L);
   const int T = min(kFftCap / Ls, tmax);
   float2 *buf = lds, *tw = lds + kFftLds;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
   int64_t in_base, plane;
   if (MODE == MODE_CONV) { in_base = d.pad; plane = (int64_t)d.Mh * d.Mw; }
   else if (MODE == MODE_CORR) { in_base = d.pix; plane = (int64_t)d.H * d.W; }
   else { in_base = d.psf; plane = (int64_t)d.K * d.K; }
   const float *src = in + in_base * n_ch + ch * plane;
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, (uint32_t)plane * 4u);
   const int r0 = w.unit * 2 * T;
   const FDiv divL(L);
   {
@@ -421,9 +443,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
       const int ra = r0 + 2 * t, rb = ra + 1;
       const int c = n - g.in_col0;
       const bool cin = idx < T * L && c >= 0 && c < g.in_cols;
-      va[it] = (cin && ra < g.in_rows) ? src[(int64_t)ra * g.in_cols + c] : 0.0f;
-      vb[it] = (cin && rb < g.in_rows) ? src[(int64_t)rb * g.in_cols + c] : 0.0f;
+      const bool oka = cin && ra < g.in_rows, okb = cin && rb < g.in_rows;
+      va[it] = bload_f32(rsrc, oka ? (uint32_t)(ra * g.in_cols + c) * 4u : kOutOfRange);
+      vb[it] = bload_f32(rsrc, okb ? (uint32_t)(rb * g.in_cols + c) * 4u : kOutOfRange);
     }
+    stage_twiddles(tw, tw_all + pl.tw_off, L);
 #pragma unroll
     for (int it = 0; it < kFftIters; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
@@ -477,9 +501,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
   const int k0 = w.unit * C;
   const int nc = min(C, Lh - k0);
   float2 *buf = lds, *tw = lds + kFftLds;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
-  const float2 *src = S1 + s1_off[s] * n_ch + (int64_t)ch * Lh * g.in_rows + (int64_t)k0 * g.in_rows;
+  const float2 *spec = S1 + s1_off[s] * n_ch + (int64_t)ch * Lh * g.in_rows;
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(spec, (uint32_t)(Lh * g.in_rows) * 8u);
   const FDiv divL(L);
   {
     float2 v[kFftIters];
@@ -488,9 +512,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
       const int idx = (int)threadIdx.x + it * kThreads;
       const int c = divL(idx), y = idx - c * L;
       const int r = y - g.col_row0;
-      v[it] = (idx < C * L && c < nc && r >= 0 && r < g.in_rows) ? src[(int64_t)c * g.in_rows + r]
-                                                                  : make_float2(0.f, 0.f);
+      const bool ok = idx < C * L && c < nc && r >= 0 && r < g.in_rows;
+      v[it] = bload_f32x2(rsrc, ok ? (uint32_t)((k0 + c) * g.in_rows + r) * 8u : kOutOfRange);
     }
+    stage_twiddles(tw, tw_all + pl.tw_off, L);
 #pragma unroll
     for (int it = 0; it < kFftIters; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
@@ -505,13 +530,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
     for (int idx = threadIdx.x; idx < nc * L; idx += blockDim.x) dst[idx] = cscale(buf[lp(idx)], sc);
     return;
   }
-  const float2 *H = otf + pd.otf + (int64_t)k0 * L;
+  const __amdgpu_buffer_rsrc_t hrsrc = make_rsrc(otf + pd.otf, (uint32_t)(L * Lh) * 8u);
   {
     float2 hv[kFftIters];
 #pragma unroll
     for (int it = 0; it < kFftIters; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
-      hv[it] = idx < nc * L ? H[idx] : make_float2(0.f, 0.f);
+      hv[it] = bload_f32x2(hrsrc, idx < nc * L ? (uint32_t)(k0 * L + idx) * 8u : kOutOfRange);
     }
 #pragma unroll
     for (int it = 0; it < kFftIters; ++it) {
@@ -554,9 +579,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   const Geo g = geo_of(MODE, d, L);
   const int T = min(kFftCap / Ls, tmax);
   float2 *buf = lds, *tw = lds + kFftLds;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_all[pl.tw_off + i];
 
   const float2 *src = S2 + s2_off[s] * n_ch + (int64_t)ch * Lh * g.out_rows;
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, (uint32_t)(Lh * g.out_rows) * 8u);
   const int r0 = w.unit * 2 * T;
   const FDiv divT(T);
   {
@@ -568,10 +593,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
       const int ra = r0 + 2 * t, rb = ra + 1;
       const bool ok = idx < T * L;
       const int kk = k > L / 2 ? L - k : k;
-      const float2 *col = src + (int64_t)kk * g.out_rows;
-      va[it] = (ok && ra < g.out_rows) ? col[ra] : make_float2(0.f, 0.f);
-      vb[it] = (ok && rb < g.out_rows) ? col[rb] : make_float2(0.f, 0.f);
+      const bool oka = ok && ra < g.out_rows, okb = ok && rb < g.out_rows;
+      const uint32_t cb = (uint32_t)(kk * g.out_rows);
+      va[it] = bload_f32x2(rsrc, oka ? (cb + (uint32_t)ra) * 8u : kOutOfRange);
+      vb[it] = bload_f32x2(rsrc, okb ? (cb + (uint32_t)rb) * 8u : kOutOfRange);
     }
+    stage_twiddles(tw, tw_all + pl.tw_off, L);
 #pragma unroll
     for (int it = 0; it < kFftIters; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;

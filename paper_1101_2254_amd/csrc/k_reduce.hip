@@ -38,10 +38,10 @@ __device__ __forceinline__ float sky_of(const TT *theta, const StampDesc &d) {
 
 // ------------------------------------------------------------------ chi^2
 // r = sqrt(w) (d - m - sky); per workgroup a (hi, lo) partial of sum r^2.
-// Stamps whose image offsets are multiples of four floats (and pointers
-// 16-byte aligned: vec_ok) move four pixels per 16-byte load; every thread
-// issues all of its loads before the first use.  Pixels past the stamp end
-// enter with zero weight, so they add exact zeros.
+// A chunk that lies wholly inside a stamp whose image offsets are multiples
+// of four floats (pointers 16-byte aligned: vec_ok) moves four pixels per
+// 16-byte load, all issued before the first use; the last chunk of a stamp
+// takes the scalar path.
 constexpr int kChi2Vec = kPixChunk / (4 * kThreads);
 
 template <typename TT>
@@ -58,29 +58,17 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
   const int npix = d.H * d.W;
   const int p0 = w.unit * kPixChunk;
   F2 acc = {0.f, 0.f};
-  if (vec_ok && ((d.pix | d.img) & 3) == 0) {
+  if (vec_ok && ((d.pix | d.img) & 3) == 0 && p0 + kPixChunk <= npix) {
+    // whole chunk inside the stamp (uniform over the workgroup): every load
+    // is unconditional and all of them are in flight before the first use
     const float *mp = model + d.pix, *dp = data + d.img, *wp = weight + d.img;
     float4 mv[kChi2Vec], dv[kChi2Vec], wv[kChi2Vec];
 #pragma unroll
     for (int k = 0; k < kChi2Vec; ++k) {
       const int p = p0 + 4 * (k * kThreads + (int)threadIdx.x);
-      if (p + 4 <= npix) {
-        mv[k] = *reinterpret_cast<const float4 *>(mp + p);
-        dv[k] = *reinterpret_cast<const float4 *>(dp + p);
-        wv[k] = *reinterpret_cast<const float4 *>(wp + p);
-      } else {
-        float t[3][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool in = p + j < npix;
-          t[0][j] = in ? mp[p + j] : 0.f;
-          t[1][j] = in ? dp[p + j] : 0.f;
-          t[2][j] = in ? wp[p + j] : 0.f;
-        }
-        mv[k] = make_float4(t[0][0], t[0][1], t[0][2], t[0][3]);
-        dv[k] = make_float4(t[1][0], t[1][1], t[1][2], t[1][3]);
-        wv[k] = make_float4(t[2][0], t[2][1], t[2][2], t[2][3]);
-      }
+      mv[k] = *reinterpret_cast<const float4 *>(mp + p);
+      dv[k] = *reinterpret_cast<const float4 *>(dp + p);
+      wv[k] = *reinterpret_cast<const float4 *>(wp + p);
     }
 #pragma unroll
     for (int k = 0; k < kChi2Vec; ++k) {
@@ -89,14 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
                                    sqrtf(wv[k].y) * (dv[k].y - (mv[k].y + sky)),
                                    sqrtf(wv[k].z) * (dv[k].z - (mv[k].z + sky)),
                                    sqrtf(wv[k].w) * (dv[k].w - (mv[k].w + sky)));
-      if (resid) {
-        if (p + 4 <= npix) {
-          *reinterpret_cast<float4 *>(resid + d.pix + p) = r;
-        } else {
-          const float rr[4] = {r.x, r.y, r.z, r.w};
-          for (int j = 0; j < 4 && p + j < npix; ++j) resid[d.pix + p + j] = rr[j];
-        }
-      }
+      if (resid) *reinterpret_cast<float4 *>(resid + d.pix + p) = r;
       acc = f2_add1(acc, r.x * r.x);
       acc = f2_add1(acc, r.y * r.y);
       acc = f2_add1(acc, r.z * r.z);
