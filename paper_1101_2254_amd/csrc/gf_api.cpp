@@ -13,20 +13,21 @@
 namespace gf {
 std::vector<float4> build_bn_table();
 hipError_t launch_eval(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, const int *);
-hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, const int *);
+hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, const int *,
+                         const WorkView *);
 hipError_t launch_eval_jac(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, int,
                            const int *);
 hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, int,
-                             const int *);
+                             const int *, const WorkView *);
 hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float4 *, const float *,
                                    float *);
 hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
-                           float *, const int *);
+                           float *, const int *, const WorkView *);
 hipError_t launch_fft_corr(hipStream_t, const gf_batch *, const gf_psf *, const float *, float2 *, float2 *, float *);
 hipError_t launch_fft_otf(hipStream_t, const gf_batch *, const gf_psf *, const float *, const Work *, int,
                           const Work *, int, const int64_t *, float2 *, const int64_t *);
 hipError_t launch_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float *, bool,
-                         const int *);
+                         const int *, const WorkView *);
 hipError_t launch_chi2(hipStream_t, const gf_batch *, const float *, const void *, bool, const float *,
                        const float *, float *, float2 *, unsigned int *, float2 *, const int *);
 hipError_t launch_cot_prep(hipStream_t, const gf_batch *, const float *, const float *, float, float *, float2 *);
@@ -35,13 +36,13 @@ hipError_t launch_adjoint_final(hipStream_t, const gf_batch *, const int32_t *, 
 hipError_t launch_jac_assemble(hipStream_t, const gf_batch *, const float *, int, float *);
 hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *);
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float *, int, int, const int *);
+                            const float *, float *, int, int, const int *, const WorkView *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, double *, const gf_lm_opts *, LMState *,
                            double *, const double *, double *, int *, int *, int *);
 hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float2 *, const int *);
+                            const float *, float2 *, const int *, const WorkView *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
                             const double *, int *, int *, int *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
@@ -652,8 +653,8 @@ gf_status gf_eval_model(gf_ctx *c, const gf_batch *b, const float *theta, int S,
 
 static gf_status convolve(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *in, int n_ch, float *out,
                           float2 *S1, float2 *S2, const int *mask) {
-  GF_TRY(c, launch_fft_conv(c->stream, b, p, in, n_ch, S1, S2, out, mask));
-  GF_TRY(c, launch_direct(c->stream, b, p, in, n_ch, out, false, mask));
+  GF_TRY(c, launch_fft_conv(c->stream, b, p, in, n_ch, S1, S2, out, mask, nullptr));
+  GF_TRY(c, launch_direct(c->stream, b, p, in, n_ch, out, false, mask, nullptr));
   return GF_OK;
 }
 
@@ -802,7 +803,7 @@ gf_status gf_jacobian(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
   float *cpart = a.take<float>((int64_t)b->h_eval.size() * (kMaxP - 1));
   GF_TRY(c, launch_cot_prep(c->stream, b, cot, weight, scale, cimg, spart));
   GF_TRY(c, launch_fft_corr(c->stream, b, p, cimg, S1, S2, adj));
-  GF_TRY(c, launch_direct(c->stream, b, p, cimg, 1, adj, true, nullptr));
+  GF_TRY(c, launch_direct(c->stream, b, p, cimg, 1, adj, true, nullptr, nullptr));
   GF_TRY(c, launch_adjoint_contract(c->stream, b, theta, S, c->d_bn, adj, cpart));
   GF_TRY(c, launch_adjoint_final(c->stream, b, b->d_eval_first, cpart, spart, out));
   return GF_OK;
@@ -835,7 +836,67 @@ struct LMBufs {
   double *Ag, *theta_t, *Gsum;
   LMState *st;
   int *mjac, *mtrial, *cnt;
+  Work *lists;   // compacted work lists of the stamps still iterating
 };
+
+int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
+  return (int64_t)b->h_eval.size() + b->h_pix.size() + b->h_neq.size() + p->h_rows.size() + p->h_cols.size() +
+         p->h_irows.size() + p->h_rows_n.size() + p->h_cols_n.size() + p->h_irows_n.size() + p->h_direct.size();
+}
+
+// Work lists restricted to the stamps flagged in act, filtered from `from`
+// (the previous restriction, or the full lists when `from` is empty), stored
+// in `to` and uploaded into dev; the view points into dev.
+struct HostLists {
+  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct;
+  bool empty() const { return eval.empty() && pix.empty(); }
+};
+
+hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, const std::vector<char> &act,
+                          const HostLists &from, HostLists &to, Work *dev, WorkView &v) {
+  const bool full = from.empty();
+  auto filt = [&](const std::vector<Work> &src, std::vector<Work> &dst) {
+    std::vector<Work> out;
+    out.reserve(src.size());
+    for (const Work &w : src)
+      if (act[w.stamp]) out.push_back(w);
+    dst.swap(out);
+  };
+  filt(full ? b->h_eval : from.eval, to.eval);
+  filt(full ? b->h_pix : from.pix, to.pix);
+  filt(full ? b->h_neq : from.neq, to.neq);
+  filt(full ? p->h_rows : from.rows, to.rows);
+  filt(full ? p->h_cols : from.cols, to.cols);
+  filt(full ? p->h_irows : from.irows, to.irows);
+  filt(full ? p->h_rows_n : from.rows_n, to.rows_n);
+  filt(full ? p->h_cols_n : from.cols_n, to.cols_n);
+  filt(full ? p->h_irows_n : from.irows_n, to.irows_n);
+  filt(full ? p->h_direct : from.direct, to.direct);
+  Work *q = dev;
+  auto put = [&](const std::vector<Work> &src, const Work *&ptr, int &n) -> hipError_t {
+    ptr = q;
+    n = (int)src.size();
+    if (n) {
+      hipError_t e = hipMemcpyAsync(q, src.data(), src.size() * sizeof(Work), hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+    q += src.size();
+    return hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = put(to.eval, v.eval, v.n_eval);
+  if (e == hipSuccess) e = put(to.pix, v.pix, v.n_pix);
+  if (e == hipSuccess) e = put(to.neq, v.neq, v.n_neq);
+  if (e == hipSuccess) e = put(to.rows, v.rows, v.n_rows);
+  if (e == hipSuccess) e = put(to.cols, v.cols, v.n_cols);
+  if (e == hipSuccess) e = put(to.irows, v.irows, v.n_irows);
+  if (e == hipSuccess) e = put(to.rows_n, v.rows_n, v.n_rows_n);
+  if (e == hipSuccess) e = put(to.cols_n, v.cols_n, v.n_cols_n);
+  if (e == hipSuccess) e = put(to.irows_n, v.irows_n, v.n_irows_n);
+  if (e == hipSuccess) e = put(to.direct, v.direct, v.n_direct);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors must outlive the copies
+  return e;
+}
 
 void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a, LMBufs &B) {
   B.cpad = a.take<float>(b->n_pad * nchan);
@@ -854,6 +915,7 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.mjac = a.take<int>(b->n);
   B.mtrial = a.take<int>(b->n);
   B.cnt = a.take<int>(16);
+  B.lists = a.take<Work>(full_list_units(b, p));
 }
 
 }  // namespace
@@ -901,33 +963,48 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
     // start point: clip, evaluate, chi2
     GF_TRY(c, launch_lm_clip(cs, b->n_par, theta, o.lo, o.hi, B.theta_t));
-    GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr));
-    GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, nullptr));
-    GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, nullptr));
+    GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr));
+    GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, nullptr, nullptr));
+    GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, nullptr, nullptr));
     GF_TRY(c, launch_chi2(cs, b, B.mconv, B.theta_t, true, data, weight, nullptr, B.cpart, c->d_counters, B.chi2t,
                           nullptr));
     GF_TRY(c, launch_lm_init(cs, b, o.lambda0, B.chi2t, B.st, B.mjac, B.mtrial, B.cnt));
+    WorkView view;
+    const WorkView *vw = nullptr;   // null: the full lists
+    HostLists cur, nxt;
+    int view_stamps = b->n;
     auto iteration = [&]() -> gf_status {
-      GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac));
-      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac));
-      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac));
+      GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw));
+      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
+      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw));
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, B.Gsum, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
-      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial));
-      GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial));
-      GF_TRY(c, launch_chi2_part(cs, b, B.mconv, B.theta_t, data, weight, B.cpart, B.mtrial));
+      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial, vw));
+      GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial, vw));
+      GF_TRY(c, launch_chi2_part(cs, b, B.mconv, B.theta_t, data, weight, B.cpart, B.mtrial, vw));
       GF_TRY(c, launch_lm_update(cs, b, &o, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
       return GF_OK;
     };
-    if (o.use_graph && o.max_iter > 0) {
+    auto capture = [&]() -> gf_status {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
       GF_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       gf_status s2 = iteration();
       hipError_t ce = hipStreamEndCapture(cs, &graph);
       if (s2 != GF_OK) return s2;
       GF_TRY(c, ce);
       GF_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      return GF_OK;
+    };
+    if (o.use_graph && o.max_iter > 0) {
+      gf_status s2 = capture();
+      if (s2 != GF_OK) return s2;
     }
+    std::vector<LMState> hst;
+    std::vector<char> act;
     for (int it = 0; it < o.max_iter; ++it) {
       if (exec) {
         GF_TRY(c, hipGraphLaunch(exec, cs));
@@ -938,7 +1015,34 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       if ((it + 1) % o.poll_every == 0 || it + 1 == o.max_iter) {
         GF_TRY(c, hipMemcpyAsync(c->h_pinned, B.cnt, sizeof(int), hipMemcpyDeviceToHost, cs));
         GF_TRY(c, hipStreamSynchronize(cs));
-        if (*(volatile int *)c->h_pinned == 0) break;
+        const int active = *(volatile int *)c->h_pinned;
+        if (active == 0) break;
+        // Once half of the stamps in the current lists have finished, restrict
+        // the lists to the stamps still iterating (finished stamps would
+        // otherwise still cost their workgroups in every launch).
+        if (b->n > 1 && 2 * active <= view_stamps && it + 1 < o.max_iter) {
+          hst.resize(b->n);
+          GF_TRY(c, hipMemcpy(hst.data(), B.st, b->n * sizeof(LMState), hipMemcpyDeviceToHost));
+          act.assign(b->n, 0);
+          for (int q = 0; q < b->n; ++q) act[q] = hst[q].active ? 1 : 0;
+          GF_TRY(c, restrict_lists(cs, b, p, act, cur, nxt, B.lists, view));
+          cur.eval.swap(nxt.eval);
+          cur.pix.swap(nxt.pix);
+          cur.neq.swap(nxt.neq);
+          cur.rows.swap(nxt.rows);
+          cur.cols.swap(nxt.cols);
+          cur.irows.swap(nxt.irows);
+          cur.rows_n.swap(nxt.rows_n);
+          cur.cols_n.swap(nxt.cols_n);
+          cur.irows_n.swap(nxt.irows_n);
+          cur.direct.swap(nxt.direct);
+          vw = &view;
+          view_stamps = active;
+          if (exec) {
+            gf_status s2 = capture();
+            if (s2 != GF_OK) return s2;
+          }
+        }
       }
     }
     GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
@@ -1036,10 +1140,10 @@ gf_status gf_fit_simplex(gf_ctx *c, const gf_batch *b, const gf_psf *p, const fl
     GF_TRY(c, launch_nm_init(cs, b, theta, o.step, &o, X, theta_t, state, mask, cnt));
     auto iteration = [&]() -> gf_status {
       GF_TRY(c, launch_nm_zero(cs, cnt));
-      GF_TRY(c, launch_eval_d(cs, b, theta_t, S, c->d_bn, mpad, mask));
-      GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, mask));
-      GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, mask));
-      GF_TRY(c, launch_chi2_part(cs, b, mconv, theta_t, data, weight, cpart, mask));
+      GF_TRY(c, launch_eval_d(cs, b, theta_t, S, c->d_bn, mpad, mask, nullptr));
+      GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, mask, nullptr));
+      GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, mask, nullptr));
+      GF_TRY(c, launch_chi2_part(cs, b, mconv, theta_t, data, weight, cpart, mask, nullptr));
       GF_TRY(c, launch_nm_step(cs, b, cpart, &o, state, X, F, XR, theta_t, mask, trace, trace_cap, cnt));
       return GF_OK;
     };
@@ -1124,18 +1228,18 @@ gf_status gf_mcmc_run(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
   layout(a);
   hipStream_t cs = c->stream;
   // chi^2 of the start point
-  GF_TRY(c, launch_eval_d(cs, b, theta, S, c->d_bn, mpad, nullptr));
-  GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, nullptr));
-  GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, nullptr));
+  GF_TRY(c, launch_eval_d(cs, b, theta, S, c->d_bn, mpad, nullptr, nullptr));
+  GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, nullptr, nullptr));
+  GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, nullptr, nullptr));
   GF_TRY(c, launch_chi2(cs, b, mconv, theta, true, data, weight, nullptr, cpart, c->d_counters, pairs, nullptr));
   GF_TRY(c, launch_mcmc_init(cs, b->n, pairs, chi2_d, tstep));
   auto step = [&](hipStream_t sx) -> gf_status {
     GF_TRY(c, launch_mcmc_propose(sx, b, theta, o.scale, o.lo, o.hi, o.key0, o.key1, o.stream, o.step0, tstep,
                                   theta_t, mask));
-    GF_TRY(c, launch_eval_d(sx, b, theta_t, S, c->d_bn, mpad, mask));
-    GF_TRY(c, launch_fft_conv(sx, b, p, mpad, 1, S1, S2, mconv, mask));
-    GF_TRY(c, launch_direct(sx, b, p, mpad, 1, mconv, false, mask));
-    GF_TRY(c, launch_chi2_part(sx, b, mconv, theta_t, data, weight, cpart, mask));
+    GF_TRY(c, launch_eval_d(sx, b, theta_t, S, c->d_bn, mpad, mask, nullptr));
+    GF_TRY(c, launch_fft_conv(sx, b, p, mpad, 1, S1, S2, mconv, mask, nullptr));
+    GF_TRY(c, launch_direct(sx, b, p, mpad, 1, mconv, false, mask, nullptr));
+    GF_TRY(c, launch_chi2_part(sx, b, mconv, theta_t, data, weight, cpart, mask, nullptr));
     GF_TRY(c, launch_mcmc_accept(sx, b, cpart, mask, o.key0, o.key1, o.stream, o.step0, tstep, theta, theta_t, chi2_d,
                                  accepted, samples, o.thin));
     return GF_OK;

@@ -66,6 +66,21 @@ struct Work {
   int32_t unit;
 };
 
+// Work lists of one launch set: by default a batch's and a prepared PSF's
+// full lists; gf_fit_lm substitutes lists that hold only the stamps still
+// iterating, so finished stamps cost no workgroups.  Null pointers mean
+// "the full list".
+struct WorkView {
+  const Work *eval = nullptr, *pix = nullptr, *neq = nullptr;
+  int n_eval = 0, n_pix = 0, n_neq = 0;
+  const Work *rows = nullptr, *cols = nullptr, *irows = nullptr;
+  int n_rows = 0, n_cols = 0, n_irows = 0;
+  const Work *rows_n = nullptr, *cols_n = nullptr, *irows_n = nullptr;
+  int n_rows_n = 0, n_cols_n = 0, n_irows_n = 0;
+  const Work *direct = nullptr;
+  int n_direct = 0;
+};
+
 // Per-component constants of the evaluation kernels (computed per workgroup).
 struct CompC {
   int32_t ix, iy;    // integer part of the centre

@@ -102,19 +102,20 @@ static size_t direct_lds_bytes(int K) {
 }
 
 hipError_t launch_direct(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch, float *out,
-                         bool corr, const int *mask) {
-  const std::vector<Work> &lst = corr ? p->h_adirect : p->h_direct;
-  if (lst.empty()) return hipSuccess;
+                         bool corr, const int *mask, const WorkView *v) {
+  const bool view = !corr && v && v->rows;   // a view always carries a direct list (possibly empty)
+  const int nlst = view ? v->n_direct : (int)(corr ? p->h_adirect : p->h_direct).size();
+  if (nlst == 0) return hipSuccess;
   int maxK = 1;
   for (const auto &d : b->h_desc) maxK = d.K > maxK ? d.K : maxK;
   const size_t lds = direct_lds_bytes(maxK);
   ProfScope ps(st, corr ? "k_direct_corr" : "k_direct");
   if (corr)
-    hipLaunchKernelGGL((k_direct<1>), dim3((unsigned)lst.size(), n_ch), dim3(kThreads), lds, st, b->d_desc,
+    hipLaunchKernelGGL((k_direct<1>), dim3((unsigned)nlst, n_ch), dim3(kThreads), lds, st, b->d_desc,
                        p->d_adirect, in, n_ch, p->d_taps, out, mask);
   else
-    hipLaunchKernelGGL((k_direct<0>), dim3((unsigned)lst.size(), n_ch), dim3(kThreads), lds, st, b->d_desc,
-                       p->d_direct, in, n_ch, p->d_taps, out, mask);
+    hipLaunchKernelGGL((k_direct<0>), dim3((unsigned)nlst, n_ch), dim3(kThreads), lds, st, b->d_desc,
+                       view ? v->direct : p->d_direct, in, n_ch, p->d_taps, out, mask);
   return hipGetLastError();
 }
 

@@ -268,14 +268,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
 // ----------------------------------------------------------------- launchers
 template <typename TT>
 static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
-                                float *out, const int *mask) {
-  dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
+                                float *out, const int *mask, const WorkView *v) {
+  const Work *lst = v && v->eval ? v->eval : b->d_eval;
+  dim3 grid((unsigned)(v && v->eval ? v->n_eval : (int)b->h_eval.size())), block(kThreads);
   if (grid.x == 0) return hipSuccess;
   ProfScope ps(st, "k_eval");
   switch (S) {
 #define GF_EVAL_CASE(SS)                                                                          \
   case SS:                                                                                        \
-    hipLaunchKernelGGL((k_eval<TT, SS>), grid, block, 0, st, b->d_desc, b->d_eval, theta, bn, out, mask); \
+    hipLaunchKernelGGL((k_eval<TT, SS>), grid, block, 0, st, b->d_desc, lst, theta, bn, out, mask); \
     break;
     GF_EVAL_CASE(1) GF_EVAL_CASE(2) GF_EVAL_CASE(3) GF_EVAL_CASE(4)
     GF_EVAL_CASE(5) GF_EVAL_CASE(6) GF_EVAL_CASE(7) GF_EVAL_CASE(8)
@@ -288,24 +289,25 @@ static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *the
 
 hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn, float *out,
                        const int *mask) {
-  return launch_eval_t<float>(st, b, theta, S, bn, out, mask);
+  return launch_eval_t<float>(st, b, theta, S, bn, out, mask, nullptr);
 }
 
 hipError_t launch_eval_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
-                         float *out, const int *mask) {
-  return launch_eval_t<double>(st, b, theta, S, bn, out, mask);
+                         float *out, const int *mask, const WorkView *v) {
+  return launch_eval_t<double>(st, b, theta, S, bn, out, mask, v);
 }
 
 template <typename TT>
 static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
-                                    float *out, int chan_stride, const int *mask) {
-  dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
+                                    float *out, int chan_stride, const int *mask, const WorkView *v) {
+  const Work *lst = v && v->eval ? v->eval : b->d_eval;
+  dim3 grid((unsigned)(v && v->eval ? v->n_eval : (int)b->h_eval.size())), block(kThreads);
   if (grid.x == 0) return hipSuccess;
   ProfScope ps(st, "k_eval_jac");
   switch (S) {
 #define GF_EVALJ_CASE(SS)                                                                                   \
   case SS:                                                                                                  \
-    hipLaunchKernelGGL((k_eval_jac<TT, SS>), grid, block, 0, st, b->d_desc, b->d_eval, theta, bn, out,      \
+    hipLaunchKernelGGL((k_eval_jac<TT, SS>), grid, block, 0, st, b->d_desc, lst, theta, bn, out,            \
                        chan_stride, mask);                                                                  \
     break;
     GF_EVALJ_CASE(1) GF_EVALJ_CASE(2) GF_EVALJ_CASE(3) GF_EVALJ_CASE(4)
@@ -319,12 +321,12 @@ static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT 
 
 hipError_t launch_eval_jac(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn,
                            float *out, int chan_stride, const int *mask) {
-  return launch_eval_jac_t<float>(st, b, theta, S, bn, out, chan_stride, mask);
+  return launch_eval_jac_t<float>(st, b, theta, S, bn, out, chan_stride, mask, nullptr);
 }
 
 hipError_t launch_eval_jac_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
-                             float *out, int chan_stride, const int *mask) {
-  return launch_eval_jac_t<double>(st, b, theta, S, bn, out, chan_stride, mask);
+                             float *out, int chan_stride, const int *mask, const WorkView *v) {
+  return launch_eval_jac_t<double>(st, b, theta, S, bn, out, chan_stride, mask, v);
 }
 
 hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn,

@@ -634,32 +634,34 @@ static size_t fft_lds_bytes(int max_L) { return (size_t)(kFftLds + max_L) * size
 // narrow shape: one row pair or two bins per workgroup, so more CUs share the
 // latency-bound work.
 hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
-                           float2 *S1, float2 *S2, float *out, const int *mask) {
-  if (p->h_rows.empty()) return hipSuccess;
+                           float2 *S1, float2 *S2, float *out, const int *mask, const WorkView *v) {
+  const bool view = v && v->rows;
+  const int n_cols_w = view ? v->n_cols : (int)p->h_cols.size();
+  if ((view ? v->n_rows : (int)p->h_rows.size()) == 0) return hipSuccess;
   const size_t lds = fft_lds_bytes(p->max_L);
   dim3 blk(kThreads);
-  const bool narrow = (int64_t)p->h_cols.size() * n_ch < 2 * 256;
-  const std::vector<Work> &rows = narrow ? p->h_rows_n : p->h_rows;
-  const std::vector<Work> &cols = narrow ? p->h_cols_n : p->h_cols;
-  const std::vector<Work> &irows = narrow ? p->h_irows_n : p->h_irows;
-  const Work *d_rows = narrow ? p->d_rows_n : p->d_rows;
-  const Work *d_cols = narrow ? p->d_cols_n : p->d_cols;
-  const Work *d_irows = narrow ? p->d_irows_n : p->d_irows;
+  const bool narrow = (int64_t)n_cols_w * n_ch < 2 * 256;
+  const int nr = view ? (narrow ? v->n_rows_n : v->n_rows) : (int)(narrow ? p->h_rows_n : p->h_rows).size();
+  const int nc = view ? (narrow ? v->n_cols_n : v->n_cols) : (int)(narrow ? p->h_cols_n : p->h_cols).size();
+  const int ni = view ? (narrow ? v->n_irows_n : v->n_irows) : (int)(narrow ? p->h_irows_n : p->h_irows).size();
+  const Work *d_rows = view ? (narrow ? v->rows_n : v->rows) : (narrow ? p->d_rows_n : p->d_rows);
+  const Work *d_cols = view ? (narrow ? v->cols_n : v->cols) : (narrow ? p->d_cols_n : p->d_cols);
+  const Work *d_irows = view ? (narrow ? v->irows_n : v->irows) : (narrow ? p->d_irows_n : p->d_irows);
   const int tr = narrow ? kFftNarrowT : 1 << 20, tc = narrow ? kFftNarrowC : 1 << 20;
   {
     ProfScope ps(st, "k_fft_rows");
-    hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)rows.size(), n_ch), blk, lds, st, b->d_desc,
-                       p->d_path, p->d_plans, p->d_tw, d_rows, in, n_ch, p->d_s1, S1, mask, tr);
+    hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)nr, n_ch), blk, lds, st, b->d_desc, p->d_path,
+                       p->d_plans, p->d_tw, d_rows, in, n_ch, p->d_s1, S1, mask, tr);
   }
   {
     ProfScope ps(st, "k_fft_cols");
-    hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)cols.size(), n_ch), blk, lds, st, b->d_desc,
-                       p->d_path, p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
+    hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)nc, n_ch), blk, lds, st, b->d_desc, p->d_path,
+                       p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
   }
   {
     ProfScope ps(st, "k_fft_irows");
-    hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)irows.size(), n_ch), blk, lds, st, b->d_desc,
-                       p->d_path, p->d_plans, p->d_tw, d_irows, n_ch, p->d_s2, S2, out, mask, tr);
+    hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)ni, n_ch), blk, lds, st, b->d_desc, p->d_path,
+                       p->d_plans, p->d_tw, d_irows, n_ch, p->d_s2, S2, out, mask, tr);
   }
   return hipGetLastError();
 }

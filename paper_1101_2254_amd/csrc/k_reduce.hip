@@ -49,7 +49,8 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
                                                    const float *__restrict__ model, const TT *__restrict__ theta,
                                                    const float *__restrict__ data, const float *__restrict__ weight,
                                                    float *__restrict__ resid, float2 *__restrict__ part,
-                                                   const int *__restrict__ mask, int vec_ok) {
+                                                   const int32_t *__restrict__ first, const int *__restrict__ mask,
+                                                   int vec_ok) {
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
     }
   }
   const F2 tot = block_sum(acc);
-  if (threadIdx.x == 0) part[blockIdx.x] = make_float2(tot.hi, tot.lo);
+  if (threadIdx.x == 0) part[first[s] + w.unit] = make_float2(tot.hi, tot.lo);   // the unit's own slot
 }
 
 static inline int aligned16(const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -118,13 +119,15 @@ __global__ __launch_bounds__(64) void k_pair_final(const int32_t *__restrict__ f
 }
 
 hipError_t launch_chi2_part(hipStream_t st, const gf_batch *b, const float *model, const double *theta,
-                            const float *data, const float *weight, float2 *part, const int *mask) {
-  dim3 grid((unsigned)b->h_pix.size()), blk(kThreads);
+                            const float *data, const float *weight, float2 *part, const int *mask,
+                            const WorkView *v) {
+  const bool view = v && v->pix;
+  dim3 grid((unsigned)(view ? v->n_pix : (int)b->h_pix.size())), blk(kThreads);
   if (grid.x == 0) return hipSuccess;
   ProfScope ps(st, "k_chi2");
   const int vec_ok = aligned16(model) && aligned16(data) && aligned16(weight);
-  hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, model, theta, data, weight,
-                     (float *)nullptr, part, mask, vec_ok);
+  hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, view ? v->pix : b->d_pix, model, theta, data,
+                     weight, (float *)nullptr, part, b->d_pix_first, mask, vec_ok);
   return hipGetLastError();
 }
 
@@ -139,10 +142,10 @@ hipError_t launch_chi2(hipStream_t st, const gf_batch *b, const float *model, co
     const int vec_ok = aligned16(model) && aligned16(data) && aligned16(weight) && aligned16(resid);
     if (theta_f64)
       hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, b->d_pix, model, (const double *)theta,
-                         data, weight, resid, part, mask, vec_ok);
+                         data, weight, resid, part, b->d_pix_first, mask, vec_ok);
     else
       hipLaunchKernelGGL((k_chi2<float>), grid, blk, 0, st, b->d_desc, b->d_pix, model, (const float *)theta, data,
-                         weight, resid, part, mask, vec_ok);
+                         weight, resid, part, b->d_pix_first, mask, vec_ok);
   }
   {
     ProfScope ps(st, "k_pair_final");
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
                                                    const float *__restrict__ jc, int nchan,
                                                    const double *__restrict__ theta, const float *__restrict__ data,
                                                    const float *__restrict__ weight, float *__restrict__ part,
-                                                   const int *__restrict__ mask) {
+                                                   const int32_t *__restrict__ first, const int *__restrict__ mask) {
   constexpr int P = kNPC * NC + 1;
   static_assert(P + 1 <= 16, "augmented Jacobian must fit 16 columns");
   __shared__ float red[kGramThreads / 64][256];
@@ -342,15 +345,17 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
     float v = 0.0f;
 #pragma unroll
     for (int ww = 0; ww < kGramThreads / 64; ++ww) v += red[ww][e];
-    part[(int64_t)blockIdx.x * 256 + e] = v;
+    part[(int64_t)(first[s] + wk.unit) * 256 + e] = v;   // the unit's own slot
   }
 }
 
 hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, const double *theta,
                             const float *data, const float *weight, float *part, int nacc_stride, int nchan,
-                            const int *mask) {
+                            const int *mask, const WorkView *v) {
   (void)nacc_stride;
-  dim3 grid((unsigned)b->h_neq.size()), blk(kGramThreads);
+  const bool view = v && v->neq;
+  const Work *lst = view ? v->neq : b->d_neq;
+  dim3 grid((unsigned)(view ? v->n_neq : (int)b->h_neq.size())), blk(kGramThreads);
   if (grid.x == 0) return hipSuccess;
   ProfScope ps(st, "k_gram");
   bool has1 = false, has2 = false;
@@ -359,9 +364,11 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
     has2 |= d.ncomp == 2;
   }
   if (has1)
-    hipLaunchKernelGGL((k_gram<1>), grid, blk, 0, st, b->d_desc, b->d_neq, jc, nchan, theta, data, weight, part, mask);
+    hipLaunchKernelGGL((k_gram<1>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part,
+                       b->d_neq_first, mask);
   if (has2)
-    hipLaunchKernelGGL((k_gram<2>), grid, blk, 0, st, b->d_desc, b->d_neq, jc, nchan, theta, data, weight, part, mask);
+    hipLaunchKernelGGL((k_gram<2>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part,
+                       b->d_neq_first, mask);
   return hipGetLastError();
 }
 
