@@ -14,11 +14,11 @@ namespace gf {
 std::vector<float4> build_bn_table();
 hipError_t launch_eval(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, const int *);
 hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, const int *,
-                         const WorkView *);
+                         const WorkView *, CompC *cc = nullptr, bool prep = true);
 hipError_t launch_eval_jac(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, int,
                            const int *);
 hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, int,
-                             const int *, const WorkView *);
+                             const int *, const WorkView *, CompC *cc = nullptr, bool prep = true);
 hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float4 *, const float *,
                                    float *);
 hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
@@ -40,11 +40,12 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, double *, const gf_lm_opts *, LMState *,
-                           double *, const double *, double *, int *, int *, int *);
+                           double *, const double *, double *, int *, int *, int *, CompC *, CompC *,
+                           const float4 *);
 hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const double *, const float *,
                             const float *, float2 *, const int *, const WorkView *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
-                            const double *, int *, int *, int *);
+                            const double *, int *, int *, int *, CompC *, CompC *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
 hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
@@ -392,6 +393,7 @@ static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t 
   if (e == hipSuccess) e = upload(&b->d_eval_first, b->h_eval_first);
   if (e == hipSuccess) e = upload(&b->d_gfirst, b->h_gfirst);
   if (e == hipSuccess) e = upload(&b->d_gmembers, b->h_gmembers);
+  if (e == hipSuccess) e = hipMalloc(&b->d_cc, sizeof(gf::CompC) * (size_t)b->n * kMaxComp);
   if (e != hipSuccess) {
     gf_batch_destroy(b);
     return fail(c, GF_EDEVICE, std::string("gf_batch_create: ") + hipGetErrorString(e));
@@ -422,6 +424,7 @@ void gf_batch_destroy(gf_batch *b) {
   dfree(b->d_eval_first);
   dfree(b->d_gfirst);
   dfree(b->d_gmembers);
+  dfree(b->d_cc);
   delete b;
 }
 
@@ -837,6 +840,7 @@ struct LMBufs {
   LMState *st;
   int *mjac, *mtrial, *cnt;
   Work *lists;   // compacted work lists of the stamps still iterating
+  CompC *cc_th, *cc_t;   // component constants of theta and of the trial point
 };
 
 int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
@@ -916,6 +920,8 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.mtrial = a.take<int>(b->n);
   B.cnt = a.take<int>(16);
   B.lists = a.take<Work>(full_list_units(b, p));
+  B.cc_th = a.take<CompC>((int64_t)b->n * kMaxComp);
+  B.cc_t = a.take<CompC>((int64_t)b->n * kMaxComp);
 }
 
 }  // namespace
@@ -963,7 +969,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
     // start point: clip, evaluate, chi2
     GF_TRY(c, launch_lm_clip(cs, b->n_par, theta, o.lo, o.hi, B.theta_t));
-    GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr));
+    GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, true));
     GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, nullptr, nullptr));
     GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, nullptr, nullptr));
     GF_TRY(c, launch_chi2(cs, b, B.mconv, B.theta_t, true, data, weight, nullptr, B.cpart, c->d_counters, B.chi2t,
@@ -974,16 +980,18 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     HostLists cur, nxt;
     int view_stamps = b->n;
     auto iteration = [&]() -> gf_status {
-      GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw));
+      GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw, B.cc_th, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw));
-      GF_TRY(c, launch_lm_solve(cs, b, B.npart, B.Gsum, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
-      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw));
+      GF_TRY(c, launch_lm_solve(cs, b, B.npart, B.Gsum, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt,
+                                B.cc_th, B.cc_t, c->d_bn));
+      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial, vw));
       GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial, vw));
       GF_TRY(c, launch_chi2_part(cs, b, B.mconv, B.theta_t, data, weight, B.cpart, B.mtrial, vw));
-      GF_TRY(c, launch_lm_update(cs, b, &o, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt));
+      GF_TRY(c, launch_lm_update(cs, b, &o, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
+                                 B.cc_t));
       return GF_OK;
     };
     auto capture = [&]() -> gf_status {

@@ -87,6 +87,7 @@ struct CompC {
   float fx, fy;      // centre minus integer part
   float ox[GF_MAX_OVERSAMPLE], oy[GF_MAX_OVERSAMPLE];  // sub-sample offset minus (fx, fy)
   float cs, sn;      // cos phi, sin phi
+  float cq, sq;      // cos phi / q, sin phi / q
   float iq2;         // 1/q^2
   float a1, a0;      // t = exp2(a1 * log2(R^2) + a0)
   float b1;          // b_n * log2(e)
@@ -212,6 +213,10 @@ struct gf_batch {
   gf::Work *d_eval = nullptr, *d_pix = nullptr, *d_neq = nullptr;
   std::vector<int32_t> h_pix_first, h_neq_first, h_eval_first;   // first unit index per stamp (+ total)
   int32_t *d_pix_first = nullptr, *d_neq_first = nullptr, *d_eval_first = nullptr;
+  // per-(stamp, component) constants of the current evaluation, rewritten by
+  // every evaluation launch (calls on one batch are ordered on its context's
+  // stream)
+  gf::CompC *d_cc = nullptr;
   bool uniform = true;
   // observation groups (gf_batch_create_grouped): members of group g are
   // d_gmembers[d_gfirst[g] .. d_gfirst[g+1]); one group per stamp otherwise

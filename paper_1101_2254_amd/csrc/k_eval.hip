@@ -15,83 +15,37 @@
 // cusp (R/Re)^(1/n) is steep, and is exactly zero when the centre sits on a
 // sub-sample.
 #include "gf_internal.h"
+#include "comp.h"
 
 namespace gf {
 
-__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
-__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
-
-// Cubic Hermite lookup of b_n (from node values and slopes) and of db_n/dn
-// (from node slopes and curvatures) in the FP32 table built on the host.
-__device__ __forceinline__ void bn_lookup(float n, const float4 *__restrict__ tab, float &b, float &db) {
-  const float h = (float)((kBnHi - kBnLo) / (kBnNodes - 1));
-  float u = (n - (float)kBnLo) / h;
-  u = fminf(fmaxf(u, 0.0f), (float)(kBnNodes - 1) - 1e-3f);
-  const int i = (int)u;
-  const float t = u - (float)i;
-  const float4 p0 = tab[i], p1 = tab[i + 1];
-  const float t2 = t * t, t3 = t2 * t;
-  const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2, h11 = t3 - t2;
-  b = h00 * p0.x + h01 * p1.x + h * (h10 * p0.y + h11 * p1.y);
-  db = h00 * p0.y + h01 * p1.y + h * (h10 * p0.z + h11 * p1.z);
-}
-
-// Per-component constants from the parameter vector (float or double).
-// The sub-sample offsets relative to the fractional centre,
-//   (s + 1/2)/S - 1/2 - f = ((2s + 1 - S) - 2S f) / (2S),
-// take one FMA (exact numerator up to one rounding) and one division, so a
-// sub-sample within 1e-7 px of the centre keeps its distance to full
-// relative precision; the Sersic cusp makes the value at such a point very
-// sensitive to that distance for large n.
+// One thread per (stamp, component): the constants every pixel of the
+// component needs, computed once per launch instead of once per workgroup
+// (the set-up costs about as many instructions as one wave's whole pixel
+// loop at S = 5).
 template <typename TT>
-__device__ void comp_setup(const TT *__restrict__ t, const float4 *__restrict__ bn_tab, int S, CompC &c) {
-  TT x0 = t[0], y0 = t[1];
-  TT rx = rint(x0), ry = rint(y0);
-  c.ix = (int)rx;
-  c.iy = (int)ry;
-  c.fx = (float)(x0 - rx);
-  c.fy = (float)(y0 - ry);
-  const float twoS = 2.0f * (float)S;
-  for (int a = 0; a < GF_MAX_OVERSAMPLE; ++a) {
-    const float num = (float)(2 * a + 1 - S);
-    c.ox[a] = fmaf(-twoS, c.fx, num) / twoS;
-    c.oy[a] = fmaf(-twoS, c.fy, num) / twoS;
-  }
-  float ie = (float)t[2], re = (float)t[3], n = (float)t[4], q = (float)t[5], phi = (float)t[6];
-  float sn, cs;
-  sincosf(phi, &sn, &cs);
-  float bn, dbn;
-  bn_lookup(n, bn_tab, bn, dbn);
-  c.cs = cs;
-  c.sn = sn;
-  c.iq2 = 1.0f / (q * q);
-  c.a1 = 0.5f / n;
-  c.a0 = -log2f(re) / n;
-  c.b1 = bn * 1.4426950408889634f;
-  c.lie = log2f(ie);
-  c.ie = ie;
-  c.re = re;
-  c.n = n;
-  c.q = q;
-  c.bn = bn;
-  c.dbn = dbn;
-  c.inv_n = 1.0f / n;
-  c.inv_re = 1.0f / re;
-  c.inv_q = 1.0f / q;
+__global__ void k_comp_prep(const StampDesc *__restrict__ desc, int n, const TT *__restrict__ theta,
+                            const float4 *__restrict__ bn_tab, int S, CompC *__restrict__ cc,
+                            const int *__restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = i / kMaxComp, k = i - s * kMaxComp;
+  if (s >= n || (mask && !mask[s])) return;
+  const StampDesc d = desc[s];
+  if (k < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * k, bn_tab, S, cc[i]);
 }
 
 // ----------------------------------------------------------------- values
-template <typename TT, int S>
+// R^2 = x'^2 + (y'/q)^2 with y'/q formed directly from cos phi / q and
+// sin phi / q (one multiply fewer per sub-sample than scaling y'^2).
+template <int S>
 __global__ __launch_bounds__(kThreads) void k_eval(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
-                                                   const TT *__restrict__ theta, const float4 *__restrict__ bn_tab,
-                                                   float *__restrict__ out, const int *__restrict__ mask) {
-  __shared__ CompC cc[kMaxComp];
+                                                   const CompC *__restrict__ cc, float *__restrict__ out,
+                                                   const int *__restrict__ mask) {
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
   const StampDesc d = desc[s];
-  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, S, cc[threadIdx.x]);
-  __syncthreads();
+  cc += (int64_t)s * kMaxComp;
   const int npad = d.Mh * d.Mw;
   const int p = w.unit * kEvalTile + (int)threadIdx.x;
   if (p >= npad) return;
@@ -109,13 +63,13 @@ __global__ __launch_bounds__(kThreads) void k_eval(const StampDesc *__restrict__
 #pragma unroll
     for (int b = 0; b < S; ++b) {
       const float dy = iy + C.oy[b];
-      const float dysn = dy * C.sn, dycs = dy * C.cs;
+      const float dysn = dy * C.sn, dycq = dy * C.cq;
 #pragma unroll
       for (int a = 0; a < S; ++a) {
         const float dx = ox[a];
         const float xp = fmaf(dx, C.cs, dysn);
-        const float yp = fmaf(-dx, C.sn, dycs);
-        const float r2 = fmaf(C.iq2 * yp, yp, xp * xp);
+        const float yq = fmaf(-dx, C.sq, dycq);
+        const float r2 = fmaf(yq, yq, xp * xp);
         const float t = fast_exp2(fmaf(fast_log2(r2), C.a1, C.a0));
         acc += fast_exp2(fmaf(-C.b1, t, peak));
       }
@@ -165,18 +119,16 @@ __device__ __forceinline__ void point_grad(const CompC &C, float dx, float dy, f
 // Layout: out[jac_pad_off(s) + ch * Mh*Mw + pixel] with jac_pad_off = 7 * pad
 // offset scaled by the channel count of the batch (chan_stride channels per
 // stamp).
-template <typename TT, int S>
+template <int S>
 __global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restrict__ desc,
-                                                       const Work *__restrict__ work, const TT *__restrict__ theta,
-                                                       const float4 *__restrict__ bn_tab, float *__restrict__ out,
-                                                       int chan_stride, const int *__restrict__ mask) {
-  __shared__ CompC cc[kMaxComp];
+                                                       const Work *__restrict__ work, const CompC *__restrict__ cc,
+                                                       float *__restrict__ out, int chan_stride,
+                                                       const int *__restrict__ mask) {
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   if (mask && !mask[s]) return;
   const StampDesc d = desc[s];
-  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, S, cc[threadIdx.x]);
-  __syncthreads();
+  cc += (int64_t)s * kMaxComp;
   const int npad = d.Mh * d.Mw;
   const int p = w.unit * kEvalTile + (int)threadIdx.x;
   if (p >= npad) return;
@@ -203,20 +155,17 @@ __global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restri
 //   part[chunk][p] = sum over the chunk's pixels of adj[pixel] * dM/dtheta_p
 // (component parameters only; the sky term is added by the caller).
 // adj holds one padded grid per stamp at desc.pad.
-template <typename TT, int S>
+template <int S>
 __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *__restrict__ desc,
                                                                const Work *__restrict__ work,
-                                                               const TT *__restrict__ theta,
-                                                               const float4 *__restrict__ bn_tab,
+                                                               const CompC *__restrict__ cc,
                                                                const float *__restrict__ adj,
                                                                float *__restrict__ part) {
-  __shared__ CompC cc[kMaxComp];
   __shared__ float red[kThreads / 64][kMaxP];
   const Work w = work[blockIdx.x];
   const int s = w.stamp;
   const StampDesc d = desc[s];
-  if ((int)threadIdx.x < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * threadIdx.x, bn_tab, S, cc[threadIdx.x]);
-  __syncthreads();
+  cc += (int64_t)s * kMaxComp;
   const int npad = d.Mh * d.Mw;
   const int p = w.unit * kEvalTile + (int)threadIdx.x;
   const int nq = kNPC * d.ncomp;
@@ -267,16 +216,31 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
 
 // ----------------------------------------------------------------- launchers
 template <typename TT>
+static hipError_t launch_prep(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
+                              const int *mask, CompC *cc) {
+  const int nt = b->n * kMaxComp;
+  hipLaunchKernelGGL((k_comp_prep<TT>), dim3((nt + 63) / 64), dim3(64), 0, st, b->d_desc, b->n, theta, bn, S, cc,
+                     mask);
+  return hipGetLastError();
+}
+
+template <typename TT>
 static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
-                                float *out, const int *mask, const WorkView *v) {
+                                float *out, const int *mask, const WorkView *v, CompC *cc, bool prep) {
   const Work *lst = v && v->eval ? v->eval : b->d_eval;
   dim3 grid((unsigned)(v && v->eval ? v->n_eval : (int)b->h_eval.size())), block(kThreads);
   if (grid.x == 0) return hipSuccess;
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return hipErrorInvalidValue;
+  if (!cc) cc = b->d_cc;
+  if (prep) {
+    hipError_t e = launch_prep<TT>(st, b, theta, S, bn, mask, cc);
+    if (e != hipSuccess) return e;
+  }
   ProfScope ps(st, "k_eval");
   switch (S) {
-#define GF_EVAL_CASE(SS)                                                                          \
-  case SS:                                                                                        \
-    hipLaunchKernelGGL((k_eval<TT, SS>), grid, block, 0, st, b->d_desc, lst, theta, bn, out, mask); \
+#define GF_EVAL_CASE(SS)                                                                        \
+  case SS:                                                                                      \
+    hipLaunchKernelGGL((k_eval<SS>), grid, block, 0, st, b->d_desc, lst, cc, out, mask);       \
     break;
     GF_EVAL_CASE(1) GF_EVAL_CASE(2) GF_EVAL_CASE(3) GF_EVAL_CASE(4)
     GF_EVAL_CASE(5) GF_EVAL_CASE(6) GF_EVAL_CASE(7) GF_EVAL_CASE(8)
@@ -289,26 +253,34 @@ static hipError_t launch_eval_t(hipStream_t st, const gf_batch *b, const TT *the
 
 hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn, float *out,
                        const int *mask) {
-  return launch_eval_t<float>(st, b, theta, S, bn, out, mask, nullptr);
+  return launch_eval_t<float>(st, b, theta, S, bn, out, mask, nullptr, nullptr, true);
 }
 
+// cc: where the component constants live (null: the batch's buffer); prep:
+// compute them from theta first (false: the caller keeps them current).
 hipError_t launch_eval_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
-                         float *out, const int *mask, const WorkView *v) {
-  return launch_eval_t<double>(st, b, theta, S, bn, out, mask, v);
+                         float *out, const int *mask, const WorkView *v, CompC *cc, bool prep) {
+  return launch_eval_t<double>(st, b, theta, S, bn, out, mask, v, cc, prep);
 }
 
 template <typename TT>
 static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT *theta, int S, const float4 *bn,
-                                    float *out, int chan_stride, const int *mask, const WorkView *v) {
+                                    float *out, int chan_stride, const int *mask, const WorkView *v, CompC *cc,
+                                    bool prep) {
   const Work *lst = v && v->eval ? v->eval : b->d_eval;
   dim3 grid((unsigned)(v && v->eval ? v->n_eval : (int)b->h_eval.size())), block(kThreads);
   if (grid.x == 0) return hipSuccess;
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return hipErrorInvalidValue;
+  if (!cc) cc = b->d_cc;
+  if (prep) {
+    hipError_t e = launch_prep<TT>(st, b, theta, S, bn, mask, cc);
+    if (e != hipSuccess) return e;
+  }
   ProfScope ps(st, "k_eval_jac");
   switch (S) {
-#define GF_EVALJ_CASE(SS)                                                                                   \
-  case SS:                                                                                                  \
-    hipLaunchKernelGGL((k_eval_jac<TT, SS>), grid, block, 0, st, b->d_desc, lst, theta, bn, out,            \
-                       chan_stride, mask);                                                                  \
+#define GF_EVALJ_CASE(SS)                                                                                  \
+  case SS:                                                                                                 \
+    hipLaunchKernelGGL((k_eval_jac<SS>), grid, block, 0, st, b->d_desc, lst, cc, out, chan_stride, mask);     \
     break;
     GF_EVALJ_CASE(1) GF_EVALJ_CASE(2) GF_EVALJ_CASE(3) GF_EVALJ_CASE(4)
     GF_EVALJ_CASE(5) GF_EVALJ_CASE(6) GF_EVALJ_CASE(7) GF_EVALJ_CASE(8)
@@ -321,24 +293,27 @@ static hipError_t launch_eval_jac_t(hipStream_t st, const gf_batch *b, const TT 
 
 hipError_t launch_eval_jac(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn,
                            float *out, int chan_stride, const int *mask) {
-  return launch_eval_jac_t<float>(st, b, theta, S, bn, out, chan_stride, mask, nullptr);
+  return launch_eval_jac_t<float>(st, b, theta, S, bn, out, chan_stride, mask, nullptr, nullptr, true);
 }
 
 hipError_t launch_eval_jac_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
-                             float *out, int chan_stride, const int *mask, const WorkView *v) {
-  return launch_eval_jac_t<double>(st, b, theta, S, bn, out, chan_stride, mask, v);
+                             float *out, int chan_stride, const int *mask, const WorkView *v, CompC *cc,
+                             bool prep) {
+  return launch_eval_jac_t<double>(st, b, theta, S, bn, out, chan_stride, mask, v, cc, prep);
 }
 
 hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const float *theta, int S, const float4 *bn,
                                    const float *adj, float *part) {
   dim3 grid((unsigned)b->h_eval.size()), block(kThreads);
   if (grid.x == 0) return hipSuccess;
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return hipErrorInvalidValue;
+  hipError_t e = launch_prep<float>(st, b, theta, S, bn, nullptr, b->d_cc);
+  if (e != hipSuccess) return e;
   ProfScope ps(st, "k_adjoint_contract");
   switch (S) {
-#define GF_ADJ_CASE(SS)                                                                                        \
-  case SS:                                                                                                     \
-    hipLaunchKernelGGL((k_adjoint_contract<float, SS>), grid, block, 0, st, b->d_desc, b->d_eval, theta, bn, adj, \
-                       part);                                                                                  \
+#define GF_ADJ_CASE(SS)                                                                                      \
+  case SS:                                                                                                   \
+    hipLaunchKernelGGL((k_adjoint_contract<SS>), grid, block, 0, st, b->d_desc, b->d_eval, b->d_cc, adj, part); \
     break;
     GF_ADJ_CASE(1) GF_ADJ_CASE(2) GF_ADJ_CASE(3) GF_ADJ_CASE(4)
     GF_ADJ_CASE(5) GF_ADJ_CASE(6) GF_ADJ_CASE(7) GF_ADJ_CASE(8)

@@ -11,6 +11,7 @@
 // bitwise reproducible.  (No cross-workgroup fences: on this chip a
 // device-scope release writes back the L2 of the issuing XCD.)
 #include "gf_internal.h"
+#include "comp.h"
 #include "twosum.h"
 
 namespace gf {
@@ -379,6 +380,12 @@ struct LMParams {
   double lambda_up, lambda_down, lambda_max, ftol, xtol;
   const double *lo, *hi;
   const uint8_t *free_mask;
+  // component constants kept current for the evaluation kernels (null: not
+  // kept): cc_t of the trial point (formed by k_lm_solve), cc_th of the
+  // current point (copied from cc_t on acceptance)
+  CompC *cc_t, *cc_th;
+  const float4 *bn;
+  int32_t oversample;
 };
 
 // Start: chi2 of the (clipped) start point is in chi2t.
@@ -481,6 +488,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
   __shared__ double th_s[P], lo_s[P], hi_s[P], g_s[P];
   __shared__ int fr_s[P];
   __shared__ int idx[P];
+  __shared__ double tt_s[P];
   __shared__ int nf_s, ok_s;
   const int s = blockIdx.x;
   const int tid = threadIdx.x;
@@ -612,6 +620,12 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
     double v = th_s[tid];
     if (a >= 0) v = fmin(fmax(v + y[a], lo_s[tid]), hi_s[tid]);
     theta_t[d.par + tid] = v;
+    tt_s[tid] = v;
+  }
+  if (prm.cc_t) {
+    wave_sync();
+    if (ok_s && tid < NC)
+      comp_setup<double>(tt_s + kNPC * tid, prm.bn, prm.oversample, prm.cc_t[(int64_t)s * kMaxComp + tid]);
   }
 }
 
@@ -654,6 +668,12 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
   }
   const bool accept = S.trial && c2 < S.chi2;
   if (accept && lane < P) theta[d.par + lane] = tt;
+  if (accept && prm.cc_t) {
+    const int nw = d.ncomp * (int)(sizeof(CompC) / sizeof(uint32_t));
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(prm.cc_t + (int64_t)s * kMaxComp);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(prm.cc_th + (int64_t)s * kMaxComp);
+    for (int q = lane; q < nw; q += 64) dst[q] = src[q];
+  }
   if (lane != 0) return;
   if (S.trial) {
     S.nfev += 1;
@@ -782,13 +802,13 @@ hipError_t launch_lm_clip(hipStream_t st, int64_t n_par, double *theta, const do
 
 hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, double *Gsum, const gf_lm_opts *o,
                            LMState *S, double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial,
-                           int *cnt) {
+                           int *cnt, CompC *cc_th, CompC *cc_t, const float4 *bn) {
   {
     ProfScope ps(st, "k_gram_reduce");
     hipLaunchKernelGGL(k_gram_reduce, dim3(b->n), dim3(kReduceThreads), 0, st, b->d_neq_first, part, Gsum, mjac);
   }
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
-               o->free_mask};
+               o->free_mask, cc_t, cc_th, bn, o->oversample};
   ProfScope ps(st, "k_lm_solve");
   bool has1 = false, has2 = false;
   for (const auto &d : b->h_desc) {
@@ -805,9 +825,10 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
 }
 
 hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const float2 *part, LMState *S,
-                            double *theta, const double *theta_t, int *mjac, int *mtrial, int *cnt) {
+                            double *theta, const double *theta_t, int *mjac, int *mtrial, int *cnt, CompC *cc_th,
+                            CompC *cc_t) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
-               o->free_mask};
+               o->free_mask, cc_t, cc_th, nullptr, o->oversample};
   ProfScope ps(st, "k_lm_update");
   hipLaunchKernelGGL(k_lm_update, dim3(b->n), dim3(64), 0, st, b->d_desc, b->d_pix_first, part, prm, S, theta,
                      theta_t, mjac, mtrial, cnt);
