@@ -44,7 +44,7 @@ __device__ inline void comp_setup(const TT *__restrict__ t, const float4 *__rest
   c.fx = (float)(x0 - rx);
   c.fy = (float)(y0 - ry);
   const float twoS = 2.0f * (float)S;
-  for (int a = 0; a < GF_MAX_OVERSAMPLE; ++a) {
+  for (int a = 0; a < S; ++a) {
     const float num = (float)(2 * a + 1 - S);
     c.ox[a] = fmaf(-twoS, c.fx, num) / twoS;
     c.oy[a] = fmaf(-twoS, c.fy, num) / twoS;

@@ -39,9 +39,8 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *, float *, int, int, const int *, const WorkView *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
-hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, double *, const gf_lm_opts *, LMState *,
-                           double *, const double *, double *, int *, int *, int *, CompC *, CompC *,
-                           const float4 *);
+hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
+                           const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *);
 hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const double *, const float *,
                             const float *, float2 *, const int *, const WorkView *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
@@ -836,7 +835,7 @@ namespace {
 struct LMBufs {
   float *cpad, *jc, *mpad, *mconv, *npart;
   float2 *S1, *S2, *chi2t, *cpart;
-  double *Ag, *theta_t, *Gsum;
+  double *Ag, *theta_t;
   LMState *st;
   int *mjac, *mtrial, *cnt;
   Work *lists;   // compacted work lists of the stamps still iterating
@@ -909,7 +908,6 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.S2 = a.take<float2>(p->n_s2 * nchan);
   B.npart = a.take<float>((int64_t)b->h_neq.size() * nacc);
   B.Ag = a.take<double>((int64_t)b->n * (kMaxP * kMaxP + kMaxP));
-  B.Gsum = a.take<double>((int64_t)b->n * 256);
   B.theta_t = a.take<double>(b->n_par);
   B.mpad = a.take<float>(b->n_pad);
   B.mconv = a.take<float>(b->n_pix);
@@ -984,8 +982,8 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw));
-      GF_TRY(c, launch_lm_solve(cs, b, B.npart, B.Gsum, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt,
-                                B.cc_th, B.cc_t, c->d_bn));
+      GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
+                                B.cc_t, c->d_bn));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial, vw));
       GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial, vw));

@@ -298,7 +298,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
                                                    const float *__restrict__ jc, int nchan,
                                                    const double *__restrict__ theta, const float *__restrict__ data,
                                                    const float *__restrict__ weight, float *__restrict__ part,
-                                                   const int32_t *__restrict__ first, const int *__restrict__ mask) {
+                                                   const int32_t *__restrict__ first, const int *__restrict__ mask,
+                                                   int vec_ok) {
   constexpr int P = kNPC * NC + 1;
   static_assert(P + 1 <= 16, "augmented Jacobian must fit 16 columns");
   __shared__ float red[kGramThreads / 64][256];
@@ -319,22 +320,51 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
   const int base = wk.unit * kNeqChunk + wv * per_wave;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   const int ich = i < P - 1 ? i : 0;  // channel read by this lane (clamped for the sky / residual lanes)
+  if (vec_ok && (((int64_t)d.pix * nchan | npix | d.img) & 3) == 0 && base + per_wave <= npix) {
+    // the wave's pixels all inside the stamp, 16-byte aligned (uniform over
+    // the wave): each lane loads its four consecutive pixels per operand
+    // with one 16-byte load
 #pragma unroll 4
-  for (int g = 0; g < per_wave; g += 16) {
+    for (int g = 0; g < per_wave; g += 16) {
+      const int p = base + g + 4 * kk;
+      const float4 wt = *reinterpret_cast<const float4 *>(weight + d.img + p);
+      const float4 jv = *reinterpret_cast<const float4 *>(J + (int64_t)ich * npix + p);
+      const float4 dv = *reinterpret_cast<const float4 *>(data + d.img + p);
+      float4 iv[NC];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int p = base + g + 4 * kk + q;
-      const bool ok = p < npix;
-      const int pc = ok ? p : npix - 1;  // in-bounds address for the straight-line loads
-      const float wt = weight[d.img + pc];
-      const float jv = J[(int64_t)ich * npix + pc];
-      const float dv = data[d.img + pc];
-      float m = sky;
+      for (int c = 0; c < NC; ++c) iv[c] = *reinterpret_cast<const float4 *>(J + (int64_t)(kNPC * c + 2) * npix + p);
+      const float wq[4] = {wt.x, wt.y, wt.z, wt.w}, jq[4] = {jv.x, jv.y, jv.z, jv.w};
+      const float dq[4] = {dv.x, dv.y, dv.z, dv.w};
 #pragma unroll
-      for (int c = 0; c < NC; ++c) m = fmaf(ie[c], J[(int64_t)(kNPC * c + 2) * npix + pc], m);
-      float x = (i < P - 1) ? jv : (i == P - 1) ? 1.0f : (i == P) ? dv - m : 0.0f;
-      x = ok ? x : 0.0f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, (ok ? wt : 0.0f) * x, acc, 0, 0, 0);
+      for (int q = 0; q < 4; ++q) {
+        float m = sky;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const float iq[4] = {iv[c].x, iv[c].y, iv[c].z, iv[c].w};
+          m = fmaf(ie[c], iq[q], m);
+        }
+        const float x = (i < P - 1) ? jq[q] : (i == P - 1) ? 1.0f : (i == P) ? dq[q] - m : 0.0f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
+      }
+    }
+  } else if (base < npix) {
+#pragma unroll 4
+    for (int g = 0; g < per_wave; g += 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = base + g + 4 * kk + q;
+        const bool ok = p < npix;
+        const int pc = ok ? p : npix - 1;  // in-bounds address for the straight-line loads
+        const float wt = weight[d.img + pc];
+        const float jv = J[(int64_t)ich * npix + pc];
+        const float dv = data[d.img + pc];
+        float m = sky;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) m = fmaf(ie[c], J[(int64_t)(kNPC * c + 2) * npix + pc], m);
+        float x = (i < P - 1) ? jv : (i == P - 1) ? 1.0f : (i == P) ? dv - m : 0.0f;
+        x = ok ? x : 0.0f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, (ok ? wt : 0.0f) * x, acc, 0, 0, 0);
+      }
     }
   }
   // lane (col = lane % 16, rows 4*(lane/16) .. +3) holds G[row][col]
@@ -364,12 +394,13 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
     has1 |= d.ncomp == 1;
     has2 |= d.ncomp == 2;
   }
+  const int vec_ok = aligned16(jc) && aligned16(data) && aligned16(weight);
   if (has1)
     hipLaunchKernelGGL((k_gram<1>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part,
-                       b->d_neq_first, mask);
+                       b->d_neq_first, mask, vec_ok);
   if (has2)
     hipLaunchKernelGGL((k_gram<2>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part,
-                       b->d_neq_first, mask);
+                       b->d_neq_first, mask, vec_ok);
   return hipGetLastError();
 }
 
@@ -430,84 +461,113 @@ __global__ void k_lm_clip(int64_t n_par, double *__restrict__ theta, const doubl
   theta_t[i] = v;
 }
 
-// Solve for one stamp per wave.  When the Jacobian is new, A = G[0..P-1][0..P-1]
-// (symmetrised from the lower triangle), g = G[0..P-1][P] are kept in Ag.
-// Then the wave factors the damped system over the free parameters by a
-// Cholesky in which lane i keeps row i in registers and the finished rows are
-// broadcast through LDS (only wave-level ordering is needed); lane 0 does the two triangular solves in
-// FP64 and writes the clipped trial point.  Block 0 also clears the count of
-// active stamps that the update kernel of this iteration fills.
-constexpr int kSolveThreads = 64;
-constexpr int kReduceThreads = 1024;
-
-// FP64 sums of the Gram partials of every stamp whose Jacobian is new: four
-// slices of 256 threads, each thread issuing its loads 32 at a time, the
-// slices combined in a fixed order.
-__global__ __launch_bounds__(kReduceThreads) void k_gram_reduce(const int32_t *__restrict__ neq_first,
-                                                                const float *__restrict__ part,
-                                                                double *__restrict__ Gsum,
-                                                                const int *__restrict__ mask) {
-  constexpr int NS = kReduceThreads / 256;
-  __shared__ double G[NS][256];
-  const int s = blockIdx.x;
-  if (mask && !mask[s]) return;
-  const int tid = threadIdx.x, e = tid & 255, sl = tid >> 8;
-  const int u0 = neq_first[s], u1 = neq_first[s + 1];
-  double acc = 0.0;
-  const float *pe = part + e;
-  for (int ub = u0 + sl; ub < u1; ub += 32 * NS) {
-    // straight-line loads from clamped addresses; out-of-range ones weigh 0
-    float v[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) v[q] = pe[(int64_t)min(ub + q * NS, u1 - 1) * 256];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) acc += (ub + q * NS < u1) ? (double)v[q] : 0.0;
-  }
-  G[sl][e] = acc;
-  __syncthreads();
-  if (tid < 256) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < NS; ++q) t += G[q][tid];
-    Gsum[(int64_t)s * 256 + tid] = t;
-  }
+// One workgroup per active stamp.
+//  1. When the Jacobian is new, the workgroup adds the stamp's Gram partials
+//     in FP64 (16 slices of 64 threads, each thread owning four entries of
+//     the 16 x 16 block; wide loads, because one workgroup reads all of a
+//     large stamp's partials); A = G[0..P-1][0..P-1] (symmetrised from the
+//     lower triangle)
+//     and g = G[0..P-1][P] are kept in Ag for the later iterations that reuse
+//     this Jacobian.
+//  2. The first wave damps the system over the free parameters and factors it
+//     (Cholesky; lane i keeps row i in registers, finished rows go through
+//     LDS, so only wave-level ordering is needed), then does both triangular
+//     solves column by column, broadcasting each finished unknown from its
+//     lane.
+//  3. It writes the clipped trial point and, when asked, the component
+//     constants of the trial point.
+// Block 0 also clears the count of active stamps that the update kernel of
+// this iteration fills.
+// Value of v on lane l (l uniform over the wave).
+__device__ __forceinline__ double bcast(double v, int l) {
+  const uint64_t b = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l), hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
+
+constexpr int kSolveThreads = 1024;
+constexpr int kSolveSlices = kSolveThreads / 64;
 
 template <int NC>
 __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__restrict__ desc,
-                                                       const double *__restrict__ Gsum, LMParams prm,
+                                                       const int32_t *__restrict__ neq_first,
+                                                       const float *__restrict__ part, LMParams prm,
                                                        LMState *__restrict__ st, double *__restrict__ Ag,
                                                        const double *__restrict__ theta, double *__restrict__ theta_t,
                                                        int *__restrict__ mjac, int *__restrict__ mtrial,
                                                        int *__restrict__ active_count) {
   constexpr int P = kNPC * NC + 1;
-  __shared__ double Lr[P][P];
-  __shared__ double y[P];
-  __shared__ double dmax_s;
+  __shared__ double Gp[kSolveSlices][256];
+  __shared__ double Gs[256];
   __shared__ double As[P * P];
-  __shared__ double th_s[P], lo_s[P], hi_s[P], g_s[P];
-  __shared__ int fr_s[P];
-  __shared__ int idx[P];
-  __shared__ double tt_s[P];
-  __shared__ int nf_s, ok_s;
+  __shared__ double Lr[P][P];
+  __shared__ double th_s[P], lo_s[P], hi_s[P], g_s[P], dl_s[P], tt_s[P];
+  __shared__ int fr_s[P], idx_s[P];
+  __shared__ int ok_s;
+  __shared__ double inv_s[P];
   const int s = blockIdx.x;
   const int tid = threadIdx.x;
   if (s == 0 && tid == 0) *active_count = 0;
+  // independent loads first: descriptor, state and unit range together
   const StampDesc d = desc[s];
+  const LMState S0 = st[s];
+  const int u0 = neq_first[s], u1 = neq_first[s + 1];
   if (d.ncomp != NC) return;
-  LMState S = st[s];
+  LMState S = S0;
   if (!S.active) return;
   double *Ags = Ag + (int64_t)s * (kMaxP * kMaxP + kMaxP);
-  // A and g of this iteration in LDS: from the fresh Gram sums (and kept in
-  // Ag for later iterations) or from Ag (written by an earlier launch).
+  if (tid < P) {
+    const int64_t i = d.par + tid;
+    th_s[tid] = theta[i];
+    lo_s[tid] = prm.lo ? prm.lo[i] : -INFINITY;
+    hi_s[tid] = prm.hi ? prm.hi[i] : INFINITY;
+    fr_s[tid] = prm.free_mask ? (int)prm.free_mask[i] : 1;
+    idx_s[tid] = 0;
+    dl_s[tid] = 0.0;
+  }
+  if (S.need_jac) {
+    // slice sl (64 threads) adds units u0 + sl, u0 + sl + NS, ... in order,
+    // each thread four consecutive entries per 16-byte load, so that a large
+    // stamp's partials are read in one round of loads; the slices are then
+    // added in a fixed order
+    const int e4 = tid & 63, sl = tid >> 6;
+    const float *pe = part + 4 * e4;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int ub = u0 + sl; ub < u1; ub += 16 * kSolveSlices) {
+      // straight-line loads from clamped addresses; the extra ones weigh 0
+      float4 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        v[q] = *reinterpret_cast<const float4 *>(pe + (int64_t)min(ub + q * kSolveSlices, u1 - 1) * 256);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const bool in = ub + q * kSolveSlices < u1;
+        a0 += in ? (double)v[q].x : 0.0;
+        a1 += in ? (double)v[q].y : 0.0;
+        a2 += in ? (double)v[q].z : 0.0;
+        a3 += in ? (double)v[q].w : 0.0;
+      }
+    }
+    Gp[sl][4 * e4] = a0;
+    Gp[sl][4 * e4 + 1] = a1;
+    Gp[sl][4 * e4 + 2] = a2;
+    Gp[sl][4 * e4 + 3] = a3;
+    __syncthreads();
+    if (tid < 256) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSolveSlices; ++q) t += Gp[q][tid];
+      Gs[tid] = t;
+    }
+  }
+  __syncthreads();
+  if (tid >= 64) return;   // the rest is the first wave's
   {
-    // each lane moves ceil(P*P/64) entries, all loads issued before any store
-    constexpr int NE = (P * P + kSolveThreads - 1) / kSolveThreads;
-    const double *Gs = Gsum + (int64_t)s * 256;
+    constexpr int NE = (P * P + 63) / 64;
     double v[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-      const int e = min(tid + q * kSolveThreads, P * P - 1);
+      const int e = min(tid + q * 64, P * P - 1);
       const int a = e / P, b = e - a * P;
       const int hi = a > b ? a : b, lo = a > b ? b : a;
       v[q] = S.need_jac ? Gs[hi * 16 + lo] : Ags[a * kMaxP + b];
@@ -515,7 +575,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
     const double gv = S.need_jac ? Gs[min(tid, P - 1) * 16 + P] : Ags[kMaxP * kMaxP + min(tid, P - 1)];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-      const int e = tid + q * kSolveThreads;
+      const int e = tid + q * 64;
       if (e < P * P) {
         As[e] = v[q];
         if (S.need_jac) Ags[(e / P) * kMaxP + (e % P)] = v[q];
@@ -526,37 +586,25 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
       if (S.need_jac) Ags[kMaxP * kMaxP + tid] = gv;
     }
   }
-  // stage the per-parameter data through LDS with parallel loads
-  if (tid < P) {
-    const int64_t i = d.par + tid;
-    th_s[tid] = theta[i];
-    lo_s[tid] = prm.lo ? prm.lo[i] : -INFINITY;
-    hi_s[tid] = prm.hi ? prm.hi[i] : INFINITY;
-    fr_s[tid] = prm.free_mask ? (int)prm.free_mask[i] : 1;
-  }
+  if (tid == 0) ok_s = 1;
   wave_sync();
-  if (tid == 0) {
-    int nf = 0;
-    double dm = 0.0;
-    for (int p = 0; p < P; ++p)
-      if (fr_s[p]) {
-        idx[nf++] = p;
-        dm = fmax(dm, As[p * P + p]);
-      }
-    nf_s = nf;
-    dmax_s = dm;
-    ok_s = 1;
-  }
-  wave_sync();
-  const int nf = nf_s;
-  // lane i < nf holds row i of the damped matrix (later of L)
-  double row[P];
-  const bool mine = tid < nf;
+  // free parameters in order: lane i < nf works on parameter idx_s[i]
+  const bool fr = tid < P && fr_s[tid];
+  const uint64_t fm = __ballot(fr);
+  const int nf = __popcll(fm);
+  if (fr) idx_s[__popcll(fm & ((1ull << tid) - 1ull))] = tid;
+  double dmax = fr ? As[tid * P + tid] : 0.0;
 #pragma unroll
-  for (int k = 0; k < P; ++k) row[k] = (mine && k < nf) ? As[idx[tid] * P + idx[k]] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+  wave_sync();
+  const bool mine = tid < nf;
+  const int my = mine ? idx_s[tid] : 0;
+  double row[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) row[k] = (mine && k < nf) ? As[my * P + idx_s[k]] : 0.0;
 #pragma unroll
   for (int k = 0; k < P; ++k)
-    if (mine && k == tid) row[k] += S.lambda * fmax(row[k], 1e-12 * dmax_s);
+    if (mine && k == tid) row[k] += S.lambda * fmax(row[k], 1e-12 * dmax);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     if (j < nf) {
@@ -565,7 +613,16 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
 #pragma unroll
         for (int k = 0; k < j; ++k) sj -= row[k] * row[k];
         if (!(sj > 0.0) || !isfinite(sj)) ok_s = 0;
-        row[j] = sqrt(fmax(sj, 0.0));
+        // 1/sqrt(sj) from the hardware estimate and three Newton steps
+        // (quadratic convergence: full FP64 precision from any estimate good
+        // to 2^-8), shorter on this serial path than a square root and a
+        // division
+        const double a = fmax(sj, 1e-300);
+        double r = __builtin_amdgcn_rsq(a);
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt) r = r * fma(-0.5 * a * r, r, 1.5);
+        row[j] = a * r;
+        inv_s[j] = r;
 #pragma unroll
         for (int k = 0; k <= j; ++k) Lr[j][k] = row[k];
       }
@@ -574,10 +631,39 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
         double t = row[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) t -= row[k] * Lr[j][k];
-        row[j] = t / Lr[j][j];
+        row[j] = t * inv_s[j];
       }
       wave_sync();
     }
+  }
+  const bool ok = ok_s != 0;
+  if (ok) {
+    // L y = g: lane i holds the running right-hand side of row i; y_j is
+    // final on lane j once columns 0..j-1 are subtracted.
+    double t = mine ? g_s[my] : 0.0;
+    double y = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j < nf) {
+        const double yj = bcast(t, j) * inv_s[j];
+        if (tid == j) y = yj;
+        if (mine && tid > j) t -= row[j] * yj;
+      }
+    }
+    // L^T x = y: lane k needs column k of L, L[i][k] for i >= k.
+    double col[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) col[i] = (mine && i < nf && tid <= i) ? Lr[i][tid] : 0.0;
+    double u = y, x = 0.0;
+#pragma unroll
+    for (int i = P - 1; i >= 0; --i) {
+      if (i < nf) {
+        const double xi = bcast(u, i) * inv_s[i];
+        if (tid == i) x = xi;
+        if (mine && tid < i) u -= col[i] * xi;
+      }
+    }
+    if (mine) dl_s[my] = x;
   }
   if (tid == 0) {
     S.iters += 1;
@@ -586,7 +672,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
       S.njev += 1;
     }
     mjac[s] = 0;
-    if (!ok_s) {
+    if (!ok) {
       S.lambda *= prm.lambda_up;
       S.trial = 0;
       mtrial[s] = 0;
@@ -596,16 +682,6 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
         S.reason = 4;
       }
     } else {
-      for (int i = 0; i < nf; ++i) {
-        double t = g_s[idx[i]];
-        for (int k = 0; k < i; ++k) t -= Lr[i][k] * y[k];
-        y[i] = t / Lr[i][i];
-      }
-      for (int i = nf - 1; i >= 0; --i) {
-        double t = y[i];
-        for (int k = i + 1; k < nf; ++k) t -= Lr[k][i] * y[k];
-        y[i] = t / Lr[i][i];
-      }
       S.trial = 1;
       mtrial[s] = 1;
     }
@@ -613,18 +689,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
   }
   wave_sync();
   // trial point theta' = clip(theta + delta) on the free parameters
-  if (ok_s && tid < P) {
-    int a = -1;
-    for (int q = 0; q < nf; ++q)
-      if (idx[q] == tid) a = q;
+  if (ok && tid < P) {
     double v = th_s[tid];
-    if (a >= 0) v = fmin(fmax(v + y[a], lo_s[tid]), hi_s[tid]);
+    if (fr) v = fmin(fmax(v + dl_s[tid], lo_s[tid]), hi_s[tid]);
     theta_t[d.par + tid] = v;
     tt_s[tid] = v;
   }
   if (prm.cc_t) {
     wave_sync();
-    if (ok_s && tid < NC)
+    if (ok && tid < NC)
       comp_setup<double>(tt_s + kNPC * tid, prm.bn, prm.oversample, prm.cc_t[(int64_t)s * kMaxComp + tid]);
   }
 }
@@ -800,13 +873,9 @@ hipError_t launch_lm_clip(hipStream_t st, int64_t n_par, double *theta, const do
   return hipGetLastError();
 }
 
-hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, double *Gsum, const gf_lm_opts *o,
-                           LMState *S, double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial,
-                           int *cnt, CompC *cc_th, CompC *cc_t, const float4 *bn) {
-  {
-    ProfScope ps(st, "k_gram_reduce");
-    hipLaunchKernelGGL(k_gram_reduce, dim3(b->n), dim3(kReduceThreads), 0, st, b->d_neq_first, part, Gsum, mjac);
-  }
+hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, const gf_lm_opts *o, LMState *S,
+                           double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial, int *cnt,
+                           CompC *cc_th, CompC *cc_t, const float4 *bn) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask, cc_t, cc_th, bn, o->oversample};
   ProfScope ps(st, "k_lm_solve");
@@ -816,11 +885,11 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
     has2 |= d.ncomp == 2;
   }
   if (has1)
-    hipLaunchKernelGGL((k_lm_solve<1>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, Gsum, prm, S, Ag, theta,
-                       theta_t, mjac, mtrial, cnt);
+    hipLaunchKernelGGL((k_lm_solve<1>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
+                       prm, S, Ag, theta, theta_t, mjac, mtrial, cnt);
   if (has2)
-    hipLaunchKernelGGL((k_lm_solve<2>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, Gsum, prm, S, Ag, theta,
-                       theta_t, mjac, mtrial, cnt);
+    hipLaunchKernelGGL((k_lm_solve<2>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
+                       prm, S, Ag, theta, theta_t, mjac, mtrial, cnt);
   return hipGetLastError();
 }
 
