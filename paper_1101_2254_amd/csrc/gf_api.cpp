@@ -22,7 +22,7 @@ hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int,
 hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float4 *, const float *,
                                    float *);
 hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
-                           float *, const int *, const WorkView *);
+                           float *, const int *, const WorkView *, const Chi2Epi *ep = nullptr);
 hipError_t launch_fft_corr(hipStream_t, const gf_batch *, const gf_psf *, const float *, float2 *, float2 *, float *);
 hipError_t launch_fft_otf(hipStream_t, const gf_batch *, const gf_psf *, const float *, const Work *, int,
                           const Work *, int, const int64_t *, float2 *, const int64_t *);
@@ -41,17 +41,18 @@ hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *,
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *);
-hipError_t launch_chi2_part(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float2 *, const int *, const WorkView *);
-hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const float2 *, LMState *, double *,
-                            const double *, int *, int *, int *, CompC *, CompC *);
+hipError_t launch_chi2_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, const void *, bool,
+                              const float *, const float *, float2 *, const int *, const WorkView *);
+hipError_t launch_pair_final(hipStream_t, int, const int32_t *, const float2 *, float2 *, const int *);
+hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const int32_t *, const float2 *,
+                            LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
 hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
 hipError_t launch_nm_init(hipStream_t, const gf_batch *, const double *, const double *, const gf_simplex_opts *,
                           double *, double *, void *, int *, int *);
-hipError_t launch_nm_step(hipStream_t, const gf_batch *, const float2 *, const gf_simplex_opts *, void *, double *,
-                          double *, double *, double *, int *, double *, int, int *);
+hipError_t launch_nm_step(hipStream_t, const gf_batch *, const int32_t *, const float2 *, const gf_simplex_opts *,
+                          void *, double *, double *, double *, double *, int *, double *, int, int *);
 hipError_t launch_nm_result(hipStream_t, const gf_batch *, const void *, const double *, const double *, double *,
                             gf_lm_result *);
 hipError_t launch_nm_zero(hipStream_t, int *);
@@ -59,7 +60,8 @@ size_t nm_state_bytes();
 hipError_t launch_mcmc_propose(hipStream_t, const gf_batch *, const double *, const double *, const double *,
                                const double *, uint64_t, uint64_t, uint64_t, int64_t, const int64_t *, double *, int *);
 hipError_t launch_mcmc_init(hipStream_t, int, const float2 *, double *, int64_t *);
-hipError_t launch_mcmc_accept(hipStream_t, const gf_batch *, const float2 *, const int *, uint64_t, uint64_t,
+hipError_t launch_mcmc_accept(hipStream_t, const gf_batch *, const int32_t *, const float2 *, const int *, uint64_t,
+                              uint64_t,
                               uint64_t, int64_t, int64_t *, double *, const double *, double *, int32_t *, float *,
                               int);
 }  // namespace gf
@@ -209,6 +211,24 @@ FftPlan make_plan(int L, int tw_off) {
 
 
 int padded_P(int nc) { return kNPC * nc + 1; }
+
+// Steps 2-3 for a one-channel padded model, chi^2 partials only: every stamp
+// in mask gets its partials at p->d_c2_first (FFT stamps from the inverse-row
+// pass, which writes no model image; direct stamps from the direct
+// convolution into mconv and the chi^2 kernel).
+hipError_t conv_chi2(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *mpad, float2 *S1, float2 *S2,
+                     float *mconv, const void *theta, bool theta_f64, const float *data, const float *weight,
+                     float2 *part, const int *mask, const WorkView *v) {
+  const Chi2Epi ep{data, weight, theta, theta_f64 ? 1 : 0, p->d_c2_first, part};
+  hipError_t e = launch_fft_conv(st, b, p, mpad, 1, S1, S2, mconv, mask, v, &ep);
+  if (e == hipSuccess) e = launch_direct(st, b, p, mpad, 1, mconv, false, mask, v);
+  if (e == hipSuccess) e = launch_chi2_direct(st, b, p, mconv, theta, theta_f64, data, weight, part, mask, v);
+  return e;
+}
+
+// Partial slots of a chi^2 buffer that serves both layouts (per kPixChunk
+// pixels and per conv_chi2 slot).
+int64_t chi2_slots(const gf_batch *b, const gf_psf *p) { return std::max<int64_t>((int64_t)b->h_pix.size(), p->n_c2); }
 
 }  // namespace
 
@@ -492,6 +512,14 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     pd.plan = -1;
     pd.pad0 = 0;
     pd.otf = 0;
+    p->h_c2_first.push_back((int32_t)p->n_c2);
+    if (!fft) {
+      const int np = (d.H * d.W + kPixChunk - 1) / kPixChunk;
+      for (int u = 0; u < np; ++u) p->h_pix_direct.push_back({s, u});
+      p->n_c2 += np;
+    } else {
+      p->n_c2 += (d.H + 1) / 2;
+    }
     if (!fft) {
       ++p->n_direct;
       const int tx = (d.W + kDirectTW - 1) / kDirectTW, ty = (d.H + kDirectTH - 1) / kDirectTH;
@@ -554,6 +582,11 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
       pd.otf = hit->second;   // stamps sharing a PSF (same group) share its OTF
     }
   }
+  p->h_c2_first.push_back((int32_t)p->n_c2);
+  if (p->n_c2 > 0x7fffffff) {
+    delete p;
+    return fail(c, GF_ESHAPE, "gf_psf_prepare: batch too large");
+  }
   hipError_t e = hipSuccess;
   Work *d_orows = nullptr, *d_ocols = nullptr;
   int64_t *d_otmp = nullptr, *d_ooff = nullptr;
@@ -575,6 +608,8 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   if (e == hipSuccess) e = upload(&p->d_s2a, p->h_s2a);
   if (e == hipSuccess) e = upload(&p->d_direct, p->h_direct);
   if (e == hipSuccess) e = upload(&p->d_adirect, p->h_adirect);
+  if (e == hipSuccess) e = upload(&p->d_c2_first, p->h_c2_first);
+  if (e == hipSuccess) e = upload(&p->d_pix_direct, p->h_pix_direct);
   if (e == hipSuccess) e = upload(&d_orows, otf_rows);
   if (e == hipSuccess) e = upload(&d_ocols, otf_cols);
   if (e == hipSuccess) e = upload(&d_otmp, otf_tmp);
@@ -631,6 +666,8 @@ void gf_psf_destroy(gf_psf *p) {
   dfree(p->d_s2a);
   dfree(p->d_direct);
   dfree(p->d_adirect);
+  dfree(p->d_c2_first);
+  dfree(p->d_pix_direct);
   delete p;
 }
 
@@ -699,7 +736,7 @@ static void likelihood_layout(const gf_batch *b, const gf_psf *p, Arena &a, floa
   *mconv = a.take<float>(b->n_pix);
   *S1 = a.take<float2>(p->n_s1);
   *S2 = a.take<float2>(p->n_s2);
-  *part = a.take<float2>((int64_t)b->h_pix.size());
+  *part = a.take<float2>(chi2_slots(b, p));
 }
 
 int64_t gf_likelihood_workspace(const gf_batch *b, const gf_psf *p) {
@@ -729,10 +766,8 @@ gf_status gf_likelihood(gf_ctx *c, const gf_batch *b, const gf_psf *p, const flo
   float2 *S1, *S2, *part;
   likelihood_layout(b, p, a, &mpad, &mconv, &S1, &S2, &part);
   GF_TRY(c, launch_eval(c->stream, b, theta, S, c->d_bn, mpad, nullptr));
-  st = convolve(c, b, p, mpad, 1, mconv, S1, S2, nullptr);
-  if (st != GF_OK) return st;
-  GF_TRY(c, launch_chi2(c->stream, b, mconv, theta, false, data, weight, nullptr, part, c->d_counters,
-                        (float2 *)chi2, nullptr));
+  GF_TRY(c, conv_chi2(c->stream, b, p, mpad, S1, S2, mconv, theta, false, data, weight, part, nullptr, nullptr));
+  GF_TRY(c, launch_pair_final(c->stream, b->n, p->d_c2_first, part, (float2 *)chi2, nullptr));
   return GF_OK;
 }
 
@@ -844,14 +879,15 @@ struct LMBufs {
 
 int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
   return (int64_t)b->h_eval.size() + b->h_pix.size() + b->h_neq.size() + p->h_rows.size() + p->h_cols.size() +
-         p->h_irows.size() + p->h_rows_n.size() + p->h_cols_n.size() + p->h_irows_n.size() + p->h_direct.size();
+         p->h_irows.size() + p->h_rows_n.size() + p->h_cols_n.size() + p->h_irows_n.size() + p->h_direct.size() +
+         p->h_pix_direct.size();
 }
 
 // Work lists restricted to the stamps flagged in act, filtered from `from`
 // (the previous restriction, or the full lists when `from` is empty), stored
 // in `to` and uploaded into dev; the view points into dev.
 struct HostLists {
-  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct;
+  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct, pix_direct;
   bool empty() const { return eval.empty() && pix.empty(); }
 };
 
@@ -875,6 +911,7 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   filt(full ? p->h_cols_n : from.cols_n, to.cols_n);
   filt(full ? p->h_irows_n : from.irows_n, to.irows_n);
   filt(full ? p->h_direct : from.direct, to.direct);
+  filt(full ? p->h_pix_direct : from.pix_direct, to.pix_direct);
   Work *q = dev;
   auto put = [&](const std::vector<Work> &src, const Work *&ptr, int &n) -> hipError_t {
     ptr = q;
@@ -897,6 +934,7 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   if (e == hipSuccess) e = put(to.cols_n, v.cols_n, v.n_cols_n);
   if (e == hipSuccess) e = put(to.irows_n, v.irows_n, v.n_irows_n);
   if (e == hipSuccess) e = put(to.direct, v.direct, v.n_direct);
+  if (e == hipSuccess) e = put(to.pix_direct, v.pix_direct, v.n_pix_direct);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors must outlive the copies
   return e;
 }
@@ -912,7 +950,7 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.mpad = a.take<float>(b->n_pad);
   B.mconv = a.take<float>(b->n_pix);
   B.chi2t = a.take<float2>(b->n);
-  B.cpart = a.take<float2>((int64_t)b->h_pix.size());
+  B.cpart = a.take<float2>(chi2_slots(b, p));
   B.st = a.take<LMState>(b->n);
   B.mjac = a.take<int>(b->n);
   B.mtrial = a.take<int>(b->n);
@@ -968,10 +1006,9 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     // start point: clip, evaluate, chi2
     GF_TRY(c, launch_lm_clip(cs, b->n_par, theta, o.lo, o.hi, B.theta_t));
     GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, true));
-    GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, nullptr, nullptr));
-    GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, nullptr, nullptr));
-    GF_TRY(c, launch_chi2(cs, b, B.mconv, B.theta_t, true, data, weight, nullptr, B.cpart, c->d_counters, B.chi2t,
-                          nullptr));
+    GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
+                        nullptr));
+    GF_TRY(c, launch_pair_final(cs, b->n, p->d_c2_first, B.cpart, B.chi2t, nullptr));
     GF_TRY(c, launch_lm_init(cs, b, o.lambda0, B.chi2t, B.st, B.mjac, B.mtrial, B.cnt));
     WorkView view;
     const WorkView *vw = nullptr;   // null: the full lists
@@ -985,11 +1022,10 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
                                 B.cc_t, c->d_bn));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.mpad, 1, B.S1, B.S2, B.mconv, B.mtrial, vw));
-      GF_TRY(c, launch_direct(cs, b, p, B.mpad, 1, B.mconv, false, B.mtrial, vw));
-      GF_TRY(c, launch_chi2_part(cs, b, B.mconv, B.theta_t, data, weight, B.cpart, B.mtrial, vw));
-      GF_TRY(c, launch_lm_update(cs, b, &o, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
-                                 B.cc_t));
+      GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
+                          vw));
+      GF_TRY(c, launch_lm_update(cs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
+                                 B.cnt, B.cc_th, B.cc_t));
       return GF_OK;
     };
     auto capture = [&]() -> gf_status {
@@ -1042,6 +1078,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           cur.cols_n.swap(nxt.cols_n);
           cur.irows_n.swap(nxt.irows_n);
           cur.direct.swap(nxt.direct);
+          cur.pix_direct.swap(nxt.pix_direct);
           vw = &view;
           view_stamps = active;
           if (exec) {
@@ -1116,7 +1153,7 @@ gf_status gf_fit_simplex(gf_ctx *c, const gf_batch *b, const gf_psf *p, const fl
     mconv = ar.take<float>(b->n_pix);
     S1 = ar.take<float2>(p->n_s1);
     S2 = ar.take<float2>(p->n_s2);
-    cpart = ar.take<float2>((int64_t)b->h_pix.size());
+    cpart = ar.take<float2>(chi2_slots(b, p));
     mask = ar.take<int>(b->n);
     cnt = ar.take<int>(16);
     state = ar.take<char>((int64_t)b->n * (int64_t)nm_state_bytes());
@@ -1147,10 +1184,9 @@ gf_status gf_fit_simplex(gf_ctx *c, const gf_batch *b, const gf_psf *p, const fl
     auto iteration = [&]() -> gf_status {
       GF_TRY(c, launch_nm_zero(cs, cnt));
       GF_TRY(c, launch_eval_d(cs, b, theta_t, S, c->d_bn, mpad, mask, nullptr));
-      GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, mask, nullptr));
-      GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, mask, nullptr));
-      GF_TRY(c, launch_chi2_part(cs, b, mconv, theta_t, data, weight, cpart, mask, nullptr));
-      GF_TRY(c, launch_nm_step(cs, b, cpart, &o, state, X, F, XR, theta_t, mask, trace, trace_cap, cnt));
+      GF_TRY(c, conv_chi2(cs, b, p, mpad, S1, S2, mconv, theta_t, true, data, weight, cpart, mask, nullptr));
+      GF_TRY(c, launch_nm_step(cs, b, p->d_c2_first, cpart, &o, state, X, F, XR, theta_t, mask, trace, trace_cap,
+                               cnt));
       return GF_OK;
     };
     if (o.use_graph) {
@@ -1219,7 +1255,7 @@ gf_status gf_mcmc_run(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
     mconv = ar.take<float>(b->n_pix);
     S1 = ar.take<float2>(p->n_s1);
     S2 = ar.take<float2>(p->n_s2);
-    cpart = ar.take<float2>((int64_t)b->h_pix.size());
+    cpart = ar.take<float2>(chi2_slots(b, p));
     pairs = ar.take<float2>(b->n);
     mask = ar.take<int>(b->n);
     tstep = ar.take<int64_t>(1);
@@ -1235,18 +1271,15 @@ gf_status gf_mcmc_run(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
   hipStream_t cs = c->stream;
   // chi^2 of the start point
   GF_TRY(c, launch_eval_d(cs, b, theta, S, c->d_bn, mpad, nullptr, nullptr));
-  GF_TRY(c, launch_fft_conv(cs, b, p, mpad, 1, S1, S2, mconv, nullptr, nullptr));
-  GF_TRY(c, launch_direct(cs, b, p, mpad, 1, mconv, false, nullptr, nullptr));
-  GF_TRY(c, launch_chi2(cs, b, mconv, theta, true, data, weight, nullptr, cpart, c->d_counters, pairs, nullptr));
+  GF_TRY(c, conv_chi2(cs, b, p, mpad, S1, S2, mconv, theta, true, data, weight, cpart, nullptr, nullptr));
+  GF_TRY(c, launch_pair_final(cs, b->n, p->d_c2_first, cpart, pairs, nullptr));
   GF_TRY(c, launch_mcmc_init(cs, b->n, pairs, chi2_d, tstep));
   auto step = [&](hipStream_t sx) -> gf_status {
     GF_TRY(c, launch_mcmc_propose(sx, b, theta, o.scale, o.lo, o.hi, o.key0, o.key1, o.stream, o.step0, tstep,
                                   theta_t, mask));
     GF_TRY(c, launch_eval_d(sx, b, theta_t, S, c->d_bn, mpad, mask, nullptr));
-    GF_TRY(c, launch_fft_conv(sx, b, p, mpad, 1, S1, S2, mconv, mask, nullptr));
-    GF_TRY(c, launch_direct(sx, b, p, mpad, 1, mconv, false, mask, nullptr));
-    GF_TRY(c, launch_chi2_part(sx, b, mconv, theta_t, data, weight, cpart, mask, nullptr));
-    GF_TRY(c, launch_mcmc_accept(sx, b, cpart, mask, o.key0, o.key1, o.stream, o.step0, tstep, theta, theta_t, chi2_d,
+    GF_TRY(c, conv_chi2(sx, b, p, mpad, S1, S2, mconv, theta_t, true, data, weight, cpart, mask, nullptr));
+    GF_TRY(c, launch_mcmc_accept(sx, b, p->d_c2_first, cpart, mask, o.key0, o.key1, o.stream, o.step0, tstep, theta, theta_t, chi2_d,
                                  accepted, samples, o.thin));
     return GF_OK;
   };

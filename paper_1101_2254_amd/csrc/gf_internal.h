@@ -79,6 +79,8 @@ struct WorkView {
   int n_rows_n = 0, n_cols_n = 0, n_irows_n = 0;
   const Work *direct = nullptr;
   int n_direct = 0;
+  const Work *pix_direct = nullptr;
+  int n_pix_direct = 0;
 };
 
 // Per-component constants of the evaluation kernels (computed per workgroup).
@@ -94,6 +96,18 @@ struct CompC {
   float lie;         // log2(Ie)
   float ie, re, n, q, bn, dbn;
   float inv_n, inv_re, inv_q;
+};
+
+// chi^2 epilogue of the inverse-row FFT pass: the residuals of the convolved
+// model against the observation are reduced where the model rows leave LDS,
+// one compensated (hi, lo) partial per output row pair, and the model image
+// itself is not written.
+struct Chi2Epi {
+  const float *data, *weight;
+  const void *theta;        // sky of stamp s at theta[par + 7 ncomp]
+  int32_t theta_f64;        // theta is double (else float)
+  const int32_t *first;     // first partial slot of each stamp
+  float2 *part;
 };
 
 // LM per-stamp state (device).
@@ -250,5 +264,13 @@ struct gf_psf {
   // direct path tiles
   std::vector<gf::Work> h_direct, h_adirect;
   gf::Work *d_direct = nullptr, *d_adirect = nullptr;
+  // chi^2 partial slots of the fused evaluations: an FFT stamp has one per
+  // output row pair (from the inverse-row pass), a direct stamp one per
+  // kPixChunk pixels (from the chi^2 kernel over h_pix_direct)
+  std::vector<int32_t> h_c2_first;
+  int32_t *d_c2_first = nullptr;
+  int64_t n_c2 = 0;
+  std::vector<gf::Work> h_pix_direct;
+  gf::Work *d_pix_direct = nullptr;
   int n_fft = 0, n_direct = 0;
 };

@@ -24,6 +24,7 @@
 
 #include "gf_internal.h"
 #include "bufload.h"
+#include "twosum.h"
 
 namespace gf {
 
@@ -370,7 +371,8 @@ __device__ __forceinline__ void lds_fft(float2 *buf, int T, int Ls, const FftPla
 }
 
 // Geometry of one launch mode.
-enum { MODE_CONV = 0, MODE_CORR = 1, MODE_OTF = 2 };
+// MODE_CHI2 is MODE_CONV whose inverse-row pass ends in the chi^2 epilogue.
+enum { MODE_CONV = 0, MODE_CORR = 1, MODE_OTF = 2, MODE_CHI2 = 3 };
 
 struct Geo {
   int in_rows, in_cols, in_col0;   // row pass input (cols placed at in_col0 on the L grid)
@@ -382,7 +384,7 @@ struct Geo {
 __device__ __forceinline__ Geo geo_of(int mode, const StampDesc &d, int L) {
   Geo g;
   const int km1 = d.K - 1;
-  if (mode == MODE_CONV) {
+  if (mode == MODE_CONV || mode == MODE_CHI2) {
     g.in_rows = d.Mh; g.in_cols = d.Mw; g.in_col0 = 0; g.col_row0 = 0;
     g.out_row0 = km1; g.out_rows = d.H; g.out_col0 = km1; g.out_cols = d.W;
   } else if (mode == MODE_CORR) {
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
                                                         const Work *__restrict__ work, int n_ch,
                                                         const int64_t *__restrict__ s2_off,
                                                         const float2 *__restrict__ S2, float *__restrict__ out,
-                                                        const int *__restrict__ mask, int tmax) {
+                                                        const int *__restrict__ mask, int tmax, Chi2Epi ep) {
   extern __shared__ float2 lds[];
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
@@ -615,6 +617,68 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   }
   __syncthreads();
   lds_fft<true>(buf, T, Ls, pl, tw);
+  if constexpr (MODE == MODE_CHI2) {
+    // r = sqrt(w) (d - m - sky).  All threads form the squared residuals of
+    // the workgroup's rows (every data and weight load in flight at once)
+    // and stage them in LDS; then one wave per row pair adds them, lane l
+    // taking columns l, l + 64, ... (first row, then second row, at each
+    // column), so a pair's partial does not depend on the launch shape.
+    const float sky = ep.theta_f64 ? (float)((const double *)ep.theta)[d.par + kNPC * d.ncomp]
+                                   : ((const float *)ep.theta)[d.par + kNPC * d.ncomp];
+    const uint32_t npix = (uint32_t)(d.H * d.W);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(ep.data + d.img, npix * 4u);
+    const __amdgpu_buffer_rsrc_t rw = make_rsrc(ep.weight + d.img, npix * 4u);
+    const int oc = g.out_cols, n_items = T * oc;
+    const FDiv divO(oc);
+    float da[kFftIters], wa[kFftIters], db[kFftIters], wb[kFftIters];
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      const int t = divO(idx), x = idx - t * oc;
+      const int ra = r0 + 2 * t;
+      const bool ina = idx < n_items && ra < g.out_rows, inb = ina && ra + 1 < g.out_rows;
+      const uint32_t pa = (uint32_t)(ra * oc + x) * 4u;
+      da[it] = bload_f32(rd, ina ? pa : kOutOfRange);
+      wa[it] = bload_f32(rw, ina ? pa : kOutOfRange);
+      db[it] = bload_f32(rd, inb ? pa + (uint32_t)oc * 4u : kOutOfRange);
+      wb[it] = bload_f32(rw, inb ? pa + (uint32_t)oc * 4u : kOutOfRange);
+    }
+    float2 sq[kFftIters];
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      sq[it] = make_float2(0.f, 0.f);
+      if (idx < n_items) {
+        const int t = divO(idx), x = idx - t * oc;
+        const float2 v = buf[lp(t * Ls + g.out_col0 + x)];
+        const float ea = sqrtf(wa[it]) * (da[it] - (v.x + sky));
+        const float eb = sqrtf(wb[it]) * (db[it] - (v.y + sky));
+        sq[it] = make_float2(ea * ea, eb * eb);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kFftIters; ++it) {
+      const int idx = (int)threadIdx.x + it * kThreads;
+      if (idx < n_items) buf[idx] = sq[it];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int t = wv; t < T; t += kThreads / 64) {
+      const int ra = r0 + 2 * t;
+      if (ra >= g.out_rows) break;
+      const bool hb = ra + 1 < g.out_rows;
+      F2 acc = {0.f, 0.f};
+      for (int x = lane; x < oc; x += 64) {
+        const float2 q = buf[t * oc + x];
+        acc = f2_add1(acc, q.x);
+        if (hb) acc = f2_add1(acc, q.y);
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) ep.part[ep.first[s] + (ra >> 1)] = make_float2(acc.hi, acc.lo);
+    }
+    return;
+  }
   int64_t out_base = (MODE == MODE_CONV) ? d.pix : d.pad;
   float *dst = out + out_base * n_ch + (int64_t)ch * g.out_rows * g.out_cols;
   const FDiv divC(g.out_cols);
@@ -633,8 +697,12 @@ static size_t fft_lds_bytes(int max_L) { return (size_t)(kFftLds + max_L) * size
 // Small jobs (fewer than two workgroups per CU in the wide shape) use the
 // narrow shape: one row pair or two bins per workgroup, so more CUs share the
 // latency-bound work.
+// With ep (one channel only) the inverse-row pass reduces chi^2 partials
+// instead of writing out.
 hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
-                           float2 *S1, float2 *S2, float *out, const int *mask, const WorkView *v) {
+                           float2 *S1, float2 *S2, float *out, const int *mask, const WorkView *v,
+                           const Chi2Epi *ep) {
+  if (ep && n_ch != 1) return hipErrorInvalidValue;
   const bool view = v && v->rows;
   const int n_cols_w = view ? v->n_cols : (int)p->h_cols.size();
   if ((view ? v->n_rows : (int)p->h_rows.size()) == 0) return hipSuccess;
@@ -660,8 +728,12 @@ hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, c
   }
   {
     ProfScope ps(st, "k_fft_irows");
-    hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)ni, n_ch), blk, lds, st, b->d_desc, p->d_path,
-                       p->d_plans, p->d_tw, d_irows, n_ch, p->d_s2, S2, out, mask, tr);
+    if (ep)
+      hipLaunchKernelGGL((k_fft_irows<MODE_CHI2>), dim3((unsigned)ni, 1), blk, lds, st, b->d_desc, p->d_path,
+                         p->d_plans, p->d_tw, d_irows, 1, p->d_s2, S2, out, mask, tr, *ep);
+    else
+      hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)ni, n_ch), blk, lds, st, b->d_desc, p->d_path,
+                         p->d_plans, p->d_tw, d_irows, n_ch, p->d_s2, S2, out, mask, tr, Chi2Epi{});
   }
   return hipGetLastError();
 }
@@ -679,7 +751,7 @@ hipError_t launch_fft_corr(hipStream_t st, const gf_batch *b, const gf_psf *p, c
                      (const int *)nullptr, 1 << 20);
   hipLaunchKernelGGL((k_fft_irows<MODE_CORR>), dim3((unsigned)p->h_airows.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_airows, 1, p->d_s2a, S2, out, (const int *)nullptr,
-                     1 << 20);
+                     1 << 20, Chi2Epi{});
   return hipGetLastError();
 }
 

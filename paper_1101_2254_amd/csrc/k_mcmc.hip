@@ -123,12 +123,13 @@ hipError_t launch_mcmc_init(hipStream_t st, int n, const float2 *pairs, double *
   return hipGetLastError();
 }
 
-hipError_t launch_mcmc_accept(hipStream_t st, const gf_batch *b, const float2 *part, const int *mask, uint64_t k0,
+hipError_t launch_mcmc_accept(hipStream_t st, const gf_batch *b, const int32_t *first, const float2 *part,
+                              const int *mask, uint64_t k0,
                               uint64_t k1, uint64_t stream, int64_t step0, int64_t *tstep, double *theta,
                               const double *theta_t, double *chi2, int32_t *accepted, float *samples, int thin) {
   {
     ProfScope ps(st, "k_mcmc_accept");
-    hipLaunchKernelGGL(k_mcmc_accept, dim3(b->n), dim3(64), 0, st, b->d_desc, b->d_pix_first, part, mask, k0, k1,
+    hipLaunchKernelGGL(k_mcmc_accept, dim3(b->n), dim3(64), 0, st, b->d_desc, first, part, mask, k0, k1,
                        stream, step0, tstep, theta, theta_t, chi2, accepted, samples, b->n_par, thin);
   }
   hipLaunchKernelGGL(k_mcmc_tick, dim3(1), dim3(1), 0, st, tstep);

@@ -119,16 +119,31 @@ __global__ __launch_bounds__(64) void k_pair_final(const int32_t *__restrict__ f
   if (threadIdx.x == 0) out[s] = make_float2(r.hi, r.lo);
 }
 
-hipError_t launch_chi2_part(hipStream_t st, const gf_batch *b, const float *model, const double *theta,
-                            const float *data, const float *weight, float2 *part, const int *mask,
-                            const WorkView *v) {
-  const bool view = v && v->pix;
-  dim3 grid((unsigned)(view ? v->n_pix : (int)b->h_pix.size())), blk(kThreads);
-  if (grid.x == 0) return hipSuccess;
+// chi^2 partials of the direct-path stamps at their slots p->d_c2_first (the
+// FFT stamps' partials come from the inverse-row pass).
+hipError_t launch_chi2_direct(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *model,
+                              const void *theta, bool theta_f64, const float *data, const float *weight,
+                              float2 *part, const int *mask, const WorkView *v) {
+  const bool view = v && v->rows;   // a view always carries its direct chi^2 list (possibly empty)
+  const int n = view ? v->n_pix_direct : (int)p->h_pix_direct.size();
+  if (n == 0) return hipSuccess;
+  const Work *lst = view ? v->pix_direct : p->d_pix_direct;
   ProfScope ps(st, "k_chi2");
   const int vec_ok = aligned16(model) && aligned16(data) && aligned16(weight);
-  hipLaunchKernelGGL((k_chi2<double>), grid, blk, 0, st, b->d_desc, view ? v->pix : b->d_pix, model, theta, data,
-                     weight, (float *)nullptr, part, b->d_pix_first, mask, vec_ok);
+  if (theta_f64)
+    hipLaunchKernelGGL((k_chi2<double>), dim3((unsigned)n), dim3(kThreads), 0, st, b->d_desc, lst, model,
+                       (const double *)theta, data, weight, (float *)nullptr, part, p->d_c2_first, mask, vec_ok);
+  else
+    hipLaunchKernelGGL((k_chi2<float>), dim3((unsigned)n), dim3(kThreads), 0, st, b->d_desc, lst, model,
+                       (const float *)theta, data, weight, (float *)nullptr, part, p->d_c2_first, mask, vec_ok);
+  return hipGetLastError();
+}
+
+// Per-stamp (hi, lo) chi^2 from the partials [first[s], first[s+1]).
+hipError_t launch_pair_final(hipStream_t st, int n, const int32_t *first, const float2 *part, float2 *out,
+                             const int *mask) {
+  ProfScope ps(st, "k_pair_final");
+  hipLaunchKernelGGL(k_pair_final, dim3(n), dim3(64), 0, st, first, part, out, mask);
   return hipGetLastError();
 }
 
@@ -893,13 +908,13 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
   return hipGetLastError();
 }
 
-hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const float2 *part, LMState *S,
-                            double *theta, const double *theta_t, int *mjac, int *mtrial, int *cnt, CompC *cc_th,
-                            CompC *cc_t) {
+hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const int32_t *first,
+                            const float2 *part, LMState *S, double *theta, const double *theta_t, int *mjac,
+                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask, cc_t, cc_th, nullptr, o->oversample};
   ProfScope ps(st, "k_lm_update");
-  hipLaunchKernelGGL(k_lm_update, dim3(b->n), dim3(64), 0, st, b->d_desc, b->d_pix_first, part, prm, S, theta,
+  hipLaunchKernelGGL(k_lm_update, dim3(b->n), dim3(64), 0, st, b->d_desc, first, part, prm, S, theta,
                      theta_t, mjac, mtrial, cnt);
   return hipGetLastError();
 }

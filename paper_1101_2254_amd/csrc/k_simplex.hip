@@ -280,12 +280,13 @@ hipError_t launch_nm_init(hipStream_t st, const gf_batch *b, const double *theta
   return hipGetLastError();
 }
 
-hipError_t launch_nm_step(hipStream_t st, const gf_batch *b, const float2 *part, const gf_simplex_opts *o, void *S,
+hipError_t launch_nm_step(hipStream_t st, const gf_batch *b, const int32_t *first, const float2 *part,
+                          const gf_simplex_opts *o, void *S,
                           double *X, double *F, double *XR, double *theta_t, int *mask, double *trace, int trace_cap,
                           int *cnt) {
   NMParams prm{o->max_iter, o->ftol, o->lo, o->hi};
   ProfScope ps(st, "k_nm_step");
-  hipLaunchKernelGGL(k_nm_step, dim3(b->n), dim3(64), 0, st, b->d_desc, b->d_pix_first, part, prm, (NMState *)S, X,
+  hipLaunchKernelGGL(k_nm_step, dim3(b->n), dim3(64), 0, st, b->d_desc, first, part, prm, (NMState *)S, X,
                      F, XR, theta_t, mask, trace, trace_cap, cnt);
   return hipGetLastError();
 }
