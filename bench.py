@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
     ap.add_argument("--train-stamps", type=int, default=200_000, help="C5: rendered training stamps")
     ap.add_argument("--epochs", type=int, default=4, help="C5: training epochs")
+    ap.add_argument("--mcmc-steps", type=int, default=2000, help="C4: Metropolis steps of the chain run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--breakdown", action="store_true", help="print the per-kernel breakdown to stderr")
@@ -80,6 +81,9 @@ def kernel_work(name, geo, launches_per_step):
         return "hbm", npix * 4 + geo.get("nimg", npix) * 8, "byte"
     if name == "k_gram":
         return "hbm", npix * (4 * nch + 8), "byte"
+    if name == "k_fft_irows_chi2":
+        # inverse rows of the spectra in, data and weight per distinct image
+        return "hbm", geo.get("chan_" + name, 1) * H * Lh * 8 + geo.get("nimg", npix) * 8, "byte"
     if name in ("k_fft_rows", "k_fft_cols", "k_fft_irows") and "fft_bytes" in geo:
         per_ch, once = geo["fft_bytes"][name]
         return "hbm", geo.get("chan_" + name, 1) * per_ch + once, "byte"
@@ -267,7 +271,7 @@ def run_c4(args, torch, ops, synth):
     npix = 256 * 256 * nvec
     # Metropolis chains on the same batch: one chain per vector, started from
     # this step's vectors, 2000 steps (each step = steps 1-3 for all chains)
-    n_mc = 2000
+    n_mc = args.mcmc_steps
     scale = torch.from_numpy(np.tile(np.abs(base.truth) * 1e-4 + 1e-6, nvec)).to(dev)
     lo_b, hi_b = synth.bounds(1, 256, 256)
     lo_m = torch.from_numpy(np.tile(lo_b, nvec)).to(dev)
@@ -421,35 +425,30 @@ def run_c5(args, torch, ops, synth):
 # channels per launch.  Valid only while the kernel source is the one the
 # counters were taken on (first 16 hex digits of its SHA-256).
 TRAFFIC = {
-    "c2": dict(kernel="k_fft_cols", source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="8c237da2a3e93720",
-               once=1.18e6, per_channel=3.232e6, summary="profiles/c2_fit_hbm_traffic.md"),
-    "c4": dict(kernel="k_eval", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="8dce2d07f7f0e404",
-               once=383.98e6, per_channel=0.0, summary="profiles/c4_likelihood_hbm_traffic.md"),
+    "c2": dict(kernel="k_fft_cols", source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="051ea263b03c9a32",
+               once=1.147e6, per_channel=3.233e6, summary="profiles/c2_fit_hbm_traffic.md"),
+    "c4": dict(kernel="k_eval", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="922a17b603d19fb7",
+               once=386.24e6, per_channel=0.0, summary="profiles/c4_likelihood_hbm_traffic.md"),
 }
 
 
 def stage_roofline(prof, geo):
-    """Steps 2 and 3 as whole stages, with the algorithmic bytes of their
-    definitions: convolution = read the padded model + write the stamp per
-    channel + the OTF once; chi^2 = read model, data and weight (data and
-    weight once per distinct image).  The FFT's own spectra traffic is not
-    counted here (it is in the per-kernel figures of `stages`)."""
+    """Steps 2 and 3 of the likelihood batch as one fused stage (the chi^2
+    is reduced in the inverse-row FFT pass, so the convolved model never
+    reaches HBM), with the algorithmic bytes of its definition: read the
+    padded model, data and weight once per distinct image, the OTF once.
+    The FFT's own spectra traffic is not counted here (it is in the
+    per-kernel figures of `stages`)."""
     out = {}
     L = geo.get("L", 0)
-    if L > 2 and all(k in prof for k in ("k_fft_rows", "k_fft_cols", "k_fft_irows")):
+    ks = ("k_fft_rows", "k_fft_cols", "k_fft_irows_chi2")
+    if L > 2 and all(k in prof for k in ks):
         n = prof["k_fft_rows"][0]
-        t = sum(prof[k][1] / prof[k][0] for k in ("k_fft_rows", "k_fft_cols", "k_fft_irows")) * 1e-3
-        ch = geo.get("chan_k_fft_rows", 1)
-        b = ch * (4 * geo["npad"] + 4 * geo["npix"]) + L * (L // 2 + 1) * 8
-        out["convolution"] = dict(kernels=["k_fft_rows", "k_fft_cols", "k_fft_irows"], launches=n,
-                                  bytes_per_launch=int(b), us_per_launch=round(t * 1e6, 2),
-                                  gbs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
-    if "k_chi2" in prof:
-        n, ms = prof["k_chi2"]
-        t = ms / n * 1e-3
-        b = 4 * geo["npix"] + 8 * geo.get("nimg", geo["npix"])
-        out["chi2"] = dict(kernels=["k_chi2"], launches=n, bytes_per_launch=int(b), us_per_launch=round(t * 1e6, 2),
-                           gbs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
+        t = sum(prof[k][1] / prof[k][0] for k in ks) * 1e-3
+        b = 4 * geo["npad"] + 8 * geo.get("nimg", geo["npix"]) + L * (L // 2 + 1) * 8
+        out["convolution_chi2"] = dict(kernels=list(ks), launches=n, bytes_per_launch=int(b),
+                                       us_per_launch=round(t * 1e6, 2), gbs=round(b / t / 1e9, 1),
+                                       frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
     return out
 
 
@@ -657,18 +656,22 @@ def main():
         result, prof, geo, extra = run_c5(args, torch, ops, synth)
     else:
         result, prof, geo, extra = run_c4(args, torch, ops, synth)
-    geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = 1
+    geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = geo["chan_k_fft_irows_chi2"] = 1
     if args.workload in ("c2", "c3", "c5"):
-        # per fit the FFT passes run 7 n_comp channels (Jacobian) and 1 channel (trial) per launch: use the average
+        # per fit the row and column passes run 7 n_comp channels (Jacobian)
+        # and 1 channel (trial) per launch: use the average; the plain
+        # inverse-row pass runs only for the Jacobian, the fused one only for
+        # the trial points
         n_jac = extra["njev"]
         n_trial = extra["nfev"]
         nch = 14 if args.workload == "c2" else 7
         avg = (nch * n_jac + 1 * n_trial) / max(n_jac + n_trial, 1)
-        for k in ("rows", "cols", "irows"):
+        for k in ("rows", "cols"):
             geo["chan_k_fft_" + k] = avg
+        geo["chan_k_fft_irows"] = nch
     rl, stages = roofline(prof, geo)
     rl["traffic"] = measured_traffic(args.workload, rl, geo)
-    stage_rl = stage_roofline(prof, geo) if args.workload in ("c2", "c4") else {}
+    stage_rl = stage_roofline(prof, geo) if args.workload == "c4" else {}
     if rl["traffic"] is not None:
         rl["traffic_source"] = TRAFFIC[args.workload]["summary"]
     if args.workload in ("c3", "c5"):

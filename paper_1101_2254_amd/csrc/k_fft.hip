@@ -727,7 +727,7 @@ hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, c
                        p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
   }
   {
-    ProfScope ps(st, "k_fft_irows");
+    ProfScope ps(st, ep ? "k_fft_irows_chi2" : "k_fft_irows");
     if (ep)
       hipLaunchKernelGGL((k_fft_irows<MODE_CHI2>), dim3((unsigned)ni, 1), blk, lds, st, b->d_desc, p->d_path,
                          p->d_plans, p->d_tw, d_irows, 1, p->d_s2, S2, out, mask, tr, *ep);
