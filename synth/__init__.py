@@ -243,3 +243,83 @@ def c4_vectors(step: int, n_vec: int = 1024) -> np.ndarray:
     th[:, 6] = truth[6] + 0.05 * math.pi * z[:, 6]
     th[:, 5] = np.clip(th[:, 5], 0.05, 1.0)
     return th
+
+
+# ------------------------------------------------------------ spectral lines
+# Spectra for the 1-D line-fitting family: N channels, 1..3 Gaussian emission
+# lines [A, mu, sigma] (peak, centre and width in channels) plus a constant
+# continuum, a K-tap Gaussian line-spread function.  Shaped like integral-
+# field or long-slit spectra around a few emission lines.
+LINE_SIZES = (256, 512, 1024, 2048)
+
+
+def gaussian_lsf(K: int, sigma: float) -> np.ndarray:
+    """K taps of a Gaussian sampled at integer offsets from the centre tap,
+    unit sum (float64)."""
+    if K % 2 == 0:
+        raise ValueError("LSF length must be odd")
+    x = np.arange(K, dtype=np.float64) - (K - 1) / 2
+    v = np.exp(-x * x / (2.0 * sigma * sigma))
+    return v / v.sum()
+
+
+@dataclass
+class Spectrum:
+    N: int
+    lsf: np.ndarray
+    truth: np.ndarray
+    start: np.ndarray
+    noise_sigma: float
+    noise_seed: int
+
+    @property
+    def K(self) -> int:
+        return int(self.lsf.size)
+
+    @property
+    def nlines(self) -> int:
+        return (self.truth.size - 1) // 3
+
+
+def line_spectrum(g: np.random.Generator, N: int, nlines: int, idx: int, seed: int) -> Spectrum:
+    """Lines with A ~ log-U[0.5, 5], mu ~ U[0.15 N, 0.85 N], sigma ~ U[1.5, 6];
+    continuum ~ U[0, 0.5]; LSF K ~ U{7, 9, ..., 21}, sigma_lsf ~ U[0.8, 2.5];
+    noise sigma 0.05.  Start: A and sigma x (1 + U[-0.2, 0.2]), mu + U[-0.5, 0.5]
+    sigma, continuum + U[-0.05, 0.05]."""
+    t, s = [], []
+    for _ in range(nlines):
+        a = math.exp(g.uniform(math.log(0.5), math.log(5.0)))
+        mu = g.uniform(0.15 * N, 0.85 * N)
+        sg = g.uniform(1.5, 6.0)
+        t += [a, mu, sg]
+        s += [a * (1.0 + g.uniform(-0.2, 0.2)), mu + g.uniform(-0.5, 0.5) * sg, sg * (1.0 + g.uniform(-0.2, 0.2))]
+    cont = g.uniform(0.0, 0.5)
+    t.append(cont)
+    s.append(cont + g.uniform(-0.05, 0.05))
+    K = int(g.choice(np.arange(7, 22, 2)))
+    lsf = gaussian_lsf(K, g.uniform(0.8, 2.5))
+    return Spectrum(N, lsf, np.array(t), np.array(s), 0.05, seed * 100003 + idx)
+
+
+def line_batch(n: int, seed: int = SEED_BASE + 6, sizes=LINE_SIZES):
+    g = rng(seed)
+    return [line_spectrum(g, int(g.choice(sizes)), int(g.integers(1, 4)), i, seed) for i in range(n)]
+
+
+def line_bounds(nlines: int, N: int):
+    """A in [0, 1e30], mu in [0, N - 1], sigma in [0.3, N / 4], continuum free."""
+    lo, hi = [], []
+    for _ in range(nlines):
+        lo += [0.0, 0.0, 0.3]
+        hi += [1e30, N - 1.0, N / 4.0]
+    lo.append(-1e30)
+    hi.append(1e30)
+    return np.array(lo), np.array(hi)
+
+
+def add_noise_1d(model_true: np.ndarray, sigma: float, seed: int):
+    """Observation and inverse-variance weights for a 1-D model."""
+    g = rng(seed)
+    d = model_true + sigma * g.standard_normal(model_true.shape)
+    w = np.full(model_true.shape, 1.0 / (sigma * sigma))
+    return d, w
