@@ -69,6 +69,8 @@ typedef enum {
 #define GF_MAX_K 129       /* largest PSF side */
 #define GF_MAX_FFT 2048    /* largest FFT side; stamps need H+K-1, W+K-1 <= this */
 #define GF_MAX_OVERSAMPLE 8
+#define GF_LINE_MAX_K 65       /* longest line-spread function (odd) */
+#define GF_LINE_MAX_LINES 3    /* Gaussian lines per spectrum */
 
 /* Convolution path of a prepared PSF. */
 #define GF_CONV_AUTO 0     /* chosen per stamp from the PSF and grid size */
@@ -451,6 +453,50 @@ gf_status gf_profile_get(gf_ctx *ctx, int i, char *name, int name_cap, int64_t *
  *   kind 2: four chains of exp2(log2(x) a) (hardware transcendentals) of n
  *           steps per thread; result = 10^9 transcendental operations/s. */
 gf_status gf_probe(gf_ctx *ctx, int kind, int64_t n, int reps, double *result);
+
+/* ------------------------------------------------ spectral-line fitting */
+
+/* The same three steps in one dimension (paper Sec. 5: spectral-line fitting
+ * as the next problem for the method once the dimensionality may change).
+ * Model of a spectrum of N channels (the readings of the image model, in
+ * 1-D): channel i is centred at x = i and is the mean of S sub-samples at
+ * x = i + (s + 1/2)/S - 1/2 of  sum_k A_k exp(-(x - mu_k)^2 / (2 sigma_k^2)),
+ * evaluated on a padded axis of N + K - 1 channels starting at channel -c
+ * (c = (K-1)/2), convolved with the K-tap line-spread function keeping the
+ * valid part  out[i] = sum_u lsf[u] pad[i + K - 1 - u],  plus a constant
+ * continuum.  Parameters per spectrum: [A, mu, sigma] per line (mu, sigma in
+ * channels), then the continuum: P = 3 n_lines + 1.  chi^2 = sum w (d - m)^2.
+ *
+ * A line batch holds n spectra of uneven N (>= 1), odd K (1..GF_LINE_MAX_K)
+ * and 1..GF_LINE_MAX_LINES lines each.  Flat layouts: spectrum s's data,
+ * weight and model occupy [data_off[s], data_off[s+1]), its LSF taps
+ * [lsf_off[s], lsf_off[s+1]), its parameters [par_off[s], par_off[s+1]). */
+typedef struct gf_line_batch gf_line_batch;
+
+gf_status gf_line_batch_create(gf_ctx *ctx, int n, const int32_t *N, const int32_t *K, const int32_t *n_lines,
+                               gf_line_batch **out);
+void gf_line_batch_destroy(gf_line_batch *lb);
+/* Host arrays of n + 1 offsets each (any may be NULL). */
+gf_status gf_line_batch_offsets(const gf_line_batch *lb, int64_t *data_off, int64_t *lsf_off, int64_t *par_off);
+
+/* Steps 1-2 plus continuum: out (device [n_data]) = the model spectra.
+ * lsf: device [n_lsf]; theta: device [n_par] FP32; oversample 1..8. */
+gf_status gf_line_model(gf_ctx *ctx, const gf_line_batch *lb, const float *lsf, const float *theta, int oversample,
+                        float *out);
+
+/* Steps 1-3: chi2 (device [2 n]) compensated (hi, lo) FP32 pairs as in
+ * gf_chi2; data, weight: device [n_data]. */
+gf_status gf_line_chi2(gf_ctx *ctx, const gf_line_batch *lb, const float *lsf, const float *theta, int oversample,
+                       const float *data, const float *weight, float *chi2);
+
+/* Levenberg-Marquardt over every spectrum with the rule of gf_fit_lm (opts:
+ * max_iter, oversample, lambda0/up/down/max, ftol, xtol, lo, hi, free_mask
+ * as there; poll_every and use_graph are unused).  One workgroup per
+ * spectrum runs all of that spectrum's iterations in a single launch.
+ * theta_io: device [n_par] FP64, start in, best accepted point out;
+ * res: device [n]. */
+gf_status gf_line_fit_lm(gf_ctx *ctx, const gf_line_batch *lb, const float *lsf, const float *data,
+                         const float *weight, double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
 
 /* Library version string. */
 const char *gf_version(void);

@@ -31,7 +31,8 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_cnn_create", "gf_cnn_destroy", "gf_cnn_param_count", "gf_cnn_init", "gf_cnn_set_params",
            "gf_cnn_get_params", "gf_cnn_forward", "gf_cnn_gradients", "gf_cnn_train_step", "gf_cnn_steps",
            "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
-           "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_version")
+           "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_line_batch_create", "gf_line_batch_destroy",
+           "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version")
 
 
 class GfLmOpts(ctypes.Structure):
@@ -135,6 +136,12 @@ def lib() -> ctypes.CDLL:
         "gf_profile_stop": (i32, [vp]),
         "gf_profile_kernels": (i32, [vp]),
         "gf_profile_get": (i32, [vp, i32, ctypes.c_char_p, i32, pi64, ctypes.POINTER(ctypes.c_double)]),
+        "gf_line_batch_create": (i32, [vp, i32, vp, vp, vp, pvp]),
+        "gf_line_batch_destroy": (None, [vp]),
+        "gf_line_batch_offsets": (i32, [vp, vp, vp, vp]),
+        "gf_line_model": (i32, [vp, vp, vp, vp, i32, vp]),
+        "gf_line_chi2": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
+        "gf_line_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
         "gf_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -270,6 +277,38 @@ def gf_lm_opts_default() -> GfLmOpts:
 
 def gf_fit_lm(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, opts: GfLmOpts, res_ptr):
     check(lib().gf_fit_lm(ctx, b, psf, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), res_ptr), ctx)
+
+
+def gf_line_batch_create(ctx: int, N, K, n_lines) -> int:
+    import numpy as np
+    n = len(N)
+    a = [np.ascontiguousarray(v, dtype=np.int32) for v in (N, K, n_lines)]
+    out = ctypes.c_void_p()
+    check(lib().gf_line_batch_create(ctx, n, *[x.ctypes.data for x in a], ctypes.byref(out)), ctx)
+    return out.value
+
+
+def gf_line_batch_destroy(lb: int) -> None:
+    lib().gf_line_batch_destroy(lb)
+
+
+def gf_line_batch_offsets(lb: int, n: int) -> dict:
+    import numpy as np
+    arrs = {k: np.zeros(n + 1, np.int64) for k in ("data", "lsf", "par")}
+    check(lib().gf_line_batch_offsets(lb, *[arrs[k].ctypes.data for k in ("data", "lsf", "par")]))
+    return arrs
+
+
+def gf_line_model(ctx, lb, lsf_ptr, theta_ptr, oversample, out_ptr):
+    check(lib().gf_line_model(ctx, lb, lsf_ptr, theta_ptr, oversample, out_ptr), ctx)
+
+
+def gf_line_chi2(ctx, lb, lsf_ptr, theta_ptr, oversample, data_ptr, weight_ptr, chi2_ptr):
+    check(lib().gf_line_chi2(ctx, lb, lsf_ptr, theta_ptr, oversample, data_ptr, weight_ptr, chi2_ptr), ctx)
+
+
+def gf_line_fit_lm(ctx, lb, lsf_ptr, data_ptr, weight_ptr, theta_ptr, opts: GfLmOpts, res_ptr):
+    check(lib().gf_line_fit_lm(ctx, lb, lsf_ptr, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), res_ptr), ctx)
 
 
 def gf_profile_start(ctx):

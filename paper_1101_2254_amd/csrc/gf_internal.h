@@ -110,6 +110,20 @@ struct Chi2Epi {
   float2 *part;
 };
 
+// One spectrum of a line batch.
+struct LineDesc {
+  int32_t N, K, nl, pad0;
+  int64_t data, lsf, par;   // offsets into the flat data / LSF / parameter arrays
+};
+
+// Options of the line fits, as passed to the device.
+struct LineLMParams {
+  int32_t max_iter, S;
+  double lambda0, lambda_up, lambda_down, lambda_max, ftol, xtol;
+  const double *lo, *hi;
+  const uint8_t *free_mask;
+};
+
 // LM per-stamp state (device).
 struct LMState {
   double lambda;
@@ -273,4 +287,13 @@ struct gf_psf {
   std::vector<gf::Work> h_pix_direct;
   gf::Work *d_pix_direct = nullptr;
   int n_fft = 0, n_direct = 0;
+};
+
+struct gf_line_batch {
+  gf_ctx *ctx = nullptr;
+  int n = 0;
+  std::vector<gf::LineDesc> h_desc;
+  gf::LineDesc *d_desc = nullptr;
+  int64_t n_data = 0, n_lsf = 0, n_par = 0;
+  bool has_nl[GF_LINE_MAX_LINES + 1] = {};
 };

@@ -274,6 +274,81 @@ def expand_starts(ctx: Context, theta0: torch.Tensor, n_starts: int) -> torch.Te
     return out[:G * n_starts]
 
 
+# ------------------------------------------------------------ spectral lines
+class LineBatch:
+    """Spectra of a line batch (``gf_line_batch``): N channels, K LSF taps and
+    1..3 Gaussian lines each.  Parameters per spectrum ``[A, mu, sigma] *
+    n_lines + [continuum]``; flat offsets in ``offsets['data'|'lsf'|'par']``."""
+
+    def __init__(self, ctx: Context, N, K, n_lines):
+        self.ctx = ctx
+        self.n = len(N)
+        self.ptr = L.gf_line_batch_create(ctx.ptr, N, K, n_lines)
+        self.offsets = L.gf_line_batch_offsets(self.ptr, self.n)
+        self.sizes = {k: int(v[-1]) for k, v in self.offsets.items()}
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            L.gf_line_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def line_model(ctx: Context, lb: LineBatch, lsf: torch.Tensor, theta: torch.Tensor, oversample: int = 5,
+               out=None) -> torch.Tensor:
+    """Model spectra (gf_line_model), flat [n_data] float32."""
+    _need(lsf, torch.float32, lb.sizes["lsf"], "lsf")
+    _need(theta, torch.float32, lb.sizes["par"], "theta")
+    out = _empty(ctx, lb.sizes["data"]) if out is None else _need(out, torch.float32, lb.sizes["data"], "out")
+    ctx.bind_stream()
+    L.gf_line_model(ctx.ptr, lb.ptr, _ptr(lsf), _ptr(theta), int(oversample), _ptr(out))
+    return out
+
+
+def line_chi2(ctx: Context, lb: LineBatch, lsf: torch.Tensor, theta: torch.Tensor, data: torch.Tensor,
+              weight: torch.Tensor, oversample: int = 5) -> torch.Tensor:
+    """chi^2 (hi, lo) pairs [n, 2] of every spectrum (gf_line_chi2)."""
+    _need(lsf, torch.float32, lb.sizes["lsf"], "lsf")
+    _need(theta, torch.float32, lb.sizes["par"], "theta")
+    _need(data, torch.float32, lb.sizes["data"], "data")
+    _need(weight, torch.float32, lb.sizes["data"], "weight")
+    out = torch.empty((lb.n, 2), dtype=torch.float32, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_line_chi2(ctx.ptr, lb.ptr, _ptr(lsf), _ptr(theta), int(oversample), _ptr(data), _ptr(weight), _ptr(out))
+    return out
+
+
+def line_fit_lm(ctx: Context, lb: LineBatch, lsf: torch.Tensor, data: torch.Tensor, weight: torch.Tensor,
+                theta0: torch.Tensor, lo=None, hi=None, free=None, return_device=False, **opts):
+    """Levenberg-Marquardt over every spectrum (gf_line_fit_lm), one
+    workgroup per spectrum in one launch.  theta0: float64 [n_par] (not
+    modified).  Returns (theta, per-spectrum results) as fit_lm does."""
+    n_par = lb.sizes["par"]
+    _need(lsf, torch.float32, lb.sizes["lsf"], "lsf")
+    _need(theta0, torch.float64, n_par, "theta0")
+    _need(data, torch.float32, lb.sizes["data"], "data")
+    _need(weight, torch.float32, lb.sizes["data"], "weight")
+    o = lm_options(**opts)
+    if lo is not None:
+        o.lo = _ptr(_need(lo, torch.float64, n_par, "lo"))
+    if hi is not None:
+        o.hi = _ptr(_need(hi, torch.float64, n_par, "hi"))
+    if free is not None:
+        o.free_mask = _ptr(_need(free, torch.uint8, n_par, "free"))
+    theta = theta0.clone()
+    res = torch.empty(lb.n * LM_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_line_fit_lm(ctx.ptr, lb.ptr, _ptr(lsf), _ptr(data), _ptr(weight), _ptr(theta), o, _ptr(res))
+    if return_device:
+        return theta, res
+    return theta, lm_info(res)
+
+
 # ------------------------------------------------------------------ autograd
 class Chi2Fn(torch.autograd.Function):
     """chi^2 per stamp (FP64 from the compensated pair) with the adjoint
