@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "lines"], default="c2")
     ap.add_argument("--train-stamps", type=int, default=200_000, help="C5: rendered training stamps")
     ap.add_argument("--epochs", type=int, default=4, help="C5: training epochs")
     ap.add_argument("--mcmc-steps", type=int, default=2000, help="C4: Metropolis steps of the chain run")
@@ -81,6 +81,9 @@ def kernel_work(name, geo, launches_per_step):
         return "hbm", npix * 4 + geo.get("nimg", npix) * 8, "byte"
     if name == "k_gram":
         return "hbm", npix * (4 * nch + 8), "byte"
+    if name == "k_line_lm":
+        # FP32 operations of the whole fit (see line_fit_flops), one launch
+        return "alu", geo["line_flops"], "flop"
     if name == "k_fft_irows_chi2":
         # inverse rows of the spectra in, data and weight per distinct image
         return "hbm", geo.get("chan_" + name, 1) * H * Lh * 8 + geo.get("nimg", npix) * 8, "byte"
@@ -419,6 +422,98 @@ def run_c5(args, torch, ops, synth):
     return result, prof, geo, dict(info=ic, nfev=int(ic["nfev"].sum()), njev=int(ic["njev"].sum()))
 
 
+# Algorithmic FP32 operations of one line fit, counting an FMA as two and an
+# exp2 as one: per padded channel, sub-sample and line 6 for the model
+# (offset, square, scale, exp2, accumulate) and 10 with the three
+# derivatives; per output channel 2 K per convolved plane; the Gram matrix
+# 2 (P + 1)(P + 2)/2 per output channel.
+def line_fit_flops(N, K, nl, S, nfev, njev):
+    P = 3 * nl + 1
+    npad = N + K - 1
+    model = npad * S * nl * 6 + N * 2 * K + 4 * N
+    jac = npad * S * nl * 10 + N * 2 * K * P + N * (P + 1) * (P + 2)
+    return nfev * model + njev * jac
+
+
+def run_lines(args, torch, ops, synth):
+    dev = torch.device("cuda", 0)
+    n = 65536
+    spectra = synth.line_batch(n)
+    ctx = ops.Context(0)
+    lb = ops.LineBatch(ctx, [s.N for s in spectra], [s.K for s in spectra], [s.nlines for s in spectra])
+    lsf = torch.from_numpy(np.concatenate([s.lsf for s in spectra]).astype(np.float32)).to(dev)
+    truth = torch.from_numpy(np.concatenate([s.truth for s in spectra]).astype(np.float32)).to(dev)
+    start = torch.from_numpy(np.concatenate([s.start for s in spectra])).to(dev)
+    lo = torch.from_numpy(np.concatenate([synth.line_bounds(s.nlines, s.N)[0] for s in spectra])).to(dev)
+    hi = torch.from_numpy(np.concatenate([synth.line_bounds(s.nlines, s.N)[1] for s in spectra])).to(dev)
+    # observation: the library's model at the truth plus seeded noise
+    m_true = ops.line_model(ctx, lb, lsf, truth, 5).cpu().numpy().astype(np.float64)
+    d, w = synth.add_noise_1d(m_true, 0.05, synth.SEED_BASE + 60)
+    data = torch.from_numpy(d.astype(np.float32)).to(dev)
+    weight = torch.from_numpy(w.astype(np.float32)).to(dev)
+
+    def step():
+        return ops.line_fit_lm(ctx, lb, lsf, data, weight, start, lo=lo, hi=hi, ftol=1e-5, max_iter=100,
+                               return_device=True)
+
+    K = args.steps if args.steps is not None else 20
+    W = args.warmup if args.warmup is not None else 3
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        th, res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / K * 1e3
+    info = ops.lm_info(res)
+    from paper_1101_2254_amd import _lib
+    _lib.gf_profile_start(ctx.ptr)
+    step()
+    torch.cuda.synchronize()
+    _lib.gf_profile_stop(ctx.ptr)
+    prof = _lib.gf_profile_read(ctx.ptr)
+    S = 5
+    flops = sum(line_fit_flops(s.N, s.K, s.nlines, S, int(info["nfev"][i]), int(info["njev"][i]))
+                for i, s in enumerate(spectra))
+    chan_evals = sum(s.N * (int(info["nfev"][i]) + int(info["njev"][i])) for i, s in enumerate(spectra))
+    nch = sum(s.N for s in spectra)
+    result = dict(
+        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
+        value=round(n / (ms * 1e-3), 2), unit="fits/s", ms_per_step=round(ms, 4),
+        mpix_per_s=round(chan_evals / (ms * 1e-3) / 1e6, 2),
+        lm=dict(iters_mean=float(info["iters"].mean()), iters_max=int(info["iters"].max()),
+                converged=float((info["status"] == 0).mean()), nfev=int(info["nfev"].sum()),
+                njev=int(info["njev"].sum())),
+        config=dict(workload="lines: 65536 spectra of 256..2048 channels with 1..3 Gaussian emission lines and a "
+                             "continuum, 7..21-tap Gaussian LSF, 5x sub-sampling, one gf_line_fit_lm call to chi2 "
+                             "rel tol 1e-5; one step = the whole batch",
+                    spectra=n, channels=nch, oversample=S))
+    geo = dict(npix=nch, npad=nch, Mw=1, H=1, nch=1, ncomp=1, S=S, L=2, line_flops=flops)
+    return result, prof, geo, dict(spectra=spectra, info=info, data=d, weight=w)
+
+
+def cpu_baseline_lines(extra, seconds):
+    """The line oracle fitting the same spectra (the same observations, as
+    FP32 values) one after another within the time budget."""
+    from oracle import line_ref as LR
+    import synth
+    spectra, d, w = extra["spectra"], extra["data"].astype(np.float32), extra["weight"].astype(np.float32)
+    offs = np.cumsum([0] + [s.N for s in spectra])
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds and n < len(spectra):
+        s = spectra[n]
+        lo, hi = synth.line_bounds(s.nlines, s.N)
+        LR.fit_lm(s.start, s.lsf.astype(np.float32).astype(np.float64), d[offs[n]:offs[n + 1]].astype(np.float64),
+                  w[offs[n]:offs[n + 1]].astype(np.float64), 5, lo=lo, hi=hi, ftol=1e-5, max_iter=100)
+        n += 1
+    t = time.perf_counter() - t0
+    return dict(value=round(n / t, 3), unit="fits/s", cores=1, kind="oracle",
+                sample=f"numpy FP64 line oracle fitting the first {n} spectra of the batch to ftol 1e-5, "
+                       f"{t:.1f} s on one thread")
+
+
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy calibration: fetch x2, write x1), as
 # summarised in profiles/*_hbm_traffic.md: bytes = once + per_channel x
@@ -654,6 +749,8 @@ def main():
         result, prof, geo, extra = run_c3(args, torch, ops, synth)
     elif args.workload == "c5":
         result, prof, geo, extra = run_c5(args, torch, ops, synth)
+    elif args.workload == "lines":
+        result, prof, geo, extra = run_lines(args, torch, ops, synth)
     else:
         result, prof, geo, extra = run_c4(args, torch, ops, synth)
     geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = geo["chan_k_fft_irows_chi2"] = 1
@@ -688,11 +785,13 @@ def main():
     if args.breakdown:
         print(json.dumps(stages, indent=1), file=sys.stderr)
     out = dict(metric=result["metric"], value=result["value"], unit=result["unit"], n_gpus=1,
-               steps=args.steps if args.steps is not None else (20 if args.workload == "c2" else 50),
+               steps=args.steps if args.steps is not None else (20 if args.workload in ("c2", "lines") else 50),
                warmup=args.warmup if args.warmup is not None else 3, ms_per_step=result["ms_per_step"],
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data=("synthetic (seeded; stamps rendered by the library from on-device Philox4x64-10 prior draws and "
                      "noise)" if args.workload == "c5" else
+                     "synthetic (seeded; spectra rendered by the library, noise from numpy PCG64)"
+                     if args.workload == "lines" else
                      "synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)"),
                config=result["config"], roofline=rl)
     for k in ("fits_per_s", "lm", "mpix_per_s", "c5", "mcmc"):
@@ -708,6 +807,8 @@ def main():
             out["cpu_baseline"] = cpu_baseline_c3(extra, args.cpu_seconds)
         elif args.workload == "c5":
             out["cpu_baseline"] = cpu_baseline_c5(extra, args.cpu_seconds)
+        elif args.workload == "lines":
+            out["cpu_baseline"] = cpu_baseline_lines(extra, args.cpu_seconds)
         else:
             out["cpu_baseline"] = cpu_baseline_c4(extra, args.cpu_seconds)
     print(json.dumps(out))
