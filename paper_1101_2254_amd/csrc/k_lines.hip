@@ -69,15 +69,21 @@ __device__ void line_chunk_eval(const LineC *__restrict__ lc, int S, int K, int 
     for (int k = 0; k < L; ++k) {
       const float base = (float)(xc - lc[k].mi);
       const float a = lc[k].a, k2 = lc[k].k2;
+      float fo[GF_MAX_OVERSAMPLE];
+#pragma unroll
+      for (int s = 0; s < GF_MAX_OVERSAMPLE; ++s) fo[s] = lc[k].fo[s];
       float sg = 0.0f, sm = 0.0f, ss = 0.0f;
-      for (int s = 0; s < S; ++s) {
-        const float dx = base + lc[k].fo[s];
-        const float g = __builtin_amdgcn_exp2f(dx * dx * k2);
-        sg += g;
-        if (JAC) {
-          const float gd = g * dx;
-          sm += gd;
-          ss = fmaf(gd, dx, ss);
+#pragma unroll
+      for (int s = 0; s < GF_MAX_OVERSAMPLE; ++s) {
+        if (s < S) {
+          const float dx = base + fo[s];
+          const float g = __builtin_amdgcn_exp2f(dx * dx * k2);
+          sg += g;
+          if (JAC) {
+            const float gd = g * dx;
+            sm += gd;
+            ss = fmaf(gd, dx, ss);
+          }
         }
       }
       m = fmaf(a, sg, m);
@@ -97,12 +103,21 @@ __device__ void line_chunk_eval(const LineC *__restrict__ lc, int S, int K, int 
   }
 }
 
-// Valid convolution of plane ch at this thread's output channel (tid < n_out).
-__device__ __forceinline__ float line_conv(const float *__restrict__ lsf, int K, const float *__restrict__ plane,
-                                           int tid) {
-  float v = 0.0f;
-  for (int u = 0; u < K; ++u) v = fmaf(lsf[u], plane[tid + K - 1 - u], v);
-  return v;
+// Valid convolution of planes 0 .. NP-1 at this thread's output channel
+// (tid < n_out): every plane shares each tap load, and the loop is unrolled
+// so that the LDS loads of several taps are in flight together.
+template <int NP>
+__device__ __forceinline__ void line_conv(const float *__restrict__ lsf, int K, const float (*__restrict__ pv)[kLinePadW],
+                                          int tid, float *v) {
+#pragma unroll
+  for (int q = 0; q < NP; ++q) v[q] = 0.0f;
+  const int b = tid + K - 1;
+#pragma unroll 4
+  for (int u = 0; u < K; ++u) {
+    const float l = lsf[u];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) v[q] = fmaf(l, pv[q][b - u], v[q]);
+  }
 }
 
 // Fixed-order compensated workgroup sum (waves in order).
@@ -130,7 +145,9 @@ __device__ F2 line_chi2_pass(const LineC *lc, float cont, int S, int N, int K, c
     __syncthreads();
     const int tid = threadIdx.x;
     if (tid < n_out) {
-      const float m = line_conv(lsf_s, K, pv[0], tid) + cont;
+      float mc;
+      line_conv<1>(lsf_s, K, pv, tid, &mc);
+      const float m = mc + cont;
       const float r = sqrtf(wp[i0 + tid]) * (dp[i0 + tid] - m);
       acc = f2_add1(acc, r * r);
     }
@@ -160,7 +177,11 @@ __global__ __launch_bounds__(kLT) void k_line_model(const LineDesc *__restrict__
     const int n_out = min(kLT, d.N - i0);
     line_chunk_eval<L, false>(lc, S, d.K, i0, n_out, pv);
     __syncthreads();
-    if (tid < n_out) out[d.data + i0 + tid] = line_conv(lsf_s, d.K, pv[0], tid) + cont;
+    if (tid < n_out) {
+      float mc;
+      line_conv<1>(lsf_s, d.K, pv, tid, &mc);
+      out[d.data + i0 + tid] = mc + cont;
+    }
     __syncthreads();
   }
 }
@@ -260,12 +281,12 @@ __global__ __launch_bounds__(kLT) void k_line_lm(const LineDesc *__restrict__ de
         line_chunk_eval<L, true>(lc, prm.S, d.K, i0, n_out, pv);
         __syncthreads();
         if (tid < n_out) {
-          float x[NX];
-          const float m = line_conv(lsf_s, d.K, pv[0], tid) + cont;
+          float cv[3 * L + 1], x[NX];
+          line_conv<3 * L + 1>(lsf_s, d.K, pv, tid, cv);
 #pragma unroll
-          for (int q = 0; q < 3 * L; ++q) x[q] = line_conv(lsf_s, d.K, pv[1 + q], tid);
+          for (int q = 0; q < 3 * L; ++q) x[q] = cv[1 + q];
           x[P - 1] = 1.0f;
-          x[P] = dp[i0 + tid] - m;
+          x[P] = dp[i0 + tid] - (cv[0] + cont);
           const float w = wp[i0 + tid];
           int e = 0;
 #pragma unroll
