@@ -274,6 +274,10 @@ void gf_destroy(gf_ctx *c) {
   dfree(c->ws);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  for (hipStream_t st : c->side)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : c->side_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 

@@ -217,6 +217,10 @@ struct gf_ctx {
   size_t ws_bytes = 0;
   int *h_pinned = nullptr;     // pinned host word for LM polling
   gf::Profiler prof;
+  // side streams (default priority) and fork/join events for launches that
+  // run concurrently, e.g. the per-line-count kernels of a line fit
+  hipStream_t side[GF_LINE_MAX_LINES] = {};
+  hipEvent_t side_ev[GF_LINE_MAX_LINES + 1] = {};
 };
 
 namespace gf {

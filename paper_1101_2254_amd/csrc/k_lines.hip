@@ -16,6 +16,8 @@
 #include "gf_internal.h"
 #include "twosum.h"
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 namespace gf {
 
 constexpr int kLT = 256;                         // threads; output channels per chunk
@@ -221,14 +223,14 @@ __global__ __launch_bounds__(kLT) void k_line_lm(const LineDesc *__restrict__ de
                                                  const float *__restrict__ weight, double *__restrict__ theta,
                                                  LineLMParams prm, gf_lm_result *__restrict__ res) {
   constexpr int P = 3 * L + 1;    // parameters; the continuum is the last
-  constexpr int NX = P + 1;       // Gram columns: the P derivatives, then the residual
-  constexpr int NG = NX * (NX + 1) / 2;
+  static_assert(P + 1 <= 16, "the Gram block holds 16 columns");
   __shared__ float lsf_s[GF_LINE_MAX_K];
   __shared__ float pv[3 * L + 1][kLinePadW];
   __shared__ LineC lc[L];
   __shared__ F2 red[kLT / 64];
-  __shared__ float gw[kLT / 64][NG];
-  __shared__ double Gs[NG];
+  __shared__ float xs[kLT][17];            // sqrt(w) [J 1 r] of a chunk (row stride 17: no bank conflicts)
+  __shared__ float gw[kLT / 64][256];       // per-wave Gram blocks
+  __shared__ double Gs[256];                // Gram matrix G[a][b] at a * 16 + b
   __shared__ double th_s[P], tt_s[P], lo_s[P], hi_s[P], dl_s[P];
   __shared__ double Lr[P][P], inv_s[P];
   __shared__ int fr_s[P], idx_s[P];
@@ -272,48 +274,51 @@ __global__ __launch_bounds__(kLT) void k_line_lm(const LineDesc *__restrict__ de
     iters = it;
     if (need_jac) {
       // ---- Gram matrix of [J r] at theta (lc holds theta's constants)
-      float acc[NG];
-#pragma unroll
-      for (int e = 0; e < NG; ++e) acc[e] = 0.0f;
+      // Per chunk every thread stages sqrt(w) [J 1 r] of its channel in LDS
+      // and each wave adds the 16 x 16 Gram block of its 64 channels with
+      // v_mfma_f32_16x16x4f32 (lane (i, k) feeds column i of channel k as
+      // both operands); the accumulator stays in four registers per lane.
+      floatx4 gacc = {0.f, 0.f, 0.f, 0.f};
       const float cont = (float)th_s[P - 1];
+      const int gi = lane & 15, gk = lane >> 4;
       for (int i0 = 0; i0 < d.N; i0 += kLT) {
         const int n_out = min(kLT, d.N - i0);
         line_chunk_eval<L, true>(lc, prm.S, d.K, i0, n_out, pv);
         __syncthreads();
+        float y[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) y[q] = 0.0f;
         if (tid < n_out) {
-          float cv[3 * L + 1], x[NX];
+          float cv[3 * L + 1];
           line_conv<3 * L + 1>(lsf_s, d.K, pv, tid, cv);
+          const float sw = sqrtf(wp[i0 + tid]);
 #pragma unroll
-          for (int q = 0; q < 3 * L; ++q) x[q] = cv[1 + q];
-          x[P - 1] = 1.0f;
-          x[P] = dp[i0 + tid] - (cv[0] + cont);
-          const float w = wp[i0 + tid];
-          int e = 0;
+          for (int q = 0; q < 3 * L; ++q) y[q] = sw * cv[1 + q];
+          y[P - 1] = sw;
+          y[P] = sw * (dp[i0 + tid] - (cv[0] + cont));
+        }
 #pragma unroll
-          for (int a = 0; a < NX; ++a) {
-            const float wa = w * x[a];
+        for (int q = 0; q < 16; ++q) xs[tid][q] = y[q];
+        __syncthreads();
 #pragma unroll
-            for (int b = 0; b <= a; ++b) {
-              acc[e] = fmaf(wa, x[b], acc[e]);
-              ++e;
-            }
+        for (int g = 0; g < 64; g += 16) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float v = xs[64 * wv + g + 4 * gk + q][gi];
+            gacc = __builtin_amdgcn_mfma_f32_16x16x4f32(v, v, gacc, 0, 0, 0);
           }
         }
         __syncthreads();
       }
+      // lane (col = lane % 16, rows 4 (lane / 16) .. +3) holds G[row][col]
 #pragma unroll
-      for (int e = 0; e < NG; ++e) {
-        float v = acc[e];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) gw[wv][e] = v;
-      }
+      for (int r = 0; r < 4; ++r) gw[wv][(4 * gk + r) * 16 + gi] = gacc[r];
       __syncthreads();
-      for (int e = tid; e < NG; e += kLT) {
+      {
         double t = 0.0;
 #pragma unroll
-        for (int q = 0; q < kLT / 64; ++q) t += (double)gw[q][e];
-        Gs[e] = t;
+        for (int q = 0; q < kLT / 64; ++q) t += (double)gw[q][tid];
+        Gs[tid] = t;
       }
       __syncthreads();
       ++njev;
@@ -323,10 +328,7 @@ __global__ __launch_bounds__(kLT) void k_line_lm(const LineDesc *__restrict__ de
     if (wv == 0) {
       const bool mine = lane < nf;
       const int my = mine ? idx_s[lane] : 0;
-      auto Gat = [&](int a, int b) -> double {   // A[a][b] from the packed lower triangle
-        const int hi = a > b ? a : b, lo = a > b ? b : a;
-        return Gs[hi * (hi + 1) / 2 + lo];
-      };
+      auto Gat = [&](int a, int b) -> double { return Gs[a * 16 + b]; };
       double dmax = (lane < P && fr_s[lane]) ? Gat(lane, lane) : 0.0;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
@@ -495,11 +497,14 @@ hipError_t launch_line_chi2(hipStream_t st, const gf_line_batch *lb, const float
   return hipGetLastError();
 }
 
-hipError_t launch_line_lm(hipStream_t st, const gf_line_batch *lb, const float *lsf, const float *data,
+// One kernel per line count present, each on its own stream (the kernels
+// differ in register use, so running them side by side keeps every CU busy
+// through each kernel's tail of slow spectra).
+hipError_t launch_line_lm(const hipStream_t *sts, const gf_line_batch *lb, const float *lsf, const float *data,
                           const float *weight, double *theta, const LineLMParams &prm, gf_lm_result *res) {
-  ProfScope ps(st, "k_line_lm");
   for (int L = 1; L <= GF_LINE_MAX_LINES; ++L) {
     if (!lb->has_nl[L]) continue;
+    hipStream_t st = sts[L - 1];
     if (L == 1)
       hipLaunchKernelGGL((k_line_lm<1>), dim3(lb->n), dim3(kLT), 0, st, lb->d_desc, lb->n, lsf, data, weight, theta,
                          prm, res);
@@ -509,8 +514,10 @@ hipError_t launch_line_lm(hipStream_t st, const gf_line_batch *lb, const float *
     else
       hipLaunchKernelGGL((k_line_lm<3>), dim3(lb->n), dim3(kLT), 0, st, lb->d_desc, lb->n, lsf, data, weight, theta,
                          prm, res);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace gf

@@ -10,8 +10,8 @@ namespace gf {
 hipError_t launch_line_model(hipStream_t, const gf_line_batch *, const float *, const float *, int, float *);
 hipError_t launch_line_chi2(hipStream_t, const gf_line_batch *, const float *, const float *, int, const float *,
                             const float *, float2 *);
-hipError_t launch_line_lm(hipStream_t, const gf_line_batch *, const float *, const float *, const float *, double *,
-                          const LineLMParams &, gf_lm_result *);
+hipError_t launch_line_lm(const hipStream_t *, const gf_line_batch *, const float *, const float *, const float *,
+                          double *, const LineLMParams &, gf_lm_result *);
 }  // namespace gf
 
 using namespace gf;
@@ -137,7 +137,19 @@ gf_status gf_line_fit_lm(gf_ctx *c, const gf_line_batch *lb, const float *lsf, c
     return lfail(c, GF_EINVAL, "gf_line_fit_lm: invalid options");
   LineLMParams prm{o.max_iter, o.oversample, o.lambda0, o.lambda_up, o.lambda_down, o.lambda_max, o.ftol, o.xtol,
                    o.lo, o.hi, o.free_mask};
-  LINE_TRY(c, launch_line_lm(c->stream, lb, lsf, data, weight, theta_io, prm, res));
+  // fork onto the side streams after the caller's stream, join back
+  for (int i = 0; i < GF_LINE_MAX_LINES; ++i)
+    if (!c->side[i]) LINE_TRY(c, hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+  for (int i = 0; i <= GF_LINE_MAX_LINES; ++i)
+    if (!c->side_ev[i]) LINE_TRY(c, hipEventCreateWithFlags(&c->side_ev[i], hipEventDisableTiming));
+  ProfScope ps(c->stream, "k_line_lm");
+  LINE_TRY(c, hipEventRecord(c->side_ev[0], c->stream));
+  for (int i = 0; i < GF_LINE_MAX_LINES; ++i) LINE_TRY(c, hipStreamWaitEvent(c->side[i], c->side_ev[0], 0));
+  LINE_TRY(c, launch_line_lm(c->side, lb, lsf, data, weight, theta_io, prm, res));
+  for (int i = 0; i < GF_LINE_MAX_LINES; ++i) {
+    LINE_TRY(c, hipEventRecord(c->side_ev[i + 1], c->side[i]));
+    LINE_TRY(c, hipStreamWaitEvent(c->stream, c->side_ev[i + 1], 0));
+  }
   return GF_OK;
 }
 
