@@ -68,7 +68,11 @@ __global__ __launch_bounds__(kThreads) void k_chi2(const StampDesc *__restrict__
 #pragma unroll
     for (int k = 0; k < kChi2Vec; ++k) {
       const int p = p0 + 4 * (k * kThreads + (int)threadIdx.x);
-      mv[k] = *reinterpret_cast<const float4 *>(mp + p);
+      {   // the model is read once: a streaming (non-temporal) load
+        typedef float nf4 __attribute__((ext_vector_type(4)));
+        const nf4 t = __builtin_nontemporal_load(reinterpret_cast<const nf4 *>(mp + p));
+        mv[k] = make_float4(t.x, t.y, t.z, t.w);
+      }
       dv[k] = *reinterpret_cast<const float4 *>(dp + p);
       wv[k] = *reinterpret_cast<const float4 *>(wp + p);
     }
