@@ -250,7 +250,10 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  * res: device [n_stamps].  data, weight: device [n_img].  All iterations run
  * on the device; the host only reads the count of still-active stamps every
  * poll_every iterations.  Stamps that finish stop costing work.
- * Returns GF_OK when the call ran (per-stamp outcomes are in res). */
+ * Returns GF_OK when the call ran (per-stamp outcomes are in res).  Data or
+ * weights that are not finite make that stamp's chi^2 non-finite: its fit
+ * then rejects every step and ends with GF_ENOTCONV, reason 4, at the
+ * (clipped) start; mask bad pixels with weight 0 and a finite data value. */
 gf_status gf_fit_lm(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const float *data, const float *weight,
                     double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
 

@@ -1,0 +1,93 @@
+"""Error paths of the C ABI on a device: shapes and arguments the library
+does not support come back as documented status codes with a message, before
+anything is enqueued, and non-finite observations end a fit cleanly."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_1101_2254_amd import _lib as L
+from paper_1101_2254_amd import ops
+from tests.gpu_common import GpuBatch, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("gpu errors: creating context on cuda:0", flush=True)
+    c = ops.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _status(fn, *a):
+    try:
+        fn(*a)
+    except L.GfError as e:
+        return e.status
+    return L.GF_OK
+
+
+@pytest.mark.parametrize("H,W,K,nc", [(32, 32, 14, 1), (32, 32, 131, 1), (0, 32, 5, 1), (32, 32, 5, 0), (32, 32, 5, 5)])
+def test_batch_shapes_rejected(ctx, H, W, K, nc):
+    st = _status(L.gf_batch_create, ctx.ptr, [H], [W], [K], [nc], False)
+    assert st in (L.GF_ESHAPE, L.GF_EINVAL), st
+    assert L.lib().gf_last_error(ctx.ptr).decode()
+
+
+def test_padded_side_and_direct_psf_limits(ctx):
+    # a padded side above GF_MAX_FFT is refused with the batch
+    assert _status(L.gf_batch_create, ctx.ptr, [2000], [2000], [65], [1], False) == L.GF_ESHAPE
+    # a PSF wider than the direct path takes, when the direct path is forced
+    b = ops.Batch(ctx, [64], [64], [45], [1])
+    taps = to_dev(np.full(45 * 45, 1.0 / (45 * 45), np.float32))
+    assert _status(L.gf_psf_prepare, ctx.ptr, b.ptr, int(taps.data_ptr()), L.GF_CONV_DIRECT) == L.GF_ESHAPE
+    p = ops.Psf(ctx, b, taps, ops.GF_CONV_AUTO)   # the automatic choice takes the FFT path
+    assert list(p.uses_fft) == [1]
+
+
+def test_argument_ranges(ctx):
+    st = synth.c1()
+    gb = GpuBatch(ctx, [st])
+    out = torch.empty(gb.batch.sizes["n_pad"], dtype=torch.float32, device=ctx.device)
+    ctx.bind_stream()
+    for S in (0, 9):
+        assert _status(L.gf_eval_model, ctx.ptr, gb.batch.ptr, int(gb.theta.data_ptr()), S,
+                       int(out.data_ptr())) == L.GF_EINVAL
+    assert _status(L.gf_convolve_psf, ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(out.data_ptr()), 65,
+                   int(out.data_ptr())) == L.GF_EINVAL
+    o = L.gf_lm_opts_default()
+    o.max_iter = -1
+    assert _status(L.gf_fit_lm, ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(out.data_ptr()), int(out.data_ptr()),
+                   int(out.data_ptr()), o, int(out.data_ptr())) == L.GF_EINVAL
+
+
+def test_line_batch_and_argument_errors(ctx):
+    for N, K, nl in ((16, 4, 1), (16, 67, 1), (16, 5, 0), (16, 5, 4), (0, 5, 1)):
+        assert _status(L.gf_line_batch_create, ctx.ptr, [N], [K], [nl]) == L.GF_ESHAPE, (N, K, nl)
+    lb = ops.LineBatch(ctx, [32], [5], [1])
+    lsf = to_dev(np.array([0, 0, 1, 0, 0], np.float32))
+    th = to_dev(np.array([1.0, 10.0, 2.0, 0.0], np.float32))
+    out = torch.empty(32, dtype=torch.float32, device=ctx.device)
+    assert _status(L.gf_line_model, ctx.ptr, lb.ptr, int(lsf.data_ptr()), int(th.data_ptr()), 0,
+                   int(out.data_ptr())) == L.GF_EINVAL
+    assert _status(L.gf_line_model, ctx.ptr, lb.ptr, 0, int(th.data_ptr()), 5, int(out.data_ptr())) == L.GF_EINVAL
+
+
+def test_nonfinite_data_ends_the_fit(ctx, gfo):
+    st = synth.c1()
+    m = gfo.model(st.H, st.W, st.truth, st.psf.astype(np.float32).astype(np.float64), 5)
+    d, w = synth.add_gaussian_noise(m, 0.02, 5)
+    d[3, 4] = np.nan
+    gb = GpuBatch(ctx, [st], data=[d], weights=[w])
+    th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(st.start, torch.float64))
+    assert info["status"][0] == L.GF_ENOTCONV and info["reason"][0] == 4
+    np.testing.assert_array_equal(th.cpu().numpy(), st.start)
+    # a zero weight masks the same pixel: the fit runs normally
+    d[3, 4] = 0.0
+    w[3, 4] = 0.0
+    gb2 = GpuBatch(ctx, [st], data=[d], weights=[w])
+    th2, info2 = ops.fit_lm(ctx, gb2.batch, gb2.psf, gb2.data, gb2.weight, to_dev(st.start, torch.float64))
+    assert info2["status"][0] == L.GF_OK
