@@ -2,6 +2,7 @@
 // (FFT plans, OTFs, work lists), the step 1-3 entry points, derivatives and
 // the device-resident Levenberg-Marquardt driver.
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <cmath>
 #include <cstring>
@@ -70,6 +71,11 @@ using namespace gf;
 
 namespace gf {
 thread_local Profiler *t_prof = nullptr;
+
+uint64_t next_uid() {
+  static std::atomic<uint64_t> n{0};
+  return ++n;
+}
 }
 
 namespace {
@@ -278,6 +284,10 @@ void gf_destroy(gf_ctx *c) {
     if (st) (void)hipStreamDestroy(st);
   for (hipEvent_t e : c->side_ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->lm_exec) (void)hipGraphExecDestroy(c->lm_exec);
+  if (c->lm_graph) (void)hipGraphDestroy(c->lm_graph);
+  if (c->lm_stream) (void)hipStreamDestroy(c->lm_stream);
+  if (c->lm_ev) (void)hipEventDestroy(c->lm_ev);
   delete c;
 }
 
@@ -323,6 +333,7 @@ static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t 
   gf_batch *b = new (std::nothrow) gf_batch();
   if (!b) return fail(c, GF_ENOMEM, "gf_batch_create: host allocation");
   b->ctx = c;
+  b->uid = next_uid();
   b->n = n;
   b->shared = shared != 0;
   b->h_desc.resize(n);
@@ -488,6 +499,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   gf_psf *p = new (std::nothrow) gf_psf();
   if (!p) return fail(c, GF_ENOMEM, "gf_psf_prepare: host allocation");
   p->ctx = c;
+  p->uid = next_uid();
   p->batch = b;
   p->d_taps = taps;
   const int n = b->n;
@@ -994,18 +1006,48 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   lm_layout(b, p, nchan, nacc, a, B);
   const int S = o.oversample;
 
-  hipStream_t cs = nullptr;
-  hipEvent_t ev = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  GF_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  GF_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  // The fit runs on the context's LM stream, joined to the caller's stream
+  // by an event at both ends.  The captured iteration over the full work
+  // lists stays in the context and is replayed by later calls with the same
+  // key; graphs over compacted lists belong to this call only.
+  if (!c->lm_stream) GF_TRY(c, hipStreamCreateWithFlags(&c->lm_stream, hipStreamNonBlocking));
+  if (!c->lm_ev) GF_TRY(c, hipEventCreateWithFlags(&c->lm_ev, hipEventDisableTiming));
+  hipStream_t cs = c->lm_stream;
+  hipEvent_t ev = c->lm_ev;
+  LmGraphKey key;
+  key.batch_uid = b->uid;
+  key.psf_uid = p->uid;
+  key.data = data;
+  key.weight = weight;
+  key.theta = theta;
+  key.ws = c->ws;
+  key.lo = o.lo;
+  key.hi = o.hi;
+  key.free_mask = o.free_mask;
+  key.max_iter = o.max_iter;
+  key.oversample = o.oversample;
+  key.lambda_up = o.lambda_up;
+  key.lambda_down = o.lambda_down;
+  key.lambda_max = o.lambda_max;
+  key.ftol = o.ftol;
+  key.xtol = o.xtol;
+  const bool graphs = o.use_graph && o.max_iter > 0;
+  const bool reuse = graphs && c->lm_exec && c->lm_key == key;
+  if (graphs && !reuse && c->lm_exec) {
+    // nothing of an earlier call may still be replaying the graph
+    GF_TRY(c, hipStreamSynchronize(cs));
+    (void)hipGraphExecDestroy(c->lm_exec);
+    (void)hipGraphDestroy(c->lm_graph);
+    c->lm_exec = nullptr;
+    c->lm_graph = nullptr;
+    c->lm_key = LmGraphKey{};
+  }
+  hipGraph_t vgraph = nullptr;
+  hipGraphExec_t vexec = nullptr;
+  hipGraphExec_t exec = reuse ? c->lm_exec : nullptr;
   auto cleanup = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamSynchronize(cs);
-    (void)hipStreamDestroy(cs);
-    (void)hipEventDestroy(ev);
+    if (vexec) (void)hipGraphExecDestroy(vexec);
+    if (vgraph) (void)hipGraphDestroy(vgraph);
   };
   auto run = [&]() -> gf_status {
     GF_TRY(c, hipEventRecord(ev, c->stream));
@@ -1035,22 +1077,25 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
                                  B.cnt, B.cc_th, B.cc_t));
       return GF_OK;
     };
-    auto capture = [&]() -> gf_status {
-      if (exec) (void)hipGraphExecDestroy(exec);
-      if (graph) (void)hipGraphDestroy(graph);
-      exec = nullptr;
-      graph = nullptr;
+    // capture one iteration into (g, e), replacing what they held
+    auto capture = [&](hipGraph_t &g, hipGraphExec_t &e) -> gf_status {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      e = nullptr;
+      g = nullptr;
       GF_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       gf_status s2 = iteration();
-      hipError_t ce = hipStreamEndCapture(cs, &graph);
+      hipError_t ce = hipStreamEndCapture(cs, &g);
       if (s2 != GF_OK) return s2;
       GF_TRY(c, ce);
-      GF_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      GF_TRY(c, hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
       return GF_OK;
     };
-    if (o.use_graph && o.max_iter > 0) {
-      gf_status s2 = capture();
+    if (graphs && !reuse) {
+      gf_status s2 = capture(c->lm_graph, c->lm_exec);
       if (s2 != GF_OK) return s2;
+      c->lm_key = key;
+      exec = c->lm_exec;
     }
     std::vector<LMState> hst;
     std::vector<char> act;
@@ -1089,8 +1134,9 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           vw = &view;
           view_stamps = active;
           if (exec) {
-            gf_status s2 = capture();
+            gf_status s2 = capture(vgraph, vexec);
             if (s2 != GF_OK) return s2;
+            exec = vexec;
           }
         }
       }

@@ -205,6 +205,28 @@ struct ProfScope {
 
 }  // namespace gf
 
+namespace gf {
+// What one captured LM iteration depends on besides the context: the batch
+// and PSF (their launch grids and device lists, by unique id, so an object
+// freed and replaced at the same address does not match), the caller's
+// pointers, the workspace, and the options that reach the kernels.
+struct LmGraphKey {
+  uint64_t batch_uid = 0, psf_uid = 0;
+  const void *data = nullptr, *weight = nullptr, *theta = nullptr, *ws = nullptr;
+  const void *lo = nullptr, *hi = nullptr, *free_mask = nullptr;
+  int32_t max_iter = 0, oversample = 0;
+  double lambda_up = 0, lambda_down = 0, lambda_max = 0, ftol = 0, xtol = 0;
+  bool operator==(const LmGraphKey &o) const {
+    return batch_uid == o.batch_uid && psf_uid == o.psf_uid && data == o.data && weight == o.weight &&
+           theta == o.theta && ws == o.ws && lo == o.lo && hi == o.hi && free_mask == o.free_mask &&
+           max_iter == o.max_iter && oversample == o.oversample && lambda_up == o.lambda_up &&
+           lambda_down == o.lambda_down && lambda_max == o.lambda_max && ftol == o.ftol && xtol == o.xtol;
+  }
+};
+// Process-wide unique, nonzero id for batches and PSFs.
+uint64_t next_uid();
+}  // namespace gf
+
 // ---------------------------------------------------------------- host objects
 struct gf_ctx {
   int device = 0;
@@ -221,6 +243,13 @@ struct gf_ctx {
   // run concurrently, e.g. the per-line-count kernels of a line fit
   hipStream_t side[GF_LINE_MAX_LINES] = {};
   hipEvent_t side_ev[GF_LINE_MAX_LINES + 1] = {};
+  // LM fits: their stream and join event, and the last captured iteration
+  // graph with what it was captured for (replayed while the key matches)
+  hipStream_t lm_stream = nullptr;
+  hipEvent_t lm_ev = nullptr;
+  gf::LmGraphKey lm_key;
+  hipGraph_t lm_graph = nullptr;
+  hipGraphExec_t lm_exec = nullptr;
 };
 
 namespace gf {
@@ -234,6 +263,7 @@ struct ProfBind {
 
 struct gf_batch {
   gf_ctx *ctx = nullptr;
+  uint64_t uid = 0;
   int n = 0;
   bool shared = false;
   std::vector<gf::StampDesc> h_desc;
@@ -259,6 +289,7 @@ struct gf_batch {
 
 struct gf_psf {
   gf_ctx *ctx = nullptr;
+  uint64_t uid = 0;
   const gf_batch *batch = nullptr;
   const float *d_taps = nullptr;
   std::vector<gf::PathDesc> h_path;
