@@ -38,7 +38,8 @@ hipError_t launch_jac_assemble(hipStream_t, const gf_batch *, const float *, int
 hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *);
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
                             const float *, float *, int, int, const int *, const WorkView *);
-hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const float2 *, LMState *, int *, int *, int *);
+hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
+                          int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *);
@@ -888,7 +889,7 @@ namespace {
 
 struct LMBufs {
   float *cpad, *jc, *mpad, *mconv, *npart;
-  float2 *S1, *S2, *chi2t, *cpart;
+  float2 *S1, *S2, *cpart;
   double *Ag, *theta_t;
   LMState *st;
   int *mjac, *mtrial, *cnt;
@@ -968,7 +969,6 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.theta_t = a.take<double>(b->n_par);
   B.mpad = a.take<float>(b->n_pad);
   B.mconv = a.take<float>(b->n_pix);
-  B.chi2t = a.take<float2>(b->n);
   B.cpart = a.take<float2>(chi2_slots(b, p));
   B.st = a.take<LMState>(b->n);
   B.mjac = a.take<int>(b->n);
@@ -1057,8 +1057,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, true));
     GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
                         nullptr));
-    GF_TRY(c, launch_pair_final(cs, b->n, p->d_c2_first, B.cpart, B.chi2t, nullptr));
-    GF_TRY(c, launch_lm_init(cs, b, o.lambda0, B.chi2t, B.st, B.mjac, B.mtrial, B.cnt));
+    GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt));
     WorkView view;
     const WorkView *vw = nullptr;   // null: the full lists
     HostLists cur, nxt;
@@ -1091,24 +1090,36 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
       return GF_OK;
     };
-    if (graphs && !reuse) {
-      gf_status s2 = capture(c->lm_graph, c->lm_exec);
-      if (s2 != GF_OK) return s2;
-      c->lm_key = key;
-      exec = c->lm_exec;
-    }
     std::vector<LMState> hst;
     std::vector<char> act;
+    // the result records are written before every poll, so a fit that the
+    // poll finds finished returns without another launch; the host waits
+    // only for the count
+    bool res_fresh = false;
     for (int it = 0; it < o.max_iter; ++it) {
-      if (exec) {
+      // The first iteration is launched kernel by kernel, so the device starts
+      // on it while the host is still enqueueing (a graph launch hands over
+      // nothing until the whole graph is submitted); the graph, captured here
+      // when the context holds none for this key, replays the rest.
+      if (exec && it > 0) {
         GF_TRY(c, hipGraphLaunch(exec, cs));
       } else {
         gf_status s2 = iteration();
         if (s2 != GF_OK) return s2;
       }
+      if (it == 0 && graphs && !reuse && o.max_iter > 1) {
+        gf_status s2 = capture(c->lm_graph, c->lm_exec);
+        if (s2 != GF_OK) return s2;
+        c->lm_key = key;
+        exec = c->lm_exec;
+      }
+      res_fresh = false;
       if ((it + 1) % o.poll_every == 0 || it + 1 == o.max_iter) {
         GF_TRY(c, hipMemcpyAsync(c->h_pinned, B.cnt, sizeof(int), hipMemcpyDeviceToHost, cs));
-        GF_TRY(c, hipStreamSynchronize(cs));
+        GF_TRY(c, hipEventRecord(ev, cs));
+        GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
+        res_fresh = true;
+        GF_TRY(c, hipEventSynchronize(ev));
         const int active = *(volatile int *)c->h_pinned;
         if (active == 0) break;
         // Once half of the stamps in the current lists have finished, restrict
@@ -1141,7 +1152,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
         }
       }
     }
-    GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
+    if (!res_fresh) GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
     GF_TRY(c, hipEventRecord(ev, cs));
     GF_TRY(c, hipStreamWaitEvent(c->stream, ev, 0));
     return GF_OK;

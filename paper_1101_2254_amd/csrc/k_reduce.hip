@@ -438,34 +438,43 @@ struct LMParams {
   int32_t oversample;
 };
 
-// Start: chi2 of the (clipped) start point is in chi2t.
-__global__ void k_lm_init(const StampDesc *__restrict__ desc, int n, double lambda0, const float2 *__restrict__ chi2t,
-                          LMState *__restrict__ st, int *__restrict__ mjac, int *__restrict__ mtrial,
-                          int *__restrict__ active_count) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < n) {
-    LMState S;
-    S.lambda = lambda0;
-    S.chi2 = (double)chi2t[s].x + (double)chi2t[s].y;
-    S.chi2_trial = S.chi2;
-    S.iters = 0;
-    S.nfev = 1;
-    S.njev = 0;
-    S.status = GF_ENOTCONV;
-    S.reason = 5;
-    S.active = 1;
-    S.need_jac = 1;
-    S.trial = 0;
-    if (S.chi2 == 0.0) {
-      S.status = GF_OK;
-      S.reason = 3;
-      S.active = 0;
-    }
-    st[s] = S;
-    mjac[s] = S.active;
-    mtrial[s] = 0;
+// Start: one wave per stamp adds the chi^2 partials of the (clipped) start
+// point in the order of k_pair_final (the same value, bit for bit), and its
+// first lane sets up the stamp's state.
+__global__ __launch_bounds__(64) void k_lm_init(int n, double lambda0, const int32_t *__restrict__ first,
+                                                const float2 *__restrict__ part, LMState *__restrict__ st,
+                                                int *__restrict__ mjac, int *__restrict__ mtrial,
+                                                int *__restrict__ active_count) {
+  const int s = blockIdx.x;
+  if (s == 0 && threadIdx.x == 0) *active_count = n;
+  F2 r = {0.f, 0.f};
+  for (int u = first[s] + (int)threadIdx.x; u < first[s + 1]; u += 64) {
+    const float2 v = part[u];
+    F2 t = {v.x, v.y};
+    r = f2_add(r, t);
   }
-  if (s == 0) *active_count = n;
+  r = wave_sum(r);
+  if (threadIdx.x != 0) return;
+  LMState S;
+  S.lambda = lambda0;
+  S.chi2 = (double)r.hi + (double)r.lo;
+  S.chi2_trial = S.chi2;
+  S.iters = 0;
+  S.nfev = 1;
+  S.njev = 0;
+  S.status = GF_ENOTCONV;
+  S.reason = 5;
+  S.active = 1;
+  S.need_jac = 1;
+  S.trial = 0;
+  if (S.chi2 == 0.0) {
+    S.status = GF_OK;
+    S.reason = 3;
+    S.active = 0;
+  }
+  st[s] = S;
+  mjac[s] = S.active;
+  mtrial[s] = 0;
 }
 
 // Clip the start point into the box: theta_t = clip(theta).
@@ -878,10 +887,10 @@ hipError_t launch_expand_starts(hipStream_t st, int G, int S, const double *thet
   return hipGetLastError();
 }
 
-hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, const float2 *chi2t, LMState *S,
-                          int *mjac, int *mtrial, int *cnt) {
-  hipLaunchKernelGGL(k_lm_init, dim3((b->n + 255) / 256), dim3(256), 0, st, b->d_desc, b->n, lambda0, chi2t, S,
-                     mjac, mtrial, cnt);
+hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, const int32_t *first,
+                          const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt) {
+  hipLaunchKernelGGL(k_lm_init, dim3((unsigned)b->n), dim3(64), 0, st, b->n, lambda0, first, part, S, mjac, mtrial,
+                     cnt);
   return hipGetLastError();
 }
 
