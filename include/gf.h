@@ -224,6 +224,8 @@ typedef struct {
   const uint8_t *free_mask; /* device [n_par], nonzero = fitted, or NULL = all free */
   int32_t poll_every;   /* iterations between host checks of the active-stamp count (default 4) */
   int32_t use_graph;    /* capture one iteration in a HIP graph and replay it (default 1) */
+  int32_t speculate;    /* evaluate the Jacobian together with every trial point instead of after
+                           acceptance: 1 on, 0 off, -1 (default) on for single-stamp batches */
 } gf_lm_opts;
 
 typedef struct {
@@ -247,6 +249,13 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  *   theta' = clip(theta + delta, lo, hi); accept iff chi2(theta') < chi2(theta)
  *   (lambda /= down), else reject (lambda *= up).
  * theta_io: device [n_par] FP64, start in, best accepted point out.
+ * With speculate the trial point's model comes from its Jacobian images
+ * (the model is linear in each Ie: m = sky + sum_c Ie_c dm/dIe_c), so an
+ * accepted step already has the next normal equations; a rejected one has
+ * spent a Jacobian instead of one model.  This pays where launches are
+ * latency-bound (one large image), not in large batches with many
+ * rejections.  The steps taken are the same rule either way; chi^2 values
+ * differ in the last bits.
  * res: device [n_stamps].  data, weight: device [n_img].  All iterations run
  * on the device; the host only reads the count of still-active stamps every
  * poll_every iterations.  Stamps that finish stop costing work.

@@ -37,7 +37,7 @@ hipError_t launch_adjoint_final(hipStream_t, const gf_batch *, const int32_t *, 
 hipError_t launch_jac_assemble(hipStream_t, const gf_batch *, const float *, int, float *);
 hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *);
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float *, int, int, const int *, const WorkView *);
+                            const float *, float *, int, int, const int *, const WorkView *, float2 *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
                           int *);
 hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
@@ -883,6 +883,7 @@ void gf_lm_opts_default(gf_lm_opts *o) {
   o->free_mask = nullptr;
   o->poll_every = 4;
   o->use_graph = 1;
+  o->speculate = -1;
 }
 
 namespace {
@@ -890,6 +891,7 @@ namespace {
 struct LMBufs {
   float *cpad, *jc, *mpad, *mconv, *npart;
   float2 *S1, *S2, *cpart;
+  float2 *gpart;   // chi^2 partials per normal-equation unit (speculative iterations)
   double *Ag, *theta_t;
   LMState *st;
   int *mjac, *mtrial, *cnt;
@@ -970,6 +972,7 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.mpad = a.take<float>(b->n_pad);
   B.mconv = a.take<float>(b->n_pix);
   B.cpart = a.take<float2>(chi2_slots(b, p));
+  B.gpart = a.take<float2>((int64_t)b->h_neq.size());
   B.st = a.take<LMState>(b->n);
   B.mjac = a.take<int>(b->n);
   B.mtrial = a.take<int>(b->n);
@@ -989,8 +992,9 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   gf_lm_opts o;
   if (opts) o = *opts; else gf_lm_opts_default(&o);
   if (o.max_iter < 0 || o.oversample < 1 || o.oversample > GF_MAX_OVERSAMPLE || !(o.lambda_up > 1.0) ||
-      !(o.lambda_down > 1.0) || !(o.lambda0 > 0.0))
+      !(o.lambda_down > 1.0) || !(o.lambda0 > 0.0) || o.speculate < -1 || o.speculate > 1)
     return fail(c, GF_EINVAL, "gf_fit_lm: invalid options");
+  const bool spec = o.speculate > 0 || (o.speculate < 0 && b->n == 1);
   if (o.poll_every < 1) o.poll_every = 1;
   if (b->max_nc > 2) return fail(c, GF_ESHAPE, "gf_fit_lm: at most two components per stamp");
   const int nchan = kNPC * b->max_nc;
@@ -1026,6 +1030,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   key.free_mask = o.free_mask;
   key.max_iter = o.max_iter;
   key.oversample = o.oversample;
+  key.spec = spec ? 1 : 0;
   key.lambda_up = o.lambda_up;
   key.lambda_down = o.lambda_down;
   key.lambda_max = o.lambda_max;
@@ -1052,21 +1057,48 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   auto run = [&]() -> gf_status {
     GF_TRY(c, hipEventRecord(ev, c->stream));
     GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
-    // start point: clip, evaluate, chi2
+    // start point: clip, evaluate, chi2 (speculative: the Jacobian images and
+    // normal equations of the start point, chi^2 from the same model)
     GF_TRY(c, launch_lm_clip(cs, b->n_par, theta, o.lo, o.hi, B.theta_t));
-    GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, true));
-    GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
-                        nullptr));
-    GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt));
+    if (spec) {
+      GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, nullptr, nullptr, B.cc_th, true));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, nullptr, nullptr));
+      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, nullptr, nullptr));
+      GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, nullptr, nullptr,
+                                 B.gpart));
+      GF_TRY(c, launch_lm_init(cs, b, o.lambda0, b->d_neq_first, B.gpart, B.st, B.mjac, B.mtrial, B.cnt));
+    } else {
+      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, true));
+      GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
+                          nullptr));
+      GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt));
+    }
     WorkView view;
     const WorkView *vw = nullptr;   // null: the full lists
     HostLists cur, nxt;
     int view_stamps = b->n;
+    // Speculative iteration: solve, then Jacobian images, normal equations
+    // and chi^2 at the trial point, accept or reject.  An accepted trial
+    // leaves its normal equations for the next solve; after a rejection the
+    // solve reuses the stored system of the current point.
+    auto iteration_spec = [&]() -> gf_status {
+      GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
+                                B.cc_t, c->d_bn));
+      GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, B.mtrial, vw, B.cc_t, false));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mtrial, vw));
+      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mtrial, vw));
+      GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, B.mtrial, vw,
+                                 B.gpart));
+      GF_TRY(c, launch_lm_update(cs, b, &o, b->d_neq_first, B.gpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
+                                 B.cnt, B.cc_th, B.cc_t));
+      return GF_OK;
+    };
     auto iteration = [&]() -> gf_status {
+      if (spec) return iteration_spec();
       GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw, B.cc_th, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
-      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw));
+      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr));
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
                                 B.cc_t, c->d_bn));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));

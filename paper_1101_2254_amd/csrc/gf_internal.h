@@ -214,12 +214,12 @@ struct LmGraphKey {
   uint64_t batch_uid = 0, psf_uid = 0;
   const void *data = nullptr, *weight = nullptr, *theta = nullptr, *ws = nullptr;
   const void *lo = nullptr, *hi = nullptr, *free_mask = nullptr;
-  int32_t max_iter = 0, oversample = 0;
+  int32_t max_iter = 0, oversample = 0, spec = 0;
   double lambda_up = 0, lambda_down = 0, lambda_max = 0, ftol = 0, xtol = 0;
   bool operator==(const LmGraphKey &o) const {
     return batch_uid == o.batch_uid && psf_uid == o.psf_uid && data == o.data && weight == o.weight &&
            theta == o.theta && ws == o.ws && lo == o.lo && hi == o.hi && free_mask == o.free_mask &&
-           max_iter == o.max_iter && oversample == o.oversample && lambda_up == o.lambda_up &&
+           max_iter == o.max_iter && oversample == o.oversample && spec == o.spec && lambda_up == o.lambda_up &&
            lambda_down == o.lambda_down && lambda_max == o.lambda_max && ftol == o.ftol && xtol == o.xtol;
   }
 };

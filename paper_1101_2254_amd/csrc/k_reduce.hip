@@ -312,13 +312,15 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int kGramThreads = 256;
 
-template <int NC>
+// With C2 the workgroup also reduces its chunk's chi^2 of the same model
+// (compensated FP32, the residual lanes only) into c2part at the unit's slot.
+template <int NC, bool C2>
 __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
                                                    const float *__restrict__ jc, int nchan,
                                                    const double *__restrict__ theta, const float *__restrict__ data,
                                                    const float *__restrict__ weight, float *__restrict__ part,
                                                    const int32_t *__restrict__ first, const int *__restrict__ mask,
-                                                   int vec_ok) {
+                                                   int vec_ok, float2 *__restrict__ c2part) {
   constexpr int P = kNPC * NC + 1;
   static_assert(P + 1 <= 16, "augmented Jacobian must fit 16 columns");
   __shared__ float red[kGramThreads / 64][256];
@@ -338,6 +340,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
   constexpr int per_wave = kNeqChunk / (kGramThreads / 64);
   const int base = wk.unit * kNeqChunk + wv * per_wave;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  F2 c2acc = {0.f, 0.f};
   const int ich = i < P - 1 ? i : 0;  // channel read by this lane (clamped for the sky / residual lanes)
   if (vec_ok && (((int64_t)d.pix * nchan | npix | d.img) & 3) == 0 && base + per_wave <= npix) {
     // the wave's pixels all inside the stamp, 16-byte aligned (uniform over
@@ -364,6 +367,12 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
         }
         const float x = (i < P - 1) ? jq[q] : (i == P - 1) ? 1.0f : (i == P) ? dq[q] - m : 0.0f;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
+        if constexpr (C2) {
+          if (i == P) {
+            const float e = sqrtf(wq[q]) * x;
+            c2acc = f2_add1(c2acc, e * e);
+          }
+        }
       }
     }
   } else if (base < npix) {
@@ -383,12 +392,23 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
         float x = (i < P - 1) ? jv : (i == P - 1) ? 1.0f : (i == P) ? dv - m : 0.0f;
         x = ok ? x : 0.0f;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, (ok ? wt : 0.0f) * x, acc, 0, 0, 0);
+        if constexpr (C2) {
+          if (i == P) {
+            const float e = sqrtf(ok ? wt : 0.0f) * x;
+            c2acc = f2_add1(c2acc, e * e);
+          }
+        }
       }
     }
   }
   // lane (col = lane % 16, rows 4*(lane/16) .. +3) holds G[row][col]
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wv][(4 * kk + r) * 16 + i] = acc[r];
+  __shared__ F2 c2w[kGramThreads / 64];
+  if constexpr (C2) {
+    c2acc = wave_sum(c2acc);
+    if (lane == 0) c2w[wv] = c2acc;
+  }
   __syncthreads();
   if (threadIdx.x < 256) {
     const int e = threadIdx.x;  // 256 entries, one per thread
@@ -397,11 +417,19 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
     for (int ww = 0; ww < kGramThreads / 64; ++ww) v += red[ww][e];
     part[(int64_t)(first[s] + wk.unit) * 256 + e] = v;   // the unit's own slot
   }
+  if constexpr (C2) {
+    if (threadIdx.x == 0) {
+      F2 t = c2w[0];
+#pragma unroll
+      for (int ww = 1; ww < kGramThreads / 64; ++ww) t = f2_add(t, c2w[ww]);
+      c2part[first[s] + wk.unit] = make_float2(t.hi, t.lo);
+    }
+  }
 }
 
 hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, const double *theta,
                             const float *data, const float *weight, float *part, int nacc_stride, int nchan,
-                            const int *mask, const WorkView *v) {
+                            const int *mask, const WorkView *v, float2 *c2part) {
   (void)nacc_stride;
   const bool view = v && v->neq;
   const Work *lst = view ? v->neq : b->d_neq;
@@ -414,12 +442,16 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
     has2 |= d.ncomp == 2;
   }
   const int vec_ok = aligned16(jc) && aligned16(data) && aligned16(weight);
-  if (has1)
-    hipLaunchKernelGGL((k_gram<1>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part,
-                       b->d_neq_first, mask, vec_ok);
-  if (has2)
-    hipLaunchKernelGGL((k_gram<2>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part,
-                       b->d_neq_first, mask, vec_ok);
+#define GF_GRAM(NC, C2)                                                                                         \
+  hipLaunchKernelGGL((k_gram<NC, C2>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part, \
+                     b->d_neq_first, mask, vec_ok, c2part)
+  if (has1) {
+    if (c2part) GF_GRAM(1, true); else GF_GRAM(1, false);
+  }
+  if (has2) {
+    if (c2part) GF_GRAM(2, true); else GF_GRAM(2, false);
+  }
+#undef GF_GRAM
   return hipGetLastError();
 }
 

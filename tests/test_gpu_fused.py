@@ -75,16 +75,17 @@ def test_fused_likelihood_ragged(ctx, gfo):
     assert torch.equal(pairs, ops.likelihood(ctx, gb.batch, gb.psf, gb.theta, gb.data, gb.weight, 5))
 
 
-def test_fused_fit_ragged_batch_and_alone(ctx, gfo):
+@pytest.mark.parametrize("spec", [0, 1])
+def test_fused_fit_ragged_batch_and_alone(ctx, gfo, spec):
     stamps = _stamps(32)
     data, weights = _observed(gfo, stamps)
     gb = GpuBatch(ctx, stamps, data=data, weights=weights)
     lo = np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in stamps])
     hi = np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in stamps])
     start = np.concatenate([s.start for s in stamps])
-    print("fit of the ragged batch", flush=True)
+    print(f"fit of the ragged batch, speculate={spec}", flush=True)
     th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(start, torch.float64),
-                          lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-5)
+                          lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-5, speculate=spec)
     th = th.cpu().numpy()
     assert np.all(np.isfinite(th)) and np.all(info["iters"] >= 1)
     po = gb.batch.offsets["par"]
@@ -92,7 +93,7 @@ def test_fused_fit_ragged_batch_and_alone(ctx, gfo):
         one = GpuBatch(ctx, [st], data=[data[s]], weights=[weights[s]])
         l, h = synth.bounds(1, st.H, st.W)
         t1, i1 = ops.fit_lm(ctx, one.batch, one.psf, one.data, one.weight, to_dev(st.start, torch.float64),
-                            lo=to_dev(l, torch.float64), hi=to_dev(h, torch.float64), ftol=1e-5)
+                            lo=to_dev(l, torch.float64), hi=to_dev(h, torch.float64), ftol=1e-5, speculate=spec)
         np.testing.assert_array_equal(t1.cpu().numpy(), th[po[s]:po[s] + 8], err_msg=str(s))
         assert i1["chi2"][0] == info["chi2"][s] and i1["iters"][0] == info["iters"][s], s
     # the reported chi^2 is the oracle's at the returned parameters

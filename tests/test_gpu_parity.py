@@ -410,12 +410,12 @@ def test_fit_lm_uneven_batch_c3(ctx, gfo):
         o = gb.batch.offsets["par"][s]
         assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), s
         _param_close(fit[o:o + 8], ref, 1, 0.02)
-    # the same stamp alone
+    # the same stamp alone, in the batch's (non-speculative) mode
     s = small[0]
     one = GpuBatch(ctx, [stamps[s]], data=[data[s]], weights=[weights[s]])
     l, h = synth.bounds(1, stamps[s].H, stamps[s].W)
     f1, r1 = ops.fit_lm(ctx, one.batch, one.psf, one.data, one.weight, to_dev(stamps[s].start, torch.float64),
-                        lo=to_dev(l, torch.float64), hi=to_dev(h, torch.float64), **opts)
+                        lo=to_dev(l, torch.float64), hi=to_dev(h, torch.float64), speculate=0, **opts)
     o = gb.batch.offsets["par"][s]
     np.testing.assert_array_equal(f1.cpu().numpy(), fit[o:o + 8])
     assert r1["chi2"][0] == res["chi2"][s] and r1["iters"][0] == res["iters"][s]
