@@ -357,6 +357,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
       for (int c = 0; c < NC; ++c) iv[c] = *reinterpret_cast<const float4 *>(J + (int64_t)(kNPC * c + 2) * npix + p);
       const float wq[4] = {wt.x, wt.y, wt.z, wt.w}, jq[4] = {jv.x, jv.y, jv.z, jv.w};
       const float dq[4] = {dv.x, dv.y, dv.z, dv.w};
+      float rq[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         float m = sky;
@@ -365,19 +366,24 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
           const float iq[4] = {iv[c].x, iv[c].y, iv[c].z, iv[c].w};
           m = fmaf(ie[c], iq[q], m);
         }
-        const float x = (i < P - 1) ? jq[q] : (i == P - 1) ? 1.0f : (i == P) ? dq[q] - m : 0.0f;
+        rq[q] = dq[q] - m;
+        const float x = (i < P - 1) ? jq[q] : (i == P - 1) ? 1.0f : (i == P) ? rq[q] : 0.0f;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
-        if constexpr (C2) {
-          if (i == P) {
-            const float e = sqrtf(wq[q]) * x;
-            c2acc = f2_add1(c2acc, e * e);
-          }
+      }
+      if constexpr (C2) {
+        // lanes i = 0..3 of each 16-lane group take pixel q = i of the group
+        const float r = i == 0 ? rq[0] : i == 1 ? rq[1] : i == 2 ? rq[2] : rq[3];
+        const float ww = i == 0 ? wq[0] : i == 1 ? wq[1] : i == 2 ? wq[2] : wq[3];
+        if (i < 4) {
+          const float e = sqrtf(ww) * r;
+          c2acc = f2_add1(c2acc, e * e);
         }
       }
     }
   } else if (base < npix) {
 #pragma unroll 4
     for (int g = 0; g < per_wave; g += 16) {
+      float rq[4], wq[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int p = base + g + 4 * kk + q;
@@ -389,14 +395,18 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
         float m = sky;
 #pragma unroll
         for (int c = 0; c < NC; ++c) m = fmaf(ie[c], J[(int64_t)(kNPC * c + 2) * npix + pc], m);
+        rq[q] = ok ? dv - m : 0.0f;
+        wq[q] = ok ? wt : 0.0f;
         float x = (i < P - 1) ? jv : (i == P - 1) ? 1.0f : (i == P) ? dv - m : 0.0f;
         x = ok ? x : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, (ok ? wt : 0.0f) * x, acc, 0, 0, 0);
-        if constexpr (C2) {
-          if (i == P) {
-            const float e = sqrtf(ok ? wt : 0.0f) * x;
-            c2acc = f2_add1(c2acc, e * e);
-          }
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
+      }
+      if constexpr (C2) {   // the same lanes and order as the vector path
+        const float r = i == 0 ? rq[0] : i == 1 ? rq[1] : i == 2 ? rq[2] : rq[3];
+        const float ww = i == 0 ? wq[0] : i == 1 ? wq[1] : i == 2 ? wq[2] : wq[3];
+        if (i < 4) {
+          const float e = sqrtf(ww) * r;
+          c2acc = f2_add1(c2acc, e * e);
         }
       }
     }
