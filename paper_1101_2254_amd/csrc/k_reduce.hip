@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
       }
     }
   } else if (base < npix) {
-#pragma unroll 4
+#pragma unroll 1
     for (int g = 0; g < per_wave; g += 16) {
       float rq[4], wq[4];
 #pragma unroll
