@@ -202,8 +202,13 @@ FftPlan make_plan(int L, int tw_off) {
   std::memset(&p, 0, sizeof(p));
   p.L = L;
   p.tw_off = tw_off;
-  std::vector<int> rad;
+  std::vector<int> rad, rad18;
   best_plan(L, 32, rad);
+  // A plan of radices up to 18 runs in the FFT kernels built without the
+  // larger butterflies (fewer registers, more waves per SIMD): take it when
+  // it needs no more LDS passes than the best plan overall.
+  best_plan(L, 18, rad18);
+  if (!rad18.empty() && rad18.size() <= rad.size()) rad = rad18;
   p.nstages = (int)rad.size();
   int ns = 1;
   for (int s = 0; s < p.nstages; ++s) {
@@ -515,6 +520,22 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   std::map<int64_t, int64_t> otf_of_psf;   // PSF offset -> OTF offset
   std::vector<Work> otf_rows, otf_cols;
   int64_t otf_tmp_n = 0;
+  // The largest radix over the plans of the FFT stamps picks the kernel
+  // build and with it the LDS capacity that sizes every work unit.
+  {
+    std::vector<char> seen(GF_MAX_FFT + 1, 0);
+    for (int s = 0; s < n; ++s) {
+      const StampDesc &d = b->h_desc[s];
+      const bool f = mode == GF_CONV_FFT || (mode == GF_CONV_AUTO && d.K > 7) || d.K > kDirectMaxK;
+      const int L = fft_side(std::max(d.Mh, d.Mw));
+      if (!f || L > GF_MAX_FFT || seen[L]) continue;
+      seen[L] = 1;
+      const FftPlan pl = make_plan(L, 0);
+      for (int q = 0; q < pl.nstages; ++q)
+        if (pl.radix[q] > 18) p->rmax = 32;
+    }
+  }
+  const int cap = fft_cap(p->rmax);
   for (int s = 0; s < n; ++s) {
     const StampDesc &d = b->h_desc[s];
     // Automatic choice: the direct sum costs about K^2 FMAs per output pixel
@@ -566,7 +587,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     pd.L = L;
     pd.plan = plan_of_L[L];
     const int Lh = L / 2 + 1;
-    const int T = kFftCap / (L + 1), C = kFftCap / L;
+    const int T = cap / (L + 1), C = cap / L;
     const int cols = (Lh + C - 1) / C;
     for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_rows.push_back({s, u});
     for (int u = 0; u < cols; ++u) p->h_cols.push_back({s, u});

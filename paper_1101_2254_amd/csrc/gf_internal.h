@@ -19,7 +19,12 @@ constexpr int kThreads = 256;          // threads per workgroup for pixel kernel
 constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one per thread)
 constexpr int kPixChunk = 4096;        // pixels per chi^2 workgroup (16 per thread)
 constexpr int kNeqChunk = 1024;        // pixels per normal-equation workgroup (256 per wave)
-constexpr int kFftCap = 3840;          // complex values in the FFT LDS buffer (T*L <= this)
+// Complex values in the FFT LDS buffer of a workgroup (T*L <= this).  The
+// kernels built for plan radices up to 18 need fewer registers; with the
+// smaller buffer five of their workgroups fit on a CU instead of four.
+constexpr int kFftCap = 3840;
+constexpr int kFftCapSmall = 3456;
+constexpr int fft_cap(int rmax) { return rmax <= 18 ? kFftCapSmall : kFftCap; }
 constexpr int kFftMaxStages = 12;
 constexpr int kFftNarrowT = 1;         // row pairs per workgroup in the narrow launch shape
 constexpr int kFftNarrowC = 2;         // bins per workgroup in the narrow launch shape
@@ -300,6 +305,7 @@ struct gf_psf {
   float2 *d_otf = nullptr;     // OTFs [L][L/2+1] per stamp (one if shared)
   int64_t n_otf = 0;
   int max_L = 0;
+  int rmax = 18;               // 32 when a plan has a radix above 18 (the FFT kernels are built for 18 and 32)
   // FFT work lists: forward rows (padded rows), columns, inverse rows (output rows)
   std::vector<gf::Work> h_rows, h_cols, h_irows, h_arows, h_acols, h_airows;
   gf::Work *d_rows = nullptr, *d_cols = nullptr, *d_irows = nullptr;

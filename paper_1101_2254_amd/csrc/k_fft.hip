@@ -5,7 +5,7 @@
 // from the circular convolution on an L x L grid with L >= max(Mh, Mw): the
 // kept "valid" rows and columns K-1 .. M-1 never see a wrapped tap.  Three
 // launches per convolution, each a batch of independent 1-D transforms held in
-// one LDS buffer of kFftCap complex values per workgroup:
+// one LDS buffer of fft_cap(RMAX) complex values per workgroup:
 //   rows   : two real rows per complex transform (z = a + i b), length L,
 //            split into the half spectra A, B (L/2+1 bins) -> spectra S1[row][k]
 //   columns: per bin k, forward transform over rows, times the OTF (or its
@@ -53,15 +53,15 @@ struct FDiv {
 // LDS index with one padding slot per 32 complex values: the strided
 // accesses of the early Stockham passes (stride R) then spread over the banks.
 __device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
-constexpr int kFftLds = kFftCap + kFftCap / 32 + 1;
-// Loops that move up to kFftCap values between memory and LDS are unrolled
+constexpr int fft_lds(int cap) { return cap + cap / 32 + 1; }
+// Loops that move up to the buffer's capacity between memory and LDS are unrolled
 // this many times so each thread issues all of its global loads before it
 // waits on any of them.  The loads go through range-checked buffer
 // resources: an element outside the valid region gets an out-of-range
 // offset and reads zero, so no load sits under a branch (a load under a
 // branch makes the compiler wait for it inside the branch, which turns the
 // batch into one round trip per load).
-constexpr int kFftIters = (kFftCap + kThreads - 1) / kThreads;
+constexpr int fft_iters(int cap) { return (cap + kThreads - 1) / kThreads; }
 constexpr int kTwIters = (GF_MAX_FFT + kThreads - 1) / kThreads;
 
 // Stage the L twiddles of a plan into LDS (loads first, then stores).
@@ -278,14 +278,14 @@ __device__ __forceinline__ void dft(float2 *v) {
 // Butterfly j of a transform reads x[j + r L/R], twiddles input r by
 // W_{Ns R}^{r k} (k = j mod Ns), does a radix-R DFT in registers and writes to
 // (j div Ns) Ns R + k + r Ns.  Every thread first loads all of its
-// butterflies (NB of them: T L <= kFftCap guarantees one round), the
+// butterflies (NB of them: T L <= CAP guarantees one round), the
 // workgroup synchronises, and then all results are stored, so a single LDS
 // buffer suffices.  For R > 8 the twiddle of input r is formed as
 // W^{(r mod 8) k} W^{8 (r div 8) k} from two table entries.
-template <int R, bool INV>
+template <int R, bool INV, int CAP>
 __device__ __forceinline__ void stockham_pass(float2 *__restrict__ buf, int T, int L, int Ls, int Ns, uint32_t ns_m,
                                               uint32_t nb_m, const float2 *__restrict__ tw) {
-  constexpr int NB = (kFftCap + kThreads * R - 1) / (kThreads * R);
+  constexpr int NB = (CAP + kThreads * R - 1) / (kThreads * R);
   const int nb = L / R;
   const int total = T * nb;
   const int twstep = L / (Ns * R);
@@ -341,31 +341,41 @@ __device__ __forceinline__ void stockham_pass(float2 *__restrict__ buf, int T, i
   __syncthreads();
 }
 
-// Full transform of T transforms in place (T * L <= kFftCap).
-template <bool INV>
+// Full transform of T transforms in place (T * L <= fft_cap(RMAX)).  RMAX is the
+// largest radix the kernel is built for: plans of radices up to 18 run in
+// kernels without the larger register butterflies, which need fewer
+// registers and so keep more waves per SIMD.
+template <bool INV, int RMAX>
 __device__ __forceinline__ void lds_fft(float2 *buf, int T, int Ls, const FftPlan &pl, const float2 *tw) {
+  constexpr int CAP = fft_cap(RMAX);
   const int L = pl.L;
   for (int s = 0; s < pl.nstages; ++s) {
     const int R = pl.radix[s], Ns = pl.ns[s];
     const uint32_t nsm = pl.ns_magic[s], nbm = pl.nb_magic[s];
     switch (R) {
-      case 2: stockham_pass<2, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 3: stockham_pass<3, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 4: stockham_pass<4, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 5: stockham_pass<5, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 6: stockham_pass<6, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 8: stockham_pass<8, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 9: stockham_pass<9, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 10: stockham_pass<10, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 12: stockham_pass<12, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 15: stockham_pass<15, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 16: stockham_pass<16, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 18: stockham_pass<18, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 20: stockham_pass<20, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 24: stockham_pass<24, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 25: stockham_pass<25, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      case 27: stockham_pass<27, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-      default: stockham_pass<32, INV>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 2: stockham_pass<2, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 3: stockham_pass<3, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 4: stockham_pass<4, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 5: stockham_pass<5, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 6: stockham_pass<6, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 8: stockham_pass<8, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 9: stockham_pass<9, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 10: stockham_pass<10, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 12: stockham_pass<12, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 15: stockham_pass<15, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 16: stockham_pass<16, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      case 18: stockham_pass<18, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+      default:
+        if constexpr (RMAX > 18) {
+          switch (R) {
+            case 20: stockham_pass<20, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+            case 24: stockham_pass<24, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+            case 25: stockham_pass<25, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+            case 27: stockham_pass<27, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+            default: stockham_pass<32, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+          }
+        }
+        break;
     }
   }
 }
@@ -407,7 +417,7 @@ __device__ __forceinline__ Geo geo_of(int mode, const StampDesc &d, int L) {
 // ------------------------------------------------------------ row pass
 // in: real images; stamp s channel ch starts at in_base(s) * n_ch + ch * plane.
 // S1: stamp s channel ch starts at s1_off[s] * n_ch + ch * (L/2+1) * in_rows.
-template <int MODE>
+template <int MODE, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restrict__ desc,
                                                        const PathDesc *__restrict__ path,
                                                        const FftPlan *__restrict__ plans,
@@ -417,6 +427,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
                                                        float2 *__restrict__ S1, const int *__restrict__ mask,
                                                        int tmax) {
   extern __shared__ float2 lds[];
+  constexpr int CAP = fft_cap(RMAX), LDS0 = fft_lds(CAP), NIT = fft_iters(CAP);
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -425,8 +436,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   const FftPlan &pl = plans[pd.plan];
   const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int T = min(kFftCap / Ls, tmax);
-  float2 *buf = lds, *tw = lds + kFftLds;
+  const int T = min(CAP / Ls, tmax);
+  float2 *buf = lds, *tw = lds + LDS0;
 
   int64_t in_base, plane;
   if (MODE == MODE_CONV) { in_base = d.pad; plane = (int64_t)d.Mh * d.Mw; }
@@ -437,9 +448,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   const int r0 = w.unit * 2 * T;
   const FDiv divL(L);
   {
-    float va[kFftIters], vb[kFftIters];
+    float va[NIT], vb[NIT];
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       const int t = divL(idx), n = idx - t * L;
       const int ra = r0 + 2 * t, rb = ra + 1;
@@ -451,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
     }
     stage_twiddles(tw, tw_all + pl.tw_off, L);
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       if (idx < T * L) {
         const int t = divL(idx), n = idx - t * L;
@@ -460,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
     }
   }
   __syncthreads();
-  lds_fft<false>(buf, T, Ls, pl, tw);
+  lds_fft<false, RMAX>(buf, T, Ls, pl, tw);
   float2 *dst = S1 + s1_off[s] * n_ch + (int64_t)ch * Lh * g.in_rows;
   const int nr = min(2 * T, g.in_rows - r0);
   const FDiv divNr(nr);
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
 // MODE_CONV multiplies by the OTF, MODE_CORR by its conjugate, MODE_OTF only
 // transforms forward and scales by 1/L^2 (writing the OTF itself, bin-major
 // [L/2+1][L]).
-template <int MODE>
+template <int MODE, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restrict__ desc,
                                                        const PathDesc *__restrict__ path,
                                                        const FftPlan *__restrict__ plans,
@@ -491,6 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
                                                        const int64_t *__restrict__ s2_off, float2 *__restrict__ S2,
                                                        const int *__restrict__ mask, int tmax) {
   extern __shared__ float2 lds[];
+  constexpr int CAP = fft_cap(RMAX), LDS0 = fft_lds(CAP), NIT = fft_iters(CAP);
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -499,18 +511,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
   const FftPlan &pl = plans[pd.plan];
   const int L = pl.L, Lh = L / 2 + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int C = min(kFftCap / L, tmax);
+  const int C = min(CAP / L, tmax);
   const int k0 = w.unit * C;
   const int nc = min(C, Lh - k0);
-  float2 *buf = lds, *tw = lds + kFftLds;
+  float2 *buf = lds, *tw = lds + LDS0;
 
   const float2 *spec = S1 + s1_off[s] * n_ch + (int64_t)ch * Lh * g.in_rows;
   const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(spec, (uint32_t)(Lh * g.in_rows) * 8u);
   const FDiv divL(L);
   {
-    float2 v[kFftIters];
+    float2 v[NIT];
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       const int c = divL(idx), y = idx - c * L;
       const int r = y - g.col_row0;
@@ -519,13 +531,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
     }
     stage_twiddles(tw, tw_all + pl.tw_off, L);
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       if (idx < C * L) buf[lp(idx)] = v[it];
     }
   }
   __syncthreads();
-  lds_fft<false>(buf, C, L, pl, tw);
+  lds_fft<false, RMAX>(buf, C, L, pl, tw);
   if (MODE == MODE_OTF) {
     const float sc = 1.0f / ((float)L * (float)L);
     float2 *dst = S2 + s2_off[s] + (int64_t)k0 * L;
@@ -534,14 +546,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
   }
   const __amdgpu_buffer_rsrc_t hrsrc = make_rsrc(otf + pd.otf, (uint32_t)(L * Lh) * 8u);
   {
-    float2 hv[kFftIters];
+    float2 hv[NIT];
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       hv[it] = bload_f32x2(hrsrc, idx < nc * L ? (uint32_t)(k0 * L + idx) * 8u : kOutOfRange);
     }
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       if (idx < nc * L) {
         const float2 x = buf[lp(idx)];
@@ -550,7 +562,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
     }
   }
   __syncthreads();
-  lds_fft<true>(buf, C, L, pl, tw);
+  lds_fft<true, RMAX>(buf, C, L, pl, tw);
   float2 *dst = S2 + s2_off[s] * n_ch + (int64_t)ch * Lh * g.out_rows + (int64_t)k0 * g.out_rows;
   const FDiv divR(g.out_rows);
   for (int idx = threadIdx.x; idx < nc * g.out_rows; idx += blockDim.x) {
@@ -561,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
 
 // ------------------------------------------------------ inverse row pass
 // out: stamp s channel ch starts at out_base(s) * n_ch + ch * out_rows * out_cols.
-template <int MODE>
+template <int MODE, int RMAX>
 __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restrict__ desc,
                                                         const PathDesc *__restrict__ path,
                                                         const FftPlan *__restrict__ plans,
@@ -571,6 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
                                                         const float2 *__restrict__ S2, float *__restrict__ out,
                                                         const int *__restrict__ mask, int tmax, Chi2Epi ep) {
   extern __shared__ float2 lds[];
+  constexpr int CAP = fft_cap(RMAX), LDS0 = fft_lds(CAP), NIT = fft_iters(CAP);
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -579,17 +592,17 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   const FftPlan &pl = plans[pd.plan];
   const int L = pl.L, Lh = L / 2 + 1, Ls = L + 1;
   const Geo g = geo_of(MODE, d, L);
-  const int T = min(kFftCap / Ls, tmax);
-  float2 *buf = lds, *tw = lds + kFftLds;
+  const int T = min(CAP / Ls, tmax);
+  float2 *buf = lds, *tw = lds + LDS0;
 
   const float2 *src = S2 + s2_off[s] * n_ch + (int64_t)ch * Lh * g.out_rows;
   const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(src, (uint32_t)(Lh * g.out_rows) * 8u);
   const int r0 = w.unit * 2 * T;
   const FDiv divT(T);
   {
-    float2 va[kFftIters], vb[kFftIters];
+    float2 va[NIT], vb[NIT];
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       const int k = divT(idx), t = idx - k * T;
       const int ra = r0 + 2 * t, rb = ra + 1;
@@ -602,7 +615,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
     }
     stage_twiddles(tw, tw_all + pl.tw_off, L);
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       if (idx < T * L) {
         const int k = divT(idx), t = idx - k * T;
@@ -616,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
     }
   }
   __syncthreads();
-  lds_fft<true>(buf, T, Ls, pl, tw);
+  lds_fft<true, RMAX>(buf, T, Ls, pl, tw);
   if constexpr (MODE == MODE_CHI2) {
     // r = sqrt(w) (d - m - sky).  All threads form the squared residuals of
     // the workgroup's rows (every data and weight load in flight at once)
@@ -630,9 +643,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
     const __amdgpu_buffer_rsrc_t rw = make_rsrc(ep.weight + d.img, npix * 4u);
     const int oc = g.out_cols, n_items = T * oc;
     const FDiv divO(oc);
-    float da[kFftIters], wa[kFftIters], db[kFftIters], wb[kFftIters];
+    float da[NIT], wa[NIT], db[NIT], wb[NIT];
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       const int t = divO(idx), x = idx - t * oc;
       const int ra = r0 + 2 * t;
@@ -643,9 +656,9 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
       db[it] = bload_f32(rd, inb ? pa + (uint32_t)oc * 4u : kOutOfRange);
       wb[it] = bload_f32(rw, inb ? pa + (uint32_t)oc * 4u : kOutOfRange);
     }
-    float2 sq[kFftIters];
+    float2 sq[NIT];
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       sq[it] = make_float2(0.f, 0.f);
       if (idx < n_items) {
@@ -658,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kFftIters; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
       if (idx < n_items) buf[idx] = sq[it];
     }
@@ -692,7 +705,16 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
 }
 
 // ----------------------------------------------------------------- launchers
-static size_t fft_lds_bytes(int max_L) { return (size_t)(kFftLds + max_L) * sizeof(float2); }
+static size_t fft_lds_bytes(const gf_psf *p) { return (size_t)(fft_lds(fft_cap(p->rmax)) + p->max_L) * sizeof(float2); }
+
+// Launch the kernel built for the PSF's largest plan radix.
+#define GF_FFT_LAUNCH(KERNEL, MODE, ...)                                  \
+  do {                                                                   \
+    if (p->rmax <= 18)                                                   \
+      hipLaunchKernelGGL((KERNEL<MODE, 18>), __VA_ARGS__);               \
+    else                                                                 \
+      hipLaunchKernelGGL((KERNEL<MODE, 32>), __VA_ARGS__);               \
+  } while (0)
 
 // Small jobs (fewer than two workgroups per CU in the wide shape) use the
 // narrow shape: one row pair or two bins per workgroup, so more CUs share the
@@ -706,7 +728,7 @@ hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, c
   const bool view = v && v->rows;
   const int n_cols_w = view ? v->n_cols : (int)p->h_cols.size();
   if ((view ? v->n_rows : (int)p->h_rows.size()) == 0) return hipSuccess;
-  const size_t lds = fft_lds_bytes(p->max_L);
+  const size_t lds = fft_lds_bytes(p);
   dim3 blk(kThreads);
   const bool narrow = (int64_t)n_cols_w * n_ch < 2 * 256;
   const int nr = view ? (narrow ? v->n_rows_n : v->n_rows) : (int)(narrow ? p->h_rows_n : p->h_rows).size();
@@ -718,21 +740,21 @@ hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, c
   const int tr = narrow ? kFftNarrowT : 1 << 20, tc = narrow ? kFftNarrowC : 1 << 20;
   {
     ProfScope ps(st, "k_fft_rows");
-    hipLaunchKernelGGL((k_fft_rows<MODE_CONV>), dim3((unsigned)nr, n_ch), blk, lds, st, b->d_desc, p->d_path,
+    GF_FFT_LAUNCH(k_fft_rows, MODE_CONV, dim3((unsigned)nr, n_ch), blk, lds, st, b->d_desc, p->d_path,
                        p->d_plans, p->d_tw, d_rows, in, n_ch, p->d_s1, S1, mask, tr);
   }
   {
     ProfScope ps(st, "k_fft_cols");
-    hipLaunchKernelGGL((k_fft_cols<MODE_CONV>), dim3((unsigned)nc, n_ch), blk, lds, st, b->d_desc, p->d_path,
+    GF_FFT_LAUNCH(k_fft_cols, MODE_CONV, dim3((unsigned)nc, n_ch), blk, lds, st, b->d_desc, p->d_path,
                        p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
   }
   {
     ProfScope ps(st, ep ? "k_fft_irows_chi2" : "k_fft_irows");
     if (ep)
-      hipLaunchKernelGGL((k_fft_irows<MODE_CHI2>), dim3((unsigned)ni, 1), blk, lds, st, b->d_desc, p->d_path,
+      GF_FFT_LAUNCH(k_fft_irows, MODE_CHI2, dim3((unsigned)ni, 1), blk, lds, st, b->d_desc, p->d_path,
                          p->d_plans, p->d_tw, d_irows, 1, p->d_s2, S2, out, mask, tr, *ep);
     else
-      hipLaunchKernelGGL((k_fft_irows<MODE_CONV>), dim3((unsigned)ni, n_ch), blk, lds, st, b->d_desc, p->d_path,
+      GF_FFT_LAUNCH(k_fft_irows, MODE_CONV, dim3((unsigned)ni, n_ch), blk, lds, st, b->d_desc, p->d_path,
                          p->d_plans, p->d_tw, d_irows, n_ch, p->d_s2, S2, out, mask, tr, Chi2Epi{});
   }
   return hipGetLastError();
@@ -742,14 +764,14 @@ hipError_t launch_fft_corr(hipStream_t st, const gf_batch *b, const gf_psf *p, c
                            float2 *S2, float *out) {
   if (p->h_arows.empty()) return hipSuccess;
   ProfScope ps(st, "k_fft_corr");
-  const size_t lds = fft_lds_bytes(p->max_L);
+  const size_t lds = fft_lds_bytes(p);
   dim3 blk(kThreads);
-  hipLaunchKernelGGL((k_fft_rows<MODE_CORR>), dim3((unsigned)p->h_arows.size(), 1), blk, lds, st, b->d_desc,
+  GF_FFT_LAUNCH(k_fft_rows, MODE_CORR, dim3((unsigned)p->h_arows.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_arows, in, 1, p->d_s1a, S1, (const int *)nullptr, 1 << 20);
-  hipLaunchKernelGGL((k_fft_cols<MODE_CORR>), dim3((unsigned)p->h_acols.size(), 1), blk, lds, st, b->d_desc,
+  GF_FFT_LAUNCH(k_fft_cols, MODE_CORR, dim3((unsigned)p->h_acols.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_acols, 1, p->d_s1a, S1, p->d_otf, p->d_s2a, S2,
                      (const int *)nullptr, 1 << 20);
-  hipLaunchKernelGGL((k_fft_irows<MODE_CORR>), dim3((unsigned)p->h_airows.size(), 1), blk, lds, st, b->d_desc,
+  GF_FFT_LAUNCH(k_fft_irows, MODE_CORR, dim3((unsigned)p->h_airows.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_airows, 1, p->d_s2a, S2, out, (const int *)nullptr,
                      1 << 20, Chi2Epi{});
   return hipGetLastError();
@@ -761,11 +783,11 @@ hipError_t launch_fft_otf(hipStream_t st, const gf_batch *b, const gf_psf *p, co
                           const gf::Work *rows, int n_rows, const gf::Work *cols, int n_cols, const int64_t *s1_off,
                           float2 *S1, const int64_t *otf_off) {
   if (n_rows == 0) return hipSuccess;
-  const size_t lds = fft_lds_bytes(p->max_L);
+  const size_t lds = fft_lds_bytes(p);
   dim3 blk(kThreads);
-  hipLaunchKernelGGL((k_fft_rows<MODE_OTF>), dim3((unsigned)n_rows, 1), blk, lds, st, b->d_desc, p->d_path,
+  GF_FFT_LAUNCH(k_fft_rows, MODE_OTF, dim3((unsigned)n_rows, 1), blk, lds, st, b->d_desc, p->d_path,
                      p->d_plans, p->d_tw, rows, taps, 1, s1_off, S1, (const int *)nullptr, 1 << 20);
-  hipLaunchKernelGGL((k_fft_cols<MODE_OTF>), dim3((unsigned)n_cols, 1), blk, lds, st, b->d_desc, p->d_path,
+  GF_FFT_LAUNCH(k_fft_cols, MODE_OTF, dim3((unsigned)n_cols, 1), blk, lds, st, b->d_desc, p->d_path,
                      p->d_plans, p->d_tw, cols, 1, s1_off, S1, (const float2 *)nullptr, otf_off, p->d_otf,
                      (const int *)nullptr, 1 << 20);
   return hipGetLastError();
