@@ -537,8 +537,8 @@ def cpu_baseline_lines(extra, seconds):
 # channels per launch.  Valid only while the kernel source is the one the
 # counters were taken on (first 16 hex digits of its SHA-256).
 TRAFFIC = {
-    "c2": dict(kernel="k_fft_cols", source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="051ea263b03c9a32",
-               once=1.147e6, per_channel=3.233e6, summary="profiles/c2_fit_hbm_traffic.md"),
+    "c2": dict(kernel="k_eval_jac", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="922a17b603d19fb7",
+               once=1.88000e+07, per_channel=0.0, summary="profiles/c2_fit_hbm_traffic.md"),
     "c4": dict(kernel="k_eval", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="922a17b603d19fb7",
                once=386.24e6, per_channel=0.0, summary="profiles/c4_likelihood_hbm_traffic.md"),
 }
@@ -792,11 +792,12 @@ def main():
     geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = geo["chan_k_fft_irows_chi2"] = 1
     if args.workload in ("c2", "c3", "c5"):
         # per fit the row and column passes run 7 n_comp channels (Jacobian)
-        # and 1 channel (trial) per launch: use the average; the plain
-        # inverse-row pass runs only for the Jacobian, the fused one only for
-        # the trial points
-        n_jac = extra["njev"]
-        n_trial = extra["nfev"]
+        # and 1 channel (trial) per launch: use the average over the launches
+        # of the profiled fit; the plain inverse-row pass runs only for the
+        # Jacobian, the fused one only for the trial points (a speculative
+        # fit has no one-channel launches)
+        n_jac = prof.get("k_eval_jac", (0, 0.0))[0]
+        n_trial = prof.get("k_fft_irows_chi2", (0, 0.0))[0]
         nch = 14 if args.workload == "c2" else 7
         avg = (nch * n_jac + 1 * n_trial) / max(n_jac + n_trial, 1)
         for k in ("rows", "cols"):
