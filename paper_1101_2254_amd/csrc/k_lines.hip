@@ -217,11 +217,13 @@ __global__ __launch_bounds__(kLT) void k_line_chi2(const LineDesc *__restrict__ 
 //   (A + lambda diag(max(A_ii, 1e-12 max A_jj))) delta = g by FP64 Cholesky
 //   (not positive definite: lambda *= up), theta' = clip(theta + delta),
 //   accept iff chi2(theta') < chi2(theta) (compensated FP32 sums).
+// Registers capped for four waves per SIMD (the LDS of the three-line build
+// allows four workgroups per CU; uncapped it took 139 VGPRs, three waves).
 template <int L>
-__global__ __launch_bounds__(kLT) void k_line_lm(const LineDesc *__restrict__ desc, int n,
-                                                 const float *__restrict__ lsf, const float *__restrict__ data,
-                                                 const float *__restrict__ weight, double *__restrict__ theta,
-                                                 LineLMParams prm, gf_lm_result *__restrict__ res) {
+__global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_line_lm(const LineDesc *__restrict__ desc, int n, const float *__restrict__ lsf, const float *__restrict__ data,
+               const float *__restrict__ weight, double *__restrict__ theta, LineLMParams prm,
+               gf_lm_result *__restrict__ res) {
   constexpr int P = 3 * L + 1;    // parameters; the continuum is the last
   static_assert(P + 1 <= 16, "the Gram block holds 16 columns");
   __shared__ float lsf_s[GF_LINE_MAX_K];
