@@ -79,39 +79,56 @@ __global__ __launch_bounds__(kThreads) void k_eval(const StampDesc *__restrict__
 }
 
 // -------------------------------------------------------------- derivatives
-// Point derivatives of one component at offset (dx, dy) from its centre,
-// accumulated into g[0..6] in parameter order [x0, y0, Ie, Re, n, q, phi];
-// the Ie slot holds I/Ie (the model is linear in Ie).  With u = R/Re,
-// t = u^(1/n), E = b_n t:  dI/dRe = I E/(n Re),  dI/dn = I (b'_n (1-t) + E ln u/n^2),
+// Point derivatives of one component at offset (dx, dy) from its centre, in
+// parameter order [x0, y0, Ie, Re, n, q, phi]; the Ie slot holds I/Ie (the
+// model is linear in Ie).  With u = R/Re, t = u^(1/n), E = b_n t:
+// dI/dRe = I E/(n Re),  dI/dn = I (b'_n (1-t) + E ln u/n^2),
 // dI/d(R^2) = -I E/(2 n R^2).  At R = 0 exactly the 1/R^2 and ln u terms are 0.
-struct PointGrad {
-  float g[kNPC];
+// The rotation, axis-ratio and n factors are constants of the component, so
+// each sub-sample only adds to eight sums (w = -2 dI/d(R^2), x' and y' the
+// rotated offsets, y'' = y'/q^2):
+//   U = sum w x', V = sum w y'', W5 = sum w y'' y', W6 = sum w x' y',
+//   sum I/Ie, sum I E, A4 = sum I (1-t), B4 = sum I E log2 t,
+// and grad_finish turns them into the seven derivatives once per pixel.
+struct GradAcc {
+  float U = 0.f, V = 0.f, W5 = 0.f, W6 = 0.f, Js = 0.f, IEs = 0.f, A4 = 0.f, B4 = 0.f;
 };
 
-__device__ __forceinline__ void point_grad(const CompC &C, float dx, float dy, float *g) {
+__device__ __forceinline__ void grad_acc(const CompC &C, float dx, float dy, GradAcc &a) {
   const float xp = fmaf(dx, C.cs, dy * C.sn);
   const float yp = fmaf(-dx, C.sn, dy * C.cs);
-  const float r2 = fmaf(C.iq2 * yp, yp, xp * xp);
+  const float yi = C.iq2 * yp;
+  const float r2 = fmaf(yi, yp, xp * xp);
   const float l2 = fast_log2(r2);
   const float lt = fmaf(l2, C.a1, C.a0);               // log2 t
   const float t = fast_exp2(lt);
   const float omt = 1.0f - t;
   const float J = fast_exp2(C.b1 * omt);               // I / Ie
   const float I = J * C.ie;
-  const float E = C.bn * t;
+  const float IE = I * (C.bn * t);
   const bool nz = r2 > 0.0f;
-  // ln u = (log2(R^2)/2 - log2 Re) ln 2 = log2(t) * n * ln 2
-  const float lnu = lt * (C.n * 0.69314718055994531f);
-  const float IE = I * E;
-  const float G = nz ? (IE * (-0.5f * C.inv_n)) * __builtin_amdgcn_rcpf(r2) : 0.0f;   // dI / d(R^2)
-  const float m2G = -2.0f * G;
-  g[0] = fmaf(m2G, fmaf(xp, C.cs, -yp * C.sn * C.iq2), g[0]);
-  g[1] = fmaf(m2G, fmaf(xp, C.sn, yp * C.cs * C.iq2), g[1]);
-  g[2] += J;
-  g[3] = fmaf(IE, C.inv_n * C.inv_re, g[3]);
-  g[4] = fmaf(I, fmaf(C.dbn, omt, nz ? E * lnu * (C.inv_n * C.inv_n) : 0.0f), g[4]);
-  g[5] = fmaf(m2G * yp * yp, C.iq2 * C.inv_q, g[5]);
-  g[6] = fmaf(-m2G * xp * yp, 1.0f - C.iq2, g[6]);
+  const float w = nz ? (IE * C.inv_n) * __builtin_amdgcn_rcpf(r2) : 0.0f;   // -2 dI / d(R^2)
+  const float u = w * xp, v = w * yi;
+  a.U += u;
+  a.V += v;
+  a.W5 = fmaf(v, yp, a.W5);
+  a.W6 = fmaf(u, yp, a.W6);
+  a.Js += J;
+  a.IEs += IE;
+  a.A4 = fmaf(I, omt, a.A4);
+  a.B4 = fmaf(IE, nz ? lt : 0.0f, a.B4);
+}
+
+// d x'/d x0 = -cos, d y'/d x0 = sin, ... applied to the sums; ln u / n^2 =
+// log2(t) ln 2 / n.
+__device__ __forceinline__ void grad_finish(const CompC &C, const GradAcc &a, float *g) {
+  g[0] = fmaf(C.cs, a.U, -C.sn * a.V);
+  g[1] = fmaf(C.sn, a.U, C.cs * a.V);
+  g[2] = a.Js;
+  g[3] = a.IEs * (C.inv_n * C.inv_re);
+  g[4] = fmaf(C.dbn, a.A4, a.B4 * (0.69314718055994531f * C.inv_n));
+  g[5] = a.W5 * C.inv_q;
+  g[6] = -a.W6 * (1.0f - C.iq2);
 }
 
 // Writes 7 * ncomp channels per stamp on the padded grid: channel 7k + p is
@@ -139,13 +156,15 @@ __global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restri
   for (int k = 0; k < d.ncomp; ++k) {
     const CompC C = cc[k];
     const float jx = (float)(j - C.ix), iy = (float)(i - C.iy);
-    float g[kNPC] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    GradAcc acc;
 #pragma unroll 1
     for (int b = 0; b < S; ++b) {
       const float dy = iy + cc[k].oy[b];
 #pragma unroll
-      for (int a = 0; a < S; ++a) point_grad(C, jx + C.ox[a], dy, g);
+      for (int a = 0; a < S; ++a) grad_acc(C, jx + C.ox[a], dy, acc);
     }
+    float g[kNPC];
+    grad_finish(C, acc, g);
 #pragma unroll
     for (int q = 0; q < kNPC; ++q) o[(int64_t)(kNPC * k + q) * npad] = g[q] * (1.0f / (float)(S * S));
   }
@@ -180,13 +199,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
     for (int k = 0; k < d.ncomp; ++k) {
       const CompC C = cc[k];
       const float jx = (float)(j - C.ix), iy = (float)(i - C.iy);
-      float g[kNPC] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      GradAcc ga;
 #pragma unroll 1
       for (int b = 0; b < S; ++b) {
         const float dy = iy + cc[k].oy[b];
 #pragma unroll
-        for (int aa = 0; aa < S; ++aa) point_grad(C, jx + C.ox[aa], dy, g);
+        for (int aa = 0; aa < S; ++aa) grad_acc(C, jx + C.ox[aa], dy, ga);
       }
+      float g[kNPC];
+      grad_finish(C, ga, g);
       // Ie slot: dI/dIe = I/Ie
 #pragma unroll
       for (int q = 0; q < kNPC; ++q) {
