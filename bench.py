@@ -65,7 +65,7 @@ def parse():
 # Evaluation: FP32 operations per sub-sample and component, counting an FMA as
 # two and a transcendental (log2 / exp2) as one.
 EVAL_FLOP_PER_SUB = 17
-EVAL_JAC_FLOP_PER_SUB = 54
+EVAL_JAC_FLOP_PER_SUB = 35
 
 
 def kernel_work(name, geo, launches_per_step):
