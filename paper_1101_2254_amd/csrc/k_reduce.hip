@@ -533,9 +533,10 @@ __global__ void k_lm_clip(int64_t n_par, double *__restrict__ theta, const doubl
 
 // One workgroup per active stamp.
 //  1. When the Jacobian is new, the workgroup adds the stamp's Gram partials
-//     in FP64 (16 slices of 64 threads, each thread owning four entries of
+//     in FP64 (8 slices of 64 threads, each thread owning four entries of
 //     the 16 x 16 block; wide loads, because one workgroup reads all of a
-//     large stamp's partials); A = G[0..P-1][0..P-1] (symmetrised from the
+//     large stamp's partials; 512 threads, so two workgroups share a CU in
+//     batches); A = G[0..P-1][0..P-1] (symmetrised from the
 //     lower triangle)
 //     and g = G[0..P-1][P] are kept in Ag for the later iterations that reuse
 //     this Jacobian.
@@ -555,7 +556,7 @@ __device__ __forceinline__ double bcast(double v, int l) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-constexpr int kSolveThreads = 1024;
+constexpr int kSolveThreads = 512;
 constexpr int kSolveSlices = kSolveThreads / 64;
 
 template <int NC>
