@@ -537,10 +537,16 @@ def cpu_baseline_lines(extra, seconds):
 # channels per launch.  Valid only while the kernel source is the one the
 # counters were taken on (first 16 hex digits of its SHA-256).
 TRAFFIC = {
-    "c2": dict(kernel="k_eval_jac", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="922a17b603d19fb7",
-               once=1.88000e+07, per_channel=0.0, summary="profiles/c2_fit_hbm_traffic.md"),
-    "c4": dict(kernel="k_eval", source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="922a17b603d19fb7",
-               once=386.24e6, per_channel=0.0, summary="profiles/c4_likelihood_hbm_traffic.md"),
+    "c2": {
+        "k_eval_jac": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="4c929de5291c6242", once=1.8800e+07,
+                           per_channel=0.0),
+        "k_fft_cols": dict(source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="cb831d803c9c3d12", once=1.1472e+06,
+                           per_channel=3.2334e+06),
+        "summary": "profiles/c2_fit_hbm_traffic.md"},
+    "c4": {
+        "k_eval": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="4c929de5291c6242",
+                       once=3.8624e+08, per_channel=0.0),
+        "summary": "profiles/c4_likelihood_hbm_traffic.md"},
 }
 
 
@@ -585,8 +591,8 @@ def stage_roofline(prof, geo):
 
 def measured_traffic(workload, rl, geo):
     import hashlib
-    t = TRAFFIC.get(workload)
-    if not t or rl.get("kernel") != t["kernel"]:
+    t = TRAFFIC.get(workload, {}).get(rl.get("kernel"))
+    if not t:
         return None
     try:
         with open(os.path.join(ROOT, t["source"]), "rb") as f:
@@ -594,7 +600,7 @@ def measured_traffic(workload, rl, geo):
                 return None
     except OSError:
         return None
-    return round(t["once"] + t["per_channel"] * geo.get("chan_" + t["kernel"], 1), 0)
+    return round(t["once"] + t["per_channel"] * geo.get("chan_" + rl["kernel"], 1), 0)
 
 
 def roofline(prof, geo):
