@@ -202,13 +202,17 @@ FftPlan make_plan(int L, int tw_off) {
   std::memset(&p, 0, sizeof(p));
   p.L = L;
   p.tw_off = tw_off;
-  std::vector<int> rad, rad18;
+  std::vector<int> rad, rad18, rad24;
   best_plan(L, 32, rad);
-  // A plan of radices up to 18 runs in the FFT kernels built without the
-  // larger butterflies (fewer registers, more waves per SIMD): take it when
-  // it needs no more LDS passes than the best plan overall.
+  // A plan of radices up to 18 (else 24) runs in the FFT kernels built
+  // without the larger butterflies (fewer registers, more waves per SIMD):
+  // take it when it needs no more LDS passes than the best plan overall.
   best_plan(L, 18, rad18);
-  if (!rad18.empty() && rad18.size() <= rad.size()) rad = rad18;
+  best_plan(L, 24, rad24);
+  if (!rad18.empty() && rad18.size() <= rad.size())
+    rad = rad18;
+  else if (!rad24.empty() && rad24.size() <= rad.size())
+    rad = rad24;
   p.nstages = (int)rad.size();
   int ns = 1;
   for (int s = 0; s < p.nstages; ++s) {
@@ -532,7 +536,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
       seen[L] = 1;
       const FftPlan pl = make_plan(L, 0);
       for (int q = 0; q < pl.nstages; ++q)
-        if (pl.radix[q] > 18) p->rmax = 32;
+        p->rmax = std::max(p->rmax, pl.radix[q] <= 18 ? 18 : pl.radix[q] <= 24 ? 24 : 32);
     }
   }
   const int cap = fft_cap(p->rmax);

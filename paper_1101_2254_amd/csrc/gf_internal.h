@@ -20,11 +20,13 @@ constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one 
 constexpr int kPixChunk = 4096;        // pixels per chi^2 workgroup (16 per thread)
 constexpr int kNeqChunk = 1024;        // pixels per normal-equation workgroup (256 per wave)
 // Complex values in the FFT LDS buffer of a workgroup (T*L <= this).  The
-// kernels built for plan radices up to 18 need fewer registers; with the
-// smaller buffer five of their workgroups fit on a CU instead of four.
+// kernels built for plan radices up to 18 or up to 24 need fewer registers;
+// with their smaller buffers five workgroups fit on a CU instead of four
+// (for the radix-24 build up to L = 576).
 constexpr int kFftCap = 3840;
 constexpr int kFftCapSmall = 3456;
-constexpr int fft_cap(int rmax) { return rmax <= 18 ? kFftCapSmall : kFftCap; }
+constexpr int kFftCapMid = 3408;
+constexpr int fft_cap(int rmax) { return rmax <= 18 ? kFftCapSmall : rmax <= 24 ? kFftCapMid : kFftCap; }
 constexpr int kFftMaxStages = 12;
 constexpr int kFftNarrowT = 1;         // row pairs per workgroup in the narrow launch shape
 constexpr int kFftNarrowC = 2;         // bins per workgroup in the narrow launch shape
@@ -305,7 +307,7 @@ struct gf_psf {
   float2 *d_otf = nullptr;     // OTFs [L][L/2+1] per stamp (one if shared)
   int64_t n_otf = 0;
   int max_L = 0;
-  int rmax = 18;               // 32 when a plan has a radix above 18 (the FFT kernels are built for 18 and 32)
+  int rmax = 18;               // largest plan radix class: 18, 24 or 32 (the FFT kernels are built for each)
   // FFT work lists: forward rows (padded rows), columns, inverse rows (output rows)
   std::vector<gf::Work> h_rows, h_cols, h_irows, h_arows, h_acols, h_airows;
   gf::Work *d_rows = nullptr, *d_cols = nullptr, *d_irows = nullptr;

@@ -342,8 +342,8 @@ __device__ __forceinline__ void stockham_pass(float2 *__restrict__ buf, int T, i
 }
 
 // Full transform of T transforms in place (T * L <= fft_cap(RMAX)).  RMAX is the
-// largest radix the kernel is built for: plans of radices up to 18 run in
-// kernels without the larger register butterflies, which need fewer
+// largest radix the kernel is built for (18, 24 or 32): plans of small radices
+// run in kernels without the larger register butterflies, which need fewer
 // registers and so keep more waves per SIMD.
 template <bool INV, int RMAX>
 __device__ __forceinline__ void lds_fft(float2 *buf, int T, int Ls, const FftPlan &pl, const float2 *tw) {
@@ -370,9 +370,15 @@ __device__ __forceinline__ void lds_fft(float2 *buf, int T, int Ls, const FftPla
           switch (R) {
             case 20: stockham_pass<20, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
             case 24: stockham_pass<24, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-            case 25: stockham_pass<25, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-            case 27: stockham_pass<27, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
-            default: stockham_pass<32, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+            default:
+              if constexpr (RMAX > 24) {
+                switch (R) {
+                  case 25: stockham_pass<25, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+                  case 27: stockham_pass<27, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+                  default: stockham_pass<32, INV, CAP>(buf, T, L, Ls, Ns, nsm, nbm, tw); break;
+                }
+              }
+              break;
           }
         }
         break;
@@ -712,6 +718,8 @@ static size_t fft_lds_bytes(const gf_psf *p) { return (size_t)(fft_lds(fft_cap(p
   do {                                                                   \
     if (p->rmax <= 18)                                                   \
       hipLaunchKernelGGL((KERNEL<MODE, 18>), __VA_ARGS__);               \
+    else if (p->rmax <= 24)                                              \
+      hipLaunchKernelGGL((KERNEL<MODE, 24>), __VA_ARGS__);               \
     else                                                                 \
       hipLaunchKernelGGL((KERNEL<MODE, 32>), __VA_ARGS__);               \
   } while (0)
