@@ -232,8 +232,9 @@ typedef struct {
   double chi2;     /* chi^2 at the returned parameters */
   double lambda;   /* damping at exit */
   int32_t iters;   /* iterations taken */
-  int32_t nfev;    /* model evaluations (steps 1-3) */
-  int32_t njev;    /* Jacobian evaluations */
+  int32_t nfev;    /* model evaluations (steps 1-3): the start point and every trial */
+  int32_t njev;    /* Jacobians that enter a solve (with speculate, every trial also evaluates
+                      one, from which its model comes) */
   int32_t status;  /* GF_OK (converged) or GF_ENOTCONV */
   int32_t reason;  /* 1 ftol, 2 xtol, 3 chi2 = 0, 4 lambda above lambda_max, 5 iteration cap */
   int32_t pad;
