@@ -130,3 +130,27 @@ def test_speculative_edge_cases(ctx, gfo):
     with pytest.raises(L.GfError):
         L.gf_fit_lm(ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(gb.data.data_ptr()), int(gb.weight.data_ptr()),
                     int(start.data_ptr()), o, int(start.data_ptr()))
+
+
+def test_speculative_direct_path_stamps(ctx, gfo):
+    # small PSFs take the direct convolution: the speculative iterations
+    # convolve their Jacobian images on that path too
+    g = synth.rng(83)
+    stamps = []
+    for i, N in enumerate([32, 48, 40]):
+        st = synth.c3_stamp(g, N, i, 8300 + i)
+        st.psf = synth.gaussian_psf(5, 1.0)
+        stamps.append(st)
+    gb, lo, hi = _problem(ctx, gfo, stamps)
+    assert not any(gb.psf.uses_fft)
+    start = to_dev(np.concatenate([s.start for s in stamps]), torch.float64)
+    res = {}
+    for spec in (0, 1):
+        print(f"direct-path stamps, speculate={spec}", flush=True)
+        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-6,
+                              speculate=spec)
+        th = th.cpu().numpy()
+        assert np.all(np.isfinite(th)) and np.all((info["status"] == L.GF_OK) | (info["reason"] == 4)), info
+        _check_chi2_at_theta(gfo, gb, th, info)
+        res[spec] = info
+    np.testing.assert_allclose(res[1]["chi2"], res[0]["chi2"], rtol=1e-5)
