@@ -40,7 +40,8 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *, float *, int, int, const int *, const WorkView *, float2 *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
                           int *);
-hipError_t launch_lm_clip(hipStream_t, int64_t, double *, const double *, const double *, double *);
+hipError_t launch_lm_start(hipStream_t, const gf_batch *, double *, const double *, const double *, double *, int,
+                           const float4 *, CompC *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *);
 hipError_t launch_chi2_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, const void *, bool,
@@ -1082,18 +1083,18 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   auto run = [&]() -> gf_status {
     GF_TRY(c, hipEventRecord(ev, c->stream));
     GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
-    // start point: clip, evaluate, chi2 (speculative: the Jacobian images and
+    // start point: clip and set up, evaluate, chi2 (speculative: the Jacobian images and
     // normal equations of the start point, chi^2 from the same model)
-    GF_TRY(c, launch_lm_clip(cs, b->n_par, theta, o.lo, o.hi, B.theta_t));
+    GF_TRY(c, launch_lm_start(cs, b, theta, o.lo, o.hi, B.theta_t, S, c->d_bn, B.cc_th));
     if (spec) {
-      GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, nullptr, nullptr, B.cc_th, true));
+      GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, nullptr, nullptr, B.cc_th, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, nullptr, nullptr));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, nullptr, nullptr));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, nullptr, nullptr,
                                  B.gpart));
       GF_TRY(c, launch_lm_init(cs, b, o.lambda0, b->d_neq_first, B.gpart, B.st, B.mjac, B.mtrial, B.cnt));
     } else {
-      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, true));
+      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
                           nullptr));
       GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt));

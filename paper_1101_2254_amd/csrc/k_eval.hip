@@ -34,6 +34,34 @@ __global__ void k_comp_prep(const StampDesc *__restrict__ desc, int n, const TT 
   if (k < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * k, bn_tab, S, cc[i]);
 }
 
+// Start of an LM fit: the start point clipped into the box (written to theta
+// and to the trial buffer) and its component constants, in one launch.
+// Thread (stamp, k) clips the seven parameters of component k, and the sky
+// for k = 0, then sets up component k from the clipped values.
+__global__ void k_lm_start(const StampDesc *__restrict__ desc, int n, double *__restrict__ theta,
+                           const double *__restrict__ lo, const double *__restrict__ hi,
+                           double *__restrict__ theta_t, const float4 *__restrict__ bn_tab, int S,
+                           CompC *__restrict__ cc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = i / kMaxComp, k = i - s * kMaxComp;
+  if (s >= n) return;
+  const StampDesc d = desc[s];
+  if (k >= d.ncomp) return;
+  auto clip = [&](int64_t j) {
+    double v = theta[j];
+    if (lo && v < lo[j]) v = lo[j];
+    if (hi && v > hi[j]) v = hi[j];
+    theta[j] = v;
+    theta_t[j] = v;
+    return v;
+  };
+  double t[kNPC];
+#pragma unroll
+  for (int q = 0; q < kNPC; ++q) t[q] = clip(d.par + kNPC * k + q);
+  if (k == 0) (void)clip(d.par + kNPC * d.ncomp);
+  comp_setup<double>(t, bn_tab, S, cc[i]);
+}
+
 // ----------------------------------------------------------------- values
 // R^2 = x'^2 + (y'/q)^2 with y'/q formed directly from cos phi / q and
 // sin phi / q (one multiply fewer per sub-sample than scaling y'^2).
@@ -279,6 +307,15 @@ hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, in
 
 // cc: where the component constants live (null: the batch's buffer); prep:
 // compute them from theta first (false: the caller keeps them current).
+hipError_t launch_lm_start(hipStream_t st, const gf_batch *b, double *theta, const double *lo, const double *hi,
+                           double *theta_t, int S, const float4 *bn, CompC *cc) {
+  if (S < 1 || S > GF_MAX_OVERSAMPLE) return hipErrorInvalidValue;
+  const int nt = b->n * kMaxComp;
+  hipLaunchKernelGGL(k_lm_start, dim3((nt + 63) / 64), dim3(64), 0, st, b->d_desc, b->n, theta, lo, hi, theta_t, bn,
+                     S, cc);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval_d(hipStream_t st, const gf_batch *b, const double *theta, int S, const float4 *bn,
                          float *out, const int *mask, const WorkView *v, CompC *cc, bool prep) {
   return launch_eval_t<double>(st, b, theta, S, bn, out, mask, v, cc, prep);

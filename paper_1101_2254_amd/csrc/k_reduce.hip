@@ -519,18 +519,6 @@ __global__ __launch_bounds__(64) void k_lm_init(int n, double lambda0, const int
   mtrial[s] = 0;
 }
 
-// Clip the start point into the box: theta_t = clip(theta).
-__global__ void k_lm_clip(int64_t n_par, double *__restrict__ theta, const double *__restrict__ lo,
-                          const double *__restrict__ hi, double *__restrict__ theta_t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_par) return;
-  double v = theta[i];
-  if (lo && v < lo[i]) v = lo[i];
-  if (hi && v > hi[i]) v = hi[i];
-  theta[i] = v;
-  theta_t[i] = v;
-}
-
 // One workgroup per active stamp.
 //  1. When the Jacobian is new, the workgroup adds the stamp's Gram partials
 //     in FP64 (8 slices of 64 threads, each thread owning four entries of
@@ -934,13 +922,6 @@ hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, con
                           const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt) {
   hipLaunchKernelGGL(k_lm_init, dim3((unsigned)b->n), dim3(64), 0, st, b->n, lambda0, first, part, S, mjac, mtrial,
                      cnt);
-  return hipGetLastError();
-}
-
-hipError_t launch_lm_clip(hipStream_t st, int64_t n_par, double *theta, const double *lo, const double *hi,
-                          double *theta_t) {
-  hipLaunchKernelGGL(k_lm_clip, dim3((unsigned)((n_par + 255) / 256)), dim3(256), 0, st, n_par, theta, lo, hi,
-                     theta_t);
   return hipGetLastError();
 }
 
