@@ -538,13 +538,13 @@ def cpu_baseline_lines(extra, seconds):
 # counters were taken on (first 16 hex digits of its SHA-256).
 TRAFFIC = {
     "c2": {
-        "k_eval_jac": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="4c929de5291c6242", once=1.8800e+07,
+        "k_eval_jac": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="a105fba5eba902aa", once=1.8800e+07,
                            per_channel=0.0),
         "k_fft_cols": dict(source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="e5ad3e6d0c9bfbf0", once=1.5038e+06,
                            per_channel=2.8225e+06),
         "summary": "profiles/c2_fit_hbm_traffic.md"},
     "c4": {
-        "k_eval": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="4c929de5291c6242", once=3.8624e+08,
+        "k_eval": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="a105fba5eba902aa", once=3.8624e+08,
                        per_channel=0.0),
         "summary": "profiles/c4_likelihood_hbm_traffic.md"},
 }
