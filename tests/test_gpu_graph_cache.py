@@ -89,6 +89,13 @@ def test_graph_reuse_matches_fresh_context(ctx, gfo):
     # a new start tensor is a new pointer
     p1.start = p1.start.clone()
     _same(p1.fit(ctx, ftol=1e-5), ref1)
+    # another entry point grows (reallocates) the context's workspace
+    g = synth.rng(72)
+    big = [synth.c3_stamp(g, 256, i, 7200 + i) for i in range(48)]
+    gbig = GpuBatch(ctx, big)
+    ops.likelihood(ctx, gbig.batch, gbig.psf, gbig.theta, torch.zeros(gbig.batch.sizes["n_img"], device=ctx.device),
+                   torch.ones(gbig.batch.sizes["n_img"], device=ctx.device), 5)
+    _same(p1.fit(ctx, ftol=1e-5), ref1)
     # batch and PSF destroyed and replaced by another shape
     p1.gb.psf.close()
     p1.gb.batch.close()
