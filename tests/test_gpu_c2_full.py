@@ -1,0 +1,64 @@
+"""The benchmarked fit at its full size (one 512x512 image, Sersic bulge +
+exponential disk, 65x65 Moffat PSF, 576-point FFT, 15 parameters, the
+speculative iterations a single stamp takes by default) against the FP64
+oracle's fit of the same oracle-rendered observation."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_1101_2254_amd import _lib as L
+from paper_1101_2254_amd import ops
+from tests.gpu_common import GpuBatch, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("gpu c2 full size: creating context on cuda:0", flush=True)
+    c = ops.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def test_c2_fit_full_size_matches_oracle(ctx, gfo):
+    st = synth.c2()
+    psf64 = st.psf.astype(np.float32).astype(np.float64)
+    m = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf64, 5)
+    d, w = synth.add_poisson_read_noise(m, st.meta["read_noise"], st.meta["gain"], st.noise_seed)
+    gb = GpuBatch(ctx, [st], data=[d], weights=[w], mode=ops.GF_CONV_FFT)
+    assert list(gb.psf.uses_fft) == [1] and list(gb.psf.fft_side) == [576]
+    lo, hi = synth.bounds(2, st.H, st.W)
+    d64, w64 = gb.d32[0].astype(np.float64), gb.w32[0].astype(np.float64)
+    print("oracle fit of the 512x512 image", flush=True)
+    ref, rinfo = gfo.fit_lm(st.start, psf64, d64, w64, 5, lo=lo, hi=hi, ftol=1e-8)
+    assert rinfo["status"] == 0, rinfo
+    for ftol in (1e-8, 1e-5):
+        print(f"GPU fit, ftol {ftol}", flush=True)
+        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(st.start, torch.float64),
+                              lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=ftol)
+        th = th.cpu().numpy()
+        assert info["status"][0] == L.GF_OK or info["reason"][0] == 4, info
+        # the reported chi^2 is the oracle's at the returned parameters
+        mt = gfo.model(st.H, st.W, th, psf64, 5)
+        c_at = gfo.chi2(d64, w64, mt)
+        wm = math.sqrt(float(np.sum(w64 * mt * mt)))
+        assert abs(info["chi2"][0] - c_at) <= 1e-5 * c_at + 2 * 2e-6 * math.sqrt(c_at) * wm, (info["chi2"][0], c_at)
+        # the same minimum: chi^2 within the tolerance the fit stops at
+        assert info["chi2"][0] == pytest.approx(rinfo["chi2"], rel=max(ftol, 1e-6)), (info["chi2"][0], rinfo)
+        if ftol == 1e-8:
+            for k in range(2):
+                re = abs(ref[7 * k + 3])
+                for p in range(7):
+                    i = 7 * k + p
+                    if p == 6:
+                        dd = (th[i] - ref[i] + math.pi / 2) % math.pi - math.pi / 2
+                        assert abs(dd) <= 1e-4 * math.pi, (i, th[i], ref[i])
+                    else:
+                        s = re if p in (0, 1) else 0.0
+                        assert abs(th[i] - ref[i]) <= 1e-4 * max(abs(ref[i]), s), (i, th[i], ref[i])
+            assert abs(th[-1] - ref[-1]) <= 1e-4 * abs(ref[-1]), (th[-1], ref[-1])
