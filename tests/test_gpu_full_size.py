@@ -1,7 +1,9 @@
-"""The benchmarked fit at its full size (one 512x512 image, Sersic bulge +
-exponential disk, 65x65 Moffat PSF, 576-point FFT, 15 parameters, the
-speculative iterations a single stamp takes by default) against the FP64
-oracle's fit of the same oracle-rendered observation."""
+"""The benchmarked configurations at their full sizes against the FP64
+oracle on oracle-rendered observations: the fit of one 512x512 image (Sersic
+bulge + exponential disk, 65x65 Moffat PSF, 576-point FFT, 15 parameters, the
+speculative iterations a single stamp takes by default), and the likelihood
+step of 1024 parameter vectors against one 256x256 image (33x33 Moffat PSF,
+288-point FFT) on sampled vectors."""
 import math
 
 import numpy as np
@@ -18,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def ctx():
-    print("gpu c2 full size: creating context on cuda:0", flush=True)
+    print("gpu full size: creating context on cuda:0", flush=True)
     c = ops.Context(0)
     yield c
     torch.cuda.synchronize()
@@ -62,3 +64,24 @@ def test_c2_fit_full_size_matches_oracle(ctx, gfo):
                         s = re if p in (0, 1) else 0.0
                         assert abs(th[i] - ref[i]) <= 1e-4 * max(abs(ref[i]), s), (i, th[i], ref[i])
             assert abs(th[-1] - ref[-1]) <= 1e-4 * abs(ref[-1]), (th[-1], ref[-1])
+
+
+def test_c4_likelihood_full_batch_sampled(ctx, gfo):
+    base = synth.c4_truth()
+    psf64 = base.psf.astype(np.float32).astype(np.float64)
+    m = gfo.model(256, 256, base.truth.astype(np.float32).astype(np.float64), psf64, 5)
+    d, w = synth.add_gaussian_noise(m, 0.02, base.noise_seed)
+    th = synth.c4_vectors(0, 1024)
+    gb = GpuBatch(ctx, [base] * 1024, thetas=list(th), data=[d], weights=[w], shared=True)
+    assert list(gb.psf.fft_side)[:1] == [288]
+    print("likelihood of 1024 vectors", flush=True)
+    chi = ops.pairs_to_f64(ops.likelihood(ctx, gb.batch, gb.psf, gb.theta, gb.data, gb.weight, 5)).cpu().numpy()
+    assert np.all(np.isfinite(chi))
+    d64, w64 = gb.d32[0].astype(np.float64), gb.w32[0].astype(np.float64)
+    for s in (0, 1, 255, 511, 777, 1023):
+        mt = gfo.model(256, 256, gb.th64(s), psf64, 5)
+        ref = gfo.chi2(d64, w64, mt)
+        # away from the minimum the FP32 model error enters through the cross
+        # term (Cauchy-Schwarz), as in the other trial-point checks
+        wm = math.sqrt(float(np.sum(w64 * mt * mt)))
+        assert abs(chi[s] - ref) <= 1e-5 * ref + 2 * 2e-6 * math.sqrt(ref) * wm, (s, chi[s], ref)
