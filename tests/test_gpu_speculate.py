@@ -154,3 +154,23 @@ def test_speculative_direct_path_stamps(ctx, gfo):
         _check_chi2_at_theta(gfo, gb, th, info)
         res[spec] = info
     np.testing.assert_allclose(res[1]["chi2"], res[0]["chi2"], rtol=1e-5)
+
+
+def test_speculative_free_mask(ctx, gfo):
+    # fixed parameters (n, q and PA held) stay at the start in both forms and
+    # the fits reach the same chi^2
+    stamps = _stamps(84, 3)
+    gb, lo, hi = _problem(ctx, gfo, stamps)
+    st0 = np.concatenate([s.start for s in stamps])
+    start = to_dev(st0, torch.float64)
+    free = np.concatenate([[1, 1, 1, 1, 0, 0, 0, 1] for _ in stamps]).astype(np.uint8)
+    out = {}
+    for spec in (0, 1):
+        print(f"free mask, speculate={spec}", flush=True)
+        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-6,
+                              free=to_dev(free, torch.uint8), speculate=spec)
+        th = th.cpu().numpy()
+        np.testing.assert_array_equal(th[free == 0], np.clip(st0, lo.cpu().numpy(), hi.cpu().numpy())[free == 0])
+        _check_chi2_at_theta(gfo, gb, th, info)
+        out[spec] = info
+    np.testing.assert_allclose(out[1]["chi2"], out[0]["chi2"], rtol=1e-5)
