@@ -174,3 +174,24 @@ def test_speculative_free_mask(ctx, gfo):
         _check_chi2_at_theta(gfo, gb, th, info)
         out[spec] = info
     np.testing.assert_allclose(out[1]["chi2"], out[0]["chi2"], rtol=1e-5)
+
+
+def test_speculative_nonfinite_stamp_in_batch(ctx, gfo):
+    # one stamp's data holds a NaN: that fit ends at its (clipped) start by the
+    # damping cap; the other stamps of the batch fit as they do without it
+    stamps = _stamps(85, 3)
+    gb, lo, hi = _problem(ctx, gfo, stamps)
+    start = to_dev(np.concatenate([s.start for s in stamps]), torch.float64)
+    ref, rinfo = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-6,
+                            speculate=1)
+    bad = gb.data.clone()
+    bad[gb.batch.offsets["img"][1] + 5] = float("nan")
+    th, info = ops.fit_lm(ctx, gb.batch, gb.psf, bad, gb.weight, start, lo=lo, hi=hi, ftol=1e-6, speculate=1)
+    th, ref = th.cpu().numpy(), ref.cpu().numpy()
+    po = gb.batch.offsets["par"]
+    assert info["status"][1] == L.GF_ENOTCONV and info["reason"][1] == 4
+    s1 = np.clip(np.concatenate([s.start for s in stamps]), lo.cpu().numpy(), hi.cpu().numpy())
+    np.testing.assert_array_equal(th[po[1]:po[1] + 8], s1[po[1]:po[1] + 8])
+    for s in (0, 2):
+        np.testing.assert_array_equal(th[po[s]:po[s] + 8], ref[po[s]:po[s] + 8])
+        assert info["chi2"][s] == rinfo["chi2"][s]
