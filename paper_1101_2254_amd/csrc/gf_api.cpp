@@ -43,12 +43,14 @@ hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *
 hipError_t launch_lm_start(hipStream_t, const gf_batch *, double *, const double *, const double *, double *, int,
                            const float4 *, CompC *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
-                           const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *);
+                           const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *,
+                           const WorkView *);
 hipError_t launch_chi2_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, const void *, bool,
                               const float *, const float *, float2 *, const int *, const WorkView *);
 hipError_t launch_pair_final(hipStream_t, int, const int32_t *, const float2 *, float2 *, const int *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const int32_t *, const float2 *,
-                            LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *);
+                            LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *,
+                            const WorkView *);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
 hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
@@ -928,14 +930,14 @@ struct LMBufs {
 int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
   return (int64_t)b->h_eval.size() + b->h_pix.size() + b->h_neq.size() + p->h_rows.size() + p->h_cols.size() +
          p->h_irows.size() + p->h_rows_n.size() + p->h_cols_n.size() + p->h_irows_n.size() + p->h_direct.size() +
-         p->h_pix_direct.size();
+         p->h_pix_direct.size() + b->n;
 }
 
 // Work lists restricted to the stamps flagged in act, filtered from `from`
 // (the previous restriction, or the full lists when `from` is empty), stored
 // in `to` and uploaded into dev; the view points into dev.
 struct HostLists {
-  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct, pix_direct;
+  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct, pix_direct, stamps;
   bool empty() const { return eval.empty() && pix.empty(); }
 };
 
@@ -960,6 +962,9 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   filt(full ? p->h_irows_n : from.irows_n, to.irows_n);
   filt(full ? p->h_direct : from.direct, to.direct);
   filt(full ? p->h_pix_direct : from.pix_direct, to.pix_direct);
+  to.stamps.clear();
+  for (int s = 0; s < b->n; ++s)
+    if (act[s]) to.stamps.push_back({s, 0});
   Work *q = dev;
   auto put = [&](const std::vector<Work> &src, const Work *&ptr, int &n) -> hipError_t {
     ptr = q;
@@ -983,6 +988,7 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   if (e == hipSuccess) e = put(to.irows_n, v.irows_n, v.n_irows_n);
   if (e == hipSuccess) e = put(to.direct, v.direct, v.n_direct);
   if (e == hipSuccess) e = put(to.pix_direct, v.pix_direct, v.n_pix_direct);
+  if (e == hipSuccess) e = put(to.stamps, v.stamps, v.n_stamps);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors must outlive the copies
   return e;
 }
@@ -1109,14 +1115,14 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     // solve reuses the stored system of the current point.
     auto iteration_spec = [&]() -> gf_status {
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
-                                B.cc_t, c->d_bn));
+                                B.cc_t, c->d_bn, vw));
       GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, B.mtrial, vw, B.cc_t, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mtrial, vw));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mtrial, vw));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, B.mtrial, vw,
                                  B.gpart));
       GF_TRY(c, launch_lm_update(cs, b, &o, b->d_neq_first, B.gpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, B.cc_th, B.cc_t));
+                                 B.cnt, B.cc_th, B.cc_t, vw));
       return GF_OK;
     };
     auto iteration = [&]() -> gf_status {
@@ -1126,12 +1132,12 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr));
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
-                                B.cc_t, c->d_bn));
+                                B.cc_t, c->d_bn, vw));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
                           vw));
       GF_TRY(c, launch_lm_update(cs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, B.cc_th, B.cc_t));
+                                 B.cnt, B.cc_th, B.cc_t, vw));
       return GF_OK;
     };
     // capture one iteration into (g, e), replacing what they held
@@ -1200,6 +1206,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           cur.irows_n.swap(nxt.irows_n);
           cur.direct.swap(nxt.direct);
           cur.pix_direct.swap(nxt.pix_direct);
+          cur.stamps.swap(nxt.stamps);
           vw = &view;
           view_stamps = active;
           if (exec) {

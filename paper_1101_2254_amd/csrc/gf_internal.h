@@ -88,6 +88,8 @@ struct WorkView {
   int n_direct = 0;
   const Work *pix_direct = nullptr;
   int n_pix_direct = 0;
+  const Work *stamps = nullptr;   // the stamps still iterating (unit 0), for the per-stamp LM kernels
+  int n_stamps = 0;
 };
 
 // Per-component constants of the evaluation kernels (computed per workgroup).

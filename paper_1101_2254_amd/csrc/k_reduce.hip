@@ -554,7 +554,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
                                                        LMState *__restrict__ st, double *__restrict__ Ag,
                                                        const double *__restrict__ theta, double *__restrict__ theta_t,
                                                        int *__restrict__ mjac, int *__restrict__ mtrial,
-                                                       int *__restrict__ active_count) {
+                                                       int *__restrict__ active_count,
+                                                       const Work *__restrict__ list) {
   constexpr int P = kNPC * NC + 1;
   __shared__ double Gp[kSolveSlices][256];
   __shared__ double Gs[256];
@@ -564,9 +565,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
   __shared__ int fr_s[P], idx_s[P];
   __shared__ int ok_s;
   __shared__ double inv_s[P];
-  const int s = blockIdx.x;
+  const int s = list ? list[blockIdx.x].stamp : (int)blockIdx.x;
   const int tid = threadIdx.x;
-  if (s == 0 && tid == 0) *active_count = 0;
+  if (blockIdx.x == 0 && tid == 0) *active_count = 0;
   // independent loads first: descriptor, state and unit range together
   const StampDesc d = desc[s];
   const LMState S0 = st[s];
@@ -770,8 +771,9 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
                                                   const float2 *__restrict__ part, LMParams prm,
                                                   LMState *__restrict__ st, double *__restrict__ theta,
                                                   const double *__restrict__ theta_t, int *__restrict__ mjac,
-                                                  int *__restrict__ mtrial, int *__restrict__ active_count) {
-  const int s = blockIdx.x;
+                                                  int *__restrict__ mtrial, int *__restrict__ active_count,
+                                                  const Work *__restrict__ list) {
+  const int s = list ? list[blockIdx.x].stamp : (int)blockIdx.x;
   LMState S = st[s];
   if (!S.active) return;
   const StampDesc d = desc[s];
@@ -927,7 +929,7 @@ hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, con
 
 hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, const gf_lm_opts *o, LMState *S,
                            double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial, int *cnt,
-                           CompC *cc_th, CompC *cc_t, const float4 *bn) {
+                           CompC *cc_th, CompC *cc_t, const float4 *bn, const WorkView *v) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask, cc_t, cc_th, bn, o->oversample};
   ProfScope ps(st, "k_lm_solve");
@@ -936,23 +938,31 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
     has1 |= d.ncomp == 1;
     has2 |= d.ncomp == 2;
   }
+  // a compacted view lists the stamps still iterating; the others would
+  // only start and end a workgroup
+  const Work *list = v && v->stamps ? v->stamps : nullptr;
+  const unsigned grid = list ? (unsigned)v->n_stamps : (unsigned)b->n;
+  if (grid == 0) return hipSuccess;
   if (has1)
-    hipLaunchKernelGGL((k_lm_solve<1>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
-                       prm, S, Ag, theta, theta_t, mjac, mtrial, cnt);
+    hipLaunchKernelGGL((k_lm_solve<1>), dim3(grid), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
+                       prm, S, Ag, theta, theta_t, mjac, mtrial, cnt, list);
   if (has2)
-    hipLaunchKernelGGL((k_lm_solve<2>), dim3(b->n), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
-                       prm, S, Ag, theta, theta_t, mjac, mtrial, cnt);
+    hipLaunchKernelGGL((k_lm_solve<2>), dim3(grid), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
+                       prm, S, Ag, theta, theta_t, mjac, mtrial, cnt, list);
   return hipGetLastError();
 }
 
 hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const int32_t *first,
                             const float2 *part, LMState *S, double *theta, const double *theta_t, int *mjac,
-                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t) {
+                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t, const WorkView *v) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask, cc_t, cc_th, nullptr, o->oversample};
   ProfScope ps(st, "k_lm_update");
-  hipLaunchKernelGGL(k_lm_update, dim3(b->n), dim3(64), 0, st, b->d_desc, first, part, prm, S, theta,
-                     theta_t, mjac, mtrial, cnt);
+  const Work *list = v && v->stamps ? v->stamps : nullptr;
+  const unsigned grid = list ? (unsigned)v->n_stamps : (unsigned)b->n;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lm_update, dim3(grid), dim3(64), 0, st, b->d_desc, first, part, prm, S, theta,
+                     theta_t, mjac, mtrial, cnt, list);
   return hipGetLastError();
 }
 
