@@ -217,10 +217,11 @@ __global__ __launch_bounds__(kLT) void k_line_chi2(const LineDesc *__restrict__ 
 //   (A + lambda diag(max(A_ii, 1e-12 max A_jj))) delta = g by FP64 Cholesky
 //   (not positive definite: lambda *= up), theta' = clip(theta + delta),
 //   accept iff chi2(theta') < chi2(theta) (compensated FP32 sums).
-// Registers capped for four waves per SIMD (the LDS of the three-line build
-// allows four workgroups per CU; uncapped it took 139 VGPRs, three waves).
+// Registers capped for as many waves per SIMD as the LDS of each build allows
+// workgroups per CU: six for one line, five for two, four for three
+// (uncapped the three-line build took 139 VGPRs, three waves).
 template <int L>
-__global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(L == 1 ? 6 : L == 2 ? 5 : 4)))
 void k_line_lm(const LineDesc *__restrict__ desc, int n, const float *__restrict__ lsf, const float *__restrict__ data,
                const float *__restrict__ weight, double *__restrict__ theta, LineLMParams prm,
                gf_lm_result *__restrict__ res) {
@@ -231,7 +232,9 @@ void k_line_lm(const LineDesc *__restrict__ desc, int n, const float *__restrict
   __shared__ LineC lc[L];
   __shared__ F2 red[kLT / 64];
   __shared__ float xs[kLT][17];            // sqrt(w) [J 1 r] of a chunk (row stride 17: no bank conflicts)
-  __shared__ float gw[kLT / 64][256];       // per-wave Gram blocks
+  // per-wave Gram blocks, in the chunk staging buffer (free once a Jacobian's
+  // chunks are done), so the LDS of a workgroup stays smaller
+  float(*gw)[256] = reinterpret_cast<float(*)[256]>(&xs[0][0]);
   __shared__ double Gs[256];                // Gram matrix G[a][b] at a * 16 + b
   __shared__ double th_s[P], tt_s[P], lo_s[P], hi_s[P], dl_s[P];
   __shared__ double Lr[P][P], inv_s[P];
