@@ -226,6 +226,9 @@ typedef struct {
   int32_t use_graph;    /* capture one iteration in a HIP graph and replay it (default 1) */
   int32_t speculate;    /* evaluate the Jacobian together with every trial point instead of after
                            acceptance: 1 on, 0 off, -1 (default) on for single-stamp batches */
+  const double *start;  /* device [n_par] start point, or NULL (default): theta_io holds it.  When
+                           set, theta_io is output only and start is not written; the two are the
+                           same buffer or do not overlap. */
 } gf_lm_opts;
 
 typedef struct {
@@ -249,7 +252,8 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  *   (not positive definite: lambda *= up, try again),
  *   theta' = clip(theta + delta, lo, hi); accept iff chi2(theta') < chi2(theta)
  *   (lambda /= down), else reject (lambda *= up).
- * theta_io: device [n_par] FP64, start in, best accepted point out.
+ * theta_io: device [n_par] FP64, start in (unless opts->start gives it), best accepted
+ * point out.
  * With speculate the trial point's model comes from its Jacobian images
  * (the model is linear in each Ie: m = sky + sum_c Ie_c dm/dIe_c), so an
  * accepted step already has the next normal equations; a rejected one has

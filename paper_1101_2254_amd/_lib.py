@@ -40,7 +40,8 @@ class GfLmOpts(ctypes.Structure):
                 ("lambda_up", ctypes.c_double), ("lambda_down", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("ftol", ctypes.c_double), ("xtol", ctypes.c_double),
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("free_mask", ctypes.c_void_p),
-                ("poll_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("speculate", ctypes.c_int32)]
+                ("poll_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("speculate", ctypes.c_int32),
+                ("start", ctypes.c_void_p)]
 
 
 class GfMcmcOpts(ctypes.Structure):

@@ -40,8 +40,8 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *, float *, int, int, const int *, const WorkView *, float2 *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
                           int *);
-hipError_t launch_lm_start(hipStream_t, const gf_batch *, double *, const double *, const double *, double *, int,
-                           const float4 *, CompC *);
+hipError_t launch_lm_start(hipStream_t, const gf_batch *, const double *, double *, const double *, const double *,
+                           double *, int, const float4 *, CompC *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *,
                            const WorkView *);
@@ -912,6 +912,7 @@ void gf_lm_opts_default(gf_lm_opts *o) {
   o->poll_every = 4;
   o->use_graph = 1;
   o->speculate = -1;
+  o->start = nullptr;
 }
 
 namespace {
@@ -1028,6 +1029,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     return fail(c, GF_EINVAL, "gf_fit_lm: invalid options");
   const bool spec = o.speculate > 0 || (o.speculate < 0 && b->n == 1);
   if (o.poll_every < 1) o.poll_every = 1;
+  if (o.start == theta) o.start = nullptr;
   if (b->max_nc > 2) return fail(c, GF_ESHAPE, "gf_fit_lm: at most two components per stamp");
   const int nchan = kNPC * b->max_nc;
   const int nacc = 256;  // 16 x 16 Gram matrix per workgroup
@@ -1091,7 +1093,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     GF_TRY(c, hipStreamWaitEvent(cs, ev, 0));
     // start point: clip and set up, evaluate, chi2 (speculative: the Jacobian images and
     // normal equations of the start point, chi^2 from the same model)
-    GF_TRY(c, launch_lm_start(cs, b, theta, o.lo, o.hi, B.theta_t, S, c->d_bn, B.cc_th));
+    GF_TRY(c, launch_lm_start(cs, b, o.start, theta, o.lo, o.hi, B.theta_t, S, c->d_bn, B.cc_th));
     if (spec) {
       GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, nullptr, nullptr, B.cc_th, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, nullptr, nullptr));

@@ -34,11 +34,12 @@ __global__ void k_comp_prep(const StampDesc *__restrict__ desc, int n, const TT 
   if (k < d.ncomp) comp_setup<TT>(theta + d.par + kNPC * k, bn_tab, S, cc[i]);
 }
 
-// Start of an LM fit: the start point clipped into the box (written to theta
-// and to the trial buffer) and its component constants, in one launch.
+// Start of an LM fit: the start point (read from start, or from theta when
+// start is null) clipped into the box (written to theta and to the trial
+// buffer) and its component constants, in one launch.
 // Thread (stamp, k) clips the seven parameters of component k, and the sky
 // for k = 0, then sets up component k from the clipped values.
-__global__ void k_lm_start(const StampDesc *__restrict__ desc, int n, double *__restrict__ theta,
+__global__ void k_lm_start(const StampDesc *__restrict__ desc, int n, const double *start, double *theta,
                            const double *__restrict__ lo, const double *__restrict__ hi,
                            double *__restrict__ theta_t, const float4 *__restrict__ bn_tab, int S,
                            CompC *__restrict__ cc) {
@@ -48,7 +49,7 @@ __global__ void k_lm_start(const StampDesc *__restrict__ desc, int n, double *__
   const StampDesc d = desc[s];
   if (k >= d.ncomp) return;
   auto clip = [&](int64_t j) {
-    double v = theta[j];
+    double v = start ? start[j] : theta[j];
     if (lo && v < lo[j]) v = lo[j];
     if (hi && v > hi[j]) v = hi[j];
     theta[j] = v;
@@ -307,11 +308,11 @@ hipError_t launch_eval(hipStream_t st, const gf_batch *b, const float *theta, in
 
 // cc: where the component constants live (null: the batch's buffer); prep:
 // compute them from theta first (false: the caller keeps them current).
-hipError_t launch_lm_start(hipStream_t st, const gf_batch *b, double *theta, const double *lo, const double *hi,
-                           double *theta_t, int S, const float4 *bn, CompC *cc) {
+hipError_t launch_lm_start(hipStream_t st, const gf_batch *b, const double *start, double *theta, const double *lo,
+                           const double *hi, double *theta_t, int S, const float4 *bn, CompC *cc) {
   if (S < 1 || S > GF_MAX_OVERSAMPLE) return hipErrorInvalidValue;
   const int nt = b->n * kMaxComp;
-  hipLaunchKernelGGL(k_lm_start, dim3((nt + 63) / 64), dim3(64), 0, st, b->d_desc, b->n, theta, lo, hi, theta_t, bn,
+  hipLaunchKernelGGL(k_lm_start, dim3((nt + 63) / 64), dim3(64), 0, st, b->d_desc, b->n, start, theta, lo, hi, theta_t, bn,
                      S, cc);
   return hipGetLastError();
 }

@@ -238,7 +238,11 @@ def fit_lm(ctx: Context, batch: Batch, psf: Psf, data: torch.Tensor, weight: tor
         o.hi = _ptr(_need(hi, torch.float64, n_par, "hi"))
     if free is not None:
         o.free_mask = _ptr(_need(free, torch.uint8, n_par, "free"))
-    theta = theta0.clone()
+    # the library reads the start from theta0 and writes the fit to theta
+    o.start = _ptr(theta0)
+    theta = torch.empty_like(theta0)
+    if theta0.numel() > n_par:
+        theta[n_par:].copy_(theta0[n_par:])
     res = torch.empty(batch.n * LM_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
     ctx.bind_stream()
     L.gf_fit_lm(ctx.ptr, batch.ptr, psf.ptr, _ptr(data), _ptr(weight), _ptr(theta), o, _ptr(res))

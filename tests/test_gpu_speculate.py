@@ -195,3 +195,33 @@ def test_speculative_nonfinite_stamp_in_batch(ctx, gfo):
     for s in (0, 2):
         np.testing.assert_array_equal(th[po[s]:po[s] + 8], ref[po[s]:po[s] + 8])
         assert info["chi2"][s] == rinfo["chi2"][s]
+
+
+def test_start_pointer_matches_in_place(ctx, gfo):
+    # gf_lm_opts.start: the start is read from its own buffer (left as it is)
+    # and theta_io is output only; the fit is the in-place fit, bit for bit
+    stamps = _stamps(86, 3)
+    gb, lo, hi = _problem(ctx, gfo, stamps)
+    st0 = np.concatenate([s.start for s in stamps])
+    start = to_dev(st0, torch.float64)
+    nb = len(stamps) * ops.LM_RESULT_DTYPE.itemsize
+    ctx.bind_stream()
+    for spec in (0, 1):
+        print(f"start pointer, speculate={spec}", flush=True)
+        o = L.gf_lm_opts_default()
+        o.lo, o.hi, o.ftol, o.speculate = int(lo.data_ptr()), int(hi.data_ptr()), 1e-6, spec
+        th_a = start.clone()
+        res_a = torch.empty(nb, dtype=torch.uint8, device=ctx.device)
+        L.gf_fit_lm(ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(gb.data.data_ptr()), int(gb.weight.data_ptr()),
+                    int(th_a.data_ptr()), o, int(res_a.data_ptr()))
+        th_b = torch.full_like(start, float("nan"))
+        res_b = torch.empty(nb, dtype=torch.uint8, device=ctx.device)
+        o.start = int(start.data_ptr())
+        L.gf_fit_lm(ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(gb.data.data_ptr()), int(gb.weight.data_ptr()),
+                    int(th_b.data_ptr()), o, int(res_b.data_ptr()))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(th_b.cpu().numpy(), th_a.cpu().numpy())
+        ia, ib = ops.lm_info(res_a), ops.lm_info(res_b)
+        for f in ("chi2", "iters", "nfev", "njev", "status", "reason"):
+            np.testing.assert_array_equal(ib[f], ia[f], err_msg=f)
+        np.testing.assert_array_equal(start.cpu().numpy(), st0)
