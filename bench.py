@@ -765,7 +765,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {max(args.gpus, world)} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {max(args.gpus, world)} is not supported "
               "(the hot path shards as described in the design notes, but only the one-GPU kernel is built)",
               file=sys.stderr)
         sys.exit(2)
