@@ -225,3 +225,21 @@ def test_start_pointer_matches_in_place(ctx, gfo):
         for f in ("chi2", "iters", "nfev", "njev", "status", "reason"):
             np.testing.assert_array_equal(ib[f], ia[f], err_msg=f)
         np.testing.assert_array_equal(start.cpu().numpy(), st0)
+
+
+def test_fit_lm_leaves_theta0_and_keeps_tail(ctx, gfo):
+    # ops.fit_lm reads the start from theta0, which it leaves as it is; a
+    # theta0 longer than the batch's parameters passes its tail through
+    stamps = _stamps(87, 2)
+    gb, lo, hi = _problem(ctx, gfo, stamps)
+    st0 = np.concatenate([s.start for s in stamps])
+    n = st0.size
+    ext = np.concatenate([st0, [1.5, -2.5, 7.0]])
+    t_ext = to_dev(ext, torch.float64)
+    th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, t_ext, lo=lo, hi=hi, ftol=1e-6)
+    ref, rinfo = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, t_ext[:n].clone(), lo=lo, hi=hi, ftol=1e-6)
+    th = th.cpu().numpy()
+    np.testing.assert_array_equal(t_ext.cpu().numpy(), ext)
+    np.testing.assert_array_equal(th[n:], ext[n:])
+    np.testing.assert_array_equal(th[:n], ref.cpu().numpy())
+    np.testing.assert_array_equal(info["chi2"], rinfo["chi2"])
