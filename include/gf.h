@@ -211,6 +211,9 @@ gf_status gf_jacobian(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, con
 /* ----------------------------------------------- steps 4-5: LM fitting */
 
 typedef struct {
+  int32_t struct_size;  /* sizeof(gf_lm_opts): set by gf_lm_opts_default, checked by every call that
+                           takes the struct (GF_EINVAL otherwise), so a caller built against a
+                           header with another layout is refused instead of misread */
   int32_t max_iter;     /* iteration cap (default 100) */
   int32_t oversample;   /* S (default 5) */
   double lambda0;       /* initial damping (1e-3) */
@@ -243,6 +246,8 @@ typedef struct {
   int32_t pad;
 } gf_lm_result;
 
+/* Fills every field with its default, struct_size included.  Initialise the
+ * struct with this call and then change fields. */
 void gf_lm_opts_default(gf_lm_opts *opts);
 
 /* Levenberg-Marquardt over every stamp of the batch at once (Marquardt 1963;

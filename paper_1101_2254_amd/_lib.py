@@ -36,7 +36,8 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
 
 
 class GfLmOpts(ctypes.Structure):
-    _fields_ = [("max_iter", ctypes.c_int32), ("oversample", ctypes.c_int32), ("lambda0", ctypes.c_double),
+    _fields_ = [("struct_size", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("oversample", ctypes.c_int32),
+                ("lambda0", ctypes.c_double),
                 ("lambda_up", ctypes.c_double), ("lambda_down", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("ftol", ctypes.c_double), ("xtol", ctypes.c_double),
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("free_mask", ctypes.c_void_p),

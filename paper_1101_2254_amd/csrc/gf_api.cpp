@@ -253,7 +253,7 @@ int64_t chi2_slots(const gf_batch *b, const gf_psf *p) { return std::max<int64_t
 
 extern "C" {
 
-const char *gf_version(void) { return "libgf 0.1 (gfx950)"; }
+const char *gf_version(void) { return "libgf 0.2 (gfx950)"; }
 
 gf_status gf_create(gf_ctx **out, int device) {
   if (!out) return GF_EINVAL;
@@ -898,6 +898,7 @@ gf_status gf_jacobian(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
 void gf_lm_opts_default(gf_lm_opts *o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(gf_lm_opts);
   o->max_iter = 100;
   o->oversample = 5;
   o->lambda0 = 1e-3;
@@ -1022,6 +1023,8 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   ProfBind pb_(c);
   if (!c || !b || !p || !data || !weight || !theta || !res) return fail(c, GF_EINVAL, "gf_fit_lm: null argument");
   if (p->batch != b) return fail(c, GF_EINVAL, "gf_fit_lm: PSF prepared for another batch");
+  if (opts && opts->struct_size != (int32_t)sizeof(gf_lm_opts))
+    return fail(c, GF_EINVAL, "gf_fit_lm: opts->struct_size differs from sizeof(gf_lm_opts) (initialise with gf_lm_opts_default)");
   gf_lm_opts o;
   if (opts) o = *opts; else gf_lm_opts_default(&o);
   if (o.max_iter < 0 || o.oversample < 1 || o.oversample > GF_MAX_OVERSAMPLE || !(o.lambda_up > 1.0) ||
@@ -1302,9 +1305,9 @@ gf_status gf_fit_simplex(gf_ctx *c, const gf_batch *b, const gf_psf *p, const fl
   GF_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   GF_TRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   auto cleanup = [&]() {
+    (void)hipStreamSynchronize(cs);   // graph launches may still be in flight
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamSynchronize(cs);
     (void)hipStreamDestroy(cs);
     (void)hipEventDestroy(ev);
   };
@@ -1437,9 +1440,9 @@ gf_status gf_mcmc_run(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
       return GF_OK;
     };
     r = body();
+    (void)hipStreamSynchronize(gs);   // graph launches may still be in flight
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamSynchronize(gs);
     (void)hipStreamDestroy(gs);
     if (ev) (void)hipEventDestroy(ev);
     return r;

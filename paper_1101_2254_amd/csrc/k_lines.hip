@@ -408,6 +408,9 @@ void k_line_lm(const LineDesc *__restrict__ desc, int n, const float *__restrict
         status = GF_ENOTCONV;
         reason = 4;
       }
+      // every wave has read the flag before the first wave's next solve
+      // sets it again
+      __syncthreads();
       continue;
     }
     // ---- trial point and its chi^2

@@ -124,6 +124,8 @@ gf_status gf_line_chi2(gf_ctx *c, const gf_line_batch *lb, const float *lsf, con
 gf_status gf_line_fit_lm(gf_ctx *c, const gf_line_batch *lb, const float *lsf, const float *data,
                          const float *weight, double *theta_io, const gf_lm_opts *opts, gf_lm_result *res) {
   ProfBind pb_(c);
+  if (opts && opts->struct_size != (int32_t)sizeof(gf_lm_opts))
+    return lfail(c, GF_EINVAL, "gf_line_fit_lm: opts->struct_size differs from sizeof(gf_lm_opts) (initialise with gf_lm_opts_default)");
   gf_lm_opts o;
   if (opts)
     o = *opts;

@@ -33,6 +33,9 @@ def test_lm_struct_layout_matches_header():
     o = _lib.gf_lm_opts_default()
     assert o.max_iter == 100 and o.oversample == 5 and o.lambda0 == 1e-3 and o.lambda_max == 1e10
     assert o.ftol == 1e-5 and o.poll_every == 4 and o.use_graph == 1 and o.speculate == -1 and o.start is None
+    # the library's sizeof(gf_lm_opts), which every call checks, is the
+    # binding's layout
+    assert o.struct_size == ctypes.sizeof(_lib.GfLmOpts) == 112
     assert ctypes.sizeof(_lib.GfLmResult) == 40
     from paper_1101_2254_amd.ops import LM_RESULT_DTYPE
     assert LM_RESULT_DTYPE.itemsize == 40

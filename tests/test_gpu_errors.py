@@ -1,6 +1,8 @@
 """Error paths of the C ABI on a device: shapes and arguments the library
 does not support come back as documented status codes with a message, before
 anything is enqueued, and non-finite observations end a fit cleanly."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -62,6 +64,14 @@ def test_argument_ranges(ctx):
     o.max_iter = -1
     assert _status(L.gf_fit_lm, ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(out.data_ptr()), int(out.data_ptr()),
                    int(out.data_ptr()), o, int(out.data_ptr())) == L.GF_EINVAL
+    # an options struct of another layout (struct_size not set by
+    # gf_lm_opts_default) is refused before anything is read from it
+    o = L.gf_lm_opts_default()
+    assert o.struct_size == ctypes.sizeof(L.GfLmOpts)
+    o.struct_size = 100
+    assert _status(L.gf_fit_lm, ctx.ptr, gb.batch.ptr, gb.psf.ptr, int(out.data_ptr()), int(out.data_ptr()),
+                   int(out.data_ptr()), o, int(out.data_ptr())) == L.GF_EINVAL
+    assert "struct_size" in L.lib().gf_last_error(ctx.ptr).decode()
 
 
 def test_line_batch_and_argument_errors(ctx):

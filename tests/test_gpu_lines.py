@@ -171,3 +171,41 @@ def test_line_fit_edge_cases(ctx):
     th2, info2 = ops.line_fit_lm(ctx, ls.lb, ls.lsf, ls.data, ls.weight, to_dev(st, torch.float64),
                                  free=to_dev(free, torch.uint8), ftol=1e-12, xtol=1e-12)
     np.testing.assert_array_equal(th2.cpu().numpy()[free == 0], st[free == 0])
+
+
+def test_line_fit_failed_factorisation(ctx):
+    """A spectrum with one non-finite weight makes every damped Gram matrix
+    non-finite, so each iteration's Cholesky fails and only raises the
+    damping (the path where the whole workgroup re-reads the failure flag
+    before the next solve).  The fit must end by the damping cap at the
+    clipped start, like the oracle's, while the other spectra of the batch
+    fit exactly as without it."""
+    shapes = [(200, 2, None), (300, 1, None), (512, 3, None)]
+    sp = _spectra(605, shapes)
+    ls = LineSet(ctx, sp)
+    lo, hi = _bounds(sp)
+    start = np.concatenate([s.start for s in sp])
+    opts = dict(ftol=1e-8, max_iter=100)
+    ref_th, ref_info = ops.line_fit_lm(ctx, ls.lb, ls.lsf, ls.data, ls.weight, to_dev(start, torch.float64),
+                                       lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), **opts)
+    w = ls.weight.clone()
+    w[ls.lb.offsets["data"][0] + 37] = float("nan")
+    print("line fit with a non-finite weight", flush=True)
+    th, info = ops.line_fit_lm(ctx, ls.lb, ls.lsf, ls.data, w, to_dev(start, torch.float64),
+                               lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), **opts)
+    po = ls.lb.offsets["par"]
+    l0, h0 = synth.line_bounds(sp[0].nlines, sp[0].N)
+    w0 = ls.w32[0].astype(np.float64).copy()
+    w0[37] = np.nan
+    r_th, r_info = LR.fit_lm(sp[0].start, ls.lsf32[0].astype(np.float64), ls.d32[0].astype(np.float64), w0, 5,
+                             lo=l0, hi=h0, **opts)
+    assert info["status"][0] == r_info["status"] == 6 and info["reason"][0] == r_info["reason"] == 4
+    assert info["iters"][0] == r_info["iters"] == 14
+    assert info["lambda"][0] == pytest.approx(r_info["lam"], rel=1e-12)
+    # no trial point was formed: each iteration ended at the factorisation
+    assert info["nfev"][0] == 1 and info["njev"][0] == 1
+    np.testing.assert_array_equal(th.cpu().numpy()[po[0]:po[1]], r_th)
+    # the other spectra are untouched by it
+    np.testing.assert_array_equal(th.cpu().numpy()[po[1]:], ref_th.cpu().numpy()[po[1]:])
+    for k in ("chi2", "iters", "nfev", "status"):
+        np.testing.assert_array_equal(np.asarray(info[k])[1:], np.asarray(ref_info[k])[1:])

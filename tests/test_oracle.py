@@ -356,3 +356,95 @@ def test_lm_bounds_are_respected(gfo):
     fit, info = gfo.fit_lm(np.r_[th[:5], 0.8, th[6:]], psf, d, w, 5, lo=lo, hi=hi, max_iter=60)
     assert fit[5] <= 0.9
     assert np.all(fit >= lo) and np.all(fit <= hi)
+
+
+# ------------------------------------------------ LM step and damping trace
+def _fd_jacobian(gfo, H, W, th, psf, S=5):
+    """Central differences of the oracle's model (independent of its
+    analytic Jacobian)."""
+    J = np.empty((th.size, H, W))
+    for p in range(th.size):
+        h = 1e-5 * max(abs(th[p]), 1.0)
+        a, b = th.copy(), th.copy()
+        a[p] += h
+        b[p] -= h
+        J[p] = (gfo.model(H, W, a, psf, S) - gfo.model(H, W, b, psf, S)) / (2 * h)
+    return J
+
+
+def _damped_step(J, w, r, lam, keep):
+    """Marquardt's step on the parameters in keep: (A + lam D) delta = g with
+    A = J^T W J, g = J^T W r, D = diag(max(A_ii, 1e-12 max_j A_jj)), by a
+    general solve (not a Cholesky factorisation)."""
+    Jk = J[keep].reshape(len(keep), -1)
+    A = (Jk * w.ravel()) @ Jk.T
+    g = (Jk * w.ravel()) @ r.ravel()
+    D = np.maximum(np.diag(A), 1e-12 * np.diag(A).max())
+    return np.linalg.solve(A + lam * np.diag(D), g)
+
+
+def test_lm_damping_trace_across_rejections(gfo):
+    """From a start far from the minimum the first four damped steps raise
+    chi^2 and are rejected (lambda 1e-3 -> 1e-2 -> 0.1 -> 1 -> 10, the
+    Jacobian kept), the fifth (lambda = 10) lowers it and is accepted
+    (lambda -> 1).  Each trial point is recomputed here from a
+    finite-difference Jacobian and a general linear solve; the oracle's
+    state after k iterations must follow it."""
+    H = W = 24
+    psf = synth.gaussian_psf(5, 1.2)
+    truth = np.array([12.3, 11.6, 1.0, 3.0, 2.5, 0.7, 0.5, 0.01])
+    d, w = synth.add_gaussian_noise(gfo.model(H, W, truth, psf, 5), 0.02, 11)
+    t0 = truth * np.array([1, 1, 0.3, 0.4, 3.0, 1, 1, 1])
+    m0 = gfo.model(H, W, t0, psf, 5)
+    c0 = float(np.sum(w * (d - m0) ** 2))
+    J = _fd_jacobian(gfo, H, W, t0, psf)
+    keep = list(range(8))
+    lam, accepted_at = 1e-3, None
+    for k in range(1, 6):
+        trial = t0 + _damped_step(J, w, d - m0, lam, keep)
+        ct = float(np.sum(w * (d - gfo.model(H, W, trial, psf, 5)) ** 2))
+        th, info = gfo.fit_lm(t0, psf, d, w, 5, max_iter=k)
+        assert info["njev"] == 1 and info["nfev"] == k + 1 and info["iters"] == k
+        if ct < c0:
+            accepted_at = k
+            np.testing.assert_allclose(th, trial, rtol=1e-6, atol=1e-8)
+            assert info["chi2"] == pytest.approx(ct, rel=1e-7)
+            assert info["lam"] == pytest.approx(lam / 10.0, rel=1e-15)
+            break
+        np.testing.assert_array_equal(th, t0)      # rejected: theta stays
+        assert info["chi2"] == pytest.approx(c0, rel=1e-12)
+        lam *= 10.0
+        assert info["lam"] == pytest.approx(lam, rel=1e-15)
+    assert accepted_at == 5
+    # the damping changes the step: the undamped (Gauss-Newton) step and a
+    # unit-matrix damping both land far from the accepted point
+    gn = t0 + _damped_step(J, w, d - m0, 0.0, keep)
+    assert np.abs(gn - th).max() > 1e-2
+    Jk = J.reshape(8, -1)
+    A = (Jk * w.ravel()) @ Jk.T
+    g = (Jk * w.ravel()) @ (d - m0).ravel()
+    unit = t0 + np.linalg.solve(A + 10.0 * np.eye(8), g)
+    assert np.abs(unit - th).max() > 1e-2
+
+
+def test_lm_damping_floor_keeps_a_flat_direction_solvable(gfo):
+    """A round component (q = 1) does not depend on phi, so phi's Jacobian
+    column and its diagonal of A are exactly zero.  The floor
+    1e-12 max_j A_jj in D keeps A + lambda D positive definite: the step is
+    taken, phi does not move, and the other parameters take the step of the
+    system without phi."""
+    H = W = 24
+    psf = synth.gaussian_psf(5, 1.2)
+    truth = np.array([12.3, 11.6, 1.0, 3.0, 2.5, 1.0, 0.5, 0.01])
+    d, w = synth.add_gaussian_noise(gfo.model(H, W, truth, psf, 5), 0.02, 12)
+    t0 = truth * np.array([1.01, 0.99, 1.1, 1.1, 0.95, 1.0, 1.0, 1.2])
+    J = _fd_jacobian(gfo, H, W, t0, psf)
+    ref = gfo.jacobian(H, W, t0, psf, 5)
+    assert np.all(ref[6] == 0.0)
+    keep = [0, 1, 2, 3, 4, 5, 7]
+    trial = t0.copy()
+    trial[keep] += _damped_step(J, w, d - gfo.model(H, W, t0, psf, 5), 1e-3, keep)
+    th, info = gfo.fit_lm(t0, psf, d, w, 5, max_iter=1)
+    assert info["nfev"] == 2 and info["lam"] == pytest.approx(1e-4)
+    assert th[6] == t0[6]
+    np.testing.assert_allclose(th, trial, rtol=1e-6, atol=1e-8)
