@@ -74,8 +74,13 @@ typedef enum {
 
 /* Convolution path of a prepared PSF. */
 #define GF_CONV_AUTO 0     /* chosen per stamp from the PSF and grid size */
-#define GF_CONV_FFT 1      /* Fourier-space product (Sec. 3, step 2) */
+#define GF_CONV_FFT 1      /* Fourier-space product (Sec. 3, step 2); one-workgroup form
+                              where the side allows it, else multi-pass */
 #define GF_CONV_DIRECT 2   /* direct sum over taps */
+#define GF_CONV_FFT_MULTIPASS 3  /* Fourier-space product, multi-pass form for every stamp */
+#define GF_CONV_FFT_FUSED 4      /* Fourier-space product, one-workgroup form for every stamp
+                                    (GF_ESHAPE when a side L exceeds GF_FFT_FUSED_MAX) */
+#define GF_FFT_FUSED_MAX 192     /* largest side of the one-workgroup form */
 
 /* gf_jacobian modes. */
 #define GF_JAC_FULL 0      /* d m / d theta images */
@@ -143,12 +148,23 @@ int gf_batch_count(const gf_batch *batch);
 /* Prepare the PSF of every stamp (device array of n_psf floats, taps used as
  * given: normalise them beforehand if unit sum is wanted).  For stamps on the
  * FFT path this computes the optical transfer function on an L x L grid
- * (L = smallest 2^a 3^b 5^c >= the padded side) on the device; the prepared
- * object owns that memory.  `mode` is GF_CONV_AUTO, GF_CONV_FFT or
- * GF_CONV_DIRECT.  The psf array must stay valid while *out is used. */
+ * (L = smallest even 2^a 3^b 5^c >= the padded side) on the device; the
+ * prepared object owns that memory.  `mode` is one of the GF_CONV_* values.
+ * The FFT path comes in two forms that compute the same convolution:
+ *   one-workgroup (L <= GF_FFT_FUSED_MAX): a workgroup holds a whole
+ *     channel's 2-D spectrum in on-chip memory (the paper's all-to-all FFT
+ *     step without a trip through device memory);
+ *   multi-pass: row, column and inverse-row launches with the spectra in
+ *     device memory, for any L.
+ * GF_CONV_AUTO takes the direct sum for K <= 7 and the FFT otherwise, in the
+ * form the context's tuning table names for that side (gf_create), else the
+ * one-workgroup form where it applies.  The psf array must stay valid while
+ * *out is used. */
 gf_status gf_psf_prepare(gf_ctx *ctx, const gf_batch *batch, const float *psf, int mode, gf_psf **out);
 void gf_psf_destroy(gf_psf *psf);
-/* Host array of n_stamps ints: 1 where the stamp uses the FFT path. */
+/* Host arrays of n_stamps ints (either may be NULL): uses_fft[s] = 0 for the
+ * direct sum, 1 for the multi-pass FFT, 2 for the one-workgroup FFT;
+ * fft_side[s] = L (0 on the direct path). */
 gf_status gf_psf_paths(const gf_psf *psf, int32_t *uses_fft, int32_t *fft_side);
 
 /* ------------------------------------------------------ step 1: evaluate */

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ESHAPE", 3: "GF_ENOMEM", 4: "
                 6: "GF_ENOTCONV"}
 GF_NPC = 7
 GF_MAX_COMP = 4
-GF_CONV_AUTO, GF_CONV_FFT, GF_CONV_DIRECT = 0, 1, 2
+GF_CONV_AUTO, GF_CONV_FFT, GF_CONV_DIRECT, GF_CONV_FFT_MULTIPASS, GF_CONV_FFT_FUSED = 0, 1, 2, 3, 4
+GF_FFT_FUSED_MAX = 192
 GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
 
 # Every symbol that include/gf.h declares.

@@ -27,6 +27,7 @@ hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const 
 hipError_t launch_fft_corr(hipStream_t, const gf_batch *, const gf_psf *, const float *, float2 *, float2 *, float *);
 hipError_t launch_fft_otf(hipStream_t, const gf_batch *, const gf_psf *, const float *, const Work *, int,
                           const Work *, int, const int64_t *, float2 *, const int64_t *);
+hipError_t launch_fft2d_otf(hipStream_t, const gf_batch *, const gf_psf *, const float *, const Work *, const int *);
 hipError_t launch_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float *, bool,
                          const int *, const WorkView *);
 hipError_t launch_chi2(hipStream_t, const gf_batch *, const float *, const void *, bool, const float *,
@@ -506,7 +507,7 @@ gf_status gf_batch_offsets(const gf_batch *b, int64_t *pix, int64_t *pad, int64_
 
 // ---------------------------------------------------------------------- PSF
 gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mode, gf_psf **out) {
-  if (!c || !b || !taps || !out || mode < GF_CONV_AUTO || mode > GF_CONV_DIRECT)
+  if (!c || !b || !taps || !out || mode < GF_CONV_AUTO || mode > GF_CONV_FFT_FUSED)
     return fail(c, GF_EINVAL, "gf_psf_prepare: bad argument");
   *out = nullptr;
   gf_psf *p = new (std::nothrow) gf_psf();
@@ -526,14 +527,32 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   std::vector<int64_t> otf_tmp(n, 0), otf_off(n, 0);
   std::map<int64_t, int64_t> otf_of_psf;   // PSF offset -> OTF offset
   std::vector<Work> otf_rows, otf_cols;
+  std::vector<Work> f2d_cls[kF2dN], f2d_otf_cls[kF2dN];
   int64_t otf_tmp_n = 0;
-  // The largest radix over the plans of the FFT stamps picks the kernel
-  // build and with it the LDS capacity that sizes every work unit.
+  // Path of each stamp: 0 direct, 1 multi-pass FFT, 2 one-workgroup FFT.
+  // Automatic choice: the direct sum costs about K^2 FMAs per output pixel
+  // and channel (K = 15: ~32 ps per pixel-channel measured), the FFT path a
+  // roughly K-independent ~7-10 ps, so the FFT wins from K = 9 on; of the two
+  // FFT forms the one-workgroup one is taken where the side allows it unless
+  // the context's tuning table names the multi-pass form for that side.
+  auto path_of = [&](const StampDesc &d) -> int {
+    const int L = fft_side(std::max(d.Mh, d.Mw));
+    const bool fits = f2d_class(L) >= 0;
+    if (mode == GF_CONV_DIRECT) return d.K > kDirectMaxK ? 1 : 0;
+    if (mode == GF_CONV_FFT_MULTIPASS) return 1;
+    if (mode == GF_CONV_FFT_FUSED) return 2;
+    if (mode == GF_CONV_AUTO && d.K <= 7) return 0;
+    if (!fits) return 1;
+    if (mode == GF_CONV_AUTO && c->tune_multipass(L)) return 1;
+    return 2;
+  };
+  // The largest radix over the plans of the multi-pass stamps picks the
+  // kernel build and with it the LDS capacity that sizes every work unit.
   {
     std::vector<char> seen(GF_MAX_FFT + 1, 0);
     for (int s = 0; s < n; ++s) {
       const StampDesc &d = b->h_desc[s];
-      const bool f = mode == GF_CONV_FFT || (mode == GF_CONV_AUTO && d.K > 7) || d.K > kDirectMaxK;
+      const bool f = path_of(d) == 1;
       const int L = fft_side(std::max(d.Mh, d.Mw));
       if (!f || L > GF_MAX_FFT || seen[L]) continue;
       seen[L] = 1;
@@ -545,17 +564,18 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   const int cap = fft_cap(p->rmax);
   for (int s = 0; s < n; ++s) {
     const StampDesc &d = b->h_desc[s];
-    // Automatic choice: the direct sum costs about K^2 FMAs per output pixel
-    // and channel (K = 15: ~32 ps per pixel-channel measured), the FFT path
-    // a roughly K-independent ~7-10 ps, so the FFT wins from K = 9 on.
-    bool fft = mode == GF_CONV_FFT || (mode == GF_CONV_AUTO && d.K > 7);
+    int path = path_of(d);
     if (mode == GF_CONV_DIRECT && d.K > kDirectMaxK) {
       delete p;
       return fail(c, GF_ESHAPE, "gf_psf_prepare: PSF too large for the direct path");
     }
-    if (!fft && d.K > kDirectMaxK) fft = true;
+    const bool fft = path != 0;
+    if (path == 2 && f2d_class(fft_side(std::max(d.Mh, d.Mw))) < 0) {
+      delete p;
+      return fail(c, GF_ESHAPE, "gf_psf_prepare: padded grid exceeds the one-workgroup FFT side");
+    }
     PathDesc &pd = p->h_path[s];
-    pd.fft = fft ? 1 : 0;
+    pd.fft = path;
     pd.L = 0;
     pd.plan = -1;
     pd.pad0 = 0;
@@ -594,6 +614,22 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     pd.L = L;
     pd.plan = plan_of_L[L];
     const int Lh = L / 2 + 1;
+    if (path == 2) {
+      const int cls = f2d_class(L);
+      ++p->n_f2d;
+      p->f2d_tw[cls] = p->h_plans[pd.plan].tw_off;
+      f2d_cls[cls].push_back({s, cls});
+      auto hit = otf_of_psf.find(d.psf);
+      if (hit == otf_of_psf.end()) {
+        otf_of_psf[d.psf] = p->n_otf;
+        pd.otf = p->n_otf;
+        p->n_otf += (int64_t)L * Lh;
+        f2d_otf_cls[cls].push_back({s, cls});
+      } else {
+        pd.otf = hit->second;
+      }
+      continue;
+    }
     const int T = cap / (L + 1), C = cap / L;
     const int cols = (Lh + C - 1) / C;
     for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_rows.push_back({s, u});
@@ -635,8 +671,18 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     delete p;
     return fail(c, GF_ESHAPE, "gf_psf_prepare: batch too large");
   }
+  std::vector<Work> f2d_otf;
+  int f2d_otf_first[kF2dN + 1] = {};
+  for (int k = 0; k < kF2dN; ++k) {
+    p->f2d_first[k] = (int)p->h_f2d.size();
+    p->h_f2d.insert(p->h_f2d.end(), f2d_cls[k].begin(), f2d_cls[k].end());
+    f2d_otf_first[k] = (int)f2d_otf.size();
+    f2d_otf.insert(f2d_otf.end(), f2d_otf_cls[k].begin(), f2d_otf_cls[k].end());
+  }
+  p->f2d_first[kF2dN] = (int)p->h_f2d.size();
+  f2d_otf_first[kF2dN] = (int)f2d_otf.size();
   hipError_t e = hipSuccess;
-  Work *d_orows = nullptr, *d_ocols = nullptr;
+  Work *d_orows = nullptr, *d_ocols = nullptr, *d_o2d = nullptr;
   int64_t *d_otmp = nullptr, *d_ooff = nullptr;
   if (e == hipSuccess) e = upload(&p->d_path, p->h_path);
   if (e == hipSuccess) e = upload(&p->d_plans, p->h_plans);
@@ -662,8 +708,11 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   if (e == hipSuccess) e = upload(&d_ocols, otf_cols);
   if (e == hipSuccess) e = upload(&d_otmp, otf_tmp);
   if (e == hipSuccess) e = upload(&d_ooff, otf_off);
+  if (e == hipSuccess) e = upload(&p->d_f2d, p->h_f2d);
+  if (e == hipSuccess) e = upload(&d_o2d, f2d_otf);
   if (e == hipSuccess && p->n_otf > 0) e = hipMalloc((void **)&p->d_otf, p->n_otf * sizeof(float2));
   if (e != hipSuccess) {
+    dfree(d_o2d);
     dfree(d_orows);
     dfree(d_ocols);
     dfree(d_otmp);
@@ -681,6 +730,12 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
       if (e != hipSuccess) st = fail(c, GF_EDEVICE, std::string("gf_psf_prepare (OTF): ") + hipGetErrorString(e));
     }
   }
+  if (st == GF_OK && !f2d_otf.empty()) {
+    e = launch_fft2d_otf(c->stream, b, p, taps, d_o2d, f2d_otf_first);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = fail(c, GF_EDEVICE, std::string("gf_psf_prepare (OTF): ") + hipGetErrorString(e));
+  }
+  dfree(d_o2d);
   dfree(d_orows);
   dfree(d_ocols);
   dfree(d_otmp);
@@ -716,6 +771,7 @@ void gf_psf_destroy(gf_psf *p) {
   dfree(p->d_adirect);
   dfree(p->d_c2_first);
   dfree(p->d_pix_direct);
+  dfree(p->d_f2d);
   delete p;
 }
 
@@ -932,14 +988,14 @@ struct LMBufs {
 int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
   return (int64_t)b->h_eval.size() + b->h_pix.size() + b->h_neq.size() + p->h_rows.size() + p->h_cols.size() +
          p->h_irows.size() + p->h_rows_n.size() + p->h_cols_n.size() + p->h_irows_n.size() + p->h_direct.size() +
-         p->h_pix_direct.size() + b->n;
+         p->h_pix_direct.size() + p->h_f2d.size() + b->n;
 }
 
 // Work lists restricted to the stamps flagged in act, filtered from `from`
 // (the previous restriction, or the full lists when `from` is empty), stored
 // in `to` and uploaded into dev; the view points into dev.
 struct HostLists {
-  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct, pix_direct, stamps;
+  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct, pix_direct, f2d, stamps;
   bool empty() const { return eval.empty() && pix.empty(); }
 };
 
@@ -964,6 +1020,7 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   filt(full ? p->h_irows_n : from.irows_n, to.irows_n);
   filt(full ? p->h_direct : from.direct, to.direct);
   filt(full ? p->h_pix_direct : from.pix_direct, to.pix_direct);
+  filt(full ? p->h_f2d : from.f2d, to.f2d);   // stays grouped by side class (unit)
   to.stamps.clear();
   for (int s = 0; s < b->n; ++s)
     if (act[s]) to.stamps.push_back({s, 0});
@@ -991,6 +1048,11 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   if (e == hipSuccess) e = put(to.direct, v.direct, v.n_direct);
   if (e == hipSuccess) e = put(to.pix_direct, v.pix_direct, v.n_pix_direct);
   if (e == hipSuccess) e = put(to.stamps, v.stamps, v.n_stamps);
+  int n_f2d = 0;
+  if (e == hipSuccess) e = put(to.f2d, v.f2d, n_f2d);
+  for (int k = 0; k <= kF2dN; ++k) v.f2d_first[k] = 0;
+  for (const Work &w : to.f2d) ++v.f2d_first[w.unit + 1];
+  for (int k = 0; k < kF2dN; ++k) v.f2d_first[k + 1] += v.f2d_first[k];
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors must outlive the copies
   return e;
 }
@@ -1200,18 +1262,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           act.assign(b->n, 0);
           for (int q = 0; q < b->n; ++q) act[q] = hst[q].active ? 1 : 0;
           GF_TRY(c, restrict_lists(cs, b, p, act, cur, nxt, B.lists, view));
-          cur.eval.swap(nxt.eval);
-          cur.pix.swap(nxt.pix);
-          cur.neq.swap(nxt.neq);
-          cur.rows.swap(nxt.rows);
-          cur.cols.swap(nxt.cols);
-          cur.irows.swap(nxt.irows);
-          cur.rows_n.swap(nxt.rows_n);
-          cur.cols_n.swap(nxt.cols_n);
-          cur.irows_n.swap(nxt.irows_n);
-          cur.direct.swap(nxt.direct);
-          cur.pix_direct.swap(nxt.pix_direct);
-          cur.stamps.swap(nxt.stamps);
+          std::swap(cur, nxt);   // every list at once: the next restriction filters these
           vw = &view;
           view_stamps = active;
           if (exec) {

@@ -50,7 +50,7 @@ struct StampDesc {
 
 // Per-stamp convolution path chosen by gf_psf_prepare.
 struct PathDesc {
-  int32_t fft;    // 1 = FFT path, 0 = direct
+  int32_t fft;    // 0 = direct, 1 = multi-pass FFT, 2 = one-workgroup FFT (fused)
   int32_t L;      // FFT side (0 on the direct path)
   int32_t plan;   // index into the plan table (-1 on the direct path)
   int32_t pad0;
@@ -73,6 +73,25 @@ struct Work {
   int32_t unit;
 };
 
+// What an FFT convolution launch computes: the valid convolution of the
+// padded model (CONV), the adjoint correlation of an image onto the padded
+// grid (CORR), the OTF of the PSF taps (OTF), or CONV ending in the chi^2
+// epilogue instead of writing the model (CHI2).
+enum { MODE_CONV = 0, MODE_CORR = 1, MODE_OTF = 2, MODE_CHI2 = 3 };
+
+// FFT sides that the one-workgroup 2-D convolution covers: every even
+// 2^a 3^b 5^c up to 192, whose half spectrum (L + 1 rows of L/2 + 1 bins,
+// one padding slot per 32) fits one workgroup's LDS.
+constexpr int kF2dSides[] = {8,  10, 12, 16, 18, 20,  24,  30,  32,  36,  40,  48,  50,  54,  60,
+                             64, 72, 80, 90, 96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192};
+constexpr int kF2dN = (int)(sizeof(kF2dSides) / sizeof(kF2dSides[0]));
+constexpr int kF2dMaxL = 192;
+inline int f2d_class(int L) {
+  for (int i = 0; i < kF2dN; ++i)
+    if (kF2dSides[i] == L) return i;
+  return -1;
+}
+
 // Work lists of one launch set: by default a batch's and a prepared PSF's
 // full lists; gf_fit_lm substitutes lists that hold only the stamps still
 // iterating, so finished stamps cost no workgroups.  Null pointers mean
@@ -90,6 +109,10 @@ struct WorkView {
   int n_pix_direct = 0;
   const Work *stamps = nullptr;   // the stamps still iterating (unit 0), for the per-stamp LM kernels
   int n_stamps = 0;
+  // one-workgroup FFT convolutions: entries of side class c at
+  // f2d[f2d_first[c] .. f2d_first[c + 1])
+  const Work *f2d = nullptr;
+  int f2d_first[kF2dN + 1] = {};
 };
 
 // Per-component constants of the evaluation kernels (computed per workgroup).
@@ -259,6 +282,17 @@ struct gf_ctx {
   gf::LmGraphKey lm_key;
   hipGraph_t lm_graph = nullptr;
   hipGraphExec_t lm_exec = nullptr;
+  // tuning table: per one-workgroup side class, the FFT form that the
+  // automatic path choice takes (-1 untuned, 1 multi-pass, 2 one-workgroup)
+  int8_t tune_form[gf::kF2dN];
+  std::string tune_path;      // file the table is read from and written to ("" = none)
+  gf_ctx() {
+    for (int i = 0; i < gf::kF2dN; ++i) tune_form[i] = -1;
+  }
+  bool tune_multipass(int L) const {
+    const int k = gf::f2d_class(L);
+    return k >= 0 && tune_form[k] == 1;
+  }
 };
 
 namespace gf {
@@ -331,7 +365,14 @@ struct gf_psf {
   int64_t n_c2 = 0;
   std::vector<gf::Work> h_pix_direct;
   gf::Work *d_pix_direct = nullptr;
-  int n_fft = 0, n_direct = 0;
+  // one-workgroup FFT convolutions (sides up to kF2dMaxL): one entry per
+  // stamp, grouped by side class; the OTFs of these stamps are stored
+  // row-major [L][L/2+1]
+  std::vector<gf::Work> h_f2d;
+  gf::Work *d_f2d = nullptr;
+  int f2d_first[gf::kF2dN + 1] = {};
+  int64_t f2d_tw[gf::kF2dN] = {};     // twiddle offset of each side class in d_tw
+  int n_fft = 0, n_direct = 0, n_f2d = 0;
 };
 
 struct gf_line_batch {

@@ -17,6 +17,7 @@ import torch
 from . import _lib as L
 
 GF_CONV_AUTO, GF_CONV_FFT, GF_CONV_DIRECT = L.GF_CONV_AUTO, L.GF_CONV_FFT, L.GF_CONV_DIRECT
+GF_CONV_FFT_MULTIPASS, GF_CONV_FFT_FUSED = L.GF_CONV_FFT_MULTIPASS, L.GF_CONV_FFT_FUSED
 
 LM_RESULT_DTYPE = np.dtype([("chi2", "<f8"), ("lambda", "<f8"), ("iters", "<i4"), ("nfev", "<i4"),
                             ("njev", "<i4"), ("status", "<i4"), ("reason", "<i4"), ("pad", "<i4")])

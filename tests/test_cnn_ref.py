@@ -91,3 +91,26 @@ def test_input_normalisation():
     fr = st[0][mask]
     assert z[0, 8, 8, 0] == pytest.approx(np.arcsinh((10 - fr.mean()) / fr.std()))
     assert z.shape == (1, 16, 16, 1)
+
+
+def test_bf16_error_model_covers_rounded_network():
+    """The element-wise error model used by the GPU forward test covers a CPU
+    network that rounds every operand to BF16 (6 standard deviations), and
+    it is tight enough to mean something (well below the outputs)."""
+    from tests import cnn_bound as CB
+    import synth
+    side, n = 64, 16
+    p = C.init_params(5, side)
+    g = synth.rng(6)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = 0.05 * g.standard_normal(p[k].shape)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    yy, xx = np.mgrid[0:side, 0:side]
+    x = (0.02 * g.standard_normal((n, side, side))
+         + np.exp(-((yy - 32.0) ** 2 / 50.0 + (xx - 30.0) ** 2 / 80.0))[None]).astype(np.float32)
+    y, sd = CB.forward_error_sigma(p, x)
+    ys = CB.forward_bf16(p, x)
+    assert np.all(np.abs(ys - y) <= 6 * sd + 1e-6)
+    assert sd.max() < 0.05 * np.abs(y).max()
+    assert np.abs(ys - y).max() > 0.05 * sd.max()   # the rounding is really there

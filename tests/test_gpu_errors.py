@@ -47,7 +47,7 @@ def test_padded_side_and_direct_psf_limits(ctx):
     taps = to_dev(np.full(45 * 45, 1.0 / (45 * 45), np.float32))
     assert _status(L.gf_psf_prepare, ctx.ptr, b.ptr, int(taps.data_ptr()), L.GF_CONV_DIRECT) == L.GF_ESHAPE
     p = ops.Psf(ctx, b, taps, ops.GF_CONV_AUTO)   # the automatic choice takes the FFT path
-    assert list(p.uses_fft) == [1]
+    assert list(p.uses_fft) == [2]                 # padded side 108: the one-workgroup form
 
 
 def test_argument_ranges(ctx):
@@ -100,4 +100,8 @@ def test_nonfinite_data_ends_the_fit(ctx, gfo):
     w[3, 4] = 0.0
     gb2 = GpuBatch(ctx, [st], data=[d], weights=[w])
     th2, info2 = ops.fit_lm(ctx, gb2.batch, gb2.psf, gb2.data, gb2.weight, to_dev(st.start, torch.float64))
-    assert info2["status"][0] == L.GF_OK
+    # it converges (or ends by the damping cap once the FP32 chi^2 no longer
+    # resolves the last decreases) at the oracle's minimum
+    _, ref = gfo.fit_lm(st.start, gb2.psf64(0), gb2.d32[0].astype(np.float64), gb2.w32[0].astype(np.float64), 5)
+    assert info2["status"][0] == L.GF_OK or info2["reason"][0] == 4, info2
+    assert info2["chi2"][0] == pytest.approx(ref["chi2"], rel=1e-5)

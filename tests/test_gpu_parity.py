@@ -360,9 +360,13 @@ def test_fit_lm_c1_matches_oracle(ctx, gfo):
 
 
 def test_fit_lm_batch_default_tolerance(ctx, gfo):
-    """A batch of uneven stamps fitted at ftol = 1e-5: every stamp reaches a
-    chi^2 within 1e-5 (relative) of... its own oracle fit from the same start."""
-    stamps = _c3_small(4, seed=123)
+    """A batch of uneven stamps (32 to 256 px) fitted at the throughput
+    tolerance, ftol = 1e-5, on both sides: every stamp's final chi^2 within
+    1e-5 (relative) of the oracle's fit from the same start.  (Parameter
+    parity at ftol 1e-12 for the same sizes is in
+    test_gpu_workload_parity.py.)"""
+    g = synth.rng(123)
+    stamps = [synth.c3_stamp(g, N, i, 123) for i, N in enumerate([32, 64, 96, 128, 192, 256])]
     ths = [st.truth.astype(np.float32).astype(np.float64) for st in stamps]
     data, weights = _observed(gfo, stamps, ths, 500)
     gb = GpuBatch(ctx, stamps, data=data, weights=weights)
@@ -370,16 +374,17 @@ def test_fit_lm_batch_default_tolerance(ctx, gfo):
     hi = np.concatenate([synth.bounds(1, st.H, st.W)[1] for st in stamps])
     start = np.concatenate([st.start for st in stamps])
     fit, res = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(start, torch.float64),
-                          lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-12, xtol=1e-10,
-                          max_iter=200)
-    fit = fit.cpu().numpy()
+                          lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-5)
     for s, st in enumerate(stamps):
         l, h = synth.bounds(1, st.H, st.W)
         ref, info = gfo.fit_lm(st.start, gb.psf64(s), gb.d32[s].astype(np.float64), gb.w32[s].astype(np.float64),
-                               5, lo=l, hi=h, ftol=1e-12, xtol=1e-10, max_iter=200)
-        o = gb.batch.offsets["par"][s]
-        assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), s
-        _param_close(fit[o:o + 8], ref, 1, 0.02)
+                               5, lo=l, hi=h, ftol=1e-5)
+        # the oracle converges by ftol; the GPU too, or by the damping cap once
+        # its FP32 chi^2 no longer resolves the last decreases, at the same
+        # chi^2
+        assert info["status"] == 0, (s, info)
+        assert res["status"][s] == 0 or res["reason"][s] == 4, (s, res[s])
+        assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), (s, st.H, res[s], info)
 
 
 def test_fit_lm_uneven_batch_c3(ctx, gfo):

@@ -164,6 +164,20 @@ def test_network_forward(net_case):
     assert rel_l2(got, ref) < 3e-2, rel_l2(got, ref)
 
 
+def test_network_forward_elementwise(net_case):
+    """Every output of the forward pass within 6 standard deviations of the
+    BF16 rounding model (tests/cnn_bound.py, itself checked on the CPU
+    against a network that rounds every operand) of the FP64 reference."""
+    from tests import cnn_bound as CB
+    side, n, p32, x, t, net = net_case
+    got = net.forward(to_dev(x)).cpu().numpy().astype(np.float64)
+    p64 = {k: v.astype(np.float64) for k, v in p32.items()}
+    ref, sd = CB.forward_error_sigma(p64, x)
+    err = np.abs(got - ref)
+    print("forward: max |err| / sd", float((err / sd).max()), "max sd", float(sd.max()), flush=True)
+    assert np.all(err <= 6.0 * sd + 1e-6), (err / sd).max()
+
+
 def test_network_gradients(net_case):
     print("network gradients", flush=True)
     side, n, p32, x, t, net = net_case
