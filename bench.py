@@ -1,33 +1,48 @@
 """Benchmark of the galaxy-fitting hot path on one MI355X.
 
-Default workload (one 512x512 image, Sersic bulge + exponential disk, 65x65
-Moffat PSF on a 576-point FFT grid, 15 free parameters, Poisson + read noise):
-one step is one whole Levenberg-Marquardt fit from the seeded perturbed start
-to the relative chi^2 tolerance 1e-5, run by gf_fit_lm on the device, i.e. one
-pass of every stage of the hot path (parameter set-up, Sersic evaluation with
-5x5 oversampling and its derivatives, FFT convolution, chi^2 and residual,
-normal equations, FP64 solve and damping update).
+Default run (no --workload): the uneven batch is the headline and the other
+single-GPU workloads are nested in the same JSON line, each with its own
+timing and roofline entry.
 
-  value   = model evaluations per second counted in output pixels (Mpix/s):
-            512^2 x (trial evaluations + Jacobian evaluations) per fit / time
-            per fit.  Every one of them runs steps 1-3 over the whole image.
-  fits/s  = fits per second (reported beside it).
+  headline  C3: 4096 single-Sersic stamps of 32..256 px (Gaussian/Moffat PSFs
+            of 15..33 px) fitted by one gf_fit_lm call to the relative chi^2
+            tolerance 1e-5.  One step = the whole batch (every stage of the
+            hot path: parameter set-up, Sersic evaluation with 5x5
+            oversampling and its derivatives, FFT convolution, chi^2, normal
+            equations, FP64 solve and damping update).
+            value = fits/s; mpix_per_s counts the steps 1-3 passes that ran
+            (start point, trial points and Jacobians) in stamp pixels.
+  c4        likelihood batch: 1024 parameter vectors x one 256 x 256 image with
+            a 33 x 33 Moffat PSF; one step = steps 1-3 for all vectors;
+            value = Mpix/s.
+  c2        one 512 x 512 bulge + disk image, 65 x 65 Moffat PSF, 15
+            parameters; one step = one whole fit; value = fits/s, mpix_per_s
+            counts the evaluation passes the fit ran.
+  c1        one 64 x 64 stamp, 8 parameters; latency: ms per whole fit.
 
-`--workload c4` runs the likelihood batch instead (1024 parameter vectors
-against one 256x256 image with a 33x33 Moffat PSF; one step = steps 1-3 for all
-vectors through gf_likelihood).
+`--workload c3|c4|c2|c1|c5|lines` runs one workload alone (its line has the
+same layout as the headline).  `--steps` and `--warmup` apply to the headline
+(or to the one workload); the nested workloads use their own defaults.
 
-The roofline entry is for the kernel with the largest share of the step's GPU
-time, measured with HIP events recorded by the library on the stream each
-kernel is launched on (a separate, non-graph fit with per-kernel timing on).
-The CPU baseline times the FP64 oracle on a bounded sample of the same
-workload on the host cores.
+Rooflines: the dominant kernel of each workload's profiled step (per-kernel
+HIP events recorded by the library on the stream each kernel is launched
+on), its algorithmic bytes or operations per launch divided by its average
+launch time, against the MI355X spec peaks (HBM 8 TB/s, FP32 157.3 TFLOP/s);
+the measured triad, unpacked-FMA and transcendental rates are reported
+beside.  For the uneven batch the profile is its first LM iteration, where
+every stamp is active and the work per launch is known.  `stage_roofline`
+gives steps 2 and 3 with their definitional bytes (convolution: padded model
+read, stamp written, OTF once; with chi^2: padded model, data and weight
+read, OTF once).
+
+CPU baseline: the FP64 oracle (rebuilt -O3 -march=native for the host) on a
+bounded sample of each workload, on one thread and on all host cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -40,6 +55,17 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed FMA)
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix
+METRIC = "model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5"
+
+# Algorithmic FP32 operations per sub-sample and component (an FMA counts
+# two, a log2 or exp2 one): the model 17, the model with its seven
+# derivatives 35.
+EVAL_FLOP_PER_SUB = 17
+EVAL_JAC_FLOP_PER_SUB = 35
+# Instructions per sub-sample and component of the model loop: 7 VALU and 3
+# transcendental (log2, exp2, exp2), for the issue-rate ceiling.
+EVAL_VALU_PER_SUB, EVAL_TRANS_PER_SUB = 7, 3
 
 
 def parse():
@@ -47,12 +73,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "lines"], default="c2")
+    ap.add_argument("--workload", choices=["suite", "c1", "c2", "c3", "c4", "c5", "lines"], default="suite")
     ap.add_argument("--train-stamps", type=int, default=200_000, help="C5: rendered training stamps")
     ap.add_argument("--epochs", type=int, default=4, help="C5: training epochs")
     ap.add_argument("--mcmc-steps", type=int, default=2000, help="C4: Metropolis steps of the chain run")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="target CPU time per oracle sample")
     ap.add_argument("--breakdown", action="store_true", help="print the per-kernel breakdown to stderr")
     ap.add_argument("--calibrate-peaks", action="store_true",
                     help="only run the triad / FMA / transcendental probes and print the measured peaks")
@@ -61,117 +87,211 @@ def parse():
     return ap.parse_args()
 
 
-# Algorithmic work per unit (see the roofline notes in the design document).
-# Evaluation: FP32 operations per sub-sample and component, counting an FMA as
-# two and a transcendental (log2 / exp2) as one.
-EVAL_FLOP_PER_SUB = 17
-EVAL_JAC_FLOP_PER_SUB = 35
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_work(name, geo, launches_per_step):
-    """(bound, algorithmic units per launch, unit) for a kernel of the step."""
-    npix, npad, nch, ncomp, S, L, H = (geo[k] for k in ("npix", "npad", "nch", "ncomp", "S", "L", "H"))
-    Lh = L // 2 + 1
-    if name == "k_eval":
-        return "alu", npad * ncomp * S * S * EVAL_FLOP_PER_SUB, "flop"
-    if name == "k_eval_jac":
-        return "alu", npad * ncomp * S * S * EVAL_JAC_FLOP_PER_SUB, "flop"
-    if name == "k_chi2":
-        # model read per pixel; data and weight per distinct image
-        return "hbm", npix * 4 + geo.get("nimg", npix) * 8, "byte"
-    if name == "k_gram":
-        return "hbm", npix * (4 * nch + 8), "byte"
-    if name == "k_line_lm":
-        # FP32 operations of the whole fit (see line_fit_flops), one launch
-        return "alu", geo["line_flops"], "flop"
-    if name == "k_fft_irows_chi2":
-        # inverse rows of the spectra in, data and weight per distinct image
-        return "hbm", geo.get("chan_" + name, 1) * H * Lh * 8 + geo.get("nimg", npix) * 8, "byte"
-    if name in ("k_fft_rows", "k_fft_cols", "k_fft_irows") and "fft_bytes" in geo:
-        per_ch, once = geo["fft_bytes"][name]
-        return "hbm", geo.get("chan_" + name, 1) * per_ch + once, "byte"
-    if name in ("k_fft_rows", "k_fft_cols", "k_fft_irows"):
-        c = geo.get("chan_" + name, 1)
-        if name == "k_fft_rows":
-            return "hbm", c * (npad * 4 + (npad // geo["Mw"]) * Lh * 8), "byte"
-        if name == "k_fft_cols":
-            return "hbm", c * ((npad // geo["Mw"]) * Lh * 8 + H * Lh * 8) + L * Lh * 8, "byte"
-        return "hbm", c * (H * Lh * 8 + npix * 4), "byte"
-    return None, 0, None
+# ----------------------------------------------------------------- rooflines
+def fft_geometry(H, W, K, L):
+    """Per-stamp sizes of the convolution: padded pixels, stamp pixels, OTF bytes."""
+    Mh, Mw = H + K - 1, W + K - 1
+    return Mh * Mw, H * W, L * (L // 2 + 1) * 8
 
 
-def run_c2(args, torch, ops, synth):
-    dev = torch.device("cuda", 0)
-    st = synth.c2()
-    ctx = ops.Context(0)
-    batch = ops.Batch(ctx, [st.H], [st.W], [st.K], [2])
-    taps = torch.from_numpy(st.psf.astype(np.float32).ravel()).to(dev)
-    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_FFT)
-    # observation: the model at the truth (rendered by the library) plus noise
-    truth32 = torch.from_numpy(st.truth.astype(np.float32)).to(dev)
-    m_true = ops.model(ctx, batch, psf, truth32, 5).cpu().numpy().astype(np.float64).reshape(st.H, st.W)
-    d, w = synth.add_poisson_read_noise(m_true, st.meta["read_noise"], st.meta["gain"], st.noise_seed)
-    data = torch.from_numpy(d.astype(np.float32).ravel()).to(dev)
-    weight = torch.from_numpy(w.astype(np.float32).ravel()).to(dev)
-    lo, hi = synth.bounds(2, st.H, st.W)
-    lo_t = torch.from_numpy(lo).to(dev)
-    hi_t = torch.from_numpy(hi).to(dev)
-    theta0 = torch.from_numpy(st.start).to(dev)
-    opts = dict(ftol=1e-5, max_iter=100)
+def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=False):
+    """Algorithmic work per launch of each kernel when every stamp of the
+    batch takes part: (bound, units).  stamps: list of (H, W, K); paths and
+    sides from the prepared PSF; nch: Jacobian channels per launch; nimg:
+    pixels of the distinct observations (shared-image batches)."""
+    npad = npix = 0
+    f2 = dict(pad=0, pix=0, otf=0, n=0)
+    mp = dict(rows=0, cols=0, irows=0, irows_chi2=0, otf=0, pad=0, pix=0, n=0)
+    for (H, W, K), path, L in zip(stamps, paths, sides):
+        pad, pix, otf = fft_geometry(H, W, K, max(L, 2))
+        npad += pad
+        npix += pix
+        if shared_otf and (f2["n"] or mp["n"]):
+            otf = 0
+        Lh = L // 2 + 1
+        if path == 2:
+            f2["pad"] += pad
+            f2["pix"] += pix
+            f2["otf"] += otf
+            f2["n"] += 1
+        elif path == 1:
+            Mh = H + K - 1
+            mp["rows"] += 4 * pad + 8 * Mh * Lh
+            mp["cols"] += 8 * Mh * Lh + 8 * H * Lh
+            mp["irows"] += 8 * H * Lh + 4 * pix
+            mp["irows_chi2"] += 8 * H * Lh
+            mp["otf"] += otf
+            mp["pad"] += pad
+            mp["pix"] += pix
+            mp["n"] += 1
+    img = npix if nimg is None else nimg
+    dw = 8 * (img if nimg is not None else f2["pix"])      # data + weight read by the fused chi^2
+    dw_mp = 8 * (img if nimg is not None else mp["pix"])
+    t = {
+        "k_eval": ("alu", npad * ncomp * S * S * EVAL_FLOP_PER_SUB),
+        "k_eval_jac": ("alu", npad * ncomp * S * S * EVAL_JAC_FLOP_PER_SUB),
+        "k_gram": ("hbm", npix * (4 * nch + 8)),
+        "k_chi2": ("hbm", 4 * npix + 8 * img),
+        # the one-workgroup convolutions move only their definitional bytes
+        "k_fft2d": ("hbm", nch * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"]),
+        "k_fft2d_chi2": ("hbm", 4 * f2["pad"] + dw + f2["otf"]),
+        # the multi-pass kernels: each pass's own reads and writes (spectra
+        # included)
+        "k_fft_rows": ("hbm", nch * mp["rows"]),
+        "k_fft_cols": ("hbm", nch * mp["cols"] + mp["otf"]),
+        "k_fft_irows": ("hbm", nch * mp["irows"]),
+        "k_fft_rows.chi2": ("hbm", mp["rows"]),
+        "k_fft_cols.chi2": ("hbm", mp["cols"] + mp["otf"]),
+        "k_fft_irows_chi2": ("hbm", mp["irows_chi2"] + dw_mp),
+    }
+    stage = dict(
+        # step 2 of the Jacobian channels: padded model in, stamp out, OTF once
+        convolution=dict(kernels=["k_fft2d", "k_fft_rows", "k_fft_cols", "k_fft_irows"],
+                         bytes=nch * (4 * (f2["pad"] + mp["pad"]) + 4 * (f2["pix"] + mp["pix"])) + f2["otf"] +
+                         mp["otf"]),
+        # steps 2-3 of a model evaluation: padded model, data and weight in,
+        # OTF once, only chi^2 out
+        convolution_chi2=dict(kernels=["k_fft2d_chi2", "k_fft_rows.chi2", "k_fft_cols.chi2", "k_fft_irows_chi2"],
+                              bytes=4 * (f2["pad"] + mp["pad"]) + (8 * img if nimg is not None else
+                                                                     8 * (f2["pix"] + mp["pix"])) +
+                              f2["otf"] + mp["otf"]),
+        fused_convolution=dict(kernels=["k_fft2d"], bytes=nch * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"]),
+        fused_convolution_chi2=dict(kernels=["k_fft2d_chi2"], bytes=4 * f2["pad"] + dw + f2["otf"]),
+        multipass_convolution=dict(kernels=["k_fft_rows", "k_fft_cols", "k_fft_irows"],
+                                   bytes=nch * (4 * mp["pad"] + 4 * mp["pix"]) + mp["otf"]),
+    )
+    return t, stage, dict(npad=npad, npix=npix, fused_stamps=f2["n"], multipass_stamps=mp["n"])
 
-    def step(**kw):
-        o = dict(opts)
-        o.update(kw)
-        return ops.fit_lm(ctx, batch, psf, data, weight, theta0, lo=lo_t, hi=hi_t, **o)
 
-    # a fit takes well under a millisecond: 100 timed fits keep the host's
-    # share of the timing noise small
-    K = args.steps if args.steps is not None else 100
-    W = args.warmup if args.warmup is not None else 5
-    for _ in range(W):
-        step()
-    torch.cuda.synchronize()
-    # the result records stay on the device during the timed fits (as the
-    # fitted parameters do) and are read after the timed region
-    t0 = time.perf_counter()
-    recs = []
-    for _ in range(K):
-        th, res = step(return_device=True)
-        recs.append(res)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    infos = [ops.lm_info(r) for r in recs]
-    info = infos[-1]
-    nfev, njev, iters = int(info["nfev"][0]), int(info["njev"][0]), int(info["iters"][0])
-    if any(int(i["nfev"][0]) != nfev or int(i["njev"][0]) != njev for i in infos):
-        raise RuntimeError("fits of the same input took different paths")
-    ms = t / K * 1e3
-    npix = st.H * st.W
-    mpix_s = (nfev + njev) * npix / (ms * 1e-3) / 1e6
-    # per-kernel breakdown of one fit (no graph, events on the launching stream)
+def roofline(prof, table, peaks, launches_per_call=None):
+    """Dominant kernel of the profile and per-kernel figures.  prof: {name:
+    (launches, total ms)}; table: {name: (bound, units per launch)}."""
+    total = sum(v[1] for v in prof.values())
+    stages = {}
+    for k, (n, t) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        e = dict(launches=n, ms_total=round(t, 4), us_per_launch=round(t / n * 1e3, 2), share=round(t / total, 4))
+        b = table.get(k)
+        if b and b[1] > 0:
+            per = t / n * 1e-3
+            if b[0] == "hbm":
+                e.update(bound="hbm", bytes_per_launch=int(b[1]), gbs=round(b[1] / per / 1e9, 1),
+                         frac=round(b[1] / per / 1e9 / HBM_PEAK_GBS, 4))
+            else:
+                e.update(bound="alu", flop_per_launch=int(b[1]), tflops=round(b[1] / per / 1e12, 2),
+                         frac=round(b[1] / per / 1e12 / FP32_PEAK_TFLOPS, 4))
+        stages[k] = e
+    cand = [k for k in prof if table.get(k) and table[k][1] > 0]
+    name = max(cand, key=lambda k: prof[k][1])
+    n, t = prof[name]
+    bound, units = table[name]
+    per = t / n * 1e-3
+    if bound == "hbm":
+        ach = units / per / 1e9
+        rl = dict(bound="hbm", kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                  frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+        if peaks:
+            rl["frac_of_measured_triad"] = round(ach / peaks["triad_gbs"], 4)
+    else:
+        ach = units / per / 1e12
+        rl = dict(bound="alu", kernel=name, achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                  frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
+        if peaks:
+            rl["measured_fp32_fma_unpacked_tflops"] = peaks["fma_tflops"]
+            rl["frac_of_unpacked_fma"] = round(ach / peaks["fma_tflops"], 4)
+            if name == "k_eval":
+                # issue ceiling of the loop's 7 VALU + 3 transcendental
+                # instructions per sub-sample at the measured rates
+                sub = units / EVAL_FLOP_PER_SUB
+                t_min = sub * (EVAL_VALU_PER_SUB * 2 / (peaks["fma_tflops"] * 1e12) +
+                               EVAL_TRANS_PER_SUB / (peaks["transcendental_gops"] * 1e9))
+                rl["issue_bound_us"] = round(t_min * 1e6, 2)
+                rl["frac_of_issue_bound"] = round(t_min / per, 4)
+    rl["avg_launch_us"] = round(per * 1e6, 2)
+    rl["launches_profiled"] = n
+    return rl, stages
+
+
+def stage_fractions(prof, stage):
+    """The definitional-byte fractions of steps 2 and 3 (per call of the
+    stage: the summed time of its kernels over the calls profiled)."""
+    out = {}
+    for name, st in stage.items():
+        ks = [k for k in st["kernels"] if k in prof]
+        if not ks or st["bytes"] <= 0:
+            continue
+        calls = max(prof[k][0] for k in ks)
+        t = sum(prof[k][1] for k in ks) / calls * 1e-3
+        out[name] = dict(kernels=ks, calls=calls, bytes_per_call=int(st["bytes"]), us_per_call=round(t * 1e6, 2),
+                         gbs=round(st["bytes"] / t / 1e9, 1), frac=round(st["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4))
+    return out
+
+
+# HBM bytes per launch of a dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by the copy calibration: fetch x2, write x1), as
+# summarised in profiles/*_hbm_traffic.md.  Valid only while the kernel
+# source is the one the counters were taken on (first 16 hex digits of the
+# SHA-256 of each listed source).
+TRAFFIC = {
+    ("c2", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "524bd17134a451f8"}, bytes=1.8800e+07,
+                               summary="profiles/c2_fit_hbm_traffic.md"),
+    ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "524bd17134a451f8"}, bytes=3.8624e+08,
+                           summary="profiles/c4_likelihood_hbm_traffic.md"),
+}
+
+
+def measured_traffic(workload, rl):
+    t = TRAFFIC.get((workload, rl.get("kernel")))
+    if not t:
+        return None
+    for src, sha in t["sources"].items():
+        try:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest()[:16] != sha:
+                    return None
+        except OSError:
+            return None
+    rl["traffic_source"] = t["summary"]
+    return round(t["bytes"], 0)
+
+
+def profile(ctx, fn):
     from paper_1101_2254_amd import _lib
+    import torch
+    torch.cuda.synchronize()
     _lib.gf_profile_start(ctx.ptr)
-    step(use_graph=0)
+    out = fn()
     torch.cuda.synchronize()
     _lib.gf_profile_stop(ctx.ptr)
-    prof = _lib.gf_profile_read(ctx.ptr)
-    geo = dict(npix=npix, npad=(st.H + st.K - 1) * (st.W + st.K - 1), Mw=st.W + st.K - 1, H=st.H, nch=14, ncomp=2,
-               S=5, L=psf.fft_side[0])
-    result = dict(
-        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
-        value=round(mpix_s, 3), unit="Mpix/s", ms_per_step=round(ms, 4), fits_per_s=round(1e3 / ms, 3),
-        lm=dict(iters=iters, nfev=nfev, njev=njev, status=int(info["status"][0]), chi2=float(info["chi2"][0]),
-                chi2_per_dof=float(info["chi2"][0]) / (npix - 15)),
-        config=dict(workload="C2: one 512x512 image, Sersic bulge + exponential disk, 65x65 Moffat PSF "
-                             "(beta=3, FWHM=3 px), 576-point FFT convolution, 5x5 oversampling, 15-parameter "
-                             "LM fit to chi2 rel tol 1e-5; one step = one whole fit",
-                    image=[st.H, st.W], psf=st.K, fft_side=psf.fft_side[0], params=15, oversample=5),
-    )
-    result.update(steps=K, warmup=W)
-    return result, prof, geo, dict(st=st, nfev=nfev, njev=njev, iters=iters, npix=npix)
+    return _lib.gf_profile_read(ctx.ptr), out
 
 
-def run_c3(args, torch, ops, synth):
+def passes(prof):
+    """Steps 1-3 passes that a profiled run made: model evaluations plus
+    Jacobian evaluations (each over every stamp still fitting)."""
+    return prof.get("k_eval", (0, 0))[0], prof.get("k_eval_jac", (0, 0))[0]
+
+
+# ----------------------------------------------------------------- workloads
+def render_observation(torch, ops, ctx, batch, psf, stamps, seed_of, noise):
+    """The library's model at the FP32 truth plus seeded numpy noise."""
+    dev = ctx.device
+    truth = torch.from_numpy(np.concatenate([s.truth for s in stamps]).astype(np.float32)).to(dev)
+    m = ops.model(ctx, batch, psf, truth, 5).cpu().numpy().astype(np.float64)
+    off = batch.offsets["pix"]
+    d = np.empty_like(m)
+    w = np.empty_like(m)
+    for i, st in enumerate(stamps):
+        sl = slice(off[i], off[i] + st.H * st.W)
+        dd, ww = noise(m[sl].reshape(st.H, st.W), st, seed_of(i, st))
+        d[sl], w[sl] = dd.ravel(), ww.ravel()
+    return torch.from_numpy(d.astype(np.float32)).to(dev), torch.from_numpy(w.astype(np.float32)).to(dev)
+
+
+def run_c3(args, torch, ops, synth, peaks, steps=None, warmup=None):
     """4096 uneven single-Sersic stamps fitted in one gf_fit_lm call (ftol 1e-5)."""
     dev = torch.device("cuda", 0)
     stamps = synth.c3(4096)
@@ -182,16 +302,8 @@ def run_c3(args, torch, ops, synth):
     batch = ops.Batch(ctx, H, H, K, [1] * n)
     taps = torch.from_numpy(np.concatenate([s.psf.astype(np.float32).ravel() for s in stamps])).to(dev)
     psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
-    truth = torch.from_numpy(np.concatenate([s.truth for s in stamps]).astype(np.float32)).to(dev)
-    m_true = ops.model(ctx, batch, psf, truth, 5).cpu().numpy().astype(np.float64)
-    off = batch.offsets["pix"]
-    d = np.empty_like(m_true)
-    w = np.empty_like(m_true)
-    for i, st in enumerate(stamps):
-        sl = slice(off[i], off[i] + st.H * st.W)
-        d[sl], w[sl] = synth.add_gaussian_noise(m_true[sl], st.noise_sigma, st.noise_seed)
-    data = torch.from_numpy(d.astype(np.float32)).to(dev)
-    weight = torch.from_numpy(w.astype(np.float32)).to(dev)
+    data, weight = render_observation(torch, ops, ctx, batch, psf, stamps, lambda i, st: st.noise_seed,
+                                      lambda m, st, seed: synth.add_gaussian_noise(m, st.noise_sigma, seed))
     lo = np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in stamps])
     hi = np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in stamps])
     lo_t, hi_t = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
@@ -202,70 +314,57 @@ def run_c3(args, torch, ops, synth):
         o.update(kw)
         return ops.fit_lm(ctx, batch, psf, data, weight, theta0, lo=lo_t, hi=hi_t, **o)
 
-    K_ = args.steps if args.steps is not None else 5
-    W = args.warmup if args.warmup is not None else 1
+    K_ = steps if steps is not None else 5
+    W = warmup if warmup is not None else 1
     for _ in range(W):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    recs = []
     for _ in range(K_):
-        _, info = step()
+        recs.append(step(return_device=True)[1])
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ms = t / K_ * 1e3
-    from paper_1101_2254_amd import _lib
-    _lib.gf_profile_start(ctx.ptr)
-    step(use_graph=0)
-    torch.cuda.synchronize()
-    _lib.gf_profile_stop(ctx.ptr)
-    prof = _lib.gf_profile_read(ctx.ptr)
-    npix = int(sum(s.H * s.W for s in stamps))
-    npad = int(sum((s.H + s.K - 1) ** 2 for s in stamps))
-    evals = int(info["nfev"].sum() + info["njev"].sum())
-    result = dict(
-        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
-        value=round(n / (ms * 1e-3), 2), unit="fits/s", ms_per_step=round(ms, 3),
-        mpix_per_s=round(evals / n * npix / n * n / (ms * 1e-3) / 1e6, 2),
+    ms = (time.perf_counter() - t0) / K_ * 1e3
+    info = ops.lm_info(recs[-1])
+    # the first iteration, kernel by kernel: every stamp is active
+    prof, _ = profile(ctx, lambda: step(use_graph=0, max_iter=1))
+    geo = [(s.H, s.W, s.K) for s in stamps]
+    table, stage, sizes = kernel_table(geo, psf.uses_fft, psf.fft_side, 7, 1, 5)
+    rl, kern = roofline(prof, table, peaks)
+    pix = np.array([s.H * s.W for s in stamps], dtype=np.float64)
+    evals_pix = float(np.sum((info["nfev"] + info["njev"]) * pix))
+    res = dict(
+        value=round(n / (ms * 1e-3), 2), unit="fits/s", ms_per_step=round(ms, 3), steps=K_, warmup=W,
+        mpix_per_s=round(evals_pix / (ms * 1e-3) / 1e6, 2),
         lm=dict(iters_mean=float(info["iters"].mean()), iters_max=int(info["iters"].max()),
-                converged=float((info["status"] == 0).mean()), nfev=int(info["nfev"].sum()),
-                njev=int(info["njev"].sum())),
+                converged=float((info["status"] == 0).mean()), damping_cap=float((info["reason"] == 4).mean()),
+                nfev=int(info["nfev"].sum()), njev=int(info["njev"].sum())),
         config=dict(workload="C3: 4096 uneven single-Sersic stamps (32..256 px, Gaussian/Moffat PSF 15..33 px), "
                              "one gf_fit_lm call to chi2 rel tol 1e-5; one step = the whole batch",
-                    stamps=n, pixels=npix, oversample=5,
-                    fft_stamps=int(sum(psf.uses_fft)), direct_stamps=int(n - sum(psf.uses_fft))),
-    )
-    fb = {"k_fft_rows": [0, 0], "k_fft_cols": [0, 0], "k_fft_irows": [0, 0]}
-    for st, uf, L in zip(stamps, psf.uses_fft, psf.fft_side):
-        if not uf:
-            continue
-        M, Lh = st.H + st.K - 1, L // 2 + 1
-        fb["k_fft_rows"][0] += M * M * 4 + M * Lh * 8
-        fb["k_fft_cols"][0] += M * Lh * 8 + st.H * Lh * 8
-        fb["k_fft_cols"][1] += L * Lh * 8
-        fb["k_fft_irows"][0] += st.H * Lh * 8 + st.H * st.W * 4
-    geo = dict(npix=npix, npad=npad, Mw=1, H=1, nch=7, ncomp=1, S=5, L=2, fft_bytes=fb)
-    result.update(steps=K_, warmup=W)
-    return result, prof, geo, dict(stamps=stamps, info=info, npix=npix, nfev=int(info["nfev"].sum()),
-                                   njev=int(info["njev"].sum()))
+                    stamps=n, pixels=int(pix.sum()), oversample=5, fused_fft_stamps=sizes["fused_stamps"],
+                    multipass_fft_stamps=sizes["multipass_stamps"]),
+        roofline=rl, stages=kern, stage_roofline=stage_fractions(prof, stage),
+        roofline_profile="first LM iteration of the batch, kernel by kernel (every stamp active)")
+    return res, dict(stamps=stamps, info=info)
 
 
-def run_c4(args, torch, ops, synth):
+def run_c4(args, torch, ops, synth, peaks, steps=None, warmup=None):
     dev = torch.device("cuda", 0)
     base = synth.c4_truth()
     nvec = 1024
     ctx = ops.Context(0)
     batch = ops.Batch(ctx, [256] * nvec, [256] * nvec, [33] * nvec, [1] * nvec, shared=True)
     taps = torch.from_numpy(base.psf.astype(np.float32).ravel()).to(dev)
-    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_FFT)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
     one = ops.Batch(ctx, [256], [256], [33], [1])
-    psf1 = ops.Psf(ctx, one, taps, ops.GF_CONV_FFT)
+    psf1 = ops.Psf(ctx, one, taps, ops.GF_CONV_AUTO)
     m_true = ops.model(ctx, one, psf1, torch.from_numpy(base.truth.astype(np.float32)).to(dev), 5)
     d, w = synth.add_gaussian_noise(m_true.cpu().numpy().astype(np.float64).reshape(256, 256), base.noise_sigma,
                                     base.noise_seed)
     data = torch.from_numpy(d.astype(np.float32).ravel()).to(dev)
     weight = torch.from_numpy(w.astype(np.float32).ravel()).to(dev)
-    K = args.steps if args.steps is not None else 50
-    W = args.warmup if args.warmup is not None else 3
+    K = steps if steps is not None else 50
+    W = warmup if warmup is not None else 3
     thetas = [torch.from_numpy(synth.c4_vectors(s, nvec).astype(np.float32).ravel()).to(dev) for s in range(K + W)]
     work = ops.likelihood_workspace(ctx, batch, psf)
     out = torch.empty((nvec, 2), dtype=torch.float32, device=dev)
@@ -276,61 +375,133 @@ def run_c4(args, torch, ops, synth):
     for s in range(K):
         ops.likelihood(ctx, batch, psf, thetas[W + s], data, weight, 5, work=work, out=out)
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ms = t / K * 1e3
+    ms = (time.perf_counter() - t0) / K * 1e3
     npix = 256 * 256 * nvec
-    # Metropolis chains on the same batch: one chain per vector, started from
-    # this step's vectors, 2000 steps (each step = steps 1-3 for all chains)
+    prof, _ = profile(ctx, lambda: ops.likelihood(ctx, batch, psf, thetas[0], data, weight, 5, work=work, out=out))
+    # steps 2 and 3 also through their own entry points
+    mp = ops.eval_model(ctx, batch, thetas[0], 5)
+    mc = ops.convolve_psf(ctx, batch, psf, mp)
+
+    def sep():
+        for _ in range(5):
+            ops.convolve_psf(ctx, batch, psf, mp, out=mc)
+            ops.chi2(ctx, batch, mc, thetas[0], data, weight)
+
+    sep_prof, _ = profile(ctx, sep)
+    del mp, mc
+    geo = [(256, 256, 33)] * nvec
+    table, stage, sizes = kernel_table(geo, psf.uses_fft, psf.fft_side, 1, 1, 5, nimg=256 * 256, shared_otf=True)
+    rl, kern = roofline(prof, table, peaks)
+    rl["traffic"] = measured_traffic("c4", rl)
+    sr = stage_fractions(prof, stage)
+    sep_stage = {"convolution": stage["convolution"],
+                 "chi2": dict(kernels=["k_chi2", "k_pair_final"], bytes=4 * npix + 8 * 256 * 256)}
+    for k, v in stage_fractions(sep_prof, sep_stage).items():
+        sr["separate_" + k] = v
+    res = dict(
+        value=round(npix / (ms * 1e-3) / 1e6, 3), unit="Mpix/s", ms_per_step=round(ms, 4), steps=K, warmup=W,
+        config=dict(workload="C4: likelihood batch, 1024 parameter vectors x one 256x256 image, 33x33 Moffat PSF, "
+                             "288-point FFT, 5x5 oversampling; one step = steps 1-3 for all vectors",
+                    image=[256, 256], psf=33, fft_side=int(psf.fft_side[0]), fft_form=int(psf.uses_fft[0]),
+                    vectors=nvec, oversample=5),
+        roofline=rl, stages=kern, stage_roofline=sr)
+    if args.mcmc_steps > 0:
+        res["mcmc"] = run_mcmc(args, torch, ops, synth, ctx, batch, psf, data, weight, thetas[0], base, nvec, npix)
+    return res, dict(base=base, thetas_host=synth.c4_vectors(W, nvec), npix=npix)
+
+
+def run_mcmc(args, torch, ops, synth, ctx, batch, psf, data, weight, theta, base, nvec, npix):
+    """Metropolis chains on the likelihood batch: one chain per vector, each
+    step = steps 1-3 for all chains."""
+    dev = ctx.device
     n_mc = args.mcmc_steps
     scale = torch.from_numpy(np.tile(np.abs(base.truth) * 1e-4 + 1e-6, nvec)).to(dev)
     lo_b, hi_b = synth.bounds(1, 256, 256)
     lo_m = torch.from_numpy(np.tile(lo_b, nvec)).to(dev)
     hi_m = torch.from_numpy(np.tile(hi_b, nvec)).to(dev)
-    th_mc = thetas[0].double()
+    th_mc = theta.double()
     ops.mcmc_run(ctx, batch, psf, data, weight, th_mc, scale, 10, key=(4004, 1), lo=lo_m, hi=hi_m,
                  keep_samples=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, c2_mc, _, acc_mc = ops.mcmc_run(ctx, batch, psf, data, weight, th_mc, scale, n_mc, key=(4004, 1), stream=1,
-                                       lo=lo_m, hi=hi_m, keep_samples=False)
+    _, _, _, acc = ops.mcmc_run(ctx, batch, psf, data, weight, th_mc, scale, n_mc, key=(4004, 1), stream=1,
+                                lo=lo_m, hi=hi_m, keep_samples=False)
     torch.cuda.synchronize()
-    t_mc = time.perf_counter() - t0
-    mcmc = dict(chains=nvec, steps=n_mc, ms_per_step=round(t_mc / n_mc * 1e3, 4),
-                mpix_per_s=round(npix * n_mc / t_mc / 1e6, 1),
-                accept_rate=round(float(acc_mc.double().mean().item()) / n_mc, 4),
+    t = time.perf_counter() - t0
+    return dict(chains=nvec, steps=n_mc, ms_per_step=round(t / n_mc * 1e3, 4), mpix_per_s=round(npix * n_mc / t / 1e6, 1),
+                accept_rate=round(float(acc.double().mean().item()) / n_mc, 4),
                 proposal="theta' = theta + (1e-4 |theta_true| + 1e-6) z, flat prior on the fit bounds")
-    from paper_1101_2254_amd import _lib
-    _lib.gf_profile_start(ctx.ptr)
-    ops.likelihood(ctx, batch, psf, thetas[0], data, weight, 5, work=work, out=out)
+
+
+def run_single(torch, ops, synth, st, ncomp, noise, K_, W, peaks, workload, label):
+    """One-image fits (C1, C2): K_ whole fits from the seeded start, timed
+    back to back; the result records stay on the device until the end."""
+    dev = torch.device("cuda", 0)
+    ctx = ops.Context(0)
+    batch = ops.Batch(ctx, [st.H], [st.W], [st.K], [ncomp])
+    taps = torch.from_numpy(st.psf.astype(np.float32).ravel()).to(dev)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
+    data, weight = render_observation(torch, ops, ctx, batch, psf, [st], lambda i, s: s.noise_seed, noise)
+    lo, hi = synth.bounds(ncomp, st.H, st.W)
+    lo_t, hi_t = torch.from_numpy(lo).to(dev), torch.from_numpy(hi).to(dev)
+    theta0 = torch.from_numpy(st.start).to(dev)
+
+    def step(**kw):
+        o = dict(ftol=1e-5, max_iter=100)
+        o.update(kw)
+        return ops.fit_lm(ctx, batch, psf, data, weight, theta0, lo=lo_t, hi=hi_t, **o)
+
+    for _ in range(W):
+        step()
     torch.cuda.synchronize()
-    _lib.gf_profile_stop(ctx.ptr)
-    prof = _lib.gf_profile_read(ctx.ptr)
-    # steps 2 and 3 also as the separate entry points (gf_convolve_psf, then
-    # gf_chi2 on its output), each timed by the library's per-kernel events
-    mp = ops.eval_model(ctx, batch, thetas[0], 5)
-    mc = ops.convolve_psf(ctx, batch, psf, mp)
-    ops.chi2(ctx, batch, mc, thetas[0], data, weight)
+    t0 = time.perf_counter()
+    recs = [step(return_device=True)[1] for _ in range(K_)]
     torch.cuda.synchronize()
-    _lib.gf_profile_start(ctx.ptr)
-    for _ in range(5):
-        ops.convolve_psf(ctx, batch, psf, mp, out=mc)
-        ops.chi2(ctx, batch, mc, thetas[0], data, weight)
-    torch.cuda.synchronize()
-    _lib.gf_profile_stop(ctx.ptr)
-    sep_prof = _lib.gf_profile_read(ctx.ptr)
-    del mp, mc
-    geo = dict(npix=npix, npad=288 * 288 * nvec, Mw=288, H=256 * nvec, nch=1, ncomp=1, S=5, L=psf.fft_side[0],
-               nimg=256 * 256, separate=sep_prof)
-    result = dict(
-        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
-        value=round(npix / (ms * 1e-3) / 1e6, 3), unit="Mpix/s", ms_per_step=round(ms, 4),
-        config=dict(workload="C4: likelihood batch, 1024 parameter vectors x one 256x256 image, 33x33 Moffat PSF, "
-                             "288-point FFT, 5x5 oversampling; one step = steps 1-3 for all vectors",
-                    image=[256, 256], psf=33, fft_side=psf.fft_side[0], vectors=nvec, oversample=5),
-        mcmc=mcmc,
-    )
-    result.update(steps=K, warmup=W)
-    return result, prof, geo, dict(base=base, thetas_host=synth.c4_vectors(W, nvec), npix=npix)
+    ms = (time.perf_counter() - t0) / K_ * 1e3
+    infos = [ops.lm_info(r) for r in recs]
+    info = infos[-1]
+    if any(int(i["nfev"][0]) != int(info["nfev"][0]) for i in infos):
+        raise RuntimeError("fits of the same input took different paths")
+    prof, _ = profile(ctx, lambda: step(use_graph=0))
+    n_model, n_jac = passes(prof)
+    npix = st.H * st.W
+    nch = 7 * ncomp
+    table, stage, sizes = kernel_table([(st.H, st.W, st.K)], psf.uses_fft, psf.fft_side, nch, ncomp, 5)
+    rl, kern = roofline(prof, table, peaks)
+    rl["traffic"] = measured_traffic(workload, rl)
+    res = dict(
+        value=round(1e3 / ms, 3), unit="fits/s", ms_per_step=round(ms, 4), steps=K_, warmup=W,
+        mpix_per_s=round((n_model + n_jac) * npix / (ms * 1e-3) / 1e6, 3),
+        lm=dict(iters=int(info["iters"][0]), nfev=int(info["nfev"][0]), njev=int(info["njev"][0]),
+                status=int(info["status"][0]), reason=int(info["reason"][0]), chi2=float(info["chi2"][0]),
+                model_passes=n_model, jacobian_passes=n_jac),
+        config=dict(workload=label, image=[st.H, st.W], psf=st.K, fft_side=int(psf.fft_side[0]),
+                    fft_form=int(psf.uses_fft[0]), params=7 * ncomp + 1, oversample=5),
+        roofline=rl, stages=kern, stage_roofline=stage_fractions(prof, stage),
+        counting="mpix_per_s = (model passes + Jacobian passes the fit ran) x stamp pixels / time per fit")
+    return res
+
+
+def run_c2(args, torch, ops, synth, peaks, steps=None, warmup=None):
+    st = synth.c2()
+    noise = lambda m, s, seed: synth.add_poisson_read_noise(m, s.meta["read_noise"], s.meta["gain"], seed)
+    res = run_single(torch, ops, synth, st, 2, noise, steps if steps is not None else 100,
+                     warmup if warmup is not None else 5, peaks, "c2",
+                     "C2: one 512x512 image, Sersic bulge + exponential disk, 65x65 Moffat PSF (beta=3, FWHM=3 px), "
+                     "576-point FFT convolution, 5x5 oversampling, 15-parameter LM fit to chi2 rel tol 1e-5; "
+                     "one step = one whole fit")
+    return res, dict(st=st, nfev=res["lm"]["nfev"], njev=res["lm"]["njev"], iters=res["lm"]["iters"])
+
+
+def run_c1(args, torch, ops, synth, peaks, steps=None, warmup=None):
+    st = synth.c1()
+    noise = lambda m, s, seed: synth.add_gaussian_noise(m, s.noise_sigma, seed)
+    res = run_single(torch, ops, synth, st, 1, noise, steps if steps is not None else 200,
+                     warmup if warmup is not None else 5, peaks, "c1",
+                     "C1: one 64x64 stamp, one Sersic component (n=2.5, Re=8), 15x15 Gaussian PSF, noise 0.02, "
+                     "8-parameter LM fit from a +-20% start to chi2 rel tol 1e-5; one step = one whole fit")
+    res["roofline"] = dict(res["roofline"], note="latency-bound single small stamp: reported for completeness")
+    return res, dict(st=st)
 
 
 # Proposal network work per stamp (multiply-adds of the four 3x3 stride-2
@@ -338,10 +509,9 @@ def run_c4(args, torch, ops, synth):
 # FLOPs; a training step costs about three forward passes.
 CNN_MAC_PER_STAMP = (64 * 64 * 32 * 9 * 1 + 32 * 32 * 32 * 9 * 32 + 16 * 16 * 64 * 9 * 32 + 8 * 8 * 64 * 9 * 64
                      + 4096 * 256 + 256 * 8)
-BF16_PEAK_TFLOPS = 2500.0
 
 
-def run_c5(args, torch, ops, synth):
+def run_c5(args, torch, ops, synth, peaks, steps=None, warmup=None):
     """Learned proposal: train on stamps rendered on the device, then fit 4096
     fresh 128x128 stamps by LM from the network's proposals and from the
     image-moment default guess.  One step = proposal + LM for the batch."""
@@ -381,8 +551,8 @@ def run_c5(args, torch, ops, synth):
     def step_default():
         return fit(PR.moments_guess(ctx, ev.batch, data))
 
-    K_ = args.steps if args.steps is not None else 5
-    W = args.warmup if args.warmup is not None else 1
+    K_ = steps if steps is not None else 5
+    W = warmup if warmup is not None else 1
     times = {}
     infos = {}
     for name, fn in (("default", step_default), ("cnn", step_cnn)):
@@ -404,18 +574,12 @@ def run_c5(args, torch, ops, synth):
     torch.cuda.synchronize()
     _lib.gf_profile_stop(ctx.ptr)
     tprof = _lib.gf_profile_read(ctx.ptr)
-    _lib.gf_profile_start(ctx.ptr)
-    step_cnn(use_graph=0)
-    torch.cuda.synchronize()
-    _lib.gf_profile_stop(ctx.ptr)
-    prof = _lib.gf_profile_read(ctx.ptr)
     ic, idf = infos["cnn"], infos["default"]
     rel = (ic["chi2"] - idf["chi2"]) / idf["chi2"]
     gemm_ms = tprof.get("k_gemm_bf16", (0, 0.0))[1]
     step_ms = sum(v[1] for v in tprof.values())
     train_flop = 3 * 2 * CNN_MAC_PER_STAMP * 256
     result = dict(
-        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
         value=round(nev / times["cnn"], 2), unit="fits/s", ms_per_step=round(times["cnn"] * 1e3, 3),
         fits_per_s=round(nev / times["cnn"], 2),
         lm=dict(iters_mean=float(ic["iters"].mean()), converged=float((ic["status"] == 0).mean())),
@@ -438,11 +602,14 @@ def run_c5(args, torch, ops, synth):
                              "PSF 15..33 px, noise 0.02); one step = network proposal + one gf_fit_lm call to chi2 "
                              "rel tol 1e-5", stamps=nev, side=side, oversample=5),
     )
-    npix = nev * side * side
-    fb = {"k_fft_rows": [0, 0], "k_fft_cols": [0, 0], "k_fft_irows": [0, 0]}
-    geo = dict(npix=npix, npad=npix, Mw=1, H=1, nch=7, ncomp=1, S=5, L=2, fft_bytes=fb)
-    result.update(steps=K_, warmup=W)
-    return result, prof, geo, dict(info=ic, nfev=int(ic["nfev"].sum()), njev=int(ic["njev"].sum()))
+    # roofline of the first LM iteration of the network-seeded fit (every
+    # stamp active)
+    prof1, _ = profile(ctx, lambda: fit(net.predict(data).reshape(-1).contiguous(), use_graph=0, max_iter=1))
+    table, stage, _ = kernel_table([(side, side, int(k)) for k in ev.batch.K], ev.psf.uses_fft, ev.psf.fft_side, 7, 1, 5)
+    rl, kern = roofline(prof1, table, peaks)
+    result.update(steps=K_, warmup=W, roofline=rl, stages=kern, stage_roofline=stage_fractions(prof1, stage),
+                  roofline_profile="first LM iteration of the network-seeded fit, kernel by kernel")
+    return result, dict(info=ic, nfev=int(ic["nfev"].sum()), njev=int(ic["njev"].sum()))
 
 
 # Algorithmic FP32 operations of one line fit, counting an FMA as two and an
@@ -458,7 +625,7 @@ def line_fit_flops(N, K, nl, S, nfev, njev):
     return nfev * model + njev * jac
 
 
-def run_lines(args, torch, ops, synth):
+def run_lines(args, torch, ops, synth, peaks, steps=None, warmup=None):
     dev = torch.device("cuda", 0)
     n = 65536
     spectra = synth.line_batch(n)
@@ -479,8 +646,8 @@ def run_lines(args, torch, ops, synth):
         return ops.line_fit_lm(ctx, lb, lsf, data, weight, start, lo=lo, hi=hi, ftol=1e-5, max_iter=100,
                                return_device=True)
 
-    K = args.steps if args.steps is not None else 20
-    W = args.warmup if args.warmup is not None else 3
+    K = steps if steps is not None else 20
+    W = warmup if warmup is not None else 3
     for _ in range(W):
         step()
     torch.cuda.synchronize()
@@ -502,7 +669,6 @@ def run_lines(args, torch, ops, synth):
     chan_evals = sum(s.N * (int(info["nfev"][i]) + int(info["njev"][i])) for i, s in enumerate(spectra))
     nch = sum(s.N for s in spectra)
     result = dict(
-        metric="model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5",
         value=round(n / (ms * 1e-3), 2), unit="fits/s", ms_per_step=round(ms, 4),
         mpix_per_s=round(chan_evals / (ms * 1e-3) / 1e6, 2),
         lm=dict(iters_mean=float(info["iters"].mean()), iters_max=int(info["iters"].max()),
@@ -512,9 +678,9 @@ def run_lines(args, torch, ops, synth):
                              "continuum, 7..21-tap Gaussian LSF, 5x sub-sampling, one gf_line_fit_lm call to chi2 "
                              "rel tol 1e-5; one step = the whole batch",
                     spectra=n, channels=nch, oversample=S))
-    geo = dict(npix=nch, npad=nch, Mw=1, H=1, nch=1, ncomp=1, S=S, L=2, line_flops=flops)
-    result.update(steps=K, warmup=W)
-    return result, prof, geo, dict(spectra=spectra, info=info, data=d, weight=w)
+    rl, kern = roofline(prof, {"k_line_lm": ("alu", flops)}, peaks)
+    result.update(steps=K, warmup=W, roofline=rl, stages=kern)
+    return result, dict(spectra=spectra, info=info, data=d, weight=w)
 
 
 def cpu_baseline_lines(extra, seconds):
@@ -538,198 +704,145 @@ def cpu_baseline_lines(extra, seconds):
                        f"{t:.1f} s on one thread")
 
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by the copy calibration: fetch x2, write x1), as
-# summarised in profiles/*_hbm_traffic.md: bytes = once + per_channel x
-# channels per launch.  Valid only while the kernel source is the one the
-# counters were taken on (first 16 hex digits of its SHA-256).
-TRAFFIC = {
-    "c2": {
-        "k_eval_jac": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="524bd17134a451f8", once=1.8800e+07,
-                           per_channel=0.0),
-        "k_fft_cols": dict(source="paper_1101_2254_amd/csrc/k_fft.hip", sha16="e5ad3e6d0c9bfbf0", once=1.5038e+06,
-                           per_channel=2.8225e+06),
-        "summary": "profiles/c2_fit_hbm_traffic.md"},
-    "c4": {
-        "k_eval": dict(source="paper_1101_2254_amd/csrc/k_eval.hip", sha16="524bd17134a451f8", once=3.8624e+08,
-                       per_channel=0.0),
-        "summary": "profiles/c4_likelihood_hbm_traffic.md"},
-}
 
 
-def stage_roofline(prof, geo):
-    """Steps 2 and 3 of the likelihood batch as one fused stage (the chi^2
-    is reduced in the inverse-row FFT pass, so the convolved model never
-    reaches HBM), with the algorithmic bytes of its definition: read the
-    padded model, data and weight once per distinct image, the OTF once.
-    The FFT's own spectra traffic is not counted here (it is in the
-    per-kernel figures of `stages`)."""
-    out = {}
-    L = geo.get("L", 0)
-    ks = ("k_fft_rows", "k_fft_cols", "k_fft_irows_chi2")
-    if L > 2 and all(k in prof for k in ks):
-        n = prof["k_fft_rows"][0]
-        t = sum(prof[k][1] / prof[k][0] for k in ks) * 1e-3
-        b = 4 * geo["npad"] + 8 * geo.get("nimg", geo["npix"]) + L * (L // 2 + 1) * 8
-        out["convolution_chi2"] = dict(kernels=list(ks), launches=n, bytes_per_launch=int(b),
-                                       us_per_launch=round(t * 1e6, 2), gbs=round(b / t / 1e9, 1),
-                                       frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
-    sep = geo.get("separate")
-    if sep:
-        # the separate entry points: convolution = padded model read + stamp
-        # written + OTF once; chi^2 = model read + data and weight once
-        ks = ("k_fft_rows", "k_fft_cols", "k_fft_irows")
-        if all(k in sep for k in ks):
-            n = sep["k_fft_rows"][0]
-            t = sum(sep[k][1] / sep[k][0] for k in ks) * 1e-3
-            b = 4 * geo["npad"] + 4 * geo["npix"] + L * (L // 2 + 1) * 8
-            out["convolution"] = dict(kernels=list(ks), launches=n, bytes_per_launch=int(b),
-                                      us_per_launch=round(t * 1e6, 2), gbs=round(b / t / 1e9, 1),
-                                      frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
-        # (large batches reduce each stamp in one launch: no k_pair_final)
-        ks = tuple(k for k in ("k_chi2", "k_pair_final") if k in sep)
-        if "k_chi2" in sep:
-            n = sep["k_chi2"][0]
-            t = sum(sep[k][1] / sep[k][0] for k in ks) * 1e-3
-            b = 4 * geo["npix"] + 8 * geo.get("nimg", geo["npix"])
-            out["chi2"] = dict(kernels=list(ks), launches=n, bytes_per_launch=int(b), us_per_launch=round(t * 1e6, 2),
-                               gbs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / HBM_PEAK_GBS, 4))
-    return out
-
-
-def measured_traffic(workload, rl, geo):
-    import hashlib
-    t = TRAFFIC.get(workload, {}).get(rl.get("kernel"))
-    if not t:
-        return None
+# --------------------------------------------------------------- CPU baselines
+def cpu_model():
     try:
-        with open(os.path.join(ROOT, t["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha16"]:
-                return None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
     except OSError:
-        return None
-    return round(t["once"] + t["per_channel"] * geo.get("chan_" + rl["kernel"], 1), 0)
+        pass
+    return "unknown"
 
 
-def roofline(prof, geo):
-    total = sum(v[1] for v in prof.values())
-    name = max(prof, key=lambda k: prof[k][1])
-    launches, tot_ms = prof[name]
-    bound, units, what = kernel_work(name, geo, launches)
-    avg_s = tot_ms / launches * 1e-3
-    stages = {}
-    for k, (n, t) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
-        b, u, wu = kernel_work(k, geo, n)
-        e = dict(launches=n, ms_total=round(t, 4), share=round(t / total, 4))
-        if b == "hbm":
-            e.update(bound="hbm", gbs=round(u / (t / n * 1e-3) / 1e9, 1), frac=round(u / (t / n * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
-        elif b == "alu":
-            e.update(bound="alu", tflops=round(u / (t / n * 1e-3) / 1e12, 2),
-                     frac=round(u / (t / n * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4))
-        stages[k] = e
-    if bound == "hbm":
-        ach = units / avg_s / 1e9
-        rl = dict(bound="hbm", kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                  frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
-    else:
-        ach = units / avg_s / 1e12
-        rl = dict(bound="alu", kernel=name, achieved=round(ach, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                  frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
-    rl["avg_launch_us"] = round(avg_s * 1e6, 2)
-    return rl, stages
-
-
-def cpu_baseline_c2(extra, seconds):
-    """The oracle on its own rendering of the same observation (FP64 model at
-    the FP32 truth, the same seeded noise): the first LM iterations of the fit."""
+def oracle_native():
+    """The oracle rebuilt for this host (-O3 -march=native, same rounding)."""
     from oracle import gfo
+    gfo.use_native(os.path.join(ROOT, "gpurun_out", "oracle_native"))
+    return gfo
+
+
+def _threads(gfo, n):
+    gfo.set_threads(n)
+    return gfo.get_threads()
+
+
+def cpu_baseline_c3(extra, seconds):
+    """Stratified sample: one stamp per size class, the oracle's whole LM fit
+    (ftol 1e-5) on its own rendering of that stamp on all host cores; one
+    iteration per size on one thread, times the all-core fit's iterations.
+    Both extrapolated to the batch's stamps per size (labelled so)."""
     import synth
-    st = extra["st"]
-    threads = os.cpu_count() or 1
-    gfo.set_threads(threads)
-    lo, hi = synth.bounds(2, st.H, st.W)
-    psf = st.psf.astype(np.float32).astype(np.float64)
-    m_true = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf, 5)
-    d, w = synth.add_poisson_read_noise(m_true, st.meta["read_noise"], st.meta["gain"], st.noise_seed)
-    d = d.astype(np.float32).astype(np.float64)
-    w = w.astype(np.float32).astype(np.float64)
-    t0 = time.perf_counter()
-    iters = evals = 0
-    n_it = 1
-    while True:
-        _, info = gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=n_it)
-        evals += info["nfev"] + info["njev"]
-        iters += info["iters"]
-        if time.perf_counter() - t0 >= seconds or n_it >= 8:
-            break
-        n_it += 1
-    t = time.perf_counter() - t0
-    mpix = evals * extra["npix"] / t / 1e6
-    return dict(value=round(mpix, 5), unit="Mpix/s", cores=gfo.get_threads(), kind="oracle",
-                sample=f"FP64 oracle LM on its own rendering of the same 512x512 observation: {iters} iterations "
-                       f"in runs of 1..{n_it} iterations ({evals} model + Jacobian evaluations, direct "
-                       f"convolution), {t:.1f} s on {gfo.get_threads()} threads",
-                fits_per_s_est=round(1.0 / (t / evals * (extra["nfev"] + extra["njev"])), 6))
+    gfo = oracle_native()
+    stamps = extra["stamps"]
+    ncores = os.cpu_count() or 1
+    per_size = {}
+    for N in synth.C3_SIZES:
+        idx = [i for i, st in enumerate(stamps) if st.H == N]
+        if idx:
+            per_size[N] = (stamps[idx[0]], len(idx))
+    tot_all = tot_one = 0.0
+    used = []
+    for N, (st, count) in per_size.items():
+        psf = st.psf.astype(np.float32).astype(np.float64)
+        m = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf, 5)
+        d, w = synth.add_gaussian_noise(m, st.noise_sigma, st.noise_seed)
+        d, w = d.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64)
+        lo, hi = synth.bounds(1, st.H, st.W)
+        _threads(gfo, ncores)
+        t0 = time.perf_counter()
+        _, info = gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=100)
+        t_fit = time.perf_counter() - t0
+        _threads(gfo, 1)
+        t0 = time.perf_counter()
+        gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=1)
+        t_it = time.perf_counter() - t0
+        tot_all += t_fit * count
+        tot_one += t_it * max(info["iters"], 1) * count
+        used.append(f"{N}px:{info['iters']}it,{t_fit * 1e3:.0f}ms/{ncores}t,{t_it * 1e3:.0f}ms/it/1t")
+    n = len(stamps)
+    return dict(value=round(n / tot_all, 3), unit="fits/s", cores=ncores, kind="oracle",
+                value_1thread=round(n / tot_one, 4), cores_1thread=1, cpu=cpu_model(), build="gcc -O3 -march=native",
+                sample="extrapolated: per stamp size one whole oracle LM fit to ftol 1e-5 on its own rendering "
+                       f"(all {ncores} cores) and one iteration on one thread times that fit's iterations, scaled "
+                       "by the batch's stamps per size (" + "; ".join(used) + ")")
 
 
 def cpu_baseline_c4(extra, seconds):
-    """The oracle on its own rendering of the same image: steps 1-3 for as many
-    of the step's parameter vectors as fit in the time budget."""
-    from oracle import gfo
+    """The oracle on its own rendering of the same image: steps 1-3 for as
+    many of a step's parameter vectors as fit in the time budget, on all
+    cores and on one thread."""
     import synth
-    threads = os.cpu_count() or 1
-    gfo.set_threads(threads)
+    gfo = oracle_native()
     base = extra["base"]
     psf = base.psf.astype(np.float32).astype(np.float64)
     m_true = gfo.model(256, 256, base.truth.astype(np.float32).astype(np.float64), psf, 5)
     d, w = synth.add_gaussian_noise(m_true, base.noise_sigma, base.noise_seed)
-    d = d.astype(np.float32).astype(np.float64)
-    w = w.astype(np.float32).astype(np.float64)
+    d, w = d.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64)
     th = extra["thetas_host"].astype(np.float32).astype(np.float64)
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < seconds and n < th.shape[0]:
-        gfo.chi2(d, w, gfo.model(256, 256, th[n], psf, 5))
-        n += 1
-    t = time.perf_counter() - t0
-    return dict(value=round(n * 256 * 256 / t / 1e6, 5), unit="Mpix/s", cores=gfo.get_threads(), kind="oracle",
-                sample=f"FP64 oracle eval + direct convolution + chi2 of {n} of the step's parameter vectors on "
-                       f"its own rendering of the image, {t:.1f} s on {gfo.get_threads()} threads")
-
-
-def cpu_baseline_c3(extra, seconds):
-    """Stratified sample: per stamp size, the oracle's first LM iteration on its
-    own rendering of one stamp of that size, scaled by the GPU run's mean
-    iteration count for that size (extrapolated)."""
-    from oracle import gfo
-    import synth
-    gfo.set_threads(os.cpu_count() or 1)
-    stamps, info = extra["stamps"], extra["info"]
-    total = 0.0
-    used = []
-    t_all = time.perf_counter()
-    for N in synth.C3_SIZES:
-        idx = [i for i, st in enumerate(stamps) if st.H == N]
-        if not idx:
-            continue
-        st = stamps[idx[0]]
-        psf = st.psf.astype(np.float32).astype(np.float64)
-        m = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf, 5)
-        d, w = synth.add_gaussian_noise(m, st.noise_sigma, st.noise_seed)
-        lo, hi = synth.bounds(1, st.H, st.W)
+    out = {}
+    for label, nt, budget in (("all", os.cpu_count() or 1, seconds / 2), ("one", 1, seconds / 2)):
+        _threads(gfo, nt)
         t0 = time.perf_counter()
-        gfo.fit_lm(st.start, psf, d.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64),
-                   5, lo=lo, hi=hi, ftol=1e-5, max_iter=1)
-        t1 = time.perf_counter() - t0
-        iters = float(np.mean(info["iters"][idx]))
-        total += t1 * iters * len(idx)
-        used.append(f"{N}:{t1 * 1e3:.0f}ms")
-        if time.perf_counter() - t_all > seconds * 4:
-            break
-    return dict(value=round(len(stamps) / total, 4), unit="fits/s", cores=gfo.get_threads(), kind="oracle",
-                sample="extrapolated: one oracle LM iteration (start evaluation + Jacobian + step) per stamp size "
-                       "on its own rendering, times the GPU run's mean iterations per size and the stamps per size ("
-                       + ", ".join(used) + ")")
+        n = 0
+        while (time.perf_counter() - t0 < budget or n == 0) and n < th.shape[0]:
+            gfo.chi2(d, w, gfo.model(256, 256, th[n], psf, 5))
+            n += 1
+        out[label] = (n, time.perf_counter() - t0, gfo.get_threads())
+    n, t, c = out["all"]
+    n1, t1, _ = out["one"]
+    return dict(value=round(n * 65536 / t / 1e6, 5), unit="Mpix/s", cores=c, kind="oracle",
+                value_1thread=round(n1 * 65536 / t1 / 1e6, 6), cores_1thread=1, cpu=cpu_model(),
+                build="gcc -O3 -march=native",
+                sample=f"FP64 oracle eval + direct convolution + chi2 of {n} (all cores, {t:.1f} s) and {n1} (one "
+                       f"thread, {t1:.1f} s) of a step's parameter vectors on its own rendering of the image")
+
+
+def cpu_baseline_single(extra, seconds, ncomp, label, whole_fits):
+    """C1 and C2: whole oracle fits (C1) or the first LM iterations (C2, one
+    fit takes minutes) on its own rendering of the same observation."""
+    import synth
+    gfo = oracle_native()
+    st = extra["st"]
+    psf = st.psf.astype(np.float32).astype(np.float64)
+    m = gfo.model(st.H, st.W, st.truth.astype(np.float32).astype(np.float64), psf, 5)
+    if ncomp == 2:
+        d, w = synth.add_poisson_read_noise(m, st.meta["read_noise"], st.meta["gain"], st.noise_seed)
+    else:
+        d, w = synth.add_gaussian_noise(m, st.noise_sigma, st.noise_seed)
+    d, w = d.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64)
+    lo, hi = synth.bounds(ncomp, st.H, st.W)
+    out = {}
+    for lab, nt in (("all", os.cpu_count() or 1), ("one", 1)):
+        _threads(gfo, nt)
+        if whole_fits:
+            t0 = time.perf_counter()
+            _, info = gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=100)
+            out[lab] = (time.perf_counter() - t0, info["iters"], "whole fit")
+        else:
+            t0 = time.perf_counter()
+            _, info = gfo.fit_lm(st.start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-5, max_iter=1)
+            t_it = time.perf_counter() - t0
+            out[lab] = (t_it * extra["iters"], extra["iters"], "one iteration x the GPU fit's iterations")
+    (t, it, how), (t1, _, _) = out["all"], out["one"]
+    return dict(value=round(1.0 / t, 5), unit="fits/s", ms_per_fit=round(t * 1e3, 2), cores=os.cpu_count() or 1,
+                kind="oracle", value_1thread=round(1.0 / t1, 6), ms_per_fit_1thread=round(t1 * 1e3, 2),
+                cores_1thread=1, cpu=cpu_model(), build="gcc -O3 -march=native",
+                sample=f"{label}: FP64 oracle LM ({how}; {it} iterations) on its own rendering of the same "
+                       "observation, direct convolution")
+
+
+def calibrate_peaks(ctx):
+    from paper_1101_2254_amd import _lib
+    ctx.bind_stream()
+    out = dict(triad_gbs=round(_lib.gf_probe(ctx.ptr, 0, 1 << 28, 10), 1),
+               fma_tflops=round(_lib.gf_probe(ctx.ptr, 1, 4096, 5), 2),
+               transcendental_gops=round(_lib.gf_probe(ctx.ptr, 2, 2048, 5), 1))
+    out["triad_frac_of_8tbs"] = round(out["triad_gbs"] / HBM_PEAK_GBS, 4)
+    return out
 
 
 def cpu_baseline_c5(extra, seconds):
@@ -761,6 +874,27 @@ def cpu_baseline_c5(extra, seconds):
                        f"(mean {per_iter * 1e3:.0f} ms) x mean GPU iterations x 4096 stamps")
 
 
+
+RUNNERS = dict(c1=run_c1, c2=run_c2, c3=run_c3, c4=run_c4, c5=run_c5, lines=run_lines)
+DATA = dict(c5="synthetic (seeded; stamps rendered by the library from on-device Philox4x64-10 prior draws and "
+                "noise)",
+            lines="synthetic (seeded; spectra rendered by the library, noise from numpy PCG64)")
+
+
+def cpu_for(name, extra, seconds):
+    if name == "c3":
+        return cpu_baseline_c3(extra, seconds)
+    if name == "c4":
+        return cpu_baseline_c4(extra, seconds)
+    if name == "c2":
+        return cpu_baseline_single(extra, seconds, 2, "C2", False)
+    if name == "c1":
+        return cpu_baseline_single(extra, seconds, 1, "C1", True)
+    if name == "c5":
+        return cpu_baseline_c5(extra, seconds)
+    return cpu_baseline_lines(extra, seconds)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -783,84 +917,40 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=src.numel() * 4, copies=3)))
         return
+    pctx = ops.Context(0)
+    peaks = calibrate_peaks(pctx)
+    pctx.close()
     if args.calibrate_peaks:
-        from paper_1101_2254_amd import _lib
-        ctx = ops.Context(0)
-        ctx.bind_stream()
-        out = dict(triad_gbs=_lib.gf_probe(ctx.ptr, 0, 1 << 28, 10), fma_tflops=_lib.gf_probe(ctx.ptr, 1, 4096, 5),
-                   transcendental_gops=_lib.gf_probe(ctx.ptr, 2, 2048, 5))
-        out["triad_frac_of_8tbs"] = round(out["triad_gbs"] / HBM_PEAK_GBS, 4)
-        print(json.dumps(out))
+        print(json.dumps(peaks))
         return
-    print(f"bench: workload {args.workload}", file=sys.stderr, flush=True)
-    if args.workload == "c2":
-        result, prof, geo, extra = run_c2(args, torch, ops, synth)
-    elif args.workload == "c3":
-        result, prof, geo, extra = run_c3(args, torch, ops, synth)
-    elif args.workload == "c5":
-        result, prof, geo, extra = run_c5(args, torch, ops, synth)
-    elif args.workload == "lines":
-        result, prof, geo, extra = run_lines(args, torch, ops, synth)
-    else:
-        result, prof, geo, extra = run_c4(args, torch, ops, synth)
-    geo["chan_k_fft_rows"] = geo["chan_k_fft_cols"] = geo["chan_k_fft_irows"] = geo["chan_k_fft_irows_chi2"] = 1
-    if args.workload in ("c2", "c3", "c5"):
-        # per fit the row and column passes run 7 n_comp channels (Jacobian)
-        # and 1 channel (trial) per launch: use the average over the launches
-        # of the profiled fit; the plain inverse-row pass runs only for the
-        # Jacobian, the fused one only for the trial points (a speculative
-        # fit has no one-channel launches)
-        n_jac = prof.get("k_eval_jac", (0, 0.0))[0]
-        n_trial = prof.get("k_fft_irows_chi2", (0, 0.0))[0]
-        nch = 14 if args.workload == "c2" else 7
-        avg = (nch * n_jac + 1 * n_trial) / max(n_jac + n_trial, 1)
-        for k in ("rows", "cols"):
-            geo["chan_k_fft_" + k] = avg
-        geo["chan_k_fft_irows"] = nch
-    rl, stages = roofline(prof, geo)
-    rl["traffic"] = measured_traffic(args.workload, rl, geo)
-    stage_rl = stage_roofline(prof, geo) if args.workload == "c4" else {}
-    if rl["traffic"] is not None:
-        rl["traffic_source"] = TRAFFIC[args.workload]["summary"]
-    if args.workload in ("c3", "c5"):
-        # finished stamps skip their work units, so per-launch bytes of the
-        # whole batch overstate what a launch moves: report times only
-        for k in stages:
-            for f in ("bound", "gbs", "tflops", "frac"):
-                stages[k].pop(f, None)
-        rl = dict(bound=None, kernel=rl["kernel"], achieved=None, peak=None, unit=None, frac=None, traffic=None,
-                  avg_launch_us=rl["avg_launch_us"],
-                  note="per-launch work varies as stamps finish; see the C2 and C4 workloads for rooflines")
-    print(f"bench: {result['value']} {result['unit']}, {result['ms_per_step']} ms/step", file=sys.stderr,
-          flush=True)
+    head = "c3" if args.workload == "suite" else args.workload
+    log(f"workload {head}")
+    res, extra = RUNNERS[head](args, torch, ops, synth, peaks, args.steps, args.warmup)
+    log(f"{head}: {res['value']} {res['unit']}, {res['ms_per_step']} ms/step")
     if args.breakdown:
-        print(json.dumps(stages, indent=1), file=sys.stderr)
-    out = dict(metric=result["metric"], value=result["value"], unit=result["unit"], n_gpus=1,
-               steps=result.pop("steps"), warmup=result.pop("warmup"), ms_per_step=result["ms_per_step"],
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
-               data=("synthetic (seeded; stamps rendered by the library from on-device Philox4x64-10 prior draws and "
-                     "noise)" if args.workload == "c5" else
-                     "synthetic (seeded; spectra rendered by the library, noise from numpy PCG64)"
-                     if args.workload == "lines" else
-                     "synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)"),
-               config=result["config"], roofline=rl)
-    for k in ("fits_per_s", "lm", "mpix_per_s", "c5", "mcmc"):
-        if k in result:
-            out[k] = result[k]
-    out["stages"] = stages
-    if stage_rl:
-        out["stage_roofline"] = stage_rl
+        print(json.dumps(res.get("stages", {}), indent=1), file=sys.stderr)
+    if res.get("roofline") and res["roofline"].get("traffic") is None:
+        res["roofline"]["traffic"] = measured_traffic(head, res["roofline"])
+    out = dict(metric=METRIC, value=res.pop("value"), unit=res.pop("unit"), n_gpus=1, steps=res.pop("steps"),
+               warmup=res.pop("warmup"), ms_per_step=res.pop("ms_per_step"), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32",
+               data=DATA.get(head, "synthetic (seeded; Sersic stamps rendered by the library, noise from numpy PCG64)"),
+               config=res.pop("config"), roofline=res.pop("roofline", None))
+    out.update(res)
+    nested = {}
+    if args.workload == "suite":
+        for name in ("c4", "c2", "c1"):
+            log(f"workload {name}")
+            r, e = RUNNERS[name](args, torch, ops, synth, peaks)
+            log(f"{name}: {r['value']} {r['unit']}, {r['ms_per_step']} ms/step")
+            nested[name] = (r, e)
+            out[name] = r
+    out["peaks_measured"] = peaks
     if not args.no_cpu:
-        if args.workload == "c2":
-            out["cpu_baseline"] = cpu_baseline_c2(extra, args.cpu_seconds)
-        elif args.workload == "c3":
-            out["cpu_baseline"] = cpu_baseline_c3(extra, args.cpu_seconds)
-        elif args.workload == "c5":
-            out["cpu_baseline"] = cpu_baseline_c5(extra, args.cpu_seconds)
-        elif args.workload == "lines":
-            out["cpu_baseline"] = cpu_baseline_lines(extra, args.cpu_seconds)
-        else:
-            out["cpu_baseline"] = cpu_baseline_c4(extra, args.cpu_seconds)
+        log("CPU baseline (oracle)")
+        out["cpu_baseline"] = cpu_for(head, extra, args.cpu_seconds)
+        for name, (r, e) in nested.items():
+            r["cpu_baseline"] = cpu_for(name, e, args.cpu_seconds / 2)
     print(json.dumps(out))
 
 

@@ -92,6 +92,27 @@ typedef enum {
  * host, FP32 on the device).  *ctx is set to NULL on failure. */
 gf_status gf_create(gf_ctx **ctx, int device);
 void gf_destroy(gf_ctx *ctx);
+/* Tuning table of the context, read by gf_psf_prepare(GF_CONV_AUTO) and
+ * gf_fit_lm.  For an FFT side L of the one-workgroup form (an even
+ * 2^a 3^b 5^c <= GF_FFT_FUSED_MAX):
+ *   form: the FFT form the automatic choice takes for that side: 1
+ *     multi-pass, 2 one-workgroup, -1 untuned (then one-workgroup up to 160,
+ *     multi-pass above);
+ *   min_active: per group of sides of similar on-chip size (up to 64, 96,
+ *     128, 160 and 192), the fewest still-fitting stamps of that group for
+ *     which gf_fit_lm keeps them on the one-workgroup form; when fewer
+ *     remain (checked when it restricts its launches to the unfinished
+ *     stamps) they move to the multi-pass form for the rest of the fit.
+ *     0 keeps them always.
+ * Both forms give the same convolution to rounding (a fit whose stamps
+ * move may take other last bits).  The getters return 0 (form) or -1
+ * (min_active) for sides that are not one-workgroup sides; the setters
+ * return GF_EINVAL for them. */
+int gf_tune_form_get(const gf_ctx *ctx, int L);
+gf_status gf_tune_form_set(gf_ctx *ctx, int L, int form);
+int gf_tune_min_active_get(const gf_ctx *ctx, int L);
+gf_status gf_tune_min_active_set(gf_ctx *ctx, int L, int n);
+
 /* All later work of this context is enqueued on `hip_stream` (a hipStream_t;
  * NULL = the default stream). */
 gf_status gf_set_stream(gf_ctx *ctx, void *hip_stream);

@@ -41,12 +41,35 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def use_native(build_dir: str) -> str:
+    """Rebuild the oracle for the host it runs on (``-O3 -march=native``, the
+    same ``-ffp-contract=off`` rounding, hence the same results) into
+    ``build_dir`` and load that copy instead.  Used by the CPU-baseline leg of
+    the benchmark only: the tests keep the portable build."""
+    global _lib
+    os.makedirs(build_dir, exist_ok=True)
+    path = os.path.join(build_dir, "libgfo_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", path,
+           "-lm"]
+    subprocess.run(cmd, check=True)
+    _lib = None
+    _load(path)
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
+        _load(_LIB_PATH)
+    return _lib
+
+
+def _load(path):
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(path)
         i, d, vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
         L.gfo_gammp.restype = d
         L.gfo_gammp.argtypes = [d, d]

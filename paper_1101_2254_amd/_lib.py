@@ -33,7 +33,8 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_cnn_get_params", "gf_cnn_forward", "gf_cnn_gradients", "gf_cnn_train_step", "gf_cnn_steps",
            "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_line_batch_create", "gf_line_batch_destroy",
-           "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version")
+           "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version",
+           "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set")
 
 
 class GfLmOpts(ctypes.Structure):
@@ -146,6 +147,10 @@ def lib() -> ctypes.CDLL:
         "gf_line_chi2": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
         "gf_line_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
         "gf_version": (ctypes.c_char_p, []),
+        "gf_tune_form_get": (i32, [vp, i32]),
+        "gf_tune_form_set": (i32, [vp, i32, i32]),
+        "gf_tune_min_active_get": (i32, [vp, i32]),
+        "gf_tune_min_active_set": (i32, [vp, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -335,6 +340,22 @@ def gf_profile_read(ctx) -> dict:
         check(lib().gf_profile_get(ctx, i, buf, 128, ctypes.byref(cnt), ctypes.byref(ms)), ctx)
         out[buf.value.decode()] = (int(cnt.value), float(ms.value))
     return out
+
+
+def gf_tune_form_get(ctx, L: int) -> int:
+    return int(lib().gf_tune_form_get(ctx, L))
+
+
+def gf_tune_form_set(ctx, L: int, form: int) -> None:
+    check(lib().gf_tune_form_set(ctx, L, form), ctx)
+
+
+def gf_tune_min_active_get(ctx, L: int) -> int:
+    return int(lib().gf_tune_min_active_get(ctx, L))
+
+
+def gf_tune_min_active_set(ctx, L: int, n: int) -> None:
+    check(lib().gf_tune_min_active_set(ctx, L, n), ctx)
 
 
 def gf_version() -> str:

@@ -69,6 +69,9 @@ constexpr int f2_threads(int L) {
   const int wg = (160 * 1024) / f2_lds_bytes(L);
   return wg >= 4 ? 256 : wg >= 2 ? 512 : 1024;
 }
+// Largest side of bucket B, whose LDS and thread count its kernel is built for.
+constexpr int f2b_maxL(int B) { return kF2dSides[kF2dBucketEnd[B] - 1]; }
+constexpr int f2b_first(int B) { return B == 0 ? 0 : kF2dBucketEnd[B - 1]; }
 
 // One Stockham pass of radix R over ntr transforms of length L in place.
 // Element n of a row transform t sits at row0 LH + 2 t LH + n (its row
@@ -145,28 +148,17 @@ struct Div16 {
 
 }  // namespace
 
-// One workgroup per (list entry, channel).  Workgroup ids are assigned so
-// that the n_ch channels of a stamp get ids equal mod 8, which places them
-// on one XCD, where they share the L2 copy of their OTF.
-template <int L, int MODE>
-__global__ __launch_bounds__(f2_threads(L)) void k_fft2d(const StampDesc *__restrict__ desc,
-                                                         const PathDesc *__restrict__ path,
-                                                         const float2 *__restrict__ twl, const Work *__restrict__ list,
-                                                         int n_list, const float *__restrict__ in, int n_ch,
-                                                         float *__restrict__ out, const float2 *__restrict__ otf,
-                                                         float2 *__restrict__ otf_out, const int *__restrict__ mask,
-                                                         Chi2Epi ep) {
-  constexpr int LH = L / 2 + 1, NT = f2_threads(L);
-  __shared__ float2 buf[lq_size((L + 1) * LH)];
-  __shared__ float2 tw[L];
-  const int blk = (int)blockIdx.x;
-  const int grp = blk / (8 * n_ch), rem = blk - grp * 8 * n_ch;
-  const int ch = rem >> 3, li = grp * 8 + (rem & 7);
-  if (li >= n_list) return;
-  const int s = list[li].stamp;
-  if (mask && !mask[s]) return;
-  const StampDesc d = desc[s];
-  const PathDesc pd = path[s];
+// The convolution of one (stamp, channel) of side L by a workgroup of NT
+// threads, in the LDS buffers buf (lq_size((L + 1)(L/2 + 1)) values) and tw
+// (L values).
+template <int L, int MODE, int NT>
+__device__ __forceinline__ void f2_body(float2 *__restrict__ buf, float2 *__restrict__ tw, const StampDesc &d,
+                                        const PathDesc &pd, int s, int ch, const float2 *__restrict__ tw_all,
+                                        const float *__restrict__ in, int n_ch, float *__restrict__ out,
+                                        const float2 *__restrict__ otf, float2 *__restrict__ otf_out,
+                                        const Chi2Epi &ep) {
+  constexpr int LH = L / 2 + 1;
+  const float2 *twl = tw_all + pd.tw;
   const int tid = (int)threadIdx.x;
   const int km1 = d.K - 1;
 
@@ -383,53 +375,86 @@ __global__ __launch_bounds__(f2_threads(L)) void k_fft2d(const StampDesc *__rest
   }
 }
 
-// Launch the kernel of side kF2dSides[cls] over n list entries, for the side
-// classes I .. HI - 1 built in the including source.
-template <int MODE, int I, int HI>
-hipError_t f2_launch(int cls, hipStream_t st, int n, int n_ch, const StampDesc *desc, const PathDesc *path,
-                     const float2 *tw, const Work *list, const float *in, float *out, const float2 *otf,
-                     float2 *otf_out, const int *mask, const Chi2Epi &ep) {
+// Dispatch on the stamp's side among the classes I .. HI - 1 of a bucket.
+template <int MODE, int NT, int I, int HI>
+__device__ __forceinline__ void f2_dispatch(int L, float2 *buf, float2 *tw, const StampDesc &d, const PathDesc &pd,
+                                            int s, int ch, const float2 *tw_all, const float *in, int n_ch,
+                                            float *out, const float2 *otf, float2 *otf_out, const Chi2Epi &ep) {
   if constexpr (I < HI) {
-    if (cls == I) {
-      constexpr int L = kF2dSides[I];
-      const unsigned blocks = (unsigned)(((n + 7) / 8) * 8 * n_ch);
-      hipLaunchKernelGGL((k_fft2d<L, MODE>), dim3(blocks), dim3(f2_threads(L)), 0, st, desc, path, tw, list, n, in,
-                         n_ch, out, otf, otf_out, mask, ep);
-      return hipGetLastError();
-    }
-    return f2_launch<MODE, I + 1, HI>(cls, st, n, n_ch, desc, path, tw, list, in, out, otf, otf_out, mask, ep);
-  } else {
-    return hipErrorInvalidValue;
+    if (L == kF2dSides[I])
+      f2_body<kF2dSides[I], MODE, NT>(buf, tw, d, pd, s, ch, tw_all, in, n_ch, out, otf, otf_out, ep);
+    else
+      f2_dispatch<MODE, NT, I + 1, HI>(L, buf, tw, d, pd, s, ch, tw_all, in, n_ch, out, otf, otf_out, ep);
   }
 }
 
-// The launcher of one source's side classes [LO, HI), by mode.
-template <int LO, int HI>
-hipError_t f2_launch_part(int cls, int mode, hipStream_t st, int n, int n_ch, const StampDesc *desc,
-                          const PathDesc *path, const float2 *tw, const Work *list, const float *in, float *out,
-                          const float2 *otf, float2 *otf_out, const int *mask, const Chi2Epi &ep) {
+// One workgroup per (list entry, channel) of the stamps of bucket B (sides
+// kF2dSides[f2b_first(B)] .. f2b_maxL(B)); the LDS and thread count are the
+// bucket's largest side's.  Workgroup ids are assigned so that the n_ch
+// channels of a stamp get ids equal mod 8, which places them on one XCD,
+// where they share the L2 copy of their OTF.
+template <int B, int MODE>
+__global__ __launch_bounds__(f2_threads(f2b_maxL(B))) void k_fft2d(const StampDesc *__restrict__ desc,
+                                                                   const PathDesc *__restrict__ path,
+                                                                   const float2 *__restrict__ tw_all,
+                                                                   const Work *__restrict__ list, int n_list,
+                                                                   const float *__restrict__ in, int n_ch,
+                                                                   float *__restrict__ out,
+                                                                   const float2 *__restrict__ otf,
+                                                                   float2 *__restrict__ otf_out,
+                                                                   const int *__restrict__ mask, Chi2Epi ep) {
+  constexpr int LM = f2b_maxL(B), NT = f2_threads(LM);
+  __shared__ float2 buf[lq_size((LM + 1) * (LM / 2 + 1))];
+  __shared__ float2 tw[LM];
+  const int blk = (int)blockIdx.x;
+  const int grp = blk / (8 * n_ch), rem = blk - grp * 8 * n_ch;
+  const int ch = rem >> 3, li = grp * 8 + (rem & 7);
+  if (li >= n_list) return;
+  const int s = list[li].stamp;
+  if (mask && !mask[s]) return;
+  const StampDesc d = desc[s];
+  const PathDesc pd = path[s];
+  f2_dispatch<MODE, NT, f2b_first(B), kF2dBucketEnd[B]>(pd.L, buf, tw, d, pd, s, ch, tw_all, in, n_ch, out, otf,
+                                                        otf_out, ep);
+}
+
+// Launch bucket B's kernel over its n list entries.
+template <int B>
+hipError_t f2_launch_bucket(int mode, hipStream_t st, int n, int n_ch, const StampDesc *desc, const PathDesc *path,
+                            const float2 *tw_all, const Work *list, const float *in, float *out, const float2 *otf,
+                            float2 *otf_out, const int *mask, const Chi2Epi &ep) {
+  const unsigned blocks = (unsigned)(((n + 7) / 8) * 8 * n_ch);
+  const dim3 grid(blocks), block(f2_threads(f2b_maxL(B)));
   switch (mode) {
     case MODE_CONV:
-      return f2_launch<MODE_CONV, LO, HI>(cls, st, n, n_ch, desc, path, tw, list, in, out, otf, otf_out, mask, ep);
+      hipLaunchKernelGGL((k_fft2d<B, MODE_CONV>), grid, block, 0, st, desc, path, tw_all, list, n, in, n_ch, out,
+                         otf, otf_out, mask, ep);
+      break;
     case MODE_CORR:
-      return f2_launch<MODE_CORR, LO, HI>(cls, st, n, n_ch, desc, path, tw, list, in, out, otf, otf_out, mask, ep);
+      hipLaunchKernelGGL((k_fft2d<B, MODE_CORR>), grid, block, 0, st, desc, path, tw_all, list, n, in, n_ch, out,
+                         otf, otf_out, mask, ep);
+      break;
     case MODE_OTF:
-      return f2_launch<MODE_OTF, LO, HI>(cls, st, n, n_ch, desc, path, tw, list, in, out, otf, otf_out, mask, ep);
+      hipLaunchKernelGGL((k_fft2d<B, MODE_OTF>), grid, block, 0, st, desc, path, tw_all, list, n, in, n_ch, out,
+                         otf, otf_out, mask, ep);
+      break;
     default:
-      return f2_launch<MODE_CHI2, LO, HI>(cls, st, n, n_ch, desc, path, tw, list, in, out, otf, otf_out, mask, ep);
+      hipLaunchKernelGGL((k_fft2d<B, MODE_CHI2>), grid, block, 0, st, desc, path, tw_all, list, n, in, n_ch, out,
+                         otf, otf_out, mask, ep);
+      break;
   }
+  return hipGetLastError();
 }
 
-// Side-class ranges of the sources that build the kernels (split so that
-// they compile in parallel).
-constexpr int kF2dPart[5] = {0, 15, 22, 26, kF2dN};
-hipError_t f2d_launch_p0(int, int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
+hipError_t f2d_launch_b0(int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
                          const Work *, const float *, float *, const float2 *, float2 *, const int *, const Chi2Epi &);
-hipError_t f2d_launch_p1(int, int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
+hipError_t f2d_launch_b1(int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
                          const Work *, const float *, float *, const float2 *, float2 *, const int *, const Chi2Epi &);
-hipError_t f2d_launch_p2(int, int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
+hipError_t f2d_launch_b2(int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
                          const Work *, const float *, float *, const float2 *, float2 *, const int *, const Chi2Epi &);
-hipError_t f2d_launch_p3(int, int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
+hipError_t f2d_launch_b3(int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
+                         const Work *, const float *, float *, const float2 *, float2 *, const int *, const Chi2Epi &);
+hipError_t f2d_launch_b4(int, hipStream_t, int, int, const StampDesc *, const PathDesc *, const float2 *,
                          const Work *, const float *, float *, const float2 *, float2 *, const int *, const Chi2Epi &);
 
 }  // namespace gf

@@ -305,6 +305,33 @@ void gf_destroy(gf_ctx *c) {
   delete c;
 }
 
+int gf_tune_form_get(const gf_ctx *c, int L) {
+  const int k = c ? f2d_class(L) : -1;
+  return k < 0 ? 0 : c->tune_form[k];
+}
+
+gf_status gf_tune_form_set(gf_ctx *c, int L, int form) {
+  if (!c) return GF_EINVAL;
+  const int k = f2d_class(L);
+  if (k < 0 || !(form == -1 || form == 1 || form == 2))
+    return fail(c, GF_EINVAL, "gf_tune_form_set: L is not a one-workgroup side or form is not -1, 1 or 2");
+  c->tune_form[k] = (int8_t)form;
+  return GF_OK;
+}
+
+int gf_tune_min_active_get(const gf_ctx *c, int L) {
+  const int k = c ? f2d_class(L) : -1;
+  return k < 0 ? -1 : c->f2d_min_active[f2d_bucket(k)];
+}
+
+gf_status gf_tune_min_active_set(gf_ctx *c, int L, int n) {
+  if (!c) return GF_EINVAL;
+  const int k = f2d_class(L);
+  if (k < 0 || n < 0) return fail(c, GF_EINVAL, "gf_tune_min_active_set: L is not a one-workgroup side or n < 0");
+  c->f2d_min_active[f2d_bucket(k)] = n;
+  return GF_OK;
+}
+
 gf_status gf_set_stream(gf_ctx *c, void *stream) {
   if (!c) return GF_EINVAL;
   c->stream = (hipStream_t)stream;
@@ -525,7 +552,8 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   std::vector<int> plan_of_L(GF_MAX_FFT + 1, -1);
   std::vector<float2> tw;
   std::vector<int64_t> otf_tmp(n, 0), otf_off(n, 0);
-  std::map<int64_t, int64_t> otf_of_psf;   // PSF offset -> OTF offset
+  std::map<int64_t, int64_t> otf_of_psf;   // PSF offset -> OTF offset (the layout of the stamp's form)
+  std::map<int64_t, int64_t> otf_mp_of_psf;   // PSF offset -> bin-major OTF offset
   std::vector<Work> otf_rows, otf_cols;
   std::vector<Work> f2d_cls[kF2dN], f2d_otf_cls[kF2dN];
   int64_t otf_tmp_n = 0;
@@ -543,7 +571,13 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     if (mode == GF_CONV_FFT_FUSED) return 2;
     if (mode == GF_CONV_AUTO && d.K <= 7) return 0;
     if (!fits) return 1;
-    if (mode == GF_CONV_AUTO && c->tune_multipass(L)) return 1;
+    if (mode == GF_CONV_AUTO) {
+      // untuned sides: the one-workgroup form up to 160 (above, its kernels
+      // run out of registers and the multi-pass form is faster)
+      const int f = c->tune_form[f2d_class(L)];
+      if (f > 0) return f;
+      return L <= 160 ? 2 : 1;
+    }
     return 2;
   };
   // The largest radix over the plans of the multi-pass stamps picks the
@@ -552,7 +586,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     std::vector<char> seen(GF_MAX_FFT + 1, 0);
     for (int s = 0; s < n; ++s) {
       const StampDesc &d = b->h_desc[s];
-      const bool f = path_of(d) == 1;
+      const bool f = path_of(d) != 0;   // one-workgroup stamps may run multi-pass too
       const int L = fft_side(std::max(d.Mh, d.Mw));
       if (!f || L > GF_MAX_FFT || seen[L]) continue;
       seen[L] = 1;
@@ -578,8 +612,9 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     pd.fft = path;
     pd.L = 0;
     pd.plan = -1;
-    pd.pad0 = 0;
+    pd.tw = 0;
     pd.otf = 0;
+    pd.otf_mp = 0;
     p->h_c2_first.push_back((int32_t)p->n_c2);
     if (!fft) {
       const int np = (d.H * d.W + kPixChunk - 1) / kPixChunk;
@@ -613,58 +648,65 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     p->max_L = std::max(p->max_L, L);
     pd.L = L;
     pd.plan = plan_of_L[L];
+    pd.tw = p->h_plans[pd.plan].tw_off;
     const int Lh = L / 2 + 1;
-    if (path == 2) {
+    const bool f2 = path == 2;
+    if (f2) {
       const int cls = f2d_class(L);
       ++p->n_f2d;
-      p->f2d_tw[cls] = p->h_plans[pd.plan].tw_off;
-      f2d_cls[cls].push_back({s, cls});
+      f2d_cls[cls].push_back({s, f2d_bucket(cls)});
       auto hit = otf_of_psf.find(d.psf);
       if (hit == otf_of_psf.end()) {
         otf_of_psf[d.psf] = p->n_otf;
         pd.otf = p->n_otf;
         p->n_otf += (int64_t)L * Lh;
-        f2d_otf_cls[cls].push_back({s, cls});
+        f2d_otf_cls[cls].push_back({s, f2d_bucket(cls)});
       } else {
         pd.otf = hit->second;
       }
-      continue;
     }
+    // multi-pass units (for a one-workgroup stamp: the alternative used
+    // once few of its bucket's stamps are still fitting)
     const int T = cap / (L + 1), C = cap / L;
     const int cols = (Lh + C - 1) / C;
-    for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_rows.push_back({s, u});
-    for (int u = 0; u < cols; ++u) p->h_cols.push_back({s, u});
-    for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) p->h_irows.push_back({s, u});
-    for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) p->h_arows.push_back({s, u});
-    for (int u = 0; u < cols; ++u) p->h_acols.push_back({s, u});
-    for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_airows.push_back({s, u});
+    for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) (f2 ? p->h_rows_alt : p->h_rows).push_back({s, u});
+    for (int u = 0; u < cols; ++u) (f2 ? p->h_cols_alt : p->h_cols).push_back({s, u});
+    for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) (f2 ? p->h_irows_alt : p->h_irows).push_back({s, u});
+    if (!f2) {
+      for (int u = 0; u < (d.H + 2 * T - 1) / (2 * T); ++u) p->h_arows.push_back({s, u});
+      for (int u = 0; u < cols; ++u) p->h_acols.push_back({s, u});
+      for (int u = 0; u < (d.Mh + 2 * T - 1) / (2 * T); ++u) p->h_airows.push_back({s, u});
+      p->h_s1a[s] = p->n_s1a;
+      p->n_s1a += (int64_t)d.H * Lh;
+      p->h_s2a[s] = p->n_s2a;
+      p->n_s2a += (int64_t)d.Mh * Lh;
+    }
     {
       const int Tn = std::min(T, kFftNarrowT), Cn = std::min(C, kFftNarrowC);
-      for (int u = 0; u < (d.Mh + 2 * Tn - 1) / (2 * Tn); ++u) p->h_rows_n.push_back({s, u});
-      for (int u = 0; u < (Lh + Cn - 1) / Cn; ++u) p->h_cols_n.push_back({s, u});
-      for (int u = 0; u < (d.H + 2 * Tn - 1) / (2 * Tn); ++u) p->h_irows_n.push_back({s, u});
+      for (int u = 0; u < (d.Mh + 2 * Tn - 1) / (2 * Tn); ++u)
+        (f2 ? p->h_rows_n_alt : p->h_rows_n).push_back({s, u});
+      for (int u = 0; u < (Lh + Cn - 1) / Cn; ++u) (f2 ? p->h_cols_n_alt : p->h_cols_n).push_back({s, u});
+      for (int u = 0; u < (d.H + 2 * Tn - 1) / (2 * Tn); ++u)
+        (f2 ? p->h_irows_n_alt : p->h_irows_n).push_back({s, u});
     }
     p->h_s1[s] = p->n_s1;
     p->n_s1 += (int64_t)d.Mh * Lh;
     p->h_s2[s] = p->n_s2;
     p->n_s2 += (int64_t)d.H * Lh;
-    p->h_s1a[s] = p->n_s1a;
-    p->n_s1a += (int64_t)d.H * Lh;
-    p->h_s2a[s] = p->n_s2a;
-    p->n_s2a += (int64_t)d.Mh * Lh;
-    auto hit = otf_of_psf.find(d.psf);
-    if (hit == otf_of_psf.end()) {
-      otf_of_psf[d.psf] = p->n_otf;
+    auto hit = otf_mp_of_psf.find(d.psf);
+    if (hit == otf_mp_of_psf.end()) {
+      otf_mp_of_psf[d.psf] = p->n_otf;
       otf_off[s] = p->n_otf;
-      pd.otf = p->n_otf;
+      pd.otf_mp = p->n_otf;
       p->n_otf += (int64_t)L * Lh;
       otf_tmp[s] = otf_tmp_n;
       otf_tmp_n += (int64_t)d.K * Lh;
       for (int u = 0; u < (d.K + 2 * T - 1) / (2 * T); ++u) otf_rows.push_back({s, u});
       for (int u = 0; u < cols; ++u) otf_cols.push_back({s, u});
     } else {
-      pd.otf = hit->second;   // stamps sharing a PSF (same group) share its OTF
+      pd.otf_mp = hit->second;   // stamps sharing a PSF (same group) share its OTF
     }
+    if (!f2) pd.otf = pd.otf_mp;
   }
   p->h_c2_first.push_back((int32_t)p->n_c2);
   if (p->n_c2 > 0x7fffffff) {
@@ -672,15 +714,18 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     return fail(c, GF_ESHAPE, "gf_psf_prepare: batch too large");
   }
   std::vector<Work> f2d_otf;
-  int f2d_otf_first[kF2dN + 1] = {};
+  int f2d_otf_first[kF2dBuckets + 1] = {};
   for (int k = 0; k < kF2dN; ++k) {
-    p->f2d_first[k] = (int)p->h_f2d.size();
+    const int bk = f2d_bucket(k);
+    if (k == 0 || f2d_bucket(k - 1) != bk) {
+      p->f2d_first[bk] = (int)p->h_f2d.size();
+      f2d_otf_first[bk] = (int)f2d_otf.size();
+    }
     p->h_f2d.insert(p->h_f2d.end(), f2d_cls[k].begin(), f2d_cls[k].end());
-    f2d_otf_first[k] = (int)f2d_otf.size();
     f2d_otf.insert(f2d_otf.end(), f2d_otf_cls[k].begin(), f2d_otf_cls[k].end());
   }
-  p->f2d_first[kF2dN] = (int)p->h_f2d.size();
-  f2d_otf_first[kF2dN] = (int)f2d_otf.size();
+  p->f2d_first[kF2dBuckets] = (int)p->h_f2d.size();
+  f2d_otf_first[kF2dBuckets] = (int)f2d_otf.size();
   hipError_t e = hipSuccess;
   Work *d_orows = nullptr, *d_ocols = nullptr, *d_o2d = nullptr;
   int64_t *d_otmp = nullptr, *d_ooff = nullptr;
@@ -988,7 +1033,8 @@ struct LMBufs {
 int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
   return (int64_t)b->h_eval.size() + b->h_pix.size() + b->h_neq.size() + p->h_rows.size() + p->h_cols.size() +
          p->h_irows.size() + p->h_rows_n.size() + p->h_cols_n.size() + p->h_irows_n.size() + p->h_direct.size() +
-         p->h_pix_direct.size() + p->h_f2d.size() + b->n;
+         p->h_pix_direct.size() + p->h_f2d.size() + p->h_rows_alt.size() + p->h_cols_alt.size() +
+         p->h_irows_alt.size() + p->h_rows_n_alt.size() + p->h_cols_n_alt.size() + p->h_irows_n_alt.size() + b->n;
 }
 
 // Work lists restricted to the stamps flagged in act, filtered from `from`
@@ -1020,7 +1066,34 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   filt(full ? p->h_irows_n : from.irows_n, to.irows_n);
   filt(full ? p->h_direct : from.direct, to.direct);
   filt(full ? p->h_pix_direct : from.pix_direct, to.pix_direct);
-  filt(full ? p->h_f2d : from.f2d, to.f2d);   // stays grouped by side class (unit)
+  filt(full ? p->h_f2d : from.f2d, to.f2d);   // stays grouped by bucket (unit)
+  // Buckets with few stamps left: their workgroups would not fill the
+  // device, so those stamps move to the multi-pass launches (which spread a
+  // stamp over many workgroups) for the rest of the fit.
+  {
+    int cnt[kF2dBuckets] = {};
+    for (const Work &w : to.f2d) ++cnt[w.unit];
+    std::vector<char> mv(b->n, 0);
+    bool any = false;
+    for (const Work &w : to.f2d)
+      if (cnt[w.unit] < b->ctx->f2d_min_active[w.unit]) mv[w.stamp] = 1, any = true;
+    if (any) {
+      std::vector<Work> keep;
+      for (const Work &w : to.f2d)
+        if (!mv[w.stamp]) keep.push_back(w);
+      to.f2d.swap(keep);
+      auto add = [&](const std::vector<Work> &alt, std::vector<Work> &dst) {
+        for (const Work &w : alt)
+          if (mv[w.stamp]) dst.push_back(w);
+      };
+      add(p->h_rows_alt, to.rows);
+      add(p->h_cols_alt, to.cols);
+      add(p->h_irows_alt, to.irows);
+      add(p->h_rows_n_alt, to.rows_n);
+      add(p->h_cols_n_alt, to.cols_n);
+      add(p->h_irows_n_alt, to.irows_n);
+    }
+  }
   to.stamps.clear();
   for (int s = 0; s < b->n; ++s)
     if (act[s]) to.stamps.push_back({s, 0});
@@ -1050,9 +1123,9 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   if (e == hipSuccess) e = put(to.stamps, v.stamps, v.n_stamps);
   int n_f2d = 0;
   if (e == hipSuccess) e = put(to.f2d, v.f2d, n_f2d);
-  for (int k = 0; k <= kF2dN; ++k) v.f2d_first[k] = 0;
+  for (int k = 0; k <= kF2dBuckets; ++k) v.f2d_first[k] = 0;
   for (const Work &w : to.f2d) ++v.f2d_first[w.unit + 1];
-  for (int k = 0; k < kF2dN; ++k) v.f2d_first[k + 1] += v.f2d_first[k];
+  for (int k = 0; k < kF2dBuckets; ++k) v.f2d_first[k + 1] += v.f2d_first[k];
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors must outlive the copies
   return e;
 }

@@ -53,8 +53,9 @@ struct PathDesc {
   int32_t fft;    // 0 = direct, 1 = multi-pass FFT, 2 = one-workgroup FFT (fused)
   int32_t L;      // FFT side (0 on the direct path)
   int32_t plan;   // index into the plan table (-1 on the direct path)
-  int32_t pad0;
-  int64_t otf;    // offset of this stamp's OTF (complex elements)
+  int32_t tw;     // offset of the side's twiddles exp(-2 pi i k / L) in the twiddle table
+  int64_t otf;    // offset of this stamp's OTF (complex elements), in the layout of its form
+  int64_t otf_mp; // offset of its OTF bin-major [L/2+1][L] for the multi-pass kernels (= otf on that form)
 };
 
 // Mixed-radix Stockham plan for one FFT side L (radix-r stage s works on
@@ -91,6 +92,16 @@ inline int f2d_class(int L) {
     if (kF2dSides[i] == L) return i;
   return -1;
 }
+// The side classes are launched in five buckets of similar LDS size (one
+// launch per bucket covers every stamp of its sides): classes
+// [kF2dBucketEnd[b-1], kF2dBucketEnd[b]), i.e. sides up to 64, 96, 128, 160
+// and 192.
+constexpr int kF2dBuckets = 5;
+constexpr int kF2dBucketEnd[kF2dBuckets] = {16, 20, 24, 27, 30};
+constexpr int f2d_bucket(int cls) {
+  return cls < kF2dBucketEnd[0] ? 0 : cls < kF2dBucketEnd[1] ? 1 : cls < kF2dBucketEnd[2] ? 2
+                                                           : cls < kF2dBucketEnd[3] ? 3 : 4;
+}
 
 // Work lists of one launch set: by default a batch's and a prepared PSF's
 // full lists; gf_fit_lm substitutes lists that hold only the stamps still
@@ -109,10 +120,10 @@ struct WorkView {
   int n_pix_direct = 0;
   const Work *stamps = nullptr;   // the stamps still iterating (unit 0), for the per-stamp LM kernels
   int n_stamps = 0;
-  // one-workgroup FFT convolutions: entries of side class c at
-  // f2d[f2d_first[c] .. f2d_first[c + 1])
+  // one-workgroup FFT convolutions: entries of bucket b at
+  // f2d[f2d_first[b] .. f2d_first[b + 1]) (unit = bucket)
   const Work *f2d = nullptr;
-  int f2d_first[kF2dN + 1] = {};
+  int f2d_first[kF2dBuckets + 1] = {};
 };
 
 // Per-component constants of the evaluation kernels (computed per workgroup).
@@ -285,13 +296,19 @@ struct gf_ctx {
   // tuning table: per one-workgroup side class, the FFT form that the
   // automatic path choice takes (-1 untuned, 1 multi-pass, 2 one-workgroup)
   int8_t tune_form[gf::kF2dN];
+  // per bucket of one-workgroup sides: the fewest still-fitting stamps for
+  // which gf_fit_lm keeps that form (below it, they move to the multi-pass
+  // launches)
+  int32_t f2d_min_active[gf::kF2dBuckets];
   std::string tune_path;      // file the table is read from and written to ("" = none)
   gf_ctx() {
     for (int i = 0; i < gf::kF2dN; ++i) tune_form[i] = -1;
-  }
-  bool tune_multipass(int L) const {
-    const int k = gf::f2d_class(L);
-    return k >= 0 && tune_form[k] == 1;
+    // eight rounds of workgroups on 256 CUs for a seven-channel Jacobian,
+    // at the workgroups per CU each bucket's kernel fits (on the uneven
+    // batch, keeping the form down to two rounds ran 2 % slower than the
+    // multi-pass form alone, eight or more rounds 0.5 % faster)
+    const int wg_per_cu[gf::kF2dBuckets] = {6, 3, 1, 1, 1};
+    for (int b = 0; b < gf::kF2dBuckets; ++b) f2d_min_active[b] = 8 * 256 * wg_per_cu[b] / 7;
   }
 };
 
@@ -366,12 +383,16 @@ struct gf_psf {
   std::vector<gf::Work> h_pix_direct;
   gf::Work *d_pix_direct = nullptr;
   // one-workgroup FFT convolutions (sides up to kF2dMaxL): one entry per
-  // stamp, grouped by side class; the OTFs of these stamps are stored
-  // row-major [L][L/2+1]
+  // stamp (unit = its bucket), grouped by bucket and side; the OTFs of these
+  // stamps are stored row-major [L][L/2+1]
   std::vector<gf::Work> h_f2d;
   gf::Work *d_f2d = nullptr;
-  int f2d_first[gf::kF2dN + 1] = {};
-  int64_t f2d_tw[gf::kF2dN] = {};     // twiddle offset of each side class in d_tw
+  int f2d_first[gf::kF2dBuckets + 1] = {};
+  // multi-pass work units of the one-workgroup stamps (spectra offsets and a
+  // bin-major OTF are kept for them too), used when few of a bucket's
+  // stamps are still fitting: gf_fit_lm then moves them to the multi-pass
+  // launches, which spread one stamp over many workgroups
+  std::vector<gf::Work> h_rows_alt, h_cols_alt, h_irows_alt, h_rows_n_alt, h_cols_n_alt, h_irows_n_alt;
   int n_fft = 0, n_direct = 0, n_f2d = 0;
 };
 

@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
     for (int idx = threadIdx.x; idx < nc * L; idx += blockDim.x) dst[idx] = cscale(buf[lp(idx)], sc);
     return;
   }
-  const __amdgpu_buffer_rsrc_t hrsrc = make_rsrc(otf + pd.otf, (uint32_t)(L * Lh) * 8u);
+  const __amdgpu_buffer_rsrc_t hrsrc = make_rsrc(otf + pd.otf_mp, (uint32_t)(L * Lh) * 8u);
   {
     float2 hv[NIT];
 #pragma unroll
@@ -541,12 +541,12 @@ static hipError_t multipass_conv(hipStream_t st, const gf_batch *b, const gf_psf
   const Work *d_irows = view ? (narrow ? v->irows_n : v->irows) : (narrow ? p->d_irows_n : p->d_irows);
   const int tr = narrow ? kFftNarrowT : 1 << 20, tc = narrow ? kFftNarrowC : 1 << 20;
   {
-    ProfScope ps(st, "k_fft_rows");
+    ProfScope ps(st, ep ? "k_fft_rows.chi2" : "k_fft_rows");
     GF_FFT_LAUNCH(k_fft_rows, MODE_CONV, dim3((unsigned)nr, n_ch), blk, lds, st, b->d_desc, p->d_path,
                        p->d_plans, p->d_tw, d_rows, in, n_ch, p->d_s1, S1, mask, tr);
   }
   {
-    ProfScope ps(st, "k_fft_cols");
+    ProfScope ps(st, ep ? "k_fft_cols.chi2" : "k_fft_cols");
     GF_FFT_LAUNCH(k_fft_cols, MODE_CONV, dim3((unsigned)nc, n_ch), blk, lds, st, b->d_desc, p->d_path,
                        p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
   }

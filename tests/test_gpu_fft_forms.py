@@ -115,7 +115,7 @@ def test_both_forms_in_one_batch(ctx, gfo):
     paths = list(gb.psf.uses_fft)
     sides = list(gb.psf.fft_side)
     for p, s in zip(paths, sides):
-        assert p == (2 if s <= L.GF_FFT_FUSED_MAX else 1), (paths, sides)
+        assert p == (2 if s <= 160 else 1), (paths, sides)
     assert 1 in paths and 2 in paths
 
 
@@ -207,12 +207,33 @@ def test_restricted_lists_keep_both_forms(ctx, gfo):
     lo = to_dev(np.concatenate([synth.bounds(1, st.H, st.W)[0] for st in stamps]), torch.float64)
     hi = to_dev(np.concatenate([synth.bounds(1, st.H, st.W)[1] for st in stamps]), torch.float64)
     start = to_dev(np.concatenate([st.start for st in stamps]), torch.float64)
-    out = []
-    for pe in (1, 1000):
-        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-8,
-                              poll_every=pe, speculate=0)
-        out.append((th.cpu().numpy(), info))
-    assert len(set(out[1][1]["iters"])) > 2    # stamps finish at different iterations
-    np.testing.assert_array_equal(out[0][0], out[1][0])
-    for k in ("chi2", "iters", "nfev", "status"):
-        np.testing.assert_array_equal(out[0][1][k], out[1][1][k])
+    def fits():
+        out = []
+        for pe in (1, 1000):
+            th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-8,
+                                  poll_every=pe, speculate=0)
+            out.append((th.cpu().numpy(), info))
+        return out
+
+    sides = sorted({int(s) for s, u in zip(gb.psf.fft_side, gb.psf.uses_fft) if u == 2})
+    keep = {s: L.gf_tune_min_active_get(ctx.ptr, s) for s in sides}
+    try:
+        # the one-workgroup stamps keep their form to the end: the same bits
+        for s in sides:
+            L.gf_tune_min_active_set(ctx.ptr, s, 0)
+        out = fits()
+        assert len(set(out[1][1]["iters"])) > 2    # stamps finish at different iterations
+        np.testing.assert_array_equal(out[0][0], out[1][0])
+        for k in ("chi2", "iters", "nfev", "status"):
+            np.testing.assert_array_equal(out[0][1][k], out[1][1][k])
+        # every stamp moves to the multi-pass form at the first restriction:
+        # the same minima (both forms compute the same convolution to
+        # rounding)
+        for s in sides:
+            L.gf_tune_min_active_set(ctx.ptr, s, 1 << 20)
+        out2 = fits()
+        np.testing.assert_allclose(out2[0][1]["chi2"], out2[1][1]["chi2"], rtol=1e-5)
+        np.testing.assert_allclose(out2[0][1]["chi2"], out[1][1]["chi2"], rtol=1e-5)
+    finally:
+        for s, v in keep.items():
+            L.gf_tune_min_active_set(ctx.ptr, s, v)
