@@ -56,6 +56,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed FMA)
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix
+# the library's tuning file (FFT form per side, measured on first use)
+TUNE_FILE = os.path.join(ROOT, "gpurun_out", "gf_tune.json")
 METRIC = "model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5"
 
 # Algorithmic FP32 operations per sub-sample and component (an FMA counts
@@ -296,7 +298,7 @@ def run_c3(args, torch, ops, synth, peaks, steps=None, warmup=None):
     dev = torch.device("cuda", 0)
     stamps = synth.c3(4096)
     n = len(stamps)
-    ctx = ops.Context(0)
+    ctx = ops.Context(0, autotune_cache=TUNE_FILE)
     H = [s.H for s in stamps]
     K = [s.K for s in stamps]
     batch = ops.Batch(ctx, H, H, K, [1] * n)
@@ -437,7 +439,7 @@ def run_single(torch, ops, synth, st, ncomp, noise, K_, W, peaks, workload, labe
     """One-image fits (C1, C2): K_ whole fits from the seeded start, timed
     back to back; the result records stay on the device until the end."""
     dev = torch.device("cuda", 0)
-    ctx = ops.Context(0)
+    ctx = ops.Context(0, autotune_cache=TUNE_FILE)
     batch = ops.Batch(ctx, [st.H], [st.W], [st.K], [ncomp])
     taps = torch.from_numpy(st.psf.astype(np.float32).ravel()).to(dev)
     psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
@@ -917,6 +919,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=src.numel() * 4, copies=3)))
         return
+    os.makedirs(os.path.dirname(TUNE_FILE), exist_ok=True)
     pctx = ops.Context(0)
     peaks = calibrate_peaks(pctx)
     pctx.close()

@@ -89,8 +89,16 @@ typedef enum {
 /* ------------------------------------------------------------- contexts */
 
 /* Create a context on HIP device `device`; builds the b_n table (FP64 on the
- * host, FP32 on the device).  *ctx is set to NULL on failure. */
-gf_status gf_create(gf_ctx **ctx, int device);
+ * host, FP32 on the device).  *ctx is set to NULL on failure.
+ * autotune_cache: path of the context's tuning file (nullable).  With a
+ * path, the table it holds for this GPU (architecture and device name) is
+ * loaded, and gf_psf_prepare(GF_CONV_AUTO) measures every one-workgroup FFT
+ * side it meets that the table lacks (see gf_tune_form_get; this launches
+ * timing convolutions and allocates temporary device memory in that call)
+ * and rewrites the file.  A later context reading the same file takes the
+ * same choices, so its results are the same bits.  Without a path nothing
+ * is measured and untuned sides take the default rule. */
+gf_status gf_create(gf_ctx **ctx, int device, const char *autotune_cache);
 void gf_destroy(gf_ctx *ctx);
 /* Tuning table of the context, read by gf_psf_prepare(GF_CONV_AUTO) and
  * gf_fit_lm.  For an FFT side L of the one-workgroup form (an even
@@ -108,6 +116,12 @@ void gf_destroy(gf_ctx *ctx);
  * move may take other last bits).  The getters return 0 (form) or -1
  * (min_active) for sides that are not one-workgroup sides; the setters
  * return GF_EINVAL for them. */
+/* Measure the FFT forms of the given one-workgroup sides now (NULL and 0:
+ * every one of them): per side, 256 stamps of padded side L convolved in
+ * seven channels by each form, the faster form kept.  Writes the context's
+ * tuning file when it has one (min_active values set on the context are
+ * written too).  GF_EINVAL for a side that is not a one-workgroup side. */
+gf_status gf_autotune(gf_ctx *ctx, const int32_t *sides, int n_sides);
 int gf_tune_form_get(const gf_ctx *ctx, int L);
 gf_status gf_tune_form_set(gf_ctx *ctx, int L, int form);
 int gf_tune_min_active_get(const gf_ctx *ctx, int L);

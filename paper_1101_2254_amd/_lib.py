@@ -34,7 +34,7 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_line_batch_create", "gf_line_batch_destroy",
            "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version",
-           "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set")
+           "gf_autotune", "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set")
 
 
 class GfLmOpts(ctypes.Structure):
@@ -89,7 +89,8 @@ def lib() -> ctypes.CDLL:
     pvp = ctypes.POINTER(ctypes.c_void_p)
     pi64 = ctypes.POINTER(ctypes.c_int64)
     sig = {
-        "gf_create": (i32, [pvp, i32]),
+        "gf_create": (i32, [pvp, i32, ctypes.c_char_p]),
+        "gf_autotune": (i32, [vp, vp, i32]),
         "gf_destroy": (None, [vp]),
         "gf_set_stream": (i32, [vp, vp]),
         "gf_last_error": (ctypes.c_char_p, [vp]),
@@ -167,10 +168,20 @@ def check(status: int, ctx=None, what: str = "") -> None:
 
 
 # Thin wrappers with the C names (pointers as ints).
-def gf_create(device: int = 0) -> int:
+def gf_create(device: int = 0, autotune_cache=None) -> int:
     p = ctypes.c_void_p()
-    check(lib().gf_create(ctypes.byref(p), device), None, "gf_create failed")
+    path = None if autotune_cache is None else os.fsencode(autotune_cache)
+    check(lib().gf_create(ctypes.byref(p), device, path), None, "gf_create failed")
     return p.value
+
+
+def gf_autotune(ctx, sides=None) -> None:
+    import numpy as np
+    if not sides:
+        check(lib().gf_autotune(ctx, None, 0), ctx)
+        return
+    a = np.ascontiguousarray(sides, dtype=np.int32)
+    check(lib().gf_autotune(ctx, a.ctypes.data, a.size), ctx)
 
 
 def gf_destroy(ctx: int) -> None:

@@ -256,12 +256,13 @@ extern "C" {
 
 const char *gf_version(void) { return "libgf 0.2 (gfx950)"; }
 
-gf_status gf_create(gf_ctx **out, int device) {
+gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
   if (!out) return GF_EINVAL;
   *out = nullptr;
   gf_ctx *c = new (std::nothrow) gf_ctx();
   if (!c) return GF_ENOMEM;
   c->device = device;
+  if (autotune_cache) c->tune_path = autotune_cache;
   if (hipSetDevice(device) != hipSuccess) {
     delete c;
     return GF_EDEVICE;
@@ -282,6 +283,7 @@ gf_status gf_create(gf_ctx **out, int device) {
     delete c;
     return GF_ENOMEM;
   }
+  if (!c->tune_path.empty()) (void)tune_load(c);   // an unreadable or foreign table is ignored
   *out = c;
   return GF_OK;
 }
@@ -329,6 +331,7 @@ gf_status gf_tune_min_active_set(gf_ctx *c, int L, int n) {
   const int k = f2d_class(L);
   if (k < 0 || n < 0) return fail(c, GF_EINVAL, "gf_tune_min_active_set: L is not a one-workgroup side or n < 0");
   c->f2d_min_active[f2d_bucket(k)] = n;
+  c->tune_min_done[f2d_bucket(k)] = 1;
   return GF_OK;
 }
 
@@ -537,6 +540,19 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   if (!c || !b || !taps || !out || mode < GF_CONV_AUTO || mode > GF_CONV_FFT_FUSED)
     return fail(c, GF_EINVAL, "gf_psf_prepare: bad argument");
   *out = nullptr;
+  // first use of a one-workgroup side by the automatic choice of a context
+  // with a tuning file: measure it now
+  if (mode == GF_CONV_AUTO && !c->tune_path.empty()) {
+    std::vector<char> seen(kF2dN, 0);
+    for (const StampDesc &d : b->h_desc) {
+      const int k = d.K > 7 ? f2d_class(fft_side(std::max(d.Mh, d.Mw))) : -1;
+      if (k < 0 || seen[k] || c->tune_form[k] >= 0) continue;
+      seen[k] = 1;
+      const gf_status ts = tune_side(c, kF2dSides[k]);
+      if (ts != GF_OK) return fail(c, ts, "gf_psf_prepare: measuring the FFT forms of side " +
+                                              std::to_string(kF2dSides[k]) + " failed");
+    }
+  }
   gf_psf *p = new (std::nothrow) gf_psf();
   if (!p) return fail(c, GF_ENOMEM, "gf_psf_prepare: host allocation");
   p->ctx = c;

@@ -300,7 +300,8 @@ struct gf_ctx {
   // which gf_fit_lm keeps that form (below it, they move to the multi-pass
   // launches)
   int32_t f2d_min_active[gf::kF2dBuckets];
-  std::string tune_path;      // file the table is read from and written to ("" = none)
+  int8_t tune_min_done[gf::kF2dBuckets] = {};   // f2d_min_active measured (or read) for the bucket
+  std::string tune_path;      // file the table is read from and written to ("" = no measuring)
   gf_ctx() {
     for (int i = 0; i < gf::kF2dN; ++i) tune_form[i] = -1;
     // eight rounds of workgroups on 256 CUs for a seven-channel Jacobian,
@@ -313,6 +314,10 @@ struct gf_ctx {
 };
 
 namespace gf {
+// Tuning table I/O and measurement (tune.cpp).
+gf_status tune_load(gf_ctx *c);
+gf_status tune_save(gf_ctx *c);
+gf_status tune_side(gf_ctx *c, int L);
 // Binds a context's profiler to the calling thread for one entry point.
 struct ProfBind {
   Profiler *prev;

@@ -44,9 +44,11 @@ def _need(t, dtype, n, name):
 class Context:
     """A libgf context bound to one HIP device; work goes on torch's current stream."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, autotune_cache=None):
+        """autotune_cache: path of the tuning file (None: no measuring, the
+        default FFT-form rule)."""
         self.device = torch.device("cuda", device)
-        self.ptr = L.gf_create(device)
+        self.ptr = L.gf_create(device, autotune_cache)
 
     def bind_stream(self):
         L.gf_set_stream(self.ptr, torch.cuda.current_stream(self.device).cuda_stream)
