@@ -71,5 +71,15 @@ class GpuBatch:
         return out
 
 
+def keep_fft_forms(ctx):
+    """Keep one-workgroup stamps on that form to the end of every fit (no
+    move to the multi-pass launches when few remain), so a stamp's fit does
+    not depend on how many other stamps of its batch are still fitting:
+    the bitwise batch-independence checks rely on it."""
+    from paper_1101_2254_amd import _lib as L
+    for side in (64, 96, 128, 160, 192):
+        L.gf_tune_min_active_set(ctx.ptr, side, 0)
+
+
 def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))

@@ -17,7 +17,7 @@ import torch
 
 import synth
 from paper_1101_2254_amd import ops
-from tests.gpu_common import GpuBatch, rel_l2, to_dev
+from tests.gpu_common import keep_fft_forms, GpuBatch, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 def ctx():
     print("gpu parity: creating context on cuda:0", flush=True)
     c = ops.Context(0)
+    keep_fft_forms(c)
     yield c
     torch.cuda.synchronize()
     c.close()

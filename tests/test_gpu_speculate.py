@@ -11,7 +11,7 @@ import torch
 import synth
 from paper_1101_2254_amd import _lib as L
 from paper_1101_2254_amd import ops
-from tests.gpu_common import GpuBatch, to_dev
+from tests.gpu_common import keep_fft_forms, GpuBatch, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 def ctx():
     print("gpu speculate: creating context on cuda:0", flush=True)
     c = ops.Context(0)
+    keep_fft_forms(c)
     yield c
     torch.cuda.synchronize()
     c.close()
