@@ -237,6 +237,21 @@ gf_status gf_model(gf_ctx *ctx, const gf_batch *batch, const gf_psf *psf, const 
 gf_status gf_chi2(gf_ctx *ctx, const gf_batch *batch, const float *model, const float *theta, const float *data,
                   const float *weight, float *resid, float *chi2);
 
+/* gf_chi2 for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and the same bits as gf_chi2, with the per-chunk
+ * partials in a fixed array of GF_CHI2_NOALLOC_MAX_CHUNKS (hi, lo) pairs
+ * (1 MiB) that the library holds on each device from gf_create until the
+ * process ends, instead of the context workspace.  It allocates nothing and
+ * calls no allocating routine.  A batch with more than
+ * GF_CHI2_NOALLOC_MAX_CHUNKS chunks of 4096 pixels (about 5.4e8 pixels) is
+ * refused with GF_ESHAPE before anything is enqueued.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other contexts, other threads) race and must be ordered by the caller. */
+#define GF_CHI2_NOALLOC_MAX_CHUNKS 131072
+gf_status gf_chi2_noalloc(gf_ctx *ctx, const gf_batch *batch, const float *model, const float *theta,
+                          const float *data, const float *weight, float *resid, float *chi2);
+
 /* Steps 1-3 in one call: chi2 (device [2 * n_stamps], (hi, lo) pairs as in
  * gf_chi2) of every stamp at theta (device [n_par] FP32).  work: device
  * scratch of at least gf_likelihood_workspace() bytes, or NULL to use the

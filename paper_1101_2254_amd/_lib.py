@@ -34,7 +34,7 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_line_batch_create", "gf_line_batch_destroy",
            "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version",
-           "gf_autotune", "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set")
+           "gf_chi2_noalloc", "gf_autotune", "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set")
 
 
 class GfLmOpts(ctypes.Structure):
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "gf_create": (i32, [pvp, i32, ctypes.c_char_p]),
         "gf_autotune": (i32, [vp, vp, i32]),
+        "gf_chi2_noalloc": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "gf_destroy": (None, [vp]),
         "gf_set_stream": (i32, [vp, vp]),
         "gf_last_error": (ctypes.c_char_p, [vp]),
@@ -173,6 +174,10 @@ def gf_create(device: int = 0, autotune_cache=None) -> int:
     path = None if autotune_cache is None else os.fsencode(autotune_cache)
     check(lib().gf_create(ctypes.byref(p), device, path), None, "gf_create failed")
     return p.value
+
+
+def gf_chi2_noalloc(ctx, b, model_ptr, theta_ptr, data_ptr, weight_ptr, resid_ptr, chi2_ptr) -> None:
+    check(lib().gf_chi2_noalloc(ctx, b, model_ptr, theta_ptr, data_ptr, weight_ptr, resid_ptr, chi2_ptr), ctx)
 
 
 def gf_autotune(ctx, sides=None) -> None:

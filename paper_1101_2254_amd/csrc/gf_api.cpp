@@ -13,6 +13,7 @@
 
 namespace gf {
 std::vector<float4> build_bn_table();
+hipError_t noalloc_init(int device);
 hipError_t launch_eval(hipStream_t, const gf_batch *, const float *, int, const float4 *, float *, const int *);
 hipError_t launch_eval_d(hipStream_t, const gf_batch *, const double *, int, const float4 *, float *, const int *,
                          const WorkView *, CompC *cc = nullptr, bool prep = true);
@@ -284,6 +285,13 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
     return GF_ENOMEM;
   }
   if (!c->tune_path.empty()) (void)tune_load(c);   // an unreadable or foreign table is ignored
+  if (noalloc_init(device) != hipSuccess) {
+    dfree(c->d_bn);
+    dfree(c->d_counters);
+    (void)hipHostFree(c->h_pinned);
+    delete c;
+    return GF_EDEVICE;
+  }
   *out = c;
   return GF_OK;
 }

@@ -167,6 +167,23 @@ def chi2(ctx: Context, batch: Batch, model_img: torch.Tensor, theta: torch.Tenso
     return pairs, resid
 
 
+def chi2_noalloc(ctx: Context, batch: Batch, model_img: torch.Tensor, theta: torch.Tensor, data: torch.Tensor,
+                 weight: torch.Tensor, want_resid: bool = False, out=None, resid=None):
+    """Step 3 without any library allocation (gf_chi2_noalloc): the same
+    result as chi2().  Returns (pairs [n, 2] FP32 (hi, lo), resid or None)."""
+    _need(model_img, torch.float32, batch.sizes["n_pix"], "model")
+    _need(theta, torch.float32, batch.sizes["n_par"], "theta")
+    _need(data, torch.float32, batch.sizes["n_img"], "data")
+    _need(weight, torch.float32, batch.sizes["n_img"], "weight")
+    pairs = torch.empty((batch.n, 2), dtype=torch.float32, device=ctx.device) if out is None else out
+    if want_resid and resid is None:
+        resid = _empty(ctx, batch.sizes["n_pix"])
+    ctx.bind_stream()
+    L.gf_chi2_noalloc(ctx.ptr, batch.ptr, _ptr(model_img), _ptr(theta), _ptr(data), _ptr(weight),
+                      _ptr(resid if want_resid else None), _ptr(pairs))
+    return pairs, (resid if want_resid else None)
+
+
 def pairs_to_f64(pairs: torch.Tensor) -> torch.Tensor:
     """Unpack (hi, lo) FP32 pairs into the FP64 values they represent."""
     return pairs[:, 0].double() + pairs[:, 1].double()
