@@ -462,6 +462,12 @@ static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t 
     const int nq = (d.H * d.W + kNeqChunk - 1) / kNeqChunk;
     for (int u = 0; u < nq; ++u) b->h_neq.push_back({s, u});
   }
+  // launch order: the units of the large stamps first (eight-wave
+  // workgroups), then the rest; the partial slots stay per stamp
+  std::stable_partition(b->h_neq.begin(), b->h_neq.end(), [&](const Work &w) {
+    return b->h_desc[w.stamp].H * b->h_desc[w.stamp].W >= kNeqBigPix;
+  });
+  for (const Work &w : b->h_neq) b->n_neq_big += b->h_desc[w.stamp].H * b->h_desc[w.stamp].W >= kNeqBigPix;
   b->h_eval_first.push_back((int32_t)b->h_eval.size());
   b->h_pix_first.push_back((int32_t)b->h_pix.size());
   b->h_neq_first.push_back((int32_t)b->h_neq.size());
@@ -1136,6 +1142,8 @@ hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   if (e == hipSuccess) e = put(to.eval, v.eval, v.n_eval);
   if (e == hipSuccess) e = put(to.pix, v.pix, v.n_pix);
   if (e == hipSuccess) e = put(to.neq, v.neq, v.n_neq);
+  v.n_neq_big = 0;
+  for (const Work &w : to.neq) v.n_neq_big += b->h_desc[w.stamp].H * b->h_desc[w.stamp].W >= kNeqBigPix;
   if (e == hipSuccess) e = put(to.rows, v.rows, v.n_rows);
   if (e == hipSuccess) e = put(to.cols, v.cols, v.n_cols);
   if (e == hipSuccess) e = put(to.irows, v.irows, v.n_irows);

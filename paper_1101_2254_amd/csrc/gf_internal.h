@@ -18,7 +18,12 @@ constexpr int kMaxP = kNPC * kMaxComp + 1;
 constexpr int kThreads = 256;          // threads per workgroup for pixel kernels (4 wave64)
 constexpr int kEvalTile = 256;         // padded pixels per eval workgroup (one per thread)
 constexpr int kPixChunk = 4096;        // pixels per chi^2 workgroup (16 per thread)
-constexpr int kNeqChunk = 1024;        // pixels per normal-equation workgroup (256 per wave)
+constexpr int kNeqChunk = 1024;        // pixels per normal-equation unit (one partial Gram matrix)
+// Stamps of at least this many pixels have each unit summed by an
+// eight-wave Gram workgroup (128 pixels per wave), smaller stamps by a
+// four-wave one (256 per wave).  The split is a property of the stamp, so a
+// stamp's partials do not depend on the batch.
+constexpr int kNeqBigPix = 1 << 17;
 // Complex values in the FFT LDS buffer of a workgroup (T*L <= this).  The
 // kernels built for plan radices up to 18 or up to 24 need fewer registers;
 // with their smaller buffers five workgroups fit on a CU instead of four
@@ -109,7 +114,7 @@ constexpr int f2d_bucket(int cls) {
 // "the full list".
 struct WorkView {
   const Work *eval = nullptr, *pix = nullptr, *neq = nullptr;
-  int n_eval = 0, n_pix = 0, n_neq = 0;
+  int n_eval = 0, n_pix = 0, n_neq = 0, n_neq_big = 0;   // neq: the large stamps' units first
   const Work *rows = nullptr, *cols = nullptr, *irows = nullptr;
   int n_rows = 0, n_cols = 0, n_irows = 0;
   const Work *rows_n = nullptr, *cols_n = nullptr, *irows_n = nullptr;
@@ -336,7 +341,8 @@ struct gf_batch {
   int64_t n_pix = 0, n_pad = 0, n_psf = 0, n_par = 0, n_img = 0, n_jac = 0;
   int max_nc = 0, max_P = 0;
   // work lists
-  std::vector<gf::Work> h_eval, h_pix, h_neq;
+  std::vector<gf::Work> h_eval, h_pix, h_neq;   // h_neq: the units of stamps >= kNeqBigPix first
+  int n_neq_big = 0;
   gf::Work *d_eval = nullptr, *d_pix = nullptr, *d_neq = nullptr;
   std::vector<int32_t> h_pix_first, h_neq_first, h_eval_first;   // first unit index per stamp (+ total)
   int32_t *d_pix_first = nullptr, *d_neq_first = nullptr, *d_eval_first = nullptr;

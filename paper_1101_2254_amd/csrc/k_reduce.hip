@@ -310,20 +310,24 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kGramThreads = 256;
-
 // With C2 the workgroup also reduces its chunk's chi^2 of the same model
 // (compensated FP32, the residual lanes only) into c2part at the unit's slot.
-template <int NC, bool C2>
-__global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
-                                                   const float *__restrict__ jc, int nchan,
-                                                   const double *__restrict__ theta, const float *__restrict__ data,
-                                                   const float *__restrict__ weight, float *__restrict__ part,
-                                                   const int32_t *__restrict__ first, const int *__restrict__ mask,
-                                                   int vec_ok, float2 *__restrict__ c2part) {
+// T threads per workgroup, one unit each: 256 (four waves of 256 pixels)
+// for stamps below kNeqBigPix, 512 (eight waves of 128 pixels) above, where
+// a single large stamp has too few units to fill the device with four-wave
+// workgroups.
+template <int NC, bool C2, int T>
+__global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
+                                            const float *__restrict__ jc, int nchan,
+                                            const double *__restrict__ theta, const float *__restrict__ data,
+                                            const float *__restrict__ weight, float *__restrict__ part,
+                                            const int32_t *__restrict__ first, const int *__restrict__ mask,
+                                            int vec_ok, float2 *__restrict__ c2part) {
   constexpr int P = kNPC * NC + 1;
+  constexpr int NW = T / 64;
   static_assert(P + 1 <= 16, "augmented Jacobian must fit 16 columns");
-  __shared__ float red[kGramThreads / 64][256];
+  static_assert(T >= 256 && kNeqChunk % (16 * NW) == 0, "whole 16-pixel groups per wave, 256 reducing threads");
+  __shared__ float red[NW][256];
   const Work wk = work[blockIdx.x];
   const int s = wk.stamp;
   if (mask && !mask[s]) return;
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
   const float sky = (float)theta[d.par + kNPC * NC];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
-  constexpr int per_wave = kNeqChunk / (kGramThreads / 64);
+  constexpr int per_wave = kNeqChunk / NW;
   const int base = wk.unit * kNeqChunk + wv * per_wave;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   F2 c2acc = {0.f, 0.f};
@@ -414,7 +418,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
   // lane (col = lane % 16, rows 4*(lane/16) .. +3) holds G[row][col]
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wv][(4 * kk + r) * 16 + i] = acc[r];
-  __shared__ F2 c2w[kGramThreads / 64];
+  __shared__ F2 c2w[NW];
   if constexpr (C2) {
     c2acc = wave_sum(c2acc);
     if (lane == 0) c2w[wv] = c2acc;
@@ -424,14 +428,14 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const StampDesc *__restri
     const int e = threadIdx.x;  // 256 entries, one per thread
     float v = 0.0f;
 #pragma unroll
-    for (int ww = 0; ww < kGramThreads / 64; ++ww) v += red[ww][e];
+    for (int ww = 0; ww < NW; ++ww) v += red[ww][e];
     part[(int64_t)(first[s] + wk.unit) * 256 + e] = v;   // the unit's own slot
   }
   if constexpr (C2) {
     if (threadIdx.x == 0) {
       F2 t = c2w[0];
 #pragma unroll
-      for (int ww = 1; ww < kGramThreads / 64; ++ww) t = f2_add(t, c2w[ww]);
+      for (int ww = 1; ww < NW; ++ww) t = f2_add(t, c2w[ww]);
       c2part[first[s] + wk.unit] = make_float2(t.hi, t.lo);
     }
   }
@@ -443,8 +447,9 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
   (void)nacc_stride;
   const bool view = v && v->neq;
   const Work *lst = view ? v->neq : b->d_neq;
-  dim3 grid((unsigned)(view ? v->n_neq : (int)b->h_neq.size())), blk(kGramThreads);
-  if (grid.x == 0) return hipSuccess;
+  const int n = view ? v->n_neq : (int)b->h_neq.size();
+  const int nbig = view ? v->n_neq_big : b->n_neq_big;   // the large stamps' units come first
+  if (n == 0) return hipSuccess;
   ProfScope ps(st, "k_gram");
   bool has1 = false, has2 = false;
   for (const auto &d : b->h_desc) {
@@ -452,15 +457,22 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
     has2 |= d.ncomp == 2;
   }
   const int vec_ok = aligned16(jc) && aligned16(data) && aligned16(weight);
-#define GF_GRAM(NC, C2)                                                                                         \
-  hipLaunchKernelGGL((k_gram<NC, C2>), grid, blk, 0, st, b->d_desc, lst, jc, nchan, theta, data, weight, part, \
-                     b->d_neq_first, mask, vec_ok, c2part)
-  if (has1) {
-    if (c2part) GF_GRAM(1, true); else GF_GRAM(1, false);
-  }
-  if (has2) {
-    if (c2part) GF_GRAM(2, true); else GF_GRAM(2, false);
-  }
+#define GF_GRAM(NC, C2, T, L, G)                                                                                \
+  hipLaunchKernelGGL((k_gram<NC, C2, T>), dim3((unsigned)(G)), dim3(T), 0, st, b->d_desc, L, jc, nchan, theta,   \
+                     data, weight, part, b->d_neq_first, mask, vec_ok, c2part)
+#define GF_GRAM_NC(NC)                                                               \
+  do {                                                                               \
+    if (nbig > 0) {                                                                  \
+      if (c2part) GF_GRAM(NC, true, 512, lst, nbig); else GF_GRAM(NC, false, 512, lst, nbig); \
+    }                                                                                \
+    if (n > nbig) {                                                                  \
+      if (c2part) GF_GRAM(NC, true, 256, lst + nbig, n - nbig);                      \
+      else GF_GRAM(NC, false, 256, lst + nbig, n - nbig);                            \
+    }                                                                                \
+  } while (0)
+  if (has1) GF_GRAM_NC(1);
+  if (has2) GF_GRAM_NC(2);
+#undef GF_GRAM_NC
 #undef GF_GRAM
   return hipGetLastError();
 }
