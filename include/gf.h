@@ -586,6 +586,70 @@ gf_status gf_line_chi2(gf_ctx *ctx, const gf_line_batch *lb, const float *lsf, c
 gf_status gf_line_fit_lm(gf_ctx *ctx, const gf_line_batch *lb, const float *lsf, const float *data,
                          const float *weight, double *theta_io, const gf_lm_opts *opts, gf_lm_result *res);
 
+/* ---------------------------------------------------- data-cube fitting */
+
+/* The same three steps in three dimensions (paper Sec. 5: cube fitting as a
+ * problem for the method once the dimensionality may change; the model is a
+ * reading).  Cube s holds Nc spectral channels of an H_s x W_s image,
+ * channel-major [c][y][x]; channel c is centred at v = c (velocities in
+ * channel units), spaxel (i, j) at (x = j, y = i).  Its model is one Sersic
+ * component (the image model's profile and geometry) whose light carries a
+ * Gaussian emission line of width sigma_v centred at the line-of-sight
+ * velocity of a thin rotating disk with the component's geometry,
+ *   V(x, y) = v0 + vproj (2/pi) atan(R/rt) x'/R   (V = v0 at R = 0),
+ * x' the offset along the major axis, R the elliptical radius, vproj the
+ * projected rotation amplitude and rt the turnover radius.  A voxel is the
+ * mean over S x S spatial and Sv spectral midpoint sub-samples of
+ * I(x, y) exp(-(v - V)^2 / (2 sigma_v^2)) on a grid padded by (K-1)/2
+ * spaxels and (Kl-1)/2 channels, convolved with the K x K PSF in every
+ * channel and the Kl-tap line-spread function along every spaxel (valid
+ * part, as gf_convolve_psf and gf_line_model), plus a constant continuum.
+ * Parameters per cube (GF_CUBE_NPAR, FP64):
+ *   [xc, yc, Ie, Re, n, q, phi, continuum, v0, vproj, rt, sigma_v].
+ * chi^2 = sum over voxels of w (d - m)^2.
+ *
+ * All cubes of a batch share Nc (1..GF_CUBE_MAX_CHAN) and the odd LSF length
+ * Kl (1..GF_LINE_MAX_K); H, W and the odd PSF side K vary per cube (H + K - 1
+ * and W + K - 1 at most GF_MAX_FFT).  Flat layouts: cube s's data, weight
+ * and model occupy voxels [vox_off[s], vox_off[s+1]) (Nc H W each), its PSF
+ * taps [psf_off[s], psf_off[s+1]), its LSF taps [lsf_off[s], lsf_off[s+1]),
+ * its parameters [par_off[s], par_off[s+1]).  The batch owns the device
+ * workspace its calls need (grown on first use). */
+#define GF_CUBE_NPAR 12
+#define GF_CUBE_MAX_CHAN 1024
+typedef struct gf_cube_batch gf_cube_batch;
+
+gf_status gf_cube_batch_create(gf_ctx *ctx, int n, const int32_t *H, const int32_t *W, const int32_t *K, int n_chan,
+                               int K_lsf, gf_cube_batch **out);
+void gf_cube_batch_destroy(gf_cube_batch *cb);
+/* Host arrays of n + 1 offsets each (any may be NULL). */
+gf_status gf_cube_batch_offsets(const gf_cube_batch *cb, int64_t *vox_off, int64_t *psf_off, int64_t *lsf_off,
+                                int64_t *par_off);
+/* Kernels of every cube: psf device [psf_off[n]], lsf device [lsf_off[n]]
+ * (both copied into the batch); conv_mode as gf_psf_prepare for the spatial
+ * convolution.  Must precede the calls below.  gf_cube_batch_destroy frees
+ * the batch's device memory: call it once the work on it has finished. */
+gf_status gf_cube_set_kernels(gf_ctx *ctx, gf_cube_batch *cb, const float *psf, const float *lsf, int conv_mode);
+/* Steps 1-2 plus continuum: out (device [vox_off[n]]) = the model cubes.
+ * theta: device [par_off[n]] FP64; oversample S 1..8, oversample_v Sv 1..8. */
+gf_status gf_cube_model(gf_ctx *ctx, gf_cube_batch *cb, const double *theta, int oversample, int oversample_v,
+                        float *out);
+/* Steps 1-3: chi2 (device [2 n]) compensated (hi, lo) FP32 pairs as in
+ * gf_chi2; data, weight: device [vox_off[n]]. */
+gf_status gf_cube_chi2(gf_ctx *ctx, gf_cube_batch *cb, const double *theta, int oversample, int oversample_v,
+                       const float *data, const float *weight, float *chi2);
+/* d model / d theta: out (device [GF_CUBE_NPAR * vox_off[n]]); cube s holds
+ * GF_CUBE_NPAR cubes of Nc H W values from GF_CUBE_NPAR * vox_off[s], in
+ * parameter order (the continuum's all ones). */
+gf_status gf_cube_jacobian(gf_ctx *ctx, gf_cube_batch *cb, const double *theta, int oversample, int oversample_v,
+                           float *out);
+/* Levenberg-Marquardt over every cube with the rule of gf_fit_lm (opts:
+ * max_iter, oversample, lambda0/up/down/max, ftol, xtol, lo, hi, free_mask,
+ * poll_every, start as there; use_graph and speculate are unused).
+ * theta_io: device [par_off[n]] FP64; res: device [n]. */
+gf_status gf_cube_fit_lm(gf_ctx *ctx, gf_cube_batch *cb, const float *data, const float *weight, double *theta_io,
+                         const gf_lm_opts *opts, int oversample_v, gf_lm_result *res);
+
 /* Library version string. */
 const char *gf_version(void);
 

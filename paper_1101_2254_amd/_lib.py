@@ -21,6 +21,8 @@ GF_MAX_COMP = 4
 GF_CONV_AUTO, GF_CONV_FFT, GF_CONV_DIRECT, GF_CONV_FFT_MULTIPASS, GF_CONV_FFT_FUSED = 0, 1, 2, 3, 4
 GF_FFT_FUSED_MAX = 192
 GF_JAC_FULL, GF_JAC_ADJOINT = 0, 1
+GF_CUBE_NPAR = 12
+GF_CUBE_MAX_CHAN = 1024
 
 # Every symbol that include/gf.h declares.
 EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_synchronize", "gf_batch_create",
@@ -34,7 +36,9 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_cnn_encode", "gf_cnn_decode", "gf_philox", "gf_normal_noise", "gf_draw_prior", "gf_probe", "gf_profile_start",
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_line_batch_create", "gf_line_batch_destroy",
            "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version",
-           "gf_chi2_noalloc", "gf_autotune", "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set")
+           "gf_chi2_noalloc", "gf_autotune", "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set",
+           "gf_cube_batch_create", "gf_cube_batch_destroy", "gf_cube_batch_offsets", "gf_cube_set_kernels",
+           "gf_cube_model", "gf_cube_chi2", "gf_cube_jacobian", "gf_cube_fit_lm")
 
 
 class GfLmOpts(ctypes.Structure):
@@ -148,6 +152,14 @@ def lib() -> ctypes.CDLL:
         "gf_line_model": (i32, [vp, vp, vp, vp, i32, vp]),
         "gf_line_chi2": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
         "gf_line_fit_lm": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), vp]),
+        "gf_cube_batch_create": (i32, [vp, i32, vp, vp, vp, i32, i32, pvp]),
+        "gf_cube_batch_destroy": (None, [vp]),
+        "gf_cube_batch_offsets": (i32, [vp, vp, vp, vp, vp]),
+        "gf_cube_set_kernels": (i32, [vp, vp, vp, vp, i32]),
+        "gf_cube_model": (i32, [vp, vp, vp, i32, i32, vp]),
+        "gf_cube_chi2": (i32, [vp, vp, vp, i32, i32, vp, vp, vp]),
+        "gf_cube_jacobian": (i32, [vp, vp, vp, i32, i32, vp]),
+        "gf_cube_fit_lm": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(GfLmOpts), i32, vp]),
         "gf_version": (ctypes.c_char_p, []),
         "gf_tune_form_get": (i32, [vp, i32]),
         "gf_tune_form_set": (i32, [vp, i32, i32]),
@@ -333,6 +345,49 @@ def gf_line_chi2(ctx, lb, lsf_ptr, theta_ptr, oversample, data_ptr, weight_ptr, 
 
 def gf_line_fit_lm(ctx, lb, lsf_ptr, data_ptr, weight_ptr, theta_ptr, opts: GfLmOpts, res_ptr):
     check(lib().gf_line_fit_lm(ctx, lb, lsf_ptr, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), res_ptr), ctx)
+
+
+def gf_cube_batch_create(ctx: int, H, W, K, n_chan: int, k_lsf: int) -> int:
+    import numpy as np
+    n = len(H)
+    a = [np.ascontiguousarray(v, dtype=np.int32) for v in (H, W, K)]
+    out = ctypes.c_void_p()
+    check(lib().gf_cube_batch_create(ctx, n, *[x.ctypes.data for x in a], int(n_chan), int(k_lsf),
+                                     ctypes.byref(out)), ctx)
+    return out.value
+
+
+def gf_cube_batch_destroy(cb: int) -> None:
+    lib().gf_cube_batch_destroy(cb)
+
+
+def gf_cube_batch_offsets(cb: int, n: int) -> dict:
+    import numpy as np
+    keys = ("vox", "psf", "lsf", "par")
+    arrs = {k: np.zeros(n + 1, np.int64) for k in keys}
+    check(lib().gf_cube_batch_offsets(cb, *[arrs[k].ctypes.data for k in keys]))
+    return arrs
+
+
+def gf_cube_set_kernels(ctx, cb, psf_ptr, lsf_ptr, mode):
+    check(lib().gf_cube_set_kernels(ctx, cb, psf_ptr, lsf_ptr, mode), ctx)
+
+
+def gf_cube_model(ctx, cb, theta_ptr, oversample, oversample_v, out_ptr):
+    check(lib().gf_cube_model(ctx, cb, theta_ptr, oversample, oversample_v, out_ptr), ctx)
+
+
+def gf_cube_chi2(ctx, cb, theta_ptr, oversample, oversample_v, data_ptr, weight_ptr, chi2_ptr):
+    check(lib().gf_cube_chi2(ctx, cb, theta_ptr, oversample, oversample_v, data_ptr, weight_ptr, chi2_ptr), ctx)
+
+
+def gf_cube_jacobian(ctx, cb, theta_ptr, oversample, oversample_v, out_ptr):
+    check(lib().gf_cube_jacobian(ctx, cb, theta_ptr, oversample, oversample_v, out_ptr), ctx)
+
+
+def gf_cube_fit_lm(ctx, cb, data_ptr, weight_ptr, theta_ptr, opts: GfLmOpts, oversample_v, res_ptr):
+    check(lib().gf_cube_fit_lm(ctx, cb, data_ptr, weight_ptr, theta_ptr, ctypes.byref(opts), oversample_v, res_ptr),
+          ctx)
 
 
 def gf_profile_start(ctx):

@@ -39,14 +39,14 @@ hipError_t launch_adjoint_final(hipStream_t, const gf_batch *, const int32_t *, 
 hipError_t launch_jac_assemble(hipStream_t, const gf_batch *, const float *, int, float *);
 hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *);
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float *, int, int, const int *, const WorkView *, float2 *);
+                            const float *, float *, int, int, const int *, const WorkView *, float2 *, int px = 0);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
                           int *);
 hipError_t launch_lm_start(hipStream_t, const gf_batch *, const double *, double *, const double *, const double *,
                            double *, int, const float4 *, CompC *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *,
-                           const WorkView *);
+                           const WorkView *, int px = 0);
 hipError_t launch_chi2_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, const void *, bool,
                               const float *, const float *, float2 *, const int *, const WorkView *);
 hipError_t launch_pair_final(hipStream_t, int, const int32_t *, const float2 *, float2 *, const int *);
@@ -358,8 +358,12 @@ gf_status gf_synchronize(gf_ctx *c) {
 }
 
 // ------------------------------------------------------------------ batches
+// flat_P > 0: stamps that are flat arrays of H*W values with flat_P
+// parameters each (a data cube's voxels for chi^2, the normal equations and
+// the LM state); no convolution runs on them, so the FFT size limit does not
+// apply.
 static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t *W, const int32_t *K,
-                              const int32_t *nc, int shared, const int32_t *group, gf_batch **out) {
+                              const int32_t *nc, int shared, const int32_t *group, gf_batch **out, int flat_P = 0) {
   if (!c || !out || !H || !W || !K || !nc || n <= 0) return fail(c, GF_EINVAL, "gf_batch_create: bad argument");
   *out = nullptr;
   // groups: every stamp's observation and PSF, or one per group
@@ -400,8 +404,10 @@ static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t 
     gp += (int64_t)K[f] * K[f];
   }
   for (int s = 0; s < n; ++s) {
+    const bool fft_ok = flat_P > 0 ? K[s] == 1 && nc[s] == 1 && (int64_t)H[s] * W[s] <= (1LL << 30)
+                                   : H[s] + K[s] - 1 <= GF_MAX_FFT && W[s] + K[s] - 1 <= GF_MAX_FFT;
     if (H[s] <= 0 || W[s] <= 0 || K[s] <= 0 || (K[s] % 2) == 0 || K[s] > GF_MAX_K || nc[s] < 1 ||
-        nc[s] > GF_MAX_COMP || H[s] + K[s] - 1 > GF_MAX_FFT || W[s] + K[s] - 1 > GF_MAX_FFT) {
+        nc[s] > GF_MAX_COMP || !fft_ok) {
       delete b;
       return fail(c, GF_ESHAPE, "gf_batch_create: unsupported shape for stamp " + std::to_string(s));
     }
@@ -416,7 +422,7 @@ static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t 
     d.ncomp = nc[s];
     d.Mh = H[s] + K[s] - 1;
     d.Mw = W[s] + K[s] - 1;
-    d.P = padded_P(nc[s]);
+    d.P = flat_P > 0 ? flat_P : padded_P(nc[s]);
     d.pad0 = 0;
     d.pix = pix;
     d.pad = pad;
@@ -1661,3 +1667,11 @@ gf_status gf_profile_get(gf_ctx *c, int i, char *name, int name_cap, int64_t *la
 }
 
 }  // extern "C"
+
+namespace gf {
+// A batch of flat stamps (H*W values, P parameters each) for the cube path.
+gf_status batch_create_flat(gf_ctx *c, int n, const int32_t *H, const int32_t *W, int P, gf_batch **out) {
+  std::vector<int32_t> ones(n, 1);
+  return create_batch(c, n, H, W, ones.data(), ones.data(), 0, nullptr, out, P);
+}
+}  // namespace gf

@@ -24,6 +24,8 @@ constexpr int kNeqChunk = 1024;        // pixels per normal-equation unit (one p
 // four-wave one (256 per wave).  The split is a property of the stamp, so a
 // stamp's partials do not depend on the batch.
 constexpr int kNeqBigPix = 1 << 17;
+// Parameters of a data cube after the continuum (v0, vproj, rt, sigma_v).
+constexpr int kCubePX = 4;
 // Complex values in the FFT LDS buffer of a workgroup (T*L <= this).  The
 // kernels built for plan radices up to 18 or up to 24 need fewer registers;
 // with their smaller buffers five workgroups fit on a CU instead of four
@@ -129,6 +131,16 @@ struct WorkView {
   // f2d[f2d_first[b] .. f2d_first[b + 1]) (unit = bucket)
   const Work *f2d = nullptr;
   int f2d_first[kF2dBuckets + 1] = {};
+};
+
+// One data cube: its spatial geometry and offsets (the spectral length Nc
+// and LSF length Kl are those of the batch).
+struct CubeDesc {
+  int32_t H, W, K, Mh, Mw, pad0;
+  int64_t pad;   // spatial padded offset: sum of Mh*Mw over the earlier cubes
+  int64_t pix;   // spatial offset: sum of H*W
+  int64_t par;   // parameter offset (GF_CUBE_NPAR per cube)
+  int64_t lsf;   // LSF tap offset
 };
 
 // Per-component constants of the evaluation kernels (computed per workgroup).

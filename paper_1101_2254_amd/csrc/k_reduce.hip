@@ -315,15 +315,18 @@ __device__ __forceinline__ void wave_sync() {
 // T threads per workgroup, one unit each: 256 (four waves of 256 pixels)
 // for stamps below kNeqBigPix, 512 (eight waves of 128 pixels) above, where
 // a single large stamp has too few units to fill the device with four-wave
-// workgroups.
-template <int NC, bool C2, int T>
+// workgroups.  PX parameters follow the sky (the kinematic parameters of a
+// cube): column SK = 7 NC is the sky's constant 1, columns above it read
+// channel column - 1, column P the residual.
+template <int NC, bool C2, int T, int PX = 0>
 __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, const Work *__restrict__ work,
                                             const float *__restrict__ jc, int nchan,
                                             const double *__restrict__ theta, const float *__restrict__ data,
                                             const float *__restrict__ weight, float *__restrict__ part,
                                             const int32_t *__restrict__ first, const int *__restrict__ mask,
                                             int vec_ok, float2 *__restrict__ c2part) {
-  constexpr int P = kNPC * NC + 1;
+  constexpr int SK = kNPC * NC;
+  constexpr int P = SK + 1 + PX;
   constexpr int NW = T / 64;
   static_assert(P + 1 <= 16, "augmented Jacobian must fit 16 columns");
   static_assert(T >= 256 && kNeqChunk % (16 * NW) == 0, "whole 16-pixel groups per wave, 256 reducing threads");
@@ -338,14 +341,16 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
   float ie[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) ie[k] = (float)theta[d.par + kNPC * k + 2];
-  const float sky = (float)theta[d.par + kNPC * NC];
+  const float sky = (float)theta[d.par + SK];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
   constexpr int per_wave = kNeqChunk / NW;
   const int base = wk.unit * kNeqChunk + wv * per_wave;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   F2 c2acc = {0.f, 0.f};
-  const int ich = i < P - 1 ? i : 0;  // channel read by this lane (clamped for the sky / residual lanes)
+  // channel read by this lane (clamped for the sky / residual lanes)
+  const bool jl = i < SK || (i > SK && i < P);
+  const int ich = i < SK ? i : (i > SK && i < P) ? i - 1 : 0;
   if (vec_ok && (((int64_t)d.pix * nchan | npix | d.img) & 3) == 0 && base + per_wave <= npix) {
     // the wave's pixels all inside the stamp, 16-byte aligned (uniform over
     // the wave): each lane loads its four consecutive pixels per operand
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
           m = fmaf(ie[c], iq[q], m);
         }
         rq[q] = dq[q] - m;
-        const float x = (i < P - 1) ? jq[q] : (i == P - 1) ? 1.0f : (i == P) ? rq[q] : 0.0f;
+        const float x = jl ? jq[q] : (i == SK) ? 1.0f : (i == P) ? rq[q] : 0.0f;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
       }
       if constexpr (C2) {
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
         for (int c = 0; c < NC; ++c) m = fmaf(ie[c], J[(int64_t)(kNPC * c + 2) * npix + pc], m);
         rq[q] = ok ? dv - m : 0.0f;
         wq[q] = ok ? wt : 0.0f;
-        float x = (i < P - 1) ? jv : (i == P - 1) ? 1.0f : (i == P) ? dv - m : 0.0f;
+        float x = jl ? jv : (i == SK) ? 1.0f : (i == P) ? dv - m : 0.0f;
         x = ok ? x : 0.0f;
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
       }
@@ -443,7 +448,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
 
 hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, const double *theta,
                             const float *data, const float *weight, float *part, int nacc_stride, int nchan,
-                            const int *mask, const WorkView *v, float2 *c2part) {
+                            const int *mask, const WorkView *v, float2 *c2part, int px) {
   (void)nacc_stride;
   const bool view = v && v->neq;
   const Work *lst = view ? v->neq : b->d_neq;
@@ -460,6 +465,17 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
 #define GF_GRAM(NC, C2, T, L, G)                                                                                \
   hipLaunchKernelGGL((k_gram<NC, C2, T>), dim3((unsigned)(G)), dim3(T), 0, st, b->d_desc, L, jc, nchan, theta,   \
                      data, weight, part, b->d_neq_first, mask, vec_ok, c2part)
+  if (px == kCubePX) {   // one-component stamps with the cube's kinematic parameters, no chi^2 output
+    if (nbig > 0)
+      hipLaunchKernelGGL((k_gram<1, false, 512, kCubePX>), dim3((unsigned)nbig), dim3(512), 0, st, b->d_desc, lst,
+                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, vec_ok, (float2 *)nullptr);
+    if (n > nbig)
+      hipLaunchKernelGGL((k_gram<1, false, 256, kCubePX>), dim3((unsigned)(n - nbig)), dim3(256), 0, st, b->d_desc,
+                         lst + nbig, jc, nchan, theta, data, weight, part, b->d_neq_first, mask, vec_ok,
+                         (float2 *)nullptr);
+    return hipGetLastError();
+  }
+  if (px != 0) return hipErrorInvalidValue;
 #define GF_GRAM_NC(NC)                                                               \
   do {                                                                               \
     if (nbig > 0) {                                                                  \
@@ -559,7 +575,7 @@ __device__ __forceinline__ double bcast(double v, int l) {
 constexpr int kSolveThreads = 512;
 constexpr int kSolveSlices = kSolveThreads / 64;
 
-template <int NC>
+template <int NC, int PX = 0>
 __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__restrict__ desc,
                                                        const int32_t *__restrict__ neq_first,
                                                        const float *__restrict__ part, LMParams prm,
@@ -568,7 +584,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
                                                        int *__restrict__ mjac, int *__restrict__ mtrial,
                                                        int *__restrict__ active_count,
                                                        const Work *__restrict__ list) {
-  constexpr int P = kNPC * NC + 1;
+  constexpr int P = kNPC * NC + 1 + PX;
+  static_assert(P <= kMaxP, "parameters of a stamp");
   __shared__ double Gp[kSolveSlices][256];
   __shared__ double Gs[256];
   __shared__ double As[P * P];
@@ -767,7 +784,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_lm_solve(const StampDesc *__r
     theta_t[d.par + tid] = v;
     tt_s[tid] = v;
   }
-  if (prm.cc_t) {
+  if (PX == 0 && prm.cc_t) {
     wave_sync();
     if (ok && tid < NC)
       comp_setup<double>(tt_s + kNPC * tid, prm.bn, prm.oversample, prm.cc_t[(int64_t)s * kMaxComp + tid]);
@@ -789,7 +806,7 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
   LMState S = st[s];
   if (!S.active) return;
   const StampDesc d = desc[s];
-  const int P = kNPC * d.ncomp + 1;
+  const int P = d.P;
   const int lane = threadIdx.x;
   double c2 = 0.0;
   double stp = 0.0;
@@ -941,7 +958,7 @@ hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, con
 
 hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part, const gf_lm_opts *o, LMState *S,
                            double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial, int *cnt,
-                           CompC *cc_th, CompC *cc_t, const float4 *bn, const WorkView *v) {
+                           CompC *cc_th, CompC *cc_t, const float4 *bn, const WorkView *v, int px) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
                o->free_mask, cc_t, cc_th, bn, o->oversample};
   ProfScope ps(st, "k_lm_solve");
@@ -955,6 +972,12 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
   const Work *list = v && v->stamps ? v->stamps : nullptr;
   const unsigned grid = list ? (unsigned)v->n_stamps : (unsigned)b->n;
   if (grid == 0) return hipSuccess;
+  if (px == kCubePX) {
+    hipLaunchKernelGGL((k_lm_solve<1, kCubePX>), dim3(grid), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first,
+                       part, prm, S, Ag, theta, theta_t, mjac, mtrial, cnt, list);
+    return hipGetLastError();
+  }
+  if (px != 0) return hipErrorInvalidValue;
   if (has1)
     hipLaunchKernelGGL((k_lm_solve<1>), dim3(grid), dim3(kSolveThreads), 0, st, b->d_desc, b->d_neq_first, part,
                        prm, S, Ag, theta, theta_t, mjac, mtrial, cnt, list);

@@ -373,6 +373,97 @@ def line_fit_lm(ctx: Context, lb: LineBatch, lsf: torch.Tensor, data: torch.Tens
     return theta, lm_info(res)
 
 
+class CubeBatch:
+    """Data cubes (``gf_cube_batch``): n cubes of Nc channels of an H x W
+    image with a K x K PSF each, one LSF length for the batch.  Parameters
+    per cube ``[xc, yc, Ie, Re, n, q, phi, continuum, v0, vproj, rt,
+    sigma_v]`` (FP64); flat offsets in ``offsets['vox'|'psf'|'lsf'|'par']``.
+    ``set_kernels`` must run before the model, chi^2, Jacobian and fit."""
+
+    def __init__(self, ctx: Context, H, W, K, n_chan: int, k_lsf: int):
+        self.ctx = ctx
+        self.n = len(H)
+        self.n_chan, self.k_lsf = int(n_chan), int(k_lsf)
+        self.ptr = L.gf_cube_batch_create(ctx.ptr, H, W, K, n_chan, k_lsf)
+        self.offsets = L.gf_cube_batch_offsets(self.ptr, self.n)
+        self.sizes = {k: int(v[-1]) for k, v in self.offsets.items()}
+
+    def set_kernels(self, psf: torch.Tensor, lsf: torch.Tensor, mode: int = GF_CONV_AUTO):
+        _need(psf, torch.float32, self.sizes["psf"], "psf")
+        _need(lsf, torch.float32, self.sizes["lsf"], "lsf")
+        self.ctx.bind_stream()
+        L.gf_cube_set_kernels(self.ctx.ptr, self.ptr, _ptr(psf), _ptr(lsf), int(mode))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            L.gf_cube_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cube_model(ctx: Context, cb: CubeBatch, theta: torch.Tensor, oversample: int = 5, oversample_v: int = 3,
+               out=None) -> torch.Tensor:
+    """Model cubes (gf_cube_model), flat [n_vox] float32."""
+    _need(theta, torch.float64, cb.sizes["par"], "theta")
+    out = _empty(ctx, cb.sizes["vox"]) if out is None else _need(out, torch.float32, cb.sizes["vox"], "out")
+    ctx.bind_stream()
+    L.gf_cube_model(ctx.ptr, cb.ptr, _ptr(theta), int(oversample), int(oversample_v), _ptr(out))
+    return out
+
+
+def cube_chi2(ctx: Context, cb: CubeBatch, theta: torch.Tensor, data: torch.Tensor, weight: torch.Tensor,
+              oversample: int = 5, oversample_v: int = 3) -> torch.Tensor:
+    """chi^2 (hi, lo) pairs [n, 2] of every cube (gf_cube_chi2)."""
+    _need(theta, torch.float64, cb.sizes["par"], "theta")
+    _need(data, torch.float32, cb.sizes["vox"], "data")
+    _need(weight, torch.float32, cb.sizes["vox"], "weight")
+    out = torch.empty((cb.n, 2), dtype=torch.float32, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_cube_chi2(ctx.ptr, cb.ptr, _ptr(theta), int(oversample), int(oversample_v), _ptr(data), _ptr(weight),
+                   _ptr(out))
+    return out
+
+
+def cube_jacobian(ctx: Context, cb: CubeBatch, theta: torch.Tensor, oversample: int = 5,
+                  oversample_v: int = 3) -> torch.Tensor:
+    """d model / d theta (gf_cube_jacobian), flat [12 n_vox] float32: cube s's
+    12 derivative cubes from 12 * offsets['vox'][s]."""
+    _need(theta, torch.float64, cb.sizes["par"], "theta")
+    out = _empty(ctx, L.GF_CUBE_NPAR * cb.sizes["vox"])
+    ctx.bind_stream()
+    L.gf_cube_jacobian(ctx.ptr, cb.ptr, _ptr(theta), int(oversample), int(oversample_v), _ptr(out))
+    return out
+
+
+def cube_fit_lm(ctx: Context, cb: CubeBatch, data: torch.Tensor, weight: torch.Tensor, theta0: torch.Tensor,
+                oversample_v: int = 3, lo=None, hi=None, free=None, return_device=False, **opts):
+    """Levenberg-Marquardt over every cube (gf_cube_fit_lm).  theta0: float64
+    [n_par] (not modified).  Returns (theta, per-cube results) as fit_lm does."""
+    n_par = cb.sizes["par"]
+    _need(theta0, torch.float64, n_par, "theta0")
+    _need(data, torch.float32, cb.sizes["vox"], "data")
+    _need(weight, torch.float32, cb.sizes["vox"], "weight")
+    o = lm_options(**opts)
+    if lo is not None:
+        o.lo = _ptr(_need(lo, torch.float64, n_par, "lo"))
+    if hi is not None:
+        o.hi = _ptr(_need(hi, torch.float64, n_par, "hi"))
+    if free is not None:
+        o.free_mask = _ptr(_need(free, torch.uint8, n_par, "free"))
+    theta = theta0.clone()
+    res = torch.empty(cb.n * LM_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=ctx.device)
+    ctx.bind_stream()
+    L.gf_cube_fit_lm(ctx.ptr, cb.ptr, _ptr(data), _ptr(weight), _ptr(theta), o, int(oversample_v), _ptr(res))
+    if return_device:
+        return theta, res
+    return theta, lm_info(res)
+
+
 # ------------------------------------------------------------------ autograd
 class Chi2Fn(torch.autograd.Function):
     """chi^2 per stamp (FP64 from the compensated pair) with the adjoint

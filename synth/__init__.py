@@ -323,3 +323,80 @@ def add_noise_1d(model_true: np.ndarray, sigma: float, seed: int):
     d = model_true + sigma * g.standard_normal(model_true.shape)
     w = np.full(model_true.shape, 1.0 / (sigma * sigma))
     return d, w
+
+
+# ------------------------------------------------------------------ data cubes
+CUBE_SIZES = (32, 40, 48, 56, 64)
+
+
+@dataclass
+class Cube:
+    H: int
+    W: int
+    Nc: int
+    psf: np.ndarray
+    lsf: np.ndarray
+    truth: np.ndarray
+    start: np.ndarray
+    noise_sigma: float
+    noise_seed: int
+
+    @property
+    def K(self) -> int:
+        return int(self.psf.shape[0])
+
+    @property
+    def Kl(self) -> int:
+        return int(self.lsf.size)
+
+
+def cube_stamp(g: np.random.Generator, H: int, W: int, Nc: int, lsf: np.ndarray, idx: int, seed: int) -> Cube:
+    """An integral-field cube of a rotating disk galaxy, parameters
+    [xc, yc, Ie, Re, n, q, phi, continuum, v0, vproj, rt, sigma_v]:
+    centre (W/2, H/2) + U[-1, 1], Ie log-U[0.5, 5], Re ~ U[2, min(H, W)/5],
+    n ~ U[0.6, 2.5], q ~ U[0.35, 0.95], phi ~ U[0, pi], continuum U[0, 0.05],
+    v0 ~ Nc/2 + U[-2, 2], vproj ~ U[2, Nc/6], rt ~ U[1, 0.8 Re],
+    sigma_v ~ U[1.2, 3] channels; Gaussian or Moffat PSF with K in
+    {9, 11, 13, 15} and FWHM ~ U[2, 3.5]; noise sigma 0.02.  Start: the
+    profile parameters x (1 + U[-0.1, 0.1]) (the centre moves by U[-0.1, 0.1] Re),
+    v0 + U[-1, 1], vproj, rt and sigma_v x (1 + U[-0.15, 0.15]), continuum
+    + U[-0.01, 0.01]."""
+    re = g.uniform(2.0, min(H, W) / 5.0)
+    t = np.array([W / 2 + g.uniform(-1, 1), H / 2 + g.uniform(-1, 1), math.exp(g.uniform(math.log(0.5), math.log(5.0))),
+                  re, g.uniform(0.6, 2.5), g.uniform(0.35, 0.95), g.uniform(0.0, math.pi), g.uniform(0.0, 0.05),
+                  Nc / 2 + g.uniform(-2, 2), g.uniform(2.0, Nc / 6.0), g.uniform(1.0, 0.8 * re), g.uniform(1.2, 3.0)])
+    K = int(g.choice([9, 11, 13, 15]))
+    fwhm = g.uniform(2.0, 3.5)
+    psf = gaussian_psf(K, fwhm / 2.3548200450309493) if g.uniform() < 0.5 else moffat_psf(K, fwhm, 3.0)
+    s = t.copy()
+    for p in range(7):
+        u = g.uniform(-0.1, 0.1)
+        s[p] = t[p] + u * re if p < 2 else t[p] * (1.0 + u)
+    s[7] = t[7] + g.uniform(-0.01, 0.01)
+    s[8] = t[8] + g.uniform(-1, 1)
+    for p in (9, 10, 11):
+        s[p] = t[p] * (1.0 + g.uniform(-0.15, 0.15))
+    return Cube(H, W, Nc, psf, lsf, t, s, 0.02, seed * 100019 + idx)
+
+
+def cube_batch(n: int, seed: int = SEED_BASE + 7, sizes=CUBE_SIZES, Nc: int = 64, Kl: int = 7,
+               sigma_lsf: float = 1.1):
+    """n cubes of N x N spaxels, N ~ U{sizes}, Nc channels, one Gaussian LSF of
+    Kl taps for the batch."""
+    g = rng(seed)
+    lsf = gaussian_lsf(Kl, sigma_lsf)
+    out = []
+    for i in range(n):
+        N = int(g.choice(sizes))
+        out.append(cube_stamp(g, N, N, Nc, lsf, i, seed))
+    return out
+
+
+def cube_bounds(H: int, W: int, Nc: int):
+    """Box bounds of a cube's parameters: the profile's as ``bounds(1, H, W)``,
+    continuum free, v0 in [0, Nc - 1], vproj free, rt >= 0.1,
+    sigma_v in [0.3, Nc / 4]."""
+    lo, hi = bounds(1, H, W)
+    lo = np.r_[lo, 0.0, -1e30, 0.1, 0.3]
+    hi = np.r_[hi, Nc - 1.0, 1e30, 1e30, Nc / 4.0]
+    return lo, hi
