@@ -19,8 +19,11 @@ timing and roofline entry.
             parameters; one step = one whole fit; value = fits/s, mpix_per_s
             counts the evaluation passes the fit ran.
   c1        one 64 x 64 stamp, 8 parameters; latency: ms per whole fit.
+  cube      256 integral-field cubes (32..64 spaxels square, 64 channels) of
+            rotating disk galaxies, 12-parameter fits by one gf_cube_fit_lm
+            call; value = fits/s, mvox_per_s counts the evaluation passes.
 
-`--workload c3|c4|c2|c1|c5|lines` runs one workload alone (its line has the
+`--workload c3|c4|c2|c1|c5|lines|cube` runs one workload alone (its line has the
 same layout as the headline).  `--steps` and `--warmup` apply to the headline
 (or to the one workload); the nested workloads use their own defaults.
 
@@ -75,7 +78,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["suite", "c1", "c2", "c3", "c4", "c5", "lines"], default="suite")
+    ap.add_argument("--workload", choices=["suite", "c1", "c2", "c3", "c4", "c5", "lines", "cube"], default="suite")
     ap.add_argument("--train-stamps", type=int, default=200_000, help="C5: rendered training stamps")
     ap.add_argument("--epochs", type=int, default=4, help="C5: training epochs")
     ap.add_argument("--mcmc-steps", type=int, default=2000, help="C4: Metropolis steps of the chain run")
@@ -695,6 +698,106 @@ def run_lines(args, torch, ops, synth, peaks, steps=None, warmup=None):
     return result, dict(spectra=spectra, info=info, data=d, weight=w)
 
 
+# Algorithmic FP32 operations per (spatial sub-sample, spectral sub-sample,
+# padded channel) of the cube kernels (an FMA counts two, exp2 one): the model
+# 6 (offset, square, scale, exp2, FMA), the 11 derivative channels 37.
+CUBE_EVAL_FLOP, CUBE_JAC_FLOP = 6, 37
+
+
+def run_cube(args, torch, ops, synth, peaks, steps=None, warmup=None):
+    """256 integral-field cubes (32..64 spaxels square, 64 channels, PSF 9..15
+    px, 7-tap LSF) of rotating disk galaxies fitted by one gf_cube_fit_lm call
+    to chi^2 rel tol 1e-5 (S = 5, Sv = 3)."""
+    dev = torch.device("cuda", 0)
+    cubes = synth.cube_batch(256)
+    n, Nc, Kl = len(cubes), cubes[0].Nc, cubes[0].Kl
+    S, Sv = 5, 3
+    ctx = ops.Context(0, autotune_cache=TUNE_FILE)
+    cb = ops.CubeBatch(ctx, [c.H for c in cubes], [c.W for c in cubes], [c.K for c in cubes], Nc, Kl)
+    cb.set_kernels(torch.from_numpy(np.concatenate([c.psf.astype(np.float32).ravel() for c in cubes])).to(dev),
+                   torch.from_numpy(np.concatenate([c.lsf.astype(np.float32) for c in cubes])).to(dev))
+    truth = torch.from_numpy(np.concatenate([c.truth for c in cubes])).to(dev)
+    m = ops.cube_model(ctx, cb, truth, S, Sv).cpu().numpy().astype(np.float64)
+    off = cb.offsets["vox"]
+    d = np.empty_like(m)
+    w = np.empty_like(m)
+    for i, c in enumerate(cubes):
+        sl = slice(off[i], off[i + 1])
+        d[sl], w[sl] = synth.add_gaussian_noise(m[sl], c.noise_sigma, c.noise_seed)
+    data = torch.from_numpy(d.astype(np.float32)).to(dev)
+    weight = torch.from_numpy(w.astype(np.float32)).to(dev)
+    lo = torch.from_numpy(np.concatenate([synth.cube_bounds(c.H, c.W, Nc)[0] for c in cubes])).to(dev)
+    hi = torch.from_numpy(np.concatenate([synth.cube_bounds(c.H, c.W, Nc)[1] for c in cubes])).to(dev)
+    start = torch.from_numpy(np.concatenate([c.start for c in cubes])).to(dev)
+
+    def step(**kw):
+        o = dict(ftol=1e-5, max_iter=100, oversample=S)
+        o.update(kw)
+        return ops.cube_fit_lm(ctx, cb, data, weight, start, Sv, lo=lo, hi=hi, return_device=True, **o)
+
+    K_ = steps if steps is not None else 5
+    W = warmup if warmup is not None else 1
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K_):
+        th, res = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / K_ * 1e3
+    info = ops.lm_info(res)
+    # the first iteration kernel by kernel (every cube active): start model,
+    # Jacobian, trial model
+    prof, _ = profile(ctx, lambda: step(max_iter=1))
+    Mc = Nc + Kl - 1
+    samples = sum((c.H + c.K - 1) * (c.W + c.K - 1) for c in cubes) * S * S * Mc * Sv
+    lsf_bytes = sum((c.H + c.K - 1) * (c.W + c.K - 1) for c in cubes) * (Mc + Nc) * 4
+    table = {"k_cube_jac": ("alu", samples * CUBE_JAC_FLOP), "k_cube_eval": ("alu", samples * CUBE_EVAL_FLOP),
+             "k_cube_lsf": ("hbm", lsf_bytes * (1 + 11 + 1) / 3)}
+    rl, kern = roofline(prof, table, peaks)
+    vox = np.array([Nc * c.H * c.W for c in cubes], dtype=np.float64)
+    passes_vox = float(np.sum((info["nfev"] + info["njev"]) * vox))
+    res_d = dict(
+        value=round(n / (ms * 1e-3), 2), unit="fits/s", ms_per_step=round(ms, 3), steps=K_, warmup=W,
+        mvox_per_s=round(passes_vox / (ms * 1e-3) / 1e6, 2),
+        lm=dict(iters_mean=float(info["iters"].mean()), iters_max=int(info["iters"].max()),
+                converged=float((info["status"] == 0).mean()), nfev=int(info["nfev"].sum()),
+                njev=int(info["njev"].sum())),
+        counting="mvox_per_s = sum over cubes of (nfev + njev) x voxels / time per batch",
+        config=dict(workload="cube: 256 integral-field cubes of rotating disk galaxies (32..64 spaxels square, 64 "
+                             "channels, Gaussian/Moffat PSF 9..15 px, 7-tap Gaussian LSF), 12-parameter LM fit of "
+                             "each by one gf_cube_fit_lm call to chi2 rel tol 1e-5, 5x5 spatial and 3 spectral "
+                             "sub-samples; one step = the whole batch",
+                    cubes=n, channels=Nc, voxels=int(vox.sum()), oversample=S, oversample_v=Sv),
+        roofline=rl, stages=kern, roofline_profile="first LM iteration of the batch, kernel by kernel")
+    return res_d, dict(cubes=cubes, info=info, data=d, weight=w, off=off, S=S, Sv=Sv)
+
+
+def cpu_baseline_cube(extra, seconds):
+    """The cube oracle (numpy FP64, one thread): one LM iteration (Jacobian,
+    solve, trial model) on the batch's first cube of the smallest size, scaled
+    to the batch by padded spatial samples and by the GPU fit's iterations per
+    cube (extrapolated, labelled so)."""
+    from oracle import cube_ref as CR
+    import synth
+    cubes, info, d, w, off = extra["cubes"], extra["info"], extra["data"], extra["weight"], extra["off"]
+    S, Sv = extra["S"], extra["Sv"]
+    i = min(range(len(cubes)), key=lambda k: cubes[k].H * cubes[k].W)
+    c = cubes[i]
+    lo, hi = synth.cube_bounds(c.H, c.W, c.Nc)
+    dd = d[off[i]:off[i + 1]].astype(np.float32).astype(np.float64).reshape(c.Nc, c.H, c.W)
+    ww = w[off[i]:off[i + 1]].astype(np.float32).astype(np.float64).reshape(c.Nc, c.H, c.W)
+    t0 = time.perf_counter()
+    CR.fit_lm(c.start, c.psf.astype(np.float32).astype(np.float64), c.lsf.astype(np.float32).astype(np.float64),
+              dd, ww, S, Sv, lo=lo, hi=hi, max_iter=1)
+    t1 = time.perf_counter() - t0
+    pad = lambda cc: (cc.H + cc.K - 1) * (cc.W + cc.K - 1)
+    total = sum(t1 * pad(cc) / pad(c) * max(int(info["iters"][k]), 1) for k, cc in enumerate(cubes))
+    return dict(value=round(len(cubes) / total, 4), unit="fits/s", cores=1, kind="oracle",
+                sample=f"extrapolated: one numpy FP64 oracle LM iteration on cube {i} ({c.H}x{c.W}x{c.Nc}, "
+                       f"{t1:.1f} s on one thread), scaled by padded spaxels and by each cube's GPU iterations")
+
+
 def cpu_baseline_lines(extra, seconds):
     """The line oracle fitting the same spectra (the same observations, as
     FP32 values) one after another within the time budget."""
@@ -887,10 +990,11 @@ def cpu_baseline_c5(extra, seconds):
 
 
 
-RUNNERS = dict(c1=run_c1, c2=run_c2, c3=run_c3, c4=run_c4, c5=run_c5, lines=run_lines)
+RUNNERS = dict(c1=run_c1, c2=run_c2, c3=run_c3, c4=run_c4, c5=run_c5, lines=run_lines, cube=run_cube)
 DATA = dict(c5="synthetic (seeded; stamps rendered by the library from on-device Philox4x64-10 prior draws and "
                 "noise)",
-            lines="synthetic (seeded; spectra rendered by the library, noise from numpy PCG64)")
+            lines="synthetic (seeded; spectra rendered by the library, noise from numpy PCG64)",
+            cube="synthetic (seeded; cubes rendered by the library, noise from numpy PCG64)")
 
 
 def cpu_for(name, extra, seconds):
@@ -904,6 +1008,8 @@ def cpu_for(name, extra, seconds):
         return cpu_baseline_single(extra, seconds, 1, "C1", True)
     if name == "c5":
         return cpu_baseline_c5(extra, seconds)
+    if name == "cube":
+        return cpu_baseline_cube(extra, seconds)
     return cpu_baseline_lines(extra, seconds)
 
 
@@ -952,7 +1058,7 @@ def main():
     out.update(res)
     nested = {}
     if args.workload == "suite":
-        for name in ("c4", "c2", "c1"):
+        for name in ("c4", "c2", "c1", "cube"):
             log(f"workload {name}")
             r, e = RUNNERS[name](args, torch, ops, synth, peaks)
             log(f"{name}: {r['value']} {r['unit']}, {r['ms_per_step']} ms/step")

@@ -139,7 +139,10 @@ __global__ __launch_bounds__(kThreads) void k_cube_eval(const CubeDesc *__restri
 //   dV/dvproj = (2/pi) x' f,  dV/drt = -(2/pi) vproj x'/(rt^2 + R^2).
 // The channels are taken in blocks of CB; each block recomputes the
 // sub-samples' coefficients and keeps 11 CB sums in registers.
-constexpr int kCubeCB = 4;
+#ifndef GF_CUBE_CB
+#define GF_CUBE_CB 12
+#endif
+constexpr int kCubeCB = GF_CUBE_CB;
 
 template <int S>
 __global__ __launch_bounds__(kThreads) void k_cube_jac(const CubeDesc *__restrict__ desc, const Work *__restrict__ work,
@@ -163,6 +166,10 @@ __global__ __launch_bounds__(kThreads) void k_cube_jac(const CubeDesc *__restric
   const float inv = 1.0f / (float)(S * S * Sv);
   const float rt2 = k.rt * k.rt;
   float *dst = out + d.pad * (int64_t)Mc * 11 + p;
+  // spectral sub-sample offsets, once per thread (static register indices)
+  float ov[GF_MAX_OVERSAMPLE];
+#pragma unroll
+  for (int tv = 0; tv < GF_MAX_OVERSAMPLE; ++tv) ov[tv] = tv < Sv ? sv_off(tv, Sv) : 0.0f;
   for (int pc0 = 0; pc0 < Mc; pc0 += kCubeCB) {
     float acc[11][kCubeCB];
 #pragma unroll
@@ -213,9 +220,11 @@ __global__ __launch_bounds__(kThreads) void k_cube_jac(const CubeDesc *__restric
         const float b10 = I * k.isg;
 #pragma unroll
         for (int c = 0; c < kCubeCB; ++c) {
-          const float vb = (float)(pc0 + c - cl);
-          for (int tv = 0; tv < Sv; ++tv) {
-            const float u = vb + sv_off(tv, Sv) - V;
+          const float vb = (float)(pc0 + c - cl) - V;
+#pragma unroll
+          for (int tv = 0; tv < GF_MAX_OVERSAMPLE; ++tv) {
+            if (tv >= Sv) break;
+            const float u = vb + ov[tv];
             const float e = fast_exp2(k.kg * u * u);
             const float h = e * u * k.is2;
             acc[0][c] = fmaf(a0, e, fmaf(b0, h, acc[0][c]));
@@ -268,6 +277,48 @@ __global__ __launch_bounds__(kThreads) void k_cube_lsf(const CubeDesc *__restric
     float acc = 0.0f;
     for (int u = 0; u < Kl; ++u) acc = fmaf(l[u], src[(int64_t)(c + Kl - 1 - u) * np], acc);
     dst[(int64_t)c * np] = acc;
+  }
+}
+
+// The same for an LSF of KL taps known at compile time: each thread keeps a
+// ring of the last KL input channels in registers, so every input value is
+// loaded once (the generic kernel loads it KL times); the sums run over u in
+// the same order, so both give the same bits.
+template <int KL>
+__global__ __launch_bounds__(kThreads) void k_cube_lsf_t(const CubeDesc *__restrict__ desc,
+                                                         const Work *__restrict__ work,
+                                                         const float *__restrict__ lsf_all, int Nc, int nk,
+                                                         const int *__restrict__ mask, const float *__restrict__ in,
+                                                         float *__restrict__ out) {
+  const Work w = work[blockIdx.x];
+  const int s = w.stamp;
+  if (mask && !mask[s]) return;
+  const CubeDesc d = desc[s];
+  const int np = d.Mh * d.Mw;
+  const int p = w.unit * kThreads + (int)threadIdx.x;
+  if (p >= np) return;
+  const int j = blockIdx.y;
+  const int Mc = Nc + KL - 1;
+  const float *src = in + d.pad * (int64_t)Mc * nk + (int64_t)j * Mc * np + p;
+  float *dst = out + d.pad * (int64_t)Nc * nk + (int64_t)j * Nc * np + p;
+  float lw[KL], win[KL];
+#pragma unroll
+  for (int u = 0; u < KL; ++u) lw[u] = lsf_all[d.lsf + u];
+  // win[(i) % KL] holds input channel i once it is loaded
+#pragma unroll
+  for (int i = 0; i < KL - 1; ++i) win[i] = src[(int64_t)i * np];
+  for (int c0 = 0; c0 < Nc; c0 += KL) {
+#pragma unroll
+    for (int r = 0; r < KL; ++r) {
+      const int c = c0 + r;
+      if (c >= Nc) break;
+      // newest input: channel c + KL - 1, slot (r + KL - 1) % KL since c0 % KL == 0
+      win[(r + KL - 1) % KL] = src[(int64_t)(c + KL - 1) * np];
+      float acc = 0.0f;
+#pragma unroll
+      for (int u = 0; u < KL; ++u) acc = fmaf(lw[u], win[(r + KL - 1 - u) % KL], acc);
+      dst[(int64_t)c * np] = acc;
+    }
   }
 }
 
@@ -355,8 +406,17 @@ hipError_t launch_cube_lsf(hipStream_t st, const CubeDesc *desc, const Work *wor
                            int Nc, int Kl, int nk, const int *mask, const float *in, float *out) {
   if (n_work == 0) return hipSuccess;
   ProfScope ps(st, "k_cube_lsf");
-  hipLaunchKernelGGL(k_cube_lsf, dim3((unsigned)n_work, (unsigned)nk), dim3(kThreads), 0, st, desc, work, lsf, Nc, Kl,
-                     nk, mask, in, out);
+  const dim3 grid((unsigned)n_work, (unsigned)nk);
+#define GF_CL(KK)                                                                                                  \
+  case KK:                                                                                                         \
+    hipLaunchKernelGGL((k_cube_lsf_t<KK>), grid, dim3(kThreads), 0, st, desc, work, lsf, Nc, nk, mask, in, out); \
+    break;
+  switch (Kl) {
+    GF_CL(1) GF_CL(3) GF_CL(5) GF_CL(7) GF_CL(9) GF_CL(11) GF_CL(13) GF_CL(15)
+    default:
+      hipLaunchKernelGGL(k_cube_lsf, grid, dim3(kThreads), 0, st, desc, work, lsf, Nc, Kl, nk, mask, in, out);
+  }
+#undef GF_CL
   return hipGetLastError();
 }
 
