@@ -233,6 +233,14 @@ FftPlan make_plan(int L, int tw_off) {
 
 int padded_P(int nc) { return kNPC * nc + 1; }
 
+// Longest-processing-time-first order of a launch list: the units of the
+// costliest stamps are dispatched first, so the short ones fill the tail of
+// the launch.  The order changes no result: every unit writes its own slot.
+template <typename Key>
+void lpt_order(std::vector<Work> &v, Key key) {
+  std::stable_sort(v.begin(), v.end(), [&](const Work &a, const Work &b) { return key(a.stamp) > key(b.stamp); });
+}
+
 // Steps 2-3 for a one-channel padded model, chi^2 partials only: every stamp
 // in mask gets its partials at p->d_c2_first (FFT stamps from the inverse-row
 // pass, which writes no model image; direct stamps from the direct
@@ -468,11 +476,13 @@ static gf_status create_batch(gf_ctx *c, int n, const int32_t *H, const int32_t 
     const int nq = (d.H * d.W + kNeqChunk - 1) / kNeqChunk;
     for (int u = 0; u < nq; ++u) b->h_neq.push_back({s, u});
   }
-  // launch order: the units of the large stamps first (eight-wave
-  // workgroups), then the rest; the partial slots stay per stamp
-  std::stable_partition(b->h_neq.begin(), b->h_neq.end(), [&](const Work &w) {
-    return b->h_desc[w.stamp].H * b->h_desc[w.stamp].W >= kNeqBigPix;
-  });
+  // launch order: the largest stamps first (so the units of the stamps of
+  // at least kNeqBigPix pixels, the eight-wave workgroups, lead the list)
+  auto npad = [&](int s) { return (int64_t)b->h_desc[s].Mh * b->h_desc[s].Mw; };
+  auto npx = [&](int s) { return (int64_t)b->h_desc[s].H * b->h_desc[s].W; };
+  lpt_order(b->h_eval, npad);
+  lpt_order(b->h_pix, npx);
+  lpt_order(b->h_neq, npx);
   for (const Work &w : b->h_neq) b->n_neq_big += b->h_desc[w.stamp].H * b->h_desc[w.stamp].W >= kNeqBigPix;
   b->h_eval_first.push_back((int32_t)b->h_eval.size());
   b->h_pix_first.push_back((int32_t)b->h_pix.size());
@@ -749,16 +759,30 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     delete p;
     return fail(c, GF_ESHAPE, "gf_psf_prepare: batch too large");
   }
+  // launch lists in longest-first order (the multi-pass units by FFT side,
+  // direct tiles by PSF side; within each one-workgroup bucket the largest
+  // side first)
+  {
+    auto side = [&](int s) { return (int64_t)p->h_path[s].L; };
+    auto ksz = [&](int s) { return (int64_t)b->h_desc[s].K; };
+    for (auto *l : {&p->h_rows, &p->h_cols, &p->h_irows, &p->h_arows, &p->h_acols, &p->h_airows, &p->h_rows_n,
+                    &p->h_cols_n, &p->h_irows_n, &p->h_rows_alt, &p->h_cols_alt, &p->h_irows_alt,
+                    &p->h_rows_n_alt, &p->h_cols_n_alt, &p->h_irows_n_alt})
+      lpt_order(*l, side);
+    lpt_order(p->h_direct, ksz);
+    lpt_order(p->h_adirect, ksz);
+    lpt_order(p->h_pix_direct, ksz);
+  }
   std::vector<Work> f2d_otf;
   int f2d_otf_first[kF2dBuckets + 1] = {};
-  for (int k = 0; k < kF2dN; ++k) {
-    const int bk = f2d_bucket(k);
-    if (k == 0 || f2d_bucket(k - 1) != bk) {
-      p->f2d_first[bk] = (int)p->h_f2d.size();
-      f2d_otf_first[bk] = (int)f2d_otf.size();
+  for (int bk = 0; bk < kF2dBuckets; ++bk) {
+    p->f2d_first[bk] = (int)p->h_f2d.size();
+    f2d_otf_first[bk] = (int)f2d_otf.size();
+    for (int k = kF2dN - 1; k >= 0; --k) {
+      if (f2d_bucket(k) != bk) continue;
+      p->h_f2d.insert(p->h_f2d.end(), f2d_cls[k].begin(), f2d_cls[k].end());
+      f2d_otf.insert(f2d_otf.end(), f2d_otf_cls[k].begin(), f2d_otf_cls[k].end());
     }
-    p->h_f2d.insert(p->h_f2d.end(), f2d_cls[k].begin(), f2d_cls[k].end());
-    f2d_otf.insert(f2d_otf.end(), f2d_otf_cls[k].begin(), f2d_otf_cls[k].end());
   }
   p->f2d_first[kF2dBuckets] = (int)p->h_f2d.size();
   f2d_otf_first[kF2dBuckets] = (int)f2d_otf.size();

@@ -208,6 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
                                                                const Work *__restrict__ work,
                                                                const CompC *__restrict__ cc,
                                                                const float *__restrict__ adj,
+                                                               const int32_t *__restrict__ first,
                                                                float *__restrict__ part) {
   __shared__ float red[kThreads / 64][kMaxP];
   const Work w = work[blockIdx.x];
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_contract(const StampDesc *
     float v = 0.0f;
 #pragma unroll
     for (int ww = 0; ww < kThreads / 64; ++ww) v += red[ww][threadIdx.x];
-    part[(int64_t)blockIdx.x * (kMaxP - 1) + threadIdx.x] = v;
+    part[(int64_t)(first[s] + w.unit) * (kMaxP - 1) + threadIdx.x] = v;   // the unit's own slot
   }
 }
 
@@ -372,7 +373,8 @@ hipError_t launch_adjoint_contract(hipStream_t st, const gf_batch *b, const floa
   switch (S) {
 #define GF_ADJ_CASE(SS)                                                                                      \
   case SS:                                                                                                   \
-    hipLaunchKernelGGL((k_adjoint_contract<SS>), grid, block, 0, st, b->d_desc, b->d_eval, b->d_cc, adj, part); \
+    hipLaunchKernelGGL((k_adjoint_contract<SS>), grid, block, 0, st, b->d_desc, b->d_eval, b->d_cc, adj,         \
+                       b->d_eval_first, part);                                                               \
     break;
     GF_ADJ_CASE(1) GF_ADJ_CASE(2) GF_ADJ_CASE(3) GF_ADJ_CASE(4)
     GF_ADJ_CASE(5) GF_ADJ_CASE(6) GF_ADJ_CASE(7) GF_ADJ_CASE(8)

@@ -180,7 +180,8 @@ hipError_t launch_chi2(hipStream_t st, const gf_batch *b, const float *model, co
 __global__ __launch_bounds__(kThreads) void k_cot_prep(const StampDesc *__restrict__ desc,
                                                        const Work *__restrict__ work, const float *__restrict__ cot,
                                                        const float *__restrict__ weight, float scale,
-                                                       float *__restrict__ c, float2 *__restrict__ part) {
+                                                       float *__restrict__ c, const int32_t *__restrict__ first,
+                                                       float2 *__restrict__ part) {
   const Work w = work[blockIdx.x];
   const StampDesc d = desc[w.stamp];
   const int npix = d.H * d.W;
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_cot_prep(const StampDesc *__restri
     }
   }
   const F2 tot = block_sum(acc);
-  if (threadIdx.x == 0) part[blockIdx.x] = make_float2(tot.hi, tot.lo);
+  if (threadIdx.x == 0) part[first[w.stamp] + w.unit] = make_float2(tot.hi, tot.lo);   // the unit's own slot
 }
 
 // out[par + q] = sum of contraction partials (component parameters) and
@@ -229,7 +230,7 @@ hipError_t launch_cot_prep(hipStream_t st, const gf_batch *b, const float *cot, 
                            float *c, float2 *spart) {
   dim3 grid((unsigned)b->h_pix.size()), blk(kThreads);
   if (grid.x == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cot_prep, grid, blk, 0, st, b->d_desc, b->d_pix, cot, weight, scale, c, spart);
+  hipLaunchKernelGGL(k_cot_prep, grid, blk, 0, st, b->d_desc, b->d_pix, cot, weight, scale, c, b->d_pix_first, spart);
   return hipGetLastError();
 }
 
