@@ -251,6 +251,8 @@ TRAFFIC = {
                                summary="profiles/c2_fit_hbm_traffic.md"),
     ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "524bd17134a451f8"}, bytes=3.8621e+08,
                            summary="profiles/c4_likelihood_hbm_traffic.md"),
+    ("cube", "k_cube_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_cube.hip": "b023150d1a31c379"}, bytes=2.8513e+09,
+                                 summary="profiles/cube_fit_hbm_traffic.md"),
 }
 
 
@@ -755,6 +757,7 @@ def run_cube(args, torch, ops, synth, peaks, steps=None, warmup=None):
     table = {"k_cube_jac": ("alu", samples * CUBE_JAC_FLOP), "k_cube_eval": ("alu", samples * CUBE_EVAL_FLOP),
              "k_cube_lsf": ("hbm", lsf_bytes * (1 + 11 + 1) / 3)}
     rl, kern = roofline(prof, table, peaks)
+    rl["traffic"] = measured_traffic("cube", rl)
     vox = np.array([Nc * c.H * c.W for c in cubes], dtype=np.float64)
     passes_vox = float(np.sum((info["nfev"] + info["njev"]) * vox))
     res_d = dict(

@@ -236,3 +236,50 @@ def test_cube_fit_default_tolerance_converges(ctx, cube_fit):
     assert np.all(r2["status"] == 0) and np.all(r2["reason"] == 1), r2
     for s in range(len(cubes)):
         assert res["chi2"][s] * (1 - 1e-6) <= r2["chi2"][s] <= res["chi2"][s] * (1 + 1e-4)
+
+
+def test_cube_bench_configuration(ctx):
+    """The benchmarked cube batch's launch configuration (its first cubes:
+    32..64 spaxels, 64 channels, 9..15 px PSFs, 7-tap LSF, S = 5, Sv = 3):
+    models of one cube per size against the oracle, the Jacobian of a 48 px
+    cube, and a fit of a 32 px cube at the parameter-parity tolerance."""
+    allc = synth.cube_batch(256)
+    pick = []
+    for N in synth.CUBE_SIZES:
+        pick.append(next(i for i, c in enumerate(allc) if c.H == N))
+    cubes = [allc[i] for i in pick]
+    print("bench-configuration cubes", [(c.H, c.K) for c in cubes], flush=True)
+    gc = GpuCubes(ctx, cubes, thetas=[c.start for c in cubes])
+    m = gc.split(ops.cube_model(ctx, gc.cb, gc.theta, 5, 3))
+    for s in range(len(cubes)):
+        ref = gc.oracle_model(s, 5, 3)
+        assert rel_l2(m[s], ref) <= 1e-5, (s, rel_l2(m[s], ref))
+    s48 = [c.H for c in cubes].index(48)
+    J = gc.split(ops.cube_jacobian(ctx, gc.cb, gc.theta, 5, 3), per=CR.NPAR)[s48]
+    c = cubes[s48]
+    ref = CR.jacobian(gc.th[s48], c.H, c.W, gc.psf32[s48].astype(np.float64), gc.lsf32[s48].astype(np.float64), c.Nc,
+                      5, 3)
+    for p in range(CR.NPAR):
+        assert rel_l2(J[p], ref[p]) <= 1e-4, (p, rel_l2(J[p], ref[p]))
+    # a fit of the 32 px cube inside the five-cube batch
+    data, w = _observe(cubes, 5, 3, 4242)
+    gd = GpuCubes(ctx, cubes, thetas=[c.start for c in cubes], data=data, weights=w)
+    lo, hi = _bounds(cubes)
+    fit, res = ops.cube_fit_lm(ctx, gd.cb, gd.data, gd.weight, gd.theta, 3, lo=to_dev(lo, torch.float64),
+                               hi=to_dev(hi, torch.float64), oversample=5, **FIT)
+    fit = fit.cpu().numpy()
+    s = 0
+    c = cubes[s]
+    print("oracle fit of the 32 px cube", flush=True)
+    ref, info = CR.fit_lm(c.start, gd.psf32[s].astype(np.float64), gd.lsf32[s].astype(np.float64),
+                          gd.d32[s].astype(np.float64), gd.w32[s].astype(np.float64), 5, 3,
+                          lo=lo[:12], hi=hi[:12], **FIT)
+    assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5)
+    a = fit[:12]
+    for p in range(CR.NPAR):
+        if p == CR.PHI:
+            assert abs((a[p] - ref[p] + math.pi / 2) % math.pi - math.pi / 2) <= 1e-4 * math.pi
+            continue
+        scale = abs(ref[CR.RE]) if p in (CR.XC, CR.YC) else c.noise_sigma if p == CR.CONT else \
+            1.0 if p >= CR.V0 else 0.0
+        assert abs(a[p] - ref[p]) <= 1e-4 * max(abs(ref[p]), scale), (p, a[p], ref[p])
