@@ -353,18 +353,18 @@ class Cube:
 def cube_stamp(g: np.random.Generator, H: int, W: int, Nc: int, lsf: np.ndarray, idx: int, seed: int) -> Cube:
     """An integral-field cube of a rotating disk galaxy, parameters
     [xc, yc, Ie, Re, n, q, phi, continuum, v0, vproj, rt, sigma_v]:
-    centre (W/2, H/2) + U[-1, 1], Ie log-U[0.5, 5], Re ~ U[2, min(H, W)/5],
+    centre (W/2, H/2) + U[-1, 1], Ie log-U[0.5, 5], Re ~ U[2, max(min(H, W)/5, 2.5)],
     n ~ U[0.6, 2.5], q ~ U[0.35, 0.95], phi ~ U[0, pi], continuum U[0, 0.05],
-    v0 ~ Nc/2 + U[-2, 2], vproj ~ U[2, Nc/6], rt ~ U[1, 0.8 Re],
+    v0 ~ Nc/2 + U[-2, 2], vproj ~ U[2, max(Nc/6, 2.5)], rt ~ U[1, 0.8 Re],
     sigma_v ~ U[1.2, 3] channels; Gaussian or Moffat PSF with K in
     {9, 11, 13, 15} and FWHM ~ U[2, 3.5]; noise sigma 0.02.  Start: the
     profile parameters x (1 + U[-0.1, 0.1]) (the centre moves by U[-0.1, 0.1] Re),
     v0 + U[-1, 1], vproj, rt and sigma_v x (1 + U[-0.15, 0.15]), continuum
     + U[-0.01, 0.01]."""
-    re = g.uniform(2.0, min(H, W) / 5.0)
+    re = g.uniform(2.0, max(min(H, W) / 5.0, 2.5))
     t = np.array([W / 2 + g.uniform(-1, 1), H / 2 + g.uniform(-1, 1), math.exp(g.uniform(math.log(0.5), math.log(5.0))),
                   re, g.uniform(0.6, 2.5), g.uniform(0.35, 0.95), g.uniform(0.0, math.pi), g.uniform(0.0, 0.05),
-                  Nc / 2 + g.uniform(-2, 2), g.uniform(2.0, Nc / 6.0), g.uniform(1.0, 0.8 * re), g.uniform(1.2, 3.0)])
+                  Nc / 2 + g.uniform(-2, 2), g.uniform(2.0, max(Nc / 6.0, 2.5)), g.uniform(1.0, 0.8 * re), g.uniform(1.2, 3.0)])
     K = int(g.choice([9, 11, 13, 15]))
     fwhm = g.uniform(2.0, 3.5)
     psf = gaussian_psf(K, fwhm / 2.3548200450309493) if g.uniform() < 0.5 else moffat_psf(K, fwhm, 3.0)

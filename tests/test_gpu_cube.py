@@ -283,3 +283,28 @@ def test_cube_bench_configuration(ctx):
         scale = abs(ref[CR.RE]) if p in (CR.XC, CR.YC) else c.noise_sigma if p == CR.CONT else \
             1.0 if p >= CR.V0 else 0.0
         assert abs(a[p] - ref[p]) <= 1e-4 * max(abs(ref[p]), scale), (p, a[p], ref[p])
+
+
+@pytest.mark.parametrize("shapes,Nc,Kl", [([(1, 1, 1), (2, 3, 3)], 1, 1), ([(3, 2, 1), (5, 4, 3)], 5, 3),
+                                          ([(6, 6, 3)], 1024, 5)])
+def test_cube_degenerate_and_maximum_shapes(ctx, shapes, Nc, Kl):
+    """One spaxel, one channel, delta kernels, and the longest spectral axis."""
+    cubes = _cubes(shapes, Nc, Kl, 31)
+    th = []
+    for c in cubes:
+        t = c.truth.copy()
+        t[[0, 1, 3]] = [c.W / 2 - 0.3, c.H / 2 + 0.2, 1.5]
+        t[8] = Nc / 2 + 0.4
+        th.append(t)
+    gc = GpuCubes(ctx, cubes, thetas=th)
+    m = gc.split(ops.cube_model(ctx, gc.cb, gc.theta, 3, 2))
+    J = gc.split(ops.cube_jacobian(ctx, gc.cb, gc.theta, 3, 2), per=CR.NPAR)
+    for s, c in enumerate(cubes):
+        ref = gc.oracle_model(s, 3, 2)
+        assert rel_l2(m[s], ref) <= 1e-5, (s, rel_l2(m[s], ref))
+        if Nc <= 5:
+            rj = CR.jacobian(gc.th[s], c.H, c.W, gc.psf32[s].astype(np.float64), gc.lsf32[s].astype(np.float64), Nc,
+                             3, 2)
+            for p in range(CR.NPAR):
+                if np.linalg.norm(rj[p]) > 1e-12:
+                    assert rel_l2(J[s][p], rj[p]) <= 1e-4, (s, p, rel_l2(J[s][p], rj[p]))
