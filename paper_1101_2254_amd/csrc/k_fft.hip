@@ -298,11 +298,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
                                                        const float2 *__restrict__ S1,
                                                        const float2 *__restrict__ otf,
                                                        const int64_t *__restrict__ s2_off, float2 *__restrict__ S2,
-                                                       const int *__restrict__ mask, int tmax) {
+                                                       const int *__restrict__ mask, int tmax, int nx) {
   extern __shared__ float2 lds[];
   constexpr int CAP = fft_cap(RMAX), LDS0 = fft_lds(CAP), NIT = fft_iters(CAP);
-  const Work w = work[blockIdx.x];
-  const int s = w.stamp, ch = blockIdx.y;
+  // Workgroup b runs on XCD b % 8 (workgroups go to the eight XCDs in turn);
+  // the n_ch channels of one unit take consecutive slots of one XCD, so the
+  // unit's OTF block comes from HBM once and from that XCD's L2 for the other
+  // channels.  The grid has ceil(nx / 8) * 8 * n_ch workgroups.
+  const int xcd = (int)(blockIdx.x & 7u), slot = (int)(blockIdx.x >> 3);
+  const int q = slot / n_ch, ch = slot - q * n_ch;
+  const int ux = q * 8 + xcd;
+  if (ux >= nx) return;
+  const Work w = work[ux];
+  const int s = w.stamp;
   if (mask && !mask[s]) return;
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
@@ -519,6 +527,9 @@ static size_t fft_lds_bytes(const gf_psf *p) { return (size_t)(fft_lds(fft_cap(p
       hipLaunchKernelGGL((KERNEL<MODE, 32>), __VA_ARGS__);               \
   } while (0)
 
+// Grid of the column pass for nx work entries of n_ch channels each.
+static dim3 cols_grid(int nx, int n_ch) { return dim3((unsigned)((nx + 7) / 8 * 8 * n_ch)); }
+
 // Small jobs (fewer than two workgroups per CU in the wide shape) use the
 // narrow shape: one row pair or two bins per workgroup, so more CUs share the
 // latency-bound work.
@@ -547,8 +558,8 @@ static hipError_t multipass_conv(hipStream_t st, const gf_batch *b, const gf_psf
   }
   {
     ProfScope ps(st, ep ? "k_fft_cols.chi2" : "k_fft_cols");
-    GF_FFT_LAUNCH(k_fft_cols, MODE_CONV, dim3((unsigned)nc, n_ch), blk, lds, st, b->d_desc, p->d_path,
-                       p->d_plans, p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc);
+    GF_FFT_LAUNCH(k_fft_cols, MODE_CONV, cols_grid(nc, n_ch), blk, lds, st, b->d_desc, p->d_path, p->d_plans,
+                  p->d_tw, d_cols, n_ch, p->d_s1, S1, p->d_otf, p->d_s2, S2, mask, tc, nc);
   }
   {
     ProfScope ps(st, ep ? "k_fft_irows_chi2" : "k_fft_irows");
@@ -584,9 +595,9 @@ hipError_t launch_fft_corr(hipStream_t st, const gf_batch *b, const gf_psf *p, c
   dim3 blk(kThreads);
   GF_FFT_LAUNCH(k_fft_rows, MODE_CORR, dim3((unsigned)p->h_arows.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_arows, in, 1, p->d_s1a, S1, (const int *)nullptr, 1 << 20);
-  GF_FFT_LAUNCH(k_fft_cols, MODE_CORR, dim3((unsigned)p->h_acols.size(), 1), blk, lds, st, b->d_desc,
+  GF_FFT_LAUNCH(k_fft_cols, MODE_CORR, cols_grid((int)p->h_acols.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_acols, 1, p->d_s1a, S1, p->d_otf, p->d_s2a, S2,
-                     (const int *)nullptr, 1 << 20);
+                     (const int *)nullptr, 1 << 20, (int)p->h_acols.size());
   GF_FFT_LAUNCH(k_fft_irows, MODE_CORR, dim3((unsigned)p->h_airows.size(), 1), blk, lds, st, b->d_desc,
                      p->d_path, p->d_plans, p->d_tw, p->d_airows, 1, p->d_s2a, S2, out, (const int *)nullptr,
                      1 << 20, Chi2Epi{});
@@ -603,9 +614,9 @@ hipError_t launch_fft_otf(hipStream_t st, const gf_batch *b, const gf_psf *p, co
   dim3 blk(kThreads);
   GF_FFT_LAUNCH(k_fft_rows, MODE_OTF, dim3((unsigned)n_rows, 1), blk, lds, st, b->d_desc, p->d_path,
                      p->d_plans, p->d_tw, rows, taps, 1, s1_off, S1, (const int *)nullptr, 1 << 20);
-  GF_FFT_LAUNCH(k_fft_cols, MODE_OTF, dim3((unsigned)n_cols, 1), blk, lds, st, b->d_desc, p->d_path,
+  GF_FFT_LAUNCH(k_fft_cols, MODE_OTF, cols_grid(n_cols, 1), blk, lds, st, b->d_desc, p->d_path,
                      p->d_plans, p->d_tw, cols, 1, s1_off, S1, (const float2 *)nullptr, otf_off, p->d_otf,
-                     (const int *)nullptr, 1 << 20);
+                     (const int *)nullptr, 1 << 20, n_cols);
   return hipGetLastError();
 }
 
