@@ -325,7 +325,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
                                             const double *__restrict__ theta, const float *__restrict__ data,
                                             const float *__restrict__ weight, float *__restrict__ part,
                                             const int32_t *__restrict__ first, const int *__restrict__ mask,
-                                            int vec_ok, float2 *__restrict__ c2part) {
+                                            float2 *__restrict__ c2part) {
   constexpr int SK = kNPC * NC;
   constexpr int P = SK + 1 + PX;
   constexpr int NW = T / 64;
@@ -352,71 +352,53 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
   // channel read by this lane (clamped for the sky / residual lanes)
   const bool jl = i < SK || (i > SK && i < P);
   const int ich = i < SK ? i : (i > SK && i < P) ? i - 1 : 0;
-  if (vec_ok && (((int64_t)d.pix * nchan | npix | d.img) & 3) == 0 && base + per_wave <= npix) {
-    // the wave's pixels all inside the stamp, 16-byte aligned (uniform over
-    // the wave): each lane loads its four consecutive pixels per operand
-    // with one 16-byte load
-#pragma unroll 4
-    for (int g = 0; g < per_wave; g += 16) {
-      const int p = base + g + 4 * kk;
-      const float4 wt = *reinterpret_cast<const float4 *>(weight + d.img + p);
-      const float4 jv = *reinterpret_cast<const float4 *>(J + (int64_t)ich * npix + p);
-      const float4 dv = *reinterpret_cast<const float4 *>(data + d.img + p);
-      float4 iv[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) iv[c] = *reinterpret_cast<const float4 *>(J + (int64_t)(kNPC * c + 2) * npix + p);
-      const float wq[4] = {wt.x, wt.y, wt.z, wt.w}, jq[4] = {jv.x, jv.y, jv.z, jv.w};
-      const float dq[4] = {dv.x, dv.y, dv.z, dv.w};
-      float rq[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float m = sky;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const float iq[4] = {iv[c].x, iv[c].y, iv[c].z, iv[c].w};
-          m = fmaf(ie[c], iq[q], m);
-        }
-        rq[q] = dq[q] - m;
-        const float x = jl ? jq[q] : (i == SK) ? 1.0f : (i == P) ? rq[q] : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
-      }
-      if constexpr (C2) {
-        // lanes i = 0..3 of each 16-lane group take pixel q = i of the group
-        const float r = i == 0 ? rq[0] : i == 1 ? rq[1] : i == 2 ? rq[2] : rq[3];
-        const float ww = i == 0 ? wq[0] : i == 1 ? wq[1] : i == 2 ? wq[2] : wq[3];
-        if (i < 4) {
-          const float e = sqrtf(ww) * r;
-          c2acc = f2_add1(c2acc, e * e);
-        }
-      }
-    }
-  } else if (base < npix) {
+  // The wave stages 64 pixels at a time in LDS: each lane loads every operand
+  // of one pixel (whole rows, coalesced, no value loaded by two lanes), forms
+  // its model and residual, and stores the MFMA operands (Jacobian channels,
+  // weight, residual, in-stamp flag; zeros past the stamp).  The products
+  // then read them four pixels at a time in the same order as lane-loaded
+  // operands would give, so the sums are the same.
+  constexpr int NJ = P - 1;          // Jacobian channels (every column but the sky's)
+  constexpr int NR = NJ + 3;
+  // rows padded to 65 floats: a lane's stores of one row hit consecutive
+  // banks, and the 16 rows one product reads spread over the banks
+  __shared__ float stg[NW][NR][65];
+  float (*sg)[65] = stg[wv];
+  if (base < npix) {
 #pragma unroll 1
-    for (int g = 0; g < per_wave; g += 16) {
-      float rq[4], wq[4];
+    for (int blk = 0; blk < per_wave; blk += 64) {
+      const int p = base + blk + lane;
+      const bool ok = p < npix;
+      const int pc = ok ? p : npix - 1;   // in-bounds address for the straight-line loads
+      float jv[NJ];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int p = base + g + 4 * kk + q;
-        const bool ok = p < npix;
-        const int pc = ok ? p : npix - 1;  // in-bounds address for the straight-line loads
-        const float wt = weight[d.img + pc];
-        const float jv = J[(int64_t)ich * npix + pc];
-        const float dv = data[d.img + pc];
-        float m = sky;
+      for (int c = 0; c < NJ; ++c) jv[c] = J[(int64_t)c * npix + pc];
+      const float wt = weight[d.img + pc], dv = data[d.img + pc];
+      float m = sky;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) m = fmaf(ie[c], J[(int64_t)(kNPC * c + 2) * npix + pc], m);
-        rq[q] = ok ? dv - m : 0.0f;
-        wq[q] = ok ? wt : 0.0f;
-        float x = jl ? jv : (i == SK) ? 1.0f : (i == P) ? dv - m : 0.0f;
-        x = ok ? x : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wq[q] * x, acc, 0, 0, 0);
-      }
-      if constexpr (C2) {   // the same lanes and order as the vector path
-        const float r = i == 0 ? rq[0] : i == 1 ? rq[1] : i == 2 ? rq[2] : rq[3];
-        const float ww = i == 0 ? wq[0] : i == 1 ? wq[1] : i == 2 ? wq[2] : wq[3];
-        if (i < 4) {
-          const float e = sqrtf(ww) * r;
-          c2acc = f2_add1(c2acc, e * e);
+      for (int c = 0; c < NC; ++c) m = fmaf(ie[c], jv[kNPC * c + 2], m);
+      wave_sync();   // the previous block's operands have been read
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) sg[c][lane] = ok ? jv[c] : 0.0f;
+      sg[NJ][lane] = ok ? wt : 0.0f;
+      sg[NJ + 1][lane] = ok ? dv - m : 0.0f;
+      sg[NJ + 2][lane] = ok ? 1.0f : 0.0f;
+      wave_sync();
+#pragma unroll
+      for (int g = 0; g < 64; g += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pg = g + 4 * kk + q;
+          const float x = jl ? sg[ich][pg] : (i == SK) ? sg[NJ + 2][pg] : (i == P) ? sg[NJ + 1][pg] : 0.0f;
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, sg[NJ][pg] * x, acc, 0, 0, 0);
+        }
+        if constexpr (C2) {
+          // lanes i = 0..3 of each 16-lane group take pixel i of the group
+          if (i < 4) {
+            const int pg = g + 4 * kk + i;
+            const float e = sqrtf(sg[NJ][pg]) * sg[NJ + 1][pg];
+            c2acc = f2_add1(c2acc, e * e);
+          }
         }
       }
     }
@@ -462,18 +444,16 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
     has1 |= d.ncomp == 1;
     has2 |= d.ncomp == 2;
   }
-  const int vec_ok = aligned16(jc) && aligned16(data) && aligned16(weight);
 #define GF_GRAM(NC, C2, T, L, G)                                                                                \
   hipLaunchKernelGGL((k_gram<NC, C2, T>), dim3((unsigned)(G)), dim3(T), 0, st, b->d_desc, L, jc, nchan, theta,   \
-                     data, weight, part, b->d_neq_first, mask, vec_ok, c2part)
+                     data, weight, part, b->d_neq_first, mask, c2part)
   if (px == kCubePX) {   // one-component stamps with the cube's kinematic parameters, no chi^2 output
     if (nbig > 0)
       hipLaunchKernelGGL((k_gram<1, false, 512, kCubePX>), dim3((unsigned)nbig), dim3(512), 0, st, b->d_desc, lst,
-                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, vec_ok, (float2 *)nullptr);
+                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr);
     if (n > nbig)
       hipLaunchKernelGGL((k_gram<1, false, 256, kCubePX>), dim3((unsigned)(n - nbig)), dim3(256), 0, st, b->d_desc,
-                         lst + nbig, jc, nchan, theta, data, weight, part, b->d_neq_first, mask, vec_ok,
-                         (float2 *)nullptr);
+                         lst + nbig, jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr);
     return hipGetLastError();
   }
   if (px != 0) return hipErrorInvalidValue;
