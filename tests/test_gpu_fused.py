@@ -10,7 +10,7 @@ import torch
 
 import synth
 from paper_1101_2254_amd import ops
-from tests.gpu_common import GpuBatch, to_dev
+from tests.gpu_common import keep_fft_forms, GpuBatch, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +22,7 @@ SHAPES = [(33, 47, 9), (17, 64, 15), (1, 40, 5), (65, 31, 21), (50, 77, 25), (63
 def ctx():
     print("gpu fused chi2: creating context on cuda:0", flush=True)
     c = ops.Context(0)
+    keep_fft_forms(c)   # the fit test compares a stamp alone with the same stamp in the batch, bit for bit
     yield c
     torch.cuda.synchronize()
     c.close()
