@@ -135,12 +135,27 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16_t *__restrict__ A, int 
       }
 }
 
+// Sum of `n` values at stride `stride` in index order, with the loads of
+// eight values in flight at a time (the additions keep the same order).
+__device__ __forceinline__ float ordered_sum(const float *__restrict__ p, int n, int64_t stride) {
+  float s = 0.f;
+  int z = 0;
+  for (; z + 8 <= n; z += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = p[(int64_t)(z + j) * stride];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; z < n; ++z) s += p[(int64_t)z * stride];
+  return s;
+}
+
 // Sum of split-K partials in split order, then the epilogue.
 __global__ void k_gemm_reduce(const float *__restrict__ part, int splits, int M, int N, Epi epi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)M * N) return;
-  float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + i];
+  const float s = ordered_sum(part + i, splits, (int64_t)M * N);
   epi_store(epi, (int)(i / N), (int)(i % N), s);
 }
 
@@ -334,9 +349,7 @@ __global__ __launch_bounds__(256) void k_colsum_part_v8(const bf16_t *__restrict
 __global__ void k_colsum_final(const float *__restrict__ part, int chunks, int N, float *__restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  float s = 0.f;
-  for (int q = 0; q < chunks; ++q) s += part[(int64_t)q * N + c];
-  out[c] = s;
+  out[c] = ordered_sum(part + c, chunks, N);
 }
 
 // Mean squared error over nb x 8 outputs; dy = 2 (y - t) / (8 nb).
