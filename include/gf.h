@@ -115,17 +115,27 @@ void gf_destroy(gf_ctx *ctx);
  * Both forms give the same convolution to rounding (a fit whose stamps
  * move may take other last bits).  The getters return 0 (form) or -1
  * (min_active) for sides that are not one-workgroup sides; the setters
- * return GF_EINVAL for them. */
+ * return GF_EINVAL for them.
+ * direct_max_k: GF_CONV_AUTO convolves PSFs of side K <= direct_max_k on
+ * the direct path and larger ones by FFT (default 7; measured by
+ * gf_autotune with no sides, or on the first gf_psf_prepare(GF_CONV_AUTO)
+ * of a context with a tuning file that meets a PSF side in 3..15). */
 /* Measure the FFT forms of the given one-workgroup sides now (NULL and 0:
- * every one of them): per side, 256 stamps of padded side L convolved in
- * seven channels by each form, the faster form kept.  Writes the context's
- * tuning file when it has one (min_active values set on the context are
- * written too).  GF_EINVAL for a side that is not a one-workgroup side. */
+ * every one of them, and the direct-path threshold): per side, 256 stamps
+ * of padded side L convolved in seven channels by each form, the faster
+ * form kept; for the threshold, 256 stamps of 64 x 64 convolved in seven
+ * channels directly and by FFT for K = 3, 5, ..., 15, direct_max_k the
+ * largest K up to which the direct path is not slower.  Writes the
+ * context's tuning file when it has one (min_active values set on the
+ * context are written too).  GF_EINVAL for a side that is not a
+ * one-workgroup side. */
 gf_status gf_autotune(gf_ctx *ctx, const int32_t *sides, int n_sides);
 int gf_tune_form_get(const gf_ctx *ctx, int L);
 gf_status gf_tune_form_set(gf_ctx *ctx, int L, int form);
 int gf_tune_min_active_get(const gf_ctx *ctx, int L);
 gf_status gf_tune_min_active_set(gf_ctx *ctx, int L, int n);
+int gf_tune_direct_get(const gf_ctx *ctx);
+gf_status gf_tune_direct_set(gf_ctx *ctx, int direct_max_k);   /* 1..GF_MAX_K, odd (GF_EINVAL otherwise) */
 
 /* All later work of this context is enqueued on `hip_stream` (a hipStream_t;
  * NULL = the default stream). */

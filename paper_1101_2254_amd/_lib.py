@@ -37,6 +37,7 @@ EXPORTS = ("gf_create", "gf_destroy", "gf_set_stream", "gf_last_error", "gf_sync
            "gf_profile_stop", "gf_profile_kernels", "gf_profile_get", "gf_line_batch_create", "gf_line_batch_destroy",
            "gf_line_batch_offsets", "gf_line_model", "gf_line_chi2", "gf_line_fit_lm", "gf_version",
            "gf_chi2_noalloc", "gf_autotune", "gf_tune_form_get", "gf_tune_form_set", "gf_tune_min_active_get", "gf_tune_min_active_set",
+           "gf_tune_direct_get", "gf_tune_direct_set",
            "gf_cube_batch_create", "gf_cube_batch_destroy", "gf_cube_batch_offsets", "gf_cube_set_kernels",
            "gf_cube_model", "gf_cube_chi2", "gf_cube_jacobian", "gf_cube_fit_lm")
 
@@ -165,6 +166,8 @@ def lib() -> ctypes.CDLL:
         "gf_tune_form_set": (i32, [vp, i32, i32]),
         "gf_tune_min_active_get": (i32, [vp, i32]),
         "gf_tune_min_active_set": (i32, [vp, i32, i32]),
+        "gf_tune_direct_get": (i32, [vp]),
+        "gf_tune_direct_set": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -427,6 +430,14 @@ def gf_tune_min_active_get(ctx, L: int) -> int:
 
 def gf_tune_min_active_set(ctx, L: int, n: int) -> None:
     check(lib().gf_tune_min_active_set(ctx, L, n), ctx)
+
+
+def gf_tune_direct_get(ctx) -> int:
+    return int(lib().gf_tune_direct_get(ctx))
+
+
+def gf_tune_direct_set(ctx, k: int) -> None:
+    check(lib().gf_tune_direct_set(ctx, int(k)), ctx)
 
 
 def gf_version() -> str:

@@ -337,6 +337,16 @@ gf_status gf_tune_form_set(gf_ctx *c, int L, int form) {
   return GF_OK;
 }
 
+int gf_tune_direct_get(const gf_ctx *c) { return c ? c->tune_direct_k : 0; }
+
+gf_status gf_tune_direct_set(gf_ctx *c, int k) {
+  if (!c || k < 1 || k > GF_MAX_K || (k % 2) == 0) return fail(c, GF_EINVAL, "gf_tune_direct_set: odd K in 1..GF_MAX_K");
+  c->tune_direct_k = k;
+  c->tune_direct_done = 1;
+  (void)tune_save(c);
+  return GF_OK;
+}
+
 int gf_tune_min_active_get(const gf_ctx *c, int L) {
   const int k = c ? f2d_class(L) : -1;
   return k < 0 ? -1 : c->f2d_min_active[f2d_bucket(k)];
@@ -573,9 +583,17 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   // first use of a one-workgroup side by the automatic choice of a context
   // with a tuning file: measure it now
   if (mode == GF_CONV_AUTO && !c->tune_path.empty()) {
+    if (!c->tune_direct_done) {
+      bool near = false;   // a PSF side where the direct-path threshold decides
+      for (const StampDesc &d : b->h_desc) near |= d.K >= 3 && d.K <= 15;
+      if (near) {
+        const gf_status ts = tune_direct(c);
+        if (ts != GF_OK) return fail(c, ts, "gf_psf_prepare: measuring the direct-path threshold failed");
+      }
+    }
     std::vector<char> seen(kF2dN, 0);
     for (const StampDesc &d : b->h_desc) {
-      const int k = d.K > 7 ? f2d_class(fft_side(std::max(d.Mh, d.Mw))) : -1;
+      const int k = d.K > c->tune_direct_k ? f2d_class(fft_side(std::max(d.Mh, d.Mw))) : -1;
       if (k < 0 || seen[k] || c->tune_form[k] >= 0) continue;
       seen[k] = 1;
       const gf_status ts = tune_side(c, kF2dSides[k]);
@@ -615,7 +633,7 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
     if (mode == GF_CONV_DIRECT) return d.K > kDirectMaxK ? 1 : 0;
     if (mode == GF_CONV_FFT_MULTIPASS) return 1;
     if (mode == GF_CONV_FFT_FUSED) return 2;
-    if (mode == GF_CONV_AUTO && d.K <= 7) return 0;
+    if (mode == GF_CONV_AUTO && d.K <= c->tune_direct_k) return 0;
     if (!fits) return 1;
     if (mode == GF_CONV_AUTO) {
       // untuned sides: the one-workgroup form up to 160 (above, its kernels

@@ -319,6 +319,9 @@ struct gf_ctx {
   int32_t f2d_min_active[gf::kF2dBuckets];
   int8_t tune_min_done[gf::kF2dBuckets] = {};   // f2d_min_active measured (or read) for the bucket
   std::string tune_path;      // file the table is read from and written to ("" = no measuring)
+  // PSF sides up to this are convolved directly by GF_CONV_AUTO
+  int32_t tune_direct_k = 7;
+  int8_t tune_direct_done = 0;   // measured (or read) for this context
   gf_ctx() {
     for (int i = 0; i < gf::kF2dN; ++i) tune_form[i] = -1;
     // eight rounds of workgroups on 256 CUs for a seven-channel Jacobian,
@@ -335,6 +338,7 @@ namespace gf {
 gf_status tune_load(gf_ctx *c);
 gf_status tune_save(gf_ctx *c);
 gf_status tune_side(gf_ctx *c, int L);
+gf_status tune_direct(gf_ctx *c);
 // Binds a context's profiler to the calling thread for one entry point.
 struct ProfBind {
   Profiler *prev;

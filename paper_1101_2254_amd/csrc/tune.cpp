@@ -87,10 +87,10 @@ gf_status time_us(gf_ctx *c, int reps, F fn, double *us) {
   return GF_OK;
 }
 
-// Time of a seven-channel convolution (one Jacobian's) of n stamps of side L
-// in the given form.
-gf_status time_form(gf_ctx *c, int L, int n, int mode, double *us) {
-  const int K = L >= 24 ? 15 : 3, H = L - K + 1, M = L;
+// Time of a seven-channel convolution (one Jacobian's) of n H x H stamps
+// with K x K PSFs in the given mode.
+gf_status time_conv(gf_ctx *c, int H, int K, int n, int mode, double *us) {
+  const int M = H + K - 1;
   std::vector<int32_t> hv(n, H), kv(n, K), nc(n, 1);
   gf_batch *b = nullptr;
   gf_status st = gf_batch_create(c, n, hv.data(), hv.data(), kv.data(), nc.data(), 0, &b);
@@ -117,6 +117,12 @@ gf_status time_form(gf_ctx *c, int L, int n, int mode, double *us) {
   return st;
 }
 
+// The same for padded side L in the given FFT form.
+gf_status time_form(gf_ctx *c, int L, int n, int mode, double *us) {
+  const int K = L >= 24 ? 15 : 3;
+  return time_conv(c, L - K + 1, K, n, mode, us);
+}
+
 }  // namespace
 
 namespace gf {
@@ -133,6 +139,17 @@ gf_status tune_load(gf_ctx *c) {
   std::vector<std::pair<int, int>> form, mina;
   read_int_map(txt, "form", form);
   read_int_map(txt, "min_active", mina);
+  {
+    const size_t k = txt.find("\"direct_max_k\"");
+    if (k != std::string::npos) {
+      const size_t colon = txt.find(':', k);
+      const int v = colon == std::string::npos ? 0 : std::atoi(txt.c_str() + colon + 1);
+      if (v >= 1 && v <= GF_MAX_K && (v % 2) == 1) {
+        c->tune_direct_k = v;
+        c->tune_direct_done = 1;
+      }
+    }
+  }
   for (auto &kv : form) {
     const int k = f2d_class(kv.first);
     if (k >= 0 && (kv.second == 1 || kv.second == 2)) c->tune_form[k] = (int8_t)kv.second;
@@ -152,8 +169,9 @@ gf_status tune_save(gf_ctx *c) {
   std::string name;
   const std::string arch = device_key(c->device, &name);
   std::ostringstream o;
-  o << "{\"library\": \"" << gf_version() << "\", \"arch\": \"" << arch << "\", \"device\": \"" << name
-    << "\",\n \"form\": {";
+  o << "{\"library\": \"" << gf_version() << "\", \"arch\": \"" << arch << "\", \"device\": \"" << name << "\",\n";
+  if (c->tune_direct_done) o << " \"direct_max_k\": " << c->tune_direct_k << ",\n";
+  o << " \"form\": {";
   bool first = true;
   for (int k = 0; k < kF2dN; ++k) {
     if (c->tune_form[k] < 0) continue;
@@ -199,6 +217,27 @@ gf_status tune_side(gf_ctx *c, int L) {
   return GF_OK;
 }
 
+// The direct-path threshold: 256 stamps of 64 x 64 in seven channels, each
+// odd K from 3 to 15 convolved directly and by FFT; the threshold is the
+// largest K up to which the direct path is not slower (the direct cost grows
+// as K^2, the FFT's barely with K, so the first K where the FFT wins ends
+// the scan).
+gf_status tune_direct(gf_ctx *c) {
+  int best = 1;
+  for (int K = 3; K <= 15; K += 2) {
+    double td = 0, tf = 0;
+    gf_status st = time_conv(c, 64, K, 256, GF_CONV_DIRECT, &td);
+    if (st == GF_OK) st = time_conv(c, 64, K, 256, GF_CONV_FFT, &tf);
+    if (st != GF_OK) return st;
+    if (td > tf) break;
+    best = K;
+  }
+  c->tune_direct_k = best;
+  c->tune_direct_done = 1;
+  (void)tune_save(c);
+  return GF_OK;
+}
+
 }  // namespace gf
 
 extern "C" gf_status gf_autotune(gf_ctx *c, const int32_t *sides, int n_sides) {
@@ -219,6 +258,13 @@ extern "C" gf_status gf_autotune(gf_ctx *c, const int32_t *sides, int n_sides) {
     gf_status st = tune_side(c, L);
     if (st != GF_OK) {
       if (c->err.empty()) c->err = "gf_autotune: measuring side " + std::to_string(L) + " failed";
+      return st;
+    }
+  }
+  if (n_sides == 0) {
+    gf_status st = tune_direct(c);
+    if (st != GF_OK) {
+      if (c->err.empty()) c->err = "gf_autotune: measuring the direct-path threshold failed";
       return st;
     }
   }

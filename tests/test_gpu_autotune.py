@@ -1,7 +1,8 @@
 """The context's tuning table on a device: a context created with a tuning
-file measures the FFT form of each one-workgroup side on first use and
-writes the file; a second context reading it takes the same choices and
-gives the same bits; both forms agree with the oracle's convolution."""
+file measures the FFT form of each one-workgroup side and the direct-path
+PSF threshold on first use and writes the file; a second context reading it
+takes the same choices and gives the same bits; every path agrees with the
+oracle's convolution."""
 import json
 import os
 
@@ -19,7 +20,10 @@ pytestmark = pytest.mark.gpu
 
 def _stamps():
     g = synth.rng(9090)
-    return [synth.c3_stamp(g, N, i, 9090) for i, N in enumerate([32, 64, 96, 128, 128, 64])]
+    out = [synth.c3_stamp(g, N, i, 9090) for i, N in enumerate([32, 64, 96, 128, 128, 64])]
+    # a 9 px PSF, where the direct-path threshold decides the path
+    out[5].psf = synth.gaussian_psf(9, 1.3)
+    return out
 
 
 def _observed(gfo, stamps):
@@ -45,25 +49,29 @@ def test_tuning_file_round_trip(tmp_path, gfo):
         print(f"tuning context {run}", flush=True)
         ctx = ops.Context(0, autotune_cache=path)
         gb = GpuBatch(ctx, stamps, data=data, weights=weights)
-        sides = sorted({int(s) for s in gb.psf.fft_side})
+        dk = L.gf_tune_direct_get(ctx.ptr)
+        assert dk in range(1, 16, 2), dk
+        sides = sorted({int(s) for u, s in zip(gb.psf.uses_fft, gb.psf.fft_side) if u})
         forms = {s: L.gf_tune_form_get(ctx.ptr, s) for s in sides}
         assert all(f in (1, 2) for f in forms.values()), forms
         assert os.path.exists(path)
-        # each stamp on the form the table names for its side
-        for u, s in zip(gb.psf.uses_fft, gb.psf.fft_side):
-            assert u == forms[int(s)]
+        # each stamp on the path the table names: direct up to its PSF side
+        # threshold, else the form of its FFT side
+        for st, u, s in zip(stamps, gb.psf.uses_fft, gb.psf.fft_side):
+            assert u == (0 if st.K <= dk else forms[int(s)])
         th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(start, torch.float64),
                               lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-8)
         chi = ops.pairs_to_f64(ops.likelihood(ctx, gb.batch, gb.psf, gb.theta, gb.data, gb.weight, 5)).cpu().numpy()
         mins = {s: L.gf_tune_min_active_get(ctx.ptr, s) for s in sides}
-        out.append((forms, mins, th.cpu().numpy(), info, chi))
+        out.append((forms, mins, th.cpu().numpy(), info, chi, dk))
         torch.cuda.synchronize()
         ctx.close()
     tab = json.load(open(path))
     assert tab["arch"].startswith("gfx950")
     assert {int(k) for k in tab["form"]} >= set(out[0][0])
     # the second context read the table: same choices, same bits
-    assert out[1][0] == out[0][0] and out[1][1] == out[0][1]
+    assert out[1][0] == out[0][0] and out[1][1] == out[0][1] and out[1][5] == out[0][5]
+    assert tab["direct_max_k"] == out[0][5]   # measured on first use (the 9 px PSF)
     np.testing.assert_array_equal(out[1][2], out[0][2])
     np.testing.assert_array_equal(out[1][4], out[0][4])
     for k in ("chi2", "iters", "nfev"):
@@ -94,6 +102,19 @@ def test_autotune_call_and_errors(tmp_path):
     b = ops.Batch(c2, [34], [34], [15], [1])
     p = ops.Psf(c2, b, to_dev(np.full(225, 1 / 225.0, np.float32)), ops.GF_CONV_AUTO)
     assert list(p.uses_fft) == [2] and L.gf_tune_form_get(c2.ptr, 48) == -1
+    # every side and the direct-path threshold
+    L.gf_autotune(ctx.ptr, [])
+    dk = L.gf_tune_direct_get(ctx.ptr)
+    assert dk in range(1, 16, 2)
+    assert json.load(open(str(tmp_path / "t.json")))["direct_max_k"] == dk
+    L.gf_tune_direct_set(ctx.ptr, 9)
+    assert L.gf_tune_direct_get(ctx.ptr) == 9
+    with pytest.raises(L.GfError):
+        L.gf_tune_direct_set(ctx.ptr, 8)
+    b9 = ops.Batch(ctx, [40, 40], [40, 40], [9, 11], [1, 1])
+    p9 = ops.Psf(ctx, b9, to_dev(np.full(81 + 121, 0.01, np.float32)), ops.GF_CONV_AUTO)
+    assert list(p9.uses_fft)[0] == 0 and list(p9.uses_fft)[1] != 0
+    assert L.gf_tune_direct_get(c2.ptr) == 7        # the default rule
     torch.cuda.synchronize()
     ctx.close()
     c2.close()
