@@ -245,11 +245,11 @@ def stage_fractions(prof, stage):
 # source is the one the counters were taken on (first 16 hex digits of the
 # SHA-256 of each listed source).
 TRAFFIC = {
-    ("c3", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "524bd17134a451f8"}, bytes=3.0290e+09,
+    ("c3", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "adb99cbbc85be344"}, bytes=3.0316e+09,
                                summary="profiles/c3_batch_hbm_traffic.md"),
-    ("c2", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "524bd17134a451f8"}, bytes=1.8806e+07,
+    ("c2", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "adb99cbbc85be344"}, bytes=1.8805e+07,
                                summary="profiles/c2_fit_hbm_traffic.md"),
-    ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "524bd17134a451f8"}, bytes=3.8621e+08,
+    ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "adb99cbbc85be344"}, bytes=3.8622e+08,
                            summary="profiles/c4_likelihood_hbm_traffic.md"),
     ("cube", "k_cube_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_cube.hip": "b023150d1a31c379"}, bytes=2.8513e+09,
                                  summary="profiles/cube_fit_hbm_traffic.md"),
