@@ -912,11 +912,78 @@ def cpu_baseline_c4(extra, seconds):
         out[label] = (n, time.perf_counter() - t0, gfo.get_threads())
     n, t, c = out["all"]
     n1, t1, _ = out["one"]
-    return dict(value=round(n * 65536 / t / 1e6, 5), unit="Mpix/s", cores=c, kind="oracle",
+    ctx_fft = cpu_fft_context(gfo, "c4", extra, seconds / 2)
+    return dict(value=round(n * 65536 / t / 1e6, 5), unit="Mpix/s", cores=c, kind="oracle", fft_context=ctx_fft,
                 value_1thread=round(n1 * 65536 / t1 / 1e6, 6), cores_1thread=1, cpu=cpu_model(),
                 build="gcc -O3 -march=native",
                 sample=f"FP64 oracle eval + direct convolution + chi2 of {n} (all cores, {t:.1f} s) and {n1} (one "
                        f"thread, {t1:.1f} s) of a step's parameter vectors on its own rendering of the image")
+
+
+def _fft_valid(pads, otf, L, K, H, W, workers):
+    """'Valid' convolution of padded FP64 images (..., Mh, Mw) with a PSF
+    given by its L x L OTF, through scipy's FFT on `workers` threads."""
+    import scipy.fft as sf
+    spec = sf.rfft2(pads, s=(L, L), workers=workers)
+    full = sf.irfft2(spec * otf, s=(L, L), workers=workers)
+    return full[..., K - 1:K - 1 + H, K - 1:K - 1 + W]
+
+
+def cpu_fft_context(gfo, kind, extra, seconds):
+    """Context for the oracle figures: the same steps with the convolution
+    through scipy's FFT (FP64, all host cores) instead of the direct sum.
+    kind "c4": steps 1-3 per parameter vector, Mpix/s; kind "c2": one
+    Jacobian pass (14 derivative channels on the padded grid, their
+    convolutions, the normal equations) times the GPU fit's passes, fits/s.
+    Checked against the direct convolution on the first image."""
+    import scipy.fft as sf
+    nt = os.cpu_count() or 1
+    _threads(gfo, nt)
+    if kind == "c4":
+        base = extra["base"]
+        H = W = 256
+        psf = base.psf.astype(np.float32).astype(np.float64)
+        K = psf.shape[0]
+        L = 288
+        otf = sf.rfft2(psf, s=(L, L), workers=nt)
+        th = extra["thetas_host"].astype(np.float32).astype(np.float64)
+        import synth
+        m_true = gfo.model(H, W, base.truth.astype(np.float32).astype(np.float64), psf, 5)
+        d, w = synth.add_gaussian_noise(m_true, base.noise_sigma, base.noise_seed)
+        pad0 = gfo.eval_padded(H, W, K, th[0], 5)
+        ref = gfo.conv_valid(pad0, psf)
+        got = _fft_valid(pad0, otf, L, K, H, W, nt)
+        assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+        t0 = time.perf_counter()
+        n = 0
+        while (time.perf_counter() - t0 < seconds or n == 0) and n < th.shape[0]:
+            m = _fft_valid(gfo.eval_padded(H, W, K, th[n], 5), otf, L, K, H, W, nt) + th[n][-1]
+            float(np.sum(w * (d - m) ** 2))
+            n += 1
+        t = time.perf_counter() - t0
+        return dict(value=round(n * H * W / t / 1e6, 4), unit="Mpix/s", cores=gfo.get_threads(),
+                    sample=f"{n} vectors in {t:.1f} s: oracle evaluation (C, all cores) + scipy.fft convolution "
+                           f"(FP64, {nt} workers) + chi2")
+    st = extra["st"]
+    psf = st.psf.astype(np.float32).astype(np.float64)
+    K = psf.shape[0]
+    H, W = st.H, st.W
+    L = 576
+    otf = sf.rfft2(psf, s=(L, L), workers=nt)
+    theta = st.start.astype(np.float64)
+    t0 = time.perf_counter()
+    dp = gfo.dpadded(H, W, K, theta, 5)                       # (P - 1, Mh, Mw)
+    J = _fft_valid(dp, otf, L, K, H, W, nt).reshape(dp.shape[0], -1)
+    A = J @ J.T
+    t = time.perf_counter() - t0
+    ref = gfo.conv_valid(dp[0], psf)
+    assert np.abs(J[0].reshape(H, W) - ref).max() <= 1e-9 * np.abs(ref).max()
+    passes = max(int(extra.get("njev", 1)) + 1, 1)
+    per_fit = t * passes
+    return dict(value=round(1.0 / per_fit, 5), unit="fits/s", cores=gfo.get_threads(),
+                sample=f"one Jacobian pass ({dp.shape[0]} channels: oracle derivatives on all cores, scipy.fft "
+                       f"convolutions with {nt} workers, normal equations) in {t:.2f} s, times the GPU fit's "
+                       f"{passes} evaluation passes")
 
 
 def cpu_baseline_single(extra, seconds, ncomp, label, whole_fits):
@@ -946,7 +1013,9 @@ def cpu_baseline_single(extra, seconds, ncomp, label, whole_fits):
             t_it = time.perf_counter() - t0
             out[lab] = (t_it * extra["iters"], extra["iters"], "one iteration x the GPU fit's iterations")
     (t, it, how), (t1, _, _) = out["all"], out["one"]
+    extra_ctx = {"fft_context": cpu_fft_context(gfo, "c2", extra, seconds)} if ncomp == 2 else {}
     return dict(value=round(1.0 / t, 5), unit="fits/s", ms_per_fit=round(t * 1e3, 2), cores=os.cpu_count() or 1,
+                **extra_ctx,
                 kind="oracle", value_1thread=round(1.0 / t1, 6), ms_per_fit_1thread=round(t1 * 1e3, 2),
                 cores_1thread=1, cpu=cpu_model(), build="gcc -O3 -march=native",
                 sample=f"{label}: FP64 oracle LM ({how}; {it} iterations) on its own rendering of the same "
