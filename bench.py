@@ -46,6 +46,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -103,14 +104,25 @@ def fft_geometry(H, W, K, L):
     return Mh * Mw, H * W, L * (L // 2 + 1) * 8
 
 
+def fft_conv_flops(L, Mh, H):
+    """Nominal arithmetic of one channel's FFT convolution at side L (5 N log2 N
+    per complex transform of length N, additions and multiplications counted
+    separately): row transforms of the Mh padded rows two real rows at a
+    time, forward and inverse column transforms of the L/2 + 1 bins, the
+    spectrum product, inverse row transforms of the H kept rows."""
+    c = 5.0 * L * math.log2(L)
+    Lh = L // 2 + 1
+    return (Mh + 1) // 2 * c + 2 * Lh * c + 6 * Lh * L + (H + 1) // 2 * c
+
+
 def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=False):
     """Algorithmic work per launch of each kernel when every stamp of the
     batch takes part: (bound, units).  stamps: list of (H, W, K); paths and
     sides from the prepared PSF; nch: Jacobian channels per launch; nimg:
     pixels of the distinct observations (shared-image batches)."""
     npad = npix = 0
-    f2 = dict(pad=0, pix=0, otf=0, n=0)
-    mp = dict(rows=0, cols=0, irows=0, irows_chi2=0, otf=0, pad=0, pix=0, n=0)
+    f2 = dict(pad=0, pix=0, otf=0, n=0, flops=0.0)
+    mp = dict(rows=0, cols=0, irows=0, irows_chi2=0, otf=0, pad=0, pix=0, n=0, flops=0.0)
     for (H, W, K), path, L in zip(stamps, paths, sides):
         pad, pix, otf = fft_geometry(H, W, K, max(L, 2))
         npad += pad
@@ -123,6 +135,7 @@ def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=Fals
             f2["pix"] += pix
             f2["otf"] += otf
             f2["n"] += 1
+            f2["flops"] += fft_conv_flops(L, H + K - 1, H)
         elif path == 1:
             Mh = H + K - 1
             mp["rows"] += 4 * pad + 8 * Mh * Lh
@@ -133,6 +146,7 @@ def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=Fals
             mp["pad"] += pad
             mp["pix"] += pix
             mp["n"] += 1
+            mp["flops"] += fft_conv_flops(L, Mh, H)
     img = npix if nimg is None else nimg
     dw = 8 * (img if nimg is not None else f2["pix"])      # data + weight read by the fused chi^2
     dw_mp = 8 * (img if nimg is not None else mp["pix"])
@@ -157,17 +171,19 @@ def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=Fals
         # step 2 of the Jacobian channels: padded model in, stamp out, OTF once
         convolution=dict(kernels=["k_fft2d", "k_fft_rows", "k_fft_cols", "k_fft_irows"],
                          bytes=nch * (4 * (f2["pad"] + mp["pad"]) + 4 * (f2["pix"] + mp["pix"])) + f2["otf"] +
-                         mp["otf"]),
+                         mp["otf"], flops=nch * (f2["flops"] + mp["flops"])),
         # steps 2-3 of a model evaluation: padded model, data and weight in,
         # OTF once, only chi^2 out
         convolution_chi2=dict(kernels=["k_fft2d_chi2", "k_fft_rows.chi2", "k_fft_cols.chi2", "k_fft_irows_chi2"],
                               bytes=4 * (f2["pad"] + mp["pad"]) + (8 * img if nimg is not None else
                                                                      8 * (f2["pix"] + mp["pix"])) +
-                              f2["otf"] + mp["otf"]),
-        fused_convolution=dict(kernels=["k_fft2d"], bytes=nch * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"]),
-        fused_convolution_chi2=dict(kernels=["k_fft2d_chi2"], bytes=4 * f2["pad"] + dw + f2["otf"]),
+                              f2["otf"] + mp["otf"], flops=f2["flops"] + mp["flops"]),
+        fused_convolution=dict(kernels=["k_fft2d"], bytes=nch * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"],
+                               flops=nch * f2["flops"]),
+        fused_convolution_chi2=dict(kernels=["k_fft2d_chi2"], bytes=4 * f2["pad"] + dw + f2["otf"],
+                                    flops=f2["flops"]),
         multipass_convolution=dict(kernels=["k_fft_rows", "k_fft_cols", "k_fft_irows"],
-                                   bytes=nch * (4 * mp["pad"] + 4 * mp["pix"]) + mp["otf"]),
+                                   bytes=nch * (4 * mp["pad"] + 4 * mp["pix"]) + mp["otf"], flops=nch * mp["flops"]),
     )
     return t, stage, dict(npad=npad, npix=npix, fused_stamps=f2["n"], multipass_stamps=mp["n"])
 
@@ -224,9 +240,13 @@ def roofline(prof, table, peaks, launches_per_call=None):
     return rl, stages
 
 
-def stage_fractions(prof, stage):
+def stage_fractions(prof, stage, peaks=None):
     """The definitional-byte fractions of steps 2 and 3 (per call of the
-    stage: the summed time of its kernels over the calls profiled)."""
+    stage: the summed time of its kernels over the calls profiled).  With the
+    measured peaks, a convolution stage also gets its arithmetic floor: the
+    nominal FFT operations at the unpacked FP32 rate of one operation per lane
+    and cycle (half the measured FMA flop rate), and the fraction of 8 TB/s
+    the definitional bytes would reach at that floor."""
     out = {}
     for name, st in stage.items():
         ks = [k for k in st["kernels"] if k in prof]
@@ -234,8 +254,14 @@ def stage_fractions(prof, stage):
             continue
         calls = max(prof[k][0] for k in ks)
         t = sum(prof[k][1] for k in ks) / calls * 1e-3
-        out[name] = dict(kernels=ks, calls=calls, bytes_per_call=int(st["bytes"]), us_per_call=round(t * 1e6, 2),
-                         gbs=round(st["bytes"] / t / 1e9, 1), frac=round(st["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4))
+        e = dict(kernels=ks, calls=calls, bytes_per_call=int(st["bytes"]), us_per_call=round(t * 1e6, 2),
+                 gbs=round(st["bytes"] / t / 1e9, 1), frac=round(st["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4))
+        if peaks and st.get("flops"):
+            floor = st["flops"] / (peaks["fma_tflops"] / 2 * 1e12)
+            e.update(fft_flops_nominal=int(st["flops"]), alu_floor_us=round(floor * 1e6, 2),
+                     frac_of_alu_floor=round(floor / t, 4),
+                     hbm_frac_at_alu_floor=round(st["bytes"] / floor / 1e9 / HBM_PEAK_GBS, 4))
+        out[name] = e
     return out
 
 
@@ -359,7 +385,7 @@ def run_c3(args, torch, ops, synth, peaks, steps=None, warmup=None):
                              "one gf_fit_lm call to chi2 rel tol 1e-5; one step = the whole batch",
                     stamps=n, pixels=int(pix.sum()), oversample=5, fused_fft_stamps=sizes["fused_stamps"],
                     multipass_fft_stamps=sizes["multipass_stamps"]),
-        roofline=rl, stages=kern, stage_roofline=stage_fractions(prof, stage),
+        roofline=rl, stages=kern, stage_roofline=stage_fractions(prof, stage, peaks),
         roofline_profile="first LM iteration of the batch, kernel by kernel (every stamp active)")
     return res, dict(stamps=stamps, info=info)
 
@@ -409,10 +435,10 @@ def run_c4(args, torch, ops, synth, peaks, steps=None, warmup=None):
     table, stage, sizes = kernel_table(geo, psf.uses_fft, psf.fft_side, 1, 1, 5, nimg=256 * 256, shared_otf=True)
     rl, kern = roofline(prof, table, peaks)
     rl["traffic"] = measured_traffic("c4", rl)
-    sr = stage_fractions(prof, stage)
+    sr = stage_fractions(prof, stage, peaks)
     sep_stage = {"convolution": stage["convolution"],
                  "chi2": dict(kernels=["k_chi2", "k_pair_final"], bytes=4 * npix + 8 * 256 * 256)}
-    for k, v in stage_fractions(sep_prof, sep_stage).items():
+    for k, v in stage_fractions(sep_prof, sep_stage, peaks).items():
         sr["separate_" + k] = v
     res = dict(
         value=round(npix / (ms * 1e-3) / 1e6, 3), unit="Mpix/s", ms_per_step=round(ms, 4), steps=K, warmup=W,
@@ -493,7 +519,7 @@ def run_single(torch, ops, synth, st, ncomp, noise, K_, W, peaks, workload, labe
                 model_passes=n_model, jacobian_passes=n_jac),
         config=dict(workload=label, image=[st.H, st.W], psf=st.K, fft_side=int(psf.fft_side[0]),
                     fft_form=int(psf.uses_fft[0]), params=7 * ncomp + 1, oversample=5),
-        roofline=rl, stages=kern, stage_roofline=stage_fractions(prof, stage),
+        roofline=rl, stages=kern, stage_roofline=stage_fractions(prof, stage, peaks),
         counting="mpix_per_s = (model passes + Jacobian passes the fit ran) x stamp pixels / time per fit")
     return res
 
@@ -624,7 +650,7 @@ def run_c5(args, torch, ops, synth, peaks, steps=None, warmup=None):
     prof1, _ = profile(ctx, lambda: fit(net.predict(data).reshape(-1).contiguous(), use_graph=0, max_iter=1))
     table, stage, _ = kernel_table([(side, side, int(k)) for k in ev.batch.K], ev.psf.uses_fft, ev.psf.fft_side, 7, 1, 5)
     rl, kern = roofline(prof1, table, peaks)
-    result.update(steps=K_, warmup=W, roofline=rl, stages=kern, stage_roofline=stage_fractions(prof1, stage),
+    result.update(steps=K_, warmup=W, roofline=rl, stages=kern, stage_roofline=stage_fractions(prof1, stage, peaks),
                   roofline_profile="first LM iteration of the network-seeded fit, kernel by kernel")
     return result, dict(info=ic, nfev=int(ic["nfev"].sum()), njev=int(ic["njev"].sum()))
 
