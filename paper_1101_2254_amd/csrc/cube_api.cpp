@@ -27,7 +27,7 @@ hipError_t launch_cube_cont(hipStream_t, const gf_batch *, const double *, float
 hipError_t launch_cube_jac_assemble(hipStream_t, const gf_batch *, const float *, float *);
 hipError_t launch_cube_clip(hipStream_t, int64_t, const double *, const double *, const double *, double *);
 hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
-                           float *, const int *, const WorkView *, const Chi2Epi *ep);
+                           float *, const int *, const WorkView *, const Chi2Epi *ep, const FftFork *fork);
 hipError_t launch_direct(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float *, bool,
                          const int *, const WorkView *);
 hipError_t launch_chi2(hipStream_t, const gf_batch *, const float *, const void *, bool, const float *,
@@ -162,7 +162,7 @@ gf_status steps12(gf_ctx *c, gf_cube_batch *cb, hipStream_t st, const double *th
     CUBE_TRY(c, launch_cube_jac(st, cb->d_desc, cb->d_sp, nw, theta, c->d_bn, cb->Nc, cb->Kl, S, Sv, mask, B.pad));
   CUBE_TRY(c, launch_cube_lsf(st, cb->d_desc, cb->d_sp, nw, cb->d_lsf, cb->Nc, cb->Kl, nk, mask, B.pad, B.lsf));
   const int nch = nk * cb->Nc;
-  CUBE_TRY(c, launch_fft_conv(st, cb->conv, cb->psf, B.lsf, nch, B.S1, B.S2, B.conv, mask, nullptr, nullptr));
+  CUBE_TRY(c, launch_fft_conv(st, cb->conv, cb->psf, B.lsf, nch, B.S1, B.S2, B.conv, mask, nullptr, nullptr, &c->fork));
   CUBE_TRY(c, launch_direct(st, cb->conv, cb->psf, B.lsf, nch, B.conv, false, mask, nullptr));
   return GF_OK;
 }

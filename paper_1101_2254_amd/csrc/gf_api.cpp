@@ -24,7 +24,8 @@ hipError_t launch_eval_jac_d(hipStream_t, const gf_batch *, const double *, int,
 hipError_t launch_adjoint_contract(hipStream_t, const gf_batch *, const float *, int, const float4 *, const float *,
                                    float *);
 hipError_t launch_fft_conv(hipStream_t, const gf_batch *, const gf_psf *, const float *, int, float2 *, float2 *,
-                           float *, const int *, const WorkView *, const Chi2Epi *ep = nullptr);
+                           float *, const int *, const WorkView *, const Chi2Epi *ep = nullptr,
+                           const FftFork *fork = nullptr);
 hipError_t launch_fft_corr(hipStream_t, const gf_batch *, const gf_psf *, const float *, float2 *, float2 *, float *);
 hipError_t launch_fft_otf(hipStream_t, const gf_batch *, const gf_psf *, const float *, const Work *, int,
                           const Work *, int, const int64_t *, float2 *, const int64_t *);
@@ -247,9 +248,9 @@ void lpt_order(std::vector<Work> &v, Key key) {
 // convolution into mconv and the chi^2 kernel).
 hipError_t conv_chi2(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *mpad, float2 *S1, float2 *S2,
                      float *mconv, const void *theta, bool theta_f64, const float *data, const float *weight,
-                     float2 *part, const int *mask, const WorkView *v) {
+                     float2 *part, const int *mask, const WorkView *v, const FftFork *fork) {
   const Chi2Epi ep{data, weight, theta, theta_f64 ? 1 : 0, p->d_c2_first, part};
-  hipError_t e = launch_fft_conv(st, b, p, mpad, 1, S1, S2, mconv, mask, v, &ep);
+  hipError_t e = launch_fft_conv(st, b, p, mpad, 1, S1, S2, mconv, mask, v, &ep, fork);
   if (e == hipSuccess) e = launch_direct(st, b, p, mpad, 1, mconv, false, mask, v);
   if (e == hipSuccess) e = launch_chi2_direct(st, b, p, mconv, theta, theta_f64, data, weight, part, mask, v);
   return e;
@@ -293,7 +294,13 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
     return GF_ENOMEM;
   }
   if (!c->tune_path.empty()) (void)tune_load(c);   // an unreadable or foreign table is ignored
-  if (noalloc_init(device) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&c->fork.side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork.join, hipEventDisableTiming) != hipSuccess ||
+      noalloc_init(device) != hipSuccess) {
+    if (c->fork.side) (void)hipStreamDestroy(c->fork.side);
+    if (c->fork.fork) (void)hipEventDestroy(c->fork.fork);
+    if (c->fork.join) (void)hipEventDestroy(c->fork.join);
     dfree(c->d_bn);
     dfree(c->d_counters);
     (void)hipHostFree(c->h_pinned);
@@ -320,6 +327,9 @@ void gf_destroy(gf_ctx *c) {
   if (c->lm_graph) (void)hipGraphDestroy(c->lm_graph);
   if (c->lm_stream) (void)hipStreamDestroy(c->lm_stream);
   if (c->lm_ev) (void)hipEventDestroy(c->lm_ev);
+  if (c->fork.side) (void)hipStreamDestroy(c->fork.side);
+  if (c->fork.fork) (void)hipEventDestroy(c->fork.fork);
+  if (c->fork.join) (void)hipEventDestroy(c->fork.join);
   delete c;
 }
 
@@ -919,7 +929,7 @@ gf_status gf_eval_model(gf_ctx *c, const gf_batch *b, const float *theta, int S,
 
 static gf_status convolve(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *in, int n_ch, float *out,
                           float2 *S1, float2 *S2, const int *mask) {
-  GF_TRY(c, launch_fft_conv(c->stream, b, p, in, n_ch, S1, S2, out, mask, nullptr));
+  GF_TRY(c, launch_fft_conv(c->stream, b, p, in, n_ch, S1, S2, out, mask, nullptr, nullptr, &c->fork));
   GF_TRY(c, launch_direct(c->stream, b, p, in, n_ch, out, false, mask, nullptr));
   return GF_OK;
 }
@@ -993,7 +1003,7 @@ gf_status gf_likelihood(gf_ctx *c, const gf_batch *b, const gf_psf *p, const flo
   float2 *S1, *S2, *part;
   likelihood_layout(b, p, a, &mpad, &mconv, &S1, &S2, &part);
   GF_TRY(c, launch_eval(c->stream, b, theta, S, c->d_bn, mpad, nullptr));
-  GF_TRY(c, conv_chi2(c->stream, b, p, mpad, S1, S2, mconv, theta, false, data, weight, part, nullptr, nullptr));
+  GF_TRY(c, conv_chi2(c->stream, b, p, mpad, S1, S2, mconv, theta, false, data, weight, part, nullptr, nullptr, &c->fork));
   GF_TRY(c, launch_pair_final(c->stream, b->n, p->d_c2_first, part, (float2 *)chi2, nullptr));
   return GF_OK;
 }
@@ -1314,7 +1324,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     GF_TRY(c, launch_lm_start(cs, b, o.start, theta, o.lo, o.hi, B.theta_t, S, c->d_bn, B.cc_th));
     if (spec) {
       GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, nullptr, nullptr, B.cc_th, false));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, nullptr, nullptr));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, nullptr, nullptr, nullptr, &c->fork));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, nullptr, nullptr));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, nullptr, nullptr,
                                  B.gpart));
@@ -1322,7 +1332,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     } else {
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
-                          nullptr));
+                          nullptr, &c->fork));
       GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt));
     }
     WorkView view;
@@ -1337,7 +1347,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
                                 B.cc_t, c->d_bn, vw));
       GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, B.mtrial, vw, B.cc_t, false));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mtrial, vw));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mtrial, vw, nullptr, &c->fork));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mtrial, vw));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, B.mtrial, vw,
                                  B.gpart));
@@ -1348,14 +1358,14 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     auto iteration = [&]() -> gf_status {
       if (spec) return iteration_spec();
       GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw, B.cc_th, false));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw));
+      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw, nullptr, &c->fork));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
       GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr));
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
                                 B.cc_t, c->d_bn, vw));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
-                          vw));
+                          vw, &c->fork));
       GF_TRY(c, launch_lm_update(cs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
                                  B.cnt, B.cc_th, B.cc_t, vw));
       return GF_OK;
@@ -1522,7 +1532,7 @@ gf_status gf_fit_simplex(gf_ctx *c, const gf_batch *b, const gf_psf *p, const fl
     auto iteration = [&]() -> gf_status {
       GF_TRY(c, launch_nm_zero(cs, cnt));
       GF_TRY(c, launch_eval_d(cs, b, theta_t, S, c->d_bn, mpad, mask, nullptr));
-      GF_TRY(c, conv_chi2(cs, b, p, mpad, S1, S2, mconv, theta_t, true, data, weight, cpart, mask, nullptr));
+      GF_TRY(c, conv_chi2(cs, b, p, mpad, S1, S2, mconv, theta_t, true, data, weight, cpart, mask, nullptr, &c->fork));
       GF_TRY(c, launch_nm_step(cs, b, p->d_c2_first, cpart, &o, state, X, F, XR, theta_t, mask, trace, trace_cap,
                                cnt));
       return GF_OK;
@@ -1609,14 +1619,14 @@ gf_status gf_mcmc_run(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float
   hipStream_t cs = c->stream;
   // chi^2 of the start point
   GF_TRY(c, launch_eval_d(cs, b, theta, S, c->d_bn, mpad, nullptr, nullptr));
-  GF_TRY(c, conv_chi2(cs, b, p, mpad, S1, S2, mconv, theta, true, data, weight, cpart, nullptr, nullptr));
+  GF_TRY(c, conv_chi2(cs, b, p, mpad, S1, S2, mconv, theta, true, data, weight, cpart, nullptr, nullptr, &c->fork));
   GF_TRY(c, launch_pair_final(cs, b->n, p->d_c2_first, cpart, pairs, nullptr));
   GF_TRY(c, launch_mcmc_init(cs, b->n, pairs, chi2_d, tstep));
   auto step = [&](hipStream_t sx) -> gf_status {
     GF_TRY(c, launch_mcmc_propose(sx, b, theta, o.scale, o.lo, o.hi, o.key0, o.key1, o.stream, o.step0, tstep,
                                   theta_t, mask));
     GF_TRY(c, launch_eval_d(sx, b, theta_t, S, c->d_bn, mpad, mask, nullptr));
-    GF_TRY(c, conv_chi2(sx, b, p, mpad, S1, S2, mconv, theta_t, true, data, weight, cpart, mask, nullptr));
+    GF_TRY(c, conv_chi2(sx, b, p, mpad, S1, S2, mconv, theta_t, true, data, weight, cpart, mask, nullptr, &c->fork));
     GF_TRY(c, launch_mcmc_accept(sx, b, p->d_c2_first, cpart, mask, o.key0, o.key1, o.stream, o.step0, tstep, theta, theta_t, chi2_d,
                                  accepted, samples, o.thin));
     return GF_OK;

@@ -285,7 +285,17 @@ struct LmGraphKey {
 };
 // Process-wide unique, nonzero id for batches and PSFs.
 uint64_t next_uid();
+
+// A side stream and its fork and join events: launch_fft_conv runs the
+// one-workgroup FFT stamps on the side stream while the multi-pass stamps run
+// on the caller's stream (the two touch disjoint stamps), and joins before it
+// returns.  A null side stream runs both on the caller's stream.
+struct FftFork {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 }  // namespace gf
+
 
 // ---------------------------------------------------------------- host objects
 struct gf_ctx {
@@ -303,6 +313,10 @@ struct gf_ctx {
   // run concurrently, e.g. the per-line-count kernels of a line fit
   hipStream_t side[GF_LINE_MAX_LINES] = {};
   hipEvent_t side_ev[GF_LINE_MAX_LINES + 1] = {};
+  // the one-workgroup FFT launches of a convolution run on this stream
+  // beside the multi-pass launches of the same convolution (created with
+  // the context, so a captured LM iteration can fork onto it)
+  gf::FftFork fork{};
   // LM fits: their stream and join event, and the last captured iteration
   // graph with what it was captured for (replayed while the key matches)
   hipStream_t lm_stream = nullptr;

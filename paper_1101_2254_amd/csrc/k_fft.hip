@@ -575,12 +575,32 @@ static hipError_t multipass_conv(hipStream_t st, const gf_batch *b, const gf_psf
 
 // Every FFT-path stamp of the PSF (or of the view): the one-workgroup
 // kernels for the stamps on that form, the three multi-pass launches for the
-// rest.
+// rest.  With a fork stream and both forms present, the one-workgroup
+// launches run on it beside the multi-pass ones (disjoint stamps and outputs)
+// and the caller's stream waits for them before anything it runs next; with
+// timing records on, both run on the caller's stream so that each record
+// times its kernels alone.
 hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
                            float2 *S1, float2 *S2, float *out, const int *mask, const WorkView *v,
-                           const Chi2Epi *ep) {
+                           const Chi2Epi *ep, const FftFork *fork) {
   if (ep && n_ch != 1) return hipErrorInvalidValue;
-  hipError_t e = launch_fft2d(st, b, p, ep ? MODE_CHI2 : MODE_CONV, in, n_ch, out, mask, v, ep);
+  const int mode = ep ? MODE_CHI2 : MODE_CONV;
+  const bool has_f2d = (v && v->f2d) ? v->f2d_first[kF2dBuckets] > v->f2d_first[0]
+                                     : p->f2d_first[kF2dBuckets] > p->f2d_first[0];
+  const bool has_mp = (v && v->rows) ? v->n_rows > 0 : !p->h_rows.empty();
+  const bool timed = t_prof && t_prof->on;
+  if (fork && fork->side && has_f2d && has_mp && !timed) {
+    hipError_t e = hipEventRecord(fork->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(fork->side, fork->fork, 0);
+    if (e != hipSuccess) return e;
+    const hipError_t ef = launch_fft2d(fork->side, b, p, mode, in, n_ch, out, mask, v, ep);
+    const hipError_t em = multipass_conv(st, b, p, in, n_ch, S1, S2, out, mask, v, ep);
+    // join even after a failed launch, so no stream is left forked
+    e = hipEventRecord(fork->join, fork->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, fork->join, 0);
+    return ef != hipSuccess ? ef : em != hipSuccess ? em : e;
+  }
+  hipError_t e = launch_fft2d(st, b, p, mode, in, n_ch, out, mask, v, ep);
   if (e != hipSuccess) return e;
   return multipass_conv(st, b, p, in, n_ch, S1, S2, out, mask, v, ep);
 }
