@@ -103,3 +103,42 @@ def test_fused_fit_ragged_batch_and_alone(ctx, gfo, spec):
         ref = gfo.chi2(gb.d32[s].astype(np.float64), gb.w32[s].astype(np.float64), m)
         wm = np.sqrt(np.sum(gb.w32[s] * m * m))
         assert abs(info["chi2"][s] - ref) <= 1e-5 * ref + 2 * 2e-6 * np.sqrt(ref) * wm + 1e-9, (s, info["chi2"][s], ref)
+
+
+def test_concurrent_fft_forms_same_bits(gfo):
+    """A batch with stamps on both FFT forms: the one-workgroup launches run
+    on the context's side stream beside the multi-pass ones, in eager calls
+    and inside the captured LM iteration.  With timing records on, both run
+    on the calling stream; the two orders give the same bits."""
+    from paper_1101_2254_amd import _lib as L
+    stamps = _stamps(33)
+    data, weights = _observed(gfo, stamps)
+    lo = np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in stamps])
+    hi = np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in stamps])
+    start = np.concatenate([s.start for s in stamps])
+    out = []
+    for timed in (False, True):
+        c = ops.Context(0)
+        keep_fft_forms(c)
+        probe = GpuBatch(c, stamps, data=data, weights=weights)
+        sides = sorted({int(s) for u, s in zip(probe.psf.uses_fft, probe.psf.fft_side) if u})
+        L.gf_tune_form_set(c.ptr, sides[0], 1)      # the smallest FFT side on the multi-pass form
+        gb = GpuBatch(c, stamps, thetas=[s.start for s in stamps], data=data, weights=weights)
+        assert {1, 2} <= set(int(u) for u in gb.psf.uses_fft), list(gb.psf.uses_fft)
+        print(f"both FFT forms, timing records {'on' if timed else 'off'}", flush=True)
+        if timed:
+            L.gf_profile_start(c.ptr)
+        pairs = ops.likelihood(c, gb.batch, gb.psf, gb.theta, gb.data, gb.weight, 5)
+        mc = ops.convolve_psf(c, gb.batch, gb.psf, ops.eval_model(c, gb.batch, gb.theta, 5))
+        th, info = ops.fit_lm(c, gb.batch, gb.psf, gb.data, gb.weight, to_dev(start, torch.float64),
+                              lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-8)
+        torch.cuda.synchronize()
+        if timed:
+            L.gf_profile_stop(c.ptr)
+        out.append((pairs.cpu(), mc.cpu(), th.cpu(), info))
+        c.close()
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][2], out[1][2])
+    for k in ("chi2", "iters", "nfev"):
+        np.testing.assert_array_equal(out[0][3][k], out[1][3][k])
