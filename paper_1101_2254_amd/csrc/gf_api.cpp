@@ -266,6 +266,15 @@ extern "C" {
 
 const char *gf_version(void) { return "libgf 0.2 (gfx950)"; }
 
+static void fork_destroy(FftFork &f) {
+  for (int i = 0; i < kForkLanes; ++i) {
+    if (f.side[i]) (void)hipStreamDestroy(f.side[i]);
+    if (f.join[i]) (void)hipEventDestroy(f.join[i]);
+  }
+  if (f.fork) (void)hipEventDestroy(f.fork);
+  f = FftFork{};
+}
+
 gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
   if (!out) return GF_EINVAL;
   *out = nullptr;
@@ -294,13 +303,12 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
     return GF_ENOMEM;
   }
   if (!c->tune_path.empty()) (void)tune_load(c);   // an unreadable or foreign table is ignored
-  if (hipStreamCreateWithFlags(&c->fork.side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->fork.fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->fork.join, hipEventDisableTiming) != hipSuccess ||
-      noalloc_init(device) != hipSuccess) {
-    if (c->fork.side) (void)hipStreamDestroy(c->fork.side);
-    if (c->fork.fork) (void)hipEventDestroy(c->fork.fork);
-    if (c->fork.join) (void)hipEventDestroy(c->fork.join);
+  bool fork_ok = hipEventCreateWithFlags(&c->fork.fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < kForkLanes && fork_ok; ++i)
+    fork_ok = hipStreamCreateWithFlags(&c->fork.side[i], hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->fork.join[i], hipEventDisableTiming) == hipSuccess;
+  if (!fork_ok || noalloc_init(device) != hipSuccess) {
+    fork_destroy(c->fork);
     dfree(c->d_bn);
     dfree(c->d_counters);
     (void)hipHostFree(c->h_pinned);
@@ -327,9 +335,7 @@ void gf_destroy(gf_ctx *c) {
   if (c->lm_graph) (void)hipGraphDestroy(c->lm_graph);
   if (c->lm_stream) (void)hipStreamDestroy(c->lm_stream);
   if (c->lm_ev) (void)hipEventDestroy(c->lm_ev);
-  if (c->fork.side) (void)hipStreamDestroy(c->fork.side);
-  if (c->fork.fork) (void)hipEventDestroy(c->fork.fork);
-  if (c->fork.join) (void)hipEventDestroy(c->fork.join);
+  fork_destroy(c->fork);
   delete c;
 }
 

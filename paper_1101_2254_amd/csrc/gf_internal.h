@@ -286,13 +286,19 @@ struct LmGraphKey {
 // Process-wide unique, nonzero id for batches and PSFs.
 uint64_t next_uid();
 
-// A side stream and its fork and join events: launch_fft_conv runs the
-// one-workgroup FFT stamps on the side stream while the multi-pass stamps run
-// on the caller's stream (the two touch disjoint stamps), and joins before it
-// returns.  A null side stream runs both on the caller's stream.
+// Side streams and their fork and join events: launch_fft_conv runs the
+// one-workgroup FFT buckets on the side streams (bucket b on lane
+// kForkLane[b]) while the multi-pass stamps run on the caller's stream (all
+// of them touch disjoint stamps), and joins before it returns, so the tail
+// of each launch overlaps the others.  Null streams run everything on the
+// caller's stream.  With the caller's stream, four streams in all: the
+// hardware queues a process gets by default.
+constexpr int kForkLanes = 3;
+constexpr int kForkLane[kF2dBuckets] = {2, 2, 1, 0, 0};
 struct FftFork {
-  hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t side[kForkLanes] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kForkLanes] = {};
 };
 }  // namespace gf
 

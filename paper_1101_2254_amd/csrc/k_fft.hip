@@ -512,7 +512,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
 
 // ----------------------------------------------------------------- launchers
 hipError_t launch_fft2d(hipStream_t st, const gf_batch *b, const gf_psf *p, int mode, const float *in, int n_ch,
-                        float *out, const int *mask, const WorkView *v, const Chi2Epi *ep);
+                        float *out, const int *mask, const WorkView *v, const Chi2Epi *ep,
+                        const hipStream_t *bst = nullptr);
 
 static size_t fft_lds_bytes(const gf_psf *p) { return (size_t)(fft_lds(fft_cap(p->rmax)) + p->max_L) * sizeof(float2); }
 
@@ -575,29 +576,43 @@ static hipError_t multipass_conv(hipStream_t st, const gf_batch *b, const gf_psf
 
 // Every FFT-path stamp of the PSF (or of the view): the one-workgroup
 // kernels for the stamps on that form, the three multi-pass launches for the
-// rest.  With a fork stream and both forms present, the one-workgroup
-// launches run on it beside the multi-pass ones (disjoint stamps and outputs)
-// and the caller's stream waits for them before anything it runs next; with
-// timing records on, both run on the caller's stream so that each record
-// times its kernels alone.
+// rest.  With fork streams and work for more than one of them, the
+// one-workgroup buckets run on the side streams (lane kForkLane[b]) beside
+// the multi-pass launches (disjoint stamps and outputs) and the caller's
+// stream waits for them before anything it runs next; with timing records
+// on, everything runs on the caller's stream so that each record times its
+// kernels alone.
 hipError_t launch_fft_conv(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *in, int n_ch,
                            float2 *S1, float2 *S2, float *out, const int *mask, const WorkView *v,
                            const Chi2Epi *ep, const FftFork *fork) {
   if (ep && n_ch != 1) return hipErrorInvalidValue;
   const int mode = ep ? MODE_CHI2 : MODE_CONV;
-  const bool has_f2d = (v && v->f2d) ? v->f2d_first[kF2dBuckets] > v->f2d_first[0]
-                                     : p->f2d_first[kF2dBuckets] > p->f2d_first[0];
+  const int *first = (v && v->f2d) ? v->f2d_first : p->f2d_first;
   const bool has_mp = (v && v->rows) ? v->n_rows > 0 : !p->h_rows.empty();
+  bool lane_used[kForkLanes] = {};
+  int lanes = has_mp ? 1 : 0;
+  for (int k = 0; k < kF2dBuckets; ++k)
+    if (first[k + 1] > first[k] && !lane_used[kForkLane[k]]) {
+      lane_used[kForkLane[k]] = true;
+      ++lanes;
+    }
   const bool timed = t_prof && t_prof->on;
-  if (fork && fork->side && has_f2d && has_mp && !timed) {
+  if (fork && fork->fork && lanes > 1 && !timed) {
     hipError_t e = hipEventRecord(fork->fork, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(fork->side, fork->fork, 0);
+    for (int i = 0; i < kForkLanes && e == hipSuccess; ++i)
+      if (lane_used[i]) e = hipStreamWaitEvent(fork->side[i], fork->fork, 0);
     if (e != hipSuccess) return e;
-    const hipError_t ef = launch_fft2d(fork->side, b, p, mode, in, n_ch, out, mask, v, ep);
+    hipStream_t bst[kF2dBuckets];
+    for (int k = 0; k < kF2dBuckets; ++k) bst[k] = fork->side[kForkLane[k]];
+    const hipError_t ef = launch_fft2d(st, b, p, mode, in, n_ch, out, mask, v, ep, bst);
     const hipError_t em = multipass_conv(st, b, p, in, n_ch, S1, S2, out, mask, v, ep);
-    // join even after a failed launch, so no stream is left forked
-    e = hipEventRecord(fork->join, fork->side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, fork->join, 0);
+    // join every forked stream even after a failed launch, so none is left forked
+    for (int i = 0; i < kForkLanes; ++i) {
+      if (!lane_used[i]) continue;
+      hipError_t ej = hipEventRecord(fork->join[i], fork->side[i]);
+      if (ej == hipSuccess) ej = hipStreamWaitEvent(st, fork->join[i], 0);
+      if (e == hipSuccess) e = ej;
+    }
     return ef != hipSuccess ? ef : em != hipSuccess ? em : e;
   }
   hipError_t e = launch_fft2d(st, b, p, mode, in, n_ch, out, mask, v, ep);

@@ -14,9 +14,10 @@ static hipError_t f2d_launch(int bucket, int mode, hipStream_t st, int n, int n_
 
 // The fused convolutions of every bucket in the view (or the PSF's full
 // lists): CONV writes the n_ch valid images, CHI2 (one channel) writes the
-// chi^2 partials, CORR the adjoint onto the padded grid.
+// chi^2 partials, CORR the adjoint onto the padded grid.  bst: a stream per
+// bucket (null: all on st).
 hipError_t launch_fft2d(hipStream_t st, const gf_batch *b, const gf_psf *p, int mode, const float *in, int n_ch,
-                        float *out, const int *mask, const WorkView *v, const Chi2Epi *ep) {
+                        float *out, const int *mask, const WorkView *v, const Chi2Epi *ep, const hipStream_t *bst) {
   const bool view = v && v->f2d;
   const Work *list = view ? v->f2d : p->d_f2d;
   const int *first = view ? v->f2d_first : p->f2d_first;
@@ -27,7 +28,7 @@ hipError_t launch_fft2d(hipStream_t st, const gf_batch *b, const gf_psf *p, int 
   for (int k = 0; k < kF2dBuckets; ++k) {
     const int n = first[k + 1] - first[k];
     if (n == 0) continue;
-    const hipError_t r = f2d_launch(k, mode, st, n, mode == MODE_CHI2 ? 1 : n_ch, b->d_desc, p->d_path, p->d_tw,
+    const hipError_t r = f2d_launch(k, mode, bst ? bst[k] : st, n, mode == MODE_CHI2 ? 1 : n_ch, b->d_desc, p->d_path, p->d_tw,
                                     list + first[k], in, out, p->d_otf, nullptr, mask, e);
     if (r != hipSuccess) return r;
   }
