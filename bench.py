@@ -115,11 +115,14 @@ def fft_conv_flops(L, Mh, H):
     return (Mh + 1) // 2 * c + 2 * Lh * c + 6 * Lh * L + (H + 1) // 2 * c
 
 
-def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=False):
+def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=False, keep_model=False):
     """Algorithmic work per launch of each kernel when every stamp of the
     batch takes part: (bound, units).  stamps: list of (H, W, K); paths and
     sides from the prepared PSF; nch: Jacobian channels per launch; nimg:
-    pixels of the distinct observations (shared-image batches)."""
+    pixels of the distinct observations (shared-image batches); keep_model:
+    a plain LM fit of one-component stamps, whose chi^2 passes also write the
+    convolved model and whose Jacobian passes evaluate and convolve every
+    channel but Ie's (the normal equations take it from that model)."""
     npad = npix = 0
     f2 = dict(pad=0, pix=0, otf=0, n=0, flops=0.0)
     mp = dict(rows=0, cols=0, irows=0, irows_chi2=0, otf=0, pad=0, pix=0, n=0, flops=0.0)
@@ -150,19 +153,23 @@ def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=Fals
     img = npix if nimg is None else nimg
     dw = 8 * (img if nimg is not None else f2["pix"])      # data + weight read by the fused chi^2
     dw_mp = 8 * (img if nimg is not None else mp["pix"])
+    if keep_model:   # the model written beside the chi^2 partials
+        dw += 4 * f2["pix"]
+        dw_mp += 4 * mp["pix"]
+    nconv = nch - 1 if keep_model else nch   # convolved Jacobian channels
     t = {
         "k_eval": ("alu", npad * ncomp * S * S * EVAL_FLOP_PER_SUB),
         "k_eval_jac": ("alu", npad * ncomp * S * S * EVAL_JAC_FLOP_PER_SUB),
         "k_gram": ("hbm", npix * (4 * nch + 8)),
         "k_chi2": ("hbm", 4 * npix + 8 * img),
         # the one-workgroup convolutions move only their definitional bytes
-        "k_fft2d": ("hbm", nch * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"]),
+        "k_fft2d": ("hbm", nconv * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"]),
         "k_fft2d_chi2": ("hbm", 4 * f2["pad"] + dw + f2["otf"]),
         # the multi-pass kernels: each pass's own reads and writes (spectra
         # included)
-        "k_fft_rows": ("hbm", nch * mp["rows"]),
-        "k_fft_cols": ("hbm", nch * mp["cols"] + mp["otf"]),
-        "k_fft_irows": ("hbm", nch * mp["irows"]),
+        "k_fft_rows": ("hbm", nconv * mp["rows"]),
+        "k_fft_cols": ("hbm", nconv * mp["cols"] + mp["otf"]),
+        "k_fft_irows": ("hbm", nconv * mp["irows"]),
         "k_fft_rows.chi2": ("hbm", mp["rows"]),
         "k_fft_cols.chi2": ("hbm", mp["cols"] + mp["otf"]),
         "k_fft_irows_chi2": ("hbm", mp["irows_chi2"] + dw_mp),
@@ -170,20 +177,20 @@ def kernel_table(stamps, paths, sides, nch, ncomp, S, nimg=None, shared_otf=Fals
     stage = dict(
         # step 2 of the Jacobian channels: padded model in, stamp out, OTF once
         convolution=dict(kernels=["k_fft2d", "k_fft_rows", "k_fft_cols", "k_fft_irows"],
-                         bytes=nch * (4 * (f2["pad"] + mp["pad"]) + 4 * (f2["pix"] + mp["pix"])) + f2["otf"] +
-                         mp["otf"], flops=nch * (f2["flops"] + mp["flops"])),
+                         bytes=nconv * (4 * (f2["pad"] + mp["pad"]) + 4 * (f2["pix"] + mp["pix"])) + f2["otf"] +
+                         mp["otf"], flops=nconv * (f2["flops"] + mp["flops"])),
         # steps 2-3 of a model evaluation: padded model, data and weight in,
         # OTF once, only chi^2 out
         convolution_chi2=dict(kernels=["k_fft2d_chi2", "k_fft_rows.chi2", "k_fft_cols.chi2", "k_fft_irows_chi2"],
-                              bytes=4 * (f2["pad"] + mp["pad"]) + (8 * img if nimg is not None else
-                                                                     8 * (f2["pix"] + mp["pix"])) +
-                              f2["otf"] + mp["otf"], flops=f2["flops"] + mp["flops"]),
-        fused_convolution=dict(kernels=["k_fft2d"], bytes=nch * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"],
-                               flops=nch * f2["flops"]),
+                              bytes=4 * (f2["pad"] + mp["pad"]) + dw + dw_mp + f2["otf"] + mp["otf"]
+                              - (8 * img if nimg is not None else 0), flops=f2["flops"] + mp["flops"]),
+        fused_convolution=dict(kernels=["k_fft2d"], bytes=nconv * (4 * f2["pad"] + 4 * f2["pix"]) + f2["otf"],
+                               flops=nconv * f2["flops"]),
         fused_convolution_chi2=dict(kernels=["k_fft2d_chi2"], bytes=4 * f2["pad"] + dw + f2["otf"],
                                     flops=f2["flops"]),
         multipass_convolution=dict(kernels=["k_fft_rows", "k_fft_cols", "k_fft_irows"],
-                                   bytes=nch * (4 * mp["pad"] + 4 * mp["pix"]) + mp["otf"], flops=nch * mp["flops"]),
+                                   bytes=nconv * (4 * mp["pad"] + 4 * mp["pix"]) + mp["otf"],
+                                   flops=nconv * mp["flops"]),
     )
     return t, stage, dict(npad=npad, npix=npix, fused_stamps=f2["n"], multipass_stamps=mp["n"])
 
@@ -271,11 +278,11 @@ def stage_fractions(prof, stage, peaks=None):
 # source is the one the counters were taken on (first 16 hex digits of the
 # SHA-256 of each listed source).
 TRAFFIC = {
-    ("c3", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "adb99cbbc85be344"}, bytes=3.0316e+09,
+    ("c3", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "9228be28108cf693"}, bytes=2.6091e+09,
                                summary="profiles/c3_batch_hbm_traffic.md"),
-    ("c2", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "adb99cbbc85be344"}, bytes=1.8805e+07,
+    ("c2", "k_eval_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "9228be28108cf693"}, bytes=1.8807e+07,
                                summary="profiles/c2_fit_hbm_traffic.md"),
-    ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "adb99cbbc85be344"}, bytes=3.8622e+08,
+    ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "9228be28108cf693"}, bytes=3.8620e+08,
                            summary="profiles/c4_likelihood_hbm_traffic.md"),
     ("cube", "k_cube_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_cube.hip": "b023150d1a31c379"}, bytes=2.8513e+09,
                                  summary="profiles/cube_fit_hbm_traffic.md"),
@@ -371,7 +378,7 @@ def run_c3(args, torch, ops, synth, peaks, steps=None, warmup=None):
     # the first iteration, kernel by kernel: every stamp is active
     prof, _ = profile(ctx, lambda: step(use_graph=0, max_iter=1))
     geo = [(s.H, s.W, s.K) for s in stamps]
-    table, stage, sizes = kernel_table(geo, psf.uses_fft, psf.fft_side, 7, 1, 5)
+    table, stage, sizes = kernel_table(geo, psf.uses_fft, psf.fft_side, 7, 1, 5, keep_model=True)
     rl, kern = roofline(prof, table, peaks)
     pix = np.array([s.H * s.W for s in stamps], dtype=np.float64)
     evals_pix = float(np.sum((info["nfev"] + info["njev"]) * pix))
@@ -648,7 +655,8 @@ def run_c5(args, torch, ops, synth, peaks, steps=None, warmup=None):
     # roofline of the first LM iteration of the network-seeded fit (every
     # stamp active)
     prof1, _ = profile(ctx, lambda: fit(net.predict(data).reshape(-1).contiguous(), use_graph=0, max_iter=1))
-    table, stage, _ = kernel_table([(side, side, int(k)) for k in ev.batch.K], ev.psf.uses_fft, ev.psf.fft_side, 7, 1, 5)
+    table, stage, _ = kernel_table([(side, side, int(k)) for k in ev.batch.K], ev.psf.uses_fft, ev.psf.fft_side, 7, 1, 5,
+                                   keep_model=True)
     rl, kern = roofline(prof1, table, peaks)
     result.update(steps=K_, warmup=W, roofline=rl, stages=kern, stage_roofline=stage_fractions(prof1, stage, peaks),
                   roofline_profile="first LM iteration of the network-seeded fit, kernel by kernel")

@@ -33,15 +33,16 @@ hipError_t launch_direct(hipStream_t, const gf_batch *, const gf_psf *, const fl
 hipError_t launch_chi2(hipStream_t, const gf_batch *, const float *, const void *, bool, const float *,
                        const float *, float *, float2 *, unsigned int *, float2 *, const int *);
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float *, int, int, const int *, const WorkView *, float2 *, int px);
+                            const float *, float *, int, int, const int *, const WorkView *, float2 *, int px,
+                            const float *mie);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
-                          int *);
+                          int *, bool model_ie);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *,
                            const WorkView *, int px);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const int32_t *, const float2 *,
                             LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *,
-                            const WorkView *);
+                            const WorkView *, bool model_ie);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 }  // namespace gf
 
@@ -353,13 +354,13 @@ gf_status gf_cube_fit_lm(gf_ctx *c, gf_cube_batch *cb, const float *data, const 
   st = steps12(c, cb, cs, theta, S, Sv, 1, nullptr, B);
   if (st != GF_OK) return st;
   CUBE_TRY(c, launch_chi2(cs, fb, B.conv, theta, true, data, weight, nullptr, B.part, nullptr, B.c2, nullptr));
-  CUBE_TRY(c, launch_lm_init(cs, fb, o.lambda0, fb->d_pix_first, B.part, B.st, B.mjac, B.mtrial, B.cnt));
+  CUBE_TRY(c, launch_lm_init(cs, fb, o.lambda0, fb->d_pix_first, B.part, B.st, B.mjac, B.mtrial, B.cnt, false));
   for (int it = 0; it < o.max_iter; ++it) {
     // Jacobian of the cubes that need one, their normal equations
     st = steps12(c, cb, cs, theta, S, Sv, kJ, B.mjac, B);
     if (st != GF_OK) return st;
     CUBE_TRY(c, launch_normal_eq(cs, fb, B.conv, theta, data, weight, B.npart, 256, kJ, B.mjac, nullptr, nullptr,
-                                 kCubePX));
+                                 kCubePX, nullptr));
     CUBE_TRY(c, launch_lm_solve(cs, fb, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, nullptr,
                                 nullptr, c->d_bn, nullptr, kCubePX));
     // trial point: model, chi^2, accept or reject
@@ -368,7 +369,7 @@ gf_status gf_cube_fit_lm(gf_ctx *c, gf_cube_batch *cb, const float *data, const 
     CUBE_TRY(c, launch_chi2(cs, fb, B.conv, B.theta_t, true, data, weight, nullptr, B.part, nullptr, B.c2,
                             B.mtrial));
     CUBE_TRY(c, launch_lm_update(cs, fb, &o, fb->d_pix_first, B.part, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, nullptr, nullptr, nullptr));
+                                 B.cnt, nullptr, nullptr, nullptr, false));
     if ((it + 1) % o.poll_every == 0 || it + 1 == o.max_iter) {
       CUBE_TRY(c, hipMemcpyAsync(c->h_pinned, B.cnt, sizeof(int), hipMemcpyDeviceToHost, cs));
       CUBE_TRY(c, hipStreamSynchronize(cs));

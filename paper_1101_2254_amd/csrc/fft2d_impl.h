@@ -323,6 +323,7 @@ __device__ __forceinline__ void f2_body(float2 *__restrict__ buf, float2 *__rest
     const int lane = tid & 63, wv = tid >> 6;
     constexpr int NW = NT / 64;
     float da[NCOL], wa[NCOL], db[NCOL], wb[NCOL];
+    float *mdst = (ep.model && d.ncomp == 1) ? ep.model + d.pix : nullptr;
     auto fetch = [&](int t) {
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) {
@@ -348,6 +349,10 @@ __device__ __forceinline__ void f2_body(float2 *__restrict__ buf, float2 *__rest
           const float2 v = buf[lq((out_row0 + 2 * t) * LH + out_col0 + x)];
           ea[c] = sqrtf(wa[c]) * (da[c] - (v.x + sky));
           eb[c] = sqrtf(wb[c]) * (db[c] - (v.y + sky));
+          if (mdst) {
+            mdst[(int64_t)(2 * t) * oc + x] = v.x;
+            if (hb) mdst[(int64_t)(2 * t + 1) * oc + x] = v.y;
+          }
         }
       }
       fetch(t + NW);
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(f2_threads(f2b_maxL(B))) void k_fft2d(const StampDe
   const int ch = rem >> 3, li = grp * 8 + (rem & 7);
   if (li >= n_list) return;
   const int s = list[li].stamp;
-  if (mask && !mask[s]) return;
+  if ((mask && !mask[s]) || skip_ie(mask, s, ch)) return;
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   f2_dispatch<MODE, NT, f2b_first(B), kF2dBucketEnd[B]>(pd.L, buf, tw, d, pd, s, ch, tw_all, in, n_ch, out, otf,

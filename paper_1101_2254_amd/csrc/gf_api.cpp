@@ -40,9 +40,10 @@ hipError_t launch_adjoint_final(hipStream_t, const gf_batch *, const int32_t *, 
 hipError_t launch_jac_assemble(hipStream_t, const gf_batch *, const float *, int, float *);
 hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *);
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
-                            const float *, float *, int, int, const int *, const WorkView *, float2 *, int px = 0);
+                            const float *, float *, int, int, const int *, const WorkView *, float2 *, int px = 0,
+                            const float *mie = nullptr);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
-                          int *);
+                          int *, bool model_ie = false);
 hipError_t launch_lm_start(hipStream_t, const gf_batch *, const double *, double *, const double *, const double *,
                            double *, int, const float4 *, CompC *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
@@ -53,7 +54,7 @@ hipError_t launch_chi2_direct(hipStream_t, const gf_batch *, const gf_psf *, con
 hipError_t launch_pair_final(hipStream_t, int, const int32_t *, const float2 *, float2 *, const int *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const int32_t *, const float2 *,
                             LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *,
-                            const WorkView *);
+                            const WorkView *, bool model_ie = false);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
 hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
@@ -244,12 +245,15 @@ void lpt_order(std::vector<Work> &v, Key key) {
 
 // Steps 2-3 for a one-channel padded model, chi^2 partials only: every stamp
 // in mask gets its partials at p->d_c2_first (FFT stamps from the inverse-row
-// pass, which writes no model image; direct stamps from the direct
-// convolution into mconv and the chi^2 kernel).
+// pass, which writes no model image unless keep_model is set, and then only
+// for one-component stamps; direct stamps from the direct convolution into
+// mconv and the chi^2 kernel).  With keep_model, mconv holds the convolved
+// model of every one-component stamp in mask afterwards.
 hipError_t conv_chi2(hipStream_t st, const gf_batch *b, const gf_psf *p, const float *mpad, float2 *S1, float2 *S2,
                      float *mconv, const void *theta, bool theta_f64, const float *data, const float *weight,
-                     float2 *part, const int *mask, const WorkView *v, const FftFork *fork) {
-  const Chi2Epi ep{data, weight, theta, theta_f64 ? 1 : 0, p->d_c2_first, part};
+                     float2 *part, const int *mask, const WorkView *v, const FftFork *fork, bool keep_model = false) {
+  Chi2Epi ep{data, weight, theta, theta_f64 ? 1 : 0, p->d_c2_first, part};
+  if (keep_model) ep.model = mconv;
   hipError_t e = launch_fft_conv(st, b, p, mpad, 1, S1, S2, mconv, mask, v, &ep, fork);
   if (e == hipSuccess) e = launch_direct(st, b, p, mpad, 1, mconv, false, mask, v);
   if (e == hipSuccess) e = launch_chi2_direct(st, b, p, mconv, theta, theta_f64, data, weight, part, mask, v);
@@ -1338,8 +1342,8 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     } else {
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
-                          nullptr, &c->fork));
-      GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt));
+                          nullptr, &c->fork, true));
+      GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt, true));
     }
     WorkView view;
     const WorkView *vw = nullptr;   // null: the full lists
@@ -1366,14 +1370,15 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw, B.cc_th, false));
       GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw, nullptr, &c->fork));
       GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
-      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr));
+      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr, 0,
+                                 B.mconv));
       GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
                                 B.cc_t, c->d_bn, vw));
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
-                          vw, &c->fork));
+                          vw, &c->fork, true));
       GF_TRY(c, launch_lm_update(cs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, B.cc_th, B.cc_t, vw));
+                                 B.cnt, B.cc_th, B.cc_t, vw, true));
       return GF_OK;
     };
     // capture one iteration into (g, e), replacing what they held

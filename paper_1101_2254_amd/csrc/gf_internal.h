@@ -168,7 +168,20 @@ struct Chi2Epi {
   int32_t theta_f64;        // theta is double (else float)
   const int32_t *first;     // first partial slot of each stamp
   float2 *part;
+  // when non-null: the convolved model of each one-component stamp (without
+  // the sky) is also written, at model + its pixel offset
+  float *model = nullptr;
 };
+
+// A Jacobian mask value with this bit set (one-component stamps of an LM fit
+// in the plain form): the Ie channel is not evaluated or convolved, and the
+// normal equations take it from the convolved model of the same point, which
+// the accepted trial's chi^2 pass left in the model buffer (the model is
+// linear in Ie: dm/dIe = (m - sky) / Ie).
+constexpr int kMaskModelIe = 2;
+__device__ __host__ inline bool skip_ie(const int *mask, int s, int ch) {
+  return mask && (mask[s] & kMaskModelIe) && ch == 2;
+}
 
 // One spectrum of a line batch.
 struct LineDesc {

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(kThreads) void k_direct(const StampDesc *__restrict
   extern __shared__ float smem[];
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
-  if (mask && !mask[s]) return;
+  if ((mask && !mask[s]) || skip_ie(mask, s, ch)) return;
   const StampDesc d = desc[s];
   const int K = d.K;
   const int Hout = MODE == 0 ? d.H : d.Mh, Wout = MODE == 0 ? d.W : d.Mw;

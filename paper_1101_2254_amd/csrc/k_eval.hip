@@ -194,8 +194,10 @@ __global__ __launch_bounds__(kThreads) void k_eval_jac(const StampDesc *__restri
     }
     float g[kNPC];
     grad_finish(C, acc, g);
+    const bool no_ie = skip_ie(mask, s, kNPC * k + 2);
 #pragma unroll
-    for (int q = 0; q < kNPC; ++q) o[(int64_t)(kNPC * k + q) * npad] = g[q] * (1.0f / (float)(S * S));
+    for (int q = 0; q < kNPC; ++q)
+      if (!(q == 2 && no_ie)) o[(int64_t)(kNPC * k + q) * npad] = g[q] * (1.0f / (float)(S * S));
   }
 }
 

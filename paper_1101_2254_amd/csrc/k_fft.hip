@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows(const StampDesc *__restri
   constexpr int CAP = fft_cap(RMAX), LDS0 = fft_lds(CAP), NIT = fft_iters(CAP);
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
-  if (mask && !mask[s]) return;
+  if ((mask && !mask[s]) || skip_ie(mask, s, ch)) return;
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   const FftPlan &pl = plans[pd.plan];
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(const StampDesc *__restri
   if (ux >= nx) return;
   const Work w = work[ux];
   const int s = w.stamp;
-  if (mask && !mask[s]) return;
+  if ((mask && !mask[s]) || skip_ie(mask, s, ch)) return;
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   const FftPlan &pl = plans[pd.plan];
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   constexpr int CAP = fft_cap(RMAX), LDS0 = fft_lds(CAP), NIT = fft_iters(CAP);
   const Work w = work[blockIdx.x];
   const int s = w.stamp, ch = blockIdx.y;
-  if (mask && !mask[s]) return;
+  if ((mask && !mask[s]) || skip_ie(mask, s, ch)) return;
   const StampDesc d = desc[s];
   const PathDesc pd = path[s];
   const FftPlan &pl = plans[pd.plan];
@@ -463,6 +463,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
       wb[it] = bload_f32(rw, inb ? pa + (uint32_t)oc * 4u : kOutOfRange);
     }
     float2 sq[NIT];
+    float *mdst = (ep.model && d.ncomp == 1) ? ep.model + d.pix : nullptr;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int idx = (int)threadIdx.x + it * kThreads;
@@ -473,6 +474,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
         const float ea = sqrtf(wa[it]) * (da[it] - (v.x + sky));
         const float eb = sqrtf(wb[it]) * (db[it] - (v.y + sky));
         sq[it] = make_float2(ea * ea, eb * eb);
+        if (mdst) {
+          const int ra = r0 + 2 * t;
+          if (ra < g.out_rows) mdst[(int64_t)ra * oc + x] = v.x;
+          if (ra + 1 < g.out_rows) mdst[(int64_t)(ra + 1) * oc + x] = v.y;
+        }
       }
     }
     __syncthreads();

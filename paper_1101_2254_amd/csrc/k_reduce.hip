@@ -325,7 +325,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
                                             const double *__restrict__ theta, const float *__restrict__ data,
                                             const float *__restrict__ weight, float *__restrict__ part,
                                             const int32_t *__restrict__ first, const int *__restrict__ mask,
-                                            float2 *__restrict__ c2part) {
+                                            float2 *__restrict__ c2part, const float *__restrict__ mie) {
   constexpr int SK = kNPC * NC;
   constexpr int P = SK + 1 + PX;
   constexpr int NW = T / 64;
@@ -343,6 +343,10 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
 #pragma unroll
   for (int k = 0; k < NC; ++k) ie[k] = (float)theta[d.par + kNPC * k + 2];
   const float sky = (float)theta[d.par + SK];
+  // one-component stamps flagged in the mask: the Ie channel and the model
+  // from the convolved model mie of this point
+  const float *mdl = (NC == 1 && PX == 0 && mie && mask && (mask[s] & kMaskModelIe)) ? mie + d.pix : nullptr;
+  const float inv_ie = (float)(1.0 / theta[d.par + 2]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
   constexpr int per_wave = kNeqChunk / NW;
@@ -371,12 +375,21 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
       const bool ok = p < npix;
       const int pc = ok ? p : npix - 1;   // in-bounds address for the straight-line loads
       float jv[NJ];
-#pragma unroll
-      for (int c = 0; c < NJ; ++c) jv[c] = J[(int64_t)c * npix + pc];
-      const float wt = weight[d.img + pc], dv = data[d.img + pc];
       float m = sky;
+      if (mdl) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) m = fmaf(ie[c], jv[kNPC * c + 2], m);
+        for (int c = 0; c < NJ; ++c)
+          if (c != 2) jv[c] = J[(int64_t)c * npix + pc];
+        const float mv = mdl[pc];
+        jv[2] = mv * inv_ie;
+        m = sky + mv;
+      } else {
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) jv[c] = J[(int64_t)c * npix + pc];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) m = fmaf(ie[c], jv[kNPC * c + 2], m);
+      }
+      const float wt = weight[d.img + pc], dv = data[d.img + pc];
       wave_sync();   // the previous block's operands have been read
 #pragma unroll
       for (int c = 0; c < NJ; ++c) sg[c][lane] = ok ? jv[c] : 0.0f;
@@ -431,7 +444,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
 
 hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, const double *theta,
                             const float *data, const float *weight, float *part, int nacc_stride, int nchan,
-                            const int *mask, const WorkView *v, float2 *c2part, int px) {
+                            const int *mask, const WorkView *v, float2 *c2part, int px, const float *mie) {
   (void)nacc_stride;
   const bool view = v && v->neq;
   const Work *lst = view ? v->neq : b->d_neq;
@@ -446,14 +459,16 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
   }
 #define GF_GRAM(NC, C2, T, L, G)                                                                                \
   hipLaunchKernelGGL((k_gram<NC, C2, T>), dim3((unsigned)(G)), dim3(T), 0, st, b->d_desc, L, jc, nchan, theta,   \
-                     data, weight, part, b->d_neq_first, mask, c2part)
+                     data, weight, part, b->d_neq_first, mask, c2part, mie)
   if (px == kCubePX) {   // one-component stamps with the cube's kinematic parameters, no chi^2 output
     if (nbig > 0)
       hipLaunchKernelGGL((k_gram<1, false, 512, kCubePX>), dim3((unsigned)nbig), dim3(512), 0, st, b->d_desc, lst,
-                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr);
+                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr,
+                         (const float *)nullptr);
     if (n > nbig)
       hipLaunchKernelGGL((k_gram<1, false, 256, kCubePX>), dim3((unsigned)(n - nbig)), dim3(256), 0, st, b->d_desc,
-                         lst + nbig, jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr);
+                         lst + nbig, jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr,
+                         (const float *)nullptr);
     return hipGetLastError();
   }
   if (px != 0) return hipErrorInvalidValue;
@@ -487,15 +502,17 @@ struct LMParams {
   CompC *cc_t, *cc_th;
   const float4 *bn;
   int32_t oversample;
+  int32_t model_ie;   // flag one-component stamps' Jacobian masks with kMaskModelIe
 };
 
 // Start: one wave per stamp adds the chi^2 partials of the (clipped) start
 // point in the order of k_pair_final (the same value, bit for bit), and its
 // first lane sets up the stamp's state.
-__global__ __launch_bounds__(64) void k_lm_init(int n, double lambda0, const int32_t *__restrict__ first,
+__global__ __launch_bounds__(64) void k_lm_init(const StampDesc *__restrict__ desc, int n, double lambda0,
+                                                const int32_t *__restrict__ first,
                                                 const float2 *__restrict__ part, LMState *__restrict__ st,
                                                 int *__restrict__ mjac, int *__restrict__ mtrial,
-                                                int *__restrict__ active_count) {
+                                                int *__restrict__ active_count, int model_ie) {
   const int s = blockIdx.x;
   if (s == 0 && threadIdx.x == 0) *active_count = n;
   F2 r = {0.f, 0.f};
@@ -524,7 +541,7 @@ __global__ __launch_bounds__(64) void k_lm_init(int n, double lambda0, const int
     S.active = 0;
   }
   st[s] = S;
-  mjac[s] = S.active;
+  mjac[s] = S.active ? (model_ie && desc[s].ncomp == 1 ? 1 | kMaskModelIe : 1) : 0;
   mtrial[s] = 0;
 }
 
@@ -846,7 +863,7 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
   }
   S.trial = 0;
   mtrial[s] = 0;
-  mjac[s] = S.active && S.need_jac;
+  mjac[s] = (S.active && S.need_jac) ? (prm.model_ie && d.ncomp == 1 ? 1 | kMaskModelIe : 1) : 0;
   st[s] = S;
   if (S.active) atomicAdd(active_count, 1);
 }
@@ -931,9 +948,9 @@ hipError_t launch_expand_starts(hipStream_t st, int G, int S, const double *thet
 }
 
 hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, const int32_t *first,
-                          const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt) {
-  hipLaunchKernelGGL(k_lm_init, dim3((unsigned)b->n), dim3(64), 0, st, b->n, lambda0, first, part, S, mjac, mtrial,
-                     cnt);
+                          const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt, bool model_ie) {
+  hipLaunchKernelGGL(k_lm_init, dim3((unsigned)b->n), dim3(64), 0, st, b->d_desc, b->n, lambda0, first, part, S, mjac,
+                     mtrial, cnt, model_ie ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -941,7 +958,7 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
                            double *Ag, const double *theta, double *theta_t, int *mjac, int *mtrial, int *cnt,
                            CompC *cc_th, CompC *cc_t, const float4 *bn, const WorkView *v, int px) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
-               o->free_mask, cc_t, cc_th, bn, o->oversample};
+               o->free_mask, cc_t, cc_th, bn, o->oversample, 0};
   ProfScope ps(st, "k_lm_solve");
   bool has1 = false, has2 = false;
   for (const auto &d : b->h_desc) {
@@ -970,9 +987,9 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
 
 hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const int32_t *first,
                             const float2 *part, LMState *S, double *theta, const double *theta_t, int *mjac,
-                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t, const WorkView *v) {
+                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t, const WorkView *v, bool model_ie) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
-               o->free_mask, cc_t, cc_th, nullptr, o->oversample};
+               o->free_mask, cc_t, cc_th, nullptr, o->oversample, model_ie ? 1 : 0};
   ProfScope ps(st, "k_lm_update");
   const Work *list = v && v->stamps ? v->stamps : nullptr;
   const unsigned grid = list ? (unsigned)v->n_stamps : (unsigned)b->n;
