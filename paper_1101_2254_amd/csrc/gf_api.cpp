@@ -42,6 +42,7 @@ hipError_t launch_add_sky(hipStream_t, const gf_batch *, const float *, float *)
 hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const double *, const float *,
                             const float *, float *, int, int, const int *, const WorkView *, float2 *, int px = 0,
                             const float *mie = nullptr);
+hipError_t launch_copy_runs(hipStream_t, const CopyRun *, int, Work *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
                           int *, bool model_ie = false);
 hipError_t launch_lm_start(hipStream_t, const gf_batch *, const double *, double *, const double *, const double *,
@@ -852,6 +853,12 @@ gf_status gf_psf_prepare(gf_ctx *c, const gf_batch *b, const float *taps, int mo
   if (e == hipSuccess) e = upload(&d_otmp, otf_tmp);
   if (e == hipSuccess) e = upload(&d_ooff, otf_off);
   if (e == hipSuccess) e = upload(&p->d_f2d, p->h_f2d);
+  if (e == hipSuccess) e = upload(&p->d_rows_alt, p->h_rows_alt);
+  if (e == hipSuccess) e = upload(&p->d_cols_alt, p->h_cols_alt);
+  if (e == hipSuccess) e = upload(&p->d_irows_alt, p->h_irows_alt);
+  if (e == hipSuccess) e = upload(&p->d_rows_n_alt, p->h_rows_n_alt);
+  if (e == hipSuccess) e = upload(&p->d_cols_n_alt, p->h_cols_n_alt);
+  if (e == hipSuccess) e = upload(&p->d_irows_n_alt, p->h_irows_n_alt);
   if (e == hipSuccess) e = upload(&d_o2d, f2d_otf);
   if (e == hipSuccess && p->n_otf > 0) e = hipMalloc((void **)&p->d_otf, p->n_otf * sizeof(float2));
   if (e != hipSuccess) {
@@ -915,6 +922,12 @@ void gf_psf_destroy(gf_psf *p) {
   dfree(p->d_c2_first);
   dfree(p->d_pix_direct);
   dfree(p->d_f2d);
+  dfree(p->d_rows_alt);
+  dfree(p->d_cols_alt);
+  dfree(p->d_irows_alt);
+  dfree(p->d_rows_n_alt);
+  dfree(p->d_cols_n_alt);
+  dfree(p->d_irows_n_alt);
   delete p;
 }
 
@@ -1125,6 +1138,7 @@ struct LMBufs {
   LMState *st;
   int *mjac, *mtrial, *cnt;
   Work *lists;   // compacted work lists of the stamps still iterating
+  CopyRun *plan;   // the copies that restrict them
   CompC *cc_th, *cc_t;   // component constants of theta and of the trial point
 };
 
@@ -1135,97 +1149,140 @@ int64_t full_list_units(const gf_batch *b, const gf_psf *p) {
          p->h_irows_alt.size() + p->h_rows_n_alt.size() + p->h_cols_n_alt.size() + p->h_irows_n_alt.size() + b->n;
 }
 
-// Work lists restricted to the stamps flagged in act, filtered from `from`
-// (the previous restriction, or the full lists when `from` is empty), stored
-// in `to` and uploaded into dev; the view points into dev.
-struct HostLists {
-  std::vector<Work> eval, pix, neq, rows, cols, irows, rows_n, cols_n, irows_n, direct, pix_direct, f2d, stamps;
-  bool empty() const { return eval.empty() && pix.empty(); }
+// The lists an LM fit restricts, in a fixed order: the batch's evaluation,
+// chi^2 and Gram units, the PSF's multi-pass units (both launch shapes),
+// direct tiles and chi^2 units, one-workgroup entries, and the multi-pass
+// units kept for the one-workgroup stamps.
+enum {
+  RL_EVAL, RL_PIX, RL_NEQ, RL_ROWS, RL_COLS, RL_IROWS, RL_ROWS_N, RL_COLS_N, RL_IROWS_N, RL_DIRECT, RL_PIX_DIRECT,
+  RL_F2D, RL_ROWS_ALT, RL_COLS_ALT, RL_IROWS_ALT, RL_ROWS_N_ALT, RL_COLS_N_ALT, RL_IROWS_N_ALT, RL_COUNT
 };
 
-hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, const std::vector<char> &act,
-                          const HostLists &from, HostLists &to, Work *dev, WorkView &v) {
-  const bool full = from.empty();
-  auto filt = [&](const std::vector<Work> &src, std::vector<Work> &dst) {
-    std::vector<Work> out;
-    out.reserve(src.size());
-    for (const Work &w : src)
-      if (act[w.stamp]) out.push_back(w);
-    dst.swap(out);
-  };
-  filt(full ? b->h_eval : from.eval, to.eval);
-  filt(full ? b->h_pix : from.pix, to.pix);
-  filt(full ? b->h_neq : from.neq, to.neq);
-  filt(full ? p->h_rows : from.rows, to.rows);
-  filt(full ? p->h_cols : from.cols, to.cols);
-  filt(full ? p->h_irows : from.irows, to.irows);
-  filt(full ? p->h_rows_n : from.rows_n, to.rows_n);
-  filt(full ? p->h_cols_n : from.cols_n, to.cols_n);
-  filt(full ? p->h_irows_n : from.irows_n, to.irows_n);
-  filt(full ? p->h_direct : from.direct, to.direct);
-  filt(full ? p->h_pix_direct : from.pix_direct, to.pix_direct);
-  filt(full ? p->h_f2d : from.f2d, to.f2d);   // stays grouped by bucket (unit)
-  // Buckets with few stamps left: their workgroups would not fill the
-  // device, so those stamps move to the multi-pass launches (which spread a
-  // stamp over many workgroups) for the rest of the fit.
-  {
-    int cnt[kF2dBuckets] = {};
-    for (const Work &w : to.f2d) ++cnt[w.unit];
-    std::vector<char> mv(b->n, 0);
-    bool any = false;
-    for (const Work &w : to.f2d)
-      if (cnt[w.unit] < b->ctx->f2d_min_active[w.unit]) mv[w.stamp] = 1, any = true;
-    if (any) {
-      std::vector<Work> keep;
-      for (const Work &w : to.f2d)
-        if (!mv[w.stamp]) keep.push_back(w);
-      to.f2d.swap(keep);
-      auto add = [&](const std::vector<Work> &alt, std::vector<Work> &dst) {
-        for (const Work &w : alt)
-          if (mv[w.stamp]) dst.push_back(w);
-      };
-      add(p->h_rows_alt, to.rows);
-      add(p->h_cols_alt, to.cols);
-      add(p->h_irows_alt, to.irows);
-      add(p->h_rows_n_alt, to.rows_n);
-      add(p->h_cols_n_alt, to.cols_n);
-      add(p->h_irows_n_alt, to.irows_n);
+static void lm_lists(const gf_batch *b, const gf_psf *p, const std::vector<Work> *h[RL_COUNT],
+                     const Work *d[RL_COUNT]) {
+  const std::vector<Work> *hh[RL_COUNT] = {&b->h_eval, &b->h_pix, &b->h_neq, &p->h_rows, &p->h_cols, &p->h_irows,
+                                           &p->h_rows_n, &p->h_cols_n, &p->h_irows_n, &p->h_direct,
+                                           &p->h_pix_direct, &p->h_f2d, &p->h_rows_alt, &p->h_cols_alt,
+                                           &p->h_irows_alt, &p->h_rows_n_alt, &p->h_cols_n_alt, &p->h_irows_n_alt};
+  const Work *dd[RL_COUNT] = {b->d_eval, b->d_pix, b->d_neq, p->d_rows, p->d_cols, p->d_irows, p->d_rows_n,
+                              p->d_cols_n, p->d_irows_n, p->d_direct, p->d_pix_direct, p->d_f2d, p->d_rows_alt,
+                              p->d_cols_alt, p->d_irows_alt, p->d_rows_n_alt, p->d_cols_n_alt, p->d_irows_n_alt};
+  for (int k = 0; k < RL_COUNT; ++k) {
+    h[k] = hh[k];
+    d[k] = dd[k];
+  }
+}
+
+// Runs of every restricted list (built once per PSF); returns their total.
+static int64_t lm_runs_ensure(const gf_batch *b, const gf_psf *p) {
+  if (p->lm_runs.empty()) {
+    const std::vector<Work> *h[RL_COUNT];
+    const Work *d[RL_COUNT];
+    lm_lists(b, p, h, d);
+    p->lm_runs.resize(RL_COUNT);
+    for (int k = 0; k < RL_COUNT; ++k) {
+      ListRuns &r = p->lm_runs[k];
+      const std::vector<Work> &v = *h[k];
+      for (size_t i = 0; i < v.size(); ++i) {
+        if (i == 0 || v[i].stamp != v[i - 1].stamp) {
+          r.stamp.push_back(v[i].stamp);
+          r.beg.push_back((int32_t)i);
+          r.len.push_back(0);
+        }
+        ++r.len.back();
+      }
     }
   }
-  to.stamps.clear();
-  for (int s = 0; s < b->n; ++s)
-    if (act[s]) to.stamps.push_back({s, 0});
-  Work *q = dev;
-  auto put = [&](const std::vector<Work> &src, const Work *&ptr, int &n) -> hipError_t {
-    ptr = q;
-    n = (int)src.size();
-    if (n) {
-      hipError_t e = hipMemcpyAsync(q, src.data(), src.size() * sizeof(Work), hipMemcpyHostToDevice, st);
-      if (e != hipSuccess) return e;
+  int64_t n = 0;
+  for (const ListRuns &r : p->lm_runs) n += (int64_t)r.stamp.size();
+  return n;
+}
+
+// Work lists restricted to the stamps flagged in act, taken run by run from
+// the full device lists into dev (one copy launch over a plan uploaded to
+// plan_dev); the view points into dev.  Stamps of a one-workgroup bucket
+// with fewer active stamps than the context's minimum are flagged in moved
+// and take their multi-pass units from then on (the flag stays set for the
+// rest of the fit).  Each list keeps the order of the full list, followed
+// for the multi-pass lists by the moved stamps' units.
+hipError_t restrict_lists(hipStream_t st, const gf_batch *b, const gf_psf *p, const std::vector<char> &act,
+                          std::vector<char> &moved, CopyRun *plan_dev, Work *dev, WorkView &v) {
+  const std::vector<Work> *h[RL_COUNT];
+  const Work *d[RL_COUNT];
+  lm_lists(b, p, h, d);
+  const std::vector<ListRuns> &R = p->lm_runs;
+  // buckets with few stamps left would not fill the device: their stamps
+  // move to the multi-pass launches, which spread a stamp over many
+  // workgroups
+  {
+    const ListRuns &rf = R[RL_F2D];
+    int cnt[kF2dBuckets] = {};
+    for (size_t i = 0; i < rf.stamp.size(); ++i)
+      if (act[rf.stamp[i]] && !moved[rf.stamp[i]]) ++cnt[(*h[RL_F2D])[rf.beg[i]].unit];
+    for (size_t i = 0; i < rf.stamp.size(); ++i) {
+      const int s = rf.stamp[i];
+      if (act[s] && !moved[s] && cnt[(*h[RL_F2D])[rf.beg[i]].unit] < b->ctx->f2d_min_active[(*h[RL_F2D])[rf.beg[i]].unit])
+        moved[s] = 1;
     }
-    q += src.size();
-    return hipSuccess;
+  }
+  std::vector<CopyRun> plan;
+  int64_t off = 0;
+  // which: 0 every active stamp, 1 active stamps not moved, 2 active moved stamps
+  auto take = [&](int k, int which) {
+    const ListRuns &r = R[k];
+    for (size_t i = 0; i < r.stamp.size(); ++i) {
+      const int s = r.stamp[i];
+      if (!act[s] || (which == 1 && moved[s]) || (which == 2 && !moved[s])) continue;
+      plan.push_back(CopyRun{d[k] + r.beg[i], off, r.len[i], 0});
+      off += r.len[i];
+    }
   };
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = put(to.eval, v.eval, v.n_eval);
-  if (e == hipSuccess) e = put(to.pix, v.pix, v.n_pix);
-  if (e == hipSuccess) e = put(to.neq, v.neq, v.n_neq);
-  v.n_neq_big = 0;
-  for (const Work &w : to.neq) v.n_neq_big += b->h_desc[w.stamp].H * b->h_desc[w.stamp].W >= kNeqBigPix;
-  if (e == hipSuccess) e = put(to.rows, v.rows, v.n_rows);
-  if (e == hipSuccess) e = put(to.cols, v.cols, v.n_cols);
-  if (e == hipSuccess) e = put(to.irows, v.irows, v.n_irows);
-  if (e == hipSuccess) e = put(to.rows_n, v.rows_n, v.n_rows_n);
-  if (e == hipSuccess) e = put(to.cols_n, v.cols_n, v.n_cols_n);
-  if (e == hipSuccess) e = put(to.irows_n, v.irows_n, v.n_irows_n);
-  if (e == hipSuccess) e = put(to.direct, v.direct, v.n_direct);
-  if (e == hipSuccess) e = put(to.pix_direct, v.pix_direct, v.n_pix_direct);
-  if (e == hipSuccess) e = put(to.stamps, v.stamps, v.n_stamps);
+  auto put = [&](int k, int alt, const Work *&ptr, int &n) {
+    const int64_t start = off;
+    take(k, k == RL_F2D ? 1 : 0);
+    if (alt >= 0) take(alt, 2);
+    ptr = dev + start;
+    n = (int)(off - start);
+  };
+  put(RL_EVAL, -1, v.eval, v.n_eval);
+  put(RL_PIX, -1, v.pix, v.n_pix);
+  put(RL_NEQ, -1, v.neq, v.n_neq);
+  put(RL_ROWS, RL_ROWS_ALT, v.rows, v.n_rows);
+  put(RL_COLS, RL_COLS_ALT, v.cols, v.n_cols);
+  put(RL_IROWS, RL_IROWS_ALT, v.irows, v.n_irows);
+  put(RL_ROWS_N, RL_ROWS_N_ALT, v.rows_n, v.n_rows_n);
+  put(RL_COLS_N, RL_COLS_N_ALT, v.cols_n, v.n_cols_n);
+  put(RL_IROWS_N, RL_IROWS_N_ALT, v.irows_n, v.n_irows_n);
+  put(RL_DIRECT, -1, v.direct, v.n_direct);
+  put(RL_PIX_DIRECT, -1, v.pix_direct, v.n_pix_direct);
   int n_f2d = 0;
-  if (e == hipSuccess) e = put(to.f2d, v.f2d, n_f2d);
+  put(RL_F2D, -1, v.f2d, n_f2d);
+  // the units of stamps >= kNeqBigPix lead the Gram list, as in the full list
+  v.n_neq_big = 0;
+  {
+    const ListRuns &r = R[RL_NEQ];
+    for (size_t i = 0; i < r.stamp.size(); ++i)
+      if (act[r.stamp[i]] && b->h_desc[r.stamp[i]].H * b->h_desc[r.stamp[i]].W >= kNeqBigPix) v.n_neq_big += r.len[i];
+  }
   for (int k = 0; k <= kF2dBuckets; ++k) v.f2d_first[k] = 0;
-  for (const Work &w : to.f2d) ++v.f2d_first[w.unit + 1];
+  {
+    const ListRuns &r = R[RL_F2D];
+    for (size_t i = 0; i < r.stamp.size(); ++i)
+      if (act[r.stamp[i]] && !moved[r.stamp[i]]) ++v.f2d_first[(*h[RL_F2D])[r.beg[i]].unit + 1];
+  }
   for (int k = 0; k < kF2dBuckets; ++k) v.f2d_first[k + 1] += v.f2d_first[k];
+  // the per-stamp LM kernels' list: the active stamps, from the host
+  std::vector<Work> stamps;
+  for (int s = 0; s < b->n; ++s)
+    if (act[s]) stamps.push_back({s, 0});
+  v.stamps = dev + off;
+  v.n_stamps = (int)stamps.size();
+  hipError_t e = hipSuccess;
+  if (!stamps.empty())
+    e = hipMemcpyAsync(dev + off, stamps.data(), stamps.size() * sizeof(Work), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !plan.empty())
+    e = hipMemcpyAsync(plan_dev, plan.data(), plan.size() * sizeof(CopyRun), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_copy_runs(st, plan_dev, (int)plan.size(), dev);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors must outlive the copies
   return e;
 }
@@ -1247,6 +1304,7 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.mtrial = a.take<int>(b->n);
   B.cnt = a.take<int>(16);
   B.lists = a.take<Work>(full_list_units(b, p));
+  B.plan = a.take<CopyRun>(lm_runs_ensure(b, p) + 1);
   B.cc_th = a.take<CompC>((int64_t)b->n * kMaxComp);
   B.cc_t = a.take<CompC>((int64_t)b->n * kMaxComp);
 }
@@ -1347,7 +1405,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     }
     WorkView view;
     const WorkView *vw = nullptr;   // null: the full lists
-    HostLists cur, nxt;
+    std::vector<char> moved(b->n, 0);   // one-workgroup stamps moved to the multi-pass launches
     int view_stamps = b->n;
     // Speculative iteration: solve, then Jacobian images, normal equations
     // and chi^2 at the trial point, accept or reject.  An accepted trial
@@ -1435,8 +1493,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           GF_TRY(c, hipMemcpy(hst.data(), B.st, b->n * sizeof(LMState), hipMemcpyDeviceToHost));
           act.assign(b->n, 0);
           for (int q = 0; q < b->n; ++q) act[q] = hst[q].active ? 1 : 0;
-          GF_TRY(c, restrict_lists(cs, b, p, act, cur, nxt, B.lists, view));
-          std::swap(cur, nxt);   // every list at once: the next restriction filters these
+          GF_TRY(c, restrict_lists(cs, b, p, act, moved, B.plan, B.lists, view));
           vw = &view;
           view_stamps = active;
           if (exec) {

@@ -133,6 +133,20 @@ struct WorkView {
   int f2d_first[kF2dBuckets + 1] = {};
 };
 
+// Runs of consecutive entries of one stamp in a full work list, in list
+// order (an LM fit restricts its lists to the stamps still iterating run by
+// run).
+struct ListRuns {
+  std::vector<int32_t> stamp, beg, len;
+};
+// One contiguous piece of a restricted work list: len entries from src to
+// dst + dst_off.
+struct CopyRun {
+  const Work *src;
+  int64_t dst_off;
+  int32_t len, pad0;
+};
+
 // One data cube: its spatial geometry and offsets (the spectral length Nc
 // and LSF length Kl are those of the batch).
 struct CubeDesc {
@@ -453,6 +467,10 @@ struct gf_psf {
   // stamps are still fitting: gf_fit_lm then moves them to the multi-pass
   // launches, which spread one stamp over many workgroups
   std::vector<gf::Work> h_rows_alt, h_cols_alt, h_irows_alt, h_rows_n_alt, h_cols_n_alt, h_irows_n_alt;
+  gf::Work *d_rows_alt = nullptr, *d_cols_alt = nullptr, *d_irows_alt = nullptr;
+  gf::Work *d_rows_n_alt = nullptr, *d_cols_n_alt = nullptr, *d_irows_n_alt = nullptr;
+  // runs of the lists that LM fits restrict (built on the first fit)
+  mutable std::vector<gf::ListRuns> lm_runs;
   int n_fft = 0, n_direct = 0, n_f2d = 0;
 };
 

@@ -947,6 +947,18 @@ hipError_t launch_expand_starts(hipStream_t st, int G, int S, const double *thet
   return hipGetLastError();
 }
 
+// Restricted work lists: workgroup r copies piece r of the plan.
+__global__ __launch_bounds__(64) void k_copy_runs(const CopyRun *__restrict__ plan, Work *__restrict__ dst) {
+  const CopyRun r = plan[blockIdx.x];
+  for (int i = (int)threadIdx.x; i < r.len; i += 64) dst[r.dst_off + i] = r.src[i];
+}
+
+hipError_t launch_copy_runs(hipStream_t st, const CopyRun *plan, int n, Work *dst) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_runs, dim3((unsigned)n), dim3(64), 0, st, plan, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, const int32_t *first,
                           const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt, bool model_ie) {
   hipLaunchKernelGGL(k_lm_init, dim3((unsigned)b->n), dim3(64), 0, st, b->d_desc, b->n, lambda0, first, part, S, mjac,
