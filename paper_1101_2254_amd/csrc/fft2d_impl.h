@@ -309,7 +309,7 @@ __device__ __forceinline__ void f2_body(float2 *__restrict__ buf, float2 *__rest
   // ---- 5. output rows (crop), or the chi^2 epilogue
   const int oc = out_cols;
   if constexpr (MODE == MODE_CHI2) {
-    // r = sqrt(w) (d - m - sky); one wave per output row pair, lane l taking
+    // w (d - m - sky)^2; one wave per output row pair, lane l taking
     // columns l, l + 64, ... (first row, then second row, at each column),
     // compensated, then summed across the wave: the partial of a pair is
     // the one the multi-pass inverse-row kernel forms.  The next pair's
@@ -347,8 +347,9 @@ __device__ __forceinline__ void f2_body(float2 *__restrict__ buf, float2 *__rest
         eb[c] = 0.f;
         if (x < oc) {
           const float2 v = buf[lq((out_row0 + 2 * t) * LH + out_col0 + x)];
-          ea[c] = sqrtf(wa[c]) * (da[c] - (v.x + sky));
-          eb[c] = sqrtf(wb[c]) * (db[c] - (v.y + sky));
+          const float ra = da[c] - (v.x + sky), rb = db[c] - (v.y + sky);
+          ea[c] = (wa[c] * ra) * ra;   // w r^2: no square root
+          eb[c] = (wb[c] * rb) * rb;
           if (mdst) {
             mdst[(int64_t)(2 * t) * oc + x] = v.x;
             if (hb) mdst[(int64_t)(2 * t + 1) * oc + x] = v.y;
@@ -360,8 +361,8 @@ __device__ __forceinline__ void f2_body(float2 *__restrict__ buf, float2 *__rest
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) {
         if (lane + 64 * c < oc) {
-          acc = f2_add1(acc, ea[c] * ea[c]);
-          if (hb) acc = f2_add1(acc, eb[c] * eb[c]);
+          acc = f2_add1(acc, ea[c]);
+          if (hb) acc = f2_add1(acc, eb[c]);
         }
       }
       acc = wave_sum(acc);

@@ -437,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
   __syncthreads();
   lds_fft<true, RMAX>(buf, T, Ls, pl, tw);
   if constexpr (MODE == MODE_CHI2) {
-    // r = sqrt(w) (d - m - sky).  All threads form the squared residuals of
+    // w (d - m - sky)^2.  All threads form the squared residuals of
     // the workgroup's rows (every data and weight load in flight at once)
     // and stage them in LDS; then one wave per row pair adds them, lane l
     // taking columns l, l + 64, ... (first row, then second row, at each
@@ -471,9 +471,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_irows(const StampDesc *__restr
       if (idx < n_items) {
         const int t = divO(idx), x = idx - t * oc;
         const float2 v = buf[lp(t * Ls + g.out_col0 + x)];
-        const float ea = sqrtf(wa[it]) * (da[it] - (v.x + sky));
-        const float eb = sqrtf(wb[it]) * (db[it] - (v.y + sky));
-        sq[it] = make_float2(ea * ea, eb * eb);
+        const float ra = da[it] - (v.x + sky), rb = db[it] - (v.y + sky);
+        sq[it] = make_float2((wa[it] * ra) * ra, (wb[it] * rb) * rb);   // w r^2: no square root
         if (mdst) {
           const int ra = r0 + 2 * t;
           if (ra < g.out_rows) mdst[(int64_t)ra * oc + x] = v.x;
