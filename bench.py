@@ -284,7 +284,7 @@ TRAFFIC = {
                                summary="profiles/c2_fit_hbm_traffic.md"),
     ("c4", "k_eval"): dict(sources={"paper_1101_2254_amd/csrc/k_eval.hip": "9228be28108cf693"}, bytes=3.8620e+08,
                            summary="profiles/c4_likelihood_hbm_traffic.md"),
-    ("cube", "k_cube_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_cube.hip": "b023150d1a31c379"}, bytes=2.8513e+09,
+    ("cube", "k_cube_jac"): dict(sources={"paper_1101_2254_amd/csrc/k_cube.hip": "fa31c6afd1e9783d"}, bytes=2.5859e+09,
                                  summary="profiles/cube_fit_hbm_traffic.md"),
 }
 
@@ -789,7 +789,8 @@ def run_cube(args, torch, ops, synth, peaks, steps=None, warmup=None):
     samples = sum((c.H + c.K - 1) * (c.W + c.K - 1) for c in cubes) * S * S * Mc * Sv
     lsf_bytes = sum((c.H + c.K - 1) * (c.W + c.K - 1) for c in cubes) * (Mc + Nc) * 4
     table = {"k_cube_jac": ("alu", samples * CUBE_JAC_FLOP), "k_cube_eval": ("alu", samples * CUBE_EVAL_FLOP),
-             "k_cube_lsf": ("hbm", lsf_bytes * (1 + 11 + 1) / 3)}
+             # start model, Jacobian (every block but Ie's, which the kept model gives), trial model
+             "k_cube_lsf": ("hbm", lsf_bytes * (1 + 10 + 1) / 3)}
     rl, kern = roofline(prof, table, peaks)
     rl["traffic"] = measured_traffic("cube", rl)
     vox = np.array([Nc * c.H * c.W for c in cubes], dtype=np.float64)

@@ -36,13 +36,13 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *, float *, int, int, const int *, const WorkView *, float2 *, int px,
                             const float *mie);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
-                          int *, bool model_ie);
+                          int *, int model_ie);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
                            const double *, double *, int *, int *, int *, CompC *, CompC *, const float4 *,
                            const WorkView *, int px);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const int32_t *, const float2 *,
                             LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *,
-                            const WorkView *, bool model_ie);
+                            const WorkView *, int model_ie);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 }  // namespace gf
 
@@ -104,6 +104,7 @@ struct CubeBufs {
   double *Ag = nullptr, *theta_t = nullptr;
   LMState *st = nullptr;
   int *mjac = nullptr, *mtrial = nullptr, *cnt = nullptr;
+  float *model = nullptr;   // LM: the convolved model of the last trial (flat layout), whose Ie column it gives
 };
 
 void layout(const gf_cube_batch *cb, int nk, bool lm, Lay &a, CubeBufs &B) {
@@ -123,6 +124,7 @@ void layout(const gf_cube_batch *cb, int nk, bool lm, Lay &a, CubeBufs &B) {
   B.mjac = a.take<int>(cb->n);
   B.mtrial = a.take<int>(cb->n);
   B.cnt = a.take<int>(1);
+  B.model = a.take<float>(cb->n_pix * cb->Nc);
 }
 
 gf_status buffers(gf_ctx *c, gf_cube_batch *cb, int nk, bool lm, CubeBufs &B) {
@@ -153,9 +155,10 @@ gf_status check(gf_ctx *c, const gf_cube_batch *cb, int S, int Sv, const char *w
 }
 
 // Steps 1-2 of every cube in mask (nk = 1: the model without continuum into
-// B.conv) or of their 11 derivative channels (nk = 11).
+// out) or of their 11 derivative channels (nk = 11; with kMaskModelIe in a
+// cube's mask all but the Ie block).
 gf_status steps12(gf_ctx *c, gf_cube_batch *cb, hipStream_t st, const double *theta, int S, int Sv, int nk,
-                  const int *mask, const CubeBufs &B) {
+                  const int *mask, const CubeBufs &B, float *out) {
   const int nw = (int)cb->h_sp.size();
   if (nk == 1)
     CUBE_TRY(c, launch_cube_eval(st, cb->d_desc, cb->d_sp, nw, theta, c->d_bn, cb->Nc, cb->Kl, S, Sv, mask, B.pad));
@@ -163,8 +166,8 @@ gf_status steps12(gf_ctx *c, gf_cube_batch *cb, hipStream_t st, const double *th
     CUBE_TRY(c, launch_cube_jac(st, cb->d_desc, cb->d_sp, nw, theta, c->d_bn, cb->Nc, cb->Kl, S, Sv, mask, B.pad));
   CUBE_TRY(c, launch_cube_lsf(st, cb->d_desc, cb->d_sp, nw, cb->d_lsf, cb->Nc, cb->Kl, nk, mask, B.pad, B.lsf));
   const int nch = nk * cb->Nc;
-  CUBE_TRY(c, launch_fft_conv(st, cb->conv, cb->psf, B.lsf, nch, B.S1, B.S2, B.conv, mask, nullptr, nullptr, &c->fork));
-  CUBE_TRY(c, launch_direct(st, cb->conv, cb->psf, B.lsf, nch, B.conv, false, mask, nullptr));
+  CUBE_TRY(c, launch_fft_conv(st, cb->conv, cb->psf, B.lsf, nch, B.S1, B.S2, out, mask, nullptr, nullptr, &c->fork));
+  CUBE_TRY(c, launch_direct(st, cb->conv, cb->psf, B.lsf, nch, out, false, mask, nullptr));
   return GF_OK;
 }
 
@@ -293,7 +296,7 @@ gf_status gf_cube_model(gf_ctx *c, gf_cube_batch *cb, const double *theta, int S
   st = buffers(c, cb, 1, false, B);
   if (st != GF_OK) return st;
   B.conv = out;
-  st = steps12(c, cb, c->stream, theta, S, Sv, 1, nullptr, B);
+  st = steps12(c, cb, c->stream, theta, S, Sv, 1, nullptr, B, B.conv);
   if (st != GF_OK) return st;
   CUBE_TRY(c, launch_cube_cont(c->stream, cb->flat, theta, out));
   return GF_OK;
@@ -308,7 +311,7 @@ gf_status gf_cube_chi2(gf_ctx *c, gf_cube_batch *cb, const double *theta, int S,
   CubeBufs B;
   st = buffers(c, cb, 1, false, B);
   if (st != GF_OK) return st;
-  st = steps12(c, cb, c->stream, theta, S, Sv, 1, nullptr, B);
+  st = steps12(c, cb, c->stream, theta, S, Sv, 1, nullptr, B, B.conv);
   if (st != GF_OK) return st;
   CUBE_TRY(c, launch_chi2(c->stream, cb->flat, B.conv, theta, true, data, weight, nullptr, B.part, nullptr,
                           (float2 *)chi2, nullptr));
@@ -323,7 +326,7 @@ gf_status gf_cube_jacobian(gf_ctx *c, gf_cube_batch *cb, const double *theta, in
   CubeBufs B;
   st = buffers(c, cb, kJ, false, B);
   if (st != GF_OK) return st;
-  st = steps12(c, cb, c->stream, theta, S, Sv, kJ, nullptr, B);
+  st = steps12(c, cb, c->stream, theta, S, Sv, kJ, nullptr, B, B.conv);
   if (st != GF_OK) return st;
   CUBE_TRY(c, launch_cube_jac_assemble(c->stream, cb->flat, B.conv, out));
   return GF_OK;
@@ -351,25 +354,26 @@ gf_status gf_cube_fit_lm(gf_ctx *c, gf_cube_batch *cb, const float *data, const 
   const int64_t np = (int64_t)cb->n * GF_CUBE_NPAR;
   // start: clip, evaluate, chi^2
   CUBE_TRY(c, launch_cube_clip(cs, np, o.start ? o.start : theta, o.lo, o.hi, theta));
-  st = steps12(c, cb, cs, theta, S, Sv, 1, nullptr, B);
+  st = steps12(c, cb, cs, theta, S, Sv, 1, nullptr, B, B.model);
   if (st != GF_OK) return st;
-  CUBE_TRY(c, launch_chi2(cs, fb, B.conv, theta, true, data, weight, nullptr, B.part, nullptr, B.c2, nullptr));
-  CUBE_TRY(c, launch_lm_init(cs, fb, o.lambda0, fb->d_pix_first, B.part, B.st, B.mjac, B.mtrial, B.cnt, false));
+  CUBE_TRY(c, launch_chi2(cs, fb, B.model, theta, true, data, weight, nullptr, B.part, nullptr, B.c2, nullptr));
+  // the Jacobian masks flag every cube: its Ie column comes from the kept model
+  CUBE_TRY(c, launch_lm_init(cs, fb, o.lambda0, fb->d_pix_first, B.part, B.st, B.mjac, B.mtrial, B.cnt, cb->Nc));
   for (int it = 0; it < o.max_iter; ++it) {
     // Jacobian of the cubes that need one, their normal equations
-    st = steps12(c, cb, cs, theta, S, Sv, kJ, B.mjac, B);
+    st = steps12(c, cb, cs, theta, S, Sv, kJ, B.mjac, B, B.conv);
     if (st != GF_OK) return st;
     CUBE_TRY(c, launch_normal_eq(cs, fb, B.conv, theta, data, weight, B.npart, 256, kJ, B.mjac, nullptr, nullptr,
-                                 kCubePX, nullptr));
+                                 kCubePX, B.model));
     CUBE_TRY(c, launch_lm_solve(cs, fb, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, nullptr,
                                 nullptr, c->d_bn, nullptr, kCubePX));
     // trial point: model, chi^2, accept or reject
-    st = steps12(c, cb, cs, B.theta_t, S, Sv, 1, B.mtrial, B);
+    st = steps12(c, cb, cs, B.theta_t, S, Sv, 1, B.mtrial, B, B.model);
     if (st != GF_OK) return st;
-    CUBE_TRY(c, launch_chi2(cs, fb, B.conv, B.theta_t, true, data, weight, nullptr, B.part, nullptr, B.c2,
+    CUBE_TRY(c, launch_chi2(cs, fb, B.model, B.theta_t, true, data, weight, nullptr, B.part, nullptr, B.c2,
                             B.mtrial));
     CUBE_TRY(c, launch_lm_update(cs, fb, &o, fb->d_pix_first, B.part, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, nullptr, nullptr, nullptr, false));
+                                 B.cnt, nullptr, nullptr, nullptr, cb->Nc));
     if ((it + 1) % o.poll_every == 0 || it + 1 == o.max_iter) {
       CUBE_TRY(c, hipMemcpyAsync(c->h_pinned, B.cnt, sizeof(int), hipMemcpyDeviceToHost, cs));
       CUBE_TRY(c, hipStreamSynchronize(cs));

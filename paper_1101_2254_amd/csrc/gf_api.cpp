@@ -44,7 +44,7 @@ hipError_t launch_normal_eq(hipStream_t, const gf_batch *, const float *, const 
                             const float *mie = nullptr);
 hipError_t launch_copy_runs(hipStream_t, const CopyRun *, int, Work *);
 hipError_t launch_lm_init(hipStream_t, const gf_batch *, double, const int32_t *, const float2 *, LMState *, int *, int *,
-                          int *, bool model_ie = false);
+                          int *, int model_ie = 0);
 hipError_t launch_lm_start(hipStream_t, const gf_batch *, const double *, double *, const double *, const double *,
                            double *, int, const float4 *, CompC *);
 hipError_t launch_lm_solve(hipStream_t, const gf_batch *, const float *, const gf_lm_opts *, LMState *, double *,
@@ -55,7 +55,7 @@ hipError_t launch_chi2_direct(hipStream_t, const gf_batch *, const gf_psf *, con
 hipError_t launch_pair_final(hipStream_t, int, const int32_t *, const float2 *, float2 *, const int *);
 hipError_t launch_lm_update(hipStream_t, const gf_batch *, const gf_lm_opts *, const int32_t *, const float2 *,
                             LMState *, double *, const double *, int *, int *, int *, CompC *, CompC *,
-                            const WorkView *, bool model_ie = false);
+                            const WorkView *, int model_ie = 0);
 hipError_t launch_lm_result(hipStream_t, int, const LMState *, gf_lm_result *);
 hipError_t launch_group_best(hipStream_t, const gf_batch *, const gf_lm_result *, const double *, double *, int32_t *);
 hipError_t launch_expand_starts(hipStream_t, int, int, const double *, double *);
@@ -1401,7 +1401,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, false));
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
                           nullptr, &c->fork, true));
-      GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt, true));
+      GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt, 1));
     }
     WorkView view;
     const WorkView *vw = nullptr;   // null: the full lists
@@ -1436,7 +1436,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
                           vw, &c->fork, true));
       GF_TRY(c, launch_lm_update(cs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, B.cc_th, B.cc_t, vw, true));
+                                 B.cnt, B.cc_th, B.cc_t, vw, 1));
       return GF_OK;
     };
     // capture one iteration into (g, e), replacing what they held

@@ -188,13 +188,20 @@ struct Chi2Epi {
 };
 
 // A Jacobian mask value with this bit set (one-component stamps of an LM fit
-// in the plain form): the Ie channel is not evaluated or convolved, and the
-// normal equations take it from the convolved model of the same point, which
-// the accepted trial's chi^2 pass left in the model buffer (the model is
-// linear in Ie: dm/dIe = (m - sky) / Ie).
+// in the plain form, and the cubes of a cube fit): the Ie channels are not
+// evaluated or convolved, and the normal equations take that column from the
+// convolved model of the same point, which the accepted trial's chi^2 pass
+// left in the model buffer (the model is linear in Ie: dm/dIe = (m - sky) /
+// Ie).  Bits 8 and up hold the channels per parameter (1 for an image, the
+// spectral channels for a cube), so the Ie channels are those of parameter 2.
 constexpr int kMaskModelIe = 2;
+constexpr int kMaskCppShift = 8;
+__device__ __host__ inline int mask_model_ie(int cpp) { return 1 | kMaskModelIe | (cpp << kMaskCppShift); }
 __device__ __host__ inline bool skip_ie(const int *mask, int s, int ch) {
-  return mask && (mask[s] & kMaskModelIe) && ch == 2;
+  if (!mask) return false;
+  const int m = mask[s];
+  const int cpp = m >> kMaskCppShift;
+  return (m & kMaskModelIe) && ch >= 2 * cpp && ch < 3 * cpp;
 }
 
 // One spectrum of a line batch.

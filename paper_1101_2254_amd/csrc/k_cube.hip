@@ -166,6 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_cube_jac(const CubeDesc *__restric
   const float inv = 1.0f / (float)(S * S * Sv);
   const float rt2 = k.rt * k.rt;
   float *dst = out + d.pad * (int64_t)Mc * 11 + p;
+  const bool no_ie = mask && (mask[s] & kMaskModelIe);   // the Ie block comes from the kept model
   // spectral sub-sample offsets, once per thread (static register indices)
   float ov[GF_MAX_OVERSAMPLE];
 #pragma unroll
@@ -247,7 +248,8 @@ __global__ __launch_bounds__(kThreads) void k_cube_jac(const CubeDesc *__restric
       const int pc = pc0 + c;
       if (pc < Mc) {
 #pragma unroll
-        for (int j = 0; j < 11; ++j) dst[((int64_t)j * Mc + pc) * np] = acc[j][c] * inv;
+        for (int j = 0; j < 11; ++j)
+          if (!(j == 2 && no_ie)) dst[((int64_t)j * Mc + pc) * np] = acc[j][c] * inv;
       }
     }
   }
@@ -269,6 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_cube_lsf(const CubeDesc *__restric
   const int p = w.unit * kThreads + (int)threadIdx.x;
   if (p >= np) return;
   const int j = blockIdx.y;
+  if (nk > 1 && mask && (mask[s] & kMaskModelIe) && j == 2) return;   // the Ie block comes from the kept model
   const int Mc = Nc + Kl - 1;
   const float *src = in + d.pad * (int64_t)Mc * nk + (int64_t)j * Mc * np + p;
   float *dst = out + d.pad * (int64_t)Nc * nk + (int64_t)j * Nc * np + p;
@@ -298,6 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_cube_lsf_t(const CubeDesc *__restr
   const int p = w.unit * kThreads + (int)threadIdx.x;
   if (p >= np) return;
   const int j = blockIdx.y;
+  if (nk > 1 && mask && (mask[s] & kMaskModelIe) && j == 2) return;   // the Ie block comes from the kept model
   const int Mc = Nc + KL - 1;
   const float *src = in + d.pad * (int64_t)Mc * nk + (int64_t)j * Mc * np + p;
   float *dst = out + d.pad * (int64_t)Nc * nk + (int64_t)j * Nc * np + p;

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(T) void k_gram(const StampDesc *__restrict__ desc, 
   const float sky = (float)theta[d.par + SK];
   // one-component stamps flagged in the mask: the Ie channel and the model
   // from the convolved model mie of this point
-  const float *mdl = (NC == 1 && PX == 0 && mie && mask && (mask[s] & kMaskModelIe)) ? mie + d.pix : nullptr;
+  const float *mdl = (NC == 1 && mie && mask && (mask[s] & kMaskModelIe)) ? mie + d.pix : nullptr;
   const float inv_ie = (float)(1.0 / theta[d.par + 2]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
@@ -463,12 +463,11 @@ hipError_t launch_normal_eq(hipStream_t st, const gf_batch *b, const float *jc, 
   if (px == kCubePX) {   // one-component stamps with the cube's kinematic parameters, no chi^2 output
     if (nbig > 0)
       hipLaunchKernelGGL((k_gram<1, false, 512, kCubePX>), dim3((unsigned)nbig), dim3(512), 0, st, b->d_desc, lst,
-                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr,
-                         (const float *)nullptr);
+                         jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr, mie);
     if (n > nbig)
       hipLaunchKernelGGL((k_gram<1, false, 256, kCubePX>), dim3((unsigned)(n - nbig)), dim3(256), 0, st, b->d_desc,
                          lst + nbig, jc, nchan, theta, data, weight, part, b->d_neq_first, mask, (float2 *)nullptr,
-                         (const float *)nullptr);
+                         mie);
     return hipGetLastError();
   }
   if (px != 0) return hipErrorInvalidValue;
@@ -502,7 +501,7 @@ struct LMParams {
   CompC *cc_t, *cc_th;
   const float4 *bn;
   int32_t oversample;
-  int32_t model_ie;   // flag one-component stamps' Jacobian masks with kMaskModelIe
+  int32_t model_ie;   // > 0: flag one-component stamps' Jacobian masks with kMaskModelIe, this many channels per parameter
 };
 
 // Start: one wave per stamp adds the chi^2 partials of the (clipped) start
@@ -541,7 +540,7 @@ __global__ __launch_bounds__(64) void k_lm_init(const StampDesc *__restrict__ de
     S.active = 0;
   }
   st[s] = S;
-  mjac[s] = S.active ? (model_ie && desc[s].ncomp == 1 ? 1 | kMaskModelIe : 1) : 0;
+  mjac[s] = S.active ? (model_ie > 0 && desc[s].ncomp == 1 ? mask_model_ie(model_ie) : 1) : 0;
   mtrial[s] = 0;
 }
 
@@ -863,7 +862,7 @@ __global__ __launch_bounds__(64) void k_lm_update(const StampDesc *__restrict__ 
   }
   S.trial = 0;
   mtrial[s] = 0;
-  mjac[s] = (S.active && S.need_jac) ? (prm.model_ie && d.ncomp == 1 ? 1 | kMaskModelIe : 1) : 0;
+  mjac[s] = (S.active && S.need_jac) ? (prm.model_ie > 0 && d.ncomp == 1 ? mask_model_ie(prm.model_ie) : 1) : 0;
   st[s] = S;
   if (S.active) atomicAdd(active_count, 1);
 }
@@ -960,9 +959,9 @@ hipError_t launch_copy_runs(hipStream_t st, const CopyRun *plan, int n, Work *ds
 }
 
 hipError_t launch_lm_init(hipStream_t st, const gf_batch *b, double lambda0, const int32_t *first,
-                          const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt, bool model_ie) {
+                          const float2 *part, LMState *S, int *mjac, int *mtrial, int *cnt, int model_ie) {
   hipLaunchKernelGGL(k_lm_init, dim3((unsigned)b->n), dim3(64), 0, st, b->d_desc, b->n, lambda0, first, part, S, mjac,
-                     mtrial, cnt, model_ie ? 1 : 0);
+                     mtrial, cnt, model_ie);
   return hipGetLastError();
 }
 
@@ -999,9 +998,9 @@ hipError_t launch_lm_solve(hipStream_t st, const gf_batch *b, const float *part,
 
 hipError_t launch_lm_update(hipStream_t st, const gf_batch *b, const gf_lm_opts *o, const int32_t *first,
                             const float2 *part, LMState *S, double *theta, const double *theta_t, int *mjac,
-                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t, const WorkView *v, bool model_ie) {
+                            int *mtrial, int *cnt, CompC *cc_th, CompC *cc_t, const WorkView *v, int model_ie) {
   LMParams prm{o->max_iter, o->lambda_up, o->lambda_down, o->lambda_max, o->ftol, o->xtol, o->lo, o->hi,
-               o->free_mask, cc_t, cc_th, nullptr, o->oversample, model_ie ? 1 : 0};
+               o->free_mask, cc_t, cc_th, nullptr, o->oversample, model_ie};
   ProfScope ps(st, "k_lm_update");
   const Work *list = v && v->stamps ? v->stamps : nullptr;
   const unsigned grid = list ? (unsigned)v->n_stamps : (unsigned)b->n;
