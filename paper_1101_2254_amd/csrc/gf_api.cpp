@@ -150,7 +150,8 @@ gf_status ensure_counters(gf_ctx *c, int64_t n) {
   const int64_t nn = std::max<int64_t>(n, 1024);
   if (hipMalloc((void **)&c->d_counters, nn * sizeof(unsigned int)) != hipSuccess)
     return fail(c, GF_ENOMEM, "counter allocation failed");
-  GF_TRY(c, hipMemset(c->d_counters, 0, nn * sizeof(unsigned int)));
+  GF_TRY(c, hipMemsetAsync(c->d_counters, 0, nn * sizeof(unsigned int), c->stream));
+  GF_TRY(c, hipStreamSynchronize(c->stream));
   c->n_counters = nn;
   return GF_OK;
 }
@@ -324,13 +325,25 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
   return GF_OK;
 }
 
+// Wait for everything the context has enqueued, on its own streams only, so
+// that contexts used by other host threads (possibly capturing graphs) are
+// not touched.
+static void ctx_sync(gf_ctx *c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (hipStream_t s : {c->lm_stream, c->fork.side[0], c->fork.side[1], c->fork.side[2]})
+    if (s) (void)hipStreamSynchronize(s);
+  for (hipStream_t s : c->side)
+    if (s) (void)hipStreamSynchronize(s);
+}
+
 void gf_destroy(gf_ctx *c) {
   if (!c) return;
-  (void)hipDeviceSynchronize();
+  ctx_sync(c);
   dfree(c->d_bn);
   dfree(c->d_counters);
   dfree(c->ws);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->h_states) (void)hipHostFree(c->h_states);
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
   for (hipStream_t st : c->side)
     if (st) (void)hipStreamDestroy(st);
@@ -1338,6 +1351,15 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   if (st != GF_OK) return st;
   a = Arena{(char *)c->ws, 0};
   lm_layout(b, p, nchan, nacc, a, B);
+  const size_t states_bytes = (size_t)b->n * sizeof(LMState);
+  if (b->n > 1 && c->h_states_bytes < states_bytes) {   // no copy into it is in flight between fits
+    if (c->h_states) (void)hipHostFree(c->h_states);
+    c->h_states = nullptr;
+    c->h_states_bytes = 0;
+    if (hipHostMalloc(&c->h_states, states_bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(c, GF_ENOMEM, "gf_fit_lm: pinned host memory for the LM states");
+    c->h_states_bytes = states_bytes;
+  }
   const int S = o.oversample;
 
   // The fit runs on the context's LM stream, joined to the caller's stream
@@ -1453,7 +1475,6 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
       return GF_OK;
     };
-    std::vector<LMState> hst;
     std::vector<char> act;
     // the result records are written before every poll, so a fit that the
     // poll finds finished returns without another launch; the host waits
@@ -1489,10 +1510,13 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
         // the lists to the stamps still iterating (finished stamps would
         // otherwise still cost their workgroups in every launch).
         if (b->n > 1 && 2 * active <= view_stamps && it + 1 < o.max_iter) {
-          hst.resize(b->n);
-          GF_TRY(c, hipMemcpy(hst.data(), B.st, b->n * sizeof(LMState), hipMemcpyDeviceToHost));
+          // on the fit's stream (not the legacy stream, which would wait
+          // for other host threads' streams, possibly capturing)
+          GF_TRY(c, hipMemcpyAsync(c->h_states, B.st, b->n * sizeof(LMState), hipMemcpyDeviceToHost, cs));
+          GF_TRY(c, hipStreamSynchronize(cs));
+          const LMState *hs = static_cast<const LMState *>(c->h_states);
           act.assign(b->n, 0);
-          for (int q = 0; q < b->n; ++q) act[q] = hst[q].active ? 1 : 0;
+          for (int q = 0; q < b->n; ++q) act[q] = hs[q].active ? 1 : 0;
           GF_TRY(c, restrict_lists(cs, b, p, act, moved, B.plan, B.lists, view));
           vw = &view;
           view_stamps = active;
@@ -1754,7 +1778,8 @@ gf_status gf_profile_stop(gf_ctx *c) {
 
 int gf_profile_kernels(gf_ctx *c) {
   if (!c) return -1;
-  if (hipDeviceSynchronize() != hipSuccess) return -1;
+  for (const auto &r : c->prof.recs)
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
   std::vector<std::string> names;
   for (const auto &r : c->prof.recs)
     if (std::find(names.begin(), names.end(), r.name) == names.end()) names.push_back(r.name);
@@ -1763,7 +1788,7 @@ int gf_profile_kernels(gf_ctx *c) {
 
 gf_status gf_profile_get(gf_ctx *c, int i, char *name, int name_cap, int64_t *launches, double *total_ms) {
   if (!c || i < 0) return GF_EINVAL;
-  GF_TRY(c, hipDeviceSynchronize());
+  for (const auto &r : c->prof.recs) GF_TRY(c, hipEventSynchronize(r.b));
   std::vector<std::string> names;
   for (const auto &r : c->prof.recs)
     if (std::find(names.begin(), names.end(), r.name) == names.end()) names.push_back(r.name);

@@ -348,6 +348,8 @@ struct gf_ctx {
   void *ws = nullptr;          // grow-only workspace
   size_t ws_bytes = 0;
   int *h_pinned = nullptr;     // pinned host word for LM polling
+  void *h_states = nullptr;    // pinned copy of the LM states at a restriction (grown on demand)
+  size_t h_states_bytes = 0;
   gf::Profiler prof;
   // side streams (default priority) and fork/join events for launches that
   // run concurrently, e.g. the per-line-count kernels of a line fit
