@@ -61,7 +61,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed FMA)
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix
 # the library's tuning file (FFT form per side, measured on first use)
-TUNE_FILE = os.path.join(ROOT, "gpurun_out", "gf_tune.json")
+TUNE_FILE = os.path.join(ROOT, "bench_out", "gf_tune.json")
 METRIC = "model evals/sec (Mpix/s eval+PSF+χ²) and LM fits/sec at χ² rel tol 1e-5"
 
 # Algorithmic FP32 operations per sub-sample and component (an FMA counts
@@ -874,7 +874,7 @@ def cpu_model():
 def oracle_native():
     """The oracle rebuilt for this host (-O3 -march=native, same rounding)."""
     from oracle import gfo
-    gfo.use_native(os.path.join(ROOT, "gpurun_out", "oracle_native"))
+    gfo.use_native(os.path.join(ROOT, "bench_out", "oracle_native"))
     return gfo
 
 
@@ -1128,6 +1128,7 @@ def main():
               "(the hot path shards as described in the design notes, but only the one-GPU kernel is built)",
               file=sys.stderr)
         sys.exit(2)
+    os.makedirs(os.path.dirname(TUNE_FILE), exist_ok=True)
     import torch
     import synth
     from paper_1101_2254_amd import ops
