@@ -97,7 +97,11 @@ typedef enum {
  * timing convolutions and allocates temporary device memory in that call)
  * and rewrites the file.  A later context reading the same file takes the
  * same choices, so its results are the same bits.  Without a path nothing
- * is measured and untuned sides take the default rule. */
+ * is measured and untuned sides take the default rule.
+ * The context also creates three non-blocking streams (default priority) on
+ * which the one-workgroup FFT launches of a convolution run beside its
+ * multi-pass launches, joined to the calling stream by events before the
+ * call returns (and recorded into the LM iteration graphs). */
 gf_status gf_create(gf_ctx **ctx, int device, const char *autotune_cache);
 void gf_destroy(gf_ctx *ctx);
 /* Tuning table of the context, read by gf_psf_prepare(GF_CONV_AUTO) and
