@@ -330,7 +330,7 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
 // not touched.
 static void ctx_sync(gf_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
-  for (hipStream_t s : {c->lm_stream, c->fork.side[0], c->fork.side[1], c->fork.side[2]})
+  for (hipStream_t s : {c->lm_stream, c->lm_stream2, c->fork.side[0], c->fork.side[1], c->fork.side[2]})
     if (s) (void)hipStreamSynchronize(s);
   for (hipStream_t s : c->side)
     if (s) (void)hipStreamSynchronize(s);
@@ -353,6 +353,9 @@ void gf_destroy(gf_ctx *c) {
   if (c->lm_graph) (void)hipGraphDestroy(c->lm_graph);
   if (c->lm_stream) (void)hipStreamDestroy(c->lm_stream);
   if (c->lm_ev) (void)hipEventDestroy(c->lm_ev);
+  if (c->lm_stream2) (void)hipStreamDestroy(c->lm_stream2);
+  for (hipEvent_t e : c->lm_lane_ev)
+    if (e) (void)hipEventDestroy(e);
   fork_destroy(c->fork);
   delete c;
 }
@@ -1316,8 +1319,9 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.mjac = a.take<int>(b->n);
   B.mtrial = a.take<int>(b->n);
   B.cnt = a.take<int>(16);
-  B.lists = a.take<Work>(full_list_units(b, p));
-  B.plan = a.take<CopyRun>(lm_runs_ensure(b, p) + 1);
+  // room for the lists and copy plans of two lanes (each up to the full size)
+  B.lists = a.take<Work>(2 * full_list_units(b, p));
+  B.plan = a.take<CopyRun>(2 * (lm_runs_ensure(b, p) + 1));
   B.cc_th = a.take<CompC>((int64_t)b->n * kMaxComp);
   B.cc_t = a.take<CompC>((int64_t)b->n * kMaxComp);
 }
@@ -1399,6 +1403,15 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     c->lm_graph = nullptr;
     c->lm_key = LmGraphKey{};
   }
+  // batches of at least this many stamps run their plain-form iterations in
+  // two lanes (see run below)
+  constexpr int kLmLaneMin = 512;
+  const int lanes = (!spec && graphs && b->n >= kLmLaneMin) ? 2 : 1;
+  if (lanes == 2) {
+    if (!c->lm_stream2) GF_TRY(c, hipStreamCreateWithFlags(&c->lm_stream2, hipStreamNonBlocking));
+    for (hipEvent_t &e : c->lm_lane_ev)
+      if (!e) GF_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   hipGraph_t vgraph = nullptr;
   hipGraphExec_t vexec = nullptr;
   hipGraphExec_t exec = reuse ? c->lm_exec : nullptr;
@@ -1433,32 +1446,36 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     // and chi^2 at the trial point, accept or reject.  An accepted trial
     // leaves its normal equations for the next solve; after a rejection the
     // solve reuses the stored system of the current point.
+    // the stream, lists and active count the iteration below launches on:
+    // the fit's stream and lists, or one lane's (see run_lanes)
+    hipStream_t xs = cs;
+    int *xcnt = B.cnt;
     auto iteration_spec = [&]() -> gf_status {
-      GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
+      GF_TRY(c, launch_lm_solve(xs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, xcnt, B.cc_th,
                                 B.cc_t, c->d_bn, vw));
-      GF_TRY(c, launch_eval_jac_d(cs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, B.mtrial, vw, B.cc_t, false));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mtrial, vw, nullptr, &c->fork));
-      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mtrial, vw));
-      GF_TRY(c, launch_normal_eq(cs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, B.mtrial, vw,
+      GF_TRY(c, launch_eval_jac_d(xs, b, B.theta_t, S, c->d_bn, B.cpad, nchan, B.mtrial, vw, B.cc_t, false));
+      GF_TRY(c, launch_fft_conv(xs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mtrial, vw, nullptr, &c->fork));
+      GF_TRY(c, launch_direct(xs, b, p, B.cpad, nchan, B.jc, false, B.mtrial, vw));
+      GF_TRY(c, launch_normal_eq(xs, b, B.jc, B.theta_t, data, weight, B.npart, nacc, nchan, B.mtrial, vw,
                                  B.gpart));
-      GF_TRY(c, launch_lm_update(cs, b, &o, b->d_neq_first, B.gpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, B.cc_th, B.cc_t, vw));
+      GF_TRY(c, launch_lm_update(xs, b, &o, b->d_neq_first, B.gpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
+                                 xcnt, B.cc_th, B.cc_t, vw));
       return GF_OK;
     };
     auto iteration = [&]() -> gf_status {
       if (spec) return iteration_spec();
-      GF_TRY(c, launch_eval_jac_d(cs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw, B.cc_th, false));
-      GF_TRY(c, launch_fft_conv(cs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw, nullptr, &c->fork));
-      GF_TRY(c, launch_direct(cs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
-      GF_TRY(c, launch_normal_eq(cs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr, 0,
+      GF_TRY(c, launch_eval_jac_d(xs, b, theta, S, c->d_bn, B.cpad, nchan, B.mjac, vw, B.cc_th, false));
+      GF_TRY(c, launch_fft_conv(xs, b, p, B.cpad, nchan, B.S1, B.S2, B.jc, B.mjac, vw, nullptr, &c->fork));
+      GF_TRY(c, launch_direct(xs, b, p, B.cpad, nchan, B.jc, false, B.mjac, vw));
+      GF_TRY(c, launch_normal_eq(xs, b, B.jc, theta, data, weight, B.npart, nacc, nchan, B.mjac, vw, nullptr, 0,
                                  B.mconv));
-      GF_TRY(c, launch_lm_solve(cs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, B.cnt, B.cc_th,
+      GF_TRY(c, launch_lm_solve(xs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, xcnt, B.cc_th,
                                 B.cc_t, c->d_bn, vw));
-      GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
-      GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
+      GF_TRY(c, launch_eval_d(xs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
+      GF_TRY(c, conv_chi2(xs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
                           vw, &c->fork, true));
-      GF_TRY(c, launch_lm_update(cs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
-                                 B.cnt, B.cc_th, B.cc_t, vw, 1));
+      GF_TRY(c, launch_lm_update(xs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
+                                 xcnt, B.cc_th, B.cc_t, vw, 1));
       return GF_OK;
     };
     // capture one iteration into (g, e), replacing what they held
@@ -1467,14 +1484,132 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       if (g) (void)hipGraphDestroy(g);
       e = nullptr;
       g = nullptr;
-      GF_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      GF_TRY(c, hipStreamBeginCapture(xs, hipStreamCaptureModeThreadLocal));
       gf_status s2 = iteration();
-      hipError_t ce = hipStreamEndCapture(cs, &g);
+      hipError_t ce = hipStreamEndCapture(xs, &g);
       if (s2 != GF_OK) return s2;
       GF_TRY(c, ce);
       GF_TRY(c, hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
       return GF_OK;
     };
+    // Two lanes: a large plain-form batch runs as two halves (the stamps of
+    // even and of odd index), each with its own work lists, active count,
+    // iteration graph and restrictions, on two streams, so the tail of one
+    // half's launches overlaps the other half's work.  A stamp runs the same
+    // kernels as in one lane; only the moves of one-workgroup stamps to the
+    // multi-pass launches follow its half's counts.  Results are written once
+    // both halves have finished.
+    if (lanes == 2) {
+      struct Lane {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        WorkView view;
+        int stamps = 0;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        int *cnt = nullptr;
+        Work *dev = nullptr;
+        CopyRun *plan = nullptr;
+        volatile int *h = nullptr;
+        bool done = false;
+      };
+      Lane ln[2];
+      auto lanes_cleanup = [&]() {   // every replay has been waited for at a poll
+        for (Lane &l : ln) {
+          if (l.x) (void)hipGraphExecDestroy(l.x);
+          if (l.g) (void)hipGraphDestroy(l.g);
+          l.x = nullptr;
+          l.g = nullptr;
+        }
+      };
+      auto body = [&]() -> gf_status {
+        const int64_t units = full_list_units(b, p), runs = lm_runs_ensure(b, p) + 1;
+        for (int l = 0; l < 2; ++l) {
+          ln[l].s = l == 0 ? cs : c->lm_stream2;
+          ln[l].e = c->lm_lane_ev[l];
+          ln[l].cnt = B.cnt + 8 * l;
+          ln[l].dev = B.lists + units * l;
+          ln[l].plan = B.plan + runs * l;
+          ln[l].h = c->h_pinned + 8 * l;
+        }
+        std::vector<char> half(b->n);
+        for (int l = 0; l < 2; ++l) {   // the halves' lists (the start point is done on cs)
+          for (int q = 0; q < b->n; ++q) half[q] = (q & 1) == l;
+          GF_TRY(c, restrict_lists(cs, b, p, half, moved, ln[l].plan, ln[l].dev, ln[l].view));
+          ln[l].stamps = ln[l].view.n_stamps;
+        }
+        GF_TRY(c, hipEventRecord(ln[0].e, cs));
+        GF_TRY(c, hipStreamWaitEvent(ln[1].s, ln[0].e, 0));
+        auto use = [&](Lane &l) {
+          xs = l.s;
+          vw = &l.view;
+          xcnt = l.cnt;
+        };
+        // Each lane runs poll_every iterations, then its count is copied; the
+        // host waits on the lanes' polls in turn, so while it waits on (and
+        // restricts) one lane the other's queued iterations keep the device
+        // busy.
+        int itl[2] = {0, 0};
+        bool pending[2] = {false, false};
+        int next = 0;
+        for (;;) {
+          for (int li = 0; li < 2; ++li) {
+            Lane &l = ln[li];
+            if (l.done || pending[li]) continue;
+            use(l);
+            do {
+              if (l.x && itl[li] > 0) {
+                GF_TRY(c, hipGraphLaunch(l.x, l.s));
+              } else {
+                gf_status s2 = iteration();
+                if (s2 != GF_OK) return s2;
+              }
+              if (itl[li] == 0 && o.max_iter > 1) {
+                gf_status s2 = capture(l.g, l.x);
+                if (s2 != GF_OK) return s2;
+              }
+              ++itl[li];
+            } while (itl[li] % o.poll_every != 0 && itl[li] < o.max_iter);
+            GF_TRY(c, hipMemcpyAsync((void *)l.h, l.cnt, sizeof(int), hipMemcpyDeviceToHost, l.s));
+            GF_TRY(c, hipEventRecord(l.e, l.s));
+            pending[li] = true;
+          }
+          int li = next;
+          if (!pending[li]) li = 1 - li;
+          if (!pending[li]) break;   // both lanes done
+          next = 1 - li;
+          Lane &l = ln[li];
+          GF_TRY(c, hipEventSynchronize(l.e));
+          pending[li] = false;
+          const int active = *l.h;
+          if (active == 0 || itl[li] >= o.max_iter) {
+            l.done = true;
+            continue;
+          }
+          if (2 * active <= l.stamps) {
+            GF_TRY(c, hipMemcpyAsync(c->h_states, B.st, b->n * sizeof(LMState), hipMemcpyDeviceToHost, l.s));
+            GF_TRY(c, hipStreamSynchronize(l.s));
+            const LMState *hs = static_cast<const LMState *>(c->h_states);
+            for (int q = 0; q < b->n; ++q) half[q] = ((q & 1) == li && hs[q].active) ? 1 : 0;
+            GF_TRY(c, restrict_lists(l.s, b, p, half, moved, l.plan, l.dev, l.view));
+            l.stamps = active;
+            use(l);
+            gf_status s2 = capture(l.g, l.x);
+            if (s2 != GF_OK) return s2;
+          }
+        }
+        // both halves joined on the fit's stream, then every stamp's result
+        GF_TRY(c, hipEventRecord(ln[1].e, ln[1].s));
+        GF_TRY(c, hipStreamWaitEvent(cs, ln[1].e, 0));
+        GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
+        GF_TRY(c, hipEventRecord(ev, cs));
+        GF_TRY(c, hipStreamWaitEvent(c->stream, ev, 0));
+        return GF_OK;
+      };
+      const gf_status s2 = body();
+      lanes_cleanup();
+      return s2;
+    }
     std::vector<char> act;
     // the result records are written before every poll, so a fit that the
     // poll finds finished returns without another launch; the host waits

@@ -363,6 +363,10 @@ struct gf_ctx {
   // graph with what it was captured for (replayed while the key matches)
   hipStream_t lm_stream = nullptr;
   hipEvent_t lm_ev = nullptr;
+  // the second lane of a large plain-form fit (its stream) and the lanes'
+  // poll events
+  hipStream_t lm_stream2 = nullptr;
+  hipEvent_t lm_lane_ev[2] = {};
   gf::LmGraphKey lm_key;
   hipGraph_t lm_graph = nullptr;
   hipGraphExec_t lm_exec = nullptr;

@@ -80,3 +80,45 @@ def test_contexts_in_concurrent_threads(gfo):
             np.testing.assert_array_equal(out[k][1][f], ref[k][1][f], err_msg=f"{k} {f}")
     for c in ctxs:
         c.close()
+
+
+def test_two_lanes_match_one_lane(gfo):
+    """A plain-form batch of at least 512 stamps runs as two lanes (halves on
+    two streams with their own lists, graphs and restrictions); every stamp
+    gives the bits it gives in a smaller batch, which runs as one lane."""
+    from tests.gpu_common import keep_fft_forms
+    ctx = ops.Context(0)
+    keep_fft_forms(ctx)
+    g = synth.rng(777)
+    stamps = [synth.c3_stamp(g, int(g.choice([32, 48])), i, 777) for i in range(600)]
+    for i in range(0, 600, 7):
+        stamps[i].psf = synth.gaussian_psf(5, 1.0)   # direct-path stamps too
+    data, weights = [], []
+    for s in stamps:
+        m = gfo.model(s.H, s.W, s.truth.astype(np.float32).astype(np.float64),
+                      s.psf.astype(np.float32).astype(np.float64), 5)
+        d, w = synth.add_gaussian_noise(m, 0.02, s.noise_seed)
+        data.append(d)
+        weights.append(w)
+
+    def fit(idx):
+        sts = [stamps[i] for i in idx]
+        gb = GpuBatch(ctx, sts, data=[data[i] for i in idx], weights=[weights[i] for i in idx])
+        lo = to_dev(np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in sts]), torch.float64)
+        hi = to_dev(np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in sts]), torch.float64)
+        start = to_dev(np.concatenate([s.start for s in sts]), torch.float64)
+        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-5)
+        return th.cpu().numpy(), info, gb.batch.offsets["par"]
+
+    print("600 stamps: two lanes", flush=True)
+    t2, i2, p2 = fit(list(range(600)))
+    assert np.all(np.isfinite(t2)) and np.any(i2["iters"] > 4)
+    for lo_, hi_ in ((0, 300), (300, 600)):
+        print(f"stamps {lo_}..{hi_ - 1}: one lane", flush=True)
+        t1, i1, p1 = fit(list(range(lo_, hi_)))
+        for k, s in enumerate(range(lo_, hi_)):
+            np.testing.assert_array_equal(t1[p1[k]:p1[k] + 8], t2[p2[s]:p2[s] + 8], err_msg=str(s))
+            for f in ("chi2", "iters", "nfev", "njev", "status"):
+                assert i1[f][k] == i2[f][s], (s, f, i1[f][k], i2[f][s])
+    torch.cuda.synchronize()
+    ctx.close()
