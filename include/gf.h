@@ -349,6 +349,9 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  * res: device [n_stamps].  data, weight: device [n_img].  All iterations run
  * on the device; the host only reads the count of still-active stamps every
  * poll_every iterations.  Stamps that finish stop costing work.
+ * The fit runs on streams of the context, ordered after and before the
+ * caller's stream by events; a batch of 512 or more stamps in the plain form
+ * runs as two halves on two of them, with the same per-stamp results. 
  * Returns GF_OK when the call ran (per-stamp outcomes are in res).  Data or
  * weights that are not finite make that stamp's chi^2 non-finite: its fit
  * then rejects every step and ends with GF_ENOTCONV, reason 4, at the
