@@ -1148,7 +1148,12 @@ namespace {
 
 struct LMBufs {
   float *cpad, *jc, *mpad, *mconv, *npart;
-  float2 *S1, *S2, *cpart;
+  // Spectra of the multi-pass FFT: S1/S2 for the Jacobian images (nchan
+  // channels a stamp), S1c/S2c for the one-channel chi^2 convolutions.  A
+  // stamp's block starts at its offset times the channel count, so the two
+  // layouts overlap across stamps: they get separate buffers because the two
+  // lanes run one's chi^2 pass while the other convolves its Jacobians.
+  float2 *S1, *S2, *S1c, *S2c, *cpart;
   float2 *gpart;   // chi^2 partials per normal-equation unit (speculative iterations)
   double *Ag, *theta_t;
   LMState *st;
@@ -1308,6 +1313,8 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.jc = a.take<float>(b->n_pix * nchan);
   B.S1 = a.take<float2>(p->n_s1 * nchan);
   B.S2 = a.take<float2>(p->n_s2 * nchan);
+  B.S1c = a.take<float2>(p->n_s1);
+  B.S2c = a.take<float2>(p->n_s2);
   B.npart = a.take<float>((int64_t)b->h_neq.size() * nacc);
   B.Ag = a.take<double>((int64_t)b->n * (kMaxP * kMaxP + kMaxP));
   B.theta_t = a.take<double>(b->n_par);
@@ -1434,7 +1441,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_lm_init(cs, b, o.lambda0, b->d_neq_first, B.gpart, B.st, B.mjac, B.mtrial, B.cnt));
     } else {
       GF_TRY(c, launch_eval_d(cs, b, B.theta_t, S, c->d_bn, B.mpad, nullptr, nullptr, B.cc_th, false));
-      GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
+      GF_TRY(c, conv_chi2(cs, b, p, B.mpad, B.S1c, B.S2c, B.mconv, B.theta_t, true, data, weight, B.cpart, nullptr,
                           nullptr, &c->fork, true));
       GF_TRY(c, launch_lm_init(cs, b, o.lambda0, p->d_c2_first, B.cpart, B.st, B.mjac, B.mtrial, B.cnt, 1));
     }
@@ -1472,7 +1479,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       GF_TRY(c, launch_lm_solve(xs, b, B.npart, &o, B.st, B.Ag, theta, B.theta_t, B.mjac, B.mtrial, xcnt, B.cc_th,
                                 B.cc_t, c->d_bn, vw));
       GF_TRY(c, launch_eval_d(xs, b, B.theta_t, S, c->d_bn, B.mpad, B.mtrial, vw, B.cc_t, false));
-      GF_TRY(c, conv_chi2(xs, b, p, B.mpad, B.S1, B.S2, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
+      GF_TRY(c, conv_chi2(xs, b, p, B.mpad, B.S1c, B.S2c, B.mconv, B.theta_t, true, data, weight, B.cpart, B.mtrial,
                           vw, &c->fork, true));
       GF_TRY(c, launch_lm_update(xs, b, &o, p->d_c2_first, B.cpart, B.st, theta, B.theta_t, B.mjac, B.mtrial,
                                  xcnt, B.cc_th, B.cc_t, vw, 1));

@@ -101,24 +101,69 @@ def test_two_lanes_match_one_lane(gfo):
         data.append(d)
         weights.append(w)
 
-    def fit(idx):
+    def fit(idx, **kw):
         sts = [stamps[i] for i in idx]
         gb = GpuBatch(ctx, sts, data=[data[i] for i in idx], weights=[weights[i] for i in idx])
         lo = to_dev(np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in sts]), torch.float64)
         hi = to_dev(np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in sts]), torch.float64)
         start = to_dev(np.concatenate([s.start for s in sts]), torch.float64)
-        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-5)
+        th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-5, **kw)
         return th.cpu().numpy(), info, gb.batch.offsets["par"]
 
-    print("600 stamps: two lanes", flush=True)
-    t2, i2, p2 = fit(list(range(600)))
-    assert np.all(np.isfinite(t2)) and np.any(i2["iters"] > 4)
+    two = []
+    for pe in (4, 1):   # the count read every fourth iteration, and after every one
+        print(f"600 stamps: two lanes, poll_every {pe}", flush=True)
+        two.append(fit(list(range(600)), poll_every=pe))
+        assert np.all(np.isfinite(two[-1][0])) and np.any(two[-1][1]["iters"] > 4)
     for lo_, hi_ in ((0, 300), (300, 600)):
         print(f"stamps {lo_}..{hi_ - 1}: one lane", flush=True)
         t1, i1, p1 = fit(list(range(lo_, hi_)))
-        for k, s in enumerate(range(lo_, hi_)):
-            np.testing.assert_array_equal(t1[p1[k]:p1[k] + 8], t2[p2[s]:p2[s] + 8], err_msg=str(s))
+        for t2, i2, p2 in two:
+            for k, s in enumerate(range(lo_, hi_)):
+                np.testing.assert_array_equal(t1[p1[k]:p1[k] + 8], t2[p2[s]:p2[s] + 8], err_msg=str(s))
+                for f in ("chi2", "iters", "nfev", "njev", "status"):
+                    assert i1[f][k] == i2[f][s], (s, f, i1[f][k], i2[f][s])
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_two_lanes_with_moves_repeatable():
+    """An uneven batch (1024 stamps of 32..256 px, both FFT forms) in two
+    lanes, with one-workgroup stamps moving to the multi-pass launches once
+    few of their bucket remain (the default): one lane's chi^2 convolution
+    runs while the other convolves its Jacobian images, so the two must not
+    share scratch spectra.  Repeated fits of the same input give the same
+    bits."""
+    ctx = ops.Context(0)
+    stamps = synth.c3(1024)
+    n = len(stamps)
+    batch = ops.Batch(ctx, [s.H for s in stamps], [s.W for s in stamps], [s.K for s in stamps], [1] * n)
+    taps = to_dev(np.concatenate([s.psf.ravel() for s in stamps]), torch.float32)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
+    forms = set(int(u) for u in psf.uses_fft)
+    assert {1, 2} <= forms, forms
+    truth = to_dev(np.concatenate([s.truth for s in stamps]), torch.float32)
+    m = ops.model(ctx, batch, psf, truth, 5).cpu().numpy().astype(np.float64)
+    off = batch.offsets["pix"]
+    d, w = np.empty_like(m), np.empty_like(m)
+    for i, s in enumerate(stamps):
+        sl = slice(off[i], off[i] + s.H * s.W)
+        dd, ww = synth.add_gaussian_noise(m[sl].reshape(s.H, s.W), s.noise_sigma, s.noise_seed)
+        d[sl], w[sl] = dd.ravel(), ww.ravel()
+    data, weight = to_dev(d, torch.float32), to_dev(w, torch.float32)
+    lo = to_dev(np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in stamps]), torch.float64)
+    hi = to_dev(np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in stamps]), torch.float64)
+    start = to_dev(np.concatenate([s.start for s in stamps]), torch.float64)
+    for pe in (4, 1):
+        runs = []
+        for r in range(3):
+            print(f"1024 uneven stamps, poll_every {pe}: fit {r}", flush=True)
+            th, info = ops.fit_lm(ctx, batch, psf, data, weight, start, lo=lo, hi=hi, ftol=1e-5, poll_every=pe)
+            runs.append((th.cpu().numpy(), info))
+        assert np.all(np.isfinite(runs[0][0])) and np.any(runs[0][1]["iters"] > 10)
+        for th, info in runs[1:]:
+            np.testing.assert_array_equal(th, runs[0][0])
             for f in ("chi2", "iters", "nfev", "njev", "status"):
-                assert i1[f][k] == i2[f][s], (s, f, i1[f][k], i2[f][s])
+                np.testing.assert_array_equal(info[f], runs[0][1][f], err_msg=f)
     torch.cuda.synchronize()
     ctx.close()
