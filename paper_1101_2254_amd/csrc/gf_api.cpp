@@ -1521,7 +1521,12 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
         bool done = false;
       };
       Lane ln[2];
-      auto lanes_cleanup = [&]() {   // every replay has been waited for at a poll
+      // After a normal end every replay has been waited for at a poll; after
+      // an error, replays may still run, so the lanes' streams are waited
+      // for before their graphs go.
+      auto lanes_cleanup = [&](bool failed) {
+        for (Lane &l : ln)
+          if (failed && l.s) (void)hipStreamSynchronize(l.s);
         for (Lane &l : ln) {
           if (l.x) (void)hipGraphExecDestroy(l.x);
           if (l.g) (void)hipGraphDestroy(l.g);
@@ -1614,7 +1619,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
         return GF_OK;
       };
       const gf_status s2 = body();
-      lanes_cleanup();
+      lanes_cleanup(s2 != GF_OK);
       return s2;
     }
     std::vector<char> act;
@@ -1676,6 +1681,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     return GF_OK;
   };
   st = run();
+  if (st != GF_OK) (void)hipStreamSynchronize(cs);   // replays of this call's graph may still run
   cleanup();
   return st;
 }
