@@ -388,6 +388,42 @@ def test_fit_lm_batch_default_tolerance(ctx, gfo):
         assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), (s, st.H, res[s], info)
 
 
+def test_fit_lm_two_lanes_default_tolerance(gfo):
+    """The six stamps of the test above followed by 594 stamps of 32 px: a
+    600-stamp plain fit, which runs as two lanes (the form of the uneven-batch
+    benchmark, with the one-workgroup stamps moved to the multi-pass launches
+    once few of their bucket remain: a context of its own, with the default
+    move thresholds).  The six stamps' final chi^2 within 1e-5 (relative) of
+    the oracle's fits from the same start at ftol 1e-5."""
+    ctx = ops.Context(0)
+    g = synth.rng(123)
+    stamps = [synth.c3_stamp(g, N, i, 123) for i, N in enumerate([32, 64, 96, 128, 192, 256])]
+    g2 = synth.rng(124)
+    stamps += [synth.c3_stamp(g2, 32, 6 + i, 124) for i in range(594)]
+    ths = [st.truth.astype(np.float32).astype(np.float64) for st in stamps]
+    print("oracle renders 600 stamps", flush=True)
+    data, weights = _observed(gfo, stamps, ths, 500)
+    gb = GpuBatch(ctx, stamps, data=data, weights=weights)
+    assert {1, 2} <= set(int(u) for u in gb.psf.uses_fft[:6])
+    lo = np.concatenate([synth.bounds(1, st.H, st.W)[0] for st in stamps])
+    hi = np.concatenate([synth.bounds(1, st.H, st.W)[1] for st in stamps])
+    start = np.concatenate([st.start for st in stamps])
+    print("two-lane fit of 600 stamps", flush=True)
+    fit, res = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, to_dev(start, torch.float64),
+                          lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-5, poll_every=1)
+    assert np.all(np.isfinite(fit.cpu().numpy()))
+    for s, st in enumerate(stamps[:6]):
+        l, h = synth.bounds(1, st.H, st.W)
+        print(f"oracle fit of stamp {s} ({st.H} px)", flush=True)
+        ref, info = gfo.fit_lm(st.start, gb.psf64(s), gb.d32[s].astype(np.float64), gb.w32[s].astype(np.float64),
+                               5, lo=l, hi=h, ftol=1e-5)
+        assert info["status"] == 0, (s, info)
+        assert res["status"][s] == 0 or res["reason"][s] == 4, (s, res[s])
+        assert res["chi2"][s] == pytest.approx(info["chi2"], rel=1e-5), (s, st.H, res[s], info)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def test_fit_lm_uneven_batch_c3(ctx, gfo):
     """64 stamps with the uneven-size priors (32..256 px, PSF 15..33, Gaussian
     or Moffat) fitted in one call; six small ones checked against the oracle
