@@ -351,7 +351,11 @@ void gf_lm_opts_default(gf_lm_opts *opts);
  * poll_every iterations.  Stamps that finish stop costing work.
  * The fit runs on streams of the context, ordered after and before the
  * caller's stream by events; a batch of 512 or more stamps in the plain form
- * runs as two halves on two of them, with the same per-stamp results. 
+ * runs as two halves on two of them, each polled every poll_every
+ * iterations.  A stamp runs the same kernels as in one batch; only the
+ * iteration at which a one-workgroup FFT stamp moves to the multi-pass
+ * launches (once few stamps of its size are left) follows its half's count,
+ * which can change the last bits of its result.
  * Returns GF_OK when the call ran (per-stamp outcomes are in res).  Data or
  * weights that are not finite make that stamp's chi^2 non-finite: its fit
  * then rejects every step and ends with GF_ENOTCONV, reason 4, at the
