@@ -85,3 +85,61 @@ def test_c4_likelihood_full_batch_sampled(ctx, gfo):
         # term (Cauchy-Schwarz), as in the other trial-point checks
         wm = math.sqrt(float(np.sum(w64 * mt * mt)))
         assert abs(chi[s] - ref) <= 1e-5 * ref + 2 * 2e-6 * math.sqrt(ref) * wm, (s, chi[s], ref)
+
+
+def test_c3_full_batch_sampled(gfo):
+    """The uneven batch at its full size and in the benchmark's launch
+    configuration: 4096 stamps of 32..256 px in one gf_fit_lm call at ftol
+    1e-5 with at most 100 iterations, the count read after every iteration,
+    two lanes, one-workgroup stamps moving to the multi-pass launches once few
+    of their size remain.  The first stamp of each side gets an observation
+    rendered by the oracle (the others one rendered by the library), and its
+    final chi^2 is within 1e-5 (relative) of the oracle's fit from the same
+    start."""
+    ctx = ops.Context(0)
+    stamps = synth.c3(4096)
+    n = len(stamps)
+    batch = ops.Batch(ctx, [s.H for s in stamps], [s.W for s in stamps], [s.K for s in stamps], [1] * n)
+    taps = to_dev(np.concatenate([s.psf.ravel() for s in stamps]), torch.float32)
+    psf = ops.Psf(ctx, batch, taps, ops.GF_CONV_AUTO)
+    truth = to_dev(np.concatenate([s.truth for s in stamps]), torch.float32)
+    print("library render of 4096 stamps", flush=True)
+    m = ops.model(ctx, batch, psf, truth, 5).cpu().numpy().astype(np.float64)
+    pick = {}
+    for i, s in enumerate(stamps):
+        pick.setdefault(s.H, i)
+    assert sorted(pick) == sorted(synth.C3_SIZES)
+    assert {1, 2} <= set(int(psf.uses_fft[i]) for i in pick.values())
+    off = batch.offsets["pix"]
+    d, w = np.empty_like(m), np.empty_like(m)
+    for i, s in enumerate(stamps):
+        sl = slice(off[i], off[i] + s.H * s.W)
+        mi = m[sl].reshape(s.H, s.W)
+        if i in pick.values():
+            print(f"oracle render of stamp {i} ({s.H} px, K = {s.K})", flush=True)
+            mi = gfo.model(s.H, s.W, s.truth.astype(np.float32).astype(np.float64),
+                           s.psf.astype(np.float32).astype(np.float64), 5)
+        dd, ww = synth.add_gaussian_noise(mi, s.noise_sigma, s.noise_seed)
+        d[sl], w[sl] = dd.ravel(), ww.ravel()
+    d32, w32 = d.astype(np.float32), w.astype(np.float32)
+    lo = np.concatenate([synth.bounds(1, s.H, s.W)[0] for s in stamps])
+    hi = np.concatenate([synth.bounds(1, s.H, s.W)[1] for s in stamps])
+    start = np.concatenate([s.start for s in stamps])
+    print("fit of 4096 stamps", flush=True)
+    _, res = ops.fit_lm(ctx, batch, psf, to_dev(d32), to_dev(w32), to_dev(start, torch.float64),
+                        lo=to_dev(lo, torch.float64), hi=to_dev(hi, torch.float64), ftol=1e-5, max_iter=100,
+                        poll_every=1)
+    assert np.all(res["iters"] >= 1)
+    for N, i in sorted(pick.items()):
+        s = stamps[i]
+        sl = slice(off[i], off[i] + s.H * s.W)
+        l, h = synth.bounds(1, s.H, s.W)
+        print(f"oracle fit of stamp {i} ({N} px)", flush=True)
+        _, info = gfo.fit_lm(s.start, s.psf.astype(np.float32).astype(np.float64),
+                             d32[sl].reshape(s.H, s.W).astype(np.float64), w32[sl].reshape(s.H, s.W).astype(np.float64),
+                             5, lo=l, hi=h, ftol=1e-5, max_iter=100)
+        assert info["status"] == 0, (i, N, info)
+        assert res["status"][i] == 0 or res["reason"][i] == 4, (i, N, res[i])
+        assert res["chi2"][i] == pytest.approx(info["chi2"], rel=1e-5), (i, N, res[i], info)
+    torch.cuda.synchronize()
+    ctx.close()
