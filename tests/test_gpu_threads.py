@@ -82,10 +82,10 @@ def test_contexts_in_concurrent_threads(gfo):
         c.close()
 
 
-def test_two_lanes_match_one_lane(gfo):
-    """A plain-form batch of at least 512 stamps runs as two lanes (halves on
-    two streams with their own lists, graphs and restrictions); every stamp
-    gives the bits it gives in a smaller batch, which runs as one lane."""
+def _lane_fitter(gfo):
+    """600 stamps of 32 and 48 px (every seventh with a 5 px PSF, on the
+    direct path), observed through the oracle, and a function fitting any
+    subset of them in one call of a context that keeps the FFT forms."""
     from tests.gpu_common import keep_fft_forms
     ctx = ops.Context(0)
     keep_fft_forms(ctx)
@@ -110,6 +110,23 @@ def test_two_lanes_match_one_lane(gfo):
         th, info = ops.fit_lm(ctx, gb.batch, gb.psf, gb.data, gb.weight, start, lo=lo, hi=hi, ftol=1e-5, **kw)
         return th.cpu().numpy(), info, gb.batch.offsets["par"]
 
+    return ctx, fit
+
+
+def _same_stamps(one, two, lo_, hi_):
+    t1, i1, p1 = one
+    t2, i2, p2 = two
+    for k, s in enumerate(range(lo_, hi_)):
+        np.testing.assert_array_equal(t1[p1[k]:p1[k] + 8], t2[p2[s]:p2[s] + 8], err_msg=str(s))
+        for f in ("chi2", "iters", "nfev", "njev", "status"):
+            assert i1[f][k] == i2[f][s], (s, f, i1[f][k], i2[f][s])
+
+
+def test_two_lanes_match_one_lane(gfo):
+    """A plain-form batch of at least 512 stamps runs as two lanes (halves on
+    two streams with their own lists, graphs and restrictions); every stamp
+    gives the bits it gives in a smaller batch, which runs as one lane."""
+    ctx, fit = _lane_fitter(gfo)
     two = []
     for pe in (4, 1):   # the count read every fourth iteration, and after every one
         print(f"600 stamps: two lanes, poll_every {pe}", flush=True)
@@ -117,12 +134,26 @@ def test_two_lanes_match_one_lane(gfo):
         assert np.all(np.isfinite(two[-1][0])) and np.any(two[-1][1]["iters"] > 4)
     for lo_, hi_ in ((0, 300), (300, 600)):
         print(f"stamps {lo_}..{hi_ - 1}: one lane", flush=True)
-        t1, i1, p1 = fit(list(range(lo_, hi_)))
-        for t2, i2, p2 in two:
-            for k, s in enumerate(range(lo_, hi_)):
-                np.testing.assert_array_equal(t1[p1[k]:p1[k] + 8], t2[p2[s]:p2[s] + 8], err_msg=str(s))
-                for f in ("chi2", "iters", "nfev", "njev", "status"):
-                    assert i1[f][k] == i2[f][s], (s, f, i1[f][k], i2[f][s])
+        one = fit(list(range(lo_, hi_)))
+        for t in two:
+            _same_stamps(one, t, lo_, hi_)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+@pytest.mark.parametrize("max_iter", [1, 3])
+def test_two_lanes_iteration_cap(gfo, max_iter):
+    """Two lanes stopped by a small iteration cap (before any stamp has
+    converged, and between polls when the count is read every second
+    iteration) give every stamp the bits of the same fit as one lane."""
+    ctx, fit = _lane_fitter(gfo)
+    for pe in (1, 2):
+        print(f"600 stamps: two lanes, max_iter {max_iter}, poll_every {pe}", flush=True)
+        two = fit(list(range(600)), max_iter=max_iter, poll_every=pe)
+        assert np.all(two[1]["iters"] <= max_iter)
+        for lo_, hi_ in ((0, 300), (300, 600)):
+            print(f"stamps {lo_}..{hi_ - 1}: one lane", flush=True)
+            _same_stamps(fit(list(range(lo_, hi_)), max_iter=max_iter, poll_every=pe), two, lo_, hi_)
     torch.cuda.synchronize()
     ctx.close()
 
