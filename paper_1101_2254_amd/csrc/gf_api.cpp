@@ -297,7 +297,7 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
     delete c;
     return GF_EDEVICE;
   }
-  if (hipHostMalloc((void **)&c->h_pinned, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void **)&c->h_pinned, sizeof(int) * 8 * std::max(2, kLmLanes), hipHostMallocDefault) != hipSuccess) {
     dfree(c->d_bn);
     delete c;
     return GF_ENOMEM;
@@ -330,7 +330,9 @@ gf_status gf_create(gf_ctx **out, int device, const char *autotune_cache) {
 // not touched.
 static void ctx_sync(gf_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
-  for (hipStream_t s : {c->lm_stream, c->lm_stream2, c->fork.side[0], c->fork.side[1], c->fork.side[2]})
+  for (hipStream_t s : {c->lm_stream, c->fork.side[0], c->fork.side[1], c->fork.side[2]})
+    if (s) (void)hipStreamSynchronize(s);
+  for (hipStream_t s : c->lm_lane_stream)
     if (s) (void)hipStreamSynchronize(s);
   for (hipStream_t s : c->side)
     if (s) (void)hipStreamSynchronize(s);
@@ -353,7 +355,8 @@ void gf_destroy(gf_ctx *c) {
   if (c->lm_graph) (void)hipGraphDestroy(c->lm_graph);
   if (c->lm_stream) (void)hipStreamDestroy(c->lm_stream);
   if (c->lm_ev) (void)hipEventDestroy(c->lm_ev);
-  if (c->lm_stream2) (void)hipStreamDestroy(c->lm_stream2);
+  for (hipStream_t s : c->lm_lane_stream)
+    if (s) (void)hipStreamDestroy(s);
   for (hipEvent_t e : c->lm_lane_ev)
     if (e) (void)hipEventDestroy(e);
   fork_destroy(c->fork);
@@ -1325,10 +1328,10 @@ void lm_layout(const gf_batch *b, const gf_psf *p, int nchan, int nacc, Arena &a
   B.st = a.take<LMState>(b->n);
   B.mjac = a.take<int>(b->n);
   B.mtrial = a.take<int>(b->n);
-  B.cnt = a.take<int>(16);
-  // room for the lists and copy plans of two lanes (each up to the full size)
-  B.lists = a.take<Work>(2 * full_list_units(b, p));
-  B.plan = a.take<CopyRun>(2 * (lm_runs_ensure(b, p) + 1));
+  B.cnt = a.take<int>(8 * std::max(2, kLmLanes));
+  // room for the lists and copy plans of every lane (each up to the full size)
+  B.lists = a.take<Work>(std::max(2, kLmLanes) * full_list_units(b, p));
+  B.plan = a.take<CopyRun>(std::max(2, kLmLanes) * (lm_runs_ensure(b, p) + 1));
   B.cc_th = a.take<CompC>((int64_t)b->n * kMaxComp);
   B.cc_t = a.take<CompC>((int64_t)b->n * kMaxComp);
 }
@@ -1413,9 +1416,10 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
   // batches of at least this many stamps run their plain-form iterations in
   // two lanes (see run below)
   constexpr int kLmLaneMin = 512;
-  const int lanes = (!spec && graphs && b->n >= kLmLaneMin) ? 2 : 1;
-  if (lanes == 2) {
-    if (!c->lm_stream2) GF_TRY(c, hipStreamCreateWithFlags(&c->lm_stream2, hipStreamNonBlocking));
+  const int lanes = (!spec && graphs && b->n >= kLmLaneMin) ? kLmLanes : 1;
+  if (lanes > 1) {
+    for (hipStream_t &s : c->lm_lane_stream)
+      if (!s) GF_TRY(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     for (hipEvent_t &e : c->lm_lane_ev)
       if (!e) GF_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
@@ -1506,7 +1510,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
     // kernels as in one lane; only the moves of one-workgroup stamps to the
     // multi-pass launches follow its half's counts.  Results are written once
     // both halves have finished.
-    if (lanes == 2) {
+    if (lanes > 1) {
       struct Lane {
         hipStream_t s = nullptr;
         hipEvent_t e = nullptr;
@@ -1520,7 +1524,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
         volatile int *h = nullptr;
         bool done = false;
       };
-      Lane ln[2];
+      Lane ln[kLmLanes];
       // After a normal end every replay has been waited for at a poll; after
       // an error, replays may still run, so the lanes' streams are waited
       // for before their graphs go.
@@ -1536,8 +1540,8 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
       };
       auto body = [&]() -> gf_status {
         const int64_t units = full_list_units(b, p), runs = lm_runs_ensure(b, p) + 1;
-        for (int l = 0; l < 2; ++l) {
-          ln[l].s = l == 0 ? cs : c->lm_stream2;
+        for (int l = 0; l < kLmLanes; ++l) {
+          ln[l].s = l == 0 ? cs : c->lm_lane_stream[l - 1];
           ln[l].e = c->lm_lane_ev[l];
           ln[l].cnt = B.cnt + 8 * l;
           ln[l].dev = B.lists + units * l;
@@ -1545,13 +1549,13 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           ln[l].h = c->h_pinned + 8 * l;
         }
         std::vector<char> half(b->n);
-        for (int l = 0; l < 2; ++l) {   // the halves' lists (the start point is done on cs)
-          for (int q = 0; q < b->n; ++q) half[q] = (q & 1) == l;
+        for (int l = 0; l < kLmLanes; ++l) {   // the lanes' lists (the start point is done on cs)
+          for (int q = 0; q < b->n; ++q) half[q] = q % kLmLanes == l;
           GF_TRY(c, restrict_lists(cs, b, p, half, moved, ln[l].plan, ln[l].dev, ln[l].view));
           ln[l].stamps = ln[l].view.n_stamps;
         }
         GF_TRY(c, hipEventRecord(ln[0].e, cs));
-        GF_TRY(c, hipStreamWaitEvent(ln[1].s, ln[0].e, 0));
+        for (int l = 1; l < kLmLanes; ++l) GF_TRY(c, hipStreamWaitEvent(ln[l].s, ln[0].e, 0));
         auto use = [&](Lane &l) {
           xs = l.s;
           vw = &l.view;
@@ -1561,11 +1565,11 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
         // host waits on the lanes' polls in turn, so while it waits on (and
         // restricts) one lane the other's queued iterations keep the device
         // busy.
-        int itl[2] = {0, 0};
-        bool pending[2] = {false, false};
+        int itl[kLmLanes] = {};
+        bool pending[kLmLanes] = {};
         int next = 0;
         for (;;) {
-          for (int li = 0; li < 2; ++li) {
+          for (int li = 0; li < kLmLanes; ++li) {
             Lane &l = ln[li];
             if (l.done || pending[li]) continue;
             use(l);
@@ -1587,9 +1591,9 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
             pending[li] = true;
           }
           int li = next;
-          if (!pending[li]) li = 1 - li;
-          if (!pending[li]) break;   // both lanes done
-          next = 1 - li;
+          for (int k = 0; k < kLmLanes && !pending[li]; ++k) li = (li + 1) % kLmLanes;
+          if (!pending[li]) break;   // every lane done
+          next = (li + 1) % kLmLanes;
           Lane &l = ln[li];
           GF_TRY(c, hipEventSynchronize(l.e));
           pending[li] = false;
@@ -1602,7 +1606,7 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
             GF_TRY(c, hipMemcpyAsync(c->h_states, B.st, b->n * sizeof(LMState), hipMemcpyDeviceToHost, l.s));
             GF_TRY(c, hipStreamSynchronize(l.s));
             const LMState *hs = static_cast<const LMState *>(c->h_states);
-            for (int q = 0; q < b->n; ++q) half[q] = ((q & 1) == li && hs[q].active) ? 1 : 0;
+            for (int q = 0; q < b->n; ++q) half[q] = (q % kLmLanes == li && hs[q].active) ? 1 : 0;
             GF_TRY(c, restrict_lists(l.s, b, p, half, moved, l.plan, l.dev, l.view));
             l.stamps = active;
             use(l);
@@ -1611,8 +1615,10 @@ gf_status gf_fit_lm(gf_ctx *c, const gf_batch *b, const gf_psf *p, const float *
           }
         }
         // both halves joined on the fit's stream, then every stamp's result
-        GF_TRY(c, hipEventRecord(ln[1].e, ln[1].s));
-        GF_TRY(c, hipStreamWaitEvent(cs, ln[1].e, 0));
+        for (int l = 1; l < kLmLanes; ++l) {
+          GF_TRY(c, hipEventRecord(ln[l].e, ln[l].s));
+          GF_TRY(c, hipStreamWaitEvent(cs, ln[l].e, 0));
+        }
         GF_TRY(c, launch_lm_result(cs, b->n, B.st, res));
         GF_TRY(c, hipEventRecord(ev, cs));
         GF_TRY(c, hipStreamWaitEvent(c->stream, ev, 0));

@@ -34,6 +34,7 @@ constexpr int kFftCap = 3840;
 constexpr int kFftCapSmall = 3456;
 constexpr int kFftCapMid = 3408;
 constexpr int fft_cap(int rmax) { return rmax <= 18 ? kFftCapSmall : rmax <= 24 ? kFftCapMid : kFftCap; }
+constexpr int kLmLanes = 2;           // lanes of a large plain-form LM fit
 constexpr int kFftMaxStages = 12;
 constexpr int kFftNarrowT = 1;         // row pairs per workgroup in the narrow launch shape
 constexpr int kFftNarrowC = 2;         // bins per workgroup in the narrow launch shape
@@ -365,8 +366,8 @@ struct gf_ctx {
   hipEvent_t lm_ev = nullptr;
   // the second lane of a large plain-form fit (its stream) and the lanes'
   // poll events
-  hipStream_t lm_stream2 = nullptr;
-  hipEvent_t lm_lane_ev[2] = {};
+  hipStream_t lm_lane_stream[gf::kLmLanes - 1] = {};   // lanes 1.. of a large LM fit
+  hipEvent_t lm_lane_ev[gf::kLmLanes] = {};
   gf::LmGraphKey lm_key;
   hipGraph_t lm_graph = nullptr;
   hipGraphExec_t lm_exec = nullptr;
