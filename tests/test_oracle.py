@@ -345,6 +345,48 @@ def test_lm_recovers_truth_noise_free(gfo):
     np.testing.assert_allclose(fit, th, rtol=1e-6, atol=1e-8)
 
 
+@pytest.mark.parametrize("ncomp", [1, 2])
+def test_lm_fit_on_noisy_data_is_a_stationary_point(gfo, ncomp):
+    """The whole fit on noisy data has no closed form, but its end point has
+    a property that needs no LM: chi^2 is stationary there.  At the oracle's
+    fit (ftol 1e-13, every parameter inside its bounds) the central-difference
+    gradient of the oracle's chi^2 along each parameter is tiny: a Newton
+    step along that axis (gradient over second difference) would lower chi^2
+    by less than 1e-9 of it, and chi^2 rises on both sides of the fit along
+    every axis.  A wrong sign or a dropped factor in any Jacobian column, or a
+    damping that stops short, leaves a gradient many orders above that."""
+    H = W = 32
+    psf = synth.gaussian_psf(9, 1.5)
+    if ncomp == 1:
+        th = np.array([15.7, 16.2, 1.0, 4.0, 2.0, 0.7, 0.5, 0.01])
+    else:
+        th = np.array([15.7, 16.2, 2.0, 2.5, 3.0, 0.8, 0.4, 15.6, 16.1, 0.5, 7.0, 1.0, 0.5, 1.2, 0.01])
+    m = gfo.model(H, W, th, psf, 5)
+    d, w = synth.add_gaussian_noise(m, 0.02, 91 + ncomp)
+    start = synth.perturb_uniform(th, synth.rng(78 + ncomp), 0.1)
+    lo, hi = synth.bounds(ncomp, H, W)
+    fit, info = gfo.fit_lm(start, psf, d, w, 5, lo=lo, hi=hi, ftol=1e-13, xtol=1e-14, max_iter=300)
+    # away from every finite bound (the open ones are +-1e30)
+    margin = np.where(hi - lo < 1e20, 1e-3 * (hi - lo), 0.0)
+    assert np.all(fit > lo + margin) and np.all(fit < hi - margin), fit
+
+    def chi2(t):
+        return gfo.chi2(d, w, gfo.model(H, W, t, psf, 5))
+
+    c0 = chi2(fit)
+    assert c0 == pytest.approx(info["chi2"], rel=1e-12)
+    for p in range(fit.size):
+        scale = max(abs(fit[p]), 1.0)
+        h1, h2 = 1e-6 * scale, 1e-3 * scale
+        e = np.zeros_like(fit)
+        e[p] = 1.0
+        g = (chi2(fit + h1 * e) - chi2(fit - h1 * e)) / (2 * h1)
+        up, dn = chi2(fit + h2 * e), chi2(fit - h2 * e)
+        curv = (up - 2 * c0 + dn) / h2 ** 2
+        assert curv > 0 and up > c0 and dn > c0, (p, up - c0, dn - c0)
+        assert g * g / (2 * curv) <= 1e-9 * c0, (p, g, curv, c0)
+
+
 def test_lm_bounds_are_respected(gfo):
     H = W = 20
     psf = synth.gaussian_psf(7, 1.2)
