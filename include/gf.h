@@ -156,8 +156,9 @@ gf_status gf_synchronize(gf_ctx *ctx);
  * shared_image != 0 declares that every stamp shares one observation and one
  * PSF (a likelihood batch: many parameter vectors against one image); all
  * stamps must then have the same H, W, K and n_comp, and data/weight/psf
- * arrays hold a single image.  Errors: GF_EINVAL, GF_ESHAPE (K even or above
- * GF_MAX_K, padded side above GF_MAX_FFT, n_comp outside 1..GF_MAX_COMP). */
+ * arrays hold a single image.  Errors: GF_EINVAL (also for n_stamps < 1: a
+ * batch holds at least one stamp), GF_ESHAPE (K even or above GF_MAX_K,
+ * padded side above GF_MAX_FFT, n_comp outside 1..GF_MAX_COMP). */
 gf_status gf_batch_create(gf_ctx *ctx, int n_stamps, const int32_t *H, const int32_t *W, const int32_t *K,
                           const int32_t *n_comp, int shared_image, gf_batch **out);
 void gf_batch_destroy(gf_batch *batch);

@@ -39,6 +39,14 @@ def test_batch_shapes_rejected(ctx, H, W, K, nc):
     assert L.lib().gf_last_error(ctx.ptr).decode()
 
 
+def test_empty_batch_rejected(ctx):
+    """A batch of no stamps is refused before anything is allocated, in both
+    forms of the call."""
+    assert _status(L.gf_batch_create, ctx.ptr, [], [], [], [], False) == L.GF_EINVAL
+    assert _status(L.gf_batch_create_grouped, ctx.ptr, [], [], [], [], []) == L.GF_EINVAL
+    assert L.lib().gf_last_error(ctx.ptr).decode()
+
+
 def test_padded_side_and_direct_psf_limits(ctx):
     # a padded side above GF_MAX_FFT is refused with the batch
     assert _status(L.gf_batch_create, ctx.ptr, [2000], [2000], [65], [1], False) == L.GF_ESHAPE
