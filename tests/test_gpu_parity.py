@@ -177,6 +177,30 @@ def test_conv_full_size_c2_sampled(ctx, gfo):
     assert rel_l2(got, ref) <= 1e-5
 
 
+def test_conv_largest_side_sampled(ctx, gfo):
+    """The largest FFT side the library takes: a 1920 x 1920 stamp with the
+    largest PSF (129 x 129) pads to 2048 x 2048.  A seeded grid of uniform
+    values in [0, 1) is convolved on the GPU (multi-pass FFT); the centre,
+    the corners and 200 random output pixels are checked against the
+    oracle's direct sum, computed one by one."""
+    N, K = 1920, 129
+    psf = synth.moffat_psf(K, 40.0, 3.0)
+    st = synth.Stamp(N, N, psf, np.zeros(8), np.zeros(8))
+    gb = GpuBatch(ctx, [st], thetas=[np.zeros(8)], mode=ops.GF_CONV_FFT)
+    assert gb.psf.fft_side[0] == 2048 and int(gb.psf.uses_fft[0]) == 1
+    g = synth.rng(2048)
+    mp_host = g.random((N + K - 1, N + K - 1)).astype(np.float32)
+    print("convolution at the largest side", flush=True)
+    out = gb.split_pix(ops.convolve_psf(ctx, gb.batch, gb.psf, to_dev(mp_host.ravel())))[0]
+    mp64 = mp_host.astype(np.float64)
+    pts = [(N // 2, N // 2), (0, 0), (0, N - 1), (N - 1, 0), (N - 1, N - 1)]
+    pts += [(int(g.integers(0, N)), int(g.integers(0, N))) for _ in range(200)]
+    got = np.array([out[i, j] for i, j in pts])
+    ref = np.array([gfo.conv_valid_pixel(mp64, gb.psf64(0), i, j) for i, j in pts])
+    assert rel_l2(got, ref) <= 1e-5, rel_l2(got, ref)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
 def test_delta_psf_is_identity_on_gpu(ctx, gfo):
     for mode in (ops.GF_CONV_FFT, ops.GF_CONV_DIRECT):
         K = 9
